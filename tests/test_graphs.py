@@ -1,0 +1,75 @@
+"""Checks of the seeded synthetic graph generators."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import connected_components
+
+from paper_2305_10356_amd import graphs
+
+
+def check_simple_symmetric_connected(g):
+    n = g.n
+    rp, ci = g.row_ptr.astype(np.int64), g.col_idx.astype(np.int64)
+    assert rp[0] == 0 and rp[-1] == ci.shape[0]
+    S = sp.csr_matrix((np.ones(ci.shape[0]), ci, rp), shape=(n, n))
+    assert (S != S.T).nnz == 0
+    assert S.diagonal().sum() == 0
+    assert S.max() == 1.0
+    for i in range(0, n, max(1, n // 50)):
+        row = ci[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(row) > 0)
+    assert g.degrees().min() >= 1
+    assert connected_components(S, directed=False)[0] == 1
+
+
+def test_config1_reproducible_and_valid():
+    g1, x1 = graphs.config_graph(1)
+    g2, x2 = graphs.config_graph(1)
+    assert np.array_equal(g1.col_idx, g2.col_idx) and np.array_equal(x1, x2)
+    check_simple_symmetric_connected(g1)
+    s = g1.stats()
+    assert s["n"] == 1000 and abs(s["mean_degree"] - 16) < 1.0
+    assert abs(s["realized_r"] - 0.3) < 0.05
+    assert min(g1.meta["sizes"]) >= 50
+    np.testing.assert_allclose(x1, np.random.default_rng(0).standard_normal((1000, 8)) / np.sqrt(1000))
+
+
+def test_config2_stats():
+    g, x = graphs.config_graph(2)
+    check_simple_symmetric_connected(g)
+    s = g.stats()
+    assert abs(s["mean_degree"] - 20) < 0.5 and abs(s["realized_r"] - 0.4) < 0.03
+    assert x.shape == (50000, 32)
+
+
+def test_dcsbm_small_heavy_tail():
+    g, _ = graphs.config_graph(3, n=64000)
+    check_simple_symmetric_connected(g)
+    s = g.stats()
+    assert 22 < s["mean_degree"] <= 25.5
+    assert abs(s["realized_r"] - 0.5) < 0.05
+    assert s["max_degree"] > 5 * s["mean_degree"]
+
+
+def test_node_order_hides_blocks():
+    g, _ = graphs.config_graph(2)
+    # consecutive ids are not in the same block more often than chance
+    same = np.mean(g.labels[1:] == g.labels[:-1])
+    assert same < 0.1
+
+
+def test_bfs_ball():
+    g, _ = graphs.config_graph(2)
+    sub = graphs.bfs_ball_subgraph(g, 500, np.random.default_rng(9))
+    assert sub.n == 500
+    check_simple_symmetric_connected(sub)
+
+
+def test_batched_specs():
+    specs = graphs.batched_graph_specs(256)
+    assert len(specs) == 256
+    assert all(1000 <= s["n"] <= 50000 and s["k"] in (4, 8, 16, 32) and 8 <= s["dbar"] <= 32
+               for s in specs)
+    g, x = graphs.batched_graph(specs[0])
+    check_simple_symmetric_connected(g)
+    assert x.shape == (specs[0]["n"], specs[0]["k"])

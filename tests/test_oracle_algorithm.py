@@ -1,0 +1,159 @@
+"""Pins of the oracle's Algorithm 2 runs against the limits of Theorems 1-4
+(dense eigendecomposition), the k = 1 closed form, the residual identities
+and planted-partition recovery."""
+import numpy as np
+import pytest
+
+from oracle import ofm_oracle as O
+from paper_2305_10356_amd import graphs
+
+
+@pytest.fixture(scope="module")
+def c1():
+    g, x0 = graphs.config_graph(1)
+    lap = O.laplacian(g.n, g.row_ptr, g.col_idx)
+    mu, U = O.dense_eigh(lap)
+    return g, x0, lap, mu, U
+
+
+def run(lap, x0, variant, iters, **kw):
+    st, _ = O.run(lap, x0, iters, O.Options(variant=variant, **kw))
+    return st.X
+
+
+def test_ofm_f1_limit(c1):
+    g, x0, lap, mu, U = c1
+    k = x0.shape[1]
+    X = run(lap, x0, O.F1, 300)
+    assert O.relres(lap, X) < 1e-6
+    lam = mu - 2.0
+    # eig(X^T X) -> -lambda_i = 2 - mu_i ; X X^T -> U_k (-Lam_k) U_k^T (Theorem 1)
+    np.testing.assert_allclose(np.sort(np.linalg.eigvalsh(X.T @ X)), np.sort(-lam[:k]), atol=1e-8)
+    P = (U[:, :k] * (-lam[:k])[None, :]) @ U[:, :k].T
+    np.testing.assert_allclose(X @ X.T, P, atol=1e-7)
+    A = O.dense_A(lap)
+    np.testing.assert_allclose(O.f1_dense(A, X), np.sum(lam[k:] ** 2), rtol=1e-9)
+
+
+def test_ofm_f2_limit(c1):
+    g, x0, lap, mu, U = c1
+    k = x0.shape[1]
+    X = run(lap, x0, O.F2, 400)
+    assert O.relres(lap, X) < 1e-5
+    np.testing.assert_allclose(X.T @ X, np.eye(k), atol=1e-6)
+    np.testing.assert_allclose(X @ X.T, U[:, :k] @ U[:, :k].T, atol=1e-5)
+    np.testing.assert_allclose(O.f2_dense(O.dense_A(lap), X), np.sum(mu[:k] - 2.0), rtol=1e-9)
+
+
+def _columns_match(X, U, scale):
+    for i in range(X.shape[1]):
+        target = U[:, i] * scale[i]
+        s = np.sign(np.dot(X[:, i], target))
+        yield np.abs(X[:, i] - s * target).max()
+
+
+def test_tri_f1_limit_with_restart(c1):
+    g, x0, lap, mu, U = c1
+    X = run(lap, x0, O.TRI_F1, 400, restart=True)
+    assert O.relres(lap, X) < 1e-5
+    errs = list(_columns_match(X, U, np.sqrt(2.0 - mu)))
+    # Theorem 2: column i -> +-sqrt(-lambda_i) u_i ; the error is set by the
+    # residual over the eigenvalue gap
+    assert max(errs) < 1e-3
+
+
+def test_tri_f2_limit(c1):
+    g, x0, lap, mu, U = c1
+    X = run(lap, x0, O.TRI_F2, 400)
+    assert O.relres(lap, X) < 1e-5
+    errs = list(_columns_match(X, U, np.ones(X.shape[1])))
+    assert max(errs) < 1e-3
+
+
+@pytest.mark.parametrize("variant,c", [(O.F1, np.sqrt(2.0)), (O.TRI_F1, np.sqrt(2.0)),
+                                       (O.F2, 1.0), (O.TRI_F2, 1.0)])
+def test_single_column_closed_form(c1, variant, c):
+    # k = 1: x -> +-c D^{1/2} 1 / ||D^{1/2} 1||, c = sqrt(-lambda_1) = sqrt(2) for f1
+    g, x0, lap, mu, U = c1
+    X = run(lap, x0[:, :1], variant, 300)
+    t = np.sqrt(g.degrees().astype(float))
+    t = c * t / np.linalg.norm(t)
+    s = np.sign(np.dot(X[:, 0], t))
+    np.testing.assert_allclose(X[:, 0], s * t, atol=1e-6)
+
+
+def test_residual_forms_agree(c1):
+    g, x0, lap, mu, U = c1
+    for X in (x0, run(lap, x0, O.F2, 20), run(lap, x0, O.F1, 40)):
+        a = O.relres(lap, X)
+        b = O.relres_direct(lap, X)
+        c = O.relres_ritz(lap, X)
+        assert a == pytest.approx(c, rel=1e-6)
+        assert b == pytest.approx(c, rel=1e-10)
+
+
+@pytest.mark.parametrize("variant", [O.F1, O.F2])
+def test_ofm_objective_monotone(c1, variant):
+    g, x0, lap, mu, U = c1
+    opts = O.Options(variant=variant)
+    st, _ = O.init(lap, x0, opts)
+    fprev = O.objective(variant, lap, x0)
+    f = O.objective(variant, lap, st.X)
+    assert f <= fprev + 1e-12 * abs(fprev)
+    for _ in range(60):
+        fprev = f
+        st, _ = O.step(lap, st, opts)
+        f = O.objective(variant, lap, st.X)
+        assert f <= fprev + 1e-10 * abs(fprev)
+
+
+def test_fixed_first_step(c1):
+    g, x0, lap, mu, U = c1
+    st, info = O.init(lap, x0, O.Options(variant=O.F1, first_step="fixed", alpha0=0.05))
+    G = O.direction(O.F1, x0, O.apply_A(lap, x0))
+    np.testing.assert_allclose(st.X, x0 - 0.05 * G, rtol=1e-15)
+
+
+def test_clustering_matches_dense_features(c1):
+    # Theorems 1-4: the limits are U_k sqrt(-Lam_k) Q (f1) or U_k Q (f2); an
+    # orthogonal Q keeps row norms and distances, so K-means on the limits
+    # reproduces K-means on the dense features with the same seeds
+    g, x0, lap, mu, U = c1
+    k = x0.shape[1]
+    Uk = U[:, :k]
+    feats = {"f1": Uk * np.sqrt(2.0 - mu[:k])[None, :], "f2": Uk}
+    ref = {}
+    for key, Y in feats.items():
+        ref[key] = O.cluster(Y, k, repeats=3, truth=g.labels)
+    for variant, key in ((O.F1, "f1"), (O.F2, "f2"), (O.TRI_F2, "f2")):
+        X = run(lap, x0, variant, 300)
+        labs, a, _ = O.cluster(X, k, repeats=3, truth=g.labels)
+        assert a == pytest.approx(ref[key][1], abs=0.02)
+        for l1, l2 in zip(labs, ref[key][0]):
+            assert O.ari(l1, l2) > 0.98
+    # the paper's hypothesis (Figure 1): weighted and plain features cluster
+    # comparably; recorded loosely here
+    assert abs(ref["f1"][1] - ref["f2"][1]) < 0.2
+
+
+def test_disjoint_cliques_perfect_recovery():
+    c, m = 4, 30
+    rows, cols = [], []
+    for b in range(c):
+        for i in range(m):
+            for j in range(m):
+                if i != j:
+                    rows.append(b * m + i)
+                    cols.append(b * m + j)
+    # a single weak bridge keeps the graph connected
+    rows += [0, m]
+    cols += [m, 0]
+    order = np.lexsort((cols, rows))
+    rows, cols = np.array(rows)[order], np.array(cols)[order]
+    rp = np.cumsum(np.concatenate([[0], np.bincount(rows, minlength=c * m)]))
+    lap = O.laplacian(c * m, rp, cols)
+    x0 = np.random.default_rng(0).standard_normal((c * m, c)) / np.sqrt(c * m)
+    X = run(lap, x0, O.F2, 200)
+    truth = np.repeat(np.arange(c), m)
+    _, a, nm = O.cluster(X, c, repeats=2, truth=truth)
+    assert a == pytest.approx(1.0) and nm == pytest.approx(1.0)
