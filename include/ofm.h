@@ -1,0 +1,287 @@
+/*
+ * ofm.h -- C ABI of the MI355X (gfx950) orthogonalization-free spectral
+ * clustering library (libofm.so).
+ *
+ * The library computes low-dimensional spectral features of an undirected
+ * graph without any orthogonalization, by running the gradient-type iteration
+ * of Pang & Yang, "Spectral clustering via orthogonalization-free methods"
+ * (arXiv 2305.10356), on the shifted normalized Laplacian A = L - 2I, and
+ * provides the post-processing of its Algorithm 1 (row normalisation and the
+ * K-means assignment step).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers are DEVICE pointers unless a parameter name starts with "host_".
+ * - The caller owns every array it passes in; the library never frees them.
+ *   Handles (ofm_laplacian, ofm_workspace) own only library-allocated memory.
+ * - Dense feature blocks (X, Z, Y, V, G) are N x k, row-major (C-contiguous),
+ *   FP64 for OFM_FP64 and FP32 for OFM_FP32.  Supported widths:
+ *   k in {4, 8, 16, 32, 64}.  (Zero columns are fixed points of every
+ *   variant and never influence the other columns, so a block of another
+ *   width can be zero-padded to the next supported one.)
+ * - Graph indices are int32 (nnz < 2^31).
+ * - All work is enqueued on the given HIP stream (0 = null stream) and is
+ *   asynchronous unless the comment says "synchronizing".  No entry point
+ *   synchronizes the device as a whole.  Handles are not thread-safe.
+ * - Every entry point returns an ofm_status and never throws.  Argument and
+ *   shape errors are detected on the host before anything is enqueued.
+ *   Numerical failures detected on the device (non-finite values, Cholesky
+ *   failure in the residual) set a device status word that the next
+ *   synchronizing call (ofm_solve, ofm_get_stats) returns.
+ */
+#ifndef OFM_H
+#define OFM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ofm_status {
+  OFM_OK = 0,
+  OFM_E_INVALID_ARG = -1,  /* null pointer, negative size, bad enum value   */
+  OFM_E_SHAPE = -2,        /* unsupported k, k > N, mismatched sizes        */
+  OFM_E_GRAPH = -3,        /* malformed CSR, column out of range, a node of
+                              zero degree, or (with OFM_LAP_VALIDATE) a
+                              pattern that is not symmetric                  */
+  OFM_E_NONFINITE = -4,    /* NaN/Inf met in a Gram, a step size or beta     */
+  OFM_E_NUMERIC = -5,      /* X^T X not positive definite in the residual   */
+  OFM_E_HIP = -6,          /* a HIP runtime call failed                      */
+  OFM_E_NOMEM = -7,        /* device allocation failed                       */
+  OFM_E_UNSUPPORTED = -8   /* option combination not implemented             */
+} ofm_status;
+
+/* The four methods (Introduction and Section 2):
+ *   OFM_F1     gradient of f1(X) = ||A + X X^T||_F^2      (eq. gradientf1)
+ *   OFM_TRI_F1 g1(X) = A X + X triu(X^T X)                 (eq. gradientg1)
+ *   OFM_F2     gradient of f2(X) = tr((2I - X^T X) X^T A X) (eq. gradientf2)
+ *   OFM_TRI_F2 g2(X) = 2AX - AX triu(X^T X) - X triu(X^T A X) (eq. gradientg2) */
+typedef enum ofm_variant { OFM_F1 = 0, OFM_TRI_F1 = 1, OFM_F2 = 2, OFM_TRI_F2 = 3 } ofm_variant;
+
+/* Arithmetic of the N x k passes.  k x k products (Grams), step sizes, beta
+ * and the residual are FP64 in both modes.
+ *   OFM_FP64: X, SpMM accumulation and the N x k updates in FP64.
+ *   OFM_FP32: X in FP32; SpMM with FP32 edge weights and FP32 accumulation;
+ *             N x k updates in FP32; Grams accumulated in FP64 from the FP32
+ *             values (every product exact). */
+typedef enum ofm_precision { OFM_FP64 = 0, OFM_FP32 = 1 } ofm_precision;
+
+/* ofm_build_laplacian flags */
+#define OFM_LAP_VALIDATE 1u   /* also check that the pattern is symmetric    */
+#define OFM_LAP_NO_REORDER 2u /* process rows in index order, not by degree  */
+
+typedef struct ofm_laplacian_s* ofm_laplacian;
+typedef struct ofm_workspace_s* ofm_workspace;
+
+typedef struct ofm_opts {
+  int variant;      /* ofm_variant                                            */
+  int precision;    /* ofm_precision                                          */
+  int max_iter;     /* ofm_solve: maximum number of X updates (>= 1)          */
+  int check_every;  /* residual computed every check_every updates (>= 1)     */
+  int first_step;   /* 0: exact line search for the update before the loop of
+                       Algorithm 2; 1: use alpha0 (the algorithm's input step) */
+  int restart;      /* 1: descent restart, beta_i := 0 when <V_i, G_i> >= 0
+                       (a safeguard outside Algorithm 2; 0 = as printed)      */
+  double alpha0;    /* step for first_step = 1                                */
+  double tol;       /* ofm_solve stops when the residual <= tol (0: never)    */
+} ofm_opts;
+
+typedef struct ofm_stats {
+  int64_t iters;     /* number of X updates done since ofm_init               */
+  int32_t status;    /* ofm_status of the device status word                  */
+  int32_t converged; /* 1 when the last residual <= tol                       */
+  double relres;     /* last residual ||A U - U Lam||_F / ||U Lam||_F of the Ritz
+                        pairs (Lam, U) of A on span(X), numerical results
+                        section "Evaluation metrics"; computed from X^T X,
+                        X^T A X and (AX)^T (AX) without orthogonalization;
+                        -1 if none was computed yet                           */
+  double objective;  /* f1 or f2 at the X of the last residual                */
+  int64_t relres_iter; /* iteration whose X the residual belongs to           */
+} ofm_stats;
+
+/* Human-readable name of a status code (static string). */
+const char* ofm_status_string(int status);
+
+/* Library version string (static). */
+const char* ofm_version(void);
+
+/*
+ * Build the shifted normalized Laplacian A = L - 2I = -I - D^{-1/2} S D^{-1/2}
+ * (Introduction, eq. (1); Algorithm 1, step 2) of an undirected graph given as
+ * a CSR similarity matrix S (both directions of every edge stored).
+ *   n, nnz      number of nodes and of stored entries
+ *   row_ptr     int32[n+1], row_ptr[0] = 0, row_ptr[n] = nnz, non-decreasing
+ *   col_idx     int32[nnz], entries in [0, n)
+ *   vals        nullable: NULL means S_ij = 1 for every stored entry;
+ *               otherwise FP64[nnz] weights (must be symmetric)
+ *   flags       OFM_LAP_VALIDATE, OFM_LAP_NO_REORDER
+ * Computes D_ii = sum_j S_ij, D^{-1/2}, ||A||_F^2 and the normalized edge
+ * weights w_ij = D_ii^{-1/2} S_ij D_jj^{-1/2} (FP64 and FP32 copies, laid out
+ * in the row-processing order).  Synchronizing (the checks are read back).
+ * The input arrays are only read during the call.
+ * Errors: OFM_E_GRAPH for a malformed CSR, an out-of-range column, a zero
+ * degree or (when validating) an asymmetric pattern.
+ */
+ofm_status ofm_build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr,
+                               const int32_t* col_idx, const double* vals,
+                               unsigned flags, hipStream_t stream, ofm_laplacian* out);
+
+ofm_status ofm_laplacian_destroy(ofm_laplacian lap);
+
+/* Host copies of the basic graph quantities: n, nnz, ||A||_F^2, and (nullable
+ * outputs) the degrees D_ii as FP64[n] into host_degrees. Synchronizing. */
+ofm_status ofm_laplacian_info(ofm_laplacian lap, int64_t* host_n, int64_t* host_nnz,
+                              double* host_normA2, double* host_degrees);
+
+/*
+ * Y = A Z for an N x k block Z (the sparse-times-tall-skinny product of the
+ * iteration, Section 3.3 eq. spmm with the shift of Algorithm 1).
+ * Z and Y must not overlap.  precision selects FP64 or FP32 storage and
+ * arithmetic as described at ofm_precision.
+ */
+ofm_status ofm_apply_A(ofm_laplacian lap, int k, int precision, const void* Z, void* Y,
+                       hipStream_t stream);
+
+/*
+ * Create the iteration workspace: the direction and CG buffers V, V_prev, G,
+ * G_prev, AX (f2 variants), the k x k FP64 products and the reduction scratch.
+ * Allocates device memory (about (4 + [f2]) N k element slots plus O(k^2)
+ * per block).  host_opts is copied.
+ */
+ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_opts* host_opts,
+                                ofm_workspace* out);
+ofm_status ofm_workspace_destroy(ofm_workspace ws);
+
+/*
+ * Algorithm 2 before its loop: G0 = g(X0), V0 = -G0, step size (exact line
+ * search, or alpha0 when first_step = 1), X1 = X0 + V0 diag(alpha).
+ * X (N x k, in/out) is updated in place.  Resets the iteration counter to 1.
+ */
+ofm_status ofm_init(ofm_workspace ws, void* X, hipStream_t stream);
+
+/*
+ * One loop iteration of Algorithm 2 on X (in/out, N x k):
+ *   G = g(X);  beta_i = sum_r (G - G_prev)_ri G_ri / sum_r G_prev,ri^2
+ *   (beta_i = 0 when the denominator is 0);  V_i = -G_i + beta_i V_prev,i;
+ *   exact line search (Section 3.2): the cubic of eq. f1-derivative /
+ *   f2-derivative (one step for all columns) or of eq. alphai-f1 /
+ *   alphai-f2 (one step per column), real roots by Cardano's formula and
+ *   the root rules of Section 3.2 (the triangular variants take the real root
+ *   of smallest |alpha| when there are three);  X_i += alpha_i V_i.
+ * Every check_every iterations it also computes the residual of X^t (the
+ * iterate entering the step).  Enqueues kernels only: no host
+ * synchronization and no allocation, so the call can be captured in a HIP
+ * graph (once ofm_init has run).
+ */
+ofm_status ofm_step(ofm_workspace ws, void* X, hipStream_t stream);
+
+/*
+ * ofm_init, then ofm_step until the residual <= tol or max_iter updates.
+ * Synchronizing: reads the stats every check_every iterations.
+ */
+ofm_status ofm_solve(ofm_workspace ws, void* X, hipStream_t stream, ofm_stats* host_out);
+
+/* Residual and objective of X now (enqueues the products, then reads back).
+ * Synchronizing. */
+ofm_status ofm_residual(ofm_workspace ws, const void* X, hipStream_t stream, ofm_stats* host_out);
+
+/* Copy of the current stats and device status word. Synchronizing. */
+ofm_status ofm_get_stats(ofm_workspace ws, hipStream_t stream, ofm_stats* host_out);
+
+/*
+ * CG state exchange (checkpoint / resume, and step-by-step comparison).
+ * ofm_get_state copies V^{t-1} and G^{t-1} (N x k each, workspace precision)
+ * into caller buffers.  ofm_set_state loads them from caller buffers, sets the
+ * iteration counter to t (>= 1) and recomputes the products of X the next
+ * step needs; the next ofm_step then continues from (X, V_prev, G_prev).
+ */
+ofm_status ofm_get_state(ofm_workspace ws, void* V_prev, void* G_prev, hipStream_t stream);
+ofm_status ofm_set_state(ofm_workspace ws, const void* X, const void* V_prev,
+                         const void* G_prev, int64_t t, hipStream_t stream);
+
+/*
+ * Scalars of the last step (synchronizing); any host pointer may be NULL.
+ *   host_alpha  double[k] step sizes (all equal for OFM_F1 / OFM_F2)
+ *   host_beta   double[k] CG coefficients (0 for the step before the loop)
+ *   host_coef   double[4*k] cubic coefficients (a3, a2, a1, a0) per column:
+ *               host_coef[4*i + j]; the OFM variants store their single cubic
+ *               in column 0
+ *   host_nroots int32[k] number of real roots found
+ */
+ofm_status ofm_get_step_info(ofm_workspace ws, double* host_alpha, double* host_beta,
+                             double* host_coef, int32_t* host_nroots, hipStream_t stream);
+
+/*
+ * Host copy (synchronizing) of one k x k FP64 product held by the workspace,
+ * row-major into host_kxk[k*k]:
+ *   0: X^T X   1: X^T A X   2: (AX)^T (AX)   3: V^T V   4: X^T V
+ *   5: X^T A V 6: V^T A V
+ * The values are those of the last pass that produced them (X^T X after an
+ * update is that of the new X; X^T A X and (AX)^T (AX) are those of the last
+ * residual evaluation, and X^T A X of the last direction for the f2 variants).
+ */
+ofm_status ofm_get_products(ofm_workspace ws, int which, double* host_kxk, hipStream_t stream);
+
+/*
+ * Per-pass device timing with HIP events recorded on the caller's stream
+ * around every kernel the workspace launches (off by default; recording adds
+ * a few microseconds of host time per launch and nothing on the device).
+ * Pass ids (OFM_PASS_*) index host_ms / host_count:
+ */
+#define OFM_PASS_SPMM_X 0     /* A X with the fused direction epilogue        */
+#define OFM_PASS_G 1          /* direction pass of the f2 variants            */
+#define OFM_PASS_V 2          /* V = -G + V_prev diag(beta) and its products  */
+#define OFM_PASS_SPMM_V 3     /* A V with the line-search products            */
+#define OFM_PASS_LINESEARCH 4 /* cubic coefficients, roots, step sizes        */
+#define OFM_PASS_UPDATE 5     /* X += V diag(alpha) and X^T X                 */
+#define OFM_PASS_REDUCE 6     /* cross-block reductions of the k x k products */
+#define OFM_PASS_RESIDUAL 7   /* residual and objective                       */
+#define OFM_PASS_OTHER 8      /* products of set-up calls                     */
+#define OFM_NUM_PASSES 9
+ofm_status ofm_set_timing(ofm_workspace ws, int enable);
+/* Synchronizing: waits for the recorded events, adds the elapsed times (ms)
+ * and launch counts since the last reset into host_ms[OFM_NUM_PASSES] and
+ * host_count[OFM_NUM_PASSES]; reset != 0 clears the totals afterwards. */
+ofm_status ofm_get_timing(ofm_workspace ws, double* host_ms, int64_t* host_count, int reset);
+
+/*
+ * Algorithm 1, step 4: Y_l = X_l / ||X_l||_2 for every row (a zero row stays
+ * zero).  X and Y are N x k of the given precision; X == Y is allowed.
+ */
+ofm_status ofm_row_normalize(int64_t n, int k, int precision, const void* X, void* Y,
+                             hipStream_t stream);
+
+/*
+ * Algorithm 1, step 5, assignment step of Euclidean K-means:
+ *   labels[l] = argmin_c sum_d (Y_ld - mu_cd)^2, lowest c on ties,
+ *   dist2[l] = that minimum (nullable).
+ * Y FP32 [n x dim], centroids FP32 [n_clusters x dim], dim in [1, 64],
+ * n_clusters in [1, 1024].  Distances are accumulated in FP32.
+ */
+ofm_status ofm_kmeans_assign(int64_t n, int dim, int n_clusters, const float* Y,
+                             const float* centroids, int32_t* labels, float* dist2,
+                             hipStream_t stream);
+
+/*
+ * Euclidean K-means on the rows of Y (FP32 [n x dim]): k-means++ seeding
+ * (Arthur & Vassilvitskii 2007) driven by the caller's uniforms
+ * host_uniforms[0..n_clusters-1] in [0, 1) (centre 0 = point floor(u_0 n);
+ * centre c = first point whose running sum of squared distances to the
+ * nearest chosen centre exceeds u_c times the total), then Lloyd iterations
+ * until no label changes or max_iter; an empty cluster keeps its centroid.
+ * labels int32[n] and centroids FP32[n_clusters x dim] are outputs;
+ * host_iters (nullable) receives the number of Lloyd iterations.
+ * Synchronizing; allocates temporary device memory.
+ */
+ofm_status ofm_kmeans(int64_t n, int dim, int n_clusters, const float* Y,
+                      const double* host_uniforms, int max_iter, int32_t* labels,
+                      float* centroids, int32_t* host_iters, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OFM_H */

@@ -1,0 +1,874 @@
+// C ABI of libofm: argument checking, handles, and the kernel sequence of
+// every call.  See include/ofm.h for the contract of each entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "ofm_internal.hpp"
+
+using namespace ofm;
+
+#define HIPCHK(expr)                                   \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return ofm_from_hip(e_);     \
+  } while (0)
+
+#define OFMCHK(expr)                 \
+  do {                               \
+    ofm_status s_ = (expr);          \
+    if (s_ != OFM_OK) return s_;     \
+  } while (0)
+
+static ofm_status ofm_from_hip(hipError_t e) {
+  if (e == hipErrorOutOfMemory) return OFM_E_NOMEM;
+  return OFM_E_HIP;
+}
+
+namespace {
+
+template <typename T>
+ofm_status dev_alloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? OFM_E_NOMEM : OFM_E_HIP;
+  }
+  return OFM_OK;
+}
+
+template <typename T>
+void dev_free(T*& p) {
+  if (p) (void)hipFree(reinterpret_cast<void*>(p));
+  p = nullptr;
+}
+
+bool supported_k(int k, int precision) {
+  if (precision == OFM_FP64) return k == 4 || k == 8 || k == 16 || k == 32;
+  return k == 4 || k == 8 || k == 16 || k == 32 || k == 64;
+}
+
+int sc_total(int k) {
+  switch (k) {
+    case 4: return SC<4>::TOTAL;
+    case 8: return SC<8>::TOTAL;
+    case 16: return SC<16>::TOTAL;
+    case 32: return SC<32>::TOTAL;
+    case 64: return SC<64>::TOTAL;
+  }
+  return 0;
+}
+
+struct SCOff {
+  int M, H, K, GG, GGP, BETA, ALPHA, COEF, NROOT, RELRES, FVAL;
+};
+
+template <int KP>
+SCOff sc_off_t() {
+  using S = SC<KP>;
+  return SCOff{S::M, S::H, S::K, S::GG, S::GGP, S::BETA, S::ALPHA, S::COEF, S::NROOT, S::RELRES,
+               S::FVAL};
+}
+
+SCOff sc_off(int k) {
+  switch (k) {
+    case 4: return sc_off_t<4>();
+    case 8: return sc_off_t<8>();
+    case 16: return sc_off_t<16>();
+    case 32: return sc_off_t<32>();
+    default: return sc_off_t<64>();
+  }
+}
+
+}  // namespace
+
+struct TileTable {
+  int tr = 0;
+  int32_t* dev = nullptr;
+  int64_t ntiles = 0;
+};
+
+struct ofm_laplacian_s {
+  LaplacianDev g;
+  TileTable tt[3];  // TR = 16, 32, 64
+  std::vector<double> host_deg;
+};
+
+struct ofm_workspace_s {
+  ofm_laplacian lap = nullptr;
+  int k = 0;
+  ofm_opts opts{};
+  int64_t n = 0;
+  size_t esz = 0;
+  void* V[2] = {nullptr, nullptr};
+  void* G[2] = {nullptr, nullptr};
+  void* AX = nullptr;
+  int cur = 0;
+  double* sc = nullptr;
+  double* partials = nullptr;
+  double* lvl2 = nullptr;
+  int* tickets = nullptr;
+  int* status = nullptr;
+  int64_t t = 0;
+  int64_t last_check = -1;
+  bool initialized = false;
+  const TileTable* tiles = nullptr;
+  const void* pk = nullptr;
+  // per-pass event timing
+  bool timing = false;
+  struct Pending {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[OFM_NUM_PASSES] = {0};
+  int64_t count[OFM_NUM_PASSES] = {0};
+};
+
+namespace {
+
+hipEvent_t take_event(ofm_workspace ws) {
+  if (!ws->pool.empty()) {
+    hipEvent_t e = ws->pool.back();
+    ws->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// run one launch, bracketed by events when timing is on
+template <typename F>
+hipError_t timed(ofm_workspace ws, int kind, hipStream_t s, F&& launch) {
+  if (!ws->timing) return launch();
+  hipEvent_t a = take_event(ws), b = take_event(ws);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, s);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, s);
+  if (e != hipSuccess) return e;
+  ws->pending.push_back({kind, a, b});
+  return hipSuccess;
+}
+
+int pass_kind(int mode) {
+  switch (mode) {
+    case kGF1:
+    case kAXF2: return OFM_PASS_SPMM_X;
+    case kGPassF2: return OFM_PASS_G;
+    case kVPass: return OFM_PASS_V;
+    case kAVF1:
+    case kAVF2: return OFM_PASS_SPMM_V;
+    case kUpdate: return OFM_PASS_UPDATE;
+    default: return OFM_PASS_OTHER;
+  }
+}
+
+}  // namespace
+
+static const char* kStatusNames[] = {"OFM_OK",          "OFM_E_INVALID_ARG", "OFM_E_SHAPE",
+                                     "OFM_E_GRAPH",     "OFM_E_NONFINITE",   "OFM_E_NUMERIC",
+                                     "OFM_E_HIP",       "OFM_E_NOMEM",       "OFM_E_UNSUPPORTED"};
+
+extern "C" const char* ofm_status_string(int status) {
+  if (status > 0 || status < -8) return "OFM_E_UNKNOWN";
+  return kStatusNames[-status];
+}
+
+extern "C" const char* ofm_version(void) { return "ofm-gfx950 0.1"; }
+
+// ---------------------------------------------------------------------------
+// Laplacian
+// ---------------------------------------------------------------------------
+
+static void free_lap(ofm_laplacian L) {
+  if (!L) return;
+  dev_free(L->g.deg);
+  dev_free(L->g.dinv);
+  dev_free(L->g.sched);
+  dev_free(L->g.sptr);
+  dev_free(L->g.pk32);
+  dev_free(L->g.pk64);
+  for (auto& t : L->tt) dev_free(t.dev);
+  delete L;
+}
+
+static std::vector<int32_t> build_tiles(const std::vector<int32_t>& sdeg, int tr, bool reorder) {
+  // tiles of consecutive positions: rows of degree >= kHeavyDeg (first when
+  // rows are sorted by degree) form "heavy" tiles of at most tr rows and
+  // kHeavyTileNnz entries, processed one row per wavefront; the rest form
+  // tiles of tr rows.  The heavy flag is the sign bit.
+  std::vector<int32_t> t;
+  const int64_t n = (int64_t)sdeg.size();
+  int64_t p = 0;
+  if (reorder) {
+    while (p < n && sdeg[p] >= kHeavyDeg) {
+      const int64_t st = p;
+      int64_t nz = 0;
+      while (p < n && sdeg[p] >= kHeavyDeg && p - st < tr &&
+             (p == st || nz + sdeg[p] <= kHeavyTileNnz)) {
+        nz += sdeg[p];
+        ++p;
+      }
+      t.push_back((int32_t)st | (int32_t)0x80000000);
+    }
+  }
+  while (p < n) {
+    t.push_back((int32_t)p);
+    p = std::min<int64_t>(n, p + tr);
+  }
+  t.push_back((int32_t)n);
+  return t;
+}
+
+extern "C" ofm_status ofm_build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr,
+                                          const int32_t* col_idx, const double* vals,
+                                          unsigned flags, hipStream_t stream,
+                                          ofm_laplacian* out) {
+  if (!out) return OFM_E_INVALID_ARG;
+  *out = nullptr;
+  if (n <= 0 || nnz < 0 || !row_ptr || (nnz > 0 && !col_idx)) return OFM_E_INVALID_ARG;
+  if (n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 31)) return OFM_E_SHAPE;
+  if (flags & ~(OFM_LAP_VALIDATE | OFM_LAP_NO_REORDER)) return OFM_E_INVALID_ARG;
+  auto* L = new ofm_laplacian_s();
+  LaplacianDev& g = L->g;
+  g.n = n;
+  g.nnz = nnz;
+  g.reorder = !(flags & OFM_LAP_NO_REORDER);
+  (void)hipGetDevice(&g.device);
+  int* dflags = nullptr;
+  double* w64 = nullptr;
+  double* parts = nullptr;
+  const int64_t nb = (n + 255) / 256;
+  ofm_status st = OFM_OK;
+  auto fail = [&](ofm_status s) {
+    dev_free(dflags);
+    dev_free(w64);
+    dev_free(parts);
+    free_lap(L);
+    return s;
+  };
+  if ((st = dev_alloc(&g.deg, n)) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(&g.dinv, n)) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(&dflags, 1)) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(&w64, nnz)) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(&parts, nb)) != OFM_OK) return fail(st);
+  if (hipMemsetAsync(dflags, 0, sizeof(int), stream) != hipSuccess) return fail(OFM_E_HIP);
+  if (launch_graph_check(n, nnz, row_ptr, col_idx, vals, g.deg, dflags, stream) != hipSuccess)
+    return fail(OFM_E_HIP);
+  int hflags = 0;
+  if (hipMemcpyAsync(&hflags, dflags, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return fail(OFM_E_HIP);
+  if (hflags & (1 | 2 | 4 | 32)) return fail(OFM_E_GRAPH);
+  if (flags & OFM_LAP_VALIDATE) {
+    if (launch_graph_symcheck(n, row_ptr, col_idx, vals, dflags, stream) != hipSuccess)
+      return fail(OFM_E_HIP);
+    if (hipMemcpyAsync(&hflags, dflags, sizeof(int), hipMemcpyDeviceToHost, stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return fail(OFM_E_HIP);
+    if (hflags & 16) return fail(OFM_E_GRAPH);
+  }
+  if (launch_graph_weights(n, row_ptr, col_idx, vals, g.deg, g.dinv, w64, parts, stream) !=
+      hipSuccess)
+    return fail(OFM_E_HIP);
+  std::vector<double> hparts(nb);
+  std::vector<int32_t> hrp(n + 1);
+  L->host_deg.resize(n);
+  if (hipMemcpyAsync(hparts.data(), parts, nb * sizeof(double), hipMemcpyDeviceToHost, stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(hrp.data(), row_ptr, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost,
+                     stream) != hipSuccess ||
+      hipMemcpyAsync(L->host_deg.data(), g.deg, n * sizeof(double), hipMemcpyDeviceToHost,
+                     stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return fail(OFM_E_HIP);
+  double na = 0.0;
+  for (double v : hparts) na += v;
+  g.normA2 = na;
+  // row-processing order: by number of entries, descending (stable)
+  std::vector<int32_t> sched(n);
+  std::iota(sched.begin(), sched.end(), 0);
+  if (g.reorder) {
+    std::stable_sort(sched.begin(), sched.end(), [&](int32_t a, int32_t b) {
+      return (hrp[a + 1] - hrp[a]) > (hrp[b + 1] - hrp[b]);
+    });
+  }
+  std::vector<int32_t> sptr(n + 1), sdeg(n);
+  sptr[0] = 0;
+  for (int64_t p = 0; p < n; ++p) {
+    sdeg[p] = hrp[sched[p] + 1] - hrp[sched[p]];
+    sptr[p + 1] = sptr[p] + sdeg[p];
+  }
+  if ((st = dev_alloc(&g.sched, n)) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(&g.sptr, n + 1)) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(reinterpret_cast<int64_t**>(&g.pk32), nnz)) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(reinterpret_cast<double**>(&g.pk64), 2 * nnz)) != OFM_OK) return fail(st);
+  if (hipMemcpyAsync(g.sched, sched.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(g.sptr, sptr.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
+                     stream) != hipSuccess)
+    return fail(OFM_E_HIP);
+  if (launch_graph_pack(n, g.sched, row_ptr, col_idx, w64, g.sptr, g.pk32, g.pk64, stream) !=
+      hipSuccess)
+    return fail(OFM_E_HIP);
+  const int trs[3] = {16, 32, 64};
+  for (int i = 0; i < 3; ++i) {
+    std::vector<int32_t> t = build_tiles(sdeg, trs[i], g.reorder);
+    L->tt[i].tr = trs[i];
+    L->tt[i].ntiles = (int64_t)t.size() - 1;
+    if ((st = dev_alloc(&L->tt[i].dev, t.size())) != OFM_OK) return fail(st);
+    if (hipMemcpyAsync(L->tt[i].dev, t.data(), t.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                       stream) != hipSuccess)
+      return fail(OFM_E_HIP);
+  }
+  if (hipStreamSynchronize(stream) != hipSuccess) return fail(OFM_E_HIP);
+  dev_free(dflags);
+  dev_free(w64);
+  dev_free(parts);
+  *out = L;
+  return OFM_OK;
+}
+
+extern "C" ofm_status ofm_laplacian_destroy(ofm_laplacian lap) {
+  if (!lap) return OFM_E_INVALID_ARG;
+  free_lap(lap);
+  return OFM_OK;
+}
+
+extern "C" ofm_status ofm_laplacian_info(ofm_laplacian lap, int64_t* host_n, int64_t* host_nnz,
+                                         double* host_normA2, double* host_degrees) {
+  if (!lap) return OFM_E_INVALID_ARG;
+  if (host_n) *host_n = lap->g.n;
+  if (host_nnz) *host_nnz = lap->g.nnz;
+  if (host_normA2) *host_normA2 = lap->g.normA2;
+  if (host_degrees)
+    std::memcpy(host_degrees, lap->host_deg.data(), lap->g.n * sizeof(double));
+  return OFM_OK;
+}
+
+static const TileTable* tiles_for(ofm_laplacian lap, int precision, int k) {
+  const int tr = tile_rows(precision, k);
+  for (auto& t : lap->tt)
+    if (t.tr == tr) return &t;
+  return nullptr;
+}
+
+static void fill_graph(PassArgs& a, ofm_laplacian lap, const TileTable* tt, int precision) {
+  a.sched = lap->g.sched;
+  a.sptr = lap->g.sptr;
+  a.tiles = tt->dev;
+  a.ntiles = tt->ntiles;
+  a.pk = precision == OFM_FP64 ? lap->g.pk64 : lap->g.pk32;
+}
+
+extern "C" ofm_status ofm_apply_A(ofm_laplacian lap, int k, int precision, const void* Z, void* Y,
+                                  hipStream_t stream) {
+  if (!lap || !Z || !Y) return OFM_E_INVALID_ARG;
+  if (precision != OFM_FP32 && precision != OFM_FP64) return OFM_E_INVALID_ARG;
+  if (!supported_k(k, precision)) return OFM_E_SHAPE;
+  if (Z == Y) return OFM_E_INVALID_ARG;
+  const TileTable* tt = tiles_for(lap, precision, k);
+  if (!tt) return OFM_E_UNSUPPORTED;
+  PassArgs a;
+  a.n = lap->g.n;
+  a.k = k;
+  a.mode = kApply;
+  a.Z = Z;
+  a.Y = Y;
+  fill_graph(a, lap, tt, precision);
+  a.nblocks = pass_blocks(precision, k, tt->ntiles);
+  HIPCHK(launch_spmm(precision, k, a, stream));
+  return OFM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace and the iteration
+// ---------------------------------------------------------------------------
+
+static void free_ws(ofm_workspace ws) {
+  if (!ws) return;
+  for (auto& p : ws->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : ws->pool) (void)hipEventDestroy(e);
+  for (int i = 0; i < 2; ++i) {
+    dev_free(ws->V[i]);
+    dev_free(ws->G[i]);
+  }
+  dev_free(ws->AX);
+  dev_free(ws->sc);
+  dev_free(ws->partials);
+  dev_free(ws->lvl2);
+  dev_free(ws->tickets);
+  dev_free(ws->status);
+  delete ws;
+}
+
+extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_opts* host_opts,
+                                           ofm_workspace* out) {
+  if (!out) return OFM_E_INVALID_ARG;
+  *out = nullptr;
+  if (!lap || !host_opts) return OFM_E_INVALID_ARG;
+  const ofm_opts& o = *host_opts;
+  if (o.variant < 0 || o.variant > 3) return OFM_E_INVALID_ARG;
+  if (o.precision != OFM_FP32 && o.precision != OFM_FP64) return OFM_E_INVALID_ARG;
+  if (o.max_iter < 1 || o.check_every < 1) return OFM_E_INVALID_ARG;
+  if (o.first_step != 0 && o.first_step != 1) return OFM_E_INVALID_ARG;
+  if (o.restart != 0 && o.restart != 1) return OFM_E_INVALID_ARG;
+  if (!std::isfinite(o.alpha0) || !(o.tol >= 0.0)) return OFM_E_INVALID_ARG;
+  if (!supported_k(k, o.precision)) return o.precision == OFM_FP64 && k == 64 ? OFM_E_UNSUPPORTED
+                                                                              : OFM_E_SHAPE;
+  if (k > lap->g.n) return OFM_E_SHAPE;
+  const TileTable* tt = tiles_for(lap, o.precision, k);
+  if (!tt) return OFM_E_UNSUPPORTED;
+  auto* ws = new ofm_workspace_s();
+  ws->lap = lap;
+  ws->k = k;
+  ws->opts = o;
+  ws->n = lap->g.n;
+  ws->esz = o.precision == OFM_FP64 ? 8 : 4;
+  ws->tiles = tt;
+  ws->pk = o.precision == OFM_FP64 ? lap->g.pk64 : lap->g.pk32;
+  const size_t blk = (size_t)ws->n * k * ws->esz;
+  const int nvmax = 2 * k * k + 3 * k;
+  const int ny = (kMaxBlocks + kFinChunk - 1) / kFinChunk;
+  ofm_status st = OFM_OK;
+  auto fail = [&](ofm_status s) {
+    free_ws(ws);
+    return s;
+  };
+  for (int i = 0; i < 2; ++i) {
+    if ((st = dev_alloc(reinterpret_cast<char**>(&ws->V[i]), blk)) != OFM_OK) return fail(st);
+    if ((st = dev_alloc(reinterpret_cast<char**>(&ws->G[i]), blk)) != OFM_OK) return fail(st);
+  }
+  if ((st = dev_alloc(reinterpret_cast<char**>(&ws->AX), blk)) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(&ws->sc, sc_total(k))) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(&ws->partials, (size_t)kMaxBlocks * nvmax)) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(&ws->lvl2, (size_t)ny * nvmax)) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(&ws->tickets, (nvmax + 63) / 64)) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(&ws->status, 1)) != OFM_OK) return fail(st);
+  if (hipMemset(ws->sc, 0, sc_total(k) * sizeof(double)) != hipSuccess ||
+      hipMemset(ws->tickets, 0, ((nvmax + 63) / 64) * sizeof(int)) != hipSuccess ||
+      hipMemset(ws->status, 0, sizeof(int)) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess)
+    return fail(OFM_E_HIP);
+  *out = ws;
+  return OFM_OK;
+}
+
+extern "C" ofm_status ofm_workspace_destroy(ofm_workspace ws) {
+  if (!ws) return OFM_E_INVALID_ARG;
+  free_ws(ws);
+  return OFM_OK;
+}
+
+static PassArgs base_args(ofm_workspace ws, int mode, int flags) {
+  PassArgs a;
+  a.n = ws->n;
+  a.k = ws->k;
+  a.mode = mode;
+  a.variant = ws->opts.variant;
+  a.flags = flags;
+  a.sc = ws->sc;
+  a.partials = ws->partials;
+  a.status = ws->status;
+  a.nv = partial_nv(ws->k, mode, flags);
+  return a;
+}
+
+static ofm_status finalize(ofm_workspace ws, const PassArgs& a, hipStream_t s) {
+  if (a.nv == 0) return OFM_OK;
+  HIPCHK(timed(ws, OFM_PASS_REDUCE, s, [&] {
+    return launch_finalize(ws->partials, a.nblocks, a.nv, ws->sc + partial_off(ws->k, a.mode),
+                           ws->lvl2, ws->tickets, s);
+  }));
+  return OFM_OK;
+}
+
+static ofm_status run_spmm(ofm_workspace ws, PassArgs& a, hipStream_t s) {
+  fill_graph(a, ws->lap, ws->tiles, ws->opts.precision);
+  a.nblocks = pass_blocks(ws->opts.precision, ws->k, ws->tiles->ntiles);
+  HIPCHK(timed(ws, pass_kind(a.mode), s, [&] { return launch_spmm(ws->opts.precision, ws->k, a, s); }));
+  return finalize(ws, a, s);
+}
+
+static ofm_status run_dense(ofm_workspace ws, PassArgs& a, hipStream_t s) {
+  const int tr = tile_rows(ws->opts.precision, ws->k);
+  a.nblocks = pass_blocks(ws->opts.precision, ws->k, (ws->n + tr - 1) / tr);
+  HIPCHK(timed(ws, pass_kind(a.mode), s, [&] { return launch_dense(ws->opts.precision, ws->k, a, s); }));
+  return finalize(ws, a, s);
+}
+
+static hipError_t run_residual(ofm_workspace ws, hipStream_t s) {
+  return timed(ws, OFM_PASS_RESIDUAL, s, [&] {
+    return launch_residual(ws->k, ws->opts.variant, ws->lap->g.normA2, ws->sc, ws->status, s);
+  });
+}
+
+extern "C" ofm_status ofm_set_timing(ofm_workspace ws, int enable) {
+  if (!ws) return OFM_E_INVALID_ARG;
+  ws->timing = enable != 0;
+  return OFM_OK;
+}
+
+extern "C" ofm_status ofm_get_timing(ofm_workspace ws, double* host_ms, int64_t* host_count,
+                                     int reset) {
+  if (!ws) return OFM_E_INVALID_ARG;
+  for (auto& p : ws->pending) {
+    HIPCHK(hipEventSynchronize(p.b));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+    ws->ms[p.kind] += ms;
+    ws->count[p.kind] += 1;
+    ws->pool.push_back(p.a);
+    ws->pool.push_back(p.b);
+  }
+  ws->pending.clear();
+  for (int i = 0; i < OFM_NUM_PASSES; ++i) {
+    if (host_ms) host_ms[i] = ws->ms[i];
+    if (host_count) host_count[i] = ws->count[i];
+    if (reset) {
+      ws->ms[i] = 0.0;
+      ws->count[i] = 0;
+    }
+  }
+  return OFM_OK;
+}
+
+static bool is_f2(int v) { return v == OFM_F2 || v == OFM_TRI_F2; }
+
+// G = g(X) into G[cur] with the per-column sums; f2 variants go through AX.
+static ofm_status direction(ofm_workspace ws, void* X, const void* Gp, const void* Vp, int check,
+                            hipStream_t s) {
+  const int restart = ws->opts.restart ? kFlagRestart : 0;
+  if (!is_f2(ws->opts.variant)) {
+    PassArgs a = base_args(ws, kGF1, (check ? kFlagCheck : 0) | restart);
+    a.Z = X;
+    a.G = ws->G[ws->cur];
+    a.Gp = Gp;
+    a.Vp = Vp;
+    OFMCHK(run_spmm(ws, a, s));
+    if (check) HIPCHK(run_residual(ws, s));
+  } else {
+    PassArgs a = base_args(ws, kAXF2, check ? kFlagCheck : 0);
+    a.Z = X;
+    a.Y = ws->AX;
+    OFMCHK(run_spmm(ws, a, s));
+    if (check) HIPCHK(run_residual(ws, s));
+    PassArgs b = base_args(ws, kGPassF2, restart);
+    b.X = X;
+    b.AX = ws->AX;
+    b.G = ws->G[ws->cur];
+    b.Gp = Gp;
+    b.Vp = Vp;
+    OFMCHK(run_dense(ws, b, s));
+  }
+  return OFM_OK;
+}
+
+// V pass, SpMM(V), line search and update for direction G[cur]
+static ofm_status search_and_update(ofm_workspace ws, void* X, const void* Vp, bool first,
+                                    hipStream_t s) {
+  const int cur = ws->cur;
+  PassArgs v = base_args(ws, kVPass, (first ? kFlagFirst : 0) | (ws->opts.restart ? kFlagRestart : 0));
+  v.G = ws->G[cur];
+  v.Vp = Vp;
+  v.V = ws->V[cur];
+  v.X = X;
+  OFMCHK(run_dense(ws, v, s));
+  PassArgs w = base_args(ws, is_f2(ws->opts.variant) ? kAVF2 : kAVF1, 0);
+  w.Z = ws->V[cur];
+  w.X = X;
+  OFMCHK(run_spmm(ws, w, s));
+  HIPCHK(timed(ws, OFM_PASS_LINESEARCH, s, [&] {
+    return launch_linesearch(ws->k, ws->opts.variant, first && ws->opts.first_step == 1,
+                             ws->opts.alpha0, ws->sc, ws->status, s);
+  }));
+  PassArgs u = base_args(ws, kUpdate, 0);
+  u.X = X;
+  u.Xw = X;
+  u.V = ws->V[cur];
+  OFMCHK(run_dense(ws, u, s));
+  ws->cur ^= 1;
+  ws->t += 1;
+  return OFM_OK;
+}
+
+static ofm_status gram_m(ofm_workspace ws, const void* X, hipStream_t s) {
+  PassArgs a = base_args(ws, kGramM, 0);
+  a.X = X;
+  return run_dense(ws, a, s);
+}
+
+extern "C" ofm_status ofm_init(ofm_workspace ws, void* X, hipStream_t stream) {
+  if (!ws || !X) return OFM_E_INVALID_ARG;
+  ws->cur = 0;
+  ws->t = 0;
+  ws->last_check = -1;
+  OFMCHK(gram_m(ws, X, stream));
+  OFMCHK(direction(ws, X, nullptr, nullptr, 0, stream));
+  OFMCHK(search_and_update(ws, X, nullptr, true, stream));
+  ws->initialized = true;
+  return OFM_OK;
+}
+
+extern "C" ofm_status ofm_step(ofm_workspace ws, void* X, hipStream_t stream) {
+  if (!ws || !X) return OFM_E_INVALID_ARG;
+  if (!ws->initialized) return OFM_E_INVALID_ARG;
+  const int prev = ws->cur ^ 1;
+  const int check = (ws->t % ws->opts.check_every) == 0;
+  OFMCHK(direction(ws, X, ws->G[prev], ws->V[prev], check, stream));
+  if (check) ws->last_check = ws->t;
+  OFMCHK(search_and_update(ws, X, ws->V[prev], false, stream));
+  return OFM_OK;
+}
+
+static ofm_status read_stats(ofm_workspace ws, hipStream_t stream, ofm_stats* o) {
+  const SCOff so = sc_off(ws->k);
+  double rv[2] = {0.0, 0.0};
+  int st = 0;
+  HIPCHK(hipMemcpyAsync(rv, ws->sc + so.RELRES, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(&st, ws->status, sizeof(int), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  o->iters = ws->t;
+  o->relres = ws->last_check >= 0 ? rv[0] : -1.0;
+  o->objective = rv[1];
+  o->relres_iter = ws->last_check;
+  o->status = (st & kStNonfinite) ? OFM_E_NONFINITE : (st & kStCholesky) ? OFM_E_NUMERIC : OFM_OK;
+  o->converged = (ws->last_check >= 0 && ws->opts.tol > 0.0 && rv[0] <= ws->opts.tol) ? 1 : 0;
+  return OFM_OK;
+}
+
+extern "C" ofm_status ofm_get_stats(ofm_workspace ws, hipStream_t stream, ofm_stats* host_out) {
+  if (!ws || !host_out) return OFM_E_INVALID_ARG;
+  OFMCHK(read_stats(ws, stream, host_out));
+  return (ofm_status)host_out->status;
+}
+
+extern "C" ofm_status ofm_solve(ofm_workspace ws, void* X, hipStream_t stream,
+                                ofm_stats* host_out) {
+  if (!ws || !X) return OFM_E_INVALID_ARG;
+  OFMCHK(ofm_init(ws, X, stream));
+  ofm_stats st{};
+  while (ws->t < ws->opts.max_iter) {
+    const bool will_check = (ws->t % ws->opts.check_every) == 0;
+    OFMCHK(ofm_step(ws, X, stream));
+    if (will_check) {
+      OFMCHK(read_stats(ws, stream, &st));
+      if (st.status != OFM_OK) break;
+      if (st.converged) break;
+    }
+  }
+  OFMCHK(read_stats(ws, stream, &st));
+  if (host_out) *host_out = st;
+  return (ofm_status)st.status;
+}
+
+extern "C" ofm_status ofm_residual(ofm_workspace ws, const void* X, hipStream_t stream,
+                                   ofm_stats* host_out) {
+  if (!ws || !X) return OFM_E_INVALID_ARG;
+  OFMCHK(gram_m(ws, X, stream));
+  PassArgs a = base_args(ws, kAXF2, kFlagCheck);
+  a.Z = X;
+  a.Y = ws->AX;
+  OFMCHK(run_spmm(ws, a, stream));
+  HIPCHK(run_residual(ws, stream));
+  ws->last_check = ws->t;
+  ofm_stats st{};
+  OFMCHK(read_stats(ws, stream, &st));
+  if (host_out) *host_out = st;
+  return (ofm_status)st.status;
+}
+
+extern "C" ofm_status ofm_get_state(ofm_workspace ws, void* V_prev, void* G_prev,
+                                    hipStream_t stream) {
+  if (!ws || !V_prev || !G_prev) return OFM_E_INVALID_ARG;
+  if (!ws->initialized) return OFM_E_INVALID_ARG;
+  const int prev = ws->cur ^ 1;
+  const size_t blk = (size_t)ws->n * ws->k * ws->esz;
+  HIPCHK(hipMemcpyAsync(V_prev, ws->V[prev], blk, hipMemcpyDeviceToDevice, stream));
+  HIPCHK(hipMemcpyAsync(G_prev, ws->G[prev], blk, hipMemcpyDeviceToDevice, stream));
+  return OFM_OK;
+}
+
+extern "C" ofm_status ofm_set_state(ofm_workspace ws, const void* X, const void* V_prev,
+                                    const void* G_prev, int64_t t, hipStream_t stream) {
+  if (!ws || !X || !V_prev || !G_prev || t < 1) return OFM_E_INVALID_ARG;
+  ws->cur = 0;
+  const int prev = 1;
+  const size_t blk = (size_t)ws->n * ws->k * ws->esz;
+  HIPCHK(hipMemcpyAsync(ws->V[prev], V_prev, blk, hipMemcpyDeviceToDevice, stream));
+  HIPCHK(hipMemcpyAsync(ws->G[prev], G_prev, blk, hipMemcpyDeviceToDevice, stream));
+  OFMCHK(gram_m(ws, X, stream));
+  PassArgs a = base_args(ws, kGGP, 0);
+  a.Gp = ws->G[prev];
+  OFMCHK(run_dense(ws, a, stream));
+  ws->t = t;
+  ws->last_check = -1;
+  ws->initialized = true;
+  return OFM_OK;
+}
+
+extern "C" ofm_status ofm_get_step_info(ofm_workspace ws, double* host_alpha, double* host_beta,
+                                        double* host_coef, int32_t* host_nroots,
+                                        hipStream_t stream) {
+  if (!ws) return OFM_E_INVALID_ARG;
+  const SCOff so = sc_off(ws->k);
+  const int k = ws->k;
+  std::vector<double> nr(k);
+  if (host_alpha)
+    HIPCHK(hipMemcpyAsync(host_alpha, ws->sc + so.ALPHA, k * sizeof(double), hipMemcpyDeviceToHost, stream));
+  if (host_beta)
+    HIPCHK(hipMemcpyAsync(host_beta, ws->sc + so.BETA, k * sizeof(double), hipMemcpyDeviceToHost, stream));
+  if (host_coef)
+    HIPCHK(hipMemcpyAsync(host_coef, ws->sc + so.COEF, 4 * k * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(nr.data(), ws->sc + so.NROOT, k * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (host_nroots)
+    for (int i = 0; i < k; ++i) host_nroots[i] = (int32_t)nr[i];
+  return OFM_OK;
+}
+
+template <int KP>
+static int product_off(int which) {
+  using S = SC<KP>;
+  const int offs[7] = {S::M, S::H, S::K, S::P, S::C, S::E, S::F};
+  return offs[which];
+}
+
+extern "C" ofm_status ofm_get_products(ofm_workspace ws, int which, double* host_kxk,
+                                       hipStream_t stream) {
+  if (!ws || !host_kxk || which < 0 || which > 6) return OFM_E_INVALID_ARG;
+  int off = 0;
+  switch (ws->k) {
+    case 4: off = product_off<4>(which); break;
+    case 8: off = product_off<8>(which); break;
+    case 16: off = product_off<16>(which); break;
+    case 32: off = product_off<32>(which); break;
+    default: off = product_off<64>(which); break;
+  }
+  HIPCHK(hipMemcpyAsync(host_kxk, ws->sc + off, (size_t)ws->k * ws->k * sizeof(double),
+                        hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  return OFM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Post-processing
+// ---------------------------------------------------------------------------
+
+extern "C" ofm_status ofm_row_normalize(int64_t n, int k, int precision, const void* X, void* Y,
+                                        hipStream_t stream) {
+  if (n < 0 || k < 1 || k > 64 || !X || !Y) return n < 0 || !X || !Y ? OFM_E_INVALID_ARG : OFM_E_SHAPE;
+  if (precision != OFM_FP32 && precision != OFM_FP64) return OFM_E_INVALID_ARG;
+  if (n == 0) return OFM_OK;
+  HIPCHK(launch_row_normalize(n, k, precision, X, Y, stream));
+  return OFM_OK;
+}
+
+extern "C" ofm_status ofm_kmeans_assign(int64_t n, int dim, int n_clusters, const float* Y,
+                                        const float* centroids, int32_t* labels, float* dist2,
+                                        hipStream_t stream) {
+  if (n < 0 || !Y || !centroids || !labels) return OFM_E_INVALID_ARG;
+  if (dim < 1 || dim > 64 || n_clusters < 1 || n_clusters > 1024) return OFM_E_SHAPE;
+  if (n == 0) return OFM_OK;
+  HIPCHK(launch_kmeans_assign(n, dim, n_clusters, Y, centroids, labels, dist2, stream));
+  return OFM_OK;
+}
+
+extern "C" ofm_status ofm_kmeans(int64_t n, int dim, int n_clusters, const float* Y,
+                                 const double* host_uniforms, int max_iter, int32_t* labels,
+                                 float* centroids, int32_t* host_iters, hipStream_t stream) {
+  if (n <= 0 || !Y || !host_uniforms || !labels || !centroids || max_iter < 1)
+    return OFM_E_INVALID_ARG;
+  if (dim < 1 || dim > 64 || n_clusters < 1 || n_clusters > 1024) return OFM_E_SHAPE;
+  if (n_clusters > n) return OFM_E_SHAPE;
+  for (int c = 0; c < n_clusters; ++c)
+    if (!(host_uniforms[c] >= 0.0 && host_uniforms[c] < 1.0)) return OFM_E_INVALID_ARG;
+  const int nbk = kmeans_blocks(n);
+  const int nbs = 1024;
+  float* d2 = nullptr;
+  int32_t* pick = nullptr;
+  double* sums = nullptr;
+  int32_t* prev = nullptr;
+  double* part = nullptr;
+  float* cnew = nullptr;
+  int* changed = nullptr;
+  ofm_status st = OFM_OK;
+  auto cleanup = [&]() {
+    dev_free(d2);
+    dev_free(pick);
+    dev_free(sums);
+    dev_free(prev);
+    dev_free(part);
+    dev_free(cnew);
+    dev_free(changed);
+  };
+  auto fail = [&](ofm_status s) {
+    cleanup();
+    return s;
+  };
+  if ((st = dev_alloc(&d2, n)) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(&pick, 1)) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(&sums, nbs)) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(&prev, n)) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(&part, (size_t)nbk * n_clusters * (dim + 1))) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(&cnew, (size_t)n_clusters * dim)) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(&changed, 1)) != OFM_OK) return fail(st);
+  // k-means++ seeding
+  int32_t first = (int32_t)std::min<int64_t>((int64_t)(host_uniforms[0] * (double)n), n - 1);
+  if (hipMemcpyAsync(pick, &first, sizeof(int32_t), hipMemcpyHostToDevice, stream) != hipSuccess)
+    return fail(OFM_E_HIP);
+  if (launch_kmeans_copy_centre(dim, Y, pick, centroids, 0, stream) != hipSuccess ||
+      launch_kmeans_mindist(n, dim, Y, centroids, d2, 1, stream) != hipSuccess)
+    return fail(OFM_E_HIP);
+  for (int c = 1; c < n_clusters; ++c) {
+    if (launch_kmeans_pick(n, d2, host_uniforms[c], sums, nbs, pick, stream) != hipSuccess ||
+        launch_kmeans_copy_centre(dim, Y, pick, centroids, c, stream) != hipSuccess ||
+        launch_kmeans_mindist(n, dim, Y, centroids + (size_t)c * dim, d2, 0, stream) != hipSuccess)
+      return fail(OFM_E_HIP);
+  }
+  // Lloyd iterations
+  int it = 0;
+  for (; it < max_iter; ++it) {
+    if (launch_kmeans_assign(n, dim, n_clusters, Y, centroids, labels, nullptr, stream) !=
+        hipSuccess)
+      return fail(OFM_E_HIP);
+    if (it > 0) {
+      int h = 0;
+      if (hipMemsetAsync(changed, 0, sizeof(int), stream) != hipSuccess ||
+          launch_count_changes(n, labels, prev, changed, stream) != hipSuccess ||
+          hipMemcpyAsync(&h, changed, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+          hipStreamSynchronize(stream) != hipSuccess)
+        return fail(OFM_E_HIP);
+      if (h == 0) break;
+    }
+    if (launch_kmeans_centroid_sums(n, dim, n_clusters, Y, labels, part, nbk, stream) !=
+            hipSuccess ||
+        launch_kmeans_centroid_final(dim, n_clusters, part, nbk, centroids, cnew, stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(centroids, cnew, (size_t)n_clusters * dim * sizeof(float),
+                       hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(prev, labels, n * sizeof(int32_t), hipMemcpyDeviceToDevice, stream) !=
+            hipSuccess)
+      return fail(OFM_E_HIP);
+  }
+  if (hipStreamSynchronize(stream) != hipSuccess) return fail(OFM_E_HIP);
+  if (host_iters) *host_iters = it;
+  cleanup();
+  return OFM_OK;
+}

@@ -1,0 +1,179 @@
+// Internal declarations shared by the HIP translation units of libofm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ofm.h"
+
+namespace ofm {
+
+constexpr int kWave = 64;
+constexpr int kHeavyDeg = 64;     // rows of at least this degree use a whole wave
+constexpr int kHeavyTileNnz = 1024;
+constexpr int kMaxBlocks = 1024;  // persistent grid cap for reduction kernels
+constexpr int kFinChunk = 32;     // partial rows summed per first-level finalize block
+
+// Row-major N x KP tile geometry of a wave: each row is KP*sizeof(T) bytes,
+// read as 16-byte vectors by LPR consecutive lanes; a wave handles RPW rows
+// per pass and TR rows per tile (TR >= 16 for the 16-row MFMA sub-tiles).
+template <typename T, int KP>
+struct Geo {
+  static constexpr int VECN = 16 / (int)sizeof(T);
+  static constexpr int LPR = KP / VECN;
+  static constexpr int RPW = kWave / LPR;
+  static constexpr int TR = RPW > 16 ? RPW : 16;
+  static constexpr int NPASS = TR / RPW;
+  static constexpr int NSUB = TR / 16;
+  static constexpr int LDST = KP + 1;           // LDS row stride, in elements
+  static constexpr int NT = KP >= 16 ? KP / 16 : 1;
+  static constexpr int KSTEP = KP / 4;          // k-steps of a 16x16x4 product
+  static constexpr int TILE_ELEMS = TR * LDST;
+  static constexpr int FRAG_ELEMS = KSTEP * NT * kWave;
+  static_assert(KP * (int)sizeof(T) >= 16, "row narrower than one vector");
+};
+
+// Layout of the FP64 scalar block (k x k products, per-column sums, step
+// scalars).  Groups written by one producer are contiguous so that one
+// finalize reduces them in a single pass.
+template <int KP>
+struct SC {
+  static constexpr int KK = KP * KP;
+  static constexpr int M = 0;                 // X^T X
+  static constexpr int GG = M + KK;           // diag G^T G
+  static constexpr int GPG = GG + KP;         // diag G_prev^T G
+  static constexpr int VPG = GPG + KP;        // diag V_prev^T G
+  static constexpr int H = VPG + KP;          // X^T A X
+  static constexpr int K = H + KK;            // (AX)^T (AX)
+  static constexpr int P = K + KK;            // V^T V
+  static constexpr int C = P + KK;            // X^T V
+  static constexpr int VG = C + KK;           // diag V^T G
+  static constexpr int FD = VG + KP;          // diag V^T A V
+  static constexpr int E = FD + KP;           // X^T A V
+  static constexpr int F = E + KK;            // V^T A V
+  static constexpr int GGP = F + KK;          // diag G_prev^T G_prev
+  static constexpr int BETA = GGP + KP;
+  static constexpr int ALPHA = BETA + KP;
+  static constexpr int COEF = ALPHA + KP;     // 4 * KP: coef[4 i + j] = a_{3-j}
+  static constexpr int NROOT = COEF + 4 * KP;
+  static constexpr int RELRES = NROOT + KP;
+  static constexpr int FVAL = RELRES + 1;
+  static constexpr int TOTAL = FVAL + 1;
+};
+
+// Device status bits (OR-ed by kernels, mapped to ofm_status on the host).
+enum : int { kStNonfinite = 1, kStCholesky = 2 };
+
+// Epilogue / pass modes.
+enum Mode : int {
+  kApply = 0,     // Y = A Z
+  kGF1 = 1,       // G = c (AX + X M'), gg, gpg [, vpg] [, H, K]
+  kAXF2 = 2,      // store AX, H [, K]
+  kAVF1 = 3,      // diag V^T A V
+  kAVF2 = 4,      // diag V^T A V, X^T A V, V^T A V
+  kGPassF2 = 5,   // G = a AX - b (X H' + AX M'), gg, gpg [, vpg]
+  kVPass = 6,     // V = -G + beta V_prev, V^T V, X^T V, diag V^T G
+  kUpdate = 7,    // X += alpha V, X^T X
+  kGramM = 8,     // X^T X
+  kGGP = 9        // diag G_prev^T G_prev
+};
+
+struct LaplacianDev {
+  int64_t n = 0, nnz = 0;
+  int device = 0;
+  double normA2 = 0.0;
+  double* deg = nullptr;       // [n]
+  double* dinv = nullptr;      // [n]
+  int32_t* sched = nullptr;    // [n] processing position -> row
+  int32_t* sptr = nullptr;     // [n+1] entry offsets by position
+  int32_t* tiles = nullptr;    // [ntiles+1] first position of every tile
+  int64_t ntiles = 0;
+  int tile_rows = 0;           // TR the tile table was built for
+  int tile_kind = -1;          // (precision, k) pair the tiles were built for
+  void* pk32 = nullptr;        // [nnz] {int col, float w} in position order
+  void* pk64 = nullptr;        // [nnz] {int col, int pad, double w}
+  int32_t* row_ptr = nullptr;  // [n+1] own copy of the input CSR
+  int32_t* col_idx = nullptr;  // [nnz]
+  double* w64_csr = nullptr;   // [nnz] w_ij in input CSR order
+  bool reorder = true;
+};
+
+// Arguments of the N x k kernels (everything a mode may need).
+struct PassArgs {
+  int64_t n = 0;
+  int k = 0;
+  int mode = 0;
+  int variant = 0;
+  int flags = 0;          // kFlagCheck, kFlagRestart, kFlagFirst
+  const void* Z = nullptr;     // SpMM input (X or V)
+  void* Y = nullptr;           // SpMM plain output (Y or AX)
+  const void* X = nullptr;     // own X rows
+  void* Xw = nullptr;          // X written by the update pass
+  const void* AX = nullptr;
+  void* G = nullptr;           // current direction (written or read)
+  const void* Gp = nullptr;    // previous direction
+  const void* Vp = nullptr;    // previous search direction
+  void* V = nullptr;           // current search direction
+  double* sc = nullptr;        // scalar block
+  double* partials = nullptr;  // [blocks][nv]
+  int nv = 0;
+  int nblocks = 0;
+  int* status = nullptr;
+  // graph (SpMM only)
+  const int32_t* sched = nullptr;
+  const int32_t* sptr = nullptr;
+  const int32_t* tiles = nullptr;
+  int64_t ntiles = 0;
+  const void* pk = nullptr;
+};
+
+enum : int { kFlagCheck = 1, kFlagRestart = 2, kFlagFirst = 4 };
+
+// Launchers (ofm_kernels.hip).  Each returns a hipError_t.
+hipError_t launch_spmm(int precision, int k, PassArgs& a, hipStream_t s);
+hipError_t launch_dense(int precision, int k, PassArgs& a, hipStream_t s);
+hipError_t launch_finalize(const double* partials, int nb, int nv, double* out, double* lvl2,
+                           int* tickets, hipStream_t s);
+hipError_t launch_linesearch(int k, int variant, int first, double alpha0, double* sc,
+                             int* status, hipStream_t s);
+hipError_t launch_residual(int k, int variant, double normA2, double* sc, int* status,
+                           hipStream_t s);
+int tile_rows(int precision, int k);
+int pass_blocks(int precision, int k, int64_t ntiles);
+int partial_nv(int k, int mode, int flags);
+int partial_off(int k, int mode);
+
+// Graph build (ofm_graph.hip)
+hipError_t launch_graph_check(int64_t n, int64_t nnz, const int32_t* row_ptr,
+                              const int32_t* col_idx, const double* vals, double* deg,
+                              int* flags, hipStream_t s);
+hipError_t launch_graph_symcheck(int64_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                                 const double* vals, int* flags, hipStream_t s);
+hipError_t launch_graph_weights(int64_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                                const double* vals, const double* deg, double* dinv,
+                                double* w64, double* normA2_parts, hipStream_t s);
+hipError_t launch_graph_pack(int64_t n, const int32_t* sched, const int32_t* row_ptr,
+                             const int32_t* col_idx, const double* w64, const int32_t* sptr,
+                             void* pk32, void* pk64, hipStream_t s);
+
+// Post-processing (ofm_post.hip)
+hipError_t launch_row_normalize(int64_t n, int k, int precision, const void* X, void* Y,
+                                hipStream_t s);
+hipError_t launch_kmeans_assign(int64_t n, int dim, int nc, const float* Y, const float* C,
+                                int32_t* labels, float* dist2, hipStream_t s);
+hipError_t launch_kmeans_centroid_sums(int64_t n, int dim, int nc, const float* Y,
+                                       const int32_t* labels, double* part, int nb,
+                                       hipStream_t s);
+hipError_t launch_kmeans_centroid_final(int dim, int nc, const double* part, int nb,
+                                        const float* old_c, float* new_c, hipStream_t s);
+hipError_t launch_kmeans_mindist(int64_t n, int dim, const float* Y, const float* centre,
+                                 float* d2, int first, hipStream_t s);
+hipError_t launch_kmeans_pick(int64_t n, const float* d2, double u, double* blocksums,
+                              int nb, int32_t* pick, hipStream_t s);
+hipError_t launch_kmeans_copy_centre(int dim, const float* Y, const int32_t* pick,
+                                     float* C, int c, hipStream_t s);
+hipError_t launch_count_changes(int64_t n, const int32_t* a, const int32_t* b, int* out,
+                                hipStream_t s);
+int kmeans_blocks(int64_t n);
+
+}  // namespace ofm

@@ -1,0 +1,1418 @@
+// Kernels of the orthogonalization-free iteration on gfx950.
+//
+// One iteration of Algorithm 2 (Pang & Yang, arXiv 2305.10356) is a short
+// sequence of N x k passes, each ending in a deterministic reduction of
+// FP64 k x k products:
+//   SpMM(X) with a fused epilogue   -> G (f1 variants) or AX (f2 variants)
+//   [G pass for the f2 variants]
+//   V pass: V = -G + beta V_prev,  V^T V, X^T V, diag V^T G
+//   SpMM(V) with a fused epilogue    -> diag V^T A V [, X^T A V, V^T A V]
+//   line search (one workgroup, FP64)
+//   update: X += V diag(alpha),  X^T X
+// Rows are tiled 16 at a time per wavefront; row vectors move as 16-byte
+// loads by LPR consecutive lanes; the k x k products run on the matrix
+// cores (v_mfma 16x16x4, FP64 for Grams, the working precision for
+// X * (k x k)) from LDS-staged tiles.
+#include <float.h>
+#include <math.h>
+
+#include "ofm_internal.hpp"
+
+namespace ofm {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MF;
+// Output layout of the 16x16x4 products (inputs: A[i][k] in lane i + 16k,
+// B[k][j] in lane j + 16k): D[i][j] sits in lane j + 16 (i / 4), register
+// i % 4 for the FP32 instruction and in lane j + 16 (i % 4), register i / 4
+// for the FP64 one.  out_row gives i for (lane, register).
+template <>
+struct MF<float> {
+  typedef f4 acc_t;
+  __device__ static inline int out_row(int lane, int q) { return 4 * (lane >> 4) + q; }
+  __device__ static inline acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct MF<double> {
+  typedef d4 acc_t;
+  __device__ static inline int out_row(int lane, int q) { return 4 * q + (lane >> 4); }
+  __device__ static inline acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename T, int KP>
+using GramAcc = d4[Geo<T, KP>::NT][Geo<T, KP>::NT];
+template <typename T, int KP>
+using ColAcc = double[3][Geo<T, KP>::VECN];
+
+__device__ inline d4 mma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+struct V16 {
+  T v[16 / sizeof(T)];
+};
+
+template <typename T>
+__device__ inline V16<T> ld16(const T* p) {
+  V16<T> r;
+  *reinterpret_cast<uint4*>(&r) = *reinterpret_cast<const uint4*>(p);
+  return r;
+}
+template <typename T>
+__device__ inline void st16(T* p, const V16<T>& r) {
+  *reinterpret_cast<uint4*>(p) = *reinterpret_cast<const uint4*>(&r);
+}
+
+struct __align__(8) Ent32 {
+  int col;
+  float w;
+};
+struct __align__(16) Ent64 {
+  int col;
+  int pad;
+  double w;
+};
+template <typename T>
+struct EntT;
+template <>
+struct EntT<float> {
+  typedef Ent32 type;
+};
+template <>
+struct EntT<double> {
+  typedef Ent64 type;
+};
+
+// waves per block: keep the dynamic LDS of a block under 60 KiB
+template <typename T, int KP>
+struct Cfg {
+  static constexpr int TB = Geo<T, KP>::TILE_ELEMS * (int)sizeof(T);
+  static constexpr int FB = Geo<T, KP>::FRAG_ELEMS * (int)sizeof(T);
+  static constexpr int per_wave = 3 * TB + Geo<T, KP>::TR * 4;
+  static constexpr int WPB = (2 * FB + 4 * per_wave <= 60 * 1024)   ? 4
+                             : (2 * FB + 2 * per_wave <= 60 * 1024) ? 2
+                                                                    : 1;
+};
+
+constexpr int nbuf_of(int mode) {
+  return mode == kGF1 ? 3
+         : mode == kAXF2 ? 2
+         : mode == kAVF2 ? 3
+         : mode == kGPassF2 ? 3
+         : mode == kVPass ? 2
+         : (mode == kUpdate || mode == kGramM) ? 1
+                                                : 0;
+}
+constexpr int nfrag_of(int mode) { return mode == kGF1 ? 1 : mode == kGPassF2 ? 2 : 0; }
+constexpr int nvec_of(int mode) {
+  return (mode == kGF1 || mode == kGPassF2) ? 3
+         : (mode == kVPass || mode == kAVF1 || mode == kAVF2 || mode == kGGP) ? 1
+                                                                               : 0;
+}
+
+template <typename T, int KP, int MODE>
+struct Smem {
+  using G = Geo<T, KP>;
+  static constexpr int WPB = Cfg<T, KP>::WPB;
+  static constexpr int NB = nbuf_of(MODE);
+  static constexpr int frag_bytes = nfrag_of(MODE) * G::FRAG_ELEMS * (int)sizeof(T);
+  static constexpr int wave_bytes = NB * G::TILE_ELEMS * (int)sizeof(T) + G::TR * 4;
+  static constexpr int main_bytes = frag_bytes + WPB * wave_bytes;
+  static constexpr int red_bytes = (KP * KP > 3 * KP ? KP * KP : 3 * KP) * 8;
+  static constexpr int bytes = main_bytes > red_bytes ? main_bytes : red_bytes;
+};
+
+// ---------------------------------------------------------------------------
+// partial-row layout of every mode (relative to the first SC slot it fills)
+// ---------------------------------------------------------------------------
+
+template <int KP>
+__host__ __device__ inline int mode_nv(int mode, int flags) {
+  const int KK = KP * KP;
+  switch (mode) {
+    case kGF1: return 3 * KP + ((flags & kFlagCheck) ? 2 * KK : 0);
+    case kAXF2: return KK + ((flags & kFlagCheck) ? KK : 0);
+    case kAVF1: return KP;
+    case kAVF2: return KP + 2 * KK;
+    case kGPassF2: return 3 * KP;
+    case kVPass: return 2 * KK + KP;
+    case kUpdate:
+    case kGramM: return KK;
+    case kGGP: return KP;
+    default: return 0;
+  }
+}
+template <int KP>
+__host__ __device__ inline int mode_off(int mode) {
+  switch (mode) {
+    case kGF1:
+    case kGPassF2: return SC<KP>::GG;
+    case kAXF2: return SC<KP>::H;
+    case kAVF1:
+    case kAVF2: return SC<KP>::FD;
+    case kVPass: return SC<KP>::P;
+    case kUpdate:
+    case kGramM: return SC<KP>::M;
+    case kGGP: return SC<KP>::GGP;
+    default: return 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// wavefront building blocks
+// ---------------------------------------------------------------------------
+
+// Sum of S_ij-weighted rows Z_j over entries [e_first, end) taken in chunks;
+// the LPR lanes of a group share every entry through lane shuffles.
+template <typename T, int KP>
+__device__ inline void gather_rows(const typename EntT<T>::type* __restrict__ pk,
+                                   const T* __restrict__ Z, int e_first, int end, int cstride,
+                                   int gbase, int j, V16<T>& acc) {
+  using G = Geo<T, KP>;
+  constexpr int CH = G::LPR >= 8 ? G::LPR : 8;
+  constexpr int PER = CH / G::LPR;
+  for (int e0 = e_first; e0 < end; e0 += cstride) {
+    int col[PER];
+    T w[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = e0 + u * G::LPR + j;
+      if (e < end) {
+        const auto en = pk[e];
+        col[u] = en.col;
+        w[u] = en.w;
+      } else {
+        col[u] = 0;
+        w[u] = T(0);
+      }
+    }
+    V16<T> z[CH];
+#pragma unroll
+    for (int s = 0; s < CH; ++s) {
+      const int src = gbase + (s % G::LPR);
+      const int c = __shfl(col[s / G::LPR], src);
+      if (e0 + s < end) {
+        z[s] = ld16(Z + (size_t)c * KP + j * G::VECN);
+      } else {
+#pragma unroll
+        for (int q = 0; q < G::VECN; ++q) z[s].v[q] = T(0);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < CH; ++s) {
+      const int src = gbase + (s % G::LPR);
+      const T ww = __shfl(w[s / G::LPR], src);
+#pragma unroll
+      for (int q = 0; q < G::VECN; ++q) acc.v[q] = fma(ww, z[s].v[q], acc.v[q]);
+    }
+  }
+}
+
+template <typename T, int KP>
+__device__ inline void tile_store_vec(T* tile, int r, int j, const V16<T>& x) {
+  using G = Geo<T, KP>;
+#pragma unroll
+  for (int q = 0; q < G::VECN; ++q) tile[r * G::LDST + j * G::VECN + q] = x.v[q];
+}
+template <typename T, int KP>
+__device__ inline V16<T> tile_load_vec(const T* tile, int r, int j) {
+  using G = Geo<T, KP>;
+  V16<T> x;
+#pragma unroll
+  for (int q = 0; q < G::VECN; ++q) x.v[q] = tile[r * G::LDST + j * G::VECN + q];
+  return x;
+}
+template <typename T, int KP>
+__device__ inline void tile_zero_rows(T* tile, int from, int lane) {
+  using G = Geo<T, KP>;
+  for (int e = from * G::LDST + lane; e < G::TR * G::LDST; e += kWave) tile[e] = T(0);
+}
+
+// B operand fragments of a k x k matrix (FP64 source) for X * B:
+// frag[(s*NT + tj)*64 + l] = B[4s + l/16][16 tj + l%16]; tri keeps the upper
+// triangle (including the diagonal) only.
+template <typename T, int KP>
+__device__ inline void load_frags(T* frag, const double* B, bool tri) {
+  using G = Geo<T, KP>;
+  for (int e = threadIdx.x; e < G::FRAG_ELEMS; e += blockDim.x) {
+    const int l = e & 63;
+    const int st = e >> 6;
+    const int tj = st % G::NT;
+    const int s = st / G::NT;
+    const int row = 4 * s + l / 16;
+    const int col = 16 * tj + (l & 15);
+    double v = 0.0;
+    if (col < KP && (!tri || row <= col)) v = B[row * KP + col];
+    frag[e] = (T)v;
+  }
+}
+
+// out tile (C layout -> LDS) += In(16-row sub-tile) * B for every sub-tile.
+template <typename T, int KP>
+__device__ inline void tile_times_matrix(const T* in, const T* frag, T* out, int lane,
+                                         bool accumulate_from_out) {
+  using G = Geo<T, KP>;
+  using acc_t = typename MF<T>::acc_t;
+#pragma unroll
+  for (int sub = 0; sub < G::NSUB; ++sub) {
+    acc_t acc[G::NT];
+#pragma unroll
+    for (int tj = 0; tj < G::NT; ++tj) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = sub * 16 + MF<T>::out_row(lane, q);
+        const int c = 16 * tj + (lane & 15);
+        acc[tj][q] = (accumulate_from_out && c < KP) ? out[r * G::LDST + c] : T(0);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < G::KSTEP; ++s) {
+      const T av = in[(sub * 16 + (lane & 15)) * G::LDST + 4 * s + (lane >> 4)];
+#pragma unroll
+      for (int tj = 0; tj < G::NT; ++tj)
+        acc[tj] = MF<T>::mma(av, frag[(s * G::NT + tj) * 64 + lane], acc[tj]);
+    }
+#pragma unroll
+    for (int tj = 0; tj < G::NT; ++tj) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = sub * 16 + MF<T>::out_row(lane, q);
+        const int c = 16 * tj + (lane & 15);
+        if (c < KP) out[r * G::LDST + c] = acc[tj][q];
+      }
+    }
+  }
+}
+
+// FP64 Gram accumulation acc[ti][tj] += P^T Q over the TR rows of two tiles.
+template <typename T, int KP, bool SYM>
+__device__ inline void tile_gram(const T* Pt, const T* Qt, GramAcc<T, KP>& acc,
+                                 int lane) {
+  using G = Geo<T, KP>;
+  const int f = lane & 15;
+#pragma unroll
+  for (int sub = 0; sub < G::NSUB; ++sub) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int r = sub * 16 + 4 * s + (lane >> 4);
+      double a[G::NT], b[G::NT];
+#pragma unroll
+      for (int t = 0; t < G::NT; ++t) {
+        const int c = 16 * t + f;
+        a[t] = (c < KP) ? (double)Pt[r * G::LDST + c] : 0.0;
+        b[t] = (c < KP) ? (double)Qt[r * G::LDST + c] : 0.0;
+      }
+#pragma unroll
+      for (int ti = 0; ti < G::NT; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < G::NT; ++tj)
+          if (!SYM || tj >= ti) acc[ti][tj] = mma64(a[ti], b[tj], acc[ti][tj]);
+    }
+  }
+}
+
+template <typename T, int KP>
+__device__ inline void zero_gram(GramAcc<T, KP>& acc) {
+  using G = Geo<T, KP>;
+#pragma unroll
+  for (int ti = 0; ti < G::NT; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < G::NT; ++tj) acc[ti][tj] = d4{0.0, 0.0, 0.0, 0.0};
+}
+
+// Deterministic block reduction of a Gram (waves in order) into LDS red,
+// then the block writes it to its partial row at offset off.
+template <typename T, int KP, bool SYM>
+__device__ inline void block_gram_out(GramAcc<T, KP>& acc, double* red,
+                                      double* prow, int off, int wave, int lane, int nwaves) {
+  using G = Geo<T, KP>;
+  for (int w = 0; w < nwaves; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int ti = 0; ti < G::NT; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < G::NT; ++tj) {
+          if (SYM && tj < ti) continue;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int ra = 16 * ti + MF<double>::out_row(lane, q);
+            const int cb = 16 * tj + (lane & 15);
+            if (ra < KP && cb < KP) {
+              const double v = acc[ti][tj][q];
+              if (w == 0) red[ra * KP + cb] = v;
+              else red[ra * KP + cb] += v;
+              if (SYM && tj > ti) {
+                if (w == 0) red[cb * KP + ra] = v;
+                else red[cb * KP + ra] += v;
+              }
+            }
+          }
+        }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < KP * KP; e += blockDim.x) prow[off + e] = red[e];
+  __syncthreads();
+}
+
+// per-column sums held in row layout (lane j of every group holds columns
+// j*VECN..): reduce over the groups of the wave, then over the waves.
+template <typename T, int KP, int NV>
+__device__ inline void block_vec_out(ColAcc<T, KP>& cacc,
+                                     double* red, double* prow, int off, int wave, int lane,
+                                     int nwaves) {
+  using G = Geo<T, KP>;
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int q = 0; q < G::VECN; ++q) {
+      double x = cacc[v][q];
+#pragma unroll
+      for (int o = G::LPR; o < kWave; o <<= 1) x += __shfl_xor(x, o);
+      cacc[v][q] = x;
+    }
+  const int j = lane % G::LPR;
+  for (int w = 0; w < nwaves; ++w) {
+    if (wave == w && lane < G::LPR) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int q = 0; q < G::VECN; ++q) {
+          const int c = v * KP + j * G::VECN + q;
+          if (w == 0) red[c] = cacc[v][q];
+          else red[c] += cacc[v][q];
+        }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < NV * KP; e += blockDim.x) prow[off + e] = red[e];
+  __syncthreads();
+}
+
+template <typename T>
+__device__ inline bool all_finite(T x) {
+  return isfinite((double)x);
+}
+
+// ---------------------------------------------------------------------------
+// SpMM with fused epilogues:  A Z = -Z - D^{-1/2} S D^{-1/2} Z
+// ---------------------------------------------------------------------------
+
+template <typename T, int KP, int MODE>
+__global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
+    spmm_kernel(PassArgs a) {
+  using G = Geo<T, KP>;
+  using SM = Smem<T, KP, MODE>;
+  constexpr int WPB = SM::WPB;
+  constexpr int NV = nvec_of(MODE);
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* frag = reinterpret_cast<T*>(smem);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  unsigned char* wbase = smem + SM::frag_bytes + wave * SM::wave_bytes;
+  T* tA = reinterpret_cast<T*>(wbase);                                   // A Z rows
+  T* tZ = tA + G::TILE_ELEMS;                                            // own Z rows
+  T* tD = tZ + G::TILE_ELEMS;                                            // third tile
+  int* trow = reinterpret_cast<int*>(wbase + SM::NB * G::TILE_ELEMS * sizeof(T));
+
+  const bool check = (a.flags & kFlagCheck) != 0;
+  const bool restart = (a.flags & kFlagRestart) != 0;
+  const T* __restrict__ Z = static_cast<const T*>(a.Z);
+  const auto* __restrict__ pk = static_cast<const typename EntT<T>::type*>(a.pk);
+  const int g = lane / G::LPR;
+  const int j = lane % G::LPR;
+  const double* sc = a.sc;
+
+  T cf = T(1);
+  if (MODE == kGF1) {
+    load_frags<T, KP>(frag, sc + SC<KP>::M, a.variant == OFM_TRI_F1);
+    cf = (a.variant == OFM_F1) ? T(4) : T(1);
+    __syncthreads();
+  }
+
+  double cacc[3][G::VECN];
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int q = 0; q < G::VECN; ++q) cacc[v][q] = 0.0;
+  d4 gA[G::NT][G::NT], gB[G::NT][G::NT];
+  zero_gram<T, KP>(gA);
+  zero_gram<T, KP>(gB);
+
+  const int64_t stride = (int64_t)gridDim.x * WPB;
+  for (int64_t t = (int64_t)blockIdx.x * WPB + wave; t < a.ntiles; t += stride) {
+    const int tinfo = a.tiles[t];
+    const int start = tinfo & 0x7fffffff;
+    const bool heavy = tinfo < 0;
+    const int cnt = (a.tiles[t + 1] & 0x7fffffff) - start;
+
+    if (!heavy) {
+#pragma unroll
+      for (int pass = 0; pass < G::NPASS; ++pass) {
+        const int gi = pass * G::RPW + g;
+        if (gi < cnt) {
+          const int p = start + gi;
+          const int beg = a.sptr[p], end = a.sptr[p + 1];
+          const int row = a.sched[p];
+          V16<T> acc;
+#pragma unroll
+          for (int q = 0; q < G::VECN; ++q) acc.v[q] = T(0);
+          gather_rows<T, KP>(pk, Z, beg, end, G::LPR >= 8 ? G::LPR : 8, g * G::LPR, j, acc);
+          const V16<T> z = ld16(Z + (size_t)row * KP + j * G::VECN);
+#pragma unroll
+          for (int q = 0; q < G::VECN; ++q) acc.v[q] = -z.v[q] - acc.v[q];
+          if (j == 0) trow[gi] = row;
+          if (MODE == kApply || MODE == kAXF2) {
+            st16(static_cast<T*>(a.Y) + (size_t)row * KP + j * G::VECN, acc);
+          }
+          if (MODE == kAVF1 || MODE == kAVF2) {
+#pragma unroll
+            for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)z.v[q] * (double)acc.v[q];
+          }
+          if (SM::NB > 0) {
+            tile_store_vec<T, KP>(tA, gi, j, acc);
+            tile_store_vec<T, KP>(tZ, gi, j, z);
+          }
+        }
+      }
+    } else {
+      for (int gi = 0; gi < cnt; ++gi) {
+        const int p = start + gi;
+        const int beg = a.sptr[p], end = a.sptr[p + 1];
+        const int row = a.sched[p];
+        constexpr int CH = G::LPR >= 8 ? G::LPR : 8;
+        V16<T> acc;
+#pragma unroll
+        for (int q = 0; q < G::VECN; ++q) acc.v[q] = T(0);
+        gather_rows<T, KP>(pk, Z, beg + g * CH, end, G::RPW * CH, g * G::LPR, j, acc);
+#pragma unroll
+        for (int q = 0; q < G::VECN; ++q) {
+#pragma unroll
+          for (int o = G::LPR; o < kWave; o <<= 1) acc.v[q] += __shfl_xor(acc.v[q], o);
+        }
+        if (g == 0) {
+          const V16<T> z = ld16(Z + (size_t)row * KP + j * G::VECN);
+#pragma unroll
+          for (int q = 0; q < G::VECN; ++q) acc.v[q] = -z.v[q] - acc.v[q];
+          if (j == 0) trow[gi] = row;
+          if (MODE == kApply || MODE == kAXF2) {
+            st16(static_cast<T*>(a.Y) + (size_t)row * KP + j * G::VECN, acc);
+          }
+          if (MODE == kAVF1 || MODE == kAVF2) {
+#pragma unroll
+            for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)z.v[q] * (double)acc.v[q];
+          }
+          if (SM::NB > 0) {
+            tile_store_vec<T, KP>(tA, gi, j, acc);
+            tile_store_vec<T, KP>(tZ, gi, j, z);
+          }
+        }
+      }
+    }
+    if (SM::NB == 0) continue;
+    // rows beyond cnt are zero so that they add nothing to the products
+    if (cnt < G::TR) {
+      tile_zero_rows<T, KP>(tA, cnt, lane);
+      tile_zero_rows<T, KP>(tZ, cnt, lane);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+
+    if (MODE == kGF1) {
+      // D = X M' ; G = c (AX + D); per-column sums of G*G, G_prev*G, V_prev*G
+      tile_times_matrix<T, KP>(tZ, frag, tD, lane, false);
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+#pragma unroll
+      for (int pass = 0; pass < G::NPASS; ++pass) {
+        const int gi = pass * G::RPW + g;
+        if (gi < cnt) {
+          const int row = trow[gi];
+          const V16<T> ax = tile_load_vec<T, KP>(tA, gi, j);
+          const V16<T> d = tile_load_vec<T, KP>(tD, gi, j);
+          V16<T> gv;
+#pragma unroll
+          for (int q = 0; q < G::VECN; ++q) gv.v[q] = cf * (ax.v[q] + d.v[q]);
+          const size_t off = (size_t)row * KP + j * G::VECN;
+          st16(static_cast<T*>(a.G) + off, gv);
+#pragma unroll
+          for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)gv.v[q] * (double)gv.v[q];
+          if (a.Gp) {
+            const V16<T> gp = ld16(static_cast<const T*>(a.Gp) + off);
+#pragma unroll
+            for (int q = 0; q < G::VECN; ++q) cacc[1][q] += (double)gp.v[q] * (double)gv.v[q];
+          }
+          if (restart && a.Vp) {
+            const V16<T> vp = ld16(static_cast<const T*>(a.Vp) + off);
+#pragma unroll
+            for (int q = 0; q < G::VECN; ++q) cacc[2][q] += (double)vp.v[q] * (double)gv.v[q];
+          }
+        }
+      }
+      if (check) {
+        tile_gram<T, KP, false>(tZ, tA, gA, lane);  // H = X^T (AX)
+        tile_gram<T, KP, true>(tA, tA, gB, lane);   // K = (AX)^T (AX)
+      }
+    } else if (MODE == kAXF2) {
+      tile_gram<T, KP, false>(tZ, tA, gA, lane);
+      if (check) tile_gram<T, KP, true>(tA, tA, gB, lane);
+    } else if (MODE == kAVF2) {
+      // own X rows of the tile
+#pragma unroll
+      for (int pass = 0; pass < G::NPASS; ++pass) {
+        const int gi = pass * G::RPW + g;
+        V16<T> x;
+        if (gi < cnt) {
+          x = ld16(static_cast<const T*>(a.X) + (size_t)trow[gi] * KP + j * G::VECN);
+        } else {
+#pragma unroll
+          for (int q = 0; q < G::VECN; ++q) x.v[q] = T(0);
+        }
+        if (gi < G::TR) tile_store_vec<T, KP>(tD, gi, j, x);
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      tile_gram<T, KP, false>(tD, tA, gA, lane);  // E = X^T (AV)
+      tile_gram<T, KP, true>(tZ, tA, gB, lane);   // F = V^T (AV)
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  }
+
+  // block partial row
+  __syncthreads();
+  double* red = reinterpret_cast<double*>(smem);
+  if (MODE == kApply) return;
+  double* prow = a.partials + (size_t)blockIdx.x * a.nv;
+  const int KK = KP * KP;
+  if (MODE == kGF1) {
+    block_vec_out<T, KP, 3>(cacc, red, prow, 0, wave, lane, WPB);
+    if (check) {
+      block_gram_out<T, KP, false>(gA, red, prow, 3 * KP, wave, lane, WPB);
+      block_gram_out<T, KP, true>(gB, red, prow, 3 * KP + KK, wave, lane, WPB);
+    }
+  } else if (MODE == kAXF2) {
+    block_gram_out<T, KP, false>(gA, red, prow, 0, wave, lane, WPB);
+    if (check) block_gram_out<T, KP, true>(gB, red, prow, KK, wave, lane, WPB);
+  } else if (MODE == kAVF1) {
+    block_vec_out<T, KP, 1>(cacc, red, prow, 0, wave, lane, WPB);
+  } else if (MODE == kAVF2) {
+    block_vec_out<T, KP, 1>(cacc, red, prow, 0, wave, lane, WPB);
+    block_gram_out<T, KP, false>(gA, red, prow, KP, wave, lane, WPB);
+    block_gram_out<T, KP, true>(gB, red, prow, KP + KK, wave, lane, WPB);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// N x k streaming passes
+// ---------------------------------------------------------------------------
+
+template <typename T, int KP, int MODE>
+__global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
+    dense_kernel(PassArgs a) {
+  using G = Geo<T, KP>;
+  using SM = Smem<T, KP, MODE>;
+  constexpr int WPB = SM::WPB;
+  constexpr int NV = nvec_of(MODE);
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* frag = reinterpret_cast<T*>(smem);
+  T* frag2 = frag + G::FRAG_ELEMS;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  unsigned char* wbase = smem + SM::frag_bytes + wave * SM::wave_bytes;
+  T* t0 = reinterpret_cast<T*>(wbase);
+  T* t1 = t0 + G::TILE_ELEMS;
+  T* t2 = t1 + G::TILE_ELEMS;
+  const int g = lane / G::LPR;
+  const int j = lane % G::LPR;
+  const double* sc = a.sc;
+  const bool restart = (a.flags & kFlagRestart) != 0;
+  const bool first = (a.flags & kFlagFirst) != 0;
+
+  // per-column scalars of this pass (beta for V, alpha for the update)
+  T colscal[G::VECN];
+#pragma unroll
+  for (int q = 0; q < G::VECN; ++q) colscal[q] = T(0);
+  T ca = T(0), cb = T(0);
+  if (MODE == kVPass) {
+#pragma unroll
+    for (int q = 0; q < G::VECN; ++q) {
+      const int c = j * G::VECN + q;
+      double beta = 0.0;
+      if (!first) {
+        const double den = sc[SC<KP>::GGP + c];
+        const double num = sc[SC<KP>::GG + c] - sc[SC<KP>::GPG + c];
+        beta = (den != 0.0) ? num / den : 0.0;
+        if (restart && (-sc[SC<KP>::GG + c] + beta * sc[SC<KP>::VPG + c]) >= 0.0) beta = 0.0;
+      }
+      colscal[q] = (T)beta;
+      if (blockIdx.x == 0 && threadIdx.x < G::LPR) const_cast<double*>(sc)[SC<KP>::BETA + c] = beta;
+    }
+  } else if (MODE == kUpdate) {
+#pragma unroll
+    for (int q = 0; q < G::VECN; ++q) colscal[q] = (T)sc[SC<KP>::ALPHA + j * G::VECN + q];
+  } else if (MODE == kGPassF2) {
+    const bool tri = a.variant == OFM_TRI_F2;
+    load_frags<T, KP>(frag, sc + SC<KP>::H, tri);   // H'
+    load_frags<T, KP>(frag2, sc + SC<KP>::M, tri);  // M'
+    ca = tri ? T(2) : T(4);
+    cb = tri ? T(1) : T(2);
+    __syncthreads();
+  }
+
+  double cacc[3][G::VECN];
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int q = 0; q < G::VECN; ++q) cacc[v][q] = 0.0;
+  d4 gA[G::NT][G::NT], gB[G::NT][G::NT];
+  zero_gram<T, KP>(gA);
+  zero_gram<T, KP>(gB);
+
+  const int64_t ntiles = (a.n + G::TR - 1) / G::TR;
+  const int64_t stride = (int64_t)gridDim.x * WPB;
+  for (int64_t t = (int64_t)blockIdx.x * WPB + wave; t < ntiles; t += stride) {
+    const int64_t r0 = t * G::TR;
+    const int cnt = (int)((a.n - r0) < G::TR ? (a.n - r0) : G::TR);
+#pragma unroll
+    for (int pass = 0; pass < G::NPASS; ++pass) {
+      const int gi = pass * G::RPW + g;
+      const bool ok = gi < cnt;
+      const size_t off = (size_t)(r0 + gi) * KP + j * G::VECN;
+      if (MODE == kVPass) {
+        V16<T> v, gv, x;
+        if (ok) {
+          gv = ld16(static_cast<const T*>(a.G) + off);
+          x = ld16(static_cast<const T*>(a.X) + off);
+          if (!first) {
+            const V16<T> vp = ld16(static_cast<const T*>(a.Vp) + off);
+#pragma unroll
+            for (int q = 0; q < G::VECN; ++q) v.v[q] = fma(colscal[q], vp.v[q], -gv.v[q]);
+          } else {
+#pragma unroll
+            for (int q = 0; q < G::VECN; ++q) v.v[q] = -gv.v[q];
+          }
+          st16(static_cast<T*>(a.V) + off, v);
+#pragma unroll
+          for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)v.v[q] * (double)gv.v[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < G::VECN; ++q) v.v[q] = x.v[q] = T(0);
+        }
+        if (gi < G::TR) {
+          tile_store_vec<T, KP>(t0, gi, j, v);
+          tile_store_vec<T, KP>(t1, gi, j, x);
+        }
+      } else if (MODE == kUpdate || MODE == kGramM) {
+        V16<T> x;
+        if (ok) {
+          x = ld16(static_cast<const T*>(a.X) + off);
+          if (MODE == kUpdate) {
+            const V16<T> v = ld16(static_cast<const T*>(a.V) + off);
+#pragma unroll
+            for (int q = 0; q < G::VECN; ++q) x.v[q] = fma(colscal[q], v.v[q], x.v[q]);
+            st16(static_cast<T*>(a.Xw) + off, x);
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < G::VECN; ++q) x.v[q] = T(0);
+        }
+        if (gi < G::TR) tile_store_vec<T, KP>(t0, gi, j, x);
+      } else if (MODE == kGGP) {
+        if (ok) {
+          const V16<T> gp = ld16(static_cast<const T*>(a.Gp) + off);
+#pragma unroll
+          for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)gp.v[q] * (double)gp.v[q];
+        }
+      } else if (MODE == kGPassF2) {
+        V16<T> x, ax;
+        if (ok) {
+          x = ld16(static_cast<const T*>(a.X) + off);
+          ax = ld16(static_cast<const T*>(a.AX) + off);
+        } else {
+#pragma unroll
+          for (int q = 0; q < G::VECN; ++q) x.v[q] = ax.v[q] = T(0);
+        }
+        if (gi < G::TR) {
+          tile_store_vec<T, KP>(t0, gi, j, x);
+          tile_store_vec<T, KP>(t1, gi, j, ax);
+        }
+      }
+    }
+    if (SM::NB == 0) continue;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    if (MODE == kVPass) {
+      tile_gram<T, KP, true>(t0, t0, gA, lane);   // P = V^T V
+      tile_gram<T, KP, false>(t1, t0, gB, lane);  // C = X^T V
+    } else if (MODE == kUpdate || MODE == kGramM) {
+      tile_gram<T, KP, true>(t0, t0, gA, lane);   // M = X^T X
+    } else if (MODE == kGPassF2) {
+      tile_times_matrix<T, KP>(t0, frag, t2, lane, false);   // X H'
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      tile_times_matrix<T, KP>(t1, frag2, t2, lane, true);   // + AX M'
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+#pragma unroll
+      for (int pass = 0; pass < G::NPASS; ++pass) {
+        const int gi = pass * G::RPW + g;
+        if (gi < cnt) {
+          const size_t off = (size_t)(r0 + gi) * KP + j * G::VECN;
+          const V16<T> ax = tile_load_vec<T, KP>(t1, gi, j);
+          const V16<T> d = tile_load_vec<T, KP>(t2, gi, j);
+          V16<T> gv;
+#pragma unroll
+          for (int q = 0; q < G::VECN; ++q) gv.v[q] = ca * ax.v[q] - cb * d.v[q];
+          st16(static_cast<T*>(a.G) + off, gv);
+#pragma unroll
+          for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)gv.v[q] * (double)gv.v[q];
+          if (a.Gp) {
+            const V16<T> gp = ld16(static_cast<const T*>(a.Gp) + off);
+#pragma unroll
+            for (int q = 0; q < G::VECN; ++q) cacc[1][q] += (double)gp.v[q] * (double)gv.v[q];
+          }
+          if (restart && a.Vp) {
+            const V16<T> vp = ld16(static_cast<const T*>(a.Vp) + off);
+#pragma unroll
+            for (int q = 0; q < G::VECN; ++q) cacc[2][q] += (double)vp.v[q] * (double)gv.v[q];
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  }
+
+  __syncthreads();
+  double* red = reinterpret_cast<double*>(smem);
+  double* prow = a.partials + (size_t)blockIdx.x * a.nv;
+  const int KK = KP * KP;
+  if (MODE == kVPass) {
+    block_gram_out<T, KP, true>(gA, red, prow, 0, wave, lane, WPB);
+    block_gram_out<T, KP, false>(gB, red, prow, KK, wave, lane, WPB);
+    block_vec_out<T, KP, 1>(cacc, red, prow, 2 * KK, wave, lane, WPB);
+  } else if (MODE == kUpdate || MODE == kGramM) {
+    block_gram_out<T, KP, true>(gA, red, prow, 0, wave, lane, WPB);
+  } else if (MODE == kGGP) {
+    block_vec_out<T, KP, 1>(cacc, red, prow, 0, wave, lane, WPB);
+  } else if (MODE == kGPassF2) {
+    block_vec_out<T, KP, 3>(cacc, red, prow, 0, wave, lane, WPB);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic two-level reduction of partial rows:
+// out[v] = sum_b partials[b][v], summed in block order.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(64) finalize_kernel(const double* __restrict__ partials, int nb,
+                                                      int nv, double* __restrict__ out,
+                                                      double* lvl2, int* tickets) {
+  const int cx = blockIdx.x;
+  const int cy = blockIdx.y;
+  const int ny = gridDim.y;
+  const int v = cx * 64 + threadIdx.x;
+  const int b0 = cy * kFinChunk;
+  const int b1 = min(nb, b0 + kFinChunk);
+  double s = 0.0;
+  if (v < nv) {
+    for (int b = b0; b < b1; ++b) s += partials[(size_t)b * nv + v];
+    lvl2[(size_t)cy * nv + v] = s;
+  }
+  if (ny == 1) {
+    if (v < nv) out[v] = s;
+    return;
+  }
+  __threadfence();
+  __shared__ int last;
+  if (threadIdx.x == 0) last = (atomicAdd(&tickets[cx], 1) == ny - 1);
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (v < nv) {
+    double t = 0.0;
+    for (int y = 0; y < ny; ++y) t += __builtin_nontemporal_load(&lvl2[(size_t)y * nv + v]);
+    out[v] = t;
+  }
+  if (threadIdx.x == 0) atomicExch(&tickets[cx], 0);
+}
+
+// ---------------------------------------------------------------------------
+// Exact line search (Section 3.2) in one workgroup, FP64
+// ---------------------------------------------------------------------------
+
+struct Roots {
+  int n;
+  double r[3];
+  int mult[3];
+};
+
+__device__ inline double cubic_eval(double a3, double a2, double a1, double a0, double x) {
+  return ((a3 * x + a2) * x + a1) * x + a0;
+}
+
+__device__ inline double newton2(double a3, double a2, double a1, double a0, double x) {
+  for (int it = 0; it < 2; ++it) {
+    const double dp = (3.0 * a3 * x + 2.0 * a2) * x + a1;
+    if (dp == 0.0 || !isfinite(dp)) break;
+    const double xn = x - cubic_eval(a3, a2, a1, a0, x) / dp;
+    if (!isfinite(xn)) break;
+    x = xn;
+  }
+  return x;
+}
+
+__device__ inline void sort_roots(Roots& R) {
+  for (int i = 1; i < R.n; ++i)
+    for (int k = i; k > 0 && R.r[k] < R.r[k - 1]; --k) {
+      const double t = R.r[k];
+      R.r[k] = R.r[k - 1];
+      R.r[k - 1] = t;
+      const int m = R.mult[k];
+      R.mult[k] = R.mult[k - 1];
+      R.mult[k - 1] = m;
+    }
+}
+
+// Real roots of a3 x^3 + a2 x^2 + a1 x + a0: Cardano's formula for one real
+// root, the trigonometric form for three, the repeated-root closed form when
+// the discriminant vanishes (relative tolerance 1e-12); two Newton steps.
+__device__ inline Roots cubic_roots(double a3, double a2, double a1, double a0) {
+  const double tol = 1e-12;
+  Roots R;
+  R.n = 0;
+  if (a3 == 0.0) {
+    if (a2 == 0.0) {
+      if (a1 != 0.0) {
+        R.n = 1;
+        R.r[0] = -a0 / a1;
+        R.mult[0] = 1;
+      }
+      return R;
+    }
+    const double disc = a1 * a1 - 4.0 * a2 * a0;
+    const double scale = fmax(a1 * a1, fabs(4.0 * a2 * a0));
+    if (disc < -tol * scale) return R;
+    if (disc <= tol * scale) {
+      R.n = 1;
+      R.r[0] = -a1 / (2.0 * a2);
+      R.mult[0] = 2;
+      return R;
+    }
+    const double sq = sqrt(disc);
+    const double qq = -0.5 * (a1 + copysign(sq, a1));
+    const double r1 = qq / a2;
+    const double r2 = (qq != 0.0) ? a0 / qq : -a1 / a2 - r1;
+    R.n = 2;
+    R.r[0] = r1;
+    R.r[1] = r2;
+    R.mult[0] = R.mult[1] = 1;
+    sort_roots(R);
+    return R;
+  }
+  const double b = a2 / a3, c = a1 / a3, d = a0 / a3;
+  const double p = c - b * b / 3.0;
+  const double q = 2.0 * b * b * b / 27.0 - b * c / 3.0 + d;
+  const double shift = -b / 3.0;
+  const double D = q * q / 4.0 + p * p * p / 27.0;
+  const double scale = fmax(q * q / 4.0, fabs(p * p * p / 27.0));
+  if (scale == 0.0) {
+    R.n = 1;
+    R.r[0] = newton2(a3, a2, a1, a0, shift);
+    R.mult[0] = 3;
+    return R;
+  }
+  if (fabs(D) <= tol * scale) {
+    if (p == 0.0) {
+      R.n = 1;
+      R.r[0] = newton2(a3, a2, a1, a0, shift);
+      R.mult[0] = 3;
+      return R;
+    }
+    R.n = 2;
+    R.r[0] = newton2(a3, a2, a1, a0, 3.0 * q / p + shift);
+    R.mult[0] = 1;
+    R.r[1] = -3.0 * q / (2.0 * p) + shift;
+    R.mult[1] = 2;
+    sort_roots(R);
+    return R;
+  }
+  if (D > 0.0) {
+    const double sq = sqrt(D);
+    const double u = cbrt(-q / 2.0 + sq);
+    const double v = cbrt(-q / 2.0 - sq);
+    R.n = 1;
+    R.r[0] = newton2(a3, a2, a1, a0, u + v + shift);
+    R.mult[0] = 1;
+    return R;
+  }
+  const double m = 2.0 * sqrt(-p / 3.0);
+  double arg = 3.0 * q / (p * m);
+  arg = fmin(1.0, fmax(-1.0, arg));
+  const double th = acos(arg) / 3.0;
+  const double two_pi_3 = 2.0943951023931954923;  // 2 pi / 3
+  R.n = 3;
+  for (int i = 0; i < 3; ++i) {
+    R.r[i] = newton2(a3, a2, a1, a0, m * cos(th - two_pi_3 * i) + shift);
+    R.mult[i] = 1;
+  }
+  sort_roots(R);
+  return R;
+}
+
+// Root rules of Section 3.2: one real root -> it; a simple and a repeated root
+// -> the simple one; otherwise the least line objective
+// Phi(x) = a3 x^4/4 + a2 x^3/3 + a1 x^2/2 + a0 x (OFM) or the smallest |x|
+// (triangular variants).  Candidates are visited by ascending |x| then x, and
+// only a strictly smaller Phi replaces the current choice.
+__device__ inline double select_root(bool tri, double a3, double a2, double a1, double a0,
+                                     int* nroots) {
+  Roots R = cubic_roots(a3, a2, a1, a0);
+  *nroots = R.n;
+  if (R.n == 0) return 0.0;
+  if (R.n == 1) return R.r[0];
+  if (R.n == 2 && (R.mult[0] == 2 || R.mult[1] == 2)) return R.mult[0] == 1 ? R.r[0] : R.r[1];
+  double c[3];
+  for (int i = 0; i < R.n; ++i) c[i] = R.r[i];
+  for (int i = 1; i < R.n; ++i)
+    for (int k = i; k > 0; --k) {
+      const bool less = fabs(c[k]) < fabs(c[k - 1]) || (fabs(c[k]) == fabs(c[k - 1]) && c[k] < c[k - 1]);
+      if (!less) break;
+      const double t = c[k];
+      c[k] = c[k - 1];
+      c[k - 1] = t;
+    }
+  if (tri) return c[0];
+  double best = c[0];
+  double bv = ((a3 * best / 4.0 + a2 / 3.0) * best + a1 / 2.0) * best * best + a0 * best;
+  for (int i = 1; i < R.n; ++i) {
+    const double x = c[i];
+    const double val = ((a3 * x / 4.0 + a2 / 3.0) * x + a1 / 2.0) * x * x + a0 * x;
+    if (val < bv) {
+      best = x;
+      bv = val;
+    }
+  }
+  return best;
+}
+
+// deterministic block sum of one double per thread (blockDim = 256)
+__device__ inline double block_sum256(double x, double* buf) {
+  buf[threadIdx.x] = x;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) buf[threadIdx.x] += buf[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = buf[0];
+  __syncthreads();
+  return r;
+}
+
+template <int KP>
+__global__ void __launch_bounds__(256) linesearch_kernel(int variant, int first, double alpha0,
+                                                         double* sc, int* status) {
+  __shared__ double buf[256];
+  __shared__ double co[4];
+  const int KK = KP * KP;
+  const double* M = sc + SC<KP>::M;
+  const double* H = sc + SC<KP>::H;
+  const double* C = sc + SC<KP>::C;
+  const double* P = sc + SC<KP>::P;
+  const double* E = sc + SC<KP>::E;
+  const double* F = sc + SC<KP>::F;
+  const double* vg = sc + SC<KP>::VG;
+  const double* fd = sc + SC<KP>::FD;
+  double* alpha = sc + SC<KP>::ALPHA;
+  double* coef = sc + SC<KP>::COEF;
+  double* nroot = sc + SC<KP>::NROOT;
+  const int tid = threadIdx.x;
+  const bool tri = (variant == OFM_TRI_F1 || variant == OFM_TRI_F2);
+  bool bad = false;
+
+  if (!tri) {
+    // traces tr(X Y) = sum_ab X_ab Y_ba
+    double t3 = 0.0, t2 = 0.0, t1 = 0.0;
+    for (int e = tid; e < KK; e += 256) {
+      const int r = e / KP, c = e % KP;
+      const int et = c * KP + r;
+      if (variant == OFM_F1) {
+        t3 += P[e] * P[et];                                     // tr(P P)
+        t2 += P[e] * C[et];                                     // tr(P C)
+        t1 += C[et] * C[e] + C[et] * C[et] + P[e] * M[et];      // tr(C^T C^T) + tr(C^T C) + tr(P M)
+      } else {
+        t3 += P[e] * F[et];                                     // tr(P F)
+        t2 += C[et] * F[et] + P[e] * E[e];                      // tr(C^T F) + tr(P E^T)
+        t1 += 2.0 * C[et] * E[et] + 2.0 * C[et] * E[e] + P[e] * H[et] + M[e] * F[et];
+      }
+    }
+    double tr_f = 0.0, svg = 0.0;
+    if (tid < KP) {
+      tr_f = (variant == OFM_F1) ? fd[tid] : F[tid * KP + tid];
+      svg = vg[tid];
+    }
+    t3 = block_sum256(t3, buf);
+    t2 = block_sum256(t2, buf);
+    t1 = block_sum256(t1, buf);
+    tr_f = block_sum256(tr_f, buf);
+    svg = block_sum256(svg, buf);
+    if (tid == 0) {
+      double a3, a2, a1, a0;
+      if (variant == OFM_F1) {
+        // (1/4) d/da f1(X + aV), eq. f1-derivative
+        a3 = t3;
+        a2 = 3.0 * t2;
+        a1 = tr_f + t1;
+        a0 = svg / 4.0;
+      } else {
+        // d/da f2(X + aV), eq. f2-derivative
+        a3 = -4.0 * t3;
+        a2 = -6.0 * t2;
+        a1 = 2.0 * (2.0 * tr_f - t1);
+        a0 = svg;
+      }
+      co[0] = a3;
+      co[1] = a2;
+      co[2] = a1;
+      co[3] = a0;
+      int nr = 0;
+      double al = first ? alpha0 : select_root(false, a3, a2, a1, a0, &nr);
+      if (!(isfinite(a3) && isfinite(a2) && isfinite(a1) && isfinite(a0) && isfinite(al))) {
+        bad = true;
+        al = 0.0;
+      }
+      coef[0] = a3;
+      coef[1] = a2;
+      coef[2] = a1;
+      coef[3] = a0;
+      nroot[0] = nr;
+      buf[0] = al;
+      if (bad) atomicOr(status, kStNonfinite);
+    }
+    __syncthreads();
+    const double al = buf[0];
+    if (tid < KP) alpha[tid] = al;
+    if (tid > 0 && tid < KP) {
+      for (int jj = 0; jj < 4; ++jj) coef[4 * tid + jj] = 0.0;
+      nroot[tid] = 0;
+    }
+  } else if (tid < KP) {
+    // per-column cubic [V^T g(X + a_i V)]_ii, eqs. alphai-f1 / alphai-f2:
+    // [X triu(Y)]_ii = sum_{j<=i} X_ij Y_ji
+    const int i = tid;
+    double a3 = 0.0, a2 = 0.0, a1 = 0.0;
+    for (int jj = 0; jj <= i; ++jj) {
+      const int ij = i * KP + jj, ji = jj * KP + i;
+      if (variant == OFM_TRI_F1) {
+        a3 += P[ij] * P[ji];
+        a2 += P[ij] * C[ji] + P[ij] * C[ij] + C[ji] * P[ji];
+        a1 += C[ji] * C[ij] + C[ji] * C[ji] + P[ij] * M[ji];
+      } else {
+        a3 -= F[ij] * P[ji] + P[ij] * F[ji];
+        a2 -= E[ji] * P[ji] + F[ij] * C[ji] + F[ij] * C[ij] + C[ji] * F[ji] + P[ij] * E[ji] +
+              P[ij] * E[ij];
+        a1 -= E[ji] * C[ji] + E[ji] * C[ij] + F[ij] * M[ji] + C[ji] * E[ji] + C[ji] * E[ij] +
+              P[ij] * H[ji];
+      }
+    }
+    if (variant == OFM_TRI_F1) a1 += fd[i];
+    else a1 += 2.0 * F[i * KP + i];
+    const double a0 = vg[i];
+    int nr = 0;
+    double al = first ? alpha0 : select_root(true, a3, a2, a1, a0, &nr);
+    if (!(isfinite(a3) && isfinite(a2) && isfinite(a1) && isfinite(a0) && isfinite(al))) {
+      atomicOr(status, kStNonfinite);
+      al = 0.0;
+    }
+    coef[4 * i + 0] = a3;
+    coef[4 * i + 1] = a2;
+    coef[4 * i + 2] = a1;
+    coef[4 * i + 3] = a0;
+    nroot[i] = nr;
+    alpha[i] = al;
+  }
+  // the CG denominator of the next step: diag G^T G of this step
+  __syncthreads();
+  if (tid < KP) sc[SC<KP>::GGP + tid] = sc[SC<KP>::GG + tid];
+}
+
+// ---------------------------------------------------------------------------
+// Residual of the Ritz pairs of A on span(X) from M = X^T X, H = X^T A X,
+// K = (AX)^T (AX):  relres^2 = tr(M^{-1} K) / tr((M^{-1} H)^2) - 1
+// (numerical results section, "Evaluation metrics"); also the objective.
+// ---------------------------------------------------------------------------
+
+template <int KP>
+__global__ void __launch_bounds__(256) residual_kernel(int variant, double normA2, double* sc,
+                                                       int* status) {
+  __shared__ double L[KP * KP];
+  __shared__ double W[KP * KP];
+  __shared__ double buf[256];
+  __shared__ int fail;
+  const int tid = threadIdx.x;
+  const int KK = KP * KP;
+  const double* M = sc + SC<KP>::M;
+  const double* H = sc + SC<KP>::H;
+  const double* K = sc + SC<KP>::K;
+  for (int e = tid; e < KK; e += 256) L[e] = M[e];
+  if (tid == 0) fail = 0;
+  __syncthreads();
+  // Cholesky M = L L^T (lower triangle of L), column by column
+  for (int c = 0; c < KP; ++c) {
+    if (tid == 0) {
+      const double d = L[c * KP + c];
+      if (!(d > 0.0) || !isfinite(d)) fail = 1;
+      L[c * KP + c] = (d > 0.0) ? sqrt(d) : 1.0;
+    }
+    __syncthreads();
+    const double dc = L[c * KP + c];
+    for (int r = c + 1 + tid; r < KP; r += 256) L[r * KP + c] /= dc;
+    __syncthreads();
+    for (int e = tid; e < KK; e += 256) {
+      const int r = e / KP, q = e % KP;
+      if (r > c && q > c && q <= r) L[r * KP + q] -= L[r * KP + c] * L[q * KP + c];
+    }
+    __syncthreads();
+  }
+  // W = M^{-1} B for B = K then B = H (two triangular solves per column)
+  double trMK = 0.0, trMH2 = 0.0;
+  for (int which = 0; which < 2; ++which) {
+    const double* B = which == 0 ? K : H;
+    if (tid < KP) {
+      const int col = tid;
+      for (int r = 0; r < KP; ++r) {          // L y = b
+        double s = B[r * KP + col];
+        for (int q = 0; q < r; ++q) s -= L[r * KP + q] * W[q * KP + col];
+        W[r * KP + col] = s / L[r * KP + r];
+      }
+      for (int r = KP - 1; r >= 0; --r) {     // L^T x = y
+        double s = W[r * KP + col];
+        for (int q = r + 1; q < KP; ++q) s -= L[q * KP + r] * W[q * KP + col];
+        W[r * KP + col] = s / L[r * KP + r];
+      }
+    }
+    __syncthreads();
+    double part = 0.0;
+    if (which == 0) {
+      if (tid < KP) part = W[tid * KP + tid];
+      trMK = block_sum256(part, buf);
+    } else {
+      for (int e = tid; e < KK; e += 256) {
+        const int r = e / KP, q = e % KP;
+        part += W[r * KP + q] * W[q * KP + r];
+      }
+      trMH2 = block_sum256(part, buf);
+    }
+    __syncthreads();
+  }
+  // objective: f1 = ||A||^2 + 2 tr(H) + ||M||_F^2 ; f2 = 2 tr(H) - tr(M H)
+  double trH = (tid < KP) ? H[tid * KP + tid] : 0.0;
+  double mm = 0.0;
+  for (int e = tid; e < KK; e += 256) {
+    const int r = e / KP, q = e % KP;
+    mm += (variant == OFM_F1 || variant == OFM_TRI_F1) ? M[e] * M[e] : M[e] * H[q * KP + r];
+  }
+  trH = block_sum256(trH, buf);
+  mm = block_sum256(mm, buf);
+  if (tid == 0) {
+    const double rr = trMK / trMH2 - 1.0;
+    sc[SC<KP>::RELRES] = sqrt(fmax(rr, 0.0));
+    sc[SC<KP>::FVAL] = (variant == OFM_F1 || variant == OFM_TRI_F1) ? normA2 + 2.0 * trH + mm
+                                                                     : 2.0 * trH - mm;
+    if (fail) atomicOr(status, kStCholesky);
+    if (!isfinite(sc[SC<KP>::RELRES])) atomicOr(status, kStNonfinite);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+
+template <typename T, int KP>
+int tile_rows_t() {
+  return Geo<T, KP>::TR;
+}
+
+int tile_rows(int precision, int k) {
+  const bool d = precision == OFM_FP64;
+  switch (k) {
+    case 4: return d ? tile_rows_t<double, 4>() : tile_rows_t<float, 4>();
+    case 8: return d ? tile_rows_t<double, 8>() : tile_rows_t<float, 8>();
+    case 16: return d ? tile_rows_t<double, 16>() : tile_rows_t<float, 16>();
+    case 32: return d ? tile_rows_t<double, 32>() : tile_rows_t<float, 32>();
+    case 64: return d ? 16 : tile_rows_t<float, 64>();
+  }
+  return 16;
+}
+
+template <typename T, int KP>
+int wpb_t() {
+  return Cfg<T, KP>::WPB;
+}
+
+static int wpb(int precision, int k) {
+  const bool d = precision == OFM_FP64;
+  switch (k) {
+    case 4: return d ? wpb_t<double, 4>() : wpb_t<float, 4>();
+    case 8: return d ? wpb_t<double, 8>() : wpb_t<float, 8>();
+    case 16: return d ? wpb_t<double, 16>() : wpb_t<float, 16>();
+    case 32: return d ? wpb_t<double, 32>() : wpb_t<float, 32>();
+    case 64: return wpb_t<float, 64>();
+  }
+  return 1;
+}
+
+int pass_blocks(int precision, int k, int64_t ntiles) {
+  const int w = wpb(precision, k);
+  int64_t nb = (ntiles + w - 1) / w;
+  if (nb > kMaxBlocks) nb = kMaxBlocks;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+int partial_nv(int k, int mode, int flags) {
+  switch (k) {
+    case 4: return mode_nv<4>(mode, flags);
+    case 8: return mode_nv<8>(mode, flags);
+    case 16: return mode_nv<16>(mode, flags);
+    case 32: return mode_nv<32>(mode, flags);
+    case 64: return mode_nv<64>(mode, flags);
+  }
+  return 0;
+}
+
+int partial_off(int k, int mode) {
+  switch (k) {
+    case 4: return mode_off<4>(mode);
+    case 8: return mode_off<8>(mode);
+    case 16: return mode_off<16>(mode);
+    case 32: return mode_off<32>(mode);
+    case 64: return mode_off<64>(mode);
+  }
+  return 0;
+}
+
+template <typename T, int KP, int MODE>
+static hipError_t spmm_mode(PassArgs& a, hipStream_t s) {
+  using SM = Smem<T, KP, MODE>;
+  hipLaunchKernelGGL((spmm_kernel<T, KP, MODE>), dim3(a.nblocks), dim3(SM::WPB * 64),
+                     SM::bytes, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int KP>
+static hipError_t spmm_t(PassArgs& a, hipStream_t s) {
+  switch (a.mode) {
+    case kApply: return spmm_mode<T, KP, kApply>(a, s);
+    case kGF1: return spmm_mode<T, KP, kGF1>(a, s);
+    case kAXF2: return spmm_mode<T, KP, kAXF2>(a, s);
+    case kAVF1: return spmm_mode<T, KP, kAVF1>(a, s);
+    case kAVF2: return spmm_mode<T, KP, kAVF2>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int KP, int MODE>
+static hipError_t dense_mode(PassArgs& a, hipStream_t s) {
+  using SM = Smem<T, KP, MODE>;
+  hipLaunchKernelGGL((dense_kernel<T, KP, MODE>), dim3(a.nblocks), dim3(SM::WPB * 64),
+                     SM::bytes, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int KP>
+static hipError_t dense_t(PassArgs& a, hipStream_t s) {
+  switch (a.mode) {
+    case kGPassF2: return dense_mode<T, KP, kGPassF2>(a, s);
+    case kVPass: return dense_mode<T, KP, kVPass>(a, s);
+    case kUpdate: return dense_mode<T, KP, kUpdate>(a, s);
+    case kGramM: return dense_mode<T, KP, kGramM>(a, s);
+    case kGGP: return dense_mode<T, KP, kGGP>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_spmm(int precision, int k, PassArgs& a, hipStream_t s) {
+  if (precision == OFM_FP64) {
+    switch (k) {
+      case 4: return spmm_t<double, 4>(a, s);
+      case 8: return spmm_t<double, 8>(a, s);
+      case 16: return spmm_t<double, 16>(a, s);
+      case 32: return spmm_t<double, 32>(a, s);
+    }
+  } else {
+    switch (k) {
+      case 4: return spmm_t<float, 4>(a, s);
+      case 8: return spmm_t<float, 8>(a, s);
+      case 16: return spmm_t<float, 16>(a, s);
+      case 32: return spmm_t<float, 32>(a, s);
+      case 64: return spmm_t<float, 64>(a, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_dense(int precision, int k, PassArgs& a, hipStream_t s) {
+  if (precision == OFM_FP64) {
+    switch (k) {
+      case 4: return dense_t<double, 4>(a, s);
+      case 8: return dense_t<double, 8>(a, s);
+      case 16: return dense_t<double, 16>(a, s);
+      case 32: return dense_t<double, 32>(a, s);
+    }
+  } else {
+    switch (k) {
+      case 4: return dense_t<float, 4>(a, s);
+      case 8: return dense_t<float, 8>(a, s);
+      case 16: return dense_t<float, 16>(a, s);
+      case 32: return dense_t<float, 32>(a, s);
+      case 64: return dense_t<float, 64>(a, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize(const double* partials, int nb, int nv, double* out, double* lvl2,
+                           int* tickets, hipStream_t s) {
+  const int ny = (nb + kFinChunk - 1) / kFinChunk;
+  dim3 grid((nv + 63) / 64, ny);
+  hipLaunchKernelGGL(finalize_kernel, grid, dim3(64), 0, s, partials, nb, nv, out, lvl2, tickets);
+  return hipGetLastError();
+}
+
+hipError_t launch_linesearch(int k, int variant, int first, double alpha0, double* sc,
+                             int* status, hipStream_t s) {
+  switch (k) {
+    case 4: hipLaunchKernelGGL(linesearch_kernel<4>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status); break;
+    case 8: hipLaunchKernelGGL(linesearch_kernel<8>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status); break;
+    case 16: hipLaunchKernelGGL(linesearch_kernel<16>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status); break;
+    case 32: hipLaunchKernelGGL(linesearch_kernel<32>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status); break;
+    case 64: hipLaunchKernelGGL(linesearch_kernel<64>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(int k, int variant, double normA2, double* sc, int* status,
+                           hipStream_t s) {
+  switch (k) {
+    case 4: hipLaunchKernelGGL(residual_kernel<4>, dim3(1), dim3(256), 0, s, variant, normA2, sc, status); break;
+    case 8: hipLaunchKernelGGL(residual_kernel<8>, dim3(1), dim3(256), 0, s, variant, normA2, sc, status); break;
+    case 16: hipLaunchKernelGGL(residual_kernel<16>, dim3(1), dim3(256), 0, s, variant, normA2, sc, status); break;
+    case 32: hipLaunchKernelGGL(residual_kernel<32>, dim3(1), dim3(256), 0, s, variant, normA2, sc, status); break;
+    case 64: hipLaunchKernelGGL(residual_kernel<64>, dim3(1), dim3(256), 0, s, variant, normA2, sc, status); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ofm

@@ -1,0 +1,244 @@
+// Post-processing of Algorithm 1 (steps 4-5): row normalisation and
+// Euclidean K-means (assignment, deterministic centroid update, k-means++
+// seeding from caller-supplied uniforms).
+#include <math.h>
+
+#include "ofm_internal.hpp"
+
+namespace ofm {
+
+template <typename T>
+__global__ void row_normalize_kernel(int64_t n, int k, const T* __restrict__ X, T* __restrict__ Y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T* x = X + i * k;
+  double s = 0.0;
+  for (int c = 0; c < k; ++c) s += (double)x[c] * (double)x[c];
+  const double nr = sqrt(s);
+  T* y = Y + i * k;
+  for (int c = 0; c < k; ++c) y[c] = nr > 0.0 ? (T)((double)x[c] / nr) : T(0);
+}
+
+hipError_t launch_row_normalize(int64_t n, int k, int precision, const void* X, void* Y,
+                                hipStream_t s) {
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  if (precision == OFM_FP64)
+    hipLaunchKernelGGL(row_normalize_kernel<double>, dim3(nb), dim3(256), 0, s, n, k,
+                       static_cast<const double*>(X), static_cast<double*>(Y));
+  else
+    hipLaunchKernelGGL(row_normalize_kernel<float>, dim3(nb), dim3(256), 0, s, n, k,
+                       static_cast<const float*>(X), static_cast<float*>(Y));
+  return hipGetLastError();
+}
+
+// one point per thread; centroids staged in LDS when they fit
+constexpr int kLdsCentroidFloats = 12288;
+
+__global__ void __launch_bounds__(256) kmeans_assign_kernel(int64_t n, int dim, int nc,
+                                                            const float* __restrict__ Y,
+                                                            const float* __restrict__ C,
+                                                            int32_t* __restrict__ labels,
+                                                            float* __restrict__ dist2) {
+  __shared__ float cs[kLdsCentroidFloats];
+  const bool in_lds = nc * dim <= kLdsCentroidFloats;
+  if (in_lds)
+    for (int e = threadIdx.x; e < nc * dim; e += blockDim.x) cs[e] = C[e];
+  __syncthreads();
+  const float* cc = in_lds ? cs : C;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float y[64];
+  for (int d = 0; d < dim; ++d) y[d] = Y[i * dim + d];
+  float best = INFINITY;
+  int bi = 0;
+  for (int c = 0; c < nc; ++c) {
+    float s = 0.0f;
+    for (int d = 0; d < dim; ++d) {
+      const float t = y[d] - cc[c * dim + d];
+      s = fmaf(t, t, s);
+    }
+    if (s < best) {
+      best = s;
+      bi = c;
+    }
+  }
+  labels[i] = bi;
+  if (dist2) dist2[i] = best;
+}
+
+hipError_t launch_kmeans_assign(int64_t n, int dim, int nc, const float* Y, const float* C,
+                                int32_t* labels, float* dist2, hipStream_t s) {
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(kmeans_assign_kernel, dim3(nb), dim3(256), 0, s, n, dim, nc, Y, C, labels,
+                     dist2);
+  return hipGetLastError();
+}
+
+int kmeans_blocks(int64_t n) {
+  int64_t nb = (n + 1023) / 1024;
+  if (nb > 2048) nb = 2048;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
+
+// per-block sums of the rows of every cluster plus counts, row by row in a
+// fixed order (lane = feature), so the result does not depend on timing.
+// part layout: [block][nc][dim + 1]; accumulated in LDS when it fits.
+constexpr int kLdsSumDoubles = 6144;
+
+__global__ void __launch_bounds__(64) kmeans_sums_kernel(int64_t n, int dim, int nc,
+                                                         const float* __restrict__ Y,
+                                                         const int32_t* __restrict__ labels,
+                                                         double* __restrict__ part) {
+  __shared__ double acc_lds[kLdsSumDoubles];
+  const int lane = threadIdx.x;
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = min(n, r0 + per);
+  const int nv = nc * (dim + 1);
+  double* pb = part + (size_t)blockIdx.x * nv;
+  double* acc = nv <= kLdsSumDoubles ? acc_lds : pb;
+  for (int e = lane; e < nv; e += 64) acc[e] = 0.0;
+  __syncthreads();
+  for (int64_t r = r0; r < r1; ++r) {
+    const int c = labels[r];
+    if (lane < dim) acc[(size_t)c * (dim + 1) + lane] += (double)Y[r * dim + lane];
+    if (lane == 0) acc[(size_t)c * (dim + 1) + dim] += 1.0;
+  }
+  __syncthreads();
+  if (acc != pb)
+    for (int e = lane; e < nv; e += 64) pb[e] = acc[e];
+}
+
+__global__ void kmeans_final_kernel(int dim, int nc, const double* __restrict__ part, int nb,
+                                    const float* __restrict__ old_c, float* __restrict__ new_c) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nc * dim) return;
+  const int c = e / dim, d = e % dim;
+  double s = 0.0, cnt = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    s += part[((size_t)b * nc + c) * (dim + 1) + d];
+    cnt += part[((size_t)b * nc + c) * (dim + 1) + dim];
+  }
+  new_c[e] = cnt > 0.0 ? (float)(s / cnt) : old_c[e];
+}
+
+hipError_t launch_kmeans_centroid_sums(int64_t n, int dim, int nc, const float* Y,
+                                       const int32_t* labels, double* part, int nb,
+                                       hipStream_t s) {
+  hipLaunchKernelGGL(kmeans_sums_kernel, dim3(nb), dim3(64), 0, s, n, dim, nc, Y, labels, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_kmeans_centroid_final(int dim, int nc, const double* part, int nb,
+                                        const float* old_c, float* new_c, hipStream_t s) {
+  const int tot = nc * dim;
+  hipLaunchKernelGGL(kmeans_final_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, dim, nc,
+                     part, nb, old_c, new_c);
+  return hipGetLastError();
+}
+
+// d2[i] = min(d2[i], ||y_i - centre||^2)  (first: assignment)
+__global__ void kmeans_mindist_kernel(int64_t n, int dim, const float* __restrict__ Y,
+                                      const float* __restrict__ centre, float* __restrict__ d2,
+                                      int first) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.0f;
+  for (int d = 0; d < dim; ++d) {
+    const float t = Y[i * dim + d] - centre[d];
+    s = fmaf(t, t, s);
+  }
+  d2[i] = first ? s : fminf(d2[i], s);
+}
+
+hipError_t launch_kmeans_mindist(int64_t n, int dim, const float* Y, const float* centre,
+                                 float* d2, int first, hipStream_t s) {
+  hipLaunchKernelGGL(kmeans_mindist_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                     dim, Y, centre, d2, first);
+  return hipGetLastError();
+}
+
+// chunk sums of d2 (FP64, sequential within a chunk)
+__global__ void kmeans_chunksum_kernel(int64_t n, const float* __restrict__ d2,
+                                       double* __restrict__ sums, int nb) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const int64_t per = (n + nb - 1) / nb;
+  const int64_t r0 = (int64_t)b * per;
+  const int64_t r1 = min(n, r0 + per);
+  double s = 0.0;
+  for (int64_t r = r0; r < r1; ++r) s += (double)d2[r];
+  sums[b] = s;
+}
+
+// first index whose running sum exceeds u * total (running sums in FP64)
+__global__ void kmeans_pick_kernel(int64_t n, const float* __restrict__ d2,
+                                   const double* __restrict__ sums, int nb, double u,
+                                   int32_t* pick) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double tot = 0.0;
+  for (int b = 0; b < nb; ++b) tot += sums[b];
+  if (!(tot > 0.0)) {
+    // every point coincides with a chosen centre: keep the previous pick
+    return;
+  }
+  const double target = u * tot;
+  const int64_t per = (n + nb - 1) / nb;
+  double run = 0.0;
+  int b = 0;
+  for (; b < nb; ++b) {
+    if (run + sums[b] > target) break;
+    run += sums[b];
+  }
+  if (b >= nb) {
+    pick[0] = (int32_t)(n - 1);
+    return;
+  }
+  const int64_t r0 = (int64_t)b * per;
+  const int64_t r1 = min(n, r0 + per);
+  int64_t r = r0;
+  for (; r < r1; ++r) {
+    run += (double)d2[r];
+    if (run > target) break;
+  }
+  pick[0] = (int32_t)min(r, n - 1);
+}
+
+hipError_t launch_kmeans_pick(int64_t n, const float* d2, double u, double* blocksums, int nb,
+                              int32_t* pick, hipStream_t s) {
+  hipLaunchKernelGGL(kmeans_chunksum_kernel, dim3((nb + 63) / 64), dim3(64), 0, s, n, d2,
+                     blocksums, nb);
+  hipLaunchKernelGGL(kmeans_pick_kernel, dim3(1), dim3(64), 0, s, n, d2, blocksums, nb, u, pick);
+  return hipGetLastError();
+}
+
+__global__ void kmeans_copy_centre_kernel(int dim, const float* __restrict__ Y,
+                                          const int32_t* __restrict__ pick, float* __restrict__ C,
+                                          int c) {
+  const int d = threadIdx.x;
+  if (d < dim) C[(size_t)c * dim + d] = Y[(size_t)pick[0] * dim + d];
+}
+
+hipError_t launch_kmeans_copy_centre(int dim, const float* Y, const int32_t* pick, float* C, int c,
+                                     hipStream_t s) {
+  hipLaunchKernelGGL(kmeans_copy_centre_kernel, dim3(1), dim3(64), 0, s, dim, Y, pick, C, c);
+  return hipGetLastError();
+}
+
+__global__ void count_changes_kernel(int64_t n, const int32_t* __restrict__ a,
+                                     const int32_t* __restrict__ b, int* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int ch = (i < n && a[i] != b[i]) ? 1 : 0;
+  // any change is enough
+  if (__any(ch) && (threadIdx.x & 63) == 0) atomicOr(out, 1);
+}
+
+hipError_t launch_count_changes(int64_t n, const int32_t* a, const int32_t* b, int* out,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(count_changes_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
+                     a, b, out);
+  return hipGetLastError();
+}
+
+}  // namespace ofm

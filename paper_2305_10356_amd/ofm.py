@@ -1,0 +1,362 @@
+"""Python binding of libofm (ctypes; argument marshalling only).
+
+Every computation runs in the HIP library.  Tensors are torch CUDA (ROCm)
+tensors; pointers and the current stream are handed to the C ABI declared in
+include/ofm.h.  If the compiled library is missing this module raises: there
+is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libofm.so")
+
+OFM_F1, OFM_TRI_F1, OFM_F2, OFM_TRI_F2 = 0, 1, 2, 3
+OFM_FP64, OFM_FP32 = 0, 1
+OFM_LAP_VALIDATE = 1
+OFM_LAP_NO_REORDER = 2
+
+STATUS = {
+    0: "OFM_OK", -1: "OFM_E_INVALID_ARG", -2: "OFM_E_SHAPE", -3: "OFM_E_GRAPH",
+    -4: "OFM_E_NONFINITE", -5: "OFM_E_NUMERIC", -6: "OFM_E_HIP", -7: "OFM_E_NOMEM",
+    -8: "OFM_E_UNSUPPORTED",
+}
+
+VARIANTS = {"f1": OFM_F1, "tri-f1": OFM_TRI_F1, "f2": OFM_F2, "tri-f2": OFM_TRI_F2}
+
+
+class OfmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("variant", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("max_iter", ctypes.c_int),
+        ("check_every", ctypes.c_int),
+        ("first_step", ctypes.c_int),
+        ("restart", ctypes.c_int),
+        ("alpha0", ctypes.c_double),
+        ("tol", ctypes.c_double),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int64),
+        ("status", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("relres", ctypes.c_double),
+        ("objective", ctypes.c_double),
+        ("relres_iter", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I = ctypes.c_int
+_D = ctypes.c_double
+
+_SIGS = {
+    "ofm_status_string": (ctypes.c_char_p, [_I]),
+    "ofm_version": (ctypes.c_char_p, []),
+    "ofm_build_laplacian": (_I, [_I64, _I64, _P, _P, _P, ctypes.c_uint, _P, ctypes.POINTER(_P)]),
+    "ofm_laplacian_destroy": (_I, [_P]),
+    "ofm_laplacian_info": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
+                                ctypes.POINTER(_D), _P]),
+    "ofm_apply_A": (_I, [_P, _I, _I, _P, _P, _P]),
+    "ofm_workspace_create": (_I, [_P, _I, ctypes.POINTER(Opts), ctypes.POINTER(_P)]),
+    "ofm_workspace_destroy": (_I, [_P]),
+    "ofm_init": (_I, [_P, _P, _P]),
+    "ofm_step": (_I, [_P, _P, _P]),
+    "ofm_solve": (_I, [_P, _P, _P, ctypes.POINTER(Stats)]),
+    "ofm_residual": (_I, [_P, _P, _P, ctypes.POINTER(Stats)]),
+    "ofm_get_stats": (_I, [_P, _P, ctypes.POINTER(Stats)]),
+    "ofm_get_state": (_I, [_P, _P, _P, _P]),
+    "ofm_set_state": (_I, [_P, _P, _P, _P, _I64, _P]),
+    "ofm_get_step_info": (_I, [_P, _P, _P, _P, _P, _P]),
+    "ofm_get_products": (_I, [_P, _I, _P, _P]),
+    "ofm_set_timing": (_I, [_P, _I]),
+    "ofm_get_timing": (_I, [_P, _P, _P, _I]),
+    "ofm_row_normalize": (_I, [_I64, _I, _I, _P, _P, _P]),
+    "ofm_kmeans_assign": (_I, [_I64, _I, _I, _P, _P, _P, _P, _P]),
+    "ofm_kmeans": (_I, [_I64, _I, _I, _P, _P, _I, _P, _P, _P, _P]),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load libofm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libofm.so not built at {path}; run paper_2305_10356_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise OfmError(status, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _prec(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return OFM_FP64
+    if t.dtype == torch.float32:
+        return OFM_FP32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _dev_block(t, k: Optional[int] = None):
+    torch = _torch()
+    if not (t.is_cuda and t.dim() == 2 and t.is_contiguous()):
+        raise ValueError("expected a contiguous 2-D device tensor")
+    if t.dtype not in (torch.float32, torch.float64):
+        raise TypeError("expected float32 or float64")
+    if k is not None and t.shape[1] != k:
+        raise ValueError(f"expected {k} columns")
+    return t
+
+
+class Laplacian:
+    """Handle of the shifted normalized Laplacian A = L - 2I of a graph."""
+
+    def __init__(self, row_ptr, col_idx, vals=None, validate: bool = False,
+                 reorder: bool = True, stream=None):
+        torch = _torch()
+        lib = load()
+        self._lib = lib
+        rp = torch.as_tensor(row_ptr, dtype=torch.int32).contiguous().cuda()
+        ci = torch.as_tensor(col_idx, dtype=torch.int32).contiguous().cuda()
+        vv = None if vals is None else torch.as_tensor(vals, dtype=torch.float64).contiguous().cuda()
+        n = rp.numel() - 1
+        flags = (OFM_LAP_VALIDATE if validate else 0) | (0 if reorder else OFM_LAP_NO_REORDER)
+        h = ctypes.c_void_p()
+        st = lib.ofm_build_laplacian(n, ci.numel(), _ptr(rp), _ptr(ci) if ci.numel() else None,
+                                     _ptr(vv) if vv is not None else None, flags, _stream(stream),
+                                     ctypes.byref(h))
+        _check(st, "ofm_build_laplacian")
+        self.handle = h
+        self.n = n
+        self.nnz = ci.numel()
+
+    def info(self):
+        n = ctypes.c_int64()
+        nnz = ctypes.c_int64()
+        na = ctypes.c_double()
+        deg = np.zeros(self.n, dtype=np.float64)
+        _check(self._lib.ofm_laplacian_info(self.handle, ctypes.byref(n), ctypes.byref(nnz),
+                                            ctypes.byref(na), deg.ctypes.data_as(ctypes.c_void_p)),
+               "ofm_laplacian_info")
+        return {"n": n.value, "nnz": nnz.value, "normA2": na.value, "degrees": deg}
+
+    def apply(self, Z, Y=None, stream=None):
+        """Y = A Z (same dtype as Z)."""
+        torch = _torch()
+        _dev_block(Z)
+        if Y is None:
+            Y = torch.empty_like(Z)
+        _check(self._lib.ofm_apply_A(self.handle, Z.shape[1], _prec(Z), _ptr(Z), _ptr(Y),
+                                     _stream(stream)), "ofm_apply_A")
+        return Y
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self._lib.ofm_laplacian_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Workspace:
+    """Iteration state of Algorithm 2 for one graph, k and option set."""
+
+    def __init__(self, lap: Laplacian, k: int, variant="f1", precision=OFM_FP32,
+                 max_iter: int = 1000, check_every: int = 10, first_step: int = 0,
+                 restart: bool = False, alpha0: float = 0.0, tol: float = 0.0):
+        lib = load()
+        self._lib = lib
+        self.lap = lap
+        self.k = k
+        v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        self.opts = Opts(v, int(precision), int(max_iter), int(check_every), int(first_step),
+                         1 if restart else 0, float(alpha0), float(tol))
+        h = ctypes.c_void_p()
+        _check(lib.ofm_workspace_create(lap.handle, k, ctypes.byref(self.opts), ctypes.byref(h)),
+               "ofm_workspace_create")
+        self.handle = h
+
+    @property
+    def dtype(self):
+        torch = _torch()
+        return torch.float64 if self.opts.precision == OFM_FP64 else torch.float32
+
+    def _x(self, X):
+        _dev_block(X, self.k)
+        if X.dtype != self.dtype or X.shape[0] != self.lap.n:
+            raise ValueError("X must be N x k of the workspace precision")
+        return X
+
+    def init(self, X, stream=None):
+        _check(self._lib.ofm_init(self.handle, _ptr(self._x(X)), _stream(stream)), "ofm_init")
+
+    def step(self, X, stream=None):
+        _check(self._lib.ofm_step(self.handle, _ptr(self._x(X)), _stream(stream)), "ofm_step")
+
+    def solve(self, X, stream=None) -> dict:
+        st = Stats()
+        r = self._lib.ofm_solve(self.handle, _ptr(self._x(X)), _stream(stream), ctypes.byref(st))
+        if r not in (0, -4, -5):
+            _check(r, "ofm_solve")
+        return st.as_dict()
+
+    def residual(self, X, stream=None) -> dict:
+        st = Stats()
+        r = self._lib.ofm_residual(self.handle, _ptr(self._x(X)), _stream(stream), ctypes.byref(st))
+        if r not in (0, -4, -5):
+            _check(r, "ofm_residual")
+        return st.as_dict()
+
+    def stats(self, stream=None) -> dict:
+        st = Stats()
+        self._lib.ofm_get_stats(self.handle, _stream(stream), ctypes.byref(st))
+        return st.as_dict()
+
+    def get_state(self, stream=None):
+        torch = _torch()
+        Vp = torch.empty((self.lap.n, self.k), dtype=self.dtype, device="cuda")
+        Gp = torch.empty_like(Vp)
+        _check(self._lib.ofm_get_state(self.handle, _ptr(Vp), _ptr(Gp), _stream(stream)),
+               "ofm_get_state")
+        return Vp, Gp
+
+    def set_state(self, X, V_prev, G_prev, t: int, stream=None):
+        for a in (X, V_prev, G_prev):
+            self._x(a)
+        _check(self._lib.ofm_set_state(self.handle, _ptr(X), _ptr(V_prev), _ptr(G_prev), int(t),
+                                       _stream(stream)), "ofm_set_state")
+
+    def step_info(self, stream=None) -> dict:
+        k = self.k
+        alpha = np.zeros(k)
+        beta = np.zeros(k)
+        coef = np.zeros(4 * k)
+        nr = np.zeros(k, dtype=np.int32)
+        _check(self._lib.ofm_get_step_info(
+            self.handle, alpha.ctypes.data_as(ctypes.c_void_p), beta.ctypes.data_as(ctypes.c_void_p),
+            coef.ctypes.data_as(ctypes.c_void_p), nr.ctypes.data_as(ctypes.c_void_p),
+            _stream(stream)), "ofm_get_step_info")
+        return {"alpha": alpha, "beta": beta, "coeffs": coef.reshape(k, 4).T.copy(), "nroots": nr}
+
+    PASSES = ["spmm_x", "g", "v", "spmm_v", "linesearch", "update", "reduce", "residual", "other"]
+
+    def set_timing(self, enable: bool = True):
+        _check(self._lib.ofm_set_timing(self.handle, 1 if enable else 0), "ofm_set_timing")
+
+    def timing(self, reset: bool = True) -> dict:
+        """{pass: (total ms, launches)} since the last reset (synchronizing)."""
+        ms = np.zeros(len(self.PASSES))
+        cnt = np.zeros(len(self.PASSES), dtype=np.int64)
+        _check(self._lib.ofm_get_timing(self.handle, ms.ctypes.data_as(ctypes.c_void_p),
+                                        cnt.ctypes.data_as(ctypes.c_void_p), 1 if reset else 0),
+               "ofm_get_timing")
+        return {p: (float(ms[i]), int(cnt[i])) for i, p in enumerate(self.PASSES)}
+
+    PRODUCTS = {"M": 0, "H": 1, "K": 2, "P": 3, "C": 4, "E": 5, "F": 6}
+
+    def product(self, name: str, stream=None) -> np.ndarray:
+        """Host copy of one k x k product (X^T X = "M", X^T A X = "H", ...)."""
+        out = np.zeros((self.k, self.k))
+        _check(self._lib.ofm_get_products(self.handle, self.PRODUCTS[name],
+                                          out.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+               "ofm_get_products")
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self._lib.ofm_workspace_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def row_normalize(X, Y=None, stream=None):
+    torch = _torch()
+    _dev_block(X)
+    if Y is None:
+        Y = torch.empty_like(X)
+    _check(load().ofm_row_normalize(X.shape[0], X.shape[1], _prec(X), _ptr(X), _ptr(Y),
+                                    _stream(stream)), "ofm_row_normalize")
+    return Y
+
+
+def kmeans_assign(Y, centroids, want_dist: bool = False, stream=None):
+    torch = _torch()
+    _dev_block(Y)
+    n, dim = Y.shape
+    labels = torch.empty(n, dtype=torch.int32, device=Y.device)
+    d2 = torch.empty(n, dtype=torch.float32, device=Y.device) if want_dist else None
+    _check(load().ofm_kmeans_assign(n, dim, centroids.shape[0], _ptr(Y), _ptr(centroids),
+                                    _ptr(labels), _ptr(d2) if d2 is not None else None,
+                                    _stream(stream)), "ofm_kmeans_assign")
+    return (labels, d2) if want_dist else labels
+
+
+def kmeans(Y, n_clusters: int, uniforms, max_iter: int = 300, stream=None):
+    """K-means++ seeded by ``uniforms`` then Lloyd; returns (labels, centroids, iters)."""
+    torch = _torch()
+    _dev_block(Y)
+    n, dim = Y.shape
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    if u.shape[0] < n_clusters:
+        raise ValueError("need one uniform per cluster")
+    labels = torch.empty(n, dtype=torch.int32, device=Y.device)
+    cent = torch.empty((n_clusters, dim), dtype=torch.float32, device=Y.device)
+    iters = ctypes.c_int32()
+    _check(load().ofm_kmeans(n, dim, n_clusters, _ptr(Y), u.ctypes.data_as(ctypes.c_void_p),
+                             max_iter, _ptr(labels), _ptr(cent), ctypes.byref(iters),
+                             _stream(stream)), "ofm_kmeans")
+    return labels, cent, iters.value

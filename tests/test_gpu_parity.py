@@ -1,0 +1,422 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 path 1e-10 relative, FP32 path 1e-4 relative (to the largest
+magnitude of the compared quantity).  The iteration is chaotic before it
+converges (a 1e-15 perturbation grows by roughly e^{0.3} per step), so
+iterates are compared step by step from the same state (teacher forcing),
+in a short free-running window, and through the limits of Theorems 1-4."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ofm_oracle as O
+from paper_2305_10356_amd import graphs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+VARS = [("f1", O.F1), ("tri-f1", O.TRI_F1), ("f2", O.F2), ("tri-f2", O.TRI_F2)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ofm(lib):
+    from paper_2305_10356_amd import ofm as m
+    return m
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def c1():
+    g, x0 = graphs.config_graph(1)
+    return g, x0, O.laplacian(g.n, g.row_ptr, g.col_idx)
+
+
+@pytest.fixture(scope="module")
+def c1_lap(ofm, c1):
+    g, x0, _ = c1
+    return ofm.Laplacian(g.row_ptr, g.col_idx)
+
+
+def hub_graph(n=3000, seed=3):
+    # a hub joined to every node (degree n-1 > one heavy tile), plus a sparse
+    # random graph with a degree spread around the heavy threshold
+    rng = np.random.default_rng(seed)
+    u = [np.zeros(n - 1, dtype=np.int64), rng.integers(1, n, size=20 * n)]
+    v = [np.arange(1, n, dtype=np.int64), rng.integers(1, n, size=20 * n)]
+    hubs = rng.integers(1, n, size=40)
+    for h in hubs:
+        u.append(np.full(150, h))
+        v.append(rng.integers(1, n, size=150))
+    u = np.concatenate(u)
+    v = np.concatenate(v)
+    keep = u != v
+    a = np.concatenate([u[keep], v[keep]])
+    b = np.concatenate([v[keep], u[keep]])
+    key = np.unique(a * n + b)
+    rows, cols = key // n, key % n
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, rows + 1, 1)
+    return np.cumsum(rp).astype(np.int32), cols.astype(np.int32)
+
+
+# ---------------------------------------------------------------------------
+# Laplacian and A Z
+# ---------------------------------------------------------------------------
+
+def test_laplacian_info(ofm, c1, c1_lap):
+    g, x0, lap = c1
+    info = c1_lap.info()
+    np.testing.assert_array_equal(info["degrees"], lap.d)
+    assert info["normA2"] == pytest.approx(O.norm_A_fro_sq(lap), rel=1e-12)
+
+
+@pytest.mark.parametrize("reorder", [True, False])
+@pytest.mark.parametrize("k", [4, 8, 16, 32, 64])
+def test_apply_A_graphs(ofm, k, reorder):
+    cases = []
+    g, _ = graphs.config_graph(1)
+    cases.append(("sbm1000", g.row_ptr, g.col_idx))
+    g3, _ = graphs.config_graph(3, n=20000)
+    cases.append(("dcsbm20000", g3.row_ptr, g3.col_idx))
+    rp, ci = hub_graph()
+    cases.append(("hub3000", rp, ci))
+    rng = np.random.default_rng(k)
+    for name, rp, ci in cases:
+        n = rp.shape[0] - 1
+        say(f"apply_A {name} k={k} reorder={reorder}")
+        olap = O.laplacian(n, rp, ci)
+        glap = ofm.Laplacian(rp, ci, reorder=reorder)
+        Z = rng.standard_normal((n, k))
+        ref = O.apply_A(olap, Z)
+        if k <= 32:
+            y64 = host(glap.apply(dev(Z, torch.float64)))
+            assert rel(y64, ref) < 1e-13, (name, "fp64")
+        Z32 = Z.astype(np.float32)
+        y32 = host(glap.apply(dev(Z32, torch.float32)))
+        assert rel(y32, O.apply_A(olap, Z32.astype(np.float64))) < 1e-6, (name, "fp32")
+
+
+def test_laplacian_errors(ofm):
+    # isolated node
+    rp = np.array([0, 1, 2, 2], dtype=np.int32)
+    ci = np.array([1, 0], dtype=np.int32)
+    with pytest.raises(ofm.OfmError) as e:
+        ofm.Laplacian(rp, ci)
+    assert e.value.status == -3
+    # column out of range
+    with pytest.raises(ofm.OfmError) as e:
+        ofm.Laplacian(np.array([0, 1, 2], dtype=np.int32), np.array([1, 5], dtype=np.int32))
+    assert e.value.status == -3
+    # asymmetric pattern is caught only when validating
+    rp = np.array([0, 2, 3, 4], dtype=np.int32)
+    ci = np.array([1, 2, 0, 1], dtype=np.int32)
+    ofm.Laplacian(rp, ci)
+    with pytest.raises(ofm.OfmError) as e:
+        ofm.Laplacian(rp, ci, validate=True)
+    assert e.value.status == -3
+    # symmetric graph passes validation; weights enter the degrees
+    rp = np.array([0, 1, 3, 4], dtype=np.int32)
+    ci = np.array([1, 0, 2, 1], dtype=np.int32)
+    lap = ofm.Laplacian(rp, ci, vals=np.array([2.0, 2.0, 3.0, 3.0]), validate=True)
+    np.testing.assert_allclose(lap.info()["degrees"], [2.0, 5.0, 3.0])
+
+
+def test_workspace_shape_errors(ofm, c1_lap):
+    with pytest.raises(ofm.OfmError) as e:
+        ofm.Workspace(c1_lap, 5)
+    assert e.value.status == -2
+    with pytest.raises(ofm.OfmError) as e:
+        ofm.Workspace(c1_lap, 64, precision=ofm.OFM_FP64)
+    assert e.value.status == -8
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2, one step at a time from the same state
+# ---------------------------------------------------------------------------
+
+def teacher_forced(ofm, glap, olap, x0, variant, vid, precision, checkpoints, tol, restart=False):
+    dt = torch.float64 if precision == ofm.OFM_FP64 else torch.float32
+    k = x0.shape[1]
+    opts = O.Options(variant=vid, restart=restart)
+    ws = ofm.Workspace(glap, k, variant=variant, precision=precision, restart=restart,
+                       check_every=1000000)
+    X = dev(x0.astype(np.float32) if dt == torch.float32 else x0, dt)
+    X0h = host(X)
+    ws.init(X)
+    st_o, info_o = O.init(olap, X0h, opts)
+    gi = ws.step_info()
+    assert rel(host(X), st_o.X) < tol, "init X"
+    assert rel(gi["alpha"], info_o["alpha"]) < tol * 10, "init alpha"
+    worst = 0.0
+    for t in range(1, max(checkpoints) + 1):
+        if t in checkpoints:
+            Xh = host(X)
+            Vp, Gp = ws.get_state()
+            state = O.State(X=Xh, V_prev=host(Vp), G_prev=host(Gp), t=t)
+            st_o, info_o = O.step(olap, state, opts)
+            ws.step(X)
+            gi = ws.step_info()
+            ex = rel(host(X), st_o.X)
+            # step scalars are compared where they are determined by the data:
+            # once a column's direction is at the rounding floor
+            # (||G_i|| <= 1e-6 ||AX_i||) its alpha_i and beta_i are set by
+            # rounding noise on both sides, while alpha_i V_i stays negligible
+            gn = np.linalg.norm(info_o["G"], axis=0)
+            an = np.linalg.norm(info_o["AX"], axis=0)
+            live = gn > 1e-6 * an if O.is_tri(vid) else np.full(k, gn.sum() > 1e-6 * an.sum())
+            ea = rel(gi["alpha"][live], info_o["alpha"][live]) if live.any() else 0.0
+            eb = rel(gi["beta"][live], info_o["beta"][live]) if live.any() else 0.0
+            say(f"  {variant} t={t} dX={ex:.2e} dalpha={ea:.2e} dbeta={eb:.2e} live={int(live.sum())}")
+            assert ex < tol, (variant, t, "X")
+            if precision == ofm.OFM_FP64 and live.any():
+                assert ea < 1e-8 and eb < 1e-8, (variant, t)
+                co = O.VARIANT_NAMES[vid]
+                if O.is_tri(vid):
+                    assert rel(gi["coeffs"][:, live], info_o["coeffs"][:, live]) < 1e-8, co
+                else:
+                    assert rel(gi["coeffs"][:, 0], info_o["coeffs"]) < 1e-8, co
+            worst = max(worst, ex)
+        else:
+            ws.step(X)
+    return worst
+
+
+@pytest.mark.parametrize("variant,vid", VARS)
+def test_teacher_forced_fp64_c1(ofm, c1, c1_lap, variant, vid):
+    g, x0, olap = c1
+    say(f"teacher-forced FP64 C1 {variant}")
+    teacher_forced(ofm, c1_lap, olap, x0, variant, vid, ofm.OFM_FP64,
+                   {1, 2, 5, 10, 20, 50, 100, 200, 499}, 1e-10,
+                   restart=(vid == O.TRI_F1))
+
+
+@pytest.mark.parametrize("variant,vid", VARS)
+def test_teacher_forced_fp32_c2(ofm, variant, vid):
+    g, x0 = graphs.config_graph(2)
+    olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
+    glap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    say(f"teacher-forced FP32 C2 {variant}")
+    teacher_forced(ofm, glap, olap, x0, variant, vid, ofm.OFM_FP32, {1, 2, 5, 10, 20, 40}, 1e-4,
+                   restart=(vid == O.TRI_F1))
+
+
+@pytest.mark.parametrize("k", [4, 16, 64])
+def test_teacher_forced_fp32_widths(ofm, k):
+    g, _ = graphs.config_graph(3, n=20000)
+    x0 = graphs.initial_x(g.n, k, np.random.default_rng([9, k]))
+    olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
+    glap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    for variant, vid in VARS:
+        say(f"teacher-forced FP32 k={k} {variant}")
+        teacher_forced(ofm, glap, olap, x0, variant, vid, ofm.OFM_FP32, {1, 3, 8}, 1e-4)
+
+
+@pytest.mark.parametrize("k", [4, 16, 32])
+def test_teacher_forced_fp64_widths(ofm, k):
+    g, _ = graphs.config_graph(3, n=8000)
+    x0 = graphs.initial_x(g.n, k, np.random.default_rng([8, k]))
+    olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
+    glap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    for variant, vid in VARS:
+        say(f"teacher-forced FP64 k={k} {variant}")
+        teacher_forced(ofm, glap, olap, x0, variant, vid, ofm.OFM_FP64, {1, 3, 8}, 1e-10)
+
+
+@pytest.mark.parametrize("variant,vid", VARS)
+def test_free_running_window_fp64(ofm, c1, c1_lap, variant, vid):
+    g, x0, olap = c1
+    ws = ofm.Workspace(c1_lap, 8, variant=variant, precision=ofm.OFM_FP64, check_every=1000000)
+    X = dev(x0, torch.float64)
+    ws.init(X)
+    st, _ = O.init(olap, x0, O.Options(variant=vid))
+    for t in range(1, 20):
+        ws.step(X)
+        st, _ = O.step(olap, st, O.Options(variant=vid))
+    err = rel(host(X), st.X)
+    say(f"free-running FP64 {variant} t=20 err={err:.2e}")
+    assert err < 1e-10
+
+
+def test_first_step_fixed(ofm, c1, c1_lap):
+    g, x0, olap = c1
+    ws = ofm.Workspace(c1_lap, 8, variant="f1", precision=ofm.OFM_FP64, first_step=1, alpha0=0.05)
+    X = dev(x0, torch.float64)
+    ws.init(X)
+    st, _ = O.init(olap, x0, O.Options(variant=O.F1, first_step="fixed", alpha0=0.05))
+    assert rel(host(X), st.X) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Convergence, limits, residual
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant,vid", VARS)
+def test_solve_limits_fp64_c1(ofm, c1, c1_lap, variant, vid):
+    g, x0, olap = c1
+    mu, U = O.dense_eigh(olap)
+    k = 8
+    restart = O.is_tri(vid)
+    ws = ofm.Workspace(c1_lap, k, variant=variant, precision=ofm.OFM_FP64, max_iter=500,
+                       check_every=10, tol=1e-9, restart=restart)
+    X = dev(x0, torch.float64)
+    st = ws.solve(X)
+    Xh = host(X)
+    rr_o = O.relres(olap, Xh)
+    rr_g = ws.residual(X)["relres"]
+    say(f"solve {variant}: iters={st['iters']} relres gpu={rr_g:.2e} oracle={rr_o:.2e}")
+    assert st["status"] == 0
+    assert rr_o < 1e-7
+    assert abs(rr_g - rr_o) < 1e-7
+    Uk = U[:, :k]
+    if vid in (O.F1, O.TRI_F1):
+        target = (Uk * (2.0 - mu[:k])[None, :]) @ Uk.T
+        np.testing.assert_allclose(Xh @ Xh.T, target, atol=1e-6)
+    else:
+        np.testing.assert_allclose(Xh @ Xh.T, Uk @ Uk.T, atol=1e-6)
+    # labels from the device K-means match the oracle's on the same features
+    Y = ofm.row_normalize(X.float().contiguous())
+    u = O.kmeans_uniforms(0, k)
+    lab_g, _, _ = ofm.kmeans(Y, k, u)
+    lab_o, _, _ = O.kmeans_lloyd(O.row_normalize(Xh),
+                                 O.kmeanspp_init(O.row_normalize(Xh), k, u))
+    assert O.ari(lab_g.cpu().numpy(), lab_o) > 0.99
+    assert O.ari(lab_g.cpu().numpy(), g.labels) > 0.7
+
+
+def test_residual_matches_oracle(ofm, c1, c1_lap):
+    g, x0, olap = c1
+    ws = ofm.Workspace(c1_lap, 8, variant="f2", precision=ofm.OFM_FP64)
+    for X in (x0, O.run(olap, x0, 15, O.Options(variant=O.F2))[0].X):
+        r = ws.residual(dev(X, torch.float64))
+        assert r["relres"] == pytest.approx(O.relres(olap, X), rel=1e-9)
+        assert r["objective"] == pytest.approx(O.objective(O.F2, olap, X), rel=1e-12)
+    ws1 = ofm.Workspace(c1_lap, 8, variant="f1", precision=ofm.OFM_FP64)
+    r = ws1.residual(dev(x0, torch.float64))
+    assert r["objective"] == pytest.approx(O.objective(O.F1, olap, x0), rel=1e-12)
+
+
+def test_solve_fp32_c2_reaches_tolerance(ofm):
+    g, x0 = graphs.config_graph(2)
+    glap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
+    ws = ofm.Workspace(glap, 32, variant="f1", precision=ofm.OFM_FP32, max_iter=2000,
+                       check_every=10, tol=1e-4)
+    X = dev(x0.astype(np.float32), torch.float32)
+    st = ws.solve(X)
+    rr = O.relres(olap, host(X))
+    say(f"C2 FP32 f1: iters={st['iters']} relres gpu={st['relres']:.2e} oracle(final X)={rr:.2e}")
+    assert st["converged"] == 1
+    assert rr < 2e-4
+
+
+def test_nonfinite_input_is_reported(ofm, c1, c1_lap):
+    g, x0, olap = c1
+    x = x0.copy()
+    x[3, 2] = np.nan
+    ws = ofm.Workspace(c1_lap, 8, variant="f1", precision=ofm.OFM_FP64, max_iter=5, check_every=1)
+    st = ws.solve(dev(x, torch.float64))
+    assert st["status"] == -4
+    assert st["iters"] <= 2
+
+
+def test_determinism_fp32(ofm):
+    g, x0 = graphs.config_graph(3, n=40000)
+    glap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    x0 = graphs.initial_x(g.n, 32, np.random.default_rng(4)).astype(np.float32)
+    outs = []
+    for _ in range(2):
+        ws = ofm.Workspace(glap, 32, variant="f2", precision=ofm.OFM_FP32, check_every=5)
+        X = dev(x0, torch.float32)
+        ws.init(X)
+        for _ in range(20):
+            ws.step(X)
+        outs.append(X.cpu().numpy().copy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+# ---------------------------------------------------------------------------
+# Post-processing
+# ---------------------------------------------------------------------------
+
+def test_row_normalize_and_assign(ofm):
+    rng = np.random.default_rng(0)
+    for dt, tol in ((torch.float64, 1e-15), (torch.float32, 1e-6)):
+        X = rng.standard_normal((3001, 32))
+        X[7] = 0.0
+        Y = host(ofm.row_normalize(dev(X, dt)))
+        assert rel(Y, O.row_normalize(X.astype(np.float32) if dt == torch.float32 else X)) < tol
+        assert np.all(Y[7] == 0.0)
+    Y = rng.standard_normal((5000, 16)).astype(np.float32)
+    C = rng.standard_normal((10, 16)).astype(np.float32)
+    lab, d2 = ofm.kmeans_assign(dev(Y, torch.float32), dev(C, torch.float32), want_dist=True)
+    lab = lab.cpu().numpy()
+    D = O.kmeans_dist2(Y, C)
+    best = D.min(axis=1)
+    srt = np.sort(D, axis=1)
+    clear = (srt[:, 1] - srt[:, 0]) > 1e-5 * srt[:, 1]
+    assert np.array_equal(lab[clear], np.argmin(D, axis=1)[clear])
+    # near ties: the chosen centre is (within rounding) a nearest one
+    assert np.all(D[np.arange(len(lab)), lab] <= best * (1 + 1e-5) + 1e-6)
+    np.testing.assert_allclose(host(d2), best, rtol=1e-5)
+
+
+def test_kmeans_matches_oracle_on_blobs(ofm):
+    rng = np.random.default_rng(3)
+    centers = rng.standard_normal((6, 8)) * 5
+    truth = rng.integers(0, 6, size=4000)
+    Y = (centers[truth] + rng.standard_normal((4000, 8))).astype(np.float32)
+    u = O.kmeans_uniforms(1, 6)
+    lab_g, cent_g, it_g = ofm.kmeans(dev(Y, torch.float32), 6, u)
+    lab_o, cent_o, it_o = O.kmeans_lloyd(Y.astype(np.float64),
+                                         O.kmeanspp_init(Y.astype(np.float64), 6, u))
+    assert O.ari(lab_g.cpu().numpy(), lab_o) == pytest.approx(1.0)
+    assert abs(it_g - it_o) <= 1
+    np.testing.assert_allclose(host(cent_g), cent_o, atol=1e-4)
+
+
+@pytest.mark.parametrize("k,dt", [(8, "fp64"), (32, "fp64"), (32, "fp32"), (64, "fp32"), (4, "fp32")])
+def test_products_match_oracle(ofm, k, dt):
+    # k x k products of one init step: X^T X of the new X; V^T V, X^T V of the
+    # first direction; X^T A V, V^T A V (f2) -- each against a plain product
+    g, _ = graphs.config_graph(3, n=6000)
+    olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
+    glap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    x0 = graphs.initial_x(g.n, k, np.random.default_rng([7, k]))
+    prec = ofm.OFM_FP64 if dt == "fp64" else ofm.OFM_FP32
+    tdt = torch.float64 if dt == "fp64" else torch.float32
+    tol = 1e-12 if dt == "fp64" else 1e-6
+    ws = ofm.Workspace(glap, k, variant="f2", precision=prec)
+    X = dev(x0, tdt)
+    X0 = host(X)
+    ws.init(X)
+    V0, G0 = ws.get_state()
+    V0 = host(V0)
+    X1 = host(X)
+    AV = O.apply_A(olap, V0)
+    assert rel(ws.product("M"), X1.T @ X1) < tol
+    assert rel(ws.product("P"), V0.T @ V0) < tol
+    assert rel(ws.product("C"), X0.T @ V0) < tol
+    assert rel(ws.product("E"), X0.T @ AV) < tol * 10
+    assert rel(ws.product("F"), V0.T @ AV) < tol * 10
+    assert rel(ws.product("H"), X0.T @ O.apply_A(olap, X0)) < tol * 10
