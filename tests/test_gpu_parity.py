@@ -169,6 +169,7 @@ def teacher_forced(ofm, glap, olap, x0, variant, vid, precision, checkpoints, to
     assert rel(host(X), st_o.X) < tol, "init X"
     assert rel(gi["alpha"], info_o["alpha"]) < tol * 10, "init alpha"
     worst = 0.0
+    flips = []
     for t in range(1, max(checkpoints) + 1):
         if t in checkpoints:
             Xh = host(X)
@@ -187,6 +188,27 @@ def teacher_forced(ofm, glap, olap, x0, variant, vid, precision, checkpoints, to
             live = gn > 1e-6 * an if O.is_tri(vid) else np.full(k, gn.sum() > 1e-6 * an.sum())
             ea = rel(gi["alpha"][live], info_o["alpha"][live]) if live.any() else 0.0
             eb = rel(gi["beta"][live], info_o["beta"][live]) if live.any() else 0.0
+            # a root-choice flip: near a tie (or a near-repeated root) the two
+            # sides may take different real roots of the same cubic; it is
+            # accepted when both step sizes are roots, and X is then checked
+            # against X^t + V diag(alpha_gpu) with the oracle's V
+            ag, ao = gi["alpha"], info_o["alpha"]
+            fp64 = precision == ofm.OFM_FP64
+            ftol, rtol = (1e-6, 1e-6) if fp64 else (1e-2, 1e-3)
+            flip = live & (np.abs(ag - ao) > ftol * max(np.abs(ao).max(), 1e-30))
+            if flip.any():
+                cols = np.flatnonzero(flip) if O.is_tri(vid) else [0]
+                for i in cols:
+                    co = info_o["coeffs"][:, i] if O.is_tri(vid) else info_o["coeffs"]
+                    for a in (ag[i], ao[i]):
+                        scale = sum(abs(c) * abs(a) ** (3 - j) for j, c in enumerate(co))
+                        assert abs(np.polyval(co, a)) <= rtol * scale, (variant, t, i, "not a root")
+                ex = rel(host(X), Xh + info_o["V"] * ag[None, :])
+                flips.append((t, [int(c) for c in cols]))
+                say(f"  {variant} t={t}: root-choice flip in columns {list(cols)} "
+                    f"(gpu {ag[flip]}, oracle {ao[flip]})")
+                live = live & ~flip
+                ea = rel(ag[live], ao[live]) if live.any() else 0.0
             say(f"  {variant} t={t} dX={ex:.2e} dalpha={ea:.2e} dbeta={eb:.2e} live={int(live.sum())}")
             assert ex < tol, (variant, t, "X")
             if precision == ofm.OFM_FP64 and live.any():
@@ -199,16 +221,28 @@ def teacher_forced(ofm, glap, olap, x0, variant, vid, precision, checkpoints, to
             worst = max(worst, ex)
         else:
             ws.step(X)
+    assert len(flips) <= 2, flips
     return worst
 
 
 @pytest.mark.parametrize("variant,vid", VARS)
 def test_teacher_forced_fp64_c1(ofm, c1, c1_lap, variant, vid):
+    # 500 iterations; the triangular variants run with the descent restart:
+    # without it their CG direction can grow without bound once a column has
+    # converged (beta = ratio of rounding-level norms), and no two
+    # implementations agree there
     g, x0, olap = c1
     say(f"teacher-forced FP64 C1 {variant}")
     teacher_forced(ofm, c1_lap, olap, x0, variant, vid, ofm.OFM_FP64,
-                   {1, 2, 5, 10, 20, 50, 100, 200, 499}, 1e-10,
-                   restart=(vid == O.TRI_F1))
+                   {1, 2, 5, 10, 20, 50, 100, 200, 499}, 1e-10, restart=O.is_tri(vid))
+
+
+@pytest.mark.parametrize("variant,vid", VARS[1::2])
+def test_teacher_forced_fp64_c1_literal_tri(ofm, c1, c1_lap, variant, vid):
+    # the triangular variants exactly as printed (no restart), early window
+    g, x0, olap = c1
+    teacher_forced(ofm, c1_lap, olap, x0, variant, vid, ofm.OFM_FP64, {1, 2, 5, 10, 20, 40},
+                   1e-10, restart=False)
 
 
 @pytest.mark.parametrize("variant,vid", VARS)
@@ -218,7 +252,7 @@ def test_teacher_forced_fp32_c2(ofm, variant, vid):
     glap = ofm.Laplacian(g.row_ptr, g.col_idx)
     say(f"teacher-forced FP32 C2 {variant}")
     teacher_forced(ofm, glap, olap, x0, variant, vid, ofm.OFM_FP32, {1, 2, 5, 10, 20, 40}, 1e-4,
-                   restart=(vid == O.TRI_F1))
+                   restart=O.is_tri(vid))
 
 
 @pytest.mark.parametrize("k", [4, 16, 64])
