@@ -226,6 +226,20 @@ ofm_status ofm_get_step_info(ofm_workspace ws, double* host_alpha, double* host_
 ofm_status ofm_get_products(ofm_workspace ws, int which, double* host_kxk, hipStream_t stream);
 
 /*
+ * Objective and gradient (Sections 2.1 and 2.2) for the differentiable
+ * variants of the workspace:
+ *   OFM_F1: f1(X) = ||A + X X^T||_F^2,            grad = 4AX + 4X X^T X
+ *   OFM_F2: f2(X) = tr((2I - X^T X) X^T A X),    grad = 4AX - 2X X^T A X - 2AX X^T X
+ * (eqs. gradientf1, gradientf2).  The triangular directions g1, g2 are not
+ * gradients of any function (Section 2.1), so the TRI variants return
+ * OFM_E_UNSUPPORTED.  X, grad: N x k device arrays of the workspace precision
+ * (grad may be NULL); f_out: one FP64 in device memory.  Asynchronous; uses
+ * the workspace's product buffers (call it between iterations, not inside).
+ */
+ofm_status ofm_objective(ofm_workspace ws, const void* X, double* f_out, void* grad,
+                         hipStream_t stream);
+
+/*
  * Per-pass device timing with HIP events recorded on the caller's stream
  * around every kernel the workspace launches (off by default; recording adds
  * a few microseconds of host time per launch and nothing on the device).

@@ -694,6 +694,37 @@ extern "C" ofm_status ofm_residual(ofm_workspace ws, const void* X, hipStream_t 
   return (ofm_status)st.status;
 }
 
+extern "C" ofm_status ofm_objective(ofm_workspace ws, const void* X, double* f_out, void* grad,
+                                    hipStream_t stream) {
+  if (!ws || !X || !f_out) return OFM_E_INVALID_ARG;
+  if (ws->opts.variant == OFM_TRI_F1 || ws->opts.variant == OFM_TRI_F2) return OFM_E_UNSUPPORTED;
+  // without a caller buffer the gradient goes to the current-direction slot,
+  // which the next step overwrites anyway (the CG state is in the other slot)
+  void* gout = grad ? grad : ws->G[ws->cur];
+  OFMCHK(gram_m(ws, X, stream));
+  if (ws->opts.variant == OFM_F1) {
+    // the residual variant of the pass also forms X^T A X for the objective
+    PassArgs a = base_args(ws, kGF1, kFlagCheck);
+    a.Z = X;
+    a.G = gout;
+    OFMCHK(run_spmm(ws, a, stream));
+  } else {
+    PassArgs a = base_args(ws, kAXF2, 0);
+    a.Z = X;
+    a.Y = ws->AX;
+    OFMCHK(run_spmm(ws, a, stream));
+    PassArgs b = base_args(ws, kGPassF2, 0);
+    b.X = X;
+    b.AX = ws->AX;
+    b.G = gout;
+    OFMCHK(run_dense(ws, b, stream));
+  }
+  HIPCHK(timed(ws, OFM_PASS_OTHER, stream, [&] {
+    return launch_objective(ws->k, ws->opts.variant, ws->lap->g.normA2, ws->sc, f_out, stream);
+  }));
+  return OFM_OK;
+}
+
 extern "C" ofm_status ofm_get_state(ofm_workspace ws, void* V_prev, void* G_prev,
                                     hipStream_t stream) {
   if (!ws || !V_prev || !G_prev) return OFM_E_INVALID_ARG;

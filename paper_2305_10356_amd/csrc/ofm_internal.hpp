@@ -11,7 +11,14 @@ namespace ofm {
 constexpr int kWave = 64;
 constexpr int kHeavyDeg = 64;     // rows of at least this degree use a whole wave
 constexpr int kHeavyTileNnz = 1024;
-constexpr int kMaxBlocks = 1024;  // persistent grid cap for reduction kernels
+#ifndef OFM_MAX_BLOCKS
+#define OFM_MAX_BLOCKS 1024
+#endif
+#ifndef OFM_GATHER_CH
+#define OFM_GATHER_CH 8
+#endif
+constexpr int kMaxBlocks = OFM_MAX_BLOCKS;  // persistent grid cap for reduction kernels
+constexpr int kGatherChunk = OFM_GATHER_CH; // entries in flight per lane group and pass
 constexpr int kFinChunk = 32;     // partial rows summed per first-level finalize block
 
 // Row-major N x KP tile geometry of a wave: each row is KP*sizeof(T) bytes,
@@ -138,6 +145,8 @@ hipError_t launch_linesearch(int k, int variant, int first, double alpha0, doubl
                              int* status, hipStream_t s);
 hipError_t launch_residual(int k, int variant, double normA2, double* sc, int* status,
                            hipStream_t s);
+hipError_t launch_objective(int k, int variant, double normA2, const double* sc, double* out,
+                            hipStream_t s);
 int tile_rows(int precision, int k);
 int pass_blocks(int precision, int k, int64_t ntiles);
 int partial_nv(int k, int mode, int flags);

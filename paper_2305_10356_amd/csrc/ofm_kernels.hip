@@ -177,7 +177,7 @@ __device__ inline void gather_rows(const typename EntT<T>::type* __restrict__ pk
                                    const T* __restrict__ Z, int e_first, int end, int cstride,
                                    int gbase, int j, V16<T>& acc) {
   using G = Geo<T, KP>;
-  constexpr int CH = G::LPR >= 8 ? G::LPR : 8;
+  constexpr int CH = G::LPR >= kGatherChunk ? G::LPR : kGatherChunk;
   constexpr int PER = CH / G::LPR;
   for (int e0 = e_first; e0 < end; e0 += cstride) {
     int col[PER];
@@ -406,7 +406,7 @@ __device__ inline bool all_finite(T x) {
 // SpMM with fused epilogues:  A Z = -Z - D^{-1/2} S D^{-1/2} Z
 // ---------------------------------------------------------------------------
 
-template <typename T, int KP, int MODE>
+template <typename T, int KP, int MODE, bool CHECK>
 __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
     spmm_kernel(PassArgs a) {
   using G = Geo<T, KP>;
@@ -423,7 +423,7 @@ __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
   T* tD = tZ + G::TILE_ELEMS;                                            // third tile
   int* trow = reinterpret_cast<int*>(wbase + SM::NB * G::TILE_ELEMS * sizeof(T));
 
-  const bool check = (a.flags & kFlagCheck) != 0;
+  constexpr bool check = CHECK;
   const bool restart = (a.flags & kFlagRestart) != 0;
   const T* __restrict__ Z = static_cast<const T*>(a.Z);
   const auto* __restrict__ pk = static_cast<const typename EntT<T>::type*>(a.pk);
@@ -465,7 +465,7 @@ __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
           V16<T> acc;
 #pragma unroll
           for (int q = 0; q < G::VECN; ++q) acc.v[q] = T(0);
-          gather_rows<T, KP>(pk, Z, beg, end, G::LPR >= 8 ? G::LPR : 8, g * G::LPR, j, acc);
+          gather_rows<T, KP>(pk, Z, beg, end, G::LPR >= kGatherChunk ? G::LPR : kGatherChunk, g * G::LPR, j, acc);
           const V16<T> z = ld16(Z + (size_t)row * KP + j * G::VECN);
 #pragma unroll
           for (int q = 0; q < G::VECN; ++q) acc.v[q] = -z.v[q] - acc.v[q];
@@ -488,7 +488,7 @@ __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
         const int p = start + gi;
         const int beg = a.sptr[p], end = a.sptr[p + 1];
         const int row = a.sched[p];
-        constexpr int CH = G::LPR >= 8 ? G::LPR : 8;
+        constexpr int CH = G::LPR >= kGatherChunk ? G::LPR : kGatherChunk;
         V16<T> acc;
 #pragma unroll
         for (int q = 0; q < G::VECN; ++q) acc.v[q] = T(0);
@@ -822,16 +822,22 @@ __global__ void __launch_bounds__(64) finalize_kernel(const double* __restrict__
   const int ny = gridDim.y;
   const int v = cx * 64 + threadIdx.x;
   const int b0 = cy * kFinChunk;
-  const int b1 = min(nb, b0 + kFinChunk);
+  // all loads of a level are issued before any addition; the sum then runs in
+  // block order
   double s = 0.0;
   if (v < nv) {
-    for (int b = b0; b < b1; ++b) s += partials[(size_t)b * nv + v];
-    lvl2[(size_t)cy * nv + v] = s;
+    double x[kFinChunk];
+#pragma unroll
+    for (int b = 0; b < kFinChunk; ++b)
+      x[b] = (b0 + b < nb) ? partials[(size_t)(b0 + b) * nv + v] : 0.0;
+#pragma unroll
+    for (int b = 0; b < kFinChunk; ++b) s += x[b];
   }
   if (ny == 1) {
     if (v < nv) out[v] = s;
     return;
   }
+  if (v < nv) lvl2[(size_t)cy * nv + v] = s;
   __threadfence();
   __shared__ int last;
   if (threadIdx.x == 0) last = (atomicAdd(&tickets[cx], 1) == ny - 1);
@@ -839,8 +845,13 @@ __global__ void __launch_bounds__(64) finalize_kernel(const double* __restrict__
   if (!last) return;
   __threadfence();
   if (v < nv) {
+    double x[kMaxBlocks / kFinChunk];
+#pragma unroll
+    for (int y = 0; y < kMaxBlocks / kFinChunk; ++y)
+      x[y] = (y < ny) ? lvl2[(size_t)y * nv + v] : 0.0;
     double t = 0.0;
-    for (int y = 0; y < ny; ++y) t += __builtin_nontemporal_load(&lvl2[(size_t)y * nv + v]);
+#pragma unroll
+    for (int y = 0; y < kMaxBlocks / kFinChunk; ++y) t += x[y];
     out[v] = t;
   }
   if (threadIdx.x == 0) atomicExch(&tickets[cx], 0);
@@ -1233,6 +1244,28 @@ __global__ void __launch_bounds__(256) residual_kernel(int variant, double normA
   }
 }
 
+// objective from the k x k products only: f1 = ||A||_F^2 + 2 tr(H) + ||M||_F^2,
+// f2 = 2 tr(H) - tr(M H)
+template <int KP>
+__global__ void __launch_bounds__(256) objective_kernel(int variant, double normA2,
+                                                       const double* __restrict__ sc,
+                                                       double* __restrict__ out) {
+  __shared__ double buf[256];
+  const int tid = threadIdx.x;
+  const double* M = sc + SC<KP>::M;
+  const double* H = sc + SC<KP>::H;
+  const bool f1 = (variant == OFM_F1 || variant == OFM_TRI_F1);
+  double trH = (tid < KP) ? H[tid * KP + tid] : 0.0;
+  double mm = 0.0;
+  for (int e = tid; e < KP * KP; e += 256) {
+    const int r = e / KP, q = e % KP;
+    mm += f1 ? M[e] * M[e] : M[e] * H[q * KP + r];
+  }
+  trH = block_sum256(trH, buf);
+  mm = block_sum256(mm, buf);
+  if (tid == 0) out[0] = f1 ? normA2 + 2.0 * trH + mm : 2.0 * trH - mm;
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -1304,8 +1337,14 @@ int partial_off(int k, int mode) {
 template <typename T, int KP, int MODE>
 static hipError_t spmm_mode(PassArgs& a, hipStream_t s) {
   using SM = Smem<T, KP, MODE>;
-  hipLaunchKernelGGL((spmm_kernel<T, KP, MODE>), dim3(a.nblocks), dim3(SM::WPB * 64),
-                     SM::bytes, s, a);
+  // the k x k products of the residual (X^T A X, (AX)^T (AX)) are compiled in
+  // only for the iterations that check it
+  if ((MODE == kGF1 || MODE == kAXF2) && (a.flags & kFlagCheck))
+    hipLaunchKernelGGL((spmm_kernel<T, KP, MODE, true>), dim3(a.nblocks), dim3(SM::WPB * 64),
+                       SM::bytes, s, a);
+  else
+    hipLaunchKernelGGL((spmm_kernel<T, KP, MODE, false>), dim3(a.nblocks), dim3(SM::WPB * 64),
+                       SM::bytes, s, a);
   return hipGetLastError();
 }
 
@@ -1397,6 +1436,19 @@ hipError_t launch_linesearch(int k, int variant, int first, double alpha0, doubl
     case 16: hipLaunchKernelGGL(linesearch_kernel<16>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status); break;
     case 32: hipLaunchKernelGGL(linesearch_kernel<32>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status); break;
     case 64: hipLaunchKernelGGL(linesearch_kernel<64>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_objective(int k, int variant, double normA2, const double* sc, double* out,
+                            hipStream_t s) {
+  switch (k) {
+    case 4: hipLaunchKernelGGL(objective_kernel<4>, dim3(1), dim3(256), 0, s, variant, normA2, sc, out); break;
+    case 8: hipLaunchKernelGGL(objective_kernel<8>, dim3(1), dim3(256), 0, s, variant, normA2, sc, out); break;
+    case 16: hipLaunchKernelGGL(objective_kernel<16>, dim3(1), dim3(256), 0, s, variant, normA2, sc, out); break;
+    case 32: hipLaunchKernelGGL(objective_kernel<32>, dim3(1), dim3(256), 0, s, variant, normA2, sc, out); break;
+    case 64: hipLaunchKernelGGL(objective_kernel<64>, dim3(1), dim3(256), 0, s, variant, normA2, sc, out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -89,6 +89,7 @@ _SIGS = {
     "ofm_set_state": (_I, [_P, _P, _P, _P, _I64, _P]),
     "ofm_get_step_info": (_I, [_P, _P, _P, _P, _P, _P]),
     "ofm_get_products": (_I, [_P, _I, _P, _P]),
+    "ofm_objective": (_I, [_P, _P, _P, _P, _P]),
     "ofm_set_timing": (_I, [_P, _I]),
     "ofm_get_timing": (_I, [_P, _P, _P, _I]),
     "ofm_row_normalize": (_I, [_I64, _I, _I, _P, _P, _P]),
@@ -286,6 +287,18 @@ class Workspace:
             coef.ctypes.data_as(ctypes.c_void_p), nr.ctypes.data_as(ctypes.c_void_p),
             _stream(stream)), "ofm_get_step_info")
         return {"alpha": alpha, "beta": beta, "coeffs": coef.reshape(k, 4).T.copy(), "nroots": nr}
+
+    def objective(self, X, grad=None, stream=None):
+        """(f(X) as a 1-element FP64 device tensor, grad f(X) or None)."""
+        torch = _torch()
+        self._x(X)
+        f = torch.empty(1, dtype=torch.float64, device=X.device)
+        if grad is not None:
+            self._x(grad)
+        _check(self._lib.ofm_objective(self.handle, _ptr(X), _ptr(f),
+                                       _ptr(grad) if grad is not None else None,
+                                       _stream(stream)), "ofm_objective")
+        return f, grad
 
     PASSES = ["spmm_x", "g", "v", "spmm_v", "linesearch", "update", "reduce", "residual", "other"]
 
