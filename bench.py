@@ -116,7 +116,7 @@ def main():
     def make(variant, precision=ofm.OFM_FP32, **kw):
         ws = ofm.Workspace(lap, k, variant=variant, precision=precision, check_every=10,
                            restart=variant.startswith("tri"), **kw)
-        dt = torch.float32 if precision == ofm.OFM_FP32 else torch.float64
+        dt = torch.float64 if precision == ofm.OFM_FP64 else torch.float32
         X = torch.as_tensor(x0, dtype=dt, device=dev).contiguous()
         return ws, X
 
@@ -212,6 +212,31 @@ def main():
             extras[key] = round(50 / (time.perf_counter() - t1), 1)
             w2.close()
             del X2
+        # BF16 storage of the gathered rows: iterations/s and the residual it reaches
+        w4, X4 = make(args.variant, ofm.OFM_FP32_BF16X, max_iter=300)
+        w4.init(X4)
+        for _ in range(5):
+            w4.step(X4)
+        torch.cuda.synchronize()
+        w4.set_timing(True)
+        t1 = time.perf_counter()
+        for _ in range(50):
+            w4.step(X4)
+        torch.cuda.synchronize()
+        bf_rate = 50 / (time.perf_counter() - t1)
+        w4.set_timing(False)
+        tm4 = w4.timing(reset=True)
+        w4.close()
+        w5, X5 = make(args.variant, ofm.OFM_FP32_BF16X, max_iter=300)
+        st5 = w5.solve(X5)
+        rr5 = w5.residual(X5)["relres"]
+        extras["bf16_gather"] = {
+            "iters_per_s": round(bf_rate, 1),
+            "spmm_x_us": round(1e3 * tm4["spmm_x"][0] / max(tm4["spmm_x"][1], 1), 1),
+            "spmm_v_us": round(1e3 * tm4["spmm_v"][0] / max(tm4["spmm_v"][1], 1), 1),
+            "relres_after_300": rr5, "iters": st5["iters"]}
+        w5.close()
+        del X4, X5
         # time to residual 1e-4 (solve from X0)
         ws3, X3 = make(args.variant, tol=1e-4, max_iter=3000)
         torch.cuda.synchronize()

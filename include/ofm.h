@@ -67,7 +67,14 @@ typedef enum ofm_variant { OFM_F1 = 0, OFM_TRI_F1 = 1, OFM_F2 = 2, OFM_TRI_F2 = 
  *   OFM_FP32: X in FP32; SpMM with FP32 edge weights and FP32 accumulation;
  *             N x k updates in FP32; Grams accumulated in FP64 from the FP32
  *             values (every product exact). */
-typedef enum ofm_precision { OFM_FP64 = 0, OFM_FP32 = 1 } ofm_precision;
+typedef enum ofm_precision { OFM_FP64 = 0, OFM_FP32 = 1, OFM_FP32_BF16X = 2 } ofm_precision;
+/*   OFM_FP32_BF16X (workspaces only): as OFM_FP32, but the SpMMs of the
+ *             iteration gather the neighbour rows from a BF16 copy of X (and of
+ *             V) kept by the workspace (round to nearest even); the row's own
+ *             term and every other pass stay FP32.  Halves the bytes of the
+ *             random row gathers; the reachable residual is limited to about
+ *             the BF16 rounding (~1e-3).  ofm_residual and ofm_objective use
+ *             the FP32 rows. */
 
 /* ofm_build_laplacian flags */
 #define OFM_LAP_VALIDATE 1u   /* also check that the pattern is symmetric    */

@@ -110,6 +110,9 @@ struct ofm_workspace_s {
   void* V[2] = {nullptr, nullptr};
   void* G[2] = {nullptr, nullptr};
   void* AX = nullptr;
+  void* Xb = nullptr;   // BF16 copies gathered by the SpMMs (OFM_FP32_BF16X)
+  void* Vb = nullptr;
+  int prec = 0;         // arithmetic of the kernels: OFM_FP64 or OFM_FP32
   int cur = 0;
   double* sc = nullptr;
   double* partials = nullptr;
@@ -410,6 +413,8 @@ static void free_ws(ofm_workspace ws) {
     dev_free(ws->G[i]);
   }
   dev_free(ws->AX);
+  dev_free(ws->Xb);
+  dev_free(ws->Vb);
   dev_free(ws->sc);
   dev_free(ws->partials);
   dev_free(ws->lvl2);
@@ -425,24 +430,26 @@ extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_o
   if (!lap || !host_opts) return OFM_E_INVALID_ARG;
   const ofm_opts& o = *host_opts;
   if (o.variant < 0 || o.variant > 3) return OFM_E_INVALID_ARG;
-  if (o.precision != OFM_FP32 && o.precision != OFM_FP64) return OFM_E_INVALID_ARG;
+  if (o.precision != OFM_FP32 && o.precision != OFM_FP64 && o.precision != OFM_FP32_BF16X)
+    return OFM_E_INVALID_ARG;
   if (o.max_iter < 1 || o.check_every < 1) return OFM_E_INVALID_ARG;
   if (o.first_step != 0 && o.first_step != 1) return OFM_E_INVALID_ARG;
   if (o.restart != 0 && o.restart != 1) return OFM_E_INVALID_ARG;
   if (!std::isfinite(o.alpha0) || !(o.tol >= 0.0)) return OFM_E_INVALID_ARG;
-  if (!supported_k(k, o.precision)) return o.precision == OFM_FP64 && k == 64 ? OFM_E_UNSUPPORTED
-                                                                              : OFM_E_SHAPE;
+  const int prec = o.precision == OFM_FP64 ? OFM_FP64 : OFM_FP32;
+  if (!supported_k(k, prec)) return prec == OFM_FP64 && k == 64 ? OFM_E_UNSUPPORTED : OFM_E_SHAPE;
   if (k > lap->g.n) return OFM_E_SHAPE;
-  const TileTable* tt = tiles_for(lap, o.precision, k);
+  const TileTable* tt = tiles_for(lap, prec, k);
   if (!tt) return OFM_E_UNSUPPORTED;
   auto* ws = new ofm_workspace_s();
   ws->lap = lap;
   ws->k = k;
   ws->opts = o;
   ws->n = lap->g.n;
-  ws->esz = o.precision == OFM_FP64 ? 8 : 4;
+  ws->prec = prec;
+  ws->esz = prec == OFM_FP64 ? 8 : 4;
   ws->tiles = tt;
-  ws->pk = o.precision == OFM_FP64 ? lap->g.pk64 : lap->g.pk32;
+  ws->pk = prec == OFM_FP64 ? lap->g.pk64 : lap->g.pk32;
   const size_t blk = (size_t)ws->n * k * ws->esz;
   const int nvmax = 2 * k * k + 3 * k;
   const int ny = (kMaxBlocks + kFinChunk - 1) / kFinChunk;
@@ -456,6 +463,10 @@ extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_o
     if ((st = dev_alloc(reinterpret_cast<char**>(&ws->G[i]), blk)) != OFM_OK) return fail(st);
   }
   if ((st = dev_alloc(reinterpret_cast<char**>(&ws->AX), blk)) != OFM_OK) return fail(st);
+  if (o.precision == OFM_FP32_BF16X) {
+    if ((st = dev_alloc(reinterpret_cast<char**>(&ws->Xb), blk / 2)) != OFM_OK) return fail(st);
+    if ((st = dev_alloc(reinterpret_cast<char**>(&ws->Vb), blk / 2)) != OFM_OK) return fail(st);
+  }
   if ((st = dev_alloc(&ws->sc, sc_total(k))) != OFM_OK) return fail(st);
   if ((st = dev_alloc(&ws->partials, (size_t)kMaxBlocks * nvmax)) != OFM_OK) return fail(st);
   if ((st = dev_alloc(&ws->lvl2, (size_t)ny * nvmax)) != OFM_OK) return fail(st);
@@ -500,16 +511,16 @@ static ofm_status finalize(ofm_workspace ws, const PassArgs& a, hipStream_t s) {
 }
 
 static ofm_status run_spmm(ofm_workspace ws, PassArgs& a, hipStream_t s) {
-  fill_graph(a, ws->lap, ws->tiles, ws->opts.precision);
-  a.nblocks = pass_blocks(ws->opts.precision, ws->k, ws->tiles->ntiles);
-  HIPCHK(timed(ws, pass_kind(a.mode), s, [&] { return launch_spmm(ws->opts.precision, ws->k, a, s); }));
+  fill_graph(a, ws->lap, ws->tiles, ws->prec);
+  a.nblocks = pass_blocks(ws->prec, ws->k, ws->tiles->ntiles);
+  HIPCHK(timed(ws, pass_kind(a.mode), s, [&] { return launch_spmm(ws->prec, ws->k, a, s); }));
   return finalize(ws, a, s);
 }
 
 static ofm_status run_dense(ofm_workspace ws, PassArgs& a, hipStream_t s) {
-  const int tr = tile_rows(ws->opts.precision, ws->k);
-  a.nblocks = pass_blocks(ws->opts.precision, ws->k, (ws->n + tr - 1) / tr);
-  HIPCHK(timed(ws, pass_kind(a.mode), s, [&] { return launch_dense(ws->opts.precision, ws->k, a, s); }));
+  const int tr = tile_rows(ws->prec, ws->k);
+  a.nblocks = pass_blocks(ws->prec, ws->k, (ws->n + tr - 1) / tr);
+  HIPCHK(timed(ws, pass_kind(a.mode), s, [&] { return launch_dense(ws->prec, ws->k, a, s); }));
   return finalize(ws, a, s);
 }
 
@@ -558,6 +569,7 @@ static ofm_status direction(ofm_workspace ws, void* X, const void* Gp, const voi
   if (!is_f2(ws->opts.variant)) {
     PassArgs a = base_args(ws, kGF1, (check ? kFlagCheck : 0) | restart);
     a.Z = X;
+    a.Zg = ws->Xb;
     a.G = ws->G[ws->cur];
     a.Gp = Gp;
     a.Vp = Vp;
@@ -566,6 +578,7 @@ static ofm_status direction(ofm_workspace ws, void* X, const void* Gp, const voi
   } else {
     PassArgs a = base_args(ws, kAXF2, check ? kFlagCheck : 0);
     a.Z = X;
+    a.Zg = ws->Xb;
     a.Y = ws->AX;
     OFMCHK(run_spmm(ws, a, s));
     if (check) HIPCHK(run_residual(ws, s));
@@ -588,10 +601,12 @@ static ofm_status search_and_update(ofm_workspace ws, void* X, const void* Vp, b
   v.G = ws->G[cur];
   v.Vp = Vp;
   v.V = ws->V[cur];
+  v.Vb = ws->Vb;
   v.X = X;
   OFMCHK(run_dense(ws, v, s));
   PassArgs w = base_args(ws, is_f2(ws->opts.variant) ? kAVF2 : kAVF1, 0);
   w.Z = ws->V[cur];
+  w.Zg = ws->Vb;
   w.X = X;
   OFMCHK(run_spmm(ws, w, s));
   HIPCHK(timed(ws, OFM_PASS_LINESEARCH, s, [&] {
@@ -601,6 +616,7 @@ static ofm_status search_and_update(ofm_workspace ws, void* X, const void* Vp, b
   PassArgs u = base_args(ws, kUpdate, 0);
   u.X = X;
   u.Xw = X;
+  u.Xb = ws->Xb;
   u.V = ws->V[cur];
   OFMCHK(run_dense(ws, u, s));
   ws->cur ^= 1;
@@ -611,6 +627,7 @@ static ofm_status search_and_update(ofm_workspace ws, void* X, const void* Vp, b
 static ofm_status gram_m(ofm_workspace ws, const void* X, hipStream_t s) {
   PassArgs a = base_args(ws, kGramM, 0);
   a.X = X;
+  a.Xb = ws->Xb;  // (re)creates the BF16 copy of X when the workspace keeps one
   return run_dense(ws, a, s);
 }
 

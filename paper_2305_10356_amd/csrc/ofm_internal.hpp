@@ -132,6 +132,11 @@ struct PassArgs {
   const int32_t* tiles = nullptr;
   int64_t ntiles = 0;
   const void* pk = nullptr;
+  // BF16 copies: gather source of the SpMM (null: gather Z itself) and the
+  // copies written by the producing passes
+  const void* Zg = nullptr;
+  void* Xb = nullptr;
+  void* Vb = nullptr;
 };
 
 enum : int { kFlagCheck = 1, kFlagRestart = 2, kFlagFirst = 4 };

@@ -170,11 +170,47 @@ __host__ __device__ inline int mode_off(int mode) {
 // wavefront building blocks
 // ---------------------------------------------------------------------------
 
+// FP32 -> BF16 with round to nearest even (NaN stays a quiet NaN)
+__device__ inline uint32_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (u >> 16) | 0x40u;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+// store the VECN (= 4) FP32 values of a lane as BF16 at row r, lane part j
+template <int KP>
+__device__ inline void st_bf16(void* base, size_t r, int j, const V16<float>& x) {
+  uint2 u;
+  u.x = f32_to_bf16(x.v[0]) | (f32_to_bf16(x.v[1]) << 16);
+  u.y = f32_to_bf16(x.v[2]) | (f32_to_bf16(x.v[3]) << 16);
+  *reinterpret_cast<uint2*>(static_cast<uint16_t*>(base) + r * KP + j * 4) = u;
+}
+
+// lane part j of gathered row c: 16 bytes of T, or 4 BF16 values widened
+template <typename T, int KP, bool BF>
+__device__ inline V16<T> load_row_part(const void* Z, int c, int j) {
+  using G = Geo<T, KP>;
+  if constexpr (!BF) {
+    return ld16(static_cast<const T*>(Z) + (size_t)c * KP + j * G::VECN);
+  } else {
+    static_assert(sizeof(T) == 4, "BF16 gathers feed FP32 arithmetic");
+    const uint2 u =
+        *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(Z) + (size_t)c * KP + j * 4);
+    V16<T> r;
+    r.v[0] = __uint_as_float(u.x << 16);
+    r.v[1] = __uint_as_float(u.x & 0xffff0000u);
+    r.v[2] = __uint_as_float(u.y << 16);
+    r.v[3] = __uint_as_float(u.y & 0xffff0000u);
+    return r;
+  }
+}
+
 // Sum of S_ij-weighted rows Z_j over entries [e_first, end) taken in chunks;
 // the LPR lanes of a group share every entry through lane shuffles.
-template <typename T, int KP>
+template <typename T, int KP, bool BF = false>
 __device__ inline void gather_rows(const typename EntT<T>::type* __restrict__ pk,
-                                   const T* __restrict__ Z, int e_first, int end, int cstride,
+                                   const void* __restrict__ Z, int e_first, int end, int cstride,
                                    int gbase, int j, V16<T>& acc) {
   using G = Geo<T, KP>;
   constexpr int CH = G::LPR >= kGatherChunk ? G::LPR : kGatherChunk;
@@ -200,7 +236,7 @@ __device__ inline void gather_rows(const typename EntT<T>::type* __restrict__ pk
       const int src = gbase + (s % G::LPR);
       const int c = __shfl(col[s / G::LPR], src);
       if (e0 + s < end) {
-        z[s] = ld16(Z + (size_t)c * KP + j * G::VECN);
+        z[s] = load_row_part<T, KP, BF>(Z, c, j);
       } else {
 #pragma unroll
         for (int q = 0; q < G::VECN; ++q) z[s].v[q] = T(0);
@@ -406,7 +442,7 @@ __device__ inline bool all_finite(T x) {
 // SpMM with fused epilogues:  A Z = -Z - D^{-1/2} S D^{-1/2} Z
 // ---------------------------------------------------------------------------
 
-template <typename T, int KP, int MODE, bool CHECK>
+template <typename T, int KP, int MODE, bool CHECK, bool BF>
 __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
     spmm_kernel(PassArgs a) {
   using G = Geo<T, KP>;
@@ -465,7 +501,9 @@ __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
           V16<T> acc;
 #pragma unroll
           for (int q = 0; q < G::VECN; ++q) acc.v[q] = T(0);
-          gather_rows<T, KP>(pk, Z, beg, end, G::LPR >= kGatherChunk ? G::LPR : kGatherChunk, g * G::LPR, j, acc);
+          gather_rows<T, KP, BF>(pk, BF ? a.Zg : a.Z, beg, end,
+                                 G::LPR >= kGatherChunk ? G::LPR : kGatherChunk, g * G::LPR, j,
+                                 acc);
           const V16<T> z = ld16(Z + (size_t)row * KP + j * G::VECN);
 #pragma unroll
           for (int q = 0; q < G::VECN; ++q) acc.v[q] = -z.v[q] - acc.v[q];
@@ -492,7 +530,8 @@ __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
         V16<T> acc;
 #pragma unroll
         for (int q = 0; q < G::VECN; ++q) acc.v[q] = T(0);
-        gather_rows<T, KP>(pk, Z, beg + g * CH, end, G::RPW * CH, g * G::LPR, j, acc);
+        gather_rows<T, KP, BF>(pk, BF ? a.Zg : a.Z, beg + g * CH, end, G::RPW * CH, g * G::LPR,
+                               j, acc);
 #pragma unroll
         for (int q = 0; q < G::VECN; ++q) {
 #pragma unroll
@@ -701,6 +740,9 @@ __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
             for (int q = 0; q < G::VECN; ++q) v.v[q] = -gv.v[q];
           }
           st16(static_cast<T*>(a.V) + off, v);
+          if constexpr (sizeof(T) == 4) {
+            if (a.Vb) st_bf16<KP>(a.Vb, (size_t)(r0 + gi), j, v);
+          }
 #pragma unroll
           for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)v.v[q] * (double)gv.v[q];
         } else {
@@ -720,6 +762,9 @@ __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
 #pragma unroll
             for (int q = 0; q < G::VECN; ++q) x.v[q] = fma(colscal[q], v.v[q], x.v[q]);
             st16(static_cast<T*>(a.Xw) + off, x);
+          }
+          if constexpr (sizeof(T) == 4) {
+            if (a.Xb) st_bf16<KP>(a.Xb, (size_t)(r0 + gi), j, x);
           }
         } else {
 #pragma unroll
@@ -1334,18 +1379,26 @@ int partial_off(int k, int mode) {
   return 0;
 }
 
-template <typename T, int KP, int MODE>
-static hipError_t spmm_mode(PassArgs& a, hipStream_t s) {
+template <typename T, int KP, int MODE, bool BF>
+static hipError_t spmm_mode_bf(PassArgs& a, hipStream_t s) {
   using SM = Smem<T, KP, MODE>;
   // the k x k products of the residual (X^T A X, (AX)^T (AX)) are compiled in
   // only for the iterations that check it
   if ((MODE == kGF1 || MODE == kAXF2) && (a.flags & kFlagCheck))
-    hipLaunchKernelGGL((spmm_kernel<T, KP, MODE, true>), dim3(a.nblocks), dim3(SM::WPB * 64),
+    hipLaunchKernelGGL((spmm_kernel<T, KP, MODE, true, BF>), dim3(a.nblocks), dim3(SM::WPB * 64),
                        SM::bytes, s, a);
   else
-    hipLaunchKernelGGL((spmm_kernel<T, KP, MODE, false>), dim3(a.nblocks), dim3(SM::WPB * 64),
-                       SM::bytes, s, a);
+    hipLaunchKernelGGL((spmm_kernel<T, KP, MODE, false, BF>), dim3(a.nblocks),
+                       dim3(SM::WPB * 64), SM::bytes, s, a);
   return hipGetLastError();
+}
+
+template <typename T, int KP, int MODE>
+static hipError_t spmm_mode(PassArgs& a, hipStream_t s) {
+  if constexpr (sizeof(T) == 4 && MODE != kApply) {
+    if (a.Zg) return spmm_mode_bf<T, KP, MODE, true>(a, s);
+  }
+  return spmm_mode_bf<T, KP, MODE, false>(a, s);
 }
 
 template <typename T, int KP>

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libofm.so")
 
 OFM_F1, OFM_TRI_F1, OFM_F2, OFM_TRI_F2 = 0, 1, 2, 3
-OFM_FP64, OFM_FP32 = 0, 1
+OFM_FP64, OFM_FP32, OFM_FP32_BF16X = 0, 1, 2
 OFM_LAP_VALIDATE = 1
 OFM_LAP_NO_REORDER = 2
 

@@ -1,0 +1,63 @@
+"""BF16 storage of the gathered rows (OFM_FP32_BF16X): the SpMM must equal
+the exact shifted operator applied with every neighbour row rounded to BF16
+(round to nearest even) and the row's own term in FP32; the iteration then
+reaches a residual set by that rounding and clusters like FP32."""
+import numpy as np
+import pytest
+
+from oracle import ofm_oracle as O
+from paper_2305_10356_amd import graphs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def bf16_round(x32: np.ndarray) -> np.ndarray:
+    """FP32 -> BF16 -> FP32 with round to nearest even, from the bit layout."""
+    u = np.ascontiguousarray(x32, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32)
+
+
+def test_bf16_rounding_helper():
+    x = np.array([1.0, 1.00390625, 1.005859375, -2.5, 3.0e-5], dtype=np.float32)
+    r = bf16_round(x)
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == np.float32(1.0078125) and r[3] == -2.5
+    assert abs(r[4] - 3.0e-5) <= 2.0 ** -8 * 3.0e-5
+
+
+@pytest.mark.parametrize("k", [8, 32])
+def test_bf16_gather_exact(lib, k):
+    from paper_2305_10356_amd import ofm
+    g, _ = graphs.config_graph(3, n=30000)
+    olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
+    lap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    x32 = graphs.initial_x(g.n, k, np.random.default_rng([11, k])).astype(np.float32)
+    ws = ofm.Workspace(lap, k, variant="f1", precision=ofm.OFM_FP32_BF16X)
+    X = torch.tensor(x32, device="cuda")
+    ws.init(X)
+    _, G0 = ws.get_state()
+    x = x32.astype(np.float64)
+    xb = bf16_round(x32).astype(np.float64)
+    axb = -x - olap.dinv[:, None] * (olap.S @ (olap.dinv[:, None] * xb))
+    ref = 4.0 * (axb + x @ (x.T @ x))
+    got = G0.cpu().numpy().astype(np.float64)
+    assert np.abs(got - ref).max() <= 2e-6 * np.abs(ref).max()
+
+
+def test_bf16_solve_floor_and_labels(lib):
+    from paper_2305_10356_amd import ofm
+    g, x0 = graphs.config_graph(2)
+    lap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    labels = {}
+    for prec in (ofm.OFM_FP32, ofm.OFM_FP32_BF16X):
+        ws = ofm.Workspace(lap, 32, variant="f1", precision=prec, max_iter=400, check_every=10)
+        X = torch.tensor(x0.astype(np.float32), device="cuda")
+        ws.solve(X)
+        rr = ws.residual(X)["relres"]
+        print(f"precision {prec}: relres of the final X {rr:.2e}", flush=True)
+        assert rr < (2e-4 if prec == ofm.OFM_FP32 else 5e-3)
+        Y = ofm.row_normalize(X)
+        lab, _, _ = ofm.kmeans(Y, 32, O.kmeans_uniforms(0, 32))
+        labels[prec] = lab.cpu().numpy()
+    assert O.ari(labels[ofm.OFM_FP32], labels[ofm.OFM_FP32_BF16X]) > 0.9
