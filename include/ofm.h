@@ -222,6 +222,31 @@ ofm_status ofm_get_step_info(ofm_workspace ws, double* host_alpha, double* host_
                              double* host_coef, int32_t* host_nroots, hipStream_t stream);
 
 /*
+ * Batched solves of many independent graphs (any sizes, widths k in
+ * {4, 8, 16, 32, 64}): Algorithm 2 runs on all of them in lockstep, each pass
+ * being one launch per width group over every graph of the group; a graph
+ * stops iterating (on the device) as soon as its residual meets tol.
+ * host_laps[count], host_ks[count]: the graphs and their widths (the handles
+ * must outlive the batch); host_opts: shared options (precision OFM_FP32 or
+ * OFM_FP32_BF16X; variant, max_iter, check_every, tol, restart, first_step).
+ * Allocates the per-graph state.  The block schedule (blocks per graph, each
+ * graph's blocks on one XCD) is chosen among a few candidates by timing the
+ * first iterations of every solve.
+ */
+typedef struct ofm_batch_s* ofm_batch;
+ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps, const int* host_ks,
+                            const ofm_opts* host_opts, ofm_batch* out);
+ofm_status ofm_batch_destroy(ofm_batch b);
+/* Solve every graph from its X (host_X[i]: device pointer to graph i's N_i x k_i
+ * FP32 block, updated in place); host_stats[count] receives the per-graph
+ * stats (iters = updates done, relres of the X it stopped at).  Synchronizing. */
+ofm_status ofm_batch_solve(ofm_batch b, void* const* host_X, hipStream_t stream,
+                           ofm_stats* host_stats);
+/* Schedule chosen by the last solve: host_scale = blocks-per-graph multiplier,
+ * host_ms[3] = measured time per iteration of each candidate (0 if untried). */
+ofm_status ofm_batch_schedule(ofm_batch b, int* host_scale, double* host_ms);
+
+/*
  * Host copy (synchronizing) of one k x k FP64 product held by the workspace,
  * row-major into host_kxk[k*k]:
  *   0: X^T X   1: X^T A X   2: (AX)^T (AX)   3: V^T V   4: X^T V

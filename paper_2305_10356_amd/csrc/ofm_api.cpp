@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -918,5 +919,371 @@ extern "C" ofm_status ofm_kmeans(int64_t n, int dim, int n_clusters, const float
   if (hipStreamSynchronize(stream) != hipSuccess) return fail(OFM_E_HIP);
   if (host_iters) *host_iters = it;
   cleanup();
+  return OFM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched solves
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int kBatchCand = 3;
+const int kBatchScale[kBatchCand] = {1, 2, 4};
+constexpr int kBatchMaxBlocksPerGraph = 96;
+
+struct BatchGroup {
+  int k = 0;
+  std::vector<int> idx;                 // members (batch indices)
+  std::vector<int> base;                // base blocks per member
+  BatchGraph* dgraphs[kBatchCand] = {nullptr, nullptr, nullptr};
+  BatchSeg* dseg[kBatchCand] = {nullptr, nullptr, nullptr};
+  int grid[kBatchCand] = {0, 0, 0};
+  std::vector<BatchGraph> hg;           // host copy of the descriptors (candidate 0)
+  int* active = nullptr;                // [n]
+  int64_t* done = nullptr;              // [n]
+  int* status = nullptr;                // [n]
+  double* sc = nullptr;                 // [n][SC total]
+  double* partials = nullptr;
+  char* bufs = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;
+};
+
+}  // namespace
+
+struct ofm_batch_s {
+  int count = 0;
+  ofm_opts opts{};
+  std::vector<ofm_laplacian> laps;
+  std::vector<int> ks;
+  std::vector<BatchGroup> groups;
+  int chosen = 0;
+  double cand_ms[kBatchCand] = {0, 0, 0};
+  hipEvent_t start = nullptr;
+};
+
+static void free_batch(ofm_batch b) {
+  if (!b) return;
+  for (auto& g : b->groups) {
+    for (int c = 0; c < kBatchCand; ++c) {
+      dev_free(g.dgraphs[c]);
+      dev_free(g.dseg[c]);
+    }
+    dev_free(g.active);
+    dev_free(g.done);
+    dev_free(g.status);
+    dev_free(g.sc);
+    dev_free(g.partials);
+    dev_free(g.bufs);
+    if (g.stream) (void)hipStreamDestroy(g.stream);
+    if (g.ev) (void)hipEventDestroy(g.ev);
+  }
+  if (b->start) (void)hipEventDestroy(b->start);
+  delete b;
+}
+
+// blocks of one graph all on one XCD (block ids congruent modulo 8), XCDs
+// balanced by block count; returns the grid size
+static int batch_schedule(const std::vector<int>& nblk, std::vector<BatchSeg>& seg) {
+  const int nx = 8;
+  std::vector<int> order(nblk.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return nblk[a] > nblk[c]; });
+  std::vector<std::vector<BatchSeg>> per(nx);
+  std::vector<int64_t> load(nx, 0);
+  for (int gi : order) {
+    int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    for (int r = 0; r < nblk[gi]; ++r) per[x].push_back(BatchSeg{gi, r, nblk[gi]});
+    load[x] += nblk[gi];
+  }
+  size_t mx = 0;
+  for (auto& v : per) mx = std::max(mx, v.size());
+  seg.assign(mx * nx, BatchSeg{-1, 0, 0});
+  for (int x = 0; x < nx; ++x)
+    for (size_t i = 0; i < per[x].size(); ++i) seg[i * nx + x] = per[x][i];
+  return (int)(mx * nx);
+}
+
+extern "C" ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps,
+                                       const int* host_ks, const ofm_opts* host_opts,
+                                       ofm_batch* out) {
+  if (!out) return OFM_E_INVALID_ARG;
+  *out = nullptr;
+  if (count < 1 || !host_laps || !host_ks || !host_opts) return OFM_E_INVALID_ARG;
+  const ofm_opts& o = *host_opts;
+  if (o.variant < 0 || o.variant > 3) return OFM_E_INVALID_ARG;
+  if (o.precision != OFM_FP32 && o.precision != OFM_FP32_BF16X) return OFM_E_UNSUPPORTED;
+  if (o.max_iter < 1 || o.check_every < 1 || !(o.tol >= 0.0)) return OFM_E_INVALID_ARG;
+  if (o.first_step != 0 && o.first_step != 1) return OFM_E_INVALID_ARG;
+  for (int i = 0; i < count; ++i) {
+    if (!host_laps[i]) return OFM_E_INVALID_ARG;
+    if (!supported_k(host_ks[i], OFM_FP32) || host_ks[i] > host_laps[i]->g.n) return OFM_E_SHAPE;
+  }
+  auto* B = new ofm_batch_s();
+  B->count = count;
+  B->opts = o;
+  B->laps.assign(host_laps, host_laps + count);
+  B->ks.assign(host_ks, host_ks + count);
+  auto fail = [&](ofm_status s) {
+    free_batch(B);
+    return s;
+  };
+  if (hipEventCreate(&B->start) != hipSuccess) return fail(OFM_E_HIP);
+  const int widths[5] = {4, 8, 16, 32, 64};
+  const bool bf = o.precision == OFM_FP32_BF16X;
+  for (int w : widths) {
+    BatchGroup g;
+    g.k = w;
+    for (int i = 0; i < count; ++i)
+      if (host_ks[i] == w) g.idx.push_back(i);
+    if (g.idx.empty()) continue;
+    B->groups.push_back(std::move(g));
+  }
+  for (auto& g : B->groups) {
+    const int n = (int)g.idx.size();
+    const int k = g.k;
+    const int wpbk = batch_wpb(k);
+    const int tr = tile_rows(OFM_FP32, k);
+    const int nvmax = 2 * k * k + 3 * k;
+    const int sct = sc_total(k);
+    ofm_status st;
+    if (hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&g.ev, hipEventDisableTiming) != hipSuccess)
+      return fail(OFM_E_HIP);
+    // per-graph base block count: about 8 tiles per wave
+    size_t part_total = 0, buf_total = 0;
+    std::vector<size_t> part_off(n), buf_off(n);
+    for (int m = 0; m < n; ++m) {
+      ofm_laplacian L = host_laps[g.idx[m]];
+      const TileTable* tt = tiles_for(L, OFM_FP32, k);
+      const int64_t tiles = std::max<int64_t>(tt->ntiles, (L->g.n + tr - 1) / tr);
+      int base = (int)std::min<int64_t>(kBatchMaxBlocksPerGraph, (tiles + 8 * wpbk - 1) / (8 * wpbk));
+      base = std::max(base, 1);
+      g.base.push_back(base);
+      const int maxb = std::min(kBatchMaxBlocksPerGraph, base * kBatchScale[kBatchCand - 1]);
+      part_off[m] = part_total;
+      part_total += (size_t)maxb * nvmax;
+      buf_off[m] = buf_total;
+      const size_t blk = (size_t)L->g.n * k * 4;
+      buf_total += 5 * blk + (bf ? blk : 0);   // V x2, G x2, AX (+ BF16 copies of X and V)
+      buf_total = (buf_total + 255) & ~(size_t)255;
+    }
+    if ((st = dev_alloc(&g.active, n)) != OFM_OK) return fail(st);
+    if ((st = dev_alloc(&g.done, n)) != OFM_OK) return fail(st);
+    if ((st = dev_alloc(&g.status, n)) != OFM_OK) return fail(st);
+    if ((st = dev_alloc(&g.sc, (size_t)n * sct)) != OFM_OK) return fail(st);
+    if ((st = dev_alloc(&g.partials, part_total)) != OFM_OK) return fail(st);
+    if ((st = dev_alloc(&g.bufs, buf_total)) != OFM_OK) return fail(st);
+    if (hipMemset(g.sc, 0, (size_t)n * sct * sizeof(double)) != hipSuccess) return fail(OFM_E_HIP);
+    g.hg.resize(n);
+    for (int m = 0; m < n; ++m) {
+      ofm_laplacian L = host_laps[g.idx[m]];
+      const TileTable* tt = tiles_for(L, OFM_FP32, k);
+      BatchGraph& d = g.hg[m];
+      d.n = L->g.n;
+      d.sched = L->g.sched;
+      d.sptr = L->g.sptr;
+      d.tiles = tt->dev;
+      d.ntiles = tt->ntiles;
+      d.pk = L->g.pk32;
+      const size_t blk = (size_t)L->g.n * k * 4;
+      char* p = g.bufs + buf_off[m];
+      d.V[0] = p;
+      d.V[1] = p + blk;
+      d.G[0] = p + 2 * blk;
+      d.G[1] = p + 3 * blk;
+      d.AX = p + 4 * blk;
+      d.Xb = bf ? p + 5 * blk : nullptr;
+      d.Vb = bf ? p + 5 * blk + blk / 2 : nullptr;
+      d.sc = g.sc + (size_t)m * sct;
+      d.partials = g.partials + part_off[m];
+      d.status = g.status + m;
+      d.active = g.active + m;
+      d.done_iter = g.done + m;
+      d.normA2 = L->g.normA2;
+    }
+    for (int c = 0; c < kBatchCand; ++c) {
+      std::vector<int> nb(n);
+      std::vector<BatchGraph> hc = g.hg;
+      for (int m = 0; m < n; ++m) {
+        nb[m] = std::min(kBatchMaxBlocksPerGraph, g.base[m] * kBatchScale[c]);
+        hc[m].nblk = nb[m];
+      }
+      std::vector<BatchSeg> seg;
+      g.grid[c] = batch_schedule(nb, seg);
+      if ((st = dev_alloc(&g.dgraphs[c], n)) != OFM_OK) return fail(st);
+      if ((st = dev_alloc(&g.dseg[c], seg.size())) != OFM_OK) return fail(st);
+      if (hipMemcpy(g.dgraphs[c], hc.data(), n * sizeof(BatchGraph), hipMemcpyHostToDevice) !=
+              hipSuccess ||
+          hipMemcpy(g.dseg[c], seg.data(), seg.size() * sizeof(BatchSeg), hipMemcpyHostToDevice) !=
+              hipSuccess)
+        return fail(OFM_E_HIP);
+    }
+  }
+  *out = B;
+  return OFM_OK;
+}
+
+extern "C" ofm_status ofm_batch_destroy(ofm_batch b) {
+  if (!b) return OFM_E_INVALID_ARG;
+  free_batch(b);
+  return OFM_OK;
+}
+
+extern "C" ofm_status ofm_batch_schedule(ofm_batch b, int* host_scale, double* host_ms) {
+  if (!b) return OFM_E_INVALID_ARG;
+  if (host_scale) *host_scale = kBatchScale[b->chosen];
+  if (host_ms)
+    for (int c = 0; c < kBatchCand; ++c) host_ms[c] = b->cand_ms[c];
+  return OFM_OK;
+}
+
+// the passes of one batched group: a dense or SpMM launch plus its per-graph
+// reduction
+static ofm_status bpass(BatchGroup& g, BatchArgs base, int mode, int flags, int cand, bool spmm) {
+  BatchArgs a = base;
+  a.mode = mode;
+  a.flags = flags;
+  a.graphs = g.dgraphs[cand];
+  a.seg = g.dseg[cand];
+  a.ngraphs = (int)g.idx.size();
+  a.nv = partial_nv(g.k, mode, flags);
+  a.off = partial_off(g.k, mode);
+  HIPCHK(spmm ? launch_batch_spmm(g.k, a, g.grid[cand], g.stream)
+              : launch_batch_dense(g.k, a, g.grid[cand], g.stream));
+  HIPCHK(launch_batch_finalize(a, g.stream));
+  return OFM_OK;
+}
+
+static ofm_status batch_iteration(ofm_batch B, BatchGroup& g, int cur, int64_t t, bool first,
+                                  bool check, int cand) {
+  const ofm_opts& o = B->opts;
+  BatchArgs base;
+  base.k = g.k;
+  base.variant = o.variant;
+  base.cur = cur;
+  base.bf16 = o.precision == OFM_FP32_BF16X;
+  base.tol = o.tol;
+  base.t = t;
+  base.graphs = g.dgraphs[cand];
+  base.seg = g.dseg[cand];
+  base.ngraphs = (int)g.idx.size();
+  const int rs = o.restart ? kFlagRestart : 0;
+  const int fs = first ? kFlagFirst : 0;
+  if (first) OFMCHK(bpass(g, base, kGramM, 0, cand, false));
+  const bool f2 = o.variant == OFM_F2 || o.variant == OFM_TRI_F2;
+  if (!f2) {
+    OFMCHK(bpass(g, base, kGF1, (check ? kFlagCheck : 0) | rs | fs, cand, true));
+  } else {
+    OFMCHK(bpass(g, base, kAXF2, check ? kFlagCheck : 0, cand, true));
+  }
+  if (check) HIPCHK(launch_batch_residual(g.k, base, g.stream));
+  if (f2) OFMCHK(bpass(g, base, kGPassF2, rs | fs, cand, false));
+  OFMCHK(bpass(g, base, kVPass, rs | fs, cand, false));
+  OFMCHK(bpass(g, base, f2 ? kAVF2 : kAVF1, 0, cand, true));
+  HIPCHK(launch_batch_linesearch(g.k, base, o.alpha0, first && o.first_step == 1, g.stream));
+  OFMCHK(bpass(g, base, kUpdate, 0, cand, false));
+  return OFM_OK;
+}
+
+extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStream_t stream,
+                                      ofm_stats* host_stats) {
+  if (!B || !host_X) return OFM_E_INVALID_ARG;
+  for (int i = 0; i < B->count; ++i)
+    if (!host_X[i]) return OFM_E_INVALID_ARG;
+  const ofm_opts& o = B->opts;
+  HIPCHK(hipEventRecord(B->start, stream));
+  for (auto& g : B->groups) {
+    HIPCHK(hipStreamWaitEvent(g.stream, B->start, 0));
+    const int n = (int)g.idx.size();
+    for (int m = 0; m < n; ++m) g.hg[m].X = host_X[g.idx[m]];
+    // descriptors of every candidate carry the caller's X pointers
+    for (int c = 0; c < kBatchCand; ++c) {
+      std::vector<BatchGraph> hc = g.hg;
+      for (int m = 0; m < n; ++m)
+        hc[m].nblk = std::min(kBatchMaxBlocksPerGraph, g.base[m] * kBatchScale[c]);
+      HIPCHK(hipMemcpy(g.dgraphs[c], hc.data(), n * sizeof(BatchGraph), hipMemcpyHostToDevice));
+    }
+    std::vector<int> ones(n, 1);
+    std::vector<int64_t> minus(n, -1);
+    HIPCHK(hipMemcpyAsync(g.active, ones.data(), n * sizeof(int), hipMemcpyHostToDevice, g.stream));
+    HIPCHK(hipMemcpyAsync(g.done, minus.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, g.stream));
+    HIPCHK(hipMemsetAsync(g.status, 0, n * sizeof(int), g.stream));
+    HIPCHK(hipStreamSynchronize(g.stream));
+  }
+  // set-up step of Algorithm 2, then the loop; the first iterations try the
+  // candidate schedules (two iterations each) and keep the fastest
+  int cur = 0;
+  int64_t t = 0;
+  for (auto& g : B->groups) OFMCHK(batch_iteration(B, g, cur, t, true, false, 0));
+  cur ^= 1;
+  t = 1;
+  for (int c = 0; c < kBatchCand; ++c) B->cand_ms[c] = 0.0;
+  int tuned = -1;
+  const int64_t tune_end = 1 + 2 * kBatchCand;
+  double best = 1e300;
+  int64_t last_check = -1;
+  while (t < o.max_iter) {
+    const bool tuning = t < tune_end;
+    const int cand = tuning ? (int)((t - 1) / 2) : (tuned < 0 ? 0 : tuned);
+    const bool check = (t % o.check_every) == 0;
+    auto t0 = std::chrono::steady_clock::now();
+    for (auto& g : B->groups) OFMCHK(batch_iteration(B, g, cur, t, false, check, cand));
+    if (check) last_check = t;
+    if (tuning) {
+      for (auto& g : B->groups) HIPCHK(hipStreamSynchronize(g.stream));
+      const double ms =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      if ((t - 1) % 2 == 1) {  // the second iteration of a candidate
+        B->cand_ms[cand] = ms;
+        if (ms < best) {
+          best = ms;
+          tuned = cand;
+        }
+      }
+    }
+    cur ^= 1;
+    ++t;
+    if (check) {
+      int any = 0;
+      for (auto& g : B->groups) {
+        std::vector<int> act(g.idx.size());
+        HIPCHK(hipMemcpyAsync(act.data(), g.active, act.size() * sizeof(int),
+                              hipMemcpyDeviceToHost, g.stream));
+        HIPCHK(hipStreamSynchronize(g.stream));
+        for (int a : act) any |= a;
+      }
+      if (!any) break;
+    }
+  }
+  B->chosen = tuned < 0 ? 0 : tuned;
+  // per-graph stats
+  for (auto& g : B->groups) {
+    HIPCHK(hipStreamSynchronize(g.stream));
+    const int n = (int)g.idx.size();
+    const int sct = sc_total(g.k);
+    const SCOff so = sc_off(g.k);
+    std::vector<double> sc((size_t)n * sct);
+    std::vector<int64_t> done(n);
+    std::vector<int> stt(n), act(n);
+    HIPCHK(hipMemcpy(sc.data(), g.sc, sc.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(done.data(), g.done, n * sizeof(int64_t), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(stt.data(), g.status, n * sizeof(int), hipMemcpyDeviceToHost));
+    for (int m = 0; m < n; ++m) {
+      ofm_stats st{};
+      const double* s = sc.data() + (size_t)m * sct;
+      st.iters = done[m] >= 0 ? done[m] : t;
+      st.relres = last_check >= 0 ? s[so.RELRES] : -1.0;
+      st.objective = s[so.FVAL];
+      st.relres_iter = done[m] >= 0 ? done[m] : last_check;
+      st.status = (stt[m] & kStNonfinite) ? OFM_E_NONFINITE
+                  : (stt[m] & kStCholesky) ? OFM_E_NUMERIC : OFM_OK;
+      st.converged = (done[m] >= 0 && st.status == OFM_OK) ? 1 : 0;
+      if (host_stats) host_stats[g.idx[m]] = st;
+    }
+    HIPCHK(hipEventRecord(g.ev, g.stream));
+    HIPCHK(hipStreamWaitEvent(stream, g.ev, 0));
+  }
   return OFM_OK;
 }

@@ -141,6 +141,56 @@ struct PassArgs {
 
 enum : int { kFlagCheck = 1, kFlagRestart = 2, kFlagFirst = 4 };
 
+// Batched solves: one launch per pass covers every graph of a width group.
+struct BatchGraph {
+  int64_t n = 0;
+  const int32_t* sched = nullptr;
+  const int32_t* sptr = nullptr;
+  const int32_t* tiles = nullptr;
+  int64_t ntiles = 0;
+  const void* pk = nullptr;
+  void* X = nullptr;
+  void* V[2] = {nullptr, nullptr};
+  void* G[2] = {nullptr, nullptr};
+  void* AX = nullptr;
+  void* Xb = nullptr;
+  void* Vb = nullptr;
+  double* sc = nullptr;
+  double* partials = nullptr;  // [nblk][nv]
+  int* status = nullptr;
+  int* active = nullptr;       // 1 while the graph iterates
+  int64_t* done_iter = nullptr;  // iteration whose X met the tolerance (-1: none)
+  double normA2 = 0.0;
+  int nblk = 1;                // blocks of the current schedule
+};
+struct BatchSeg {
+  int g;     // graph (-1: idle block)
+  int rank;  // block rank within the graph's blocks
+  int nblk;  // number of blocks of that graph
+};
+struct BatchArgs {
+  const BatchGraph* graphs = nullptr;
+  const BatchSeg* seg = nullptr;
+  int ngraphs = 0;
+  int k = 0;
+  int variant = 0;
+  int mode = 0;
+  int flags = 0;     // kFlagCheck / kFlagRestart / kFlagFirst
+  int cur = 0;       // ping-pong slot of the current direction
+  int bf16 = 0;      // gather BF16 copies
+  double tol = 0.0;
+  int64_t t = 0;
+  int nv = 0;
+  int off = 0;       // first scalar slot the mode's products go to
+};
+hipError_t launch_batch_spmm(int k, BatchArgs& b, int grid, hipStream_t s);
+hipError_t launch_batch_dense(int k, BatchArgs& b, int grid, hipStream_t s);
+hipError_t launch_batch_finalize(BatchArgs& b, hipStream_t s);
+hipError_t launch_batch_linesearch(int k, BatchArgs& b, double alpha0, int first_fixed,
+                                   hipStream_t s);
+hipError_t launch_batch_residual(int k, BatchArgs& b, hipStream_t s);
+int batch_wpb(int k);
+
 // Launchers (ofm_kernels.hip).  Each returns a hipError_t.
 hipError_t launch_spmm(int precision, int k, PassArgs& a, hipStream_t s);
 hipError_t launch_dense(int precision, int k, PassArgs& a, hipStream_t s);

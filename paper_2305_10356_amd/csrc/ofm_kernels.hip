@@ -442,14 +442,15 @@ __device__ inline bool all_finite(T x) {
 // SpMM with fused epilogues:  A Z = -Z - D^{-1/2} S D^{-1/2} Z
 // ---------------------------------------------------------------------------
 
+// One pass over the tiles brank, brank + nblk, ... of a graph (a grid of its
+// own, or a share of a batched launch); writes the block's partial row brank.
 template <typename T, int KP, int MODE, bool CHECK, bool BF>
-__global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
-    spmm_kernel(PassArgs a) {
+__device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk,
+                                          unsigned char* smem) {
   using G = Geo<T, KP>;
   using SM = Smem<T, KP, MODE>;
   constexpr int WPB = SM::WPB;
   constexpr int NV = nvec_of(MODE);
-  extern __shared__ __align__(16) unsigned char smem[];
   T* frag = reinterpret_cast<T*>(smem);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -483,8 +484,8 @@ __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
   zero_gram<T, KP>(gA);
   zero_gram<T, KP>(gB);
 
-  const int64_t stride = (int64_t)gridDim.x * WPB;
-  for (int64_t t = (int64_t)blockIdx.x * WPB + wave; t < a.ntiles; t += stride) {
+  const int64_t stride = (int64_t)nblk * WPB;
+  for (int64_t t = (int64_t)brank * WPB + wave; t < a.ntiles; t += stride) {
     const int tinfo = a.tiles[t];
     const int start = tinfo & 0x7fffffff;
     const bool heavy = tinfo < 0;
@@ -630,7 +631,7 @@ __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
   __syncthreads();
   double* red = reinterpret_cast<double*>(smem);
   if (MODE == kApply) return;
-  double* prow = a.partials + (size_t)blockIdx.x * a.nv;
+  double* prow = a.partials + (size_t)brank * a.nv;
   const int KK = KP * KP;
   if (MODE == kGF1) {
     block_vec_out<T, KP, 3>(cacc, red, prow, 0, wave, lane, WPB);
@@ -655,13 +656,12 @@ __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
 // ---------------------------------------------------------------------------
 
 template <typename T, int KP, int MODE>
-__global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
-    dense_kernel(PassArgs a) {
+__device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nblk,
+                                           unsigned char* smem) {
   using G = Geo<T, KP>;
   using SM = Smem<T, KP, MODE>;
   constexpr int WPB = SM::WPB;
   constexpr int NV = nvec_of(MODE);
-  extern __shared__ __align__(16) unsigned char smem[];
   T* frag = reinterpret_cast<T*>(smem);
   T* frag2 = frag + G::FRAG_ELEMS;
   const int lane = threadIdx.x & 63;
@@ -693,7 +693,7 @@ __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
         if (restart && (-sc[SC<KP>::GG + c] + beta * sc[SC<KP>::VPG + c]) >= 0.0) beta = 0.0;
       }
       colscal[q] = (T)beta;
-      if (blockIdx.x == 0 && threadIdx.x < G::LPR) const_cast<double*>(sc)[SC<KP>::BETA + c] = beta;
+      if (brank == 0 && threadIdx.x < G::LPR) const_cast<double*>(sc)[SC<KP>::BETA + c] = beta;
     }
   } else if (MODE == kUpdate) {
 #pragma unroll
@@ -717,8 +717,8 @@ __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
   zero_gram<T, KP>(gB);
 
   const int64_t ntiles = (a.n + G::TR - 1) / G::TR;
-  const int64_t stride = (int64_t)gridDim.x * WPB;
-  for (int64_t t = (int64_t)blockIdx.x * WPB + wave; t < ntiles; t += stride) {
+  const int64_t stride = (int64_t)nblk * WPB;
+  for (int64_t t = (int64_t)brank * WPB + wave; t < ntiles; t += stride) {
     const int64_t r0 = t * G::TR;
     const int cnt = (int)((a.n - r0) < G::TR ? (a.n - r0) : G::TR);
 #pragma unroll
@@ -839,7 +839,7 @@ __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
 
   __syncthreads();
   double* red = reinterpret_cast<double*>(smem);
-  double* prow = a.partials + (size_t)blockIdx.x * a.nv;
+  double* prow = a.partials + (size_t)brank * a.nv;
   const int KK = KP * KP;
   if (MODE == kVPass) {
     block_gram_out<T, KP, true>(gA, red, prow, 0, wave, lane, WPB);
@@ -852,6 +852,18 @@ __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64))
   } else if (MODE == kGPassF2) {
     block_vec_out<T, KP, 3>(cacc, red, prow, 0, wave, lane, WPB);
   }
+}
+
+template <typename T, int KP, int MODE, bool CHECK, bool BF>
+__global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64)) spmm_kernel(PassArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  spmm_body<T, KP, MODE, CHECK, BF>(a, blockIdx.x, gridDim.x, smem);
+}
+
+template <typename T, int KP, int MODE>
+__global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64)) dense_kernel(PassArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  dense_body<T, KP, MODE>(a, blockIdx.x, gridDim.x, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1075,8 +1087,8 @@ __device__ inline double block_sum256(double x, double* buf) {
 }
 
 template <int KP>
-__global__ void __launch_bounds__(256) linesearch_kernel(int variant, int first, double alpha0,
-                                                         double* sc, int* status) {
+__device__ __forceinline__ void linesearch_body(int variant, int first, double alpha0,
+                                                double* sc, int* status) {
   __shared__ double buf[256];
   __shared__ double co[4];
   const int KK = KP * KP;
@@ -1201,6 +1213,12 @@ __global__ void __launch_bounds__(256) linesearch_kernel(int variant, int first,
   if (tid < KP) sc[SC<KP>::GGP + tid] = sc[SC<KP>::GG + tid];
 }
 
+template <int KP>
+__global__ void __launch_bounds__(256) linesearch_kernel(int variant, int first, double alpha0,
+                                                         double* sc, int* status) {
+  linesearch_body<KP>(variant, first, alpha0, sc, status);
+}
+
 // ---------------------------------------------------------------------------
 // Residual of the Ritz pairs of A on span(X) from M = X^T X, H = X^T A X,
 // K = (AX)^T (AX):  relres^2 = tr(M^{-1} K) / tr((M^{-1} H)^2) - 1
@@ -1208,8 +1226,8 @@ __global__ void __launch_bounds__(256) linesearch_kernel(int variant, int first,
 // ---------------------------------------------------------------------------
 
 template <int KP>
-__global__ void __launch_bounds__(256) residual_kernel(int variant, double normA2, double* sc,
-                                                       int* status) {
+__device__ __forceinline__ void residual_body(int variant, double normA2, double* sc,
+                                              int* status) {
   __shared__ double L[KP * KP];
   __shared__ double W[KP * KP];
   __shared__ double buf[256];
@@ -1287,6 +1305,12 @@ __global__ void __launch_bounds__(256) residual_kernel(int variant, double normA
     if (fail) atomicOr(status, kStCholesky);
     if (!isfinite(sc[SC<KP>::RELRES])) atomicOr(status, kStNonfinite);
   }
+}
+
+template <int KP>
+__global__ void __launch_bounds__(256) residual_kernel(int variant, double normA2, double* sc,
+                                                       int* status) {
+  residual_body<KP>(variant, normA2, sc, status);
 }
 
 // objective from the k x k products only: f1 = ||A||_F^2 + 2 tr(H) + ||M||_F^2,
@@ -1515,6 +1539,245 @@ hipError_t launch_residual(int k, int variant, double normA2, double* sc, int* s
     case 16: hipLaunchKernelGGL(residual_kernel<16>, dim3(1), dim3(256), 0, s, variant, normA2, sc, status); break;
     case 32: hipLaunchKernelGGL(residual_kernel<32>, dim3(1), dim3(256), 0, s, variant, normA2, sc, status); break;
     case 64: hipLaunchKernelGGL(residual_kernel<64>, dim3(1), dim3(256), 0, s, variant, normA2, sc, status); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched passes: block -> (graph, rank, blocks of that graph) from a segment
+// table whose blocks of one graph share an XCD (ids congruent modulo 8), so a
+// small graph's rows stay in that XCD's L2.  Converged graphs are skipped.
+// ---------------------------------------------------------------------------
+
+__device__ inline PassArgs batch_pass_args(const BatchArgs& b, const BatchGraph& d) {
+  PassArgs a;
+  a.n = d.n;
+  a.k = b.k;
+  a.mode = b.mode;
+  a.variant = b.variant;
+  a.flags = b.flags;
+  a.sc = d.sc;
+  a.partials = d.partials;
+  a.nv = b.nv;
+  a.status = d.status;
+  a.sched = d.sched;
+  a.sptr = d.sptr;
+  a.tiles = d.tiles;
+  a.ntiles = d.ntiles;
+  a.pk = d.pk;
+  const int cur = b.cur, prev = b.cur ^ 1;
+  const bool first = (b.flags & kFlagFirst) != 0;
+  switch (b.mode) {
+    case kGF1:
+      a.Z = d.X;
+      a.Zg = b.bf16 ? d.Xb : nullptr;
+      a.G = d.G[cur];
+      a.Gp = first ? nullptr : d.G[prev];
+      a.Vp = first ? nullptr : d.V[prev];
+      break;
+    case kAXF2:
+      a.Z = d.X;
+      a.Zg = b.bf16 ? d.Xb : nullptr;
+      a.Y = d.AX;
+      break;
+    case kGPassF2:
+      a.X = d.X;
+      a.AX = d.AX;
+      a.G = d.G[cur];
+      a.Gp = first ? nullptr : d.G[prev];
+      a.Vp = first ? nullptr : d.V[prev];
+      break;
+    case kVPass:
+      a.G = d.G[cur];
+      a.Vp = first ? nullptr : d.V[prev];
+      a.V = d.V[cur];
+      a.Vb = b.bf16 ? d.Vb : nullptr;
+      a.X = d.X;
+      break;
+    case kAVF1:
+    case kAVF2:
+      a.Z = d.V[cur];
+      a.Zg = b.bf16 ? d.Vb : nullptr;
+      a.X = d.X;
+      break;
+    case kUpdate:
+      a.X = d.X;
+      a.Xw = d.X;
+      a.Xb = b.bf16 ? d.Xb : nullptr;
+      a.V = d.V[cur];
+      break;
+    case kGramM:
+      a.X = d.X;
+      a.Xb = b.bf16 ? d.Xb : nullptr;
+      break;
+  }
+  return a;
+}
+
+template <int KP, int MODE, bool CHECK, bool BF>
+__global__ void __launch_bounds__((Cfg<float, KP>::WPB * 64)) batch_spmm_kernel(BatchArgs b) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const BatchSeg sg = b.seg[blockIdx.x];
+  if (sg.g < 0) return;
+  const BatchGraph& d = b.graphs[sg.g];
+  if (*d.active == 0) return;
+  const PassArgs a = batch_pass_args(b, d);
+  spmm_body<float, KP, MODE, CHECK, BF>(a, sg.rank, sg.nblk, smem);
+}
+
+template <int KP, int MODE>
+__global__ void __launch_bounds__((Cfg<float, KP>::WPB * 64)) batch_dense_kernel(BatchArgs b) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const BatchSeg sg = b.seg[blockIdx.x];
+  if (sg.g < 0) return;
+  const BatchGraph& d = b.graphs[sg.g];
+  if (*d.active == 0) return;
+  const PassArgs a = batch_pass_args(b, d);
+  dense_body<float, KP, MODE>(a, sg.rank, sg.nblk, smem);
+}
+
+// per-graph sum of its block partial rows, in block order
+__global__ void __launch_bounds__(64) batch_finalize_kernel(BatchArgs b) {
+  const BatchGraph& d = b.graphs[blockIdx.y];
+  if (*d.active == 0) return;
+  const int v = blockIdx.x * 64 + threadIdx.x;
+  if (v >= b.nv) return;
+  double s = 0.0;
+  for (int b0 = 0; b0 < d.nblk; b0 += kFinChunk) {
+    double x[kFinChunk];
+#pragma unroll
+    for (int q = 0; q < kFinChunk; ++q)
+      x[q] = (b0 + q < d.nblk) ? d.partials[(size_t)(b0 + q) * b.nv + v] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kFinChunk; ++q) s += x[q];
+  }
+  d.sc[b.off + v] = s;
+}
+
+template <int KP>
+__global__ void __launch_bounds__(256) batch_linesearch_kernel(BatchArgs b, double alpha0,
+                                                               int first_fixed) {
+  const BatchGraph& d = b.graphs[blockIdx.x];
+  if (*d.active == 0) return;
+  linesearch_body<KP>(b.variant, first_fixed, alpha0, d.sc, d.status);
+}
+
+// residual of X^t; a graph whose residual meets the tolerance (or whose
+// status turned non-zero) stops iterating with this X
+template <int KP>
+__global__ void __launch_bounds__(256) batch_residual_kernel(BatchArgs b) {
+  const BatchGraph& d = b.graphs[blockIdx.x];
+  if (*d.active == 0) return;
+  residual_body<KP>(b.variant, d.normA2, d.sc, d.status);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double rr = d.sc[SC<KP>::RELRES];
+    if ((b.tol > 0.0 && rr <= b.tol) || *d.status != 0) {
+      *d.active = 0;
+      *d.done_iter = b.t;
+    }
+  }
+}
+
+template <int KP>
+static hipError_t batch_spmm_t(BatchArgs& b, int grid, hipStream_t s) {
+  const bool chk = (b.flags & kFlagCheck) != 0;
+#define OFM_BSPMM(MODE)                                                                      \
+  {                                                                                          \
+    using SM = Smem<float, KP, MODE>;                                                        \
+    if (b.bf16) {                                                                            \
+      if (chk) hipLaunchKernelGGL((batch_spmm_kernel<KP, MODE, true, true>), dim3(grid),      \
+                                  dim3(SM::WPB * 64), SM::bytes, s, b);                      \
+      else hipLaunchKernelGGL((batch_spmm_kernel<KP, MODE, false, true>), dim3(grid),         \
+                              dim3(SM::WPB * 64), SM::bytes, s, b);                          \
+    } else {                                                                                 \
+      if (chk) hipLaunchKernelGGL((batch_spmm_kernel<KP, MODE, true, false>), dim3(grid),     \
+                                  dim3(SM::WPB * 64), SM::bytes, s, b);                      \
+      else hipLaunchKernelGGL((batch_spmm_kernel<KP, MODE, false, false>), dim3(grid),        \
+                              dim3(SM::WPB * 64), SM::bytes, s, b);                          \
+    }                                                                                        \
+    return hipGetLastError();                                                                \
+  }
+  switch (b.mode) {
+    case kGF1: OFM_BSPMM(kGF1)
+    case kAXF2: OFM_BSPMM(kAXF2)
+    case kAVF1: OFM_BSPMM(kAVF1)
+    case kAVF2: OFM_BSPMM(kAVF2)
+  }
+#undef OFM_BSPMM
+  return hipErrorInvalidValue;
+}
+
+template <int KP>
+static hipError_t batch_dense_t(BatchArgs& b, int grid, hipStream_t s) {
+#define OFM_BDENSE(MODE)                                                                   \
+  {                                                                                        \
+    using SM = Smem<float, KP, MODE>;                                                      \
+    hipLaunchKernelGGL((batch_dense_kernel<KP, MODE>), dim3(grid), dim3(SM::WPB * 64),      \
+                       SM::bytes, s, b);                                                   \
+    return hipGetLastError();                                                              \
+  }
+  switch (b.mode) {
+    case kGPassF2: OFM_BDENSE(kGPassF2)
+    case kVPass: OFM_BDENSE(kVPass)
+    case kUpdate: OFM_BDENSE(kUpdate)
+    case kGramM: OFM_BDENSE(kGramM)
+  }
+#undef OFM_BDENSE
+  return hipErrorInvalidValue;
+}
+
+int batch_wpb(int k) { return wpb(OFM_FP32, k); }
+
+hipError_t launch_batch_spmm(int k, BatchArgs& b, int grid, hipStream_t s) {
+  switch (k) {
+    case 4: return batch_spmm_t<4>(b, grid, s);
+    case 8: return batch_spmm_t<8>(b, grid, s);
+    case 16: return batch_spmm_t<16>(b, grid, s);
+    case 32: return batch_spmm_t<32>(b, grid, s);
+    case 64: return batch_spmm_t<64>(b, grid, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_dense(int k, BatchArgs& b, int grid, hipStream_t s) {
+  switch (k) {
+    case 4: return batch_dense_t<4>(b, grid, s);
+    case 8: return batch_dense_t<8>(b, grid, s);
+    case 16: return batch_dense_t<16>(b, grid, s);
+    case 32: return batch_dense_t<32>(b, grid, s);
+    case 64: return batch_dense_t<64>(b, grid, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_finalize(BatchArgs& b, hipStream_t s) {
+  if (b.nv == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_finalize_kernel, dim3((b.nv + 63) / 64, b.ngraphs), dim3(64), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_linesearch(int k, BatchArgs& b, double alpha0, int first_fixed,
+                                   hipStream_t s) {
+  switch (k) {
+    case 4: hipLaunchKernelGGL(batch_linesearch_kernel<4>, dim3(b.ngraphs), dim3(256), 0, s, b, alpha0, first_fixed); break;
+    case 8: hipLaunchKernelGGL(batch_linesearch_kernel<8>, dim3(b.ngraphs), dim3(256), 0, s, b, alpha0, first_fixed); break;
+    case 16: hipLaunchKernelGGL(batch_linesearch_kernel<16>, dim3(b.ngraphs), dim3(256), 0, s, b, alpha0, first_fixed); break;
+    case 32: hipLaunchKernelGGL(batch_linesearch_kernel<32>, dim3(b.ngraphs), dim3(256), 0, s, b, alpha0, first_fixed); break;
+    case 64: hipLaunchKernelGGL(batch_linesearch_kernel<64>, dim3(b.ngraphs), dim3(256), 0, s, b, alpha0, first_fixed); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_residual(int k, BatchArgs& b, hipStream_t s) {
+  switch (k) {
+    case 4: hipLaunchKernelGGL(batch_residual_kernel<4>, dim3(b.ngraphs), dim3(256), 0, s, b); break;
+    case 8: hipLaunchKernelGGL(batch_residual_kernel<8>, dim3(b.ngraphs), dim3(256), 0, s, b); break;
+    case 16: hipLaunchKernelGGL(batch_residual_kernel<16>, dim3(b.ngraphs), dim3(256), 0, s, b); break;
+    case 32: hipLaunchKernelGGL(batch_residual_kernel<32>, dim3(b.ngraphs), dim3(256), 0, s, b); break;
+    case 64: hipLaunchKernelGGL(batch_residual_kernel<64>, dim3(b.ngraphs), dim3(256), 0, s, b); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -92,6 +92,10 @@ _SIGS = {
     "ofm_objective": (_I, [_P, _P, _P, _P, _P]),
     "ofm_set_timing": (_I, [_P, _I]),
     "ofm_get_timing": (_I, [_P, _P, _P, _I]),
+    "ofm_batch_create": (_I, [_I, _P, _P, ctypes.POINTER(Opts), ctypes.POINTER(_P)]),
+    "ofm_batch_destroy": (_I, [_P]),
+    "ofm_batch_solve": (_I, [_P, _P, _P, _P]),
+    "ofm_batch_schedule": (_I, [_P, _P, _P]),
     "ofm_row_normalize": (_I, [_I64, _I, _I, _P, _P, _P]),
     "ofm_kmeans_assign": (_I, [_I64, _I, _I, _P, _P, _P, _P, _P]),
     "ofm_kmeans": (_I, [_I64, _I, _I, _P, _P, _I, _P, _P, _P, _P]),
@@ -327,6 +331,60 @@ class Workspace:
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             self._lib.ofm_workspace_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent graphs solved together (one launch per pass and width
+    group).  ``laps``: Laplacian handles; ``ks``: their widths."""
+
+    def __init__(self, laps, ks, variant="f1", precision=OFM_FP32, max_iter: int = 1000,
+                 check_every: int = 10, tol: float = 1e-4, restart: bool = False,
+                 first_step: int = 0, alpha0: float = 0.0):
+        lib = load()
+        self._lib = lib
+        self.laps = list(laps)
+        self.ks = [int(k) for k in ks]
+        v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        self.opts = Opts(v, int(precision), int(max_iter), int(check_every), int(first_step),
+                         1 if restart else 0, float(alpha0), float(tol))
+        n = len(self.laps)
+        handles = (ctypes.c_void_p * n)(*[l.handle.value for l in self.laps])
+        kk = (ctypes.c_int * n)(*self.ks)
+        h = ctypes.c_void_p()
+        _check(lib.ofm_batch_create(n, handles, kk, ctypes.byref(self.opts), ctypes.byref(h)),
+               "ofm_batch_create")
+        self.handle = h
+
+    def solve(self, Xs, stream=None):
+        n = len(self.laps)
+        for X, lap, k in zip(Xs, self.laps, self.ks):
+            _dev_block(X, k)
+            if X.dtype != _torch().float32 or X.shape[0] != lap.n:
+                raise ValueError("X must be N x k FP32")
+        ptrs = (ctypes.c_void_p * n)(*[X.data_ptr() for X in Xs])
+        stats = (Stats * n)()
+        _check(self._lib.ofm_batch_solve(self.handle, ptrs, _stream(stream), stats),
+               "ofm_batch_solve")
+        return [s.as_dict() for s in stats]
+
+    def schedule(self):
+        scale = ctypes.c_int()
+        ms = np.zeros(3)
+        _check(self._lib.ofm_batch_schedule(self.handle, ctypes.byref(scale),
+                                            ms.ctypes.data_as(ctypes.c_void_p)),
+               "ofm_batch_schedule")
+        return scale.value, ms
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self._lib.ofm_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
