@@ -74,7 +74,7 @@ def cpu_baseline(g, x0, k: int, variant_id: int):
                        f"SciPy CSR x dense runs on 1 thread, dense products on {threads} BLAS threads")}
 
 
-def batched_vs_plain(variant: str, count: int = 256):
+def batched_vs_plain(variant: str, count: int = 256, plain: bool = True):
     """256 independent SBM graphs (N ~ U{1000..50000}, k ~ U{4,8,16,32}, mean
     degree ~ U[8,32], r = 0.3): wall time until every graph reaches residual
     1e-4 (checked every 10 iterations), batched FP32 vs a loop of per-graph
@@ -98,18 +98,20 @@ def batched_vs_plain(variant: str, count: int = 256):
     st_b = B.solve(Xs)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
-    scale, cand = B.schedule()
+    tpw, cand, escalated = B.schedule()
     B.close()
-    wss = [ofm.Workspace(lap, k, variant=variant, precision=ofm.OFM_FP64, max_iter=3000,
-                         check_every=10, tol=1e-4, restart=tri) for lap, k in zip(laps, ks)]
-    X64 = [torch.tensor(x0, dtype=torch.float64, device="cuda") for _, x0 in gl]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st_p = [ws.solve(X) for ws, X in zip(wss, X64)]
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    for ws in wss:
-        ws.close()
+    st_p, t_plain = [{"converged": 0, "iters": 0}], float("nan")
+    if plain:
+        wss = [ofm.Workspace(lap, k, variant=variant, precision=ofm.OFM_FP64, max_iter=3000,
+                             check_every=10, tol=1e-4, restart=tri) for lap, k in zip(laps, ks)]
+        X64 = [torch.tensor(x0, dtype=torch.float64, device="cuda") for _, x0 in gl]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st_p = [ws.solve(X) for ws, X in zip(wss, X64)]
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        for ws in wss:
+            ws.close()
     return {
         "graphs": count, "sum_n": int(sum(g.n for g, _ in gl)),
         "sum_nnz": int(sum(g.nnz for g, _ in gl)),
@@ -119,7 +121,11 @@ def batched_vs_plain(variant: str, count: int = 256):
         "plain_converged": int(sum(s["converged"] for s in st_p)),
         "batched_max_iters": int(max(s["iters"] for s in st_b)),
         "plain_max_iters": int(max(s["iters"] for s in st_p)),
-        "batched_schedule_scale": scale, "schedule_candidates_ms": [round(x, 3) for x in cand],
+        "batched_tiles_per_wave": tpw, "schedule_candidates_ms": [round(x, 3) for x in cand],
+        "batched_escalated_to_fp64": escalated,
+        "batched_not_converged": [
+            {"graph": i, "n": gl[i][0].n, "k": ks[i], "relres": st_b[i]["relres"]}
+            for i in range(count) if not st_b[i]["converged"]],
     }
 
 
@@ -133,6 +139,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched solve (no plain loop, no C3 run); prints its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -146,6 +154,9 @@ def main():
     from paper_2305_10356_amd import graphs, ofm
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.batched_only:
+        print(json.dumps(batched_vs_plain(args.variant, plain=False)), flush=True)
+        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     k = 32

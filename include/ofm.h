@@ -187,7 +187,10 @@ ofm_status ofm_step(ofm_workspace ws, void* X, hipStream_t stream);
 
 /*
  * ofm_init, then ofm_step until the residual <= tol or max_iter updates.
- * Synchronizing: reads the stats every check_every iterations.
+ * Synchronizing: reads the stats every check_every iterations.  When tol > 0,
+ * a residual evaluation that meets tol freezes X on the device (every later
+ * step size is 0 until the next ofm_init / ofm_set_state), so the returned X
+ * is the iterate whose residual was reported.
  */
 ofm_status ofm_solve(ofm_workspace ws, void* X, hipStream_t stream, ofm_stats* host_out);
 
@@ -239,12 +242,19 @@ ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps, const int
 ofm_status ofm_batch_destroy(ofm_batch b);
 /* Solve every graph from its X (host_X[i]: device pointer to graph i's N_i x k_i
  * FP32 block, updated in place); host_stats[count] receives the per-graph
- * stats (iters = updates done, relres of the X it stopped at).  Synchronizing. */
+ * stats (iters = updates done, relres of the X it stopped at).  A graph whose
+ * FP32 residual decreases by less than 5% over 10 checks before reaching tol
+ * (or that reaches max_iter) is finished by an FP64 solve (k <= 32) started
+ * from its FP32 X with a fresh CG state; that stage allocates a workspace.
+ * Synchronizing. */
 ofm_status ofm_batch_solve(ofm_batch b, void* const* host_X, hipStream_t stream,
                            ofm_stats* host_stats);
-/* Schedule chosen by the last solve: host_scale = blocks-per-graph multiplier,
- * host_ms[3] = measured time per iteration of each candidate (0 if untried). */
-ofm_status ofm_batch_schedule(ofm_batch b, int* host_scale, double* host_ms);
+/* Schedule chosen by the last solve: host_tpw = tiles per wavefront target
+ * (blocks per graph ~ tiles / (waves per block * tpw)), host_ms[3] = measured
+ * time per iteration of each candidate (0 if untried), host_escalated = number
+ * of graphs finished in FP64.  Any pointer may be NULL. */
+ofm_status ofm_batch_schedule(ofm_batch b, int* host_tpw, double* host_ms,
+                              int* host_escalated);
 
 /*
  * Host copy (synchronizing) of one k x k FP64 product held by the workspace,

@@ -120,6 +120,7 @@ struct ofm_workspace_s {
   double* lvl2 = nullptr;
   int* tickets = nullptr;
   int* status = nullptr;
+  int* frozen = nullptr;   // set on the device when the residual met tol
   int64_t t = 0;
   int64_t last_check = -1;
   bool initialized = false;
@@ -421,6 +422,7 @@ static void free_ws(ofm_workspace ws) {
   dev_free(ws->lvl2);
   dev_free(ws->tickets);
   dev_free(ws->status);
+  dev_free(ws->frozen);
   delete ws;
 }
 
@@ -473,9 +475,11 @@ extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_o
   if ((st = dev_alloc(&ws->lvl2, (size_t)ny * nvmax)) != OFM_OK) return fail(st);
   if ((st = dev_alloc(&ws->tickets, (nvmax + 63) / 64)) != OFM_OK) return fail(st);
   if ((st = dev_alloc(&ws->status, 1)) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(&ws->frozen, 1)) != OFM_OK) return fail(st);
   if (hipMemset(ws->sc, 0, sc_total(k) * sizeof(double)) != hipSuccess ||
       hipMemset(ws->tickets, 0, ((nvmax + 63) / 64) * sizeof(int)) != hipSuccess ||
       hipMemset(ws->status, 0, sizeof(int)) != hipSuccess ||
+      hipMemset(ws->frozen, 0, sizeof(int)) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess)
     return fail(OFM_E_HIP);
   *out = ws;
@@ -525,9 +529,11 @@ static ofm_status run_dense(ofm_workspace ws, PassArgs& a, hipStream_t s) {
   return finalize(ws, a, s);
 }
 
-static hipError_t run_residual(ofm_workspace ws, hipStream_t s) {
+// may_freeze: a residual <= tol freezes X (inside the iteration only)
+static hipError_t run_residual(ofm_workspace ws, hipStream_t s, bool may_freeze) {
   return timed(ws, OFM_PASS_RESIDUAL, s, [&] {
-    return launch_residual(ws->k, ws->opts.variant, ws->lap->g.normA2, ws->sc, ws->status, s);
+    return launch_residual(ws->k, ws->opts.variant, ws->lap->g.normA2, ws->sc, ws->status,
+                           may_freeze ? ws->opts.tol : 0.0, may_freeze ? ws->frozen : nullptr, s);
   });
 }
 
@@ -575,14 +581,14 @@ static ofm_status direction(ofm_workspace ws, void* X, const void* Gp, const voi
     a.Gp = Gp;
     a.Vp = Vp;
     OFMCHK(run_spmm(ws, a, s));
-    if (check) HIPCHK(run_residual(ws, s));
+    if (check) HIPCHK(run_residual(ws, s, true));
   } else {
     PassArgs a = base_args(ws, kAXF2, check ? kFlagCheck : 0);
     a.Z = X;
     a.Zg = ws->Xb;
     a.Y = ws->AX;
     OFMCHK(run_spmm(ws, a, s));
-    if (check) HIPCHK(run_residual(ws, s));
+    if (check) HIPCHK(run_residual(ws, s, true));
     PassArgs b = base_args(ws, kGPassF2, restart);
     b.X = X;
     b.AX = ws->AX;
@@ -612,7 +618,7 @@ static ofm_status search_and_update(ofm_workspace ws, void* X, const void* Vp, b
   OFMCHK(run_spmm(ws, w, s));
   HIPCHK(timed(ws, OFM_PASS_LINESEARCH, s, [&] {
     return launch_linesearch(ws->k, ws->opts.variant, first && ws->opts.first_step == 1,
-                             ws->opts.alpha0, ws->sc, ws->status, s);
+                             ws->opts.alpha0, ws->sc, ws->status, ws->frozen, s);
   }));
   PassArgs u = base_args(ws, kUpdate, 0);
   u.X = X;
@@ -634,6 +640,7 @@ static ofm_status gram_m(ofm_workspace ws, const void* X, hipStream_t s) {
 
 extern "C" ofm_status ofm_init(ofm_workspace ws, void* X, hipStream_t stream) {
   if (!ws || !X) return OFM_E_INVALID_ARG;
+  HIPCHK(hipMemsetAsync(ws->frozen, 0, sizeof(int), stream));
   ws->cur = 0;
   ws->t = 0;
   ws->last_check = -1;
@@ -688,7 +695,11 @@ extern "C" ofm_status ofm_solve(ofm_workspace ws, void* X, hipStream_t stream,
     if (will_check) {
       OFMCHK(read_stats(ws, stream, &st));
       if (st.status != OFM_OK) break;
-      if (st.converged) break;
+      if (st.converged) {
+        // the step that found the residual below tol kept X (step size 0)
+        ws->t = st.relres_iter;
+        break;
+      }
     }
   }
   OFMCHK(read_stats(ws, stream, &st));
@@ -704,7 +715,7 @@ extern "C" ofm_status ofm_residual(ofm_workspace ws, const void* X, hipStream_t 
   a.Z = X;
   a.Y = ws->AX;
   OFMCHK(run_spmm(ws, a, stream));
-  HIPCHK(run_residual(ws, stream));
+  HIPCHK(run_residual(ws, stream, false));
   ws->last_check = ws->t;
   ofm_stats st{};
   OFMCHK(read_stats(ws, stream, &st));
@@ -766,6 +777,7 @@ extern "C" ofm_status ofm_set_state(ofm_workspace ws, const void* X, const void*
   PassArgs a = base_args(ws, kGGP, 0);
   a.Gp = ws->G[prev];
   OFMCHK(run_dense(ws, a, stream));
+  HIPCHK(hipMemsetAsync(ws->frozen, 0, sizeof(int), stream));
   ws->t = t;
   ws->last_check = -1;
   ws->initialized = true;
@@ -929,20 +941,21 @@ extern "C" ofm_status ofm_kmeans(int64_t n, int dim, int n_clusters, const float
 namespace {
 
 constexpr int kBatchCand = 3;
-const int kBatchScale[kBatchCand] = {1, 2, 4};
-constexpr int kBatchMaxBlocksPerGraph = 96;
+constexpr int kBatchWorkers = 128;                 // blocks per XCD
+const int kBatchTpw[kBatchCand] = {2, 4, 8};      // candidate tiles per wavefront
 
 struct BatchGroup {
   int k = 0;
   std::vector<int> idx;                 // members (batch indices)
-  std::vector<int> base;                // base blocks per member
-  BatchGraph* dgraphs[kBatchCand] = {nullptr, nullptr, nullptr};
-  BatchSeg* dseg[kBatchCand] = {nullptr, nullptr, nullptr};
-  int grid[kBatchCand] = {0, 0, 0};
-  std::vector<BatchGraph> hg;           // host copy of the descriptors (candidate 0)
+  BatchGraph* dgraphs = nullptr;        // [n]
+  int* dxlist = nullptr;                // members ordered by XCD
+  int* dxoff = nullptr;                 // [9]
+  std::vector<BatchGraph> hg;           // host copy of the descriptors
   int* active = nullptr;                // [n]
   int64_t* done = nullptr;              // [n]
   int* status = nullptr;                // [n]
+  double* hist = nullptr;               // [n][kBatchHist]
+  int* stalled = nullptr;               // [n]
   double* sc = nullptr;                 // [n][SC total]
   double* partials = nullptr;
   char* bufs = nullptr;
@@ -960,19 +973,21 @@ struct ofm_batch_s {
   std::vector<BatchGroup> groups;
   int chosen = 0;
   double cand_ms[kBatchCand] = {0, 0, 0};
+  int escalated = 0;
   hipEvent_t start = nullptr;
 };
 
 static void free_batch(ofm_batch b) {
   if (!b) return;
   for (auto& g : b->groups) {
-    for (int c = 0; c < kBatchCand; ++c) {
-      dev_free(g.dgraphs[c]);
-      dev_free(g.dseg[c]);
-    }
+    dev_free(g.dgraphs);
+    dev_free(g.dxlist);
+    dev_free(g.dxoff);
     dev_free(g.active);
     dev_free(g.done);
     dev_free(g.status);
+    dev_free(g.hist);
+    dev_free(g.stalled);
     dev_free(g.sc);
     dev_free(g.partials);
     dev_free(g.bufs);
@@ -983,26 +998,28 @@ static void free_batch(ofm_batch b) {
   delete b;
 }
 
-// blocks of one graph all on one XCD (block ids congruent modulo 8), XCDs
-// balanced by block count; returns the grid size
-static int batch_schedule(const std::vector<int>& nblk, std::vector<BatchSeg>& seg) {
+// graphs to XCDs, largest first onto the least loaded XCD (work ~ entries +
+// rows); returns the graph order per XCD and the XCD offsets
+static void batch_assign(const std::vector<double>& work, std::vector<int>& xlist,
+                         std::vector<int>& xoff) {
   const int nx = 8;
-  std::vector<int> order(nblk.size());
+  std::vector<int> order(work.size());
   std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return nblk[a] > nblk[c]; });
-  std::vector<std::vector<BatchSeg>> per(nx);
-  std::vector<int64_t> load(nx, 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return work[a] > work[c]; });
+  std::vector<std::vector<int>> per(nx);
+  std::vector<double> load(nx, 0.0);
   for (int gi : order) {
-    int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    for (int r = 0; r < nblk[gi]; ++r) per[x].push_back(BatchSeg{gi, r, nblk[gi]});
-    load[x] += nblk[gi];
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    per[x].push_back(gi);
+    load[x] += work[gi];
   }
-  size_t mx = 0;
-  for (auto& v : per) mx = std::max(mx, v.size());
-  seg.assign(mx * nx, BatchSeg{-1, 0, 0});
-  for (int x = 0; x < nx; ++x)
-    for (size_t i = 0; i < per[x].size(); ++i) seg[i * nx + x] = per[x][i];
-  return (int)(mx * nx);
+  xlist.clear();
+  xoff.assign(nx + 1, 0);
+  for (int x = 0; x < nx; ++x) {
+    xoff[x] = (int)xlist.size();
+    xlist.insert(xlist.end(), per[x].begin(), per[x].end());
+  }
+  xoff[nx] = (int)xlist.size();
 }
 
 extern "C" ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps,
@@ -1043,27 +1060,21 @@ extern "C" ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps
   for (auto& g : B->groups) {
     const int n = (int)g.idx.size();
     const int k = g.k;
-    const int wpbk = batch_wpb(k);
-    const int tr = tile_rows(OFM_FP32, k);
     const int nvmax = 2 * k * k + 3 * k;
     const int sct = sc_total(k);
     ofm_status st;
     if (hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&g.ev, hipEventDisableTiming) != hipSuccess)
       return fail(OFM_E_HIP);
-    // per-graph base block count: about 8 tiles per wave
+    const int maxw = kBatchWorkers;
     size_t part_total = 0, buf_total = 0;
     std::vector<size_t> part_off(n), buf_off(n);
+    std::vector<double> work(n);
     for (int m = 0; m < n; ++m) {
       ofm_laplacian L = host_laps[g.idx[m]];
-      const TileTable* tt = tiles_for(L, OFM_FP32, k);
-      const int64_t tiles = std::max<int64_t>(tt->ntiles, (L->g.n + tr - 1) / tr);
-      int base = (int)std::min<int64_t>(kBatchMaxBlocksPerGraph, (tiles + 8 * wpbk - 1) / (8 * wpbk));
-      base = std::max(base, 1);
-      g.base.push_back(base);
-      const int maxb = std::min(kBatchMaxBlocksPerGraph, base * kBatchScale[kBatchCand - 1]);
+      work[m] = (double)L->g.nnz * k + 8.0 * (double)L->g.n * k;
       part_off[m] = part_total;
-      part_total += (size_t)maxb * nvmax;
+      part_total += (size_t)maxw * nvmax;
       buf_off[m] = buf_total;
       const size_t blk = (size_t)L->g.n * k * 4;
       buf_total += 5 * blk + (bf ? blk : 0);   // V x2, G x2, AX (+ BF16 copies of X and V)
@@ -1072,6 +1083,8 @@ extern "C" ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps
     if ((st = dev_alloc(&g.active, n)) != OFM_OK) return fail(st);
     if ((st = dev_alloc(&g.done, n)) != OFM_OK) return fail(st);
     if ((st = dev_alloc(&g.status, n)) != OFM_OK) return fail(st);
+    if ((st = dev_alloc(&g.hist, (size_t)n * kBatchHist)) != OFM_OK) return fail(st);
+    if ((st = dev_alloc(&g.stalled, n)) != OFM_OK) return fail(st);
     if ((st = dev_alloc(&g.sc, (size_t)n * sct)) != OFM_OK) return fail(st);
     if ((st = dev_alloc(&g.partials, part_total)) != OFM_OK) return fail(st);
     if ((st = dev_alloc(&g.bufs, buf_total)) != OFM_OK) return fail(st);
@@ -1101,25 +1114,18 @@ extern "C" ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps
       d.status = g.status + m;
       d.active = g.active + m;
       d.done_iter = g.done + m;
+      d.hist = g.hist + (size_t)m * kBatchHist;
+      d.stalled = g.stalled + m;
       d.normA2 = L->g.normA2;
     }
-    for (int c = 0; c < kBatchCand; ++c) {
-      std::vector<int> nb(n);
-      std::vector<BatchGraph> hc = g.hg;
-      for (int m = 0; m < n; ++m) {
-        nb[m] = std::min(kBatchMaxBlocksPerGraph, g.base[m] * kBatchScale[c]);
-        hc[m].nblk = nb[m];
-      }
-      std::vector<BatchSeg> seg;
-      g.grid[c] = batch_schedule(nb, seg);
-      if ((st = dev_alloc(&g.dgraphs[c], n)) != OFM_OK) return fail(st);
-      if ((st = dev_alloc(&g.dseg[c], seg.size())) != OFM_OK) return fail(st);
-      if (hipMemcpy(g.dgraphs[c], hc.data(), n * sizeof(BatchGraph), hipMemcpyHostToDevice) !=
-              hipSuccess ||
-          hipMemcpy(g.dseg[c], seg.data(), seg.size() * sizeof(BatchSeg), hipMemcpyHostToDevice) !=
-              hipSuccess)
-        return fail(OFM_E_HIP);
-    }
+    std::vector<int> xlist, xoff;
+    batch_assign(work, xlist, xoff);
+    if ((st = dev_alloc(&g.dgraphs, n)) != OFM_OK) return fail(st);
+    if ((st = dev_alloc(&g.dxlist, n)) != OFM_OK) return fail(st);
+    if ((st = dev_alloc(&g.dxoff, 9)) != OFM_OK) return fail(st);
+    if (hipMemcpy(g.dxlist, xlist.data(), n * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g.dxoff, xoff.data(), 9 * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(OFM_E_HIP);
   }
   *out = B;
   return OFM_OK;
@@ -1131,27 +1137,27 @@ extern "C" ofm_status ofm_batch_destroy(ofm_batch b) {
   return OFM_OK;
 }
 
-extern "C" ofm_status ofm_batch_schedule(ofm_batch b, int* host_scale, double* host_ms) {
+extern "C" ofm_status ofm_batch_schedule(ofm_batch b, int* host_tpw, double* host_ms,
+                                         int* host_escalated) {
   if (!b) return OFM_E_INVALID_ARG;
-  if (host_scale) *host_scale = kBatchScale[b->chosen];
+  if (host_tpw) *host_tpw = kBatchTpw[b->chosen];
   if (host_ms)
     for (int c = 0; c < kBatchCand; ++c) host_ms[c] = b->cand_ms[c];
+  if (host_escalated) *host_escalated = b->escalated;
   return OFM_OK;
 }
 
 // the passes of one batched group: a dense or SpMM launch plus its per-graph
 // reduction
-static ofm_status bpass(BatchGroup& g, BatchArgs base, int mode, int flags, int cand, bool spmm) {
+static ofm_status bpass(BatchGroup& g, BatchArgs base, int mode, int flags, bool spmm) {
   BatchArgs a = base;
   a.mode = mode;
   a.flags = flags;
-  a.graphs = g.dgraphs[cand];
-  a.seg = g.dseg[cand];
-  a.ngraphs = (int)g.idx.size();
   a.nv = partial_nv(g.k, mode, flags);
   a.off = partial_off(g.k, mode);
-  HIPCHK(spmm ? launch_batch_spmm(g.k, a, g.grid[cand], g.stream)
-              : launch_batch_dense(g.k, a, g.grid[cand], g.stream));
+  const int grid = 8 * a.workers;
+  HIPCHK(spmm ? launch_batch_spmm(g.k, a, grid, g.stream)
+              : launch_batch_dense(g.k, a, grid, g.stream));
   HIPCHK(launch_batch_finalize(a, g.stream));
   return OFM_OK;
 }
@@ -1166,24 +1172,28 @@ static ofm_status batch_iteration(ofm_batch B, BatchGroup& g, int cur, int64_t t
   base.bf16 = o.precision == OFM_FP32_BF16X;
   base.tol = o.tol;
   base.t = t;
-  base.graphs = g.dgraphs[cand];
-  base.seg = g.dseg[cand];
+  base.graphs = g.dgraphs;
+  base.xlist = g.dxlist;
+  base.xoff = g.dxoff;
+  base.workers = kBatchWorkers;
+  base.tpw = kBatchTpw[cand];
+  base.check_every = o.check_every;
   base.ngraphs = (int)g.idx.size();
   const int rs = o.restart ? kFlagRestart : 0;
   const int fs = first ? kFlagFirst : 0;
-  if (first) OFMCHK(bpass(g, base, kGramM, 0, cand, false));
+  if (first) OFMCHK(bpass(g, base, kGramM, 0, false));
   const bool f2 = o.variant == OFM_F2 || o.variant == OFM_TRI_F2;
   if (!f2) {
-    OFMCHK(bpass(g, base, kGF1, (check ? kFlagCheck : 0) | rs | fs, cand, true));
+    OFMCHK(bpass(g, base, kGF1, (check ? kFlagCheck : 0) | rs | fs, true));
   } else {
-    OFMCHK(bpass(g, base, kAXF2, check ? kFlagCheck : 0, cand, true));
+    OFMCHK(bpass(g, base, kAXF2, check ? kFlagCheck : 0, true));
   }
   if (check) HIPCHK(launch_batch_residual(g.k, base, g.stream));
-  if (f2) OFMCHK(bpass(g, base, kGPassF2, rs | fs, cand, false));
-  OFMCHK(bpass(g, base, kVPass, rs | fs, cand, false));
-  OFMCHK(bpass(g, base, f2 ? kAVF2 : kAVF1, 0, cand, true));
+  if (f2) OFMCHK(bpass(g, base, kGPassF2, rs | fs, false));
+  OFMCHK(bpass(g, base, kVPass, rs | fs, false));
+  OFMCHK(bpass(g, base, f2 ? kAVF2 : kAVF1, 0, true));
   HIPCHK(launch_batch_linesearch(g.k, base, o.alpha0, first && o.first_step == 1, g.stream));
-  OFMCHK(bpass(g, base, kUpdate, 0, cand, false));
+  OFMCHK(bpass(g, base, kUpdate, 0, false));
   return OFM_OK;
 }
 
@@ -1198,18 +1208,14 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
     HIPCHK(hipStreamWaitEvent(g.stream, B->start, 0));
     const int n = (int)g.idx.size();
     for (int m = 0; m < n; ++m) g.hg[m].X = host_X[g.idx[m]];
-    // descriptors of every candidate carry the caller's X pointers
-    for (int c = 0; c < kBatchCand; ++c) {
-      std::vector<BatchGraph> hc = g.hg;
-      for (int m = 0; m < n; ++m)
-        hc[m].nblk = std::min(kBatchMaxBlocksPerGraph, g.base[m] * kBatchScale[c]);
-      HIPCHK(hipMemcpy(g.dgraphs[c], hc.data(), n * sizeof(BatchGraph), hipMemcpyHostToDevice));
-    }
+    HIPCHK(hipMemcpy(g.dgraphs, g.hg.data(), n * sizeof(BatchGraph), hipMemcpyHostToDevice));
     std::vector<int> ones(n, 1);
     std::vector<int64_t> minus(n, -1);
     HIPCHK(hipMemcpyAsync(g.active, ones.data(), n * sizeof(int), hipMemcpyHostToDevice, g.stream));
     HIPCHK(hipMemcpyAsync(g.done, minus.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, g.stream));
     HIPCHK(hipMemsetAsync(g.status, 0, n * sizeof(int), g.stream));
+    HIPCHK(hipMemsetAsync(g.stalled, 0, n * sizeof(int), g.stream));
+    HIPCHK(hipMemsetAsync(g.hist, 0, (size_t)n * kBatchHist * sizeof(double), g.stream));
     HIPCHK(hipStreamSynchronize(g.stream));
   }
   // set-up step of Algorithm 2, then the loop; the first iterations try the
@@ -1258,7 +1264,9 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
     }
   }
   B->chosen = tuned < 0 ? 0 : tuned;
-  // per-graph stats
+  B->escalated = 0;
+  // per-graph stats; a graph whose FP32 residual stopped decreasing before the
+  // tolerance (or ran out of iterations) is finished in FP64 from its FP32 X
   for (auto& g : B->groups) {
     HIPCHK(hipStreamSynchronize(g.stream));
     const int n = (int)g.idx.size();
@@ -1266,10 +1274,11 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
     const SCOff so = sc_off(g.k);
     std::vector<double> sc((size_t)n * sct);
     std::vector<int64_t> done(n);
-    std::vector<int> stt(n), act(n);
+    std::vector<int> stt(n), stl(n);
     HIPCHK(hipMemcpy(sc.data(), g.sc, sc.size() * sizeof(double), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(done.data(), g.done, n * sizeof(int64_t), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(stt.data(), g.status, n * sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(stl.data(), g.stalled, n * sizeof(int), hipMemcpyDeviceToHost));
     for (int m = 0; m < n; ++m) {
       ofm_stats st{};
       const double* s = sc.data() + (size_t)m * sct;
@@ -1280,6 +1289,39 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
       st.status = (stt[m] & kStNonfinite) ? OFM_E_NONFINITE
                   : (stt[m] & kStCholesky) ? OFM_E_NUMERIC : OFM_OK;
       st.converged = (done[m] >= 0 && st.status == OFM_OK) ? 1 : 0;
+      const bool escalate = !st.converged && st.status == OFM_OK && o.tol > 0.0 && g.k <= 32 &&
+                            st.iters < o.max_iter;
+      if (escalate) {
+        ofm_laplacian L = B->laps[g.idx[m]];
+        ofm_opts o64 = o;
+        o64.precision = OFM_FP64;
+        o64.max_iter = (int)(o.max_iter - st.iters);
+        o64.first_step = 0;
+        ofm_workspace ws = nullptr;
+        double* X64 = nullptr;
+        const int64_t cnt = L->g.n * g.k;
+        OFMCHK(ofm_workspace_create(L, g.k, &o64, &ws));
+        ofm_status es = dev_alloc(&X64, cnt);
+        ofm_stats s64{};
+        if (es == OFM_OK && launch_convert(cnt, 1, host_X[g.idx[m]], X64, stream) != hipSuccess)
+          es = OFM_E_HIP;
+        if (es == OFM_OK) es = ofm_solve(ws, X64, stream, &s64);
+        if (es == OFM_OK || es == OFM_E_NONFINITE || es == OFM_E_NUMERIC) {
+          if (launch_convert(cnt, 0, X64, host_X[g.idx[m]], stream) != hipSuccess ||
+              hipStreamSynchronize(stream) != hipSuccess)
+            es = OFM_E_HIP;
+        }
+        dev_free(X64);
+        ofm_workspace_destroy(ws);
+        if (es == OFM_E_HIP || es == OFM_E_NOMEM) return es;
+        st.iters += s64.iters;
+        st.relres = s64.relres;
+        st.objective = s64.objective;
+        st.relres_iter = st.iters - s64.iters + s64.relres_iter;
+        st.status = s64.status;
+        st.converged = s64.converged;
+        ++B->escalated;
+      }
       if (host_stats) host_stats[g.idx[m]] = st;
     }
     HIPCHK(hipEventRecord(g.ev, g.stream));

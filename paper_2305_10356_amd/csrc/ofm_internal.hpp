@@ -160,17 +160,18 @@ struct BatchGraph {
   int* status = nullptr;
   int* active = nullptr;       // 1 while the graph iterates
   int64_t* done_iter = nullptr;  // iteration whose X met the tolerance (-1: none)
+  double* hist = nullptr;      // [kBatchHist] residuals of the last checks (ring)
+  int* stalled = nullptr;      // 1 when the residual stopped decreasing
   double normA2 = 0.0;
-  int nblk = 1;                // blocks of the current schedule
 };
-struct BatchSeg {
-  int g;     // graph (-1: idle block)
-  int rank;  // block rank within the graph's blocks
-  int nblk;  // number of blocks of that graph
-};
+constexpr int kBatchHist = 10;   // checks compared by the stall test
 struct BatchArgs {
   const BatchGraph* graphs = nullptr;
-  const BatchSeg* seg = nullptr;
+  const int* xlist = nullptr;  // graphs ordered by XCD
+  const int* xoff = nullptr;   // [9]: graphs of XCD x are xlist[xoff[x] .. xoff[x+1])
+  int workers = 1;             // blocks per XCD; block b is worker b / 8 of XCD b % 8
+  int tpw = 4;                 // target tiles per wavefront: a graph uses
+                               // min(workers, ceil(tiles / (waves per block * tpw))) workers
   int ngraphs = 0;
   int k = 0;
   int variant = 0;
@@ -180,6 +181,7 @@ struct BatchArgs {
   int bf16 = 0;      // gather BF16 copies
   double tol = 0.0;
   int64_t t = 0;
+  int check_every = 1;
   int nv = 0;
   int off = 0;       // first scalar slot the mode's products go to
 };
@@ -197,9 +199,9 @@ hipError_t launch_dense(int precision, int k, PassArgs& a, hipStream_t s);
 hipError_t launch_finalize(const double* partials, int nb, int nv, double* out, double* lvl2,
                            int* tickets, hipStream_t s);
 hipError_t launch_linesearch(int k, int variant, int first, double alpha0, double* sc,
-                             int* status, hipStream_t s);
+                             int* status, const int* frozen, hipStream_t s);
 hipError_t launch_residual(int k, int variant, double normA2, double* sc, int* status,
-                           hipStream_t s);
+                           double tol, int* frozen, hipStream_t s);
 hipError_t launch_objective(int k, int variant, double normA2, const double* sc, double* out,
                             hipStream_t s);
 int tile_rows(int precision, int k);
@@ -221,6 +223,7 @@ hipError_t launch_graph_pack(int64_t n, const int32_t* sched, const int32_t* row
                              void* pk32, void* pk64, hipStream_t s);
 
 // Post-processing (ofm_post.hip)
+hipError_t launch_convert(int64_t count, int to_fp64, const void* src, void* dst, hipStream_t s);
 hipError_t launch_row_normalize(int64_t n, int k, int precision, const void* X, void* Y,
                                 hipStream_t s);
 hipError_t launch_kmeans_assign(int64_t n, int dim, int nc, const float* Y, const float* C,

@@ -1086,9 +1086,12 @@ __device__ inline double block_sum256(double x, double* buf) {
   return r;
 }
 
+// frozen (nullable): once the residual met the tolerance every step size is
+// 0, so the iterate that met it is the one kept
 template <int KP>
 __device__ __forceinline__ void linesearch_body(int variant, int first, double alpha0,
-                                                double* sc, int* status) {
+                                                double* sc, int* status, const int* frozen) {
+  const bool frz = frozen != nullptr && *frozen != 0;
   __shared__ double buf[256];
   __shared__ double co[4];
   const int KK = KP * KP;
@@ -1158,6 +1161,7 @@ __device__ __forceinline__ void linesearch_body(int variant, int first, double a
         bad = true;
         al = 0.0;
       }
+      if (frz) al = 0.0;
       coef[0] = a3;
       coef[1] = a2;
       coef[2] = a1;
@@ -1201,6 +1205,7 @@ __device__ __forceinline__ void linesearch_body(int variant, int first, double a
       atomicOr(status, kStNonfinite);
       al = 0.0;
     }
+    if (frz) al = 0.0;
     coef[4 * i + 0] = a3;
     coef[4 * i + 1] = a2;
     coef[4 * i + 2] = a1;
@@ -1215,8 +1220,9 @@ __device__ __forceinline__ void linesearch_body(int variant, int first, double a
 
 template <int KP>
 __global__ void __launch_bounds__(256) linesearch_kernel(int variant, int first, double alpha0,
-                                                         double* sc, int* status) {
-  linesearch_body<KP>(variant, first, alpha0, sc, status);
+                                                         double* sc, int* status,
+                                                         const int* frozen) {
+  linesearch_body<KP>(variant, first, alpha0, sc, status, frozen);
 }
 
 // ---------------------------------------------------------------------------
@@ -1225,9 +1231,10 @@ __global__ void __launch_bounds__(256) linesearch_kernel(int variant, int first,
 // (numerical results section, "Evaluation metrics"); also the objective.
 // ---------------------------------------------------------------------------
 
+// tol > 0 and frozen != nullptr: a residual <= tol sets *frozen
 template <int KP>
 __device__ __forceinline__ void residual_body(int variant, double normA2, double* sc,
-                                              int* status) {
+                                              int* status, double tol, int* frozen) {
   __shared__ double L[KP * KP];
   __shared__ double W[KP * KP];
   __shared__ double buf[256];
@@ -1304,13 +1311,14 @@ __device__ __forceinline__ void residual_body(int variant, double normA2, double
                                                                      : 2.0 * trH - mm;
     if (fail) atomicOr(status, kStCholesky);
     if (!isfinite(sc[SC<KP>::RELRES])) atomicOr(status, kStNonfinite);
+    if (frozen != nullptr && tol > 0.0 && !fail && sc[SC<KP>::RELRES] <= tol) *frozen = 1;
   }
 }
 
 template <int KP>
 __global__ void __launch_bounds__(256) residual_kernel(int variant, double normA2, double* sc,
-                                                       int* status) {
-  residual_body<KP>(variant, normA2, sc, status);
+                                                       int* status, double tol, int* frozen) {
+  residual_body<KP>(variant, normA2, sc, status, tol, frozen);
 }
 
 // objective from the k x k products only: f1 = ||A||_F^2 + 2 tr(H) + ||M||_F^2,
@@ -1506,13 +1514,13 @@ hipError_t launch_finalize(const double* partials, int nb, int nv, double* out, 
 }
 
 hipError_t launch_linesearch(int k, int variant, int first, double alpha0, double* sc,
-                             int* status, hipStream_t s) {
+                             int* status, const int* frozen, hipStream_t s) {
   switch (k) {
-    case 4: hipLaunchKernelGGL(linesearch_kernel<4>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status); break;
-    case 8: hipLaunchKernelGGL(linesearch_kernel<8>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status); break;
-    case 16: hipLaunchKernelGGL(linesearch_kernel<16>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status); break;
-    case 32: hipLaunchKernelGGL(linesearch_kernel<32>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status); break;
-    case 64: hipLaunchKernelGGL(linesearch_kernel<64>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status); break;
+    case 4: hipLaunchKernelGGL(linesearch_kernel<4>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status, frozen); break;
+    case 8: hipLaunchKernelGGL(linesearch_kernel<8>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status, frozen); break;
+    case 16: hipLaunchKernelGGL(linesearch_kernel<16>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status, frozen); break;
+    case 32: hipLaunchKernelGGL(linesearch_kernel<32>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status, frozen); break;
+    case 64: hipLaunchKernelGGL(linesearch_kernel<64>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status, frozen); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1532,21 +1540,23 @@ hipError_t launch_objective(int k, int variant, double normA2, const double* sc,
 }
 
 hipError_t launch_residual(int k, int variant, double normA2, double* sc, int* status,
-                           hipStream_t s) {
+                           double tol, int* frozen, hipStream_t s) {
   switch (k) {
-    case 4: hipLaunchKernelGGL(residual_kernel<4>, dim3(1), dim3(256), 0, s, variant, normA2, sc, status); break;
-    case 8: hipLaunchKernelGGL(residual_kernel<8>, dim3(1), dim3(256), 0, s, variant, normA2, sc, status); break;
-    case 16: hipLaunchKernelGGL(residual_kernel<16>, dim3(1), dim3(256), 0, s, variant, normA2, sc, status); break;
-    case 32: hipLaunchKernelGGL(residual_kernel<32>, dim3(1), dim3(256), 0, s, variant, normA2, sc, status); break;
-    case 64: hipLaunchKernelGGL(residual_kernel<64>, dim3(1), dim3(256), 0, s, variant, normA2, sc, status); break;
+    case 4: hipLaunchKernelGGL(residual_kernel<4>, dim3(1), dim3(256), 0, s, variant, normA2, sc, status, tol, frozen); break;
+    case 8: hipLaunchKernelGGL(residual_kernel<8>, dim3(1), dim3(256), 0, s, variant, normA2, sc, status, tol, frozen); break;
+    case 16: hipLaunchKernelGGL(residual_kernel<16>, dim3(1), dim3(256), 0, s, variant, normA2, sc, status, tol, frozen); break;
+    case 32: hipLaunchKernelGGL(residual_kernel<32>, dim3(1), dim3(256), 0, s, variant, normA2, sc, status, tol, frozen); break;
+    case 64: hipLaunchKernelGGL(residual_kernel<64>, dim3(1), dim3(256), 0, s, variant, normA2, sc, status, tol, frozen); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Batched passes: block -> (graph, rank, blocks of that graph) from a segment
-// table whose blocks of one graph share an XCD (ids congruent modulo 8), so a
+// Batched passes.  Block b is worker b / 8 of XCD b % 8 (workgroups are
+// dispatched to the XCDs round-robin); the workers of an XCD sweep the graphs
+// assigned to it one after another, each graph's tiles split over all the
+// XCD's workers, so an XCD touches one or two graphs' rows at a time and a
 // small graph's rows stay in that XCD's L2.  Converged graphs are skipped.
 // ---------------------------------------------------------------------------
 
@@ -1615,40 +1625,57 @@ __device__ inline PassArgs batch_pass_args(const BatchArgs& b, const BatchGraph&
   return a;
 }
 
+// workers a graph uses: enough for about tpw tiles per wavefront
+__device__ __host__ inline int batch_graph_workers(int64_t ntiles, int wpb, int tpw, int workers) {
+  const int64_t per = (int64_t)wpb * tpw;
+  const int64_t w = (ntiles + per - 1) / per;
+  return (int)(w < 1 ? 1 : (w > workers ? workers : w));
+}
+
 template <int KP, int MODE, bool CHECK, bool BF>
 __global__ void __launch_bounds__((Cfg<float, KP>::WPB * 64)) batch_spmm_kernel(BatchArgs b) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const BatchSeg sg = b.seg[blockIdx.x];
-  if (sg.g < 0) return;
-  const BatchGraph& d = b.graphs[sg.g];
-  if (*d.active == 0) return;
-  const PassArgs a = batch_pass_args(b, d);
-  spmm_body<float, KP, MODE, CHECK, BF>(a, sg.rank, sg.nblk, smem);
+  const int x = blockIdx.x & 7;
+  const int w = blockIdx.x >> 3;
+  for (int i = b.xoff[x]; i < b.xoff[x + 1]; ++i) {
+    const BatchGraph& d = b.graphs[b.xlist[i]];
+    const int nw = batch_graph_workers(d.ntiles, Cfg<float, KP>::WPB, b.tpw, b.workers);
+    if (w >= nw || *d.active == 0) continue;
+    const PassArgs a = batch_pass_args(b, d);
+    spmm_body<float, KP, MODE, CHECK, BF>(a, w, nw, smem);
+    __syncthreads();
+  }
 }
 
 template <int KP, int MODE>
 __global__ void __launch_bounds__((Cfg<float, KP>::WPB * 64)) batch_dense_kernel(BatchArgs b) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const BatchSeg sg = b.seg[blockIdx.x];
-  if (sg.g < 0) return;
-  const BatchGraph& d = b.graphs[sg.g];
-  if (*d.active == 0) return;
-  const PassArgs a = batch_pass_args(b, d);
-  dense_body<float, KP, MODE>(a, sg.rank, sg.nblk, smem);
+  const int x = blockIdx.x & 7;
+  const int w = blockIdx.x >> 3;
+  for (int i = b.xoff[x]; i < b.xoff[x + 1]; ++i) {
+    const BatchGraph& d = b.graphs[b.xlist[i]];
+    const int nw = batch_graph_workers(d.ntiles, Cfg<float, KP>::WPB, b.tpw, b.workers);
+    if (w >= nw || *d.active == 0) continue;
+    const PassArgs a = batch_pass_args(b, d);
+    dense_body<float, KP, MODE>(a, w, nw, smem);
+    __syncthreads();
+  }
 }
 
 // per-graph sum of its block partial rows, in block order
+template <int KP>
 __global__ void __launch_bounds__(64) batch_finalize_kernel(BatchArgs b) {
   const BatchGraph& d = b.graphs[blockIdx.y];
   if (*d.active == 0) return;
   const int v = blockIdx.x * 64 + threadIdx.x;
   if (v >= b.nv) return;
+  const int nw = batch_graph_workers(d.ntiles, Cfg<float, KP>::WPB, b.tpw, b.workers);
   double s = 0.0;
-  for (int b0 = 0; b0 < d.nblk; b0 += kFinChunk) {
+  for (int b0 = 0; b0 < nw; b0 += kFinChunk) {
     double x[kFinChunk];
 #pragma unroll
     for (int q = 0; q < kFinChunk; ++q)
-      x[q] = (b0 + q < d.nblk) ? d.partials[(size_t)(b0 + q) * b.nv + v] : 0.0;
+      x[q] = (b0 + q < nw) ? d.partials[(size_t)(b0 + q) * b.nv + v] : 0.0;
 #pragma unroll
     for (int q = 0; q < kFinChunk; ++q) s += x[q];
   }
@@ -1660,7 +1687,7 @@ __global__ void __launch_bounds__(256) batch_linesearch_kernel(BatchArgs b, doub
                                                                int first_fixed) {
   const BatchGraph& d = b.graphs[blockIdx.x];
   if (*d.active == 0) return;
-  linesearch_body<KP>(b.variant, first_fixed, alpha0, d.sc, d.status);
+  linesearch_body<KP>(b.variant, first_fixed, alpha0, d.sc, d.status, nullptr);
 }
 
 // residual of X^t; a graph whose residual meets the tolerance (or whose
@@ -1669,13 +1696,23 @@ template <int KP>
 __global__ void __launch_bounds__(256) batch_residual_kernel(BatchArgs b) {
   const BatchGraph& d = b.graphs[blockIdx.x];
   if (*d.active == 0) return;
-  residual_body<KP>(b.variant, d.normA2, d.sc, d.status);
+  residual_body<KP>(b.variant, d.normA2, d.sc, d.status, 0.0, nullptr);
   __syncthreads();
   if (threadIdx.x == 0) {
     const double rr = d.sc[SC<KP>::RELRES];
     if ((b.tol > 0.0 && rr <= b.tol) || *d.status != 0) {
       *d.active = 0;
       *d.done_iter = b.t;
+    } else if (b.tol > 0.0) {
+      // stall test: less than 5% decrease over the last kBatchHist checks
+      const int64_t c = b.t / b.check_every;
+      const int slot = (int)(c % kBatchHist);
+      const double old = d.hist[slot];
+      if (c >= kBatchHist && rr > 0.95 * old) {
+        *d.active = 0;
+        *d.stalled = 1;
+      }
+      d.hist[slot] = rr;
     }
   }
 }
@@ -1754,7 +1791,15 @@ hipError_t launch_batch_dense(int k, BatchArgs& b, int grid, hipStream_t s) {
 
 hipError_t launch_batch_finalize(BatchArgs& b, hipStream_t s) {
   if (b.nv == 0) return hipSuccess;
-  hipLaunchKernelGGL(batch_finalize_kernel, dim3((b.nv + 63) / 64, b.ngraphs), dim3(64), 0, s, b);
+  const dim3 grid((b.nv + 63) / 64, b.ngraphs);
+  switch (b.k) {
+    case 4: hipLaunchKernelGGL(batch_finalize_kernel<4>, grid, dim3(64), 0, s, b); break;
+    case 8: hipLaunchKernelGGL(batch_finalize_kernel<8>, grid, dim3(64), 0, s, b); break;
+    case 16: hipLaunchKernelGGL(batch_finalize_kernel<16>, grid, dim3(64), 0, s, b); break;
+    case 32: hipLaunchKernelGGL(batch_finalize_kernel<32>, grid, dim3(64), 0, s, b); break;
+    case 64: hipLaunchKernelGGL(batch_finalize_kernel<64>, grid, dim3(64), 0, s, b); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -31,6 +31,21 @@ hipError_t launch_row_normalize(int64_t n, int k, int precision, const void* X, 
   return hipGetLastError();
 }
 
+__global__ void convert_kernel(int64_t count, int to_fp64, const void* __restrict__ src,
+                               void* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  if (to_fp64) static_cast<double*>(dst)[i] = (double)static_cast<const float*>(src)[i];
+  else static_cast<float*>(dst)[i] = (float)static_cast<const double*>(src)[i];
+}
+
+hipError_t launch_convert(int64_t count, int to_fp64, const void* src, void* dst, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(convert_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, count,
+                     to_fp64, src, dst);
+  return hipGetLastError();
+}
+
 // one point per thread; centroids staged in LDS when they fit
 constexpr int kLdsCentroidFloats = 12288;
 

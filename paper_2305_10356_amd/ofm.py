@@ -95,7 +95,7 @@ _SIGS = {
     "ofm_batch_create": (_I, [_I, _P, _P, ctypes.POINTER(Opts), ctypes.POINTER(_P)]),
     "ofm_batch_destroy": (_I, [_P]),
     "ofm_batch_solve": (_I, [_P, _P, _P, _P]),
-    "ofm_batch_schedule": (_I, [_P, _P, _P]),
+    "ofm_batch_schedule": (_I, [_P, _P, _P, _P]),
     "ofm_row_normalize": (_I, [_I64, _I, _I, _P, _P, _P]),
     "ofm_kmeans_assign": (_I, [_I64, _I, _I, _P, _P, _P, _P, _P]),
     "ofm_kmeans": (_I, [_I64, _I, _I, _P, _P, _I, _P, _P, _P, _P]),
@@ -375,12 +375,15 @@ class Batch:
         return [s.as_dict() for s in stats]
 
     def schedule(self):
-        scale = ctypes.c_int()
+        """(tiles-per-wavefront target chosen, ms per iteration of each
+        candidate, graphs finished in FP64) of the last solve."""
+        tpw = ctypes.c_int()
+        esc = ctypes.c_int()
         ms = np.zeros(3)
-        _check(self._lib.ofm_batch_schedule(self.handle, ctypes.byref(scale),
-                                            ms.ctypes.data_as(ctypes.c_void_p)),
+        _check(self._lib.ofm_batch_schedule(self.handle, ctypes.byref(tpw),
+                                            ms.ctypes.data_as(ctypes.c_void_p), ctypes.byref(esc)),
                "ofm_batch_schedule")
-        return scale.value, ms
+        return tpw.value, ms, esc.value
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -454,3 +454,25 @@ def test_products_match_oracle(ofm, k, dt):
     assert rel(ws.product("E"), X0.T @ AV) < tol * 10
     assert rel(ws.product("F"), V0.T @ AV) < tol * 10
     assert rel(ws.product("H"), X0.T @ O.apply_A(olap, X0)) < tol * 10
+
+
+def test_solve_returns_the_iterate_it_reports(ofm, c1, c1_lap):
+    # the residual reported by ofm_solve is that of the X it returns, also for a
+    # variant whose residual is not monotone
+    g, x0, olap = c1
+    for variant, restart in (("tri-f2", True), ("f2", False)):
+        ws = ofm.Workspace(c1_lap, 8, variant=variant, precision=ofm.OFM_FP64, max_iter=2000,
+                           check_every=10, tol=1e-6, restart=restart)
+        X = dev(x0, torch.float64)
+        st = ws.solve(X)
+        assert st["converged"] == 1
+        assert st["iters"] == st["relres_iter"]
+        # The Gram form of the residual subtracts two traces of size ~k, so at
+        # relres ~ 1e-6 (relres^2 ~ 1e-12) about four of its FP64 digits cancel.
+        r = O.relres(olap, host(X))
+        assert r <= 1e-6 * (1 + 1e-3)
+        assert r == pytest.approx(st["relres"], rel=1e-2)
+        # a further step keeps the frozen iterate
+        Xh = host(X)
+        ws.step(X)
+        assert np.array_equal(host(X), Xh)
