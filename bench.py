@@ -129,6 +129,51 @@ def batched_vs_plain(variant: str, count: int = 256, plain: bool = True):
     }
 
 
+def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10,
+                 cold_stages=(9,)):
+    """Growth stream of 10 snapshots, N = 200k .. 2M, k = 64, mean degree 20,
+    r = 0.3: each stage solved to residual 1e-4 (checked every 10 iterations)
+    in FP32 from the previous stage's solution (new rows N(0, 1/N_s)), with
+    the loop replayed as HIP graphs.  The stages in ``cold_stages`` are also
+    solved from a fresh random block for comparison."""
+    import torch
+    from paper_2305_10356_amd import graphs, ofm
+    from paper_2305_10356_amd.streaming import StreamingSolver
+    t = time.perf_counter()
+    gs = graphs.GrowthStream(n_final=n_final, stages=stages, k=64, dbar=20, r=0.3, seed=4)
+    log(f"growth stream generated in {time.perf_counter() - t:.1f} s")
+    tri = variant.startswith("tri")
+    warm = StreamingSolver(64, variant=variant, precision=ofm.OFM_FP32, tol=1e-4,
+                           check_every=10, max_iter=5000, graph=True, restart=tri, seed=4)
+    stages_out = []
+    for s in range(stages):
+        g = gs.snapshot(s)
+        rec = warm.solve_stage(g.row_ptr, g.col_idx, warm=True)
+        if s in cold_stages:
+            cold = StreamingSolver(64, variant=variant, precision=ofm.OFM_FP32, tol=1e-4,
+                                   check_every=10, max_iter=5000, graph=True, restart=tri,
+                                   seed=4)
+            cold.stage = s
+            rc = cold.solve_stage(g.row_ptr, g.col_idx, warm=False)
+            rec["cold_iters"] = rc["iters"]
+            rec["cold_solve_s"] = round(rc["solve_s"], 4)
+            rec["cold_converged"] = rc["converged"]
+            del cold
+        for key in ("solve_s", "laplacian_s", "xinit_s"):
+            rec[key] = round(rec[key], 4)
+        log(f"stream stage {s}: {rec}")
+        stages_out.append(rec)
+    torch.cuda.synchronize()
+    return {
+        "workload": f"growth stream {stages} snapshots N={gs.bounds[0]}..{n_final} k=64 "
+                    f"mean-degree 20 r=0.3, FP32, graph-replayed loop, tol 1e-4",
+        "variant": variant,
+        "total_solve_s": round(sum(r["solve_s"] for r in stages_out), 4),
+        "all_converged": all(r["converged"] == 1 for r in stages_out),
+        "stages": stages_out,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +186,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched solve (no plain loop, no C3 run); prints its JSON")
+    ap.add_argument("--no-streaming", action="store_true")
+    ap.add_argument("--streaming-only", action="store_true",
+                    help="run only the streaming warm-start workload; prints its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -156,6 +204,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.batched_only:
         print(json.dumps(batched_vs_plain(args.variant, plain=False)), flush=True)
+        return
+    if args.streaming_only:
+        print(json.dumps(streaming_c4(args.variant)), flush=True)
         return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -309,6 +360,8 @@ def main():
                                    "converged": st3["converged"]}
         if not args.no_batched:
             extras["batched_vs_plain"] = batched_vs_plain(args.variant)
+        if not args.no_streaming:
+            extras["streaming_warm_start"] = streaming_c4(args.variant)
         # post-processing (Algorithm 1 steps 4-5), once per solve
         torch.cuda.synchronize()
         t1 = time.perf_counter()

@@ -94,6 +94,9 @@ typedef struct ofm_opts {
                        (a safeguard outside Algorithm 2; 0 = as printed)      */
   double alpha0;    /* step for first_step = 1                                */
   double tol;       /* ofm_solve stops when the residual <= tol (0: never)    */
+  int graph;        /* ofm_solve: 1 = run the loop as replays of a HIP graph
+                       holding check_every updates (captured on first use on
+                       a stream of the workspace; see ofm_solve); 0 = eager   */
 } ofm_opts;
 
 typedef struct ofm_stats {
@@ -191,6 +194,13 @@ ofm_status ofm_step(ofm_workspace ws, void* X, hipStream_t stream);
  * a residual evaluation that meets tol freezes X on the device (every later
  * step size is 0 until the next ofm_init / ofm_set_state), so the returned X
  * is the iterate whose residual was reported.
+ * With opts.graph = 1 the updates between two residual evaluations (the
+ * check_every ofm_step calls that end with one) are captured once into a HIP
+ * graph and replayed; the kernels and their arguments are those of the eager
+ * loop, so the result is bitwise the same.  The graph is captured for the X
+ * pointer of the call (and the buffer parity of the step state) and kept by
+ * the workspace; a call with another X captures again.  Per-pass timing
+ * (ofm_set_timing) does not see replayed passes.
  */
 ofm_status ofm_solve(ofm_workspace ws, void* X, hipStream_t stream, ofm_stats* host_out);
 

@@ -121,6 +121,10 @@ struct ofm_workspace_s {
   int* tickets = nullptr;
   int* status = nullptr;
   int* frozen = nullptr;   // set on the device when the residual met tol
+  // captured solve chunks (opts.graph): one per buffer parity at chunk start
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t chunk[2] = {nullptr, nullptr};
+  const void* chunk_x = nullptr;
   int64_t t = 0;
   int64_t last_check = -1;
   bool initialized = false;
@@ -411,6 +415,10 @@ static void free_ws(ofm_workspace ws) {
   }
   for (auto e : ws->pool) (void)hipEventDestroy(e);
   for (int i = 0; i < 2; ++i) {
+    if (ws->chunk[i]) (void)hipGraphExecDestroy(ws->chunk[i]);
+  }
+  if (ws->cap_stream) (void)hipStreamDestroy(ws->cap_stream);
+  for (int i = 0; i < 2; ++i) {
     dev_free(ws->V[i]);
     dev_free(ws->G[i]);
   }
@@ -439,6 +447,7 @@ extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_o
   if (o.first_step != 0 && o.first_step != 1) return OFM_E_INVALID_ARG;
   if (o.restart != 0 && o.restart != 1) return OFM_E_INVALID_ARG;
   if (!std::isfinite(o.alpha0) || !(o.tol >= 0.0)) return OFM_E_INVALID_ARG;
+  if (o.graph != 0 && o.graph != 1) return OFM_E_INVALID_ARG;
   const int prec = o.precision == OFM_FP64 ? OFM_FP64 : OFM_FP32;
   if (!supported_k(k, prec)) return prec == OFM_FP64 && k == 64 ? OFM_E_UNSUPPORTED : OFM_E_SHAPE;
   if (k > lap->g.n) return OFM_E_SHAPE;
@@ -684,14 +693,70 @@ extern "C" ofm_status ofm_get_stats(ofm_workspace ws, hipStream_t stream, ofm_st
   return (ofm_status)host_out->status;
 }
 
+// The check_every updates that start at ws->t (a step index one past a
+// multiple of check_every) captured into a HIP graph.  Host-side step state is
+// rewound after the capture; the replay advances it.
+static ofm_status capture_chunk(ofm_workspace ws, void* X, hipGraphExec_t* out) {
+  const int ce = ws->opts.check_every;
+  if (!ws->cap_stream)
+    HIPCHK(hipStreamCreateWithFlags(&ws->cap_stream, hipStreamNonBlocking));
+  const int64_t t0 = ws->t;
+  const int cur0 = ws->cur;
+  const int64_t lc0 = ws->last_check;
+  const bool timing = ws->timing;
+  ws->timing = false;
+  hipGraph_t g = nullptr;
+  ofm_status st = OFM_OK;
+  if (hipStreamBeginCapture(ws->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    st = OFM_E_HIP;
+  } else {
+    for (int i = 0; i < ce && st == OFM_OK; ++i) st = ofm_step(ws, X, ws->cap_stream);
+    if (hipStreamEndCapture(ws->cap_stream, &g) != hipSuccess && st == OFM_OK) st = OFM_E_HIP;
+  }
+  ws->t = t0;
+  ws->cur = cur0;
+  ws->last_check = lc0;
+  ws->timing = timing;
+  if (st == OFM_OK && hipGraphInstantiate(out, g, nullptr, nullptr, 0) != hipSuccess)
+    st = OFM_E_HIP;
+  if (g) (void)hipGraphDestroy(g);
+  return st;
+}
+
+static ofm_status run_chunk(ofm_workspace ws, void* X, hipStream_t stream) {
+  const int ce = ws->opts.check_every;
+  if (ws->chunk_x != X) {
+    for (int i = 0; i < 2; ++i) {
+      if (ws->chunk[i]) HIPCHK(hipGraphExecDestroy(ws->chunk[i]));
+      ws->chunk[i] = nullptr;
+    }
+    ws->chunk_x = X;
+  }
+  hipGraphExec_t& e = ws->chunk[ws->cur];
+  if (!e) OFMCHK(capture_chunk(ws, X, &e));
+  HIPCHK(hipGraphLaunch(e, stream));
+  // the chunk's one residual evaluation is at its step index divisible by ce
+  ws->last_check = ((ws->t + ce - 1) / ce) * ce;
+  ws->t += ce;
+  ws->cur ^= (ce & 1);
+  return OFM_OK;
+}
+
 extern "C" ofm_status ofm_solve(ofm_workspace ws, void* X, hipStream_t stream,
                                 ofm_stats* host_out) {
   if (!ws || !X) return OFM_E_INVALID_ARG;
   OFMCHK(ofm_init(ws, X, stream));
   ofm_stats st{};
+  const int ce = ws->opts.check_every;
   while (ws->t < ws->opts.max_iter) {
-    const bool will_check = (ws->t % ws->opts.check_every) == 0;
-    OFMCHK(ofm_step(ws, X, stream));
+    bool will_check;
+    if (ws->opts.graph && ws->t % ce == 1 % ce && ws->t + ce <= ws->opts.max_iter) {
+      OFMCHK(run_chunk(ws, X, stream));
+      will_check = true;
+    } else {
+      will_check = (ws->t % ce) == 0;
+      OFMCHK(ofm_step(ws, X, stream));
+    }
     if (will_check) {
       OFMCHK(read_stats(ws, stream, &st));
       if (st.status != OFM_OK) break;

@@ -45,6 +45,8 @@ __all__ = [
     "bfs_ball_subgraph",
     "batched_graph_specs",
     "streaming_snapshots",
+    "GrowthStream",
+    "warm_start",
 ]
 
 
@@ -481,64 +483,150 @@ def bfs_ball_subgraph(g: Graph, size: int, rng: np.random.Generator) -> Graph:
                  meta={"kind": "bfs-ball", "parent": g.meta.get("workload")})
 
 
+class GrowthStream:
+    """Node-arrival growth process for streaming snapshots.
+
+    Nodes arrive one at a time with a uniform block label.  The first m+1
+    arrivals (m = dbar/2) form a clique; every later arrival adds m edges to
+    distinct earlier nodes.  Each edge is intra-block with probability
+    1/(1+r); its target is uniform among the earlier nodes of the arrival's
+    own block (intra) or of the other blocks (inter), or among all earlier
+    nodes while that class holds fewer than m nodes.  The mean degree is
+    therefore about dbar at every size, older nodes keep gaining edges, and
+    every node has degree >= m.
+
+    Node ids are arrival order, so the snapshot with n_s nodes is the
+    subgraph induced by ids [0, n_s) and each snapshot extends the previous
+    one: a warm start keeps the old rows of X in place and appends rows for
+    the new nodes.  The arrival order is random with respect to the blocks,
+    so storage order does not reveal them.
+
+    The full graph is stored once as a symmetric CSR with sorted columns;
+    since an edge (i, j) is present in a snapshot exactly when max(i, j) <
+    n_s, each row of a snapshot is a prefix of the same row of the full
+    graph, and ``snapshot`` cuts it out with a mask.
+    """
+
+    def __init__(self, n_final: int = 2_000_000, stages: int = 10, k: int = 64,
+                 dbar: float = 20.0, r: float = 0.3, seed: int = 4):
+        self.n_final = int(n_final)
+        self.stages = int(stages)
+        self.k = int(k)
+        self.dbar = float(dbar)
+        self.r = float(r)
+        m = int(round(dbar / 2))
+        self.m = m
+        if self.n_final <= m + 1:
+            raise ValueError("n_final must exceed dbar/2 + 1")
+        rng = np.random.default_rng([seed, 1])
+        n = self.n_final
+        labels = rng.integers(0, k, size=n).astype(np.int64)
+        self.labels = labels.astype(np.int32)
+        # rank[a] = number of earlier arrivals in the block of a;
+        # members[off[b] + j] = the j-th arrival of block b
+        members = np.argsort(labels, kind="stable")
+        counts = np.bincount(labels, minlength=k)
+        off = np.concatenate([[0], np.cumsum(counts)])
+        rank = np.empty(n, dtype=np.int64)
+        rank[members] = np.arange(n, dtype=np.int64) - off[labels[members]]
+
+        c = m + 1
+        cu, cv = np.tril_indices(c, -1)  # clique among the first m+1 arrivals
+        a = np.arange(c, n, dtype=np.int64)  # later arrivals, each with m slots
+        na = a.shape[0]
+        lab = labels[a]
+        own = rank[a]
+        intra = rng.random((na, m)) < 1.0 / (1.0 + self.r)
+        # classes too small to hold m distinct targets fall back to everyone
+        fallback = np.where(intra, (own < m)[:, None], ((a - own) < m)[:, None])
+        tgt = np.empty((na, m), dtype=np.int64)
+        todo = np.ones((na, m), dtype=bool)
+        while True:
+            self._draw(rng, tgt, todo, a, lab, own, intra, fallback, labels, members, off)
+            srt = np.sort(tgt, axis=1)
+            dup_rows = np.flatnonzero((srt[:, 1:] == srt[:, :-1]).any(axis=1))
+            if dup_rows.shape[0] == 0:
+                break
+            todo[:] = False
+            sub = tgt[dup_rows]
+            # keep the first occurrence of every target in a row, redraw the rest
+            order = np.argsort(sub, axis=1, kind="stable")
+            ss = np.take_along_axis(sub, order, axis=1)
+            rep = np.zeros_like(ss, dtype=bool)
+            rep[:, 1:] = ss[:, 1:] == ss[:, :-1]
+            redo = np.zeros_like(rep)
+            np.put_along_axis(redo, order, rep, axis=1)
+            todo[dup_rows] = redo
+        u = np.concatenate([cu.astype(np.int64), np.repeat(a, m)])
+        v = np.concatenate([cv.astype(np.int64), tgt.reshape(-1)])
+        key = np.concatenate([u * n + v, v * n + u])
+        key.sort()
+        rows = key // n
+        self.col_idx = (key % n).astype(np.int32)
+        self._rows = rows.astype(np.int32)
+        rp = np.zeros(n + 1, dtype=np.int64)
+        np.cumsum(np.bincount(rows, minlength=n), out=rp[1:])
+        self.row_ptr = rp
+        step = n // self.stages
+        self.bounds = [step * (s + 1) for s in range(self.stages)]
+        self.bounds[-1] = n
+
+    @staticmethod
+    def _draw(rng, tgt, todo, a, lab, own, intra, fallback, labels, members, off):
+        rows, cols = np.nonzero(todo)
+        if rows.shape[0] == 0:
+            return
+        aa = a[rows]
+        fb = fallback[rows, cols]
+        it = intra[rows, cols] & ~fb
+        inter = ~intra[rows, cols] & ~fb
+        out = np.empty(rows.shape[0], dtype=np.int64)
+        # any earlier node
+        idx = np.flatnonzero(fb)
+        out[idx] = (rng.random(idx.shape[0]) * aa[idx]).astype(np.int64)
+        # an earlier node of the own block
+        idx = np.flatnonzero(it)
+        j = (rng.random(idx.shape[0]) * own[rows[idx]]).astype(np.int64)
+        out[idx] = members[off[lab[rows[idx]]] + j]
+        # an earlier node of another block, by rejection
+        idx = np.flatnonzero(inter)
+        while idx.shape[0]:
+            cand = (rng.random(idx.shape[0]) * aa[idx]).astype(np.int64)
+            ok = labels[cand] != lab[rows[idx]]
+            out[idx[ok]] = cand[ok]
+            idx = idx[~ok]
+        tgt[rows, cols] = out
+
+    def snapshot(self, s: int) -> Graph:
+        """Snapshot s (0-based): the subgraph on the first bounds[s] arrivals."""
+        ns = self.bounds[s]
+        end = int(self.row_ptr[ns])
+        cols = self.col_idx[:end]
+        keep = cols < ns
+        cnt = np.bincount(self._rows[:end][keep], minlength=ns)
+        rp = np.zeros(ns + 1, dtype=np.int64)
+        np.cumsum(cnt, out=rp[1:])
+        return Graph(n=ns, row_ptr=rp.astype(np.int32), col_idx=cols[keep].copy(),
+                     labels=self.labels[:ns].copy(),
+                     meta={"kind": "growth", "stage": s, "dbar": self.dbar, "r": self.r,
+                           "m": self.m})
+
+
 def streaming_snapshots(n_final: int = 2_000_000, stages: int = 10, k: int = 64,
                         dbar: float = 20.0, r: float = 0.3, seed: int = 4):
-    """Node-arrival growth process.  Nodes arrive in random order with a uniform
-    block label; each arrival adds m = dbar/2 edges, each intra-block with
-    probability 1/(1+r), to uniformly chosen distinct earlier nodes of the
-    chosen block class (any earlier node while a class is too small).  The
-    first m+1 arrivals form a clique.  Yields (graph, n_s) after each of
-    ``stages`` equal growth steps; node ids are arrival order (snapshot s is a
-    prefix of snapshot s+1), so warm starts keep old rows in place."""
-    rng = np.random.default_rng([seed, 1])
-    m = int(round(dbar / 2))
-    labels = rng.integers(0, k, size=n_final).astype(np.int32)
-    src = []
-    dst = []
-    # bootstrap clique
-    for a in range(m + 1):
-        for b in range(a):
-            src.append(a)
-            dst.append(b)
-    src = [np.asarray(src, dtype=np.int64)]
-    dst = [np.asarray(dst, dtype=np.int64)]
-    # per-block member lists (arrival order)
-    members: List[List[int]] = [[] for _ in range(k)]
-    for a in range(m + 1):
-        members[int(labels[a])].append(a)
-    step = n_final // stages
-    bounds = [step * (s + 1) for s in range(stages)]
-    bounds[-1] = n_final
-    nxt = m + 1
-    for bound in bounds:
-        for a in range(nxt, bound):
-            lab = int(labels[a])
-            intra = rng.random(m) < 1.0 / (1.0 + r)
-            chosen = set()
-            tries = 0
-            for want_intra in intra:
-                while True:
-                    tries += 1
-                    if want_intra and len(members[lab]) >= m:
-                        pool = members[lab]
-                        t = pool[int(rng.integers(0, len(pool)))]
-                    else:
-                        cls = int(rng.integers(0, k))
-                        pool = members[cls] if (not want_intra and cls != lab and len(members[cls]) >= m) else None
-                        if pool is None:
-                            t = int(rng.integers(0, a))
-                        else:
-                            t = pool[int(rng.integers(0, len(pool)))]
-                    if t not in chosen:
-                        chosen.add(t)
-                        break
-            tt = np.fromiter(chosen, dtype=np.int64, count=len(chosen))
-            src.append(np.full(tt.shape[0], a, dtype=np.int64))
-            dst.append(tt)
-            members[lab].append(a)
-        nxt = bound
-        u = np.concatenate(src)
-        v = np.concatenate(dst)
-        row_ptr, cols = _edges_to_csr(bound, u, v)
-        yield Graph(n=bound, row_ptr=row_ptr.astype(np.int32), col_idx=cols.astype(np.int32),
-                    labels=labels[:bound].copy(), meta={"kind": "growth", "dbar": dbar, "r": r}), bound
+    """Yields (graph, n_s) for the stages of a ``GrowthStream``."""
+    gs = GrowthStream(n_final, stages, k, dbar, r, seed)
+    for s in range(gs.stages):
+        yield gs.snapshot(s), gs.bounds[s]
+
+
+def warm_start(x_prev: Optional[np.ndarray], n: int, k: int, rng: np.random.Generator,
+               dtype=np.float64) -> np.ndarray:
+    """Initial block for a grown graph: the previous solution's rows in place,
+    new rows drawn N(0, 1/n)."""
+    x = np.empty((n, k), dtype=dtype)
+    old = 0 if x_prev is None else x_prev.shape[0]
+    if old:
+        x[:old] = x_prev
+    x[old:] = rng.standard_normal((n - old, k)) / math.sqrt(n)
+    return x

@@ -1,0 +1,140 @@
+"""Streaming warm starts (numerical results, comparison on streaming graphs) and
+the graph-captured solve loop.
+
+* ofm_solve with the loop replayed as HIP graphs gives bitwise the iterate,
+  the residual and the iteration count of the eager loop;
+* every stage of a small growth stream, warm-started from the previous
+  stage, reaches the tolerance, and its limit matches the dense
+  eigendecomposition of that stage's Laplacian (Theorem 1 for f1, Theorem 3
+  for f2), checked with the FP64 oracle;
+* warm starts need fewer iterations than cold starts from N(0, 1/N)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ofm_oracle as O
+from paper_2305_10356_amd import graphs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("prec,ce,variant", [("fp64", 10, "f1"), ("fp64", 7, "tri-f2"),
+                                             ("fp64", 1, "f2"), ("fp32", 10, "f1"),
+                                             ("fp32", 5, "tri-f1")])
+def test_graph_replay_is_bitwise_eager(lib, prec, ce, variant):
+    from paper_2305_10356_amd import ofm
+    cfg = 1 if prec == "fp64" else 2
+    g, x0 = graphs.config_graph(cfg)
+    k = x0.shape[1]
+    lap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    p = ofm.OFM_FP64 if prec == "fp64" else ofm.OFM_FP32
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    tol = 1e-7 if prec == "fp64" else 1e-4
+    restart = variant.startswith("tri")
+    out = []
+    for graph in (False, True):
+        say(f"graph={graph} {prec} ce={ce} {variant}")
+        ws = ofm.Workspace(lap, k, variant=variant, precision=p, max_iter=400, check_every=ce,
+                           tol=tol, restart=restart, graph=graph)
+        X = torch.as_tensor(x0, dtype=dt).cuda()
+        st = ws.solve(X)
+        out.append((host(X), st))
+        if graph:
+            # a second solve replays the kept graphs from a fresh init
+            X2 = torch.as_tensor(x0, dtype=dt).cuda()
+            st2 = ws.solve(X2)
+            assert st2 == st
+            np.testing.assert_array_equal(host(X2), out[0][0])
+        ws.close()
+    (xe, se), (xg, sg) = out
+    assert se == sg
+    np.testing.assert_array_equal(xe, xg)
+
+
+def test_graph_replay_hits_max_iter_exactly(lib):
+    from paper_2305_10356_amd import ofm
+    g, x0 = graphs.config_graph(1)
+    lap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    res = []
+    for graph in (False, True):
+        ws = ofm.Workspace(lap, 8, variant="f1", precision=ofm.OFM_FP64, max_iter=37,
+                           check_every=10, tol=1e-30, graph=graph)
+        X = torch.as_tensor(x0).cuda()
+        st = ws.solve(X)
+        assert st["iters"] == 37 and st["relres_iter"] == 30
+        res.append(host(X))
+    np.testing.assert_array_equal(res[0], res[1])
+
+
+def _stream_case(variant, vid, prec, k, n_final, stages, tol):
+    from paper_2305_10356_amd import ofm
+    from paper_2305_10356_amd.streaming import StreamingSolver
+    gs = graphs.GrowthStream(n_final=n_final, stages=stages, k=k, dbar=20, r=0.3, seed=7)
+    warm = StreamingSolver(k, variant=variant, precision=prec, tol=tol, check_every=5,
+                           max_iter=4000, graph=True, seed=7)
+    cold = StreamingSolver(k, variant=variant, precision=prec, tol=tol, check_every=5,
+                           max_iter=4000, graph=True, seed=7)
+    recs = []
+    for s in range(stages):
+        g = gs.snapshot(s)
+        say(f"stream {variant} stage {s} n={g.n}")
+        rw = warm.solve_stage(g.row_ptr, g.col_idx, warm=True)
+        rc = cold.solve_stage(g.row_ptr, g.col_idx, warm=False)
+        assert rw["converged"] == 1 and rc["converged"] == 1, (rw, rc)
+        recs.append((g, rw, rc, host(warm.X)))
+    return recs
+
+
+@pytest.mark.parametrize("variant,vid", [("f1", O.F1), ("f2", O.F2)])
+def test_streaming_fp64_limits_match_dense_eigh(lib, variant, vid):
+    from paper_2305_10356_amd import ofm
+    k = 4
+    tol = 1e-6
+    recs = _stream_case(variant, vid, ofm.OFM_FP64, k, 2400, 3, tol)
+    for s, (g, rw, rc, X) in enumerate(recs):
+        olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
+        r = O.relres(olap, X)
+        assert r <= 1.05 * tol  # the Gram form loses ~4 digits at 1e-6
+        mu, U = O.dense_eigh(olap)
+        lam = mu - 2.0
+        gap = mu[k] - mu[k - 1]
+        assert gap > 1e-2  # the limit is well defined
+        # Davis-Kahan: sin(angle(span X, U_k)) <= ||A Q - Q T||_F / gap, where
+        # the Ritz residual is relres * ||T||_F for the Ritz values T
+        Q, _ = np.linalg.qr(X)
+        T = np.linalg.eigvalsh(Q.T @ O.apply_A(olap, Q))
+        sin_f = np.linalg.norm(Q - U[:, :k] @ (U[:, :k].T @ Q))
+        assert sin_f <= 1.5 * r * np.linalg.norm(T) / gap + 1e-12
+        # Ritz values: second order in the residual
+        np.testing.assert_allclose(T, lam[:k], atol=10 * (r * np.linalg.norm(T)) ** 2 / gap + 1e-13)
+        ev = np.sort(np.linalg.eigvalsh(X.T @ X))
+        # Theorem 1: X^T X -> -Lam_k (f1); Theorem 3: X^T X -> I (f2)
+        target = np.sort(-lam[:k]) if vid == O.F1 else np.ones(k)
+        np.testing.assert_allclose(ev, target, atol=20 * r)
+        if s > 0:
+            assert rw["iters"] < rc["iters"], (rw, rc)
+
+
+def test_streaming_fp32_k64(lib):
+    from paper_2305_10356_amd import ofm
+    recs = _stream_case("f1", O.F1, ofm.OFM_FP32, 64, 90000, 3, 1e-4)
+    warm_iters = [rw["iters"] for _, rw, _, _ in recs[1:]]
+    cold_iters = [rc["iters"] for _, _, rc, _ in recs[1:]]
+    say("warm", warm_iters, "cold", cold_iters)
+    assert sum(warm_iters) < sum(cold_iters)
+    g, rw, _, X = recs[-1]
+    olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
+    # the FP64 residual of the FP32 iterate agrees with the library's
+    assert O.relres(olap, X) == pytest.approx(rw["relres"], rel=0.05, abs=2e-6)

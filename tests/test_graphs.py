@@ -73,3 +73,47 @@ def test_batched_specs():
     g, x = graphs.batched_graph(specs[0])
     check_simple_symmetric_connected(g)
     assert x.shape == (specs[0]["n"], specs[0]["k"])
+
+
+def test_growth_stream_structure():
+    gs = graphs.GrowthStream(n_final=20000, stages=4, k=16, dbar=20, r=0.3, seed=11)
+    m = gs.m
+    prev = None
+    for s in range(gs.stages):
+        g = gs.snapshot(s)
+        assert g.n == gs.bounds[s]
+        check_simple_symmetric_connected(g)
+        rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+        earlier = np.bincount(rows[g.col_idx < rows], minlength=g.n)
+        # the clique, then exactly m distinct earlier neighbours per arrival
+        np.testing.assert_array_equal(earlier[: m + 1], np.arange(m + 1))
+        assert np.all(earlier[m + 1:] == m)
+        assert g.degrees().min() >= m
+        if prev is not None:
+            # the previous snapshot is the subgraph induced by its node ids
+            keep = (rows < prev.n) & (g.col_idx < prev.n)
+            np.testing.assert_array_equal(g.col_idx[keep], prev.col_idx)
+            np.testing.assert_array_equal(np.bincount(rows[keep], minlength=prev.n),
+                                          prev.degrees())
+        prev = g
+    st = prev.stats()
+    assert abs(st["mean_degree"] - 20) < 0.1
+    assert abs(st["realized_r"] - 0.3) < 0.04
+    # same seed, same stream
+    again = graphs.GrowthStream(n_final=20000, stages=4, k=16, dbar=20, r=0.3, seed=11)
+    np.testing.assert_array_equal(again.col_idx, gs.col_idx)
+
+
+def test_growth_stream_arrival_order_hides_blocks():
+    gs = graphs.GrowthStream(n_final=30000, stages=2, k=32, seed=3)
+    counts = np.bincount(gs.labels, minlength=32)
+    assert counts.min() > 0.8 * 30000 / 32
+    assert np.mean(gs.labels[1:] == gs.labels[:-1]) < 0.1
+
+
+def test_warm_start_rows():
+    rng = np.random.default_rng(1)
+    old = rng.standard_normal((100, 4))
+    x = graphs.warm_start(old, 5000, 4, np.random.default_rng(2))
+    np.testing.assert_array_equal(x[:100], old)
+    assert abs(x[100:].var() * 5000 - 1.0) < 0.05
