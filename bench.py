@@ -30,22 +30,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def pass_bytes(name: str, n: int, nnz: int, k: int, esz: int, variant: str, ntiles: int) -> float:
-    """Algorithmic HBM bytes of one launch of a pass (each array moved once)."""
+def pass_bytes(name: str, n: int, nnz: int, k: int, esz: int, variant: str, ntiles: int,
+               recur: bool = False) -> float:
+    """Algorithmic HBM bytes of one launch of a pass (each array moved once).
+    With the recurrence of A X the f1 variants store A X in the SpMM of X and
+    form G in a pass of their own, the SpMM of V stores A V, and the update
+    also reads and writes A X and reads A V."""
     B = n * k * esz
     ent = nnz * (8 if esz == 4 else 16)          # packed (column, weight) stream
     graph = ent + 8 * n + 4 * (ntiles + 1)       # + position offsets and row ids
     f2 = variant in ("f2", "tri-f2")
     if name == "spmm_x":
-        return graph + (2 * B if f2 else 3 * B)  # X; f1: G_prev read + G write; f2: AX write
+        # X; f1: G_prev read + G write; f2 (and the recurrence): A X write
+        return graph + (2 * B if (f2 or recur) else 3 * B)
     if name == "spmm_v":
-        return graph + (2 * B if f2 else B)      # V; f2 also reads X
+        # V; f2 also reads X; the recurrence writes A V
+        return graph + (2 * B if f2 else B) + (B if recur else 0)
     if name == "g":
         return 4 * B                             # X, AX, G_prev read; G write
     if name == "v":
         return 4 * B                             # G, V_prev, X read; V write
     if name == "update":
-        return 3 * B                             # X, V read; X write
+        return 6 * B if recur else 3 * B         # X, V (, AX, AV) read; X (, AX) write
     return 0.0
 
 
@@ -187,6 +193,8 @@ def main():
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched solve (no plain loop, no C3 run); prints its JSON")
     ap.add_argument("--no-streaming", action="store_true")
+    ap.add_argument("--recur", action="store_true",
+                    help="headline loop with A X by recurrence between residual checks")
     ap.add_argument("--streaming-only", action="store_true",
                     help="run only the streaming warm-start workload; prints its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -243,7 +251,7 @@ def main():
         del src, dst
 
     # ---------------- headline: iterations/s of the chosen variant ----------
-    ws, X = make(args.variant)
+    ws, X = make(args.variant, recur=args.recur)
     ws.init(X)
     for _ in range(args.warmup):
         ws.step(X)
@@ -267,7 +275,7 @@ def main():
         if cnt == 0:
             continue
         avg_ms = ms / cnt
-        b = pass_bytes(name, n, nnz, k, 4, args.variant, ntiles)
+        b = pass_bytes(name, n, nnz, k, 4, args.variant, ntiles, args.recur)
         passes[name] = {"launches": cnt, "avg_us": round(1e3 * avg_ms, 2),
                         "ms_per_step": round(ms / args.steps, 4)}
         if b > 0:
@@ -279,7 +287,7 @@ def main():
     from paper_2305_10356_amd import profiling
     traffic = profiling.read_traffic(os.path.join(
         ROOT, "profiles", f"pmc_traffic_ofm_step_{args.variant}_dcsbm_n2m_k32_fp32.md"))
-    if args.n is not None:
+    if args.n is not None or args.recur:
         traffic = {}
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -324,6 +332,34 @@ def main():
             extras[key] = round(50 / (time.perf_counter() - t1), 1)
             w2.close()
             del X2
+        # A X by recurrence between residual checks: one product with A per update
+        w6, X6 = make(args.variant, recur=True)
+        w6.init(X6)
+        for _ in range(9):
+            w6.step(X6)
+        torch.cuda.synchronize()
+        w6.set_timing(True)
+        t1 = time.perf_counter()
+        for _ in range(100):
+            w6.step(X6)
+        torch.cuda.synchronize()
+        rec_rate = 100 / (time.perf_counter() - t1)
+        w6.set_timing(False)
+        tm6 = w6.timing(reset=True)
+        w6.close()
+        w7, X7 = make(args.variant, recur=True, tol=1e-4, max_iter=3000)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st7 = w7.solve(X7)
+        torch.cuda.synchronize()
+        extras["recur_ax"] = {
+            "iters_per_s": round(rec_rate, 1),
+            "pass_us": {p: round(1e3 * v[0] / v[1], 1) for p, v in tm6.items() if v[1]},
+            "solve_to_1e-4": {"seconds": round(time.perf_counter() - t1, 3),
+                              "iters": st7["iters"], "relres": st7["relres"],
+                              "converged": st7["converged"]}}
+        w7.close()
+        del X6, X7
         # BF16 storage of the gathered rows: iterations/s and the residual it reaches
         w4, X4 = make(args.variant, ofm.OFM_FP32_BF16X, max_iter=300)
         w4.init(X4)
@@ -400,7 +436,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"dcsbm N={n} k={k} mean-degree 25 power-law 2.5 r=0.5 (nnz={nnz})",
                    "variant": args.variant, "precision": "fp32 passes, fp64 k x k products",
-                   "check_every": 10, "graph": gstats},
+                   "check_every": 10, "recur_ax": bool(args.recur), "graph": gstats},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "passes": passes,

@@ -97,6 +97,15 @@ typedef struct ofm_opts {
   int graph;        /* ofm_solve: 1 = run the loop as replays of a HIP graph
                        holding check_every updates (captured on first use on
                        a stream of the workspace; see ofm_solve); 0 = eager   */
+  int recur;        /* 0: two products with A per update, A X^t and A V^t, as
+                       Algorithm 2 is costed (Table 1).  1: A X^{t+1} =
+                       A X^t + A V^t diag(alpha^t) by recurrence, with A X
+                       recomputed exactly at every residual evaluation (every
+                       check_every updates), after ofm_init / ofm_set_state
+                       and after ofm_residual / ofm_objective; one product
+                       with A per update in between.  Same iteration in exact
+                       arithmetic; rounding differs.  Needs one more N x k
+                       buffer (A V).                                          */
 } ofm_opts;
 
 typedef struct ofm_stats {

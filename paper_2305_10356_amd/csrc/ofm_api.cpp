@@ -111,6 +111,8 @@ struct ofm_workspace_s {
   void* V[2] = {nullptr, nullptr};
   void* G[2] = {nullptr, nullptr};
   void* AX = nullptr;
+  void* AV = nullptr;   // A V^t kept for the recurrence of A X (opts.recur)
+  bool ax_valid = false;  // AX holds A X^t of the current iterate (opts.recur)
   void* Xb = nullptr;   // BF16 copies gathered by the SpMMs (OFM_FP32_BF16X)
   void* Vb = nullptr;
   int prec = 0;         // arithmetic of the kernels: OFM_FP64 or OFM_FP32
@@ -175,11 +177,13 @@ int pass_kind(int mode) {
   switch (mode) {
     case kGF1:
     case kAXF2: return OFM_PASS_SPMM_X;
-    case kGPassF2: return OFM_PASS_G;
+    case kGPassF2:
+    case kGPassF1: return OFM_PASS_G;
     case kVPass: return OFM_PASS_V;
     case kAVF1:
     case kAVF2: return OFM_PASS_SPMM_V;
-    case kUpdate: return OFM_PASS_UPDATE;
+    case kUpdate:
+    case kUpdateR: return OFM_PASS_UPDATE;
     default: return OFM_PASS_OTHER;
   }
 }
@@ -423,6 +427,7 @@ static void free_ws(ofm_workspace ws) {
     dev_free(ws->G[i]);
   }
   dev_free(ws->AX);
+  dev_free(ws->AV);
   dev_free(ws->Xb);
   dev_free(ws->Vb);
   dev_free(ws->sc);
@@ -448,6 +453,7 @@ extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_o
   if (o.restart != 0 && o.restart != 1) return OFM_E_INVALID_ARG;
   if (!std::isfinite(o.alpha0) || !(o.tol >= 0.0)) return OFM_E_INVALID_ARG;
   if (o.graph != 0 && o.graph != 1) return OFM_E_INVALID_ARG;
+  if (o.recur != 0 && o.recur != 1) return OFM_E_INVALID_ARG;
   const int prec = o.precision == OFM_FP64 ? OFM_FP64 : OFM_FP32;
   if (!supported_k(k, prec)) return prec == OFM_FP64 && k == 64 ? OFM_E_UNSUPPORTED : OFM_E_SHAPE;
   if (k > lap->g.n) return OFM_E_SHAPE;
@@ -475,6 +481,8 @@ extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_o
     if ((st = dev_alloc(reinterpret_cast<char**>(&ws->G[i]), blk)) != OFM_OK) return fail(st);
   }
   if ((st = dev_alloc(reinterpret_cast<char**>(&ws->AX), blk)) != OFM_OK) return fail(st);
+  if (o.recur && (st = dev_alloc(reinterpret_cast<char**>(&ws->AV), blk)) != OFM_OK)
+    return fail(st);
   if (o.precision == OFM_FP32_BF16X) {
     if ((st = dev_alloc(reinterpret_cast<char**>(&ws->Xb), blk / 2)) != OFM_OK) return fail(st);
     if ((st = dev_alloc(reinterpret_cast<char**>(&ws->Vb), blk / 2)) != OFM_OK) return fail(st);
@@ -517,9 +525,13 @@ static PassArgs base_args(ofm_workspace ws, int mode, int flags) {
 
 static ofm_status finalize(ofm_workspace ws, const PassArgs& a, hipStream_t s) {
   if (a.nv == 0) return OFM_OK;
+  // the update of the recurrence writes [M | H]: H goes to its own slot
+  const bool split = a.mode == kUpdateR && (a.flags & kFlagH);
+  const int kk = ws->k * ws->k;
+  double* out2 = split ? ws->sc + sc_off(ws->k).H : nullptr;
   HIPCHK(timed(ws, OFM_PASS_REDUCE, s, [&] {
     return launch_finalize(ws->partials, a.nblocks, a.nv, ws->sc + partial_off(ws->k, a.mode),
-                           ws->lvl2, ws->tickets, s);
+                           ws->lvl2, ws->tickets, s, split ? kk : a.nv, out2);
   }));
   return OFM_OK;
 }
@@ -582,6 +594,26 @@ static bool is_f2(int v) { return v == OFM_F2 || v == OFM_TRI_F2; }
 static ofm_status direction(ofm_workspace ws, void* X, const void* Gp, const void* Vp, int check,
                             hipStream_t s) {
   const int restart = ws->opts.restart ? kFlagRestart : 0;
+  if (ws->opts.recur) {
+    // A X exactly when the recurrence has no valid A X or a residual is due,
+    // then the direction from the stored A X
+    if (check || !ws->ax_valid) {
+      PassArgs a = base_args(ws, kAXF2, check ? kFlagCheck : 0);
+      a.Z = X;
+      a.Zg = ws->Xb;
+      a.Y = ws->AX;
+      OFMCHK(run_spmm(ws, a, s));
+      if (check) HIPCHK(run_residual(ws, s, true));
+      ws->ax_valid = true;
+    }
+    PassArgs b = base_args(ws, is_f2(ws->opts.variant) ? kGPassF2 : kGPassF1, restart);
+    b.X = X;
+    b.AX = ws->AX;
+    b.G = ws->G[ws->cur];
+    b.Gp = Gp;
+    b.Vp = Vp;
+    return run_dense(ws, b, s);
+  }
   if (!is_f2(ws->opts.variant)) {
     PassArgs a = base_args(ws, kGF1, (check ? kFlagCheck : 0) | restart);
     a.Z = X;
@@ -624,17 +656,31 @@ static ofm_status search_and_update(ofm_workspace ws, void* X, const void* Vp, b
   w.Z = ws->V[cur];
   w.Zg = ws->Vb;
   w.X = X;
+  w.Y = ws->opts.recur ? ws->AV : nullptr;
   OFMCHK(run_spmm(ws, w, s));
   HIPCHK(timed(ws, OFM_PASS_LINESEARCH, s, [&] {
     return launch_linesearch(ws->k, ws->opts.variant, first && ws->opts.first_step == 1,
                              ws->opts.alpha0, ws->sc, ws->status, ws->frozen, s);
   }));
-  PassArgs u = base_args(ws, kUpdate, 0);
-  u.X = X;
-  u.Xw = X;
-  u.Xb = ws->Xb;
-  u.V = ws->V[cur];
-  OFMCHK(run_dense(ws, u, s));
+  if (ws->opts.recur) {
+    // X += V diag(alpha), A X += A V diag(alpha); M (and H for f2) of the new X
+    PassArgs u = base_args(ws, kUpdateR, is_f2(ws->opts.variant) ? kFlagH : 0);
+    u.X = X;
+    u.Xw = X;
+    u.Xb = ws->Xb;
+    u.V = ws->V[cur];
+    u.Z = ws->AV;
+    u.AX = ws->AX;
+    u.Y = ws->AX;
+    OFMCHK(run_dense(ws, u, s));
+  } else {
+    PassArgs u = base_args(ws, kUpdate, 0);
+    u.X = X;
+    u.Xw = X;
+    u.Xb = ws->Xb;
+    u.V = ws->V[cur];
+    OFMCHK(run_dense(ws, u, s));
+  }
   ws->cur ^= 1;
   ws->t += 1;
   return OFM_OK;
@@ -653,6 +699,7 @@ extern "C" ofm_status ofm_init(ofm_workspace ws, void* X, hipStream_t stream) {
   ws->cur = 0;
   ws->t = 0;
   ws->last_check = -1;
+  ws->ax_valid = false;
   OFMCHK(gram_m(ws, X, stream));
   OFMCHK(direction(ws, X, nullptr, nullptr, 0, stream));
   OFMCHK(search_and_update(ws, X, nullptr, true, stream));
@@ -703,6 +750,7 @@ static ofm_status capture_chunk(ofm_workspace ws, void* X, hipGraphExec_t* out) 
   const int64_t t0 = ws->t;
   const int cur0 = ws->cur;
   const int64_t lc0 = ws->last_check;
+  const bool axv0 = ws->ax_valid;
   const bool timing = ws->timing;
   ws->timing = false;
   hipGraph_t g = nullptr;
@@ -716,6 +764,7 @@ static ofm_status capture_chunk(ofm_workspace ws, void* X, hipGraphExec_t* out) 
   ws->t = t0;
   ws->cur = cur0;
   ws->last_check = lc0;
+  ws->ax_valid = axv0;
   ws->timing = timing;
   if (st == OFM_OK && hipGraphInstantiate(out, g, nullptr, nullptr, 0) != hipSuccess)
     st = OFM_E_HIP;
@@ -782,6 +831,7 @@ extern "C" ofm_status ofm_residual(ofm_workspace ws, const void* X, hipStream_t 
   OFMCHK(run_spmm(ws, a, stream));
   HIPCHK(run_residual(ws, stream, false));
   ws->last_check = ws->t;
+  ws->ax_valid = false;
   ofm_stats st{};
   OFMCHK(read_stats(ws, stream, &st));
   if (host_out) *host_out = st;
@@ -792,6 +842,7 @@ extern "C" ofm_status ofm_objective(ofm_workspace ws, const void* X, double* f_o
                                     hipStream_t stream) {
   if (!ws || !X || !f_out) return OFM_E_INVALID_ARG;
   if (ws->opts.variant == OFM_TRI_F1 || ws->opts.variant == OFM_TRI_F2) return OFM_E_UNSUPPORTED;
+  ws->ax_valid = false;  // the products below overwrite A X
   // without a caller buffer the gradient goes to the current-direction slot,
   // which the next step overwrites anyway (the CG state is in the other slot)
   void* gout = grad ? grad : ws->G[ws->cur];
@@ -845,6 +896,7 @@ extern "C" ofm_status ofm_set_state(ofm_workspace ws, const void* X, const void*
   HIPCHK(hipMemsetAsync(ws->frozen, 0, sizeof(int), stream));
   ws->t = t;
   ws->last_check = -1;
+  ws->ax_valid = false;
   ws->initialized = true;
   return OFM_OK;
 }

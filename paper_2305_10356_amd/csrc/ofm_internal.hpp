@@ -82,7 +82,9 @@ enum Mode : int {
   kVPass = 6,     // V = -G + beta V_prev, V^T V, X^T V, diag V^T G
   kUpdate = 7,    // X += alpha V, X^T X
   kGramM = 8,     // X^T X
-  kGGP = 9        // diag G_prev^T G_prev
+  kGGP = 9,       // diag G_prev^T G_prev
+  kUpdateR = 10,  // X += alpha V, AX += alpha AV, X^T X [, X^T A X]
+  kGPassF1 = 11   // G = c (AX + X M') from a stored AX, gg, gpg [, vpg]
 };
 
 struct LaplacianDev {
@@ -112,8 +114,8 @@ struct PassArgs {
   int mode = 0;
   int variant = 0;
   int flags = 0;          // kFlagCheck, kFlagRestart, kFlagFirst
-  const void* Z = nullptr;     // SpMM input (X or V)
-  void* Y = nullptr;           // SpMM plain output (Y or AX)
+  const void* Z = nullptr;     // SpMM input (X or V); AV for kUpdateR
+  void* Y = nullptr;           // SpMM plain output (Y, AX or AV); AX for kUpdateR
   const void* X = nullptr;     // own X rows
   void* Xw = nullptr;          // X written by the update pass
   const void* AX = nullptr;
@@ -139,7 +141,7 @@ struct PassArgs {
   void* Vb = nullptr;
 };
 
-enum : int { kFlagCheck = 1, kFlagRestart = 2, kFlagFirst = 4 };
+enum : int { kFlagCheck = 1, kFlagRestart = 2, kFlagFirst = 4, kFlagH = 8 };
 
 // Batched solves: one launch per pass covers every graph of a width group.
 struct BatchGraph {
@@ -196,8 +198,9 @@ int batch_wpb(int k);
 // Launchers (ofm_kernels.hip).  Each returns a hipError_t.
 hipError_t launch_spmm(int precision, int k, PassArgs& a, hipStream_t s);
 hipError_t launch_dense(int precision, int k, PassArgs& a, hipStream_t s);
+// out[v] for v < split, out2[v - split] for v >= split (split = nv: one range)
 hipError_t launch_finalize(const double* partials, int nb, int nv, double* out, double* lvl2,
-                           int* tickets, hipStream_t s);
+                           int* tickets, hipStream_t s, int split, double* out2);
 hipError_t launch_linesearch(int k, int variant, int first, double alpha0, double* sc,
                              int* status, const int* frozen, hipStream_t s);
 hipError_t launch_residual(int k, int variant, double normA2, double* sc, int* status,

@@ -106,14 +106,16 @@ constexpr int nbuf_of(int mode) {
   return mode == kGF1 ? 3
          : mode == kAXF2 ? 2
          : mode == kAVF2 ? 3
-         : mode == kGPassF2 ? 3
-         : mode == kVPass ? 2
+         : (mode == kGPassF2 || mode == kGPassF1) ? 3
+         : (mode == kVPass || mode == kUpdateR) ? 2
          : (mode == kUpdate || mode == kGramM) ? 1
                                                 : 0;
 }
-constexpr int nfrag_of(int mode) { return mode == kGF1 ? 1 : mode == kGPassF2 ? 2 : 0; }
+constexpr int nfrag_of(int mode) {
+  return (mode == kGF1 || mode == kGPassF1) ? 1 : mode == kGPassF2 ? 2 : 0;
+}
 constexpr int nvec_of(int mode) {
-  return (mode == kGF1 || mode == kGPassF2) ? 3
+  return (mode == kGF1 || mode == kGPassF2 || mode == kGPassF1) ? 3
          : (mode == kVPass || mode == kAVF1 || mode == kAVF2 || mode == kGGP) ? 1
                                                                                : 0;
 }
@@ -142,8 +144,10 @@ __host__ __device__ inline int mode_nv(int mode, int flags) {
     case kAXF2: return KK + ((flags & kFlagCheck) ? KK : 0);
     case kAVF1: return KP;
     case kAVF2: return KP + 2 * KK;
-    case kGPassF2: return 3 * KP;
+    case kGPassF2:
+    case kGPassF1: return 3 * KP;
     case kVPass: return 2 * KK + KP;
+    case kUpdateR: return KK + ((flags & kFlagH) ? KK : 0);
     case kUpdate:
     case kGramM: return KK;
     case kGGP: return KP;
@@ -154,12 +158,14 @@ template <int KP>
 __host__ __device__ inline int mode_off(int mode) {
   switch (mode) {
     case kGF1:
-    case kGPassF2: return SC<KP>::GG;
+    case kGPassF2:
+    case kGPassF1: return SC<KP>::GG;
     case kAXF2: return SC<KP>::H;
     case kAVF1:
     case kAVF2: return SC<KP>::FD;
     case kVPass: return SC<KP>::P;
     case kUpdate:
+    case kUpdateR:
     case kGramM: return SC<KP>::M;
     case kGGP: return SC<KP>::GGP;
     default: return 0;
@@ -515,6 +521,7 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
           if (MODE == kAVF1 || MODE == kAVF2) {
 #pragma unroll
             for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)z.v[q] * (double)acc.v[q];
+            if (a.Y) st16(static_cast<T*>(a.Y) + (size_t)row * KP + j * G::VECN, acc);
           }
           if (SM::NB > 0) {
             tile_store_vec<T, KP>(tA, gi, j, acc);
@@ -549,6 +556,7 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
           if (MODE == kAVF1 || MODE == kAVF2) {
 #pragma unroll
             for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)z.v[q] * (double)acc.v[q];
+            if (a.Y) st16(static_cast<T*>(a.Y) + (size_t)row * KP + j * G::VECN, acc);
           }
           if (SM::NB > 0) {
             tile_store_vec<T, KP>(tA, gi, j, acc);
@@ -695,9 +703,16 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
       colscal[q] = (T)beta;
       if (brank == 0 && threadIdx.x < G::LPR) const_cast<double*>(sc)[SC<KP>::BETA + c] = beta;
     }
-  } else if (MODE == kUpdate) {
+  } else if (MODE == kUpdate || MODE == kUpdateR) {
 #pragma unroll
     for (int q = 0; q < G::VECN; ++q) colscal[q] = (T)sc[SC<KP>::ALPHA + j * G::VECN + q];
+  } else if (MODE == kGPassF1) {
+    // G = c (AX + X M'): the direction kGF1 forms, with AX read from memory
+    const bool tri = a.variant == OFM_TRI_F1;
+    load_frags<T, KP>(frag, sc + SC<KP>::M, tri);
+    ca = tri ? T(1) : T(4);
+    cb = -ca;
+    __syncthreads();
   } else if (MODE == kGPassF2) {
     const bool tri = a.variant == OFM_TRI_F2;
     load_frags<T, KP>(frag, sc + SC<KP>::H, tri);   // H'
@@ -771,13 +786,38 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
           for (int q = 0; q < G::VECN; ++q) x.v[q] = T(0);
         }
         if (gi < G::TR) tile_store_vec<T, KP>(t0, gi, j, x);
+      } else if (MODE == kUpdateR) {
+        V16<T> x, ax;
+        if (ok) {
+          x = ld16(static_cast<const T*>(a.X) + off);
+          ax = ld16(static_cast<const T*>(a.AX) + off);
+          const V16<T> v = ld16(static_cast<const T*>(a.V) + off);
+          const V16<T> av = ld16(static_cast<const T*>(a.Z) + off);
+#pragma unroll
+          for (int q = 0; q < G::VECN; ++q) {
+            x.v[q] = fma(colscal[q], v.v[q], x.v[q]);
+            ax.v[q] = fma(colscal[q], av.v[q], ax.v[q]);
+          }
+          st16(static_cast<T*>(a.Xw) + off, x);
+          st16(static_cast<T*>(a.Y) + off, ax);
+          if constexpr (sizeof(T) == 4) {
+            if (a.Xb) st_bf16<KP>(a.Xb, (size_t)(r0 + gi), j, x);
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < G::VECN; ++q) x.v[q] = ax.v[q] = T(0);
+        }
+        if (gi < G::TR) {
+          tile_store_vec<T, KP>(t0, gi, j, x);
+          tile_store_vec<T, KP>(t1, gi, j, ax);
+        }
       } else if (MODE == kGGP) {
         if (ok) {
           const V16<T> gp = ld16(static_cast<const T*>(a.Gp) + off);
 #pragma unroll
           for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)gp.v[q] * (double)gp.v[q];
         }
-      } else if (MODE == kGPassF2) {
+      } else if (MODE == kGPassF2 || MODE == kGPassF1) {
         V16<T> x, ax;
         if (ok) {
           x = ld16(static_cast<const T*>(a.X) + off);
@@ -800,13 +840,19 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
       tile_gram<T, KP, false>(t1, t0, gB, lane);  // C = X^T V
     } else if (MODE == kUpdate || MODE == kGramM) {
       tile_gram<T, KP, true>(t0, t0, gA, lane);   // M = X^T X
-    } else if (MODE == kGPassF2) {
-      tile_times_matrix<T, KP>(t0, frag, t2, lane, false);   // X H'
+    } else if (MODE == kUpdateR) {
+      tile_gram<T, KP, true>(t0, t0, gA, lane);                        // M = X^T X
+      if (a.flags & kFlagH) tile_gram<T, KP, false>(t0, t1, gB, lane);  // H = X^T (AX)
+    } else if (MODE == kGPassF2 || MODE == kGPassF1) {
+      // kGPassF2: D = X H' + AX M'; kGPassF1: D = X M'; then G = ca AX - cb D
+      tile_times_matrix<T, KP>(t0, frag, t2, lane, false);
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      tile_times_matrix<T, KP>(t1, frag2, t2, lane, true);   // + AX M'
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      if (MODE == kGPassF2) {
+        tile_times_matrix<T, KP>(t1, frag2, t2, lane, true);
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      }
 #pragma unroll
       for (int pass = 0; pass < G::NPASS; ++pass) {
         const int gi = pass * G::RPW + g;
@@ -847,9 +893,12 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
     block_vec_out<T, KP, 1>(cacc, red, prow, 2 * KK, wave, lane, WPB);
   } else if (MODE == kUpdate || MODE == kGramM) {
     block_gram_out<T, KP, true>(gA, red, prow, 0, wave, lane, WPB);
+  } else if (MODE == kUpdateR) {
+    block_gram_out<T, KP, true>(gA, red, prow, 0, wave, lane, WPB);
+    if (a.flags & kFlagH) block_gram_out<T, KP, false>(gB, red, prow, KK, wave, lane, WPB);
   } else if (MODE == kGGP) {
     block_vec_out<T, KP, 1>(cacc, red, prow, 0, wave, lane, WPB);
-  } else if (MODE == kGPassF2) {
+  } else if (MODE == kGPassF2 || MODE == kGPassF1) {
     block_vec_out<T, KP, 3>(cacc, red, prow, 0, wave, lane, WPB);
   }
 }
@@ -873,7 +922,10 @@ __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64)) dense_kernel(PassArgs 
 
 __global__ void __launch_bounds__(64) finalize_kernel(const double* __restrict__ partials, int nb,
                                                       int nv, double* __restrict__ out,
-                                                      double* lvl2, int* tickets) {
+                                                      double* lvl2, int* tickets, int split,
+                                                      double* __restrict__ out2) {
+  // values v >= split go to the second range
+  if (blockIdx.x * 64 + threadIdx.x >= split) out = out2 - split;
   const int cx = blockIdx.x;
   const int cy = blockIdx.y;
   const int ny = gridDim.y;
@@ -1457,8 +1509,10 @@ template <typename T, int KP>
 static hipError_t dense_t(PassArgs& a, hipStream_t s) {
   switch (a.mode) {
     case kGPassF2: return dense_mode<T, KP, kGPassF2>(a, s);
+    case kGPassF1: return dense_mode<T, KP, kGPassF1>(a, s);
     case kVPass: return dense_mode<T, KP, kVPass>(a, s);
     case kUpdate: return dense_mode<T, KP, kUpdate>(a, s);
+    case kUpdateR: return dense_mode<T, KP, kUpdateR>(a, s);
     case kGramM: return dense_mode<T, KP, kGramM>(a, s);
     case kGGP: return dense_mode<T, KP, kGGP>(a, s);
   }
@@ -1506,10 +1560,15 @@ hipError_t launch_dense(int precision, int k, PassArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_finalize(const double* partials, int nb, int nv, double* out, double* lvl2,
-                           int* tickets, hipStream_t s) {
+                           int* tickets, hipStream_t s, int split, double* out2) {
   const int ny = (nb + kFinChunk - 1) / kFinChunk;
   dim3 grid((nv + 63) / 64, ny);
-  hipLaunchKernelGGL(finalize_kernel, grid, dim3(64), 0, s, partials, nb, nv, out, lvl2, tickets);
+  if (split >= nv || !out2) {
+    split = nv;
+    out2 = out;
+  }
+  hipLaunchKernelGGL(finalize_kernel, grid, dim3(64), 0, s, partials, nb, nv, out, lvl2, tickets,
+                     split, out2);
   return hipGetLastError();
 }
 

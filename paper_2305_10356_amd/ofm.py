@@ -47,6 +47,7 @@ class Opts(ctypes.Structure):
         ("alpha0", ctypes.c_double),
         ("tol", ctypes.c_double),
         ("graph", ctypes.c_int),
+        ("recur", ctypes.c_int),
     ]
 
 
@@ -219,14 +220,15 @@ class Workspace:
     def __init__(self, lap: Laplacian, k: int, variant="f1", precision=OFM_FP32,
                  max_iter: int = 1000, check_every: int = 10, first_step: int = 0,
                  restart: bool = False, alpha0: float = 0.0, tol: float = 0.0,
-                 graph: bool = False):
+                 graph: bool = False, recur: bool = False):
         lib = load()
         self._lib = lib
         self.lap = lap
         self.k = k
         v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
         self.opts = Opts(v, int(precision), int(max_iter), int(check_every), int(first_step),
-                         1 if restart else 0, float(alpha0), float(tol), 1 if graph else 0)
+                         1 if restart else 0, float(alpha0), float(tol), 1 if graph else 0,
+                         1 if recur else 0)
         h = ctypes.c_void_p()
         _check(lib.ofm_workspace_create(lap.handle, k, ctypes.byref(self.opts), ctypes.byref(h)),
                "ofm_workspace_create")

@@ -8,6 +8,14 @@ the number of dispatches (rocprofv3 --pmc output converted with rocpd2csv).
 ``source-hash`` prints the SHA-256 of the kernel source, which a counter
 summary records so that a later benchmark can tell whether the counters
 still describe the kernels it runs.
+
+    python -m paper_2305_10356_amd.profiling traffic <fetch.csv> <write.csv> [<l2.csv>]
+
+``traffic`` scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch) by what the
+same counters read for the 256 MiB device copy of ``bench.py
+--copy-calibration`` and prints bytes per launch for the passes of one f1 step
+(lines ``traffic_bytes <pass> <bytes>``), with the L2 hit rate when a
+TCC_HIT/TCC_MISS file is given.
 """
 from __future__ import annotations
 
@@ -57,9 +65,70 @@ def read_traffic(summary_path: str):
     return out
 
 
+# kernel instantiation -> pass, for the FP32 k = 32 kernels of an f1 step
+F1_PASSES = {
+    "spmm_kernel<float, 32, 1, false, false>": "spmm_x",
+    "spmm_kernel<float, 32, 3, false, false>": "spmm_v",
+    "dense_kernel<float, 32, 6>": "v",
+    "dense_kernel<float, 32, 7>": "update",
+}
+COPY_BYTES = 256 * 1024 * 1024
+
+
+def _per_dispatch(path, counter):
+    out = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            if row["Counter_Name"] == counter:
+                out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return out
+
+
+def traffic(fetch_csv, write_csv, l2_csv=None, passes=F1_PASSES):
+    fe = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    wr = _per_dispatch(write_csv, "WRITE_SIZE")
+    copy = [k for k in fe if "copyBuffer" in k]
+    if not copy:
+        raise SystemExit("no calibration copy in the counter file (run with --copy-calibration)")
+    # the calibration launches are the copies of COPY_BYTES (the largest ones)
+    big_f = max(fe[copy[0]])
+    big_w = max(wr[copy[0]])
+    sf = COPY_BYTES / (big_f * 1024.0)
+    sw = COPY_BYTES / (big_w * 1024.0)
+    hits = _per_dispatch(l2_csv, "TCC_HIT_sum") if l2_csv else {}
+    miss = _per_dispatch(l2_csv, "TCC_MISS_sum") if l2_csv else {}
+    rows = []
+    for kern in sorted(fe):
+        name = next((p for key, p in passes.items() if key in kern), None)
+        if name is None:
+            continue
+        f = sum(fe[kern]) / len(fe[kern])
+        w = sum(wr.get(kern, [0.0])) / max(len(wr.get(kern, [])), 1)
+        hr = None
+        if kern in hits and kern in miss:
+            h, m = sum(hits[kern]), sum(miss[kern])
+            hr = h / (h + m) if h + m > 0 else None
+        rows.append((name, kern, f, w, 1024.0 * (f * sf + w * sw), hr))
+    return sf, sw, rows
+
+
 def main(argv):
     if len(argv) >= 1 and argv[0] == "source-hash":
         print(source_hash())
+        return 0
+    if len(argv) >= 3 and argv[0] == "traffic":
+        sf, sw, rows = traffic(argv[1], argv[2], argv[3] if len(argv) > 3 else None)
+        print(f"scale: FETCH x{sf:.3f}, WRITE x{sw:.3f}")
+        print("| pass | kernel | FETCH_SIZE KiB/launch | WRITE_SIZE KiB/launch "
+              "| scaled bytes/launch | L2 hit rate |")
+        print("|:--|:--|--:|--:|--:|--:|")
+        for name, kern, f, w, b, hr in rows:
+            k = kern.replace("void ofm::", "").replace("(ofm::PassArgs)", "")
+            h = f"{100 * hr:.1f}%" if hr is not None else "-"
+            print(f"| {name} | {k} | {f:.2f} | {w:.2f} | {b:.4g} | {h} |")
+        print()
+        for name, _, _, _, b, _ in rows:
+            print(f"    traffic_bytes {name} {int(round(b))}")
         return 0
     if len(argv) >= 2 and argv[0] == "counters":
         res = counter_means(argv[1:])
