@@ -135,6 +135,49 @@ def batched_vs_plain(variant: str, count: int = 256, plain: bool = True):
     }
 
 
+def spmm_locality_ladder(g, k: int = 32, windows=(32768, 262144, None), reps: int = 20):
+    """The SpMM kernel (Y = A Z, FP32) on graphs with the rows and degrees of
+    the headline graph but every column folded into the first W node ids
+    (col mod W, duplicates in a row merged): the gathered rows then come from
+    a W x k window of Z (W = 32768: 4 MB, the L2 of one XCD; 262144: 32 MB;
+    None: all of Z, 256 MB).  Same kernel, same entry count, different reuse."""
+    import numpy as np
+    import torch
+    from paper_2305_10356_amd import ofm
+    n = g.n
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.row_ptr))
+    Z = torch.randn(n, k, device="cuda")
+    Y = torch.empty_like(Z)
+    out = []
+    for w in windows:
+        if w is None:
+            rp, ci = g.row_ptr, g.col_idx
+        else:
+            key = np.unique(rows * w + (g.col_idx.astype(np.int64) % w))
+            r = key // w
+            ci = (key % w).astype(np.int32)
+            rp = np.zeros(n + 1, dtype=np.int64)
+            np.cumsum(np.bincount(r, minlength=n), out=rp[1:])
+            rp = rp.astype(np.int32)
+        lap = ofm.Laplacian(rp, ci)
+        for _ in range(3):
+            lap.apply(Z, Y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            lap.apply(Z, Y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        nnz = int(ci.shape[0])
+        out.append({"window_rows": w if w is not None else n,
+                    "window_MB": round((w if w is not None else n) * k * 4 / 2**20, 1),
+                    "nnz": nnz, "avg_us": round(1e3 * ms, 1),
+                    "gathered_GBs": round(nnz * k * 4 / (ms * 1e-3) / 1e9, 1)})
+        lap.close()
+    return out
+
+
 def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10,
                  cold_stages=(9,)):
     """Growth stream of 10 snapshots, N = 200k .. 2M, k = 64, mean degree 20,
@@ -314,6 +357,7 @@ def main():
         extras["spmm_apply_fp32"] = {"avg_us": round(1e3 * ms, 1), "alg_bytes": b,
                                      "alg_GBs": round(b / (ms * 1e-3) / 1e9, 1)}
         del Z, Y
+        extras["spmm_locality_ladder"] = spmm_locality_ladder(g, k)
         # the other variants, and the FP64 plain form
         for v, prec in (("tri-f1", ofm.OFM_FP32), ("f2", ofm.OFM_FP32), ("tri-f2", ofm.OFM_FP32),
                         ("f1", ofm.OFM_FP64)):
