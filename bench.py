@@ -106,6 +106,18 @@ def batched_vs_plain(variant: str, count: int = 256, plain: bool = True):
     t_batch = time.perf_counter() - t0
     tpw, cand, escalated = B.schedule()
     B.close()
+    # the same with A X by recurrence between residual checks
+    Br = ofm.Batch(laps, ks, variant=variant, precision=ofm.OFM_FP32, max_iter=3000,
+                   check_every=10, tol=1e-4, restart=tri, recur=True)
+    Xr = [torch.tensor(x0.astype(np.float32), device="cuda") for _, x0 in gl]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_r = Br.solve(Xr)
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+    _, _, esc_r = Br.schedule()
+    Br.close()
+    del Xr
     st_p, t_plain = [{"converged": 0, "iters": 0}], float("nan")
     if plain:
         wss = [ofm.Workspace(lap, k, variant=variant, precision=ofm.OFM_FP64, max_iter=3000,
@@ -129,6 +141,11 @@ def batched_vs_plain(variant: str, count: int = 256, plain: bool = True):
         "plain_max_iters": int(max(s["iters"] for s in st_p)),
         "batched_tiles_per_wave": tpw, "schedule_candidates_ms": [round(x, 3) for x in cand],
         "batched_escalated_to_fp64": escalated,
+        "batched_recur_s": round(t_rec, 4),
+        "batched_recur_converged": int(sum(s["converged"] for s in st_r)),
+        "batched_recur_max_iters": int(max(s["iters"] for s in st_r)),
+        "batched_recur_escalated_to_fp64": esc_r,
+        "speedup_recur": round(t_plain / t_rec, 2),
         "batched_not_converged": [
             {"graph": i, "n": gl[i][0].n, "k": ks[i], "relres": st_b[i]["relres"]}
             for i in range(count) if not st_b[i]["converged"]],

@@ -250,7 +250,8 @@ ofm_status ofm_get_step_info(ofm_workspace ws, double* host_alpha, double* host_
  * stops iterating (on the device) as soon as its residual meets tol.
  * host_laps[count], host_ks[count]: the graphs and their widths (the handles
  * must outlive the batch); host_opts: shared options (precision OFM_FP32 or
- * OFM_FP32_BF16X; variant, max_iter, check_every, tol, restart, first_step).
+ * OFM_FP32_BF16X; variant, max_iter, check_every, tol, restart, first_step,
+ * recur; graph applies to the FP64 finishing solves only).
  * Allocates the per-graph state.  The block schedule (blocks per graph, each
  * graph's blocks on one XCD) is chosen among a few candidates by timing the
  * first iterations of every solve.

@@ -1150,6 +1150,7 @@ extern "C" ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps
   if (o.precision != OFM_FP32 && o.precision != OFM_FP32_BF16X) return OFM_E_UNSUPPORTED;
   if (o.max_iter < 1 || o.check_every < 1 || !(o.tol >= 0.0)) return OFM_E_INVALID_ARG;
   if (o.first_step != 0 && o.first_step != 1) return OFM_E_INVALID_ARG;
+  if ((o.restart | o.graph | o.recur) & ~1) return OFM_E_INVALID_ARG;
   for (int i = 0; i < count; ++i) {
     if (!host_laps[i]) return OFM_E_INVALID_ARG;
     if (!supported_k(host_ks[i], OFM_FP32) || host_ks[i] > host_laps[i]->g.n) return OFM_E_SHAPE;
@@ -1194,7 +1195,8 @@ extern "C" ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps
       part_total += (size_t)maxw * nvmax;
       buf_off[m] = buf_total;
       const size_t blk = (size_t)L->g.n * k * 4;
-      buf_total += 5 * blk + (bf ? blk : 0);   // V x2, G x2, AX (+ BF16 copies of X and V)
+      // V x2, G x2, AX (+ AV for the recurrence) (+ BF16 copies of X and V)
+      buf_total += (o.recur ? 6 : 5) * blk + (bf ? blk : 0);
       buf_total = (buf_total + 255) & ~(size_t)255;
     }
     if ((st = dev_alloc(&g.active, n)) != OFM_OK) return fail(st);
@@ -1224,8 +1226,11 @@ extern "C" ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps
       d.G[0] = p + 2 * blk;
       d.G[1] = p + 3 * blk;
       d.AX = p + 4 * blk;
-      d.Xb = bf ? p + 5 * blk : nullptr;
-      d.Vb = bf ? p + 5 * blk + blk / 2 : nullptr;
+      char* q = p + 5 * blk;
+      d.AV = o.recur ? q : nullptr;
+      if (o.recur) q += blk;
+      d.Xb = bf ? q : nullptr;
+      d.Vb = bf ? q + blk / 2 : nullptr;
       d.sc = g.sc + (size_t)m * sct;
       d.partials = g.partials + part_off[m];
       d.status = g.status + m;
@@ -1300,17 +1305,29 @@ static ofm_status batch_iteration(ofm_batch B, BatchGroup& g, int cur, int64_t t
   const int fs = first ? kFlagFirst : 0;
   if (first) OFMCHK(bpass(g, base, kGramM, 0, false));
   const bool f2 = o.variant == OFM_F2 || o.variant == OFM_TRI_F2;
-  if (!f2) {
-    OFMCHK(bpass(g, base, kGF1, (check ? kFlagCheck : 0) | rs | fs, true));
+  if (o.recur) {
+    // A X exactly at the set-up step and when a residual is due, else by the
+    // recurrence the previous update applied
+    if (first || check) OFMCHK(bpass(g, base, kAXF2, check ? kFlagCheck : 0, true));
+    if (check) HIPCHK(launch_batch_residual(g.k, base, g.stream));
+    OFMCHK(bpass(g, base, f2 ? kGPassF2 : kGPassF1, rs | fs, false));
   } else {
-    OFMCHK(bpass(g, base, kAXF2, check ? kFlagCheck : 0, true));
+    if (!f2) {
+      OFMCHK(bpass(g, base, kGF1, (check ? kFlagCheck : 0) | rs | fs, true));
+    } else {
+      OFMCHK(bpass(g, base, kAXF2, check ? kFlagCheck : 0, true));
+    }
+    if (check) HIPCHK(launch_batch_residual(g.k, base, g.stream));
+    if (f2) OFMCHK(bpass(g, base, kGPassF2, rs | fs, false));
   }
-  if (check) HIPCHK(launch_batch_residual(g.k, base, g.stream));
-  if (f2) OFMCHK(bpass(g, base, kGPassF2, rs | fs, false));
   OFMCHK(bpass(g, base, kVPass, rs | fs, false));
   OFMCHK(bpass(g, base, f2 ? kAVF2 : kAVF1, 0, true));
   HIPCHK(launch_batch_linesearch(g.k, base, o.alpha0, first && o.first_step == 1, g.stream));
-  OFMCHK(bpass(g, base, kUpdate, 0, false));
+  if (o.recur) {
+    OFMCHK(bpass(g, base, kUpdateR, f2 ? kFlagH : 0, false));
+  } else {
+    OFMCHK(bpass(g, base, kUpdate, 0, false));
+  }
   return OFM_OK;
 }
 

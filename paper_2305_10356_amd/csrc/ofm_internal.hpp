@@ -155,6 +155,7 @@ struct BatchGraph {
   void* V[2] = {nullptr, nullptr};
   void* G[2] = {nullptr, nullptr};
   void* AX = nullptr;
+  void* AV = nullptr;          // A V kept for the recurrence of A X (null without it)
   void* Xb = nullptr;
   void* Vb = nullptr;
   double* sc = nullptr;

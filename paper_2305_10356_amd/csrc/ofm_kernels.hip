@@ -1651,6 +1651,7 @@ __device__ inline PassArgs batch_pass_args(const BatchArgs& b, const BatchGraph&
       a.Y = d.AX;
       break;
     case kGPassF2:
+    case kGPassF1:
       a.X = d.X;
       a.AX = d.AX;
       a.G = d.G[cur];
@@ -1669,12 +1670,22 @@ __device__ inline PassArgs batch_pass_args(const BatchArgs& b, const BatchGraph&
       a.Z = d.V[cur];
       a.Zg = b.bf16 ? d.Vb : nullptr;
       a.X = d.X;
+      a.Y = d.AV;
       break;
     case kUpdate:
       a.X = d.X;
       a.Xw = d.X;
       a.Xb = b.bf16 ? d.Xb : nullptr;
       a.V = d.V[cur];
+      break;
+    case kUpdateR:
+      a.X = d.X;
+      a.Xw = d.X;
+      a.Xb = b.bf16 ? d.Xb : nullptr;
+      a.V = d.V[cur];
+      a.Z = d.AV;
+      a.AX = d.AX;
+      a.Y = d.AX;
       break;
     case kGramM:
       a.X = d.X;
@@ -1738,7 +1749,9 @@ __global__ void __launch_bounds__(64) batch_finalize_kernel(BatchArgs b) {
 #pragma unroll
     for (int q = 0; q < kFinChunk; ++q) s += x[q];
   }
-  d.sc[b.off + v] = s;
+  // the update of the recurrence writes [M | H]: H goes to its own slot
+  const int split = (b.mode == kUpdateR && (b.flags & kFlagH)) ? KP * KP : b.nv;
+  d.sc[v < split ? b.off + v : SC<KP>::H + (v - split)] = s;
 }
 
 template <int KP>
@@ -1816,8 +1829,10 @@ static hipError_t batch_dense_t(BatchArgs& b, int grid, hipStream_t s) {
   }
   switch (b.mode) {
     case kGPassF2: OFM_BDENSE(kGPassF2)
+    case kGPassF1: OFM_BDENSE(kGPassF1)
     case kVPass: OFM_BDENSE(kVPass)
     case kUpdate: OFM_BDENSE(kUpdate)
+    case kUpdateR: OFM_BDENSE(kUpdateR)
     case kGramM: OFM_BDENSE(kGramM)
   }
 #undef OFM_BDENSE

@@ -350,14 +350,14 @@ class Batch:
 
     def __init__(self, laps, ks, variant="f1", precision=OFM_FP32, max_iter: int = 1000,
                  check_every: int = 10, tol: float = 1e-4, restart: bool = False,
-                 first_step: int = 0, alpha0: float = 0.0):
+                 first_step: int = 0, alpha0: float = 0.0, recur: bool = False):
         lib = load()
         self._lib = lib
         self.laps = list(laps)
         self.ks = [int(k) for k in ks]
         v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
         self.opts = Opts(v, int(precision), int(max_iter), int(check_every), int(first_step),
-                         1 if restart else 0, float(alpha0), float(tol))
+                         1 if restart else 0, float(alpha0), float(tol), 0, 1 if recur else 0)
         n = len(self.laps)
         handles = (ctypes.c_void_p * n)(*[l.handle.value for l in self.laps])
         kk = (ctypes.c_int * n)(*self.ks)

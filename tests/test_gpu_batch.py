@@ -32,16 +32,19 @@ def batch_graphs(lib):
     return gs, laps
 
 
+@pytest.mark.parametrize("recur", [False, True])
 @pytest.mark.parametrize("variant", ["f1", "f2"])
-def test_batch_early_window_matches_single(batch_graphs, variant):
+def test_batch_early_window_matches_single(batch_graphs, variant, recur):
     from paper_2305_10356_amd import ofm
     gs, laps = batch_graphs
     iters = 9
-    B = ofm.Batch(laps, [k for _, _, k in gs], variant=variant, max_iter=iters, tol=0.0)
+    B = ofm.Batch(laps, [k for _, _, k in gs], variant=variant, max_iter=iters, tol=0.0,
+                  recur=recur)
     Xs = [torch.tensor(x0.astype(np.float32), device="cuda") for _, x0, _ in gs]
     st = B.solve(Xs)
     for (g, x0, k), lap, X, s in zip(gs, laps, Xs, st):
-        ws = ofm.Workspace(lap, k, variant=variant, precision=ofm.OFM_FP32, check_every=10)
+        ws = ofm.Workspace(lap, k, variant=variant, precision=ofm.OFM_FP32, check_every=10,
+                           recur=recur)
         Y = torch.tensor(x0.astype(np.float32), device="cuda")
         ws.init(Y)
         for _ in range(iters - 1):
@@ -52,12 +55,13 @@ def test_batch_early_window_matches_single(batch_graphs, variant):
         assert s["iters"] == iters
 
 
-@pytest.mark.parametrize("variant", ["f1", "tri-f2"])
-def test_batch_converges_each_graph(batch_graphs, variant):
+@pytest.mark.parametrize("variant,recur", [("f1", False), ("tri-f2", False), ("f1", True),
+                                           ("f2", True), ("tri-f2", True)])
+def test_batch_converges_each_graph(batch_graphs, variant, recur):
     from paper_2305_10356_amd import ofm
     gs, laps = batch_graphs
     B = ofm.Batch(laps, [k for _, _, k in gs], variant=variant, max_iter=3000, tol=1e-4,
-                  check_every=10, restart=variant.startswith("tri"))
+                  check_every=10, restart=variant.startswith("tri"), recur=recur)
     Xs = [torch.tensor(x0.astype(np.float32), device="cuda") for _, x0, _ in gs]
     st = B.solve(Xs)
     tpw, ms, esc = B.schedule()
