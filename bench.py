@@ -105,6 +105,7 @@ def batched_vs_plain(variant: str, count: int = 256, plain: bool = True):
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     tpw, cand, escalated = B.schedule()
+    loop_ms, finish_ms = B.phases()
     B.close()
     # the same with A X by recurrence between residual checks
     Br = ofm.Batch(laps, ks, variant=variant, precision=ofm.OFM_FP32, max_iter=3000,
@@ -116,6 +117,7 @@ def batched_vs_plain(variant: str, count: int = 256, plain: bool = True):
     torch.cuda.synchronize()
     t_rec = time.perf_counter() - t0
     _, _, esc_r = Br.schedule()
+    loop_r, finish_r = Br.phases()
     Br.close()
     del Xr
     st_p, t_plain = [{"converged": 0, "iters": 0}], float("nan")
@@ -141,10 +143,12 @@ def batched_vs_plain(variant: str, count: int = 256, plain: bool = True):
         "plain_max_iters": int(max(s["iters"] for s in st_p)),
         "batched_tiles_per_wave": tpw, "schedule_candidates_ms": [round(x, 3) for x in cand],
         "batched_escalated_to_fp64": escalated,
+        "batched_phase_ms": {"fp32_loop": round(loop_ms, 1), "fp64_finish": round(finish_ms, 1)},
         "batched_recur_s": round(t_rec, 4),
         "batched_recur_converged": int(sum(s["converged"] for s in st_r)),
         "batched_recur_max_iters": int(max(s["iters"] for s in st_r)),
         "batched_recur_escalated_to_fp64": esc_r,
+        "batched_recur_phase_ms": {"fp32_loop": round(loop_r, 1), "fp64_finish": round(finish_r, 1)},
         "speedup_recur": round(t_plain / t_rec, 2),
         "batched_not_converged": [
             {"graph": i, "n": gl[i][0].n, "k": ks[i], "relres": st_b[i]["relres"]}
@@ -196,7 +200,7 @@ def spmm_locality_ladder(g, k: int = 32, windows=(32768, 262144, None), reps: in
 
 
 def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10,
-                 cold_stages=(9,)):
+                 cold_stages=(9,), recur: bool = False):
     """Growth stream of 10 snapshots, N = 200k .. 2M, k = 64, mean degree 20,
     r = 0.3: each stage solved to residual 1e-4 (checked every 10 iterations)
     in FP32 from the previous stage's solution (new rows N(0, 1/N_s)), with
@@ -210,7 +214,8 @@ def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10
     log(f"growth stream generated in {time.perf_counter() - t:.1f} s")
     tri = variant.startswith("tri")
     warm = StreamingSolver(64, variant=variant, precision=ofm.OFM_FP32, tol=1e-4,
-                           check_every=10, max_iter=5000, graph=True, restart=tri, seed=4)
+                           check_every=10, max_iter=5000, graph=True, restart=tri,
+                           recur=recur, seed=4)
     stages_out = []
     for s in range(stages):
         g = gs.snapshot(s)
@@ -218,7 +223,7 @@ def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10
         if s in cold_stages:
             cold = StreamingSolver(64, variant=variant, precision=ofm.OFM_FP32, tol=1e-4,
                                    check_every=10, max_iter=5000, graph=True, restart=tri,
-                                   seed=4)
+                                   recur=recur, seed=4)
             cold.stage = s
             rc = cold.solve_stage(g.row_ptr, g.col_idx, warm=False)
             rec["cold_iters"] = rc["iters"]
@@ -234,6 +239,7 @@ def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10
         "workload": f"growth stream {stages} snapshots N={gs.bounds[0]}..{n_final} k=64 "
                     f"mean-degree 20 r=0.3, FP32, graph-replayed loop, tol 1e-4",
         "variant": variant,
+        "recur_ax": recur,
         "total_solve_s": round(sum(r["solve_s"] for r in stages_out), 4),
         "all_converged": all(r["converged"] == 1 for r in stages_out),
         "stages": stages_out,
@@ -274,7 +280,7 @@ def main():
         print(json.dumps(batched_vs_plain(args.variant, plain=False)), flush=True)
         return
     if args.streaming_only:
-        print(json.dumps(streaming_c4(args.variant)), flush=True)
+        print(json.dumps(streaming_c4(args.variant, recur=args.recur)), flush=True)
         return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -459,6 +465,7 @@ def main():
             extras["batched_vs_plain"] = batched_vs_plain(args.variant)
         if not args.no_streaming:
             extras["streaming_warm_start"] = streaming_c4(args.variant)
+            extras["streaming_warm_start_recur"] = streaming_c4(args.variant, recur=True)
         # post-processing (Algorithm 1 steps 4-5), once per solve
         torch.cuda.synchronize()
         t1 = time.perf_counter()

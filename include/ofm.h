@@ -265,16 +265,21 @@ ofm_status ofm_batch_destroy(ofm_batch b);
  * stats (iters = updates done, relres of the X it stopped at).  A graph whose
  * FP32 residual decreases by less than 5% over 10 checks before reaching tol
  * (or that reaches max_iter) is finished by an FP64 solve (k <= 32) started
- * from its FP32 X with a fresh CG state; that stage allocates a workspace.
- * Synchronizing. */
+ * from its FP32 X with a fresh CG state; that stage allocates a workspace per
+ * finished graph and runs up to 4 of them at once, each on its own stream and
+ * host thread.  Synchronizing. */
 ofm_status ofm_batch_solve(ofm_batch b, void* const* host_X, hipStream_t stream,
                            ofm_stats* host_stats);
 /* Schedule chosen by the last solve: host_tpw = tiles per wavefront target
- * (blocks per graph ~ tiles / (waves per block * tpw)), host_ms[3] = measured
+ * (blocks per graph ~ tiles / (waves per block * tpw)), host_ms[4] = measured
  * time per iteration of each candidate (0 if untried), host_escalated = number
  * of graphs finished in FP64.  Any pointer may be NULL. */
 ofm_status ofm_batch_schedule(ofm_batch b, int* host_tpw, double* host_ms,
                               int* host_escalated);
+/* Host wall time of the last solve's two stages: the lockstep FP32 loop
+ * (host_loop_ms) and the FP64 finishing solves (host_finish_ms), which run
+ * concurrently on up to 4 streams of the batch.  Either pointer may be NULL. */
+ofm_status ofm_batch_phases(ofm_batch b, double* host_loop_ms, double* host_finish_ms);
 
 /*
  * Host copy (synchronizing) of one k x k FP64 product held by the workspace,

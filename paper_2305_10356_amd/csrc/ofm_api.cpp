@@ -3,10 +3,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "ofm_internal.hpp"
@@ -1057,9 +1059,9 @@ extern "C" ofm_status ofm_kmeans(int64_t n, int dim, int n_clusters, const float
 
 namespace {
 
-constexpr int kBatchCand = 3;
+constexpr int kBatchCand = 4;
 constexpr int kBatchWorkers = 128;                 // blocks per XCD
-const int kBatchTpw[kBatchCand] = {2, 4, 8};      // candidate tiles per wavefront
+const int kBatchTpw[kBatchCand] = {2, 4, 8, 16};  // candidate tiles per wavefront
 
 struct BatchGroup {
   int k = 0;
@@ -1082,6 +1084,8 @@ struct BatchGroup {
 
 }  // namespace
 
+constexpr int kFinishThreads = 4;  // concurrent FP64 finishing solves
+
 struct ofm_batch_s {
   int count = 0;
   ofm_opts opts{};
@@ -1089,13 +1093,18 @@ struct ofm_batch_s {
   std::vector<int> ks;
   std::vector<BatchGroup> groups;
   int chosen = 0;
-  double cand_ms[kBatchCand] = {0, 0, 0};
+  double cand_ms[kBatchCand] = {};
   int escalated = 0;
+  double loop_ms = 0.0;    // host time of the lockstep loop of the last solve
+  double finish_ms = 0.0;  // host time of its FP64 finishing stage
   hipEvent_t start = nullptr;
+  hipStream_t finish_streams[kFinishThreads] = {};
 };
 
 static void free_batch(ofm_batch b) {
   if (!b) return;
+  for (auto s : b->finish_streams)
+    if (s) (void)hipStreamDestroy(s);
   for (auto& g : b->groups) {
     dev_free(g.dgraphs);
     dev_free(g.dxlist);
@@ -1165,6 +1174,8 @@ extern "C" ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps
     return s;
   };
   if (hipEventCreate(&B->start) != hipSuccess) return fail(OFM_E_HIP);
+  for (auto& fs : B->finish_streams)
+    if (hipStreamCreateWithFlags(&fs, hipStreamNonBlocking) != hipSuccess) return fail(OFM_E_HIP);
   const int widths[5] = {4, 8, 16, 32, 64};
   const bool bf = o.precision == OFM_FP32_BF16X;
   for (int w : widths) {
@@ -1269,6 +1280,39 @@ extern "C" ofm_status ofm_batch_schedule(ofm_batch b, int* host_tpw, double* hos
   return OFM_OK;
 }
 
+extern "C" ofm_status ofm_batch_phases(ofm_batch b, double* host_loop_ms, double* host_finish_ms) {
+  if (!b) return OFM_E_INVALID_ARG;
+  if (host_loop_ms) *host_loop_ms = b->loop_ms;
+  if (host_finish_ms) *host_finish_ms = b->finish_ms;
+  return OFM_OK;
+}
+
+// FP64 solve of one graph from its FP32 block, on its own stream; the FP32
+// block receives the result.  Synchronizing on that stream.
+static ofm_status finish_fp64(ofm_laplacian L, int k, const ofm_opts& o, int64_t used,
+                              void* X32, hipStream_t s, ofm_stats* out) {
+  ofm_opts o64 = o;
+  o64.precision = OFM_FP64;
+  o64.max_iter = (int)(o.max_iter - used);
+  o64.first_step = 0;
+  o64.recur = 0;
+  ofm_workspace ws = nullptr;
+  ofm_status es = ofm_workspace_create(L, k, &o64, &ws);
+  if (es != OFM_OK) return es;
+  double* X64 = nullptr;
+  const int64_t cnt = L->g.n * k;
+  es = dev_alloc(&X64, cnt);
+  if (es == OFM_OK && launch_convert(cnt, 1, X32, X64, s) != hipSuccess) es = OFM_E_HIP;
+  if (es == OFM_OK) es = ofm_solve(ws, X64, s, out);
+  if (es == OFM_OK || es == OFM_E_NONFINITE || es == OFM_E_NUMERIC) {
+    if (launch_convert(cnt, 0, X64, X32, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      es = OFM_E_HIP;
+  }
+  dev_free(X64);
+  ofm_workspace_destroy(ws);
+  return es;
+}
+
 // the passes of one batched group: a dense or SpMM launch plus its per-graph
 // reduction
 static ofm_status bpass(BatchGroup& g, BatchArgs base, int mode, int flags, bool spmm) {
@@ -1337,6 +1381,7 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
   for (int i = 0; i < B->count; ++i)
     if (!host_X[i]) return OFM_E_INVALID_ARG;
   const ofm_opts& o = B->opts;
+  const auto t_solve = std::chrono::steady_clock::now();
   HIPCHK(hipEventRecord(B->start, stream));
   for (auto& g : B->groups) {
     HIPCHK(hipStreamWaitEvent(g.stream, B->start, 0));
@@ -1401,6 +1446,14 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
   B->escalated = 0;
   // per-graph stats; a graph whose FP32 residual stopped decreasing before the
   // tolerance (or ran out of iterations) is finished in FP64 from its FP32 X
+  struct Job {
+    int graph;
+    int k;
+    ofm_stats st;
+    ofm_status es;
+  };
+  std::vector<Job> jobs;
+  std::vector<ofm_stats> all(B->count);
   for (auto& g : B->groups) {
     HIPCHK(hipStreamSynchronize(g.stream));
     const int n = (int)g.idx.size();
@@ -1425,39 +1478,55 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
       st.converged = (done[m] >= 0 && st.status == OFM_OK) ? 1 : 0;
       const bool escalate = !st.converged && st.status == OFM_OK && o.tol > 0.0 && g.k <= 32 &&
                             st.iters < o.max_iter;
-      if (escalate) {
-        ofm_laplacian L = B->laps[g.idx[m]];
-        ofm_opts o64 = o;
-        o64.precision = OFM_FP64;
-        o64.max_iter = (int)(o.max_iter - st.iters);
-        o64.first_step = 0;
-        ofm_workspace ws = nullptr;
-        double* X64 = nullptr;
-        const int64_t cnt = L->g.n * g.k;
-        OFMCHK(ofm_workspace_create(L, g.k, &o64, &ws));
-        ofm_status es = dev_alloc(&X64, cnt);
-        ofm_stats s64{};
-        if (es == OFM_OK && launch_convert(cnt, 1, host_X[g.idx[m]], X64, stream) != hipSuccess)
-          es = OFM_E_HIP;
-        if (es == OFM_OK) es = ofm_solve(ws, X64, stream, &s64);
-        if (es == OFM_OK || es == OFM_E_NONFINITE || es == OFM_E_NUMERIC) {
-          if (launch_convert(cnt, 0, X64, host_X[g.idx[m]], stream) != hipSuccess ||
-              hipStreamSynchronize(stream) != hipSuccess)
-            es = OFM_E_HIP;
-        }
-        dev_free(X64);
-        ofm_workspace_destroy(ws);
-        if (es == OFM_E_HIP || es == OFM_E_NOMEM) return es;
-        st.iters += s64.iters;
-        st.relres = s64.relres;
-        st.objective = s64.objective;
-        st.relres_iter = st.iters - s64.iters + s64.relres_iter;
-        st.status = s64.status;
-        st.converged = s64.converged;
-        ++B->escalated;
-      }
-      if (host_stats) host_stats[g.idx[m]] = st;
+      if (escalate) jobs.push_back({g.idx[m], g.k, st, OFM_OK});
+      all[g.idx[m]] = st;
     }
+  }
+  const auto t_loop = std::chrono::steady_clock::now();
+  B->loop_ms = std::chrono::duration<double, std::milli>(t_loop - t_solve).count();
+  // the finishing solves run concurrently, each on a stream of its own (the
+  // batch's groups have completed: every group stream was synchronized above)
+  if (!jobs.empty()) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::atomic<int> next(0);
+    auto worker = [&](hipStream_t s) {
+      const bool on_device = hipSetDevice(dev) == hipSuccess;
+      for (int j = next++; j < (int)jobs.size(); j = next++) {
+        Job& jb = jobs[j];
+        if (!on_device) {
+          jb.es = OFM_E_HIP;
+          continue;
+        }
+        ofm_stats s64{};
+        jb.es = finish_fp64(B->laps[jb.graph], jb.k, o, jb.st.iters, host_X[jb.graph], s, &s64);
+        if (jb.es == OFM_OK || jb.es == OFM_E_NONFINITE || jb.es == OFM_E_NUMERIC) {
+          jb.st.iters += s64.iters;
+          jb.st.relres = s64.relres;
+          jb.st.objective = s64.objective;
+          jb.st.relres_iter = jb.st.iters - s64.iters + s64.relres_iter;
+          jb.st.status = s64.status;
+          jb.st.converged = s64.converged;
+        }
+      }
+    };
+    const int nt = std::min<int>(kFinishThreads, (int)jobs.size());
+    std::vector<std::thread> threads;
+    for (int i = 0; i < nt; ++i) threads.emplace_back(worker, B->finish_streams[i]);
+    for (auto& th : threads) th.join();
+    for (auto& jb : jobs) {
+      if (jb.es == OFM_E_HIP || jb.es == OFM_E_NOMEM || jb.es == OFM_E_INVALID_ARG ||
+          jb.es == OFM_E_SHAPE || jb.es == OFM_E_UNSUPPORTED)
+        return jb.es;
+      all[jb.graph] = jb.st;
+      ++B->escalated;
+    }
+  }
+  B->finish_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_loop).count();
+  if (host_stats)
+    for (int i = 0; i < B->count; ++i) host_stats[i] = all[i];
+  for (auto& g : B->groups) {
     HIPCHK(hipEventRecord(g.ev, g.stream));
     HIPCHK(hipStreamWaitEvent(stream, g.ev, 0));
   }

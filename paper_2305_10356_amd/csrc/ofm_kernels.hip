@@ -1695,6 +1695,15 @@ __device__ inline PassArgs batch_pass_args(const BatchArgs& b, const BatchGraph&
   return a;
 }
 
+// The graphs of one XCD take consecutive ranges of its workers, wrapping
+// around: graph i uses the nw_i workers that start where graph i-1's ended, so
+// small graphs run side by side instead of all on the first workers.  Returns
+// worker w's rank within the range that starts at base (>= nw: not in it).
+__device__ __host__ inline int batch_worker_rank(int w, int base, int workers) {
+  const int r = w - base;
+  return r >= 0 ? r : r + workers;
+}
+
 // workers a graph uses: enough for about tpw tiles per wavefront
 __device__ __host__ inline int batch_graph_workers(int64_t ntiles, int wpb, int tpw, int workers) {
   const int64_t per = (int64_t)wpb * tpw;
@@ -1707,12 +1716,15 @@ __global__ void __launch_bounds__((Cfg<float, KP>::WPB * 64)) batch_spmm_kernel(
   extern __shared__ __align__(16) unsigned char smem[];
   const int x = blockIdx.x & 7;
   const int w = blockIdx.x >> 3;
+  int base = 0;
   for (int i = b.xoff[x]; i < b.xoff[x + 1]; ++i) {
     const BatchGraph& d = b.graphs[b.xlist[i]];
     const int nw = batch_graph_workers(d.ntiles, Cfg<float, KP>::WPB, b.tpw, b.workers);
-    if (w >= nw || *d.active == 0) continue;
+    const int rank = batch_worker_rank(w, base, b.workers);
+    base = (base + nw) % b.workers;
+    if (rank >= nw || *d.active == 0) continue;
     const PassArgs a = batch_pass_args(b, d);
-    spmm_body<float, KP, MODE, CHECK, BF>(a, w, nw, smem);
+    spmm_body<float, KP, MODE, CHECK, BF>(a, rank, nw, smem);
     __syncthreads();
   }
 }
@@ -1722,12 +1734,15 @@ __global__ void __launch_bounds__((Cfg<float, KP>::WPB * 64)) batch_dense_kernel
   extern __shared__ __align__(16) unsigned char smem[];
   const int x = blockIdx.x & 7;
   const int w = blockIdx.x >> 3;
+  int base = 0;
   for (int i = b.xoff[x]; i < b.xoff[x + 1]; ++i) {
     const BatchGraph& d = b.graphs[b.xlist[i]];
     const int nw = batch_graph_workers(d.ntiles, Cfg<float, KP>::WPB, b.tpw, b.workers);
-    if (w >= nw || *d.active == 0) continue;
+    const int rank = batch_worker_rank(w, base, b.workers);
+    base = (base + nw) % b.workers;
+    if (rank >= nw || *d.active == 0) continue;
     const PassArgs a = batch_pass_args(b, d);
-    dense_body<float, KP, MODE>(a, w, nw, smem);
+    dense_body<float, KP, MODE>(a, rank, nw, smem);
     __syncthreads();
   }
 }

@@ -98,6 +98,7 @@ _SIGS = {
     "ofm_batch_destroy": (_I, [_P]),
     "ofm_batch_solve": (_I, [_P, _P, _P, _P]),
     "ofm_batch_schedule": (_I, [_P, _P, _P, _P]),
+    "ofm_batch_phases": (_I, [_P, _P, _P]),
     "ofm_row_normalize": (_I, [_I64, _I, _I, _P, _P, _P]),
     "ofm_kmeans_assign": (_I, [_I64, _I, _I, _P, _P, _P, _P, _P]),
     "ofm_kmeans": (_I, [_I64, _I, _I, _P, _P, _I, _P, _P, _P, _P]),
@@ -383,11 +384,19 @@ class Batch:
         candidate, graphs finished in FP64) of the last solve."""
         tpw = ctypes.c_int()
         esc = ctypes.c_int()
-        ms = np.zeros(3)
+        ms = np.zeros(4)
         _check(self._lib.ofm_batch_schedule(self.handle, ctypes.byref(tpw),
                                             ms.ctypes.data_as(ctypes.c_void_p), ctypes.byref(esc)),
                "ofm_batch_schedule")
         return tpw.value, ms, esc.value
+
+    def phases(self):
+        """(lockstep FP32 loop ms, FP64 finishing ms) of the last solve (host time)."""
+        a = ctypes.c_double()
+        b = ctypes.c_double()
+        _check(self._lib.ofm_batch_phases(self.handle, ctypes.byref(a), ctypes.byref(b)),
+               "ofm_batch_phases")
+        return a.value, b.value
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -35,7 +35,7 @@ class StreamingSolver:
 
     def __init__(self, k: int, variant="f1", precision=ofm.OFM_FP32, tol: float = 1e-4,
                  check_every: int = 10, max_iter: int = 5000, graph: bool = True,
-                 restart: bool = False, seed: int = 4):
+                 restart: bool = False, recur: bool = False, seed: int = 4):
         self.k = k
         self.variant = variant
         self.precision = precision
@@ -44,6 +44,7 @@ class StreamingSolver:
         self.max_iter = max_iter
         self.graph = graph
         self.restart = restart
+        self.recur = recur
         self.seed = seed
         self.X = None
         self.stage = 0
@@ -82,7 +83,8 @@ class StreamingSolver:
         X = self.initial_block(n, self.X if warm else None)
         ws = ofm.Workspace(lap, self.k, variant=self.variant, precision=self.precision,
                            max_iter=self.max_iter, check_every=self.check_every,
-                           tol=self.tol, graph=self.graph, restart=self.restart)
+                           tol=self.tol, graph=self.graph, restart=self.restart,
+                           recur=self.recur)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         st = ws.solve(X)

@@ -1,0 +1,167 @@
+"""Edge cases of the method and of the tiling, through the C ABI, against the
+FP64 oracle and the dense eigendecomposition:
+
+* k = N (X square): the limits are the full decompositions of Theorems 1 and
+  3, and the Ritz residual is zero for any X of full rank, so the solve is run
+  for a fixed number of updates;
+* a disconnected graph (A has eigenvalue -2 once per component);
+* graphs smaller than one tile, and one row past a tile;
+* weighted similarities;
+* a step before the set-up step is refused."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ofm_oracle as O
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def csr(n, edges, weights=None):
+    u = np.array([a for a, b in edges] + [b for a, b in edges], dtype=np.int64)
+    v = np.array([b for a, b in edges] + [a for a, b in edges], dtype=np.int64)
+    w = None if weights is None else np.concatenate([weights, weights])
+    order = np.lexsort((v, u))
+    u, v = u[order], v[order]
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, u + 1, 1)
+    rp = np.cumsum(rp).astype(np.int32)
+    return rp, v.astype(np.int32), (None if w is None else w[order])
+
+
+def cycle_edges(n, off=0):
+    return [(off + i, off + (i + 1) % n) for i in range(n)]
+
+
+def x0_for(n, k, seed):
+    return np.random.default_rng(seed).standard_normal((n, k)) / np.sqrt(n)
+
+
+def run_fixed(ofm, lap, x0, variant, iters, precision=None, restart=False):
+    precision = ofm.OFM_FP64 if precision is None else precision
+    dt = torch.float64 if precision == ofm.OFM_FP64 else torch.float32
+    ws = ofm.Workspace(lap, x0.shape[1], variant=variant, precision=precision, max_iter=iters,
+                       check_every=1000000, tol=0.0, restart=restart)
+    X = torch.as_tensor(x0, dtype=dt).cuda()
+    st = ws.solve(X)
+    assert st["iters"] == iters and st["status"] == 0, st
+    return host(X)
+
+
+@pytest.mark.parametrize("variant", ["f1", "f2"])
+def test_k_equals_n(lib, variant):
+    # an odd cycle with a chord: connected and not bipartite, so every
+    # eigenvalue of A lies in [-2, 0)
+    from paper_2305_10356_amd import ofm
+    n = 8
+    rp, ci, _ = csr(n, cycle_edges(7) + [(7, 0), (7, 3)])
+    lap = ofm.Laplacian(rp, ci)
+    olap = O.laplacian(n, rp, ci)
+    A = O.dense_A(olap)
+    assert np.linalg.eigvalsh(A).max() < -1e-3
+    X = run_fixed(ofm, lap, x0_for(n, n, 3), variant, 300)
+    if variant == "f1":
+        # Theorem 1 with k = N: X X^T = -A
+        np.testing.assert_allclose(X @ X.T, -A, atol=1e-9)
+    else:
+        # Theorem 3 with k = N: X^T X = I
+        np.testing.assert_allclose(X.T @ X, np.eye(n), atol=1e-9)
+    # the Ritz residual vanishes for every full-rank square X
+    ws = ofm.Workspace(lap, n, variant=variant, precision=ofm.OFM_FP64)
+    r = ws.residual(torch.as_tensor(x0_for(n, n, 4)).cuda())
+    assert r["relres"] < 1e-6
+
+
+def test_disconnected_graph(lib):
+    # a 5-cycle and a 7-cycle: A has eigenvalue -2 twice, then the pair of the
+    # 7-cycle at -2 + (1 - cos(2 pi / 7)); the fifth eigenvalue is separated
+    from paper_2305_10356_amd import ofm
+    n, k = 12, 4
+    rp, ci, _ = csr(n, cycle_edges(5) + cycle_edges(7, 5))
+    lap = ofm.Laplacian(rp, ci)
+    olap = O.laplacian(n, rp, ci)
+    mu, U = O.dense_eigh(olap)
+    assert abs(mu[0]) < 1e-12 and abs(mu[1]) < 1e-12 and mu[4] - mu[3] > 0.1
+    for variant, restart in (("f1", False), ("f2", False), ("tri-f1", True)):
+        X = run_fixed(ofm, lap, x0_for(n, k, 5), variant, 400, restart=restart)
+        Uk = U[:, :k]
+        if variant in ("f1", "tri-f1"):
+            target = (Uk * (2.0 - mu[:k])[None, :]) @ Uk.T
+        else:
+            target = Uk @ Uk.T
+        np.testing.assert_allclose(X @ X.T, target, atol=1e-8, err_msg=variant)
+
+
+@pytest.mark.parametrize("n,k", [(5, 4), (16, 8), (17, 16), (33, 32)])
+def test_small_and_ragged_graphs(lib, n, k):
+    from paper_2305_10356_amd import ofm
+    rng = np.random.default_rng(n)
+    edges = cycle_edges(n) + [(int(a), int(b)) for a, b in rng.integers(0, n, size=(2 * n, 2))
+                              if a != b]
+    edges = list({(min(a, b), max(a, b)) for a, b in edges})
+    rp, ci, _ = csr(n, edges)
+    lap = ofm.Laplacian(rp, ci)
+    olap = O.laplacian(n, rp, ci)
+    x0 = x0_for(n, k, n + 1)
+    # one set-up step and a few loop steps, FP64 and FP32, against the oracle
+    for prec, dt, tol in ((ofm.OFM_FP64, torch.float64, 1e-10), (ofm.OFM_FP32, torch.float32, 1e-4)):
+        xs = x0 if dt == torch.float64 else x0.astype(np.float32).astype(np.float64)
+        ws = ofm.Workspace(lap, k, variant="f2", precision=prec, check_every=1000000)
+        X = torch.as_tensor(xs, dtype=dt).cuda()
+        ws.init(X)
+        st, _ = O.init(olap, xs, O.Options(variant=O.F2))
+        for _ in range(3):
+            ws.step(X)
+            st, _ = O.step(olap, st, O.Options(variant=O.F2))
+        err = np.abs(host(X) - st.X).max() / np.abs(st.X).max()
+        say(f"n={n} k={k} prec={prec}: err {err:.2e}")
+        assert err < tol
+
+
+def test_weighted_graph(lib):
+    from paper_2305_10356_amd import graphs, ofm
+    g, x0 = graphs.config_graph(1)
+    rng = np.random.default_rng(77)
+    # symmetric positive weights: one weight per undirected edge
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    key = np.minimum(rows, g.col_idx) * g.n + np.maximum(rows, g.col_idx)
+    uniq, inv = np.unique(key, return_inverse=True)
+    w = rng.uniform(0.1, 3.0, size=uniq.shape[0])[inv]
+    lap = ofm.Laplacian(g.row_ptr, g.col_idx, vals=w, validate=True)
+    olap = O.laplacian(g.n, g.row_ptr, g.col_idx, vals=w)
+    np.testing.assert_allclose(lap.info()["degrees"], olap.d, rtol=1e-14)
+    Z = rng.standard_normal((g.n, 8))
+    Y = host(lap.apply(torch.as_tensor(Z).cuda()))
+    np.testing.assert_allclose(Y, O.apply_A(olap, Z), rtol=0, atol=1e-13 * np.abs(Y).max())
+    X = run_fixed(ofm, lap, x0, "f1", 500)
+    mu, U = O.dense_eigh(olap)
+    Uk = U[:, :8]
+    np.testing.assert_allclose(X @ X.T, (Uk * (2.0 - mu[:8])[None, :]) @ Uk.T, atol=1e-6)
+
+
+def test_step_before_init_is_refused(lib):
+    from paper_2305_10356_amd import graphs, ofm
+    g, x0 = graphs.config_graph(1)
+    lap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    ws = ofm.Workspace(lap, 8, variant="f1", precision=ofm.OFM_FP64)
+    X = torch.as_tensor(x0).cuda()
+    with pytest.raises(ofm.OfmError) as e:
+        ws.step(X)
+    assert e.value.status == -1
+    # wrong dtype / shape are refused before anything is enqueued
+    with pytest.raises(ValueError):
+        ws.init(X.float())
+    with pytest.raises(ValueError):
+        ws.init(X[:, :4].contiguous())
