@@ -308,12 +308,15 @@ ofm_status ofm_objective(ofm_workspace ws, const void* X, double* f_out, void* g
 
 /*
  * Per-pass device timing with HIP events recorded on the caller's stream
- * around every kernel the workspace launches (off by default; recording adds
- * a few microseconds of host time per launch and nothing on the device).
- * Pass ids (OFM_PASS_*) index host_ms / host_count:
+ * around the kernels of the selected passes (off by default).  Each pair of
+ * events adds a few microseconds of host time and a short gap on the stream,
+ * so time only the passes of interest inside a measured loop.
+ * Pass ids (OFM_PASS_*) index host_ms / host_count; pass_mask bit i selects
+ * pass i, 0 turns timing off, OFM_TIMING_ALL selects every pass.
  */
 #define OFM_PASS_SPMM_X 0     /* A X with the fused direction epilogue        */
-#define OFM_PASS_G 1          /* direction pass of the f2 variants            */
+#define OFM_PASS_G 1          /* direction from a stored A X (f2 variants,
+                                 f1 variants with the recurrence)             */
 #define OFM_PASS_V 2          /* V = -G + V_prev diag(beta) and its products  */
 #define OFM_PASS_SPMM_V 3     /* A V with the line-search products            */
 #define OFM_PASS_LINESEARCH 4 /* cubic coefficients, roots, step sizes        */
@@ -322,7 +325,8 @@ ofm_status ofm_objective(ofm_workspace ws, const void* X, double* f_out, void* g
 #define OFM_PASS_RESIDUAL 7   /* residual and objective                       */
 #define OFM_PASS_OTHER 8      /* products of set-up calls                     */
 #define OFM_NUM_PASSES 9
-ofm_status ofm_set_timing(ofm_workspace ws, int enable);
+#define OFM_TIMING_ALL ((1u << OFM_NUM_PASSES) - 1u)
+ofm_status ofm_set_timing(ofm_workspace ws, unsigned pass_mask);
 /* Synchronizing: waits for the recorded events, adds the elapsed times (ms)
  * and launch counts since the last reset into host_ms[OFM_NUM_PASSES] and
  * host_count[OFM_NUM_PASSES]; reset != 0 clears the totals afterwards. */

@@ -135,7 +135,7 @@ struct ofm_workspace_s {
   const TileTable* tiles = nullptr;
   const void* pk = nullptr;
   // per-pass event timing
-  bool timing = false;
+  unsigned timing = 0;   // bit i: record events around the kernels of pass i
   struct Pending {
     int kind;
     hipEvent_t a, b;
@@ -162,7 +162,7 @@ hipEvent_t take_event(ofm_workspace ws) {
 // run one launch, bracketed by events when timing is on
 template <typename F>
 hipError_t timed(ofm_workspace ws, int kind, hipStream_t s, F&& launch) {
-  if (!ws->timing) return launch();
+  if (!((ws->timing >> kind) & 1u)) return launch();
   hipEvent_t a = take_event(ws), b = take_event(ws);
   if (!a || !b) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(a, s);
@@ -560,9 +560,9 @@ static hipError_t run_residual(ofm_workspace ws, hipStream_t s, bool may_freeze)
   });
 }
 
-extern "C" ofm_status ofm_set_timing(ofm_workspace ws, int enable) {
+extern "C" ofm_status ofm_set_timing(ofm_workspace ws, unsigned pass_mask) {
   if (!ws) return OFM_E_INVALID_ARG;
-  ws->timing = enable != 0;
+  ws->timing = pass_mask & OFM_TIMING_ALL;
   return OFM_OK;
 }
 
@@ -753,8 +753,8 @@ static ofm_status capture_chunk(ofm_workspace ws, void* X, hipGraphExec_t* out) 
   const int cur0 = ws->cur;
   const int64_t lc0 = ws->last_check;
   const bool axv0 = ws->ax_valid;
-  const bool timing = ws->timing;
-  ws->timing = false;
+  const unsigned timing = ws->timing;
+  ws->timing = 0;
   hipGraph_t g = nullptr;
   ofm_status st = OFM_OK;
   if (hipStreamBeginCapture(ws->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {

@@ -92,7 +92,7 @@ _SIGS = {
     "ofm_get_step_info": (_I, [_P, _P, _P, _P, _P, _P]),
     "ofm_get_products": (_I, [_P, _I, _P, _P]),
     "ofm_objective": (_I, [_P, _P, _P, _P, _P]),
-    "ofm_set_timing": (_I, [_P, _I]),
+    "ofm_set_timing": (_I, [_P, ctypes.c_uint]),
     "ofm_get_timing": (_I, [_P, _P, _P, _I]),
     "ofm_batch_create": (_I, [_I, _P, _P, ctypes.POINTER(Opts), ctypes.POINTER(_P)]),
     "ofm_batch_destroy": (_I, [_P]),
@@ -311,8 +311,17 @@ class Workspace:
 
     PASSES = ["spmm_x", "g", "v", "spmm_v", "linesearch", "update", "reduce", "residual", "other"]
 
-    def set_timing(self, enable: bool = True):
-        _check(self._lib.ofm_set_timing(self.handle, 1 if enable else 0), "ofm_set_timing")
+    def set_timing(self, enable=True):
+        """True: time every pass; False: off; a list of pass names: those only."""
+        if enable is True:
+            mask = (1 << len(self.PASSES)) - 1
+        elif not enable:
+            mask = 0
+        else:
+            mask = 0
+            for p in enable:
+                mask |= 1 << self.PASSES.index(p)
+        _check(self._lib.ofm_set_timing(self.handle, mask), "ofm_set_timing")
 
     def timing(self, reset: bool = True) -> dict:
         """{pass: (total ms, launches)} since the last reset (synchronizing)."""

@@ -165,3 +165,25 @@ def test_step_before_init_is_refused(lib):
         ws.init(X.float())
     with pytest.raises(ValueError):
         ws.init(X[:, :4].contiguous())
+
+
+def test_timing_mask_selects_passes(lib):
+    from paper_2305_10356_amd import graphs, ofm
+    g, x0 = graphs.config_graph(1)
+    lap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    ws = ofm.Workspace(lap, 8, variant="f1", precision=ofm.OFM_FP64)
+    X = torch.as_tensor(x0).cuda()
+    ws.init(X)
+    ws.timing(reset=True)
+    ws.set_timing(["spmm_x"])
+    for _ in range(3):
+        ws.step(X)
+    ws.set_timing(False)
+    t = ws.timing(reset=True)
+    assert t["spmm_x"][1] == 3 and t["spmm_x"][0] > 0
+    assert all(cnt == 0 for p, (ms, cnt) in t.items() if p != "spmm_x")
+    ws.set_timing(True)
+    ws.step(X)
+    ws.set_timing(False)
+    t = ws.timing(reset=True)
+    assert t["spmm_x"][1] == 1 and t["v"][1] == 1 and t["update"][1] == 1

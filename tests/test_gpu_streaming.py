@@ -78,14 +78,14 @@ def test_graph_replay_hits_max_iter_exactly(lib):
     np.testing.assert_array_equal(res[0], res[1])
 
 
-def _stream_case(variant, vid, prec, k, n_final, stages, tol):
+def _stream_case(variant, vid, prec, k, n_final, stages, tol, recur=False):
     from paper_2305_10356_amd import ofm
     from paper_2305_10356_amd.streaming import StreamingSolver
     gs = graphs.GrowthStream(n_final=n_final, stages=stages, k=k, dbar=20, r=0.3, seed=7)
     warm = StreamingSolver(k, variant=variant, precision=prec, tol=tol, check_every=5,
-                           max_iter=4000, graph=True, seed=7)
+                           max_iter=4000, graph=True, recur=recur, seed=7)
     cold = StreamingSolver(k, variant=variant, precision=prec, tol=tol, check_every=5,
-                           max_iter=4000, graph=True, seed=7)
+                           max_iter=4000, graph=True, recur=recur, seed=7)
     recs = []
     for s in range(stages):
         g = gs.snapshot(s)
@@ -127,9 +127,10 @@ def test_streaming_fp64_limits_match_dense_eigh(lib, variant, vid):
             assert rw["iters"] < rc["iters"], (rw, rc)
 
 
-def test_streaming_fp32_k64(lib):
+@pytest.mark.parametrize("recur", [False, True])
+def test_streaming_fp32_k64(lib, recur):
     from paper_2305_10356_amd import ofm
-    recs = _stream_case("f1", O.F1, ofm.OFM_FP32, 64, 90000, 3, 1e-4)
+    recs = _stream_case("f1", O.F1, ofm.OFM_FP32, 64, 90000, 3, 1e-4, recur=recur)
     warm_iters = [rw["iters"] for _, rw, _, _ in recs[1:]]
     cold_iters = [rc["iters"] for _, _, rc, _ in recs[1:]]
     say("warm", warm_iters, "cold", cold_iters)
