@@ -1,0 +1,86 @@
+"""Features and clusters of a converged FP32 solve against the FP64 oracle's own
+solve on an SBM of the 50,000-node recipe (lognormal block sizes, k = 32,
+mean degree 20, r = 0.4) at 20,000 nodes.  The iterates of the two runs part
+ways after a few dozen updates (the iteration is chaotic before it
+converges), so what is compared is what both converge to: the subspace
+(principal angles between span X_gpu and span X_oracle), the eigenvalues of
+X^T X (Theorem 1: they tend to -lambda_i), and the K-means labels
+(Algorithm 1 steps 4-5) against each other and against the planted
+partition."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ofm_oracle as O
+from paper_2305_10356_amd import graphs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def sin_angles(A, B):
+    Qa, _ = np.linalg.qr(A)
+    Qb, _ = np.linalg.qr(B)
+    s = np.clip(np.linalg.svd(Qa.T @ Qb, compute_uv=False), 0.0, 1.0)
+    return np.sqrt(1.0 - s ** 2)
+
+
+def test_c2_subspace_and_labels_vs_oracle(lib):
+    from paper_2305_10356_amd import ofm
+    g, x0 = graphs.config_graph(2, n=20000)
+    k = 32
+    olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
+    lap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    ws = ofm.Workspace(lap, k, variant="f1", precision=ofm.OFM_FP32, max_iter=2000,
+                       check_every=10, tol=1e-4)
+    X = torch.as_tensor(x0.astype(np.float32)).cuda()
+    st = ws.solve(X)
+    Xg = host(X)
+    rg = O.relres(olap, Xg)
+    # the oracle's run from the same (FP32-rounded) X0, until its own residual <= 1e-4
+    opts = O.Options(variant=O.F1)
+    s, _ = O.init(olap, x0.astype(np.float32).astype(np.float64), opts)
+    it = 1
+    while True:
+        s, _ = O.step(olap, s, opts)
+        it += 1
+        if it % 10 == 0 and O.relres(olap, s.X) <= 1e-4:
+            break
+        assert it < 2000
+    Xo = s.X
+    ro = O.relres(olap, Xo)
+    sa = sin_angles(Xg, Xo)
+    say(f"C2: gpu {st['iters']} updates relres {rg:.2e}; oracle {it} updates relres {ro:.2e}; "
+        f"max sin angle {sa.max():.2e}")
+    # both blocks span the invariant subspace up to their residuals; with the
+    # spectral gap of this graph that keeps every principal angle small
+    assert st["converged"] == 1 and rg <= 1.05e-4
+    assert sa.max() < 0.05
+    # Theorem 1: eig(X^T X) -> -lambda_i; both runs agree on them
+    eg = np.sort(np.linalg.eigvalsh(Xg.T @ Xg))
+    eo = np.sort(np.linalg.eigvalsh(Xo.T @ Xo))
+    np.testing.assert_allclose(eg, eo, rtol=1e-3, atol=1e-4)
+    # labels: device K-means on the device features vs oracle K-means on the
+    # oracle's features, same seeds of the k-means++ draws
+    Y = ofm.row_normalize(X)
+    u = O.kmeans_uniforms(0, k)
+    lab_g = ofm.kmeans(Y, k, u)[0].cpu().numpy()
+    Yo = O.row_normalize(Xo)
+    lab_o = O.kmeans_lloyd(Yo, O.kmeanspp_init(Yo, k, u))[0]
+    a_go = O.ari(lab_g, lab_o)
+    a_gt = O.ari(lab_g, g.labels)
+    a_ot = O.ari(lab_o, g.labels)
+    say(f"C2 labels: ARI gpu/oracle {a_go:.3f}, gpu/truth {a_gt:.3f}, oracle/truth {a_ot:.3f}")
+    assert a_go > 0.9
+    assert abs(a_gt - a_ot) < 0.05
