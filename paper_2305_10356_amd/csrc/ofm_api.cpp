@@ -122,7 +122,6 @@ struct ofm_workspace_s {
   double* sc = nullptr;
   double* partials = nullptr;
   double* lvl2 = nullptr;
-  int* tickets = nullptr;
   int* status = nullptr;
   int* frozen = nullptr;   // set on the device when the residual met tol
   // captured solve chunks (opts.graph): one per buffer parity at chunk start
@@ -435,7 +434,6 @@ static void free_ws(ofm_workspace ws) {
   dev_free(ws->sc);
   dev_free(ws->partials);
   dev_free(ws->lvl2);
-  dev_free(ws->tickets);
   dev_free(ws->status);
   dev_free(ws->frozen);
   delete ws;
@@ -492,11 +490,9 @@ extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_o
   if ((st = dev_alloc(&ws->sc, sc_total(k))) != OFM_OK) return fail(st);
   if ((st = dev_alloc(&ws->partials, (size_t)kMaxBlocks * nvmax)) != OFM_OK) return fail(st);
   if ((st = dev_alloc(&ws->lvl2, (size_t)ny * nvmax)) != OFM_OK) return fail(st);
-  if ((st = dev_alloc(&ws->tickets, (nvmax + 63) / 64)) != OFM_OK) return fail(st);
   if ((st = dev_alloc(&ws->status, 1)) != OFM_OK) return fail(st);
   if ((st = dev_alloc(&ws->frozen, 1)) != OFM_OK) return fail(st);
   if (hipMemset(ws->sc, 0, sc_total(k) * sizeof(double)) != hipSuccess ||
-      hipMemset(ws->tickets, 0, ((nvmax + 63) / 64) * sizeof(int)) != hipSuccess ||
       hipMemset(ws->status, 0, sizeof(int)) != hipSuccess ||
       hipMemset(ws->frozen, 0, sizeof(int)) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess)
@@ -533,7 +529,7 @@ static ofm_status finalize(ofm_workspace ws, const PassArgs& a, hipStream_t s) {
   double* out2 = split ? ws->sc + sc_off(ws->k).H : nullptr;
   HIPCHK(timed(ws, OFM_PASS_REDUCE, s, [&] {
     return launch_finalize(ws->partials, a.nblocks, a.nv, ws->sc + partial_off(ws->k, a.mode),
-                           ws->lvl2, ws->tickets, s, split ? kk : a.nv, out2);
+                           ws->lvl2, s, split ? kk : a.nv, out2);
   }));
   return OFM_OK;
 }

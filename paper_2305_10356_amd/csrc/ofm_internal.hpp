@@ -201,7 +201,7 @@ hipError_t launch_spmm(int precision, int k, PassArgs& a, hipStream_t s);
 hipError_t launch_dense(int precision, int k, PassArgs& a, hipStream_t s);
 // out[v] for v < split, out2[v - split] for v >= split (split = nv: one range)
 hipError_t launch_finalize(const double* partials, int nb, int nv, double* out, double* lvl2,
-                           int* tickets, hipStream_t s, int split, double* out2);
+                           hipStream_t s, int split, double* out2);
 hipError_t launch_linesearch(int k, int variant, int first, double alpha0, double* sc,
                              int* status, const int* frozen, hipStream_t s);
 hipError_t launch_residual(int k, int variant, double normA2, double* sc, int* status,

@@ -917,53 +917,50 @@ __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64)) dense_kernel(PassArgs 
 
 // ---------------------------------------------------------------------------
 // Deterministic two-level reduction of partial rows:
-// out[v] = sum_b partials[b][v], summed in block order.
+// out[v] = sum_b partials[b][v], summed in block order.  The first level sums
+// groups of kFinChunk rows into lvl2; the second, a launch of its own, sums the
+// groups in order.  Two launches instead of one with a last-block ticket: the
+// ticket needs a device-scope release in every block, and with one L2 per XCD
+// that costs a write-back of dirty L2 lines per block.
 // ---------------------------------------------------------------------------
 
+// v < split: out[v]; v >= split: out2[v - split]
+__device__ inline void finalize_store(double* out, double* out2, int split, int v, double x) {
+  if (v < split) out[v] = x;
+  else out2[v - split] = x;
+}
+
 __global__ void __launch_bounds__(64) finalize_kernel(const double* __restrict__ partials, int nb,
-                                                      int nv, double* __restrict__ out,
-                                                      double* lvl2, int* tickets, int split,
+                                                      int nv, double* __restrict__ lvl2,
+                                                      double* __restrict__ out, int split,
                                                       double* __restrict__ out2) {
-  // values v >= split go to the second range
-  if (blockIdx.x * 64 + threadIdx.x >= split) out = out2 - split;
-  const int cx = blockIdx.x;
-  const int cy = blockIdx.y;
-  const int ny = gridDim.y;
-  const int v = cx * 64 + threadIdx.x;
-  const int b0 = cy * kFinChunk;
-  // all loads of a level are issued before any addition; the sum then runs in
-  // block order
+  const int v = blockIdx.x * 64 + threadIdx.x;
+  const int b0 = blockIdx.y * kFinChunk;
+  if (v >= nv) return;
+  // all loads are issued before any addition; the sum then runs in block order
+  double x[kFinChunk];
+#pragma unroll
+  for (int b = 0; b < kFinChunk; ++b)
+    x[b] = (b0 + b < nb) ? partials[(size_t)(b0 + b) * nv + v] : 0.0;
   double s = 0.0;
-  if (v < nv) {
-    double x[kFinChunk];
 #pragma unroll
-    for (int b = 0; b < kFinChunk; ++b)
-      x[b] = (b0 + b < nb) ? partials[(size_t)(b0 + b) * nv + v] : 0.0;
+  for (int b = 0; b < kFinChunk; ++b) s += x[b];
+  if (gridDim.y == 1) finalize_store(out, out2, split, v, s);
+  else lvl2[(size_t)blockIdx.y * nv + v] = s;
+}
+
+__global__ void __launch_bounds__(64) finalize2_kernel(const double* __restrict__ lvl2, int ny,
+                                                       int nv, double* __restrict__ out, int split,
+                                                       double* __restrict__ out2) {
+  const int v = blockIdx.x * 64 + threadIdx.x;
+  if (v >= nv) return;
+  double x[kMaxBlocks / kFinChunk];
 #pragma unroll
-    for (int b = 0; b < kFinChunk; ++b) s += x[b];
-  }
-  if (ny == 1) {
-    if (v < nv) out[v] = s;
-    return;
-  }
-  if (v < nv) lvl2[(size_t)cy * nv + v] = s;
-  __threadfence();
-  __shared__ int last;
-  if (threadIdx.x == 0) last = (atomicAdd(&tickets[cx], 1) == ny - 1);
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  if (v < nv) {
-    double x[kMaxBlocks / kFinChunk];
+  for (int y = 0; y < kMaxBlocks / kFinChunk; ++y) x[y] = (y < ny) ? lvl2[(size_t)y * nv + v] : 0.0;
+  double t = 0.0;
 #pragma unroll
-    for (int y = 0; y < kMaxBlocks / kFinChunk; ++y)
-      x[y] = (y < ny) ? lvl2[(size_t)y * nv + v] : 0.0;
-    double t = 0.0;
-#pragma unroll
-    for (int y = 0; y < kMaxBlocks / kFinChunk; ++y) t += x[y];
-    out[v] = t;
-  }
-  if (threadIdx.x == 0) atomicExch(&tickets[cx], 0);
+  for (int y = 0; y < kMaxBlocks / kFinChunk; ++y) t += x[y];
+  finalize_store(out, out2, split, v, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -1560,15 +1557,20 @@ hipError_t launch_dense(int precision, int k, PassArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_finalize(const double* partials, int nb, int nv, double* out, double* lvl2,
-                           int* tickets, hipStream_t s, int split, double* out2) {
+                           hipStream_t s, int split, double* out2) {
   const int ny = (nb + kFinChunk - 1) / kFinChunk;
-  dim3 grid((nv + 63) / 64, ny);
   if (split >= nv || !out2) {
     split = nv;
     out2 = out;
   }
-  hipLaunchKernelGGL(finalize_kernel, grid, dim3(64), 0, s, partials, nb, nv, out, lvl2, tickets,
+  const int nx = (nv + 63) / 64;
+  hipLaunchKernelGGL(finalize_kernel, dim3(nx, ny), dim3(64), 0, s, partials, nb, nv, lvl2, out,
                      split, out2);
+  if (ny > 1) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(finalize2_kernel, dim3(nx), dim3(64), 0, s, lvl2, ny, nv, out, split, out2);
+  }
   return hipGetLastError();
 }
 

@@ -11,6 +11,14 @@ still describe the kernels it runs.
 
     python -m paper_2305_10356_amd.profiling traffic <fetch.csv> <write.csv> [<l2.csv>]
 
+    python -m paper_2305_10356_amd.profiling mfma <mfma.csv>
+
+``mfma`` reads SQ_INSTS_VALU_MFMA_MOPS_F64/_F32 (units of 512 flops),
+SQ_VALU_MFMA_BUSY_CYCLES (summed over SIMDs) and GRBM_GUI_ACTIVE (summed over
+the 8 XCDs) per dispatch and prints, per kernel, the matrix-core flops per
+launch, their rate over the dispatch time and the matrix-core busy fraction
+busy / (GUI_ACTIVE / 8 x 1024 SIMDs).
+
 ``traffic`` scales FETCH_SIZE and WRITE_SIZE (KiB per dispatch) by what the
 same counters read for the 256 MiB device copy of ``bench.py
 --copy-calibration`` and prints bytes per launch for the passes of one f1 step
@@ -112,6 +120,29 @@ def traffic(fetch_csv, write_csv, l2_csv=None, passes=F1_PASSES):
     return sf, sw, rows
 
 
+def mfma(path):
+    rows = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            key = (row["Kernel_Name"], row["Dispatch_Id"])
+            d = rows.setdefault(key, {"ns": int(row["End_Timestamp"]) - int(row["Start_Timestamp"])})
+            d[row["Counter_Name"]] = float(row["Counter_Value"])
+    per = defaultdict(list)
+    for (kern, _), d in rows.items():
+        per[kern].append(d)
+    out = []
+    for kern, ds in sorted(per.items()):
+        n = len(ds)
+        f64 = sum(d.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) for d in ds) * 512 / n
+        f32 = sum(d.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) for d in ds) * 512 / n
+        ns = sum(d["ns"] for d in ds) / n
+        busy = sum(d.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) for d in ds) / n
+        gui = sum(d.get("GRBM_GUI_ACTIVE", 0.0) for d in ds) / n
+        util = busy / (gui / 8.0 * 1024.0) if gui > 0 else 0.0
+        out.append((kern, n, ns, f64, f32, util))
+    return out
+
+
 def main(argv):
     if len(argv) >= 1 and argv[0] == "source-hash":
         print(source_hash())
@@ -129,6 +160,16 @@ def main(argv):
         print()
         for name, _, _, _, b, _ in rows:
             print(f"    traffic_bytes {name} {int(round(b))}")
+        return 0
+    if len(argv) >= 2 and argv[0] == "mfma":
+        print("| kernel | launches | us/launch | F64 MFMA GFLOP | F32 MFMA GFLOP | TFLOP/s | busy |")
+        print("|:--|--:|--:|--:|--:|--:|--:|")
+        for kern, n, ns, f64, f32, util in mfma(argv[1]):
+            if f64 + f32 == 0:
+                continue
+            k = kern.replace("void ofm::", "").replace("(ofm::PassArgs)", "")
+            print(f"| {k} | {n} | {ns / 1e3:.1f} | {f64 / 1e9:.2f} | {f32 / 1e9:.2f} | "
+                  f"{(f64 + f32) / ns / 1e3:.1f} | {100 * util:.1f}% |")
         return 0
     if len(argv) >= 2 and argv[0] == "counters":
         res = counter_means(argv[1:])
