@@ -1056,7 +1056,7 @@ extern "C" ofm_status ofm_kmeans(int64_t n, int dim, int n_clusters, const float
 namespace {
 
 constexpr int kBatchCand = 4;
-constexpr int kBatchWorkers = 128;                 // blocks per XCD
+constexpr int kBatchWorkers = kBatchMaxWorkers;    // blocks per XCD
 const int kBatchTpw[kBatchCand] = {2, 4, 8, 16};  // candidate tiles per wavefront
 
 struct BatchGroup {
@@ -1073,6 +1073,7 @@ struct BatchGroup {
   int* stalled = nullptr;               // [n]
   double* sc = nullptr;                 // [n][SC total]
   double* partials = nullptr;
+  double* lvl2 = nullptr;               // [n][workers / kFinChunk][nvmax]
   char* bufs = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t ev = nullptr;
@@ -1112,6 +1113,7 @@ static void free_batch(ofm_batch b) {
     dev_free(g.stalled);
     dev_free(g.sc);
     dev_free(g.partials);
+    dev_free(g.lvl2);
     dev_free(g.bufs);
     if (g.stream) (void)hipStreamDestroy(g.stream);
     if (g.ev) (void)hipEventDestroy(g.ev);
@@ -1213,6 +1215,8 @@ extern "C" ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps
     if ((st = dev_alloc(&g.stalled, n)) != OFM_OK) return fail(st);
     if ((st = dev_alloc(&g.sc, (size_t)n * sct)) != OFM_OK) return fail(st);
     if ((st = dev_alloc(&g.partials, part_total)) != OFM_OK) return fail(st);
+    const size_t lvl2_per = (size_t)((kBatchWorkers + kFinChunk - 1) / kFinChunk) * nvmax;
+    if ((st = dev_alloc(&g.lvl2, (size_t)n * lvl2_per)) != OFM_OK) return fail(st);
     if ((st = dev_alloc(&g.bufs, buf_total)) != OFM_OK) return fail(st);
     if (hipMemset(g.sc, 0, (size_t)n * sct * sizeof(double)) != hipSuccess) return fail(OFM_E_HIP);
     g.hg.resize(n);
@@ -1240,6 +1244,7 @@ extern "C" ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps
       d.Vb = bf ? q + blk / 2 : nullptr;
       d.sc = g.sc + (size_t)m * sct;
       d.partials = g.partials + part_off[m];
+      d.lvl2 = g.lvl2 + (size_t)m * lvl2_per;
       d.status = g.status + m;
       d.active = g.active + m;
       d.done_iter = g.done + m;

@@ -160,6 +160,7 @@ struct BatchGraph {
   void* Vb = nullptr;
   double* sc = nullptr;
   double* partials = nullptr;  // [nblk][nv]
+  double* lvl2 = nullptr;      // [workers / kFinChunk][nv] group sums of the partial rows
   int* status = nullptr;
   int* active = nullptr;       // 1 while the graph iterates
   int64_t* done_iter = nullptr;  // iteration whose X met the tolerance (-1: none)
@@ -168,6 +169,7 @@ struct BatchGraph {
   double normA2 = 0.0;
 };
 constexpr int kBatchHist = 10;   // checks compared by the stall test
+constexpr int kBatchMaxWorkers = 128;  // workgroups per XCD in a batched pass
 struct BatchArgs {
   const BatchGraph* graphs = nullptr;
   const int* xlist = nullptr;  // graphs ordered by XCD

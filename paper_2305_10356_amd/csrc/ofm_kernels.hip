@@ -1749,7 +1749,17 @@ __global__ void __launch_bounds__((Cfg<float, KP>::WPB * 64)) batch_dense_kernel
   }
 }
 
-// per-graph sum of its block partial rows, in block order
+// Per-graph sum of its block partial rows, in block order: rows are summed in
+// groups of kFinChunk (blockIdx.z = group); with more than one group the group
+// sums go to the graph's lvl2 rows and batch_finalize2_kernel adds them in
+// order, which keeps several waves per graph in flight.
+template <int KP>
+__device__ inline void batch_store(const BatchArgs& b, const BatchGraph& d, int v, double s) {
+  // the update of the recurrence writes [M | H]: H goes to its own slot
+  const int split = (b.mode == kUpdateR && (b.flags & kFlagH)) ? KP * KP : b.nv;
+  d.sc[v < split ? b.off + v : SC<KP>::H + (v - split)] = s;
+}
+
 template <int KP>
 __global__ void __launch_bounds__(64) batch_finalize_kernel(BatchArgs b) {
   const BatchGraph& d = b.graphs[blockIdx.y];
@@ -1757,18 +1767,37 @@ __global__ void __launch_bounds__(64) batch_finalize_kernel(BatchArgs b) {
   const int v = blockIdx.x * 64 + threadIdx.x;
   if (v >= b.nv) return;
   const int nw = batch_graph_workers(d.ntiles, Cfg<float, KP>::WPB, b.tpw, b.workers);
+  const int ng = (nw + kFinChunk - 1) / kFinChunk;
+  const int b0 = blockIdx.z * kFinChunk;
+  if (b0 >= nw) return;
+  double x[kFinChunk];
+#pragma unroll
+  for (int q = 0; q < kFinChunk; ++q)
+    x[q] = (b0 + q < nw) ? d.partials[(size_t)(b0 + q) * b.nv + v] : 0.0;
   double s = 0.0;
-  for (int b0 = 0; b0 < nw; b0 += kFinChunk) {
-    double x[kFinChunk];
 #pragma unroll
-    for (int q = 0; q < kFinChunk; ++q)
-      x[q] = (b0 + q < nw) ? d.partials[(size_t)(b0 + q) * b.nv + v] : 0.0;
+  for (int q = 0; q < kFinChunk; ++q) s += x[q];
+  if (ng == 1) batch_store<KP>(b, d, v, s);
+  else d.lvl2[(size_t)blockIdx.z * b.nv + v] = s;
+}
+
+template <int KP>
+__global__ void __launch_bounds__(64) batch_finalize2_kernel(BatchArgs b) {
+  const BatchGraph& d = b.graphs[blockIdx.y];
+  if (*d.active == 0) return;
+  const int v = blockIdx.x * 64 + threadIdx.x;
+  if (v >= b.nv) return;
+  const int nw = batch_graph_workers(d.ntiles, Cfg<float, KP>::WPB, b.tpw, b.workers);
+  const int ng = (nw + kFinChunk - 1) / kFinChunk;
+  if (ng == 1) return;
+  constexpr int G = (kBatchMaxWorkers + kFinChunk - 1) / kFinChunk;
+  double x[G];
 #pragma unroll
-    for (int q = 0; q < kFinChunk; ++q) s += x[q];
-  }
-  // the update of the recurrence writes [M | H]: H goes to its own slot
-  const int split = (b.mode == kUpdateR && (b.flags & kFlagH)) ? KP * KP : b.nv;
-  d.sc[v < split ? b.off + v : SC<KP>::H + (v - split)] = s;
+  for (int y = 0; y < G; ++y) x[y] = (y < ng) ? d.lvl2[(size_t)y * b.nv + v] : 0.0;
+  double s = 0.0;
+#pragma unroll
+  for (int y = 0; y < G; ++y) s += x[y];
+  batch_store<KP>(b, d, v, s);
 }
 
 template <int KP>
@@ -1882,15 +1911,22 @@ hipError_t launch_batch_dense(int k, BatchArgs& b, int grid, hipStream_t s) {
 
 hipError_t launch_batch_finalize(BatchArgs& b, hipStream_t s) {
   if (b.nv == 0) return hipSuccess;
-  const dim3 grid((b.nv + 63) / 64, b.ngraphs);
+  const int groups = (b.workers + kFinChunk - 1) / kFinChunk;
+  const dim3 grid((b.nv + 63) / 64, b.ngraphs, groups);
+  const dim3 grid2((b.nv + 63) / 64, b.ngraphs);
+#define OFM_BFIN(KP)                                                                        \
+  hipLaunchKernelGGL(batch_finalize_kernel<KP>, grid, dim3(64), 0, s, b);                  \
+  if (groups > 1) hipLaunchKernelGGL(batch_finalize2_kernel<KP>, grid2, dim3(64), 0, s, b); \
+  break;
   switch (b.k) {
-    case 4: hipLaunchKernelGGL(batch_finalize_kernel<4>, grid, dim3(64), 0, s, b); break;
-    case 8: hipLaunchKernelGGL(batch_finalize_kernel<8>, grid, dim3(64), 0, s, b); break;
-    case 16: hipLaunchKernelGGL(batch_finalize_kernel<16>, grid, dim3(64), 0, s, b); break;
-    case 32: hipLaunchKernelGGL(batch_finalize_kernel<32>, grid, dim3(64), 0, s, b); break;
-    case 64: hipLaunchKernelGGL(batch_finalize_kernel<64>, grid, dim3(64), 0, s, b); break;
+    case 4: OFM_BFIN(4)
+    case 8: OFM_BFIN(8)
+    case 16: OFM_BFIN(16)
+    case 32: OFM_BFIN(32)
+    case 64: OFM_BFIN(64)
     default: return hipErrorInvalidValue;
   }
+#undef OFM_BFIN
   return hipGetLastError();
 }
 
