@@ -17,8 +17,9 @@
  * - Dense feature blocks (X, Z, Y, V, G) are N x k, row-major (C-contiguous),
  *   FP64 for OFM_FP64 and FP32 for OFM_FP32.  Supported widths:
  *   k in {4, 8, 16, 32, 64}.  (Zero columns are fixed points of every
- *   variant and never influence the other columns, so a block of another
- *   width can be zero-padded to the next supported one.)
+ *   variant and never influence the other columns, and the residual leaves
+ *   exactly zero columns out, so a block of another width can be zero-padded
+ *   to the next supported one.)
  * - Graph indices are int32 (nnz < 2^31).
  * - All work is enqueued on the given HIP stream (0 = null stream) and is
  *   asynchronous unless the comment says "synchronizing".  No entry point

@@ -1296,6 +1296,10 @@ __device__ __forceinline__ void residual_body(int variant, double normA2, double
   for (int e = tid; e < KK; e += 256) L[e] = M[e];
   if (tid == 0) fail = 0;
   __syncthreads();
+  // an exactly zero column of X (a zero-padded width) has a zero row and
+  // column in M, H and K; a unit pivot there leaves it out of both traces
+  if (tid < KP && L[tid * KP + tid] == 0.0) L[tid * KP + tid] = 1.0;
+  __syncthreads();
   // Cholesky M = L L^T (lower triangle of L), column by column
   for (int c = 0; c < KP; ++c) {
     if (tid == 0) {

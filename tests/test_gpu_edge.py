@@ -187,3 +187,32 @@ def test_timing_mask_selects_passes(lib):
     ws.set_timing(False)
     t = ws.timing(reset=True)
     assert t["spmm_x"][1] == 1 and t["v"][1] == 1 and t["update"][1] == 1
+
+
+@pytest.mark.parametrize("variant,vid", [("f1", O.F1), ("tri-f1", O.TRI_F1), ("f2", O.F2),
+                                         ("tri-f2", O.TRI_F2)])
+def test_zero_padded_width(lib, variant, vid):
+    # k = 5 run as k = 8 with three zero columns: the first five columns follow
+    # the oracle's k = 5 iteration, the padding stays zero, and the residual is
+    # that of the five columns
+    from paper_2305_10356_amd import graphs, ofm
+    g, x0 = graphs.config_graph(1)
+    lap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
+    x5 = x0[:, :5].copy()
+    xp = np.zeros((g.n, 8))
+    xp[:, :5] = x5
+    ws = ofm.Workspace(lap, 8, variant=variant, precision=ofm.OFM_FP64, check_every=1000000)
+    X = torch.as_tensor(xp).cuda()
+    ws.init(X)
+    st, _ = O.init(olap, x5, O.Options(variant=vid))
+    for _ in range(12):
+        ws.step(X)
+        st, _ = O.step(olap, st, O.Options(variant=vid))
+    Xh = host(X)
+    assert np.all(Xh[:, 5:] == 0.0)
+    err = np.abs(Xh[:, :5] - st.X).max() / np.abs(st.X).max()
+    assert err < 1e-10, err
+    r = ws.residual(X)
+    assert r["status"] == 0
+    assert r["relres"] == pytest.approx(O.relres(olap, st.X), rel=1e-6)
