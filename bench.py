@@ -68,16 +68,31 @@ def cpu_baseline(g, x0, k: int, variant_id: int):
     t0 = time.perf_counter()
     lap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     x = x0.astype(np.float32).astype(np.float64)
-    opts = O.Options(variant=variant_id)
+    # the triangular variants run with the descent restart, as on the device
+    opts = O.Options(variant=variant_id, restart=O.is_tri(variant_id))
     t1 = time.perf_counter()
     st, _ = O.init(lap, x, opts)
     st, _ = O.step(lap, st, opts)
     t2 = time.perf_counter()
+    cpu_baseline.last_x = st.X
     return {"value": 2.0 / (t2 - t1), "unit": "iters/s", "cores": int(threads),
             "kind": "oracle",
             "sample": (f"2 X updates (Algorithm 2 set-up step + 1 loop step) of the same workload, "
                        f"FP64 NumPy/SciPy; {t2 - t1:.1f} s, plus {t1 - t0:.1f} s Laplacian set-up; "
                        f"SciPy CSR x dense runs on 1 thread, dense products on {threads} BLAS threads")}
+
+
+def read_clocks():
+    """GPU clocks as rocm-smi reports them (clocks are not pinned here)."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True,
+                           timeout=20)
+        d = json.loads(r.stdout)
+        card = d[sorted(d)[0]]
+        return {k: v for k, v in card.items() if "clock" in k.lower()}
+    except Exception:
+        return None
 
 
 def batched_vs_plain(variant: str, count: int = 256, plain: bool = True):
@@ -200,7 +215,7 @@ def spmm_locality_ladder(g, k: int = 32, windows=(32768, 262144, None), reps: in
 
 
 def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10,
-                 cold_stages=(9,), recur: bool = False):
+                 cold_stages=(9,), recur: bool = False, check_every: int = 10):
     """Growth stream of 10 snapshots, N = 200k .. 2M, k = 64, mean degree 20,
     r = 0.3: each stage solved to residual 1e-4 (checked every 10 iterations)
     in FP32 from the previous stage's solution (new rows N(0, 1/N_s)), with
@@ -214,7 +229,7 @@ def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10
     log(f"growth stream generated in {time.perf_counter() - t:.1f} s")
     tri = variant.startswith("tri")
     warm = StreamingSolver(64, variant=variant, precision=ofm.OFM_FP32, tol=1e-4,
-                           check_every=10, max_iter=5000, graph=True, restart=tri,
+                           check_every=check_every, max_iter=5000, graph=True, restart=tri,
                            recur=recur, seed=4)
     stages_out = []
     for s in range(stages):
@@ -222,8 +237,8 @@ def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10
         rec = warm.solve_stage(g.row_ptr, g.col_idx, warm=True)
         if s in cold_stages:
             cold = StreamingSolver(64, variant=variant, precision=ofm.OFM_FP32, tol=1e-4,
-                                   check_every=10, max_iter=5000, graph=True, restart=tri,
-                                   recur=recur, seed=4)
+                                   check_every=check_every, max_iter=5000, graph=True,
+                                   restart=tri, recur=recur, seed=4)
             cold.stage = s
             rc = cold.solve_stage(g.row_ptr, g.col_idx, warm=False)
             rec["cold_iters"] = rc["iters"]
@@ -240,6 +255,7 @@ def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10
                     f"mean-degree 20 r=0.3, FP32, graph-replayed loop, tol 1e-4",
         "variant": variant,
         "recur_ax": recur,
+        "check_every": check_every,
         "total_solve_s": round(sum(r["solve_s"] for r in stages_out), 4),
         "all_converged": all(r["converged"] == 1 for r in stages_out),
         "stages": stages_out,
@@ -506,6 +522,21 @@ def main():
         from oracle import ofm_oracle as O
         vid = {"f1": O.F1, "tri-f1": O.TRI_F1, "f2": O.F2, "tri-f2": O.TRI_F2}[args.variant]
         cpu = cpu_baseline(g, x0, k, vid)
+        # the error of the device path against the oracle on the same two
+        # updates, per precision
+        xo = cpu_baseline.last_x
+        prec_err = {}
+        for name, prec in (("fp32", ofm.OFM_FP32), ("fp64", ofm.OFM_FP64)):
+            w8, X8 = make(args.variant, prec)
+            if prec == ofm.OFM_FP64:
+                X8.copy_(torch.as_tensor(x0.astype(np.float32).astype(np.float64)))
+            w8.init(X8)
+            w8.step(X8)
+            xg = X8.cpu().numpy().astype(np.float64)
+            prec_err[name] = float(np.abs(xg - xo).max() / np.abs(xo).max())
+            w8.close()
+            del X8
+        cpu["device_vs_oracle_rel_err"] = prec_err
 
     out = {
         "metric": METRIC,
@@ -527,6 +558,7 @@ def main():
         "cpu_baseline": cpu,
         "passes": passes,
         "relres_last_check": stats["relres"],
+        "clocks": read_clocks(),
         "extras": extras,
     }
     print(json.dumps(out), flush=True)
