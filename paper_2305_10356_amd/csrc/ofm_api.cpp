@@ -1322,9 +1322,7 @@ static ofm_status bpass(BatchGroup& g, BatchArgs base, int mode, int flags, bool
   a.flags = flags;
   a.nv = partial_nv(g.k, mode, flags);
   a.off = partial_off(g.k, mode);
-  const int grid = 8 * a.workers;
-  HIPCHK(spmm ? launch_batch_spmm(g.k, a, grid, g.stream)
-              : launch_batch_dense(g.k, a, grid, g.stream));
+  HIPCHK(spmm ? launch_batch_spmm(g.k, a, g.stream) : launch_batch_dense(g.k, a, g.stream));
   HIPCHK(launch_batch_finalize(a, g.stream));
   return OFM_OK;
 }

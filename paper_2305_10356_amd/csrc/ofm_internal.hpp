@@ -190,8 +190,8 @@ struct BatchArgs {
   int nv = 0;
   int off = 0;       // first scalar slot the mode's products go to
 };
-hipError_t launch_batch_spmm(int k, BatchArgs& b, int grid, hipStream_t s);
-hipError_t launch_batch_dense(int k, BatchArgs& b, int grid, hipStream_t s);
+hipError_t launch_batch_spmm(int k, BatchArgs& b, hipStream_t s);
+hipError_t launch_batch_dense(int k, BatchArgs& b, hipStream_t s);
 hipError_t launch_batch_finalize(BatchArgs& b, hipStream_t s);
 hipError_t launch_batch_linesearch(int k, BatchArgs& b, double alpha0, int first_fixed,
                                    hipStream_t s);

@@ -1464,18 +1464,39 @@ int partial_off(int k, int mode) {
   return 0;
 }
 
+// Workgroups of a kernel the chip holds at once (occupancy x CUs), taken at
+// its first launch.  The passes are grid-stride loops with equal work per
+// workgroup, so a grid that is not a whole number of such rounds ends with a
+// short round at low occupancy; launch_rounded trims the grid to whole rounds.
+template <auto Kernel>
+static int resident_blocks(int threads, int smem) {
+  static const int cap = [&] {
+    int occ = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, Kernel, threads, smem) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 0;
+    return occ * cus;
+  }();
+  return cap;
+}
+
+template <auto Kernel>
+static hipError_t launch_rounded(PassArgs& a, int threads, int smem, hipStream_t s) {
+  const int cap = resident_blocks<Kernel>(threads, smem);
+  if (cap > 0 && a.nblocks > cap) a.nblocks = (a.nblocks / cap) * cap;
+  hipLaunchKernelGGL(Kernel, dim3(a.nblocks), dim3(threads), smem, s, a);
+  return hipGetLastError();
+}
+
 template <typename T, int KP, int MODE, bool BF>
 static hipError_t spmm_mode_bf(PassArgs& a, hipStream_t s) {
   using SM = Smem<T, KP, MODE>;
   // the k x k products of the residual (X^T A X, (AX)^T (AX)) are compiled in
   // only for the iterations that check it
   if ((MODE == kGF1 || MODE == kAXF2) && (a.flags & kFlagCheck))
-    hipLaunchKernelGGL((spmm_kernel<T, KP, MODE, true, BF>), dim3(a.nblocks), dim3(SM::WPB * 64),
-                       SM::bytes, s, a);
-  else
-    hipLaunchKernelGGL((spmm_kernel<T, KP, MODE, false, BF>), dim3(a.nblocks),
-                       dim3(SM::WPB * 64), SM::bytes, s, a);
-  return hipGetLastError();
+    return launch_rounded<spmm_kernel<T, KP, MODE, true, BF>>(a, SM::WPB * 64, SM::bytes, s);
+  return launch_rounded<spmm_kernel<T, KP, MODE, false, BF>>(a, SM::WPB * 64, SM::bytes, s);
 }
 
 template <typename T, int KP, int MODE>
@@ -1501,9 +1522,7 @@ static hipError_t spmm_t(PassArgs& a, hipStream_t s) {
 template <typename T, int KP, int MODE>
 static hipError_t dense_mode(PassArgs& a, hipStream_t s) {
   using SM = Smem<T, KP, MODE>;
-  hipLaunchKernelGGL((dense_kernel<T, KP, MODE>), dim3(a.nblocks), dim3(SM::WPB * 64),
-                     SM::bytes, s, a);
-  return hipGetLastError();
+  return launch_rounded<dense_kernel<T, KP, MODE>>(a, SM::WPB * 64, SM::bytes, s);
 }
 
 template <typename T, int KP>
@@ -1839,24 +1858,30 @@ __global__ void __launch_bounds__(256) batch_residual_kernel(BatchArgs b) {
   }
 }
 
+// A batched pass runs 8 x workers workgroups; workers is trimmed so that the
+// whole grid is resident at once (the per-graph loops give workgroups unequal
+// work, so a second round would mostly run at low occupancy).  The reduction
+// of the pass reads b.workers, so it sees the trimmed value.
+template <auto Kernel>
+static hipError_t launch_batch(BatchArgs& b, int threads, int smem, hipStream_t s) {
+  const int cap = resident_blocks<Kernel>(threads, smem);
+  if (cap >= 8 && b.workers > cap / 8) b.workers = cap / 8;
+  hipLaunchKernelGGL(Kernel, dim3(8 * b.workers), dim3(threads), smem, s, b);
+  return hipGetLastError();
+}
+
 template <int KP>
-static hipError_t batch_spmm_t(BatchArgs& b, int grid, hipStream_t s) {
+static hipError_t batch_spmm_t(BatchArgs& b, hipStream_t s) {
   const bool chk = (b.flags & kFlagCheck) != 0;
-#define OFM_BSPMM(MODE)                                                                      \
-  {                                                                                          \
-    using SM = Smem<float, KP, MODE>;                                                        \
-    if (b.bf16) {                                                                            \
-      if (chk) hipLaunchKernelGGL((batch_spmm_kernel<KP, MODE, true, true>), dim3(grid),      \
-                                  dim3(SM::WPB * 64), SM::bytes, s, b);                      \
-      else hipLaunchKernelGGL((batch_spmm_kernel<KP, MODE, false, true>), dim3(grid),         \
-                              dim3(SM::WPB * 64), SM::bytes, s, b);                          \
-    } else {                                                                                 \
-      if (chk) hipLaunchKernelGGL((batch_spmm_kernel<KP, MODE, true, false>), dim3(grid),     \
-                                  dim3(SM::WPB * 64), SM::bytes, s, b);                      \
-      else hipLaunchKernelGGL((batch_spmm_kernel<KP, MODE, false, false>), dim3(grid),        \
-                              dim3(SM::WPB * 64), SM::bytes, s, b);                          \
-    }                                                                                        \
-    return hipGetLastError();                                                                \
+#define OFM_BSPMM(MODE)                                                                         \
+  {                                                                                             \
+    using SM = Smem<float, KP, MODE>;                                                           \
+    constexpr int T = SM::WPB * 64;                                                             \
+    if (b.bf16)                                                                                 \
+      return chk ? launch_batch<batch_spmm_kernel<KP, MODE, true, true>>(b, T, SM::bytes, s)   \
+                 : launch_batch<batch_spmm_kernel<KP, MODE, false, true>>(b, T, SM::bytes, s); \
+    return chk ? launch_batch<batch_spmm_kernel<KP, MODE, true, false>>(b, T, SM::bytes, s)    \
+               : launch_batch<batch_spmm_kernel<KP, MODE, false, false>>(b, T, SM::bytes, s);  \
   }
   switch (b.mode) {
     case kGF1: OFM_BSPMM(kGF1)
@@ -1869,13 +1894,11 @@ static hipError_t batch_spmm_t(BatchArgs& b, int grid, hipStream_t s) {
 }
 
 template <int KP>
-static hipError_t batch_dense_t(BatchArgs& b, int grid, hipStream_t s) {
-#define OFM_BDENSE(MODE)                                                                   \
-  {                                                                                        \
-    using SM = Smem<float, KP, MODE>;                                                      \
-    hipLaunchKernelGGL((batch_dense_kernel<KP, MODE>), dim3(grid), dim3(SM::WPB * 64),      \
-                       SM::bytes, s, b);                                                   \
-    return hipGetLastError();                                                              \
+static hipError_t batch_dense_t(BatchArgs& b, hipStream_t s) {
+#define OFM_BDENSE(MODE)                                                                  \
+  {                                                                                       \
+    using SM = Smem<float, KP, MODE>;                                                     \
+    return launch_batch<batch_dense_kernel<KP, MODE>>(b, SM::WPB * 64, SM::bytes, s);    \
   }
   switch (b.mode) {
     case kGPassF2: OFM_BDENSE(kGPassF2)
@@ -1891,24 +1914,24 @@ static hipError_t batch_dense_t(BatchArgs& b, int grid, hipStream_t s) {
 
 int batch_wpb(int k) { return wpb(OFM_FP32, k); }
 
-hipError_t launch_batch_spmm(int k, BatchArgs& b, int grid, hipStream_t s) {
+hipError_t launch_batch_spmm(int k, BatchArgs& b, hipStream_t s) {
   switch (k) {
-    case 4: return batch_spmm_t<4>(b, grid, s);
-    case 8: return batch_spmm_t<8>(b, grid, s);
-    case 16: return batch_spmm_t<16>(b, grid, s);
-    case 32: return batch_spmm_t<32>(b, grid, s);
-    case 64: return batch_spmm_t<64>(b, grid, s);
+    case 4: return batch_spmm_t<4>(b, s);
+    case 8: return batch_spmm_t<8>(b, s);
+    case 16: return batch_spmm_t<16>(b, s);
+    case 32: return batch_spmm_t<32>(b, s);
+    case 64: return batch_spmm_t<64>(b, s);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch_dense(int k, BatchArgs& b, int grid, hipStream_t s) {
+hipError_t launch_batch_dense(int k, BatchArgs& b, hipStream_t s) {
   switch (k) {
-    case 4: return batch_dense_t<4>(b, grid, s);
-    case 8: return batch_dense_t<8>(b, grid, s);
-    case 16: return batch_dense_t<16>(b, grid, s);
-    case 32: return batch_dense_t<32>(b, grid, s);
-    case 64: return batch_dense_t<64>(b, grid, s);
+    case 4: return batch_dense_t<4>(b, s);
+    case 8: return batch_dense_t<8>(b, s);
+    case 16: return batch_dense_t<16>(b, s);
+    case 32: return batch_dense_t<32>(b, s);
+    case 64: return batch_dense_t<64>(b, s);
   }
   return hipErrorInvalidValue;
 }
