@@ -273,7 +273,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-only", action="store_true",
-                    help="run only the batched solve (no plain loop, no C3 run); prints its JSON")
+                    help="run only the batched solve (no plain loop, no 2M-node run); prints its JSON")
     ap.add_argument("--no-streaming", action="store_true")
     ap.add_argument("--recur", action="store_true",
                     help="headline loop with A X by recurrence between residual checks")
@@ -303,7 +303,7 @@ def main():
     k = 32
     log("generating graph ...")
     t = time.perf_counter()
-    g, x0 = graphs.config_graph(3, n=args.n)
+    g, x0 = graphs.workload("dcsbm-n2m-k32", n=args.n)
     gstats = g.stats()
     log(f"graph: {gstats} in {time.perf_counter() - t:.1f} s")
     n, nnz = g.n, g.nnz

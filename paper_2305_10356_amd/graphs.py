@@ -37,7 +37,7 @@ __all__ = [
     "Graph",
     "sbm_plain",
     "dcsbm_powerlaw",
-    "config_graph",
+    "workload",
     "initial_x",
     "dirichlet_sizes",
     "lognormal_sizes",
@@ -387,43 +387,46 @@ def initial_x(n: int, k: int, rng: np.random.Generator) -> np.ndarray:
 # named workloads
 # ----------------------------------------------------------------------------
 
-CONFIGS = {
-    1: dict(name="sbm-n1000-k8-fp64", n=1000, k=8, dbar=16.0, r=0.3),
-    2: dict(name="sbm-n50k-k32", n=50_000, k=32, dbar=20.0, r=0.4),
-    3: dict(name="dcsbm-n2m-k32-pl2.5", n=2_000_000, k=32, dbar=25.0, r=0.5),
+WORKLOADS = {
+    # name: recipe; `seed` keys the graph stream ([seed, 1]) and X0 ([seed, 2])
+    "sbm-n1000-k8": dict(n=1000, k=8, dbar=16.0, r=0.3, seed=1),
+    "sbm-n50k-k32": dict(n=50_000, k=32, dbar=20.0, r=0.4, seed=2),
+    "dcsbm-n2m-k32": dict(n=2_000_000, k=32, dbar=25.0, r=0.5, seed=3),
 }
 
 
-def config_graph(cfg: int, n: Optional[int] = None):
+def workload(name: str, n: Optional[int] = None):
     """Graph and X0 of a named workload.
 
-    cfg 1: N=1000, k=8, Dirichlet(2) sizes (min 50), mean degree 16, r=0.3;
-           X0 from default_rng(0).
-    cfg 2: N=50,000, k=32, LogNormal(0, 0.5) sizes, mean degree 20, r=0.4.
-    cfg 3: N=2,000,000, k=32 equal blocks, degree-corrected power law 2.5,
-           mean degree 25, r=0.5.
+    sbm-n1000-k8:  N=1000, k=8, Dirichlet(2) sizes (min 50), mean degree 16,
+                   r=0.3; X0 from default_rng(0).
+    sbm-n50k-k32:  N=50,000, k=32, LogNormal(0, 0.5) sizes, mean degree 20,
+                   r=0.4.
+    dcsbm-n2m-k32: N=2,000,000, k=32 equal blocks, degree-corrected power law
+                   2.5, mean degree 25, r=0.5.
     ``n`` overrides N (same recipe at another size, for quick tests).
     Returns (graph, X0 float64 [n, k]).
     """
-    spec = CONFIGS[cfg]
+    if name not in WORKLOADS:
+        raise ValueError(f"unknown workload {name}")
+    spec = WORKLOADS[name]
     nn = int(n if n is not None else spec["n"])
     k = spec["k"]
-    grng = np.random.default_rng([cfg, 1])
-    if cfg == 1:
+    seed = spec["seed"]
+    grng = np.random.default_rng([seed, 1])
+    if name == "sbm-n1000-k8":
         sizes = dirichlet_sizes(nn, k, grng, 2.0, min(50, nn // (2 * k)))
         g = sbm_plain(sizes, spec["dbar"], spec["r"], grng)
         xrng = np.random.default_rng(0)
-    elif cfg == 2:
+    elif name == "sbm-n50k-k32":
         sizes = lognormal_sizes(nn, k, grng, 0.5)
         g = sbm_plain(sizes, spec["dbar"], spec["r"], grng)
-        xrng = np.random.default_rng([cfg, 2])
-    elif cfg == 3:
+        xrng = np.random.default_rng([seed, 2])
+    else:
         sizes = equal_sizes(nn, k)
         g = dcsbm_powerlaw(sizes, spec["dbar"], spec["r"], grng, 2.5)
-        xrng = np.random.default_rng([cfg, 2])
-    else:
-        raise ValueError(f"unknown workload {cfg}")
-    g.meta["workload"] = spec["name"] if n is None else f"{spec['name']}@n{nn}"
+        xrng = np.random.default_rng([seed, 2])
+    g.meta["workload"] = name if n is None else f"{name}@n{nn}"
     return g, initial_x(nn, k, xrng)
 
 

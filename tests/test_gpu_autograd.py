@@ -13,7 +13,7 @@ torch = pytest.importorskip("torch")
 
 @pytest.fixture(scope="module")
 def sub500(lib):
-    g, _ = graphs.config_graph(2)
+    g, _ = graphs.workload("sbm-n50k-k32")
     sub = graphs.bfs_ball_subgraph(g, 500, np.random.default_rng(17))
     return sub, O.laplacian(sub.n, sub.row_ptr, sub.col_idx)
 
@@ -67,9 +67,9 @@ def test_gradcheck_small(sub500):
     assert torch.autograd.gradcheck(obj, (x,), eps=1e-6, atol=1e-6, rtol=1e-5, fast_mode=True)
 
 
-def test_fp32_gradient_c2():
+def test_fp32_gradient_sbm50k():
     from paper_2305_10356_amd import autograd, ofm
-    g, x0 = graphs.config_graph(2)
+    g, x0 = graphs.workload("sbm-n50k-k32")
     olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     lap = ofm.Laplacian(g.row_ptr, g.col_idx)
     x32 = x0.astype(np.float32)

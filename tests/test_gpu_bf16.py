@@ -29,7 +29,7 @@ def test_bf16_rounding_helper():
 @pytest.mark.parametrize("k", [8, 32])
 def test_bf16_gather_exact(lib, k):
     from paper_2305_10356_amd import ofm
-    g, _ = graphs.config_graph(3, n=30000)
+    g, _ = graphs.workload("dcsbm-n2m-k32", n=30000)
     olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     lap = ofm.Laplacian(g.row_ptr, g.col_idx)
     x32 = graphs.initial_x(g.n, k, np.random.default_rng([11, k])).astype(np.float32)
@@ -47,7 +47,7 @@ def test_bf16_gather_exact(lib, k):
 
 def test_bf16_solve_floor_and_labels(lib):
     from paper_2305_10356_amd import ofm
-    g, x0 = graphs.config_graph(2)
+    g, x0 = graphs.workload("sbm-n50k-k32")
     lap = ofm.Laplacian(g.row_ptr, g.col_idx)
     labels = {}
     for prec in (ofm.OFM_FP32, ofm.OFM_FP32_BF16X):

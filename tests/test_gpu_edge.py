@@ -132,7 +132,7 @@ def test_small_and_ragged_graphs(lib, n, k):
 
 def test_weighted_graph(lib):
     from paper_2305_10356_amd import graphs, ofm
-    g, x0 = graphs.config_graph(1)
+    g, x0 = graphs.workload("sbm-n1000-k8")
     rng = np.random.default_rng(77)
     # symmetric positive weights: one weight per undirected edge
     rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
@@ -153,7 +153,7 @@ def test_weighted_graph(lib):
 
 def test_step_before_init_is_refused(lib):
     from paper_2305_10356_amd import graphs, ofm
-    g, x0 = graphs.config_graph(1)
+    g, x0 = graphs.workload("sbm-n1000-k8")
     lap = ofm.Laplacian(g.row_ptr, g.col_idx)
     ws = ofm.Workspace(lap, 8, variant="f1", precision=ofm.OFM_FP64)
     X = torch.as_tensor(x0).cuda()
@@ -169,7 +169,7 @@ def test_step_before_init_is_refused(lib):
 
 def test_timing_mask_selects_passes(lib):
     from paper_2305_10356_amd import graphs, ofm
-    g, x0 = graphs.config_graph(1)
+    g, x0 = graphs.workload("sbm-n1000-k8")
     lap = ofm.Laplacian(g.row_ptr, g.col_idx)
     ws = ofm.Workspace(lap, 8, variant="f1", precision=ofm.OFM_FP64)
     X = torch.as_tensor(x0).cuda()
@@ -196,7 +196,7 @@ def test_zero_padded_width(lib, variant, vid):
     # the oracle's k = 5 iteration, the padding stays zero, and the residual is
     # that of the five columns
     from paper_2305_10356_amd import graphs, ofm
-    g, x0 = graphs.config_graph(1)
+    g, x0 = graphs.workload("sbm-n1000-k8")
     lap = ofm.Laplacian(g.row_ptr, g.col_idx)
     olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     x5 = x0[:, :5].copy()

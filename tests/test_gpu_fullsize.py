@@ -26,10 +26,10 @@ def host(t):
 
 
 @pytest.fixture(scope="module")
-def c3(lib):
+def dcsbm2m(lib):
     from paper_2305_10356_amd import ofm
     say("generating the 2M-node graph")
-    g, x0 = graphs.config_graph(3)
+    g, x0 = graphs.workload("dcsbm-n2m-k32")
     lap = ofm.Laplacian(g.row_ptr, g.col_idx)
     return g, x0, lap
 
@@ -52,9 +52,9 @@ def oracle_rows(g, dinv, Z, rows):
     return out
 
 
-def test_c3_spmm_sampled_rows(c3):
+def test_dcsbm2m_spmm_sampled_rows(dcsbm2m):
     from paper_2305_10356_amd import ofm
-    g, _, lap = c3
+    g, _, lap = dcsbm2m
     rng = np.random.default_rng(31)
     Z32 = rng.standard_normal((g.n, 32)).astype(np.float32)
     Y = host(lap.apply(torch.as_tensor(Z32).cuda()))
@@ -62,16 +62,16 @@ def test_c3_spmm_sampled_rows(c3):
     rows = sample_rows(g, 4096, rng)
     ref = oracle_rows(g, dinv, Z32.astype(np.float64), rows)
     err = np.abs(Y[rows] - ref).max() / np.abs(ref).max()
-    say(f"C3 SpMM sampled rows: {rows.shape[0]} rows, rel err {err:.2e}")
+    say(f"2M-node SpMM sampled rows: {rows.shape[0]} rows, rel err {err:.2e}")
     assert err < 1e-6
 
 
-def test_c3_first_updates_fp32_vs_oracle(c3):
+def test_dcsbm2m_first_updates_fp32_vs_oracle(dcsbm2m):
     """The set-up update and one loop update of OFM-f1 in the benchmark's
     configuration (FP32 passes, FP64 products) against the FP64 oracle run from
     the FP32-rounded X0."""
     from paper_2305_10356_amd import ofm
-    g, x0, lap = c3
+    g, x0, lap = dcsbm2m
     ws = ofm.Workspace(lap, 32, variant="f1", precision=ofm.OFM_FP32, check_every=10)
     X = torch.as_tensor(x0.astype(np.float32)).cuda()
     x = host(X)
@@ -85,7 +85,7 @@ def test_c3_first_updates_fp32_vs_oracle(c3):
     gi = ws.step_info()
     st2, info2 = O.step(olap, st, opts)
     e2 = np.abs(host(X) - st2.X).max() / np.abs(st2.X).max()
-    say(f"C3 f1 FP32: X1 err {e1:.2e} alpha {a1[0]:.6e}/{info['alpha'][0]:.6e}; "
+    say(f"2M-node f1 FP32: X1 err {e1:.2e} alpha {a1[0]:.6e}/{info['alpha'][0]:.6e}; "
         f"X2 err {e2:.2e} alpha {gi['alpha'][0]:.6e}/{info2['alpha'][0]:.6e}")
     assert e1 < 1e-5 and e2 < 1e-4
     assert a1[0] == pytest.approx(info["alpha"][0], rel=1e-4)
@@ -93,9 +93,9 @@ def test_c3_first_updates_fp32_vs_oracle(c3):
     np.testing.assert_allclose(gi["beta"], info2["beta"], rtol=1e-3, atol=1e-6)
 
 
-def test_c3_solve_residual(c3):
+def test_dcsbm2m_solve_residual(dcsbm2m):
     from paper_2305_10356_amd import ofm
-    g, x0, lap = c3
+    g, x0, lap = dcsbm2m
     for recur in (False, True):
         ws = ofm.Workspace(lap, 32, variant="f1", precision=ofm.OFM_FP32, check_every=10,
                            tol=1e-4, max_iter=3000, recur=recur)
@@ -103,12 +103,12 @@ def test_c3_solve_residual(c3):
         st = ws.solve(X)
         olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
         rr = O.relres(olap, host(X))
-        say(f"C3 solve recur={recur}: iters {st['iters']} relres {st['relres']:.3e} oracle {rr:.3e}")
+        say(f"2M-node solve recur={recur}: iters {st['iters']} relres {st['relres']:.3e} oracle {rr:.3e}")
         assert st["converged"] == 1
         assert rr == pytest.approx(st["relres"], rel=0.02)
 
 
-def test_c4_stream_last_stage_residual(lib):
+def test_growth_stream_2m_last_stage_residual(lib):
     from paper_2305_10356_amd import ofm
     from paper_2305_10356_amd.streaming import StreamingSolver
     gs = graphs.GrowthStream(n_final=2_000_000, stages=10, k=64, dbar=20, r=0.3, seed=4)
@@ -117,7 +117,7 @@ def test_c4_stream_last_stage_residual(lib):
     for s in range(gs.stages):
         g = gs.snapshot(s)
         rec = sv.solve_stage(g.row_ptr, g.col_idx)
-        say(f"C4 stage {s}: n {rec['n']} iters {rec['iters']} relres {rec['relres']:.2e}")
+        say(f"growth stream stage {s}: n {rec['n']} iters {rec['iters']} relres {rec['relres']:.2e}")
         assert rec["converged"] == 1
     olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     rr = O.relres(olap, host(sv.X))
@@ -125,7 +125,7 @@ def test_c4_stream_last_stage_residual(lib):
 
 
 @pytest.mark.parametrize("recur", [False, True])
-def test_c5_batch_residuals(lib, recur):
+def test_batch_256_residuals(lib, recur):
     from paper_2305_10356_amd import ofm
     specs = graphs.batched_graph_specs(256)
     gl = [graphs.batched_graph(sp) for sp in specs]

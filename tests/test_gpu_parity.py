@@ -47,14 +47,14 @@ def rel(a, b):
 
 
 @pytest.fixture(scope="module")
-def c1():
-    g, x0 = graphs.config_graph(1)
+def sbm1k():
+    g, x0 = graphs.workload("sbm-n1000-k8")
     return g, x0, O.laplacian(g.n, g.row_ptr, g.col_idx)
 
 
 @pytest.fixture(scope="module")
-def c1_lap(ofm, c1):
-    g, x0, _ = c1
+def sbm1k_lap(ofm, sbm1k):
+    g, x0, _ = sbm1k
     return ofm.Laplacian(g.row_ptr, g.col_idx)
 
 
@@ -84,9 +84,9 @@ def hub_graph(n=3000, seed=3):
 # Laplacian and A Z
 # ---------------------------------------------------------------------------
 
-def test_laplacian_info(ofm, c1, c1_lap):
-    g, x0, lap = c1
-    info = c1_lap.info()
+def test_laplacian_info(ofm, sbm1k, sbm1k_lap):
+    g, x0, lap = sbm1k
+    info = sbm1k_lap.info()
     np.testing.assert_array_equal(info["degrees"], lap.d)
     assert info["normA2"] == pytest.approx(O.norm_A_fro_sq(lap), rel=1e-12)
 
@@ -95,9 +95,9 @@ def test_laplacian_info(ofm, c1, c1_lap):
 @pytest.mark.parametrize("k", [4, 8, 16, 32, 64])
 def test_apply_A_graphs(ofm, k, reorder):
     cases = []
-    g, _ = graphs.config_graph(1)
+    g, _ = graphs.workload("sbm-n1000-k8")
     cases.append(("sbm1000", g.row_ptr, g.col_idx))
-    g3, _ = graphs.config_graph(3, n=20000)
+    g3, _ = graphs.workload("dcsbm-n2m-k32", n=20000)
     cases.append(("dcsbm20000", g3.row_ptr, g3.col_idx))
     rp, ci = hub_graph()
     cases.append(("hub3000", rp, ci))
@@ -142,12 +142,12 @@ def test_laplacian_errors(ofm):
     np.testing.assert_allclose(lap.info()["degrees"], [2.0, 5.0, 3.0])
 
 
-def test_workspace_shape_errors(ofm, c1_lap):
+def test_workspace_shape_errors(ofm, sbm1k_lap):
     with pytest.raises(ofm.OfmError) as e:
-        ofm.Workspace(c1_lap, 5)
+        ofm.Workspace(sbm1k_lap, 5)
     assert e.value.status == -2
     with pytest.raises(ofm.OfmError) as e:
-        ofm.Workspace(c1_lap, 64, precision=ofm.OFM_FP64)
+        ofm.Workspace(sbm1k_lap, 64, precision=ofm.OFM_FP64)
     assert e.value.status == -8
 
 
@@ -226,38 +226,38 @@ def teacher_forced(ofm, glap, olap, x0, variant, vid, precision, checkpoints, to
 
 
 @pytest.mark.parametrize("variant,vid", VARS)
-def test_teacher_forced_fp64_c1(ofm, c1, c1_lap, variant, vid):
+def test_teacher_forced_fp64_sbm1k(ofm, sbm1k, sbm1k_lap, variant, vid):
     # 500 iterations; the triangular variants run with the descent restart:
     # without it their CG direction can grow without bound once a column has
     # converged (beta = ratio of rounding-level norms), and no two
     # implementations agree there
-    g, x0, olap = c1
-    say(f"teacher-forced FP64 C1 {variant}")
-    teacher_forced(ofm, c1_lap, olap, x0, variant, vid, ofm.OFM_FP64,
+    g, x0, olap = sbm1k
+    say(f"teacher-forced FP64 1k-node SBM {variant}")
+    teacher_forced(ofm, sbm1k_lap, olap, x0, variant, vid, ofm.OFM_FP64,
                    {1, 2, 5, 10, 20, 50, 100, 200, 499}, 1e-10, restart=O.is_tri(vid))
 
 
 @pytest.mark.parametrize("variant,vid", VARS[1::2])
-def test_teacher_forced_fp64_c1_literal_tri(ofm, c1, c1_lap, variant, vid):
+def test_teacher_forced_fp64_sbm1k_literal_tri(ofm, sbm1k, sbm1k_lap, variant, vid):
     # the triangular variants exactly as printed (no restart), early window
-    g, x0, olap = c1
-    teacher_forced(ofm, c1_lap, olap, x0, variant, vid, ofm.OFM_FP64, {1, 2, 5, 10, 20, 40},
+    g, x0, olap = sbm1k
+    teacher_forced(ofm, sbm1k_lap, olap, x0, variant, vid, ofm.OFM_FP64, {1, 2, 5, 10, 20, 40},
                    1e-10, restart=False)
 
 
 @pytest.mark.parametrize("variant,vid", VARS)
-def test_teacher_forced_fp32_c2(ofm, variant, vid):
-    g, x0 = graphs.config_graph(2)
+def test_teacher_forced_fp32_sbm50k(ofm, variant, vid):
+    g, x0 = graphs.workload("sbm-n50k-k32")
     olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     glap = ofm.Laplacian(g.row_ptr, g.col_idx)
-    say(f"teacher-forced FP32 C2 {variant}")
+    say(f"teacher-forced FP32 50k-node SBM {variant}")
     teacher_forced(ofm, glap, olap, x0, variant, vid, ofm.OFM_FP32, {1, 2, 5, 10, 20, 40}, 1e-4,
                    restart=O.is_tri(vid))
 
 
 @pytest.mark.parametrize("k", [4, 16, 64])
 def test_teacher_forced_fp32_widths(ofm, k):
-    g, _ = graphs.config_graph(3, n=20000)
+    g, _ = graphs.workload("dcsbm-n2m-k32", n=20000)
     x0 = graphs.initial_x(g.n, k, np.random.default_rng([9, k]))
     olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     glap = ofm.Laplacian(g.row_ptr, g.col_idx)
@@ -268,7 +268,7 @@ def test_teacher_forced_fp32_widths(ofm, k):
 
 @pytest.mark.parametrize("k", [4, 16, 32])
 def test_teacher_forced_fp64_widths(ofm, k):
-    g, _ = graphs.config_graph(3, n=8000)
+    g, _ = graphs.workload("dcsbm-n2m-k32", n=8000)
     x0 = graphs.initial_x(g.n, k, np.random.default_rng([8, k]))
     olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     glap = ofm.Laplacian(g.row_ptr, g.col_idx)
@@ -278,9 +278,9 @@ def test_teacher_forced_fp64_widths(ofm, k):
 
 
 @pytest.mark.parametrize("variant,vid", VARS)
-def test_free_running_window_fp64(ofm, c1, c1_lap, variant, vid):
-    g, x0, olap = c1
-    ws = ofm.Workspace(c1_lap, 8, variant=variant, precision=ofm.OFM_FP64, check_every=1000000)
+def test_free_running_window_fp64(ofm, sbm1k, sbm1k_lap, variant, vid):
+    g, x0, olap = sbm1k
+    ws = ofm.Workspace(sbm1k_lap, 8, variant=variant, precision=ofm.OFM_FP64, check_every=1000000)
     X = dev(x0, torch.float64)
     ws.init(X)
     st, _ = O.init(olap, x0, O.Options(variant=vid))
@@ -292,9 +292,9 @@ def test_free_running_window_fp64(ofm, c1, c1_lap, variant, vid):
     assert err < 1e-10
 
 
-def test_first_step_fixed(ofm, c1, c1_lap):
-    g, x0, olap = c1
-    ws = ofm.Workspace(c1_lap, 8, variant="f1", precision=ofm.OFM_FP64, first_step=1, alpha0=0.05)
+def test_first_step_fixed(ofm, sbm1k, sbm1k_lap):
+    g, x0, olap = sbm1k
+    ws = ofm.Workspace(sbm1k_lap, 8, variant="f1", precision=ofm.OFM_FP64, first_step=1, alpha0=0.05)
     X = dev(x0, torch.float64)
     ws.init(X)
     st, _ = O.init(olap, x0, O.Options(variant=O.F1, first_step="fixed", alpha0=0.05))
@@ -306,12 +306,12 @@ def test_first_step_fixed(ofm, c1, c1_lap):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("variant,vid", VARS)
-def test_solve_limits_fp64_c1(ofm, c1, c1_lap, variant, vid):
-    g, x0, olap = c1
+def test_solve_limits_fp64_sbm1k(ofm, sbm1k, sbm1k_lap, variant, vid):
+    g, x0, olap = sbm1k
     mu, U = O.dense_eigh(olap)
     k = 8
     restart = O.is_tri(vid)
-    ws = ofm.Workspace(c1_lap, k, variant=variant, precision=ofm.OFM_FP64, max_iter=500,
+    ws = ofm.Workspace(sbm1k_lap, k, variant=variant, precision=ofm.OFM_FP64, max_iter=500,
                        check_every=10, tol=1e-9, restart=restart)
     X = dev(x0, torch.float64)
     st = ws.solve(X)
@@ -338,20 +338,20 @@ def test_solve_limits_fp64_c1(ofm, c1, c1_lap, variant, vid):
     assert O.ari(lab_g.cpu().numpy(), g.labels) > 0.7
 
 
-def test_residual_matches_oracle(ofm, c1, c1_lap):
-    g, x0, olap = c1
-    ws = ofm.Workspace(c1_lap, 8, variant="f2", precision=ofm.OFM_FP64)
+def test_residual_matches_oracle(ofm, sbm1k, sbm1k_lap):
+    g, x0, olap = sbm1k
+    ws = ofm.Workspace(sbm1k_lap, 8, variant="f2", precision=ofm.OFM_FP64)
     for X in (x0, O.run(olap, x0, 15, O.Options(variant=O.F2))[0].X):
         r = ws.residual(dev(X, torch.float64))
         assert r["relres"] == pytest.approx(O.relres(olap, X), rel=1e-9)
         assert r["objective"] == pytest.approx(O.objective(O.F2, olap, X), rel=1e-12)
-    ws1 = ofm.Workspace(c1_lap, 8, variant="f1", precision=ofm.OFM_FP64)
+    ws1 = ofm.Workspace(sbm1k_lap, 8, variant="f1", precision=ofm.OFM_FP64)
     r = ws1.residual(dev(x0, torch.float64))
     assert r["objective"] == pytest.approx(O.objective(O.F1, olap, x0), rel=1e-12)
 
 
-def test_solve_fp32_c2_reaches_tolerance(ofm):
-    g, x0 = graphs.config_graph(2)
+def test_solve_fp32_sbm50k_reaches_tolerance(ofm):
+    g, x0 = graphs.workload("sbm-n50k-k32")
     glap = ofm.Laplacian(g.row_ptr, g.col_idx)
     olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     ws = ofm.Workspace(glap, 32, variant="f1", precision=ofm.OFM_FP32, max_iter=2000,
@@ -359,23 +359,23 @@ def test_solve_fp32_c2_reaches_tolerance(ofm):
     X = dev(x0.astype(np.float32), torch.float32)
     st = ws.solve(X)
     rr = O.relres(olap, host(X))
-    say(f"C2 FP32 f1: iters={st['iters']} relres gpu={st['relres']:.2e} oracle(final X)={rr:.2e}")
+    say(f"50k-node SBM FP32 f1: iters={st['iters']} relres gpu={st['relres']:.2e} oracle(final X)={rr:.2e}")
     assert st["converged"] == 1
     assert rr < 2e-4
 
 
-def test_nonfinite_input_is_reported(ofm, c1, c1_lap):
-    g, x0, olap = c1
+def test_nonfinite_input_is_reported(ofm, sbm1k, sbm1k_lap):
+    g, x0, olap = sbm1k
     x = x0.copy()
     x[3, 2] = np.nan
-    ws = ofm.Workspace(c1_lap, 8, variant="f1", precision=ofm.OFM_FP64, max_iter=5, check_every=1)
+    ws = ofm.Workspace(sbm1k_lap, 8, variant="f1", precision=ofm.OFM_FP64, max_iter=5, check_every=1)
     st = ws.solve(dev(x, torch.float64))
     assert st["status"] == -4
     assert st["iters"] <= 2
 
 
 def test_determinism_fp32(ofm):
-    g, x0 = graphs.config_graph(3, n=40000)
+    g, x0 = graphs.workload("dcsbm-n2m-k32", n=40000)
     glap = ofm.Laplacian(g.row_ptr, g.col_idx)
     x0 = graphs.initial_x(g.n, 32, np.random.default_rng(4)).astype(np.float32)
     outs = []
@@ -433,7 +433,7 @@ def test_kmeans_matches_oracle_on_blobs(ofm):
 def test_products_match_oracle(ofm, k, dt):
     # k x k products of one init step: X^T X of the new X; V^T V, X^T V of the
     # first direction; X^T A V, V^T A V (f2) -- each against a plain product
-    g, _ = graphs.config_graph(3, n=6000)
+    g, _ = graphs.workload("dcsbm-n2m-k32", n=6000)
     olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     glap = ofm.Laplacian(g.row_ptr, g.col_idx)
     x0 = graphs.initial_x(g.n, k, np.random.default_rng([7, k]))
@@ -456,12 +456,12 @@ def test_products_match_oracle(ofm, k, dt):
     assert rel(ws.product("H"), X0.T @ O.apply_A(olap, X0)) < tol * 10
 
 
-def test_solve_returns_the_iterate_it_reports(ofm, c1, c1_lap):
+def test_solve_returns_the_iterate_it_reports(ofm, sbm1k, sbm1k_lap):
     # the residual reported by ofm_solve is that of the X it returns, also for a
     # variant whose residual is not monotone
-    g, x0, olap = c1
+    g, x0, olap = sbm1k
     for variant, restart in (("tri-f2", True), ("f2", False)):
-        ws = ofm.Workspace(c1_lap, 8, variant=variant, precision=ofm.OFM_FP64, max_iter=2000,
+        ws = ofm.Workspace(sbm1k_lap, 8, variant=variant, precision=ofm.OFM_FP64, max_iter=2000,
                            check_every=10, tol=1e-6, restart=restart)
         X = dev(x0, torch.float64)
         st = ws.solve(X)

@@ -32,17 +32,17 @@ def rel(a, b):
 
 
 @pytest.fixture(scope="module")
-def c1(lib):
+def sbm1k(lib):
     from paper_2305_10356_amd import ofm
-    g, x0 = graphs.config_graph(1)
+    g, x0 = graphs.workload("sbm-n1000-k8")
     return g, x0, O.laplacian(g.n, g.row_ptr, g.col_idx), ofm.Laplacian(g.row_ptr, g.col_idx)
 
 
 @pytest.mark.parametrize("ce", [1000000, 7])
 @pytest.mark.parametrize("variant,vid", VARS)
-def test_recur_free_running_window_fp64(c1, variant, vid, ce):
+def test_recur_free_running_window_fp64(sbm1k, variant, vid, ce):
     from paper_2305_10356_amd import ofm
-    g, x0, olap, glap = c1
+    g, x0, olap, glap = sbm1k
     ws = ofm.Workspace(glap, 8, variant=variant, precision=ofm.OFM_FP64, check_every=ce,
                        recur=True)
     X = torch.as_tensor(x0).cuda()
@@ -61,7 +61,7 @@ def test_recurred_products_match_oracle(variant, vid):
     """After updates with no residual evaluation, X^T A X is formed from the
     recurred A X; it matches the oracle's product of the same X."""
     from paper_2305_10356_amd import ofm
-    g, x0 = graphs.config_graph(2)
+    g, x0 = graphs.workload("sbm-n50k-k32")
     olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     glap = ofm.Laplacian(g.row_ptr, g.col_idx)
     for prec, dt, tol in ((ofm.OFM_FP64, torch.float64, 1e-12),
@@ -81,9 +81,9 @@ def test_recurred_products_match_oracle(variant, vid):
 
 
 @pytest.mark.parametrize("variant,vid", VARS)
-def test_recur_solve_limits_fp64(c1, variant, vid):
+def test_recur_solve_limits_fp64(sbm1k, variant, vid):
     from paper_2305_10356_amd import ofm
-    g, x0, olap, glap = c1
+    g, x0, olap, glap = sbm1k
     k = 8
     mu, U = O.dense_eigh(olap)
     ws = ofm.Workspace(glap, k, variant=variant, precision=ofm.OFM_FP64, max_iter=500,
@@ -103,9 +103,9 @@ def test_recur_solve_limits_fp64(c1, variant, vid):
     np.testing.assert_allclose(Xh @ Xh.T, target, atol=1e-6)
 
 
-def test_recur_fp32_c2_reaches_tolerance():
+def test_recur_fp32_sbm50k_reaches_tolerance():
     from paper_2305_10356_amd import ofm
-    g, x0 = graphs.config_graph(2)
+    g, x0 = graphs.workload("sbm-n50k-k32")
     olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     glap = ofm.Laplacian(g.row_ptr, g.col_idx)
     iters = {}
@@ -115,7 +115,7 @@ def test_recur_fp32_c2_reaches_tolerance():
         X = torch.as_tensor(x0.astype(np.float32)).cuda()
         st = ws.solve(X)
         rr = O.relres(olap, host(X))
-        say(f"C2 FP32 f1 recur={recur}: iters={st['iters']} relres={st['relres']:.2e} "
+        say(f"50k-node SBM FP32 f1 recur={recur}: iters={st['iters']} relres={st['relres']:.2e} "
             f"oracle={rr:.2e}")
         assert st["converged"] == 1
         assert rr < 2e-4
@@ -126,7 +126,7 @@ def test_recur_fp32_c2_reaches_tolerance():
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_recur_graph_replay_is_bitwise_eager(prec):
     from paper_2305_10356_amd import ofm
-    g, x0 = graphs.config_graph(1 if prec == "fp64" else 2)
+    g, x0 = graphs.workload("sbm-n1000-k8" if prec == "fp64" else "sbm-n50k-k32")
     glap = ofm.Laplacian(g.row_ptr, g.col_idx)
     p = ofm.OFM_FP64 if prec == "fp64" else ofm.OFM_FP32
     dt = torch.float64 if prec == "fp64" else torch.float32

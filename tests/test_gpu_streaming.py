@@ -35,8 +35,7 @@ def host(t):
                                              ("fp32", 5, "tri-f1")])
 def test_graph_replay_is_bitwise_eager(lib, prec, ce, variant):
     from paper_2305_10356_amd import ofm
-    cfg = 1 if prec == "fp64" else 2
-    g, x0 = graphs.config_graph(cfg)
+    g, x0 = graphs.workload("sbm-n1000-k8" if prec == "fp64" else "sbm-n50k-k32")
     k = x0.shape[1]
     lap = ofm.Laplacian(g.row_ptr, g.col_idx)
     p = ofm.OFM_FP64 if prec == "fp64" else ofm.OFM_FP32
@@ -65,7 +64,7 @@ def test_graph_replay_is_bitwise_eager(lib, prec, ce, variant):
 
 def test_graph_replay_hits_max_iter_exactly(lib):
     from paper_2305_10356_amd import ofm
-    g, x0 = graphs.config_graph(1)
+    g, x0 = graphs.workload("sbm-n1000-k8")
     lap = ofm.Laplacian(g.row_ptr, g.col_idx)
     res = []
     for graph in (False, True):

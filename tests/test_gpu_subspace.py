@@ -36,9 +36,9 @@ def sin_angles(A, B):
     return np.sqrt(1.0 - s ** 2)
 
 
-def test_c2_subspace_and_labels_vs_oracle(lib):
+def test_sbm20k_subspace_and_labels_vs_oracle(lib):
     from paper_2305_10356_amd import ofm
-    g, x0 = graphs.config_graph(2, n=20000)
+    g, x0 = graphs.workload("sbm-n50k-k32", n=20000)
     k = 32
     olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     lap = ofm.Laplacian(g.row_ptr, g.col_idx)
@@ -61,7 +61,7 @@ def test_c2_subspace_and_labels_vs_oracle(lib):
     Xo = s.X
     ro = O.relres(olap, Xo)
     sa = sin_angles(Xg, Xo)
-    say(f"C2: gpu {st['iters']} updates relres {rg:.2e}; oracle {it} updates relres {ro:.2e}; "
+    say(f"20k-node SBM: gpu {st['iters']} updates relres {rg:.2e}; oracle {it} updates relres {ro:.2e}; "
         f"max sin angle {sa.max():.2e}")
     # both blocks span the invariant subspace up to their residuals; with the
     # spectral gap of this graph that keeps every principal angle small
@@ -81,6 +81,6 @@ def test_c2_subspace_and_labels_vs_oracle(lib):
     a_go = O.ari(lab_g, lab_o)
     a_gt = O.ari(lab_g, g.labels)
     a_ot = O.ari(lab_o, g.labels)
-    say(f"C2 labels: ARI gpu/oracle {a_go:.3f}, gpu/truth {a_gt:.3f}, oracle/truth {a_ot:.3f}")
+    say(f"20k-node SBM labels: ARI gpu/oracle {a_go:.3f}, gpu/truth {a_gt:.3f}, oracle/truth {a_ot:.3f}")
     assert a_go > 0.9
     assert abs(a_gt - a_ot) < 0.05

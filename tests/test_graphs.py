@@ -23,8 +23,8 @@ def check_simple_symmetric_connected(g):
 
 
 def test_config1_reproducible_and_valid():
-    g1, x1 = graphs.config_graph(1)
-    g2, x2 = graphs.config_graph(1)
+    g1, x1 = graphs.workload("sbm-n1000-k8")
+    g2, x2 = graphs.workload("sbm-n1000-k8")
     assert np.array_equal(g1.col_idx, g2.col_idx) and np.array_equal(x1, x2)
     check_simple_symmetric_connected(g1)
     s = g1.stats()
@@ -35,7 +35,7 @@ def test_config1_reproducible_and_valid():
 
 
 def test_config2_stats():
-    g, x = graphs.config_graph(2)
+    g, x = graphs.workload("sbm-n50k-k32")
     check_simple_symmetric_connected(g)
     s = g.stats()
     assert abs(s["mean_degree"] - 20) < 0.5 and abs(s["realized_r"] - 0.4) < 0.03
@@ -43,7 +43,7 @@ def test_config2_stats():
 
 
 def test_dcsbm_small_heavy_tail():
-    g, _ = graphs.config_graph(3, n=64000)
+    g, _ = graphs.workload("dcsbm-n2m-k32", n=64000)
     check_simple_symmetric_connected(g)
     s = g.stats()
     assert 22 < s["mean_degree"] <= 25.5
@@ -52,14 +52,14 @@ def test_dcsbm_small_heavy_tail():
 
 
 def test_node_order_hides_blocks():
-    g, _ = graphs.config_graph(2)
+    g, _ = graphs.workload("sbm-n50k-k32")
     # consecutive ids are not in the same block more often than chance
     same = np.mean(g.labels[1:] == g.labels[:-1])
     assert same < 0.1
 
 
 def test_bfs_ball():
-    g, _ = graphs.config_graph(2)
+    g, _ = graphs.workload("sbm-n50k-k32")
     sub = graphs.bfs_ball_subgraph(g, 500, np.random.default_rng(9))
     assert sub.n == 500
     check_simple_symmetric_connected(sub)

@@ -9,8 +9,8 @@ from paper_2305_10356_amd import graphs
 
 
 @pytest.fixture(scope="module")
-def c1():
-    g, x0 = graphs.config_graph(1)
+def sbm1k():
+    g, x0 = graphs.workload("sbm-n1000-k8")
     lap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     mu, U = O.dense_eigh(lap)
     return g, x0, lap, mu, U
@@ -21,8 +21,8 @@ def run(lap, x0, variant, iters, **kw):
     return st.X
 
 
-def test_ofm_f1_limit(c1):
-    g, x0, lap, mu, U = c1
+def test_ofm_f1_limit(sbm1k):
+    g, x0, lap, mu, U = sbm1k
     k = x0.shape[1]
     X = run(lap, x0, O.F1, 300)
     assert O.relres(lap, X) < 1e-6
@@ -35,8 +35,8 @@ def test_ofm_f1_limit(c1):
     np.testing.assert_allclose(O.f1_dense(A, X), np.sum(lam[k:] ** 2), rtol=1e-9)
 
 
-def test_ofm_f2_limit(c1):
-    g, x0, lap, mu, U = c1
+def test_ofm_f2_limit(sbm1k):
+    g, x0, lap, mu, U = sbm1k
     k = x0.shape[1]
     X = run(lap, x0, O.F2, 400)
     assert O.relres(lap, X) < 1e-5
@@ -52,8 +52,8 @@ def _columns_match(X, U, scale):
         yield np.abs(X[:, i] - s * target).max()
 
 
-def test_tri_f1_limit_with_restart(c1):
-    g, x0, lap, mu, U = c1
+def test_tri_f1_limit_with_restart(sbm1k):
+    g, x0, lap, mu, U = sbm1k
     X = run(lap, x0, O.TRI_F1, 400, restart=True)
     assert O.relres(lap, X) < 1e-5
     errs = list(_columns_match(X, U, np.sqrt(2.0 - mu)))
@@ -62,8 +62,8 @@ def test_tri_f1_limit_with_restart(c1):
     assert max(errs) < 1e-3
 
 
-def test_tri_f2_limit(c1):
-    g, x0, lap, mu, U = c1
+def test_tri_f2_limit(sbm1k):
+    g, x0, lap, mu, U = sbm1k
     X = run(lap, x0, O.TRI_F2, 400)
     assert O.relres(lap, X) < 1e-5
     errs = list(_columns_match(X, U, np.ones(X.shape[1])))
@@ -72,9 +72,9 @@ def test_tri_f2_limit(c1):
 
 @pytest.mark.parametrize("variant,c", [(O.F1, np.sqrt(2.0)), (O.TRI_F1, np.sqrt(2.0)),
                                        (O.F2, 1.0), (O.TRI_F2, 1.0)])
-def test_single_column_closed_form(c1, variant, c):
+def test_single_column_closed_form(sbm1k, variant, c):
     # k = 1: x -> +-c D^{1/2} 1 / ||D^{1/2} 1||, c = sqrt(-lambda_1) = sqrt(2) for f1
-    g, x0, lap, mu, U = c1
+    g, x0, lap, mu, U = sbm1k
     X = run(lap, x0[:, :1], variant, 300)
     t = np.sqrt(g.degrees().astype(float))
     t = c * t / np.linalg.norm(t)
@@ -82,8 +82,8 @@ def test_single_column_closed_form(c1, variant, c):
     np.testing.assert_allclose(X[:, 0], s * t, atol=1e-6)
 
 
-def test_residual_forms_agree(c1):
-    g, x0, lap, mu, U = c1
+def test_residual_forms_agree(sbm1k):
+    g, x0, lap, mu, U = sbm1k
     for X in (x0, run(lap, x0, O.F2, 20), run(lap, x0, O.F1, 40)):
         a = O.relres(lap, X)
         b = O.relres_direct(lap, X)
@@ -93,8 +93,8 @@ def test_residual_forms_agree(c1):
 
 
 @pytest.mark.parametrize("variant", [O.F1, O.F2])
-def test_ofm_objective_monotone(c1, variant):
-    g, x0, lap, mu, U = c1
+def test_ofm_objective_monotone(sbm1k, variant):
+    g, x0, lap, mu, U = sbm1k
     opts = O.Options(variant=variant)
     st, _ = O.init(lap, x0, opts)
     fprev = O.objective(variant, lap, x0)
@@ -107,18 +107,18 @@ def test_ofm_objective_monotone(c1, variant):
         assert f <= fprev + 1e-10 * abs(fprev)
 
 
-def test_fixed_first_step(c1):
-    g, x0, lap, mu, U = c1
+def test_fixed_first_step(sbm1k):
+    g, x0, lap, mu, U = sbm1k
     st, info = O.init(lap, x0, O.Options(variant=O.F1, first_step="fixed", alpha0=0.05))
     G = O.direction(O.F1, x0, O.apply_A(lap, x0))
     np.testing.assert_allclose(st.X, x0 - 0.05 * G, rtol=1e-15)
 
 
-def test_clustering_matches_dense_features(c1):
+def test_clustering_matches_dense_features(sbm1k):
     # Theorems 1-4: the limits are U_k sqrt(-Lam_k) Q (f1) or U_k Q (f2); an
     # orthogonal Q keeps row norms and distances, so K-means on the limits
     # reproduces K-means on the dense features with the same seeds
-    g, x0, lap, mu, U = c1
+    g, x0, lap, mu, U = sbm1k
     k = x0.shape[1]
     Uk = U[:, :k]
     feats = {"f1": Uk * np.sqrt(2.0 - mu[:k])[None, :], "f2": Uk}

@@ -9,7 +9,7 @@ from paper_2305_10356_amd import graphs
 
 @pytest.fixture(scope="module")
 def small():
-    g, _ = graphs.config_graph(1, n=120)
+    g, _ = graphs.workload("sbm-n1000-k8", n=120)
     lap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     A = O.dense_A(lap)
     rng = np.random.default_rng(11)

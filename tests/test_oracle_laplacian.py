@@ -79,7 +79,7 @@ def test_bipartite_top_eigenvalue_two():
 
 
 def test_sbm_invariants():
-    g, _ = graphs.config_graph(1)
+    g, _ = graphs.workload("sbm-n1000-k8")
     lap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     L = O.dense_L(lap)
     d = g.degrees().astype(float)

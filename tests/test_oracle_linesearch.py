@@ -15,7 +15,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 @pytest.fixture(scope="module")
 def state():
-    g, _ = graphs.config_graph(1, n=150)
+    g, _ = graphs.workload("sbm-n1000-k8", n=150)
     lap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     A = O.dense_A(lap)
     rng = np.random.default_rng(21)
