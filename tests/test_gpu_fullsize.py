@@ -66,17 +66,21 @@ def test_dcsbm2m_spmm_sampled_rows(dcsbm2m):
     assert err < 1e-6
 
 
-def test_dcsbm2m_first_updates_fp32_vs_oracle(dcsbm2m):
-    """The set-up update and one loop update of OFM-f1 in the benchmark's
-    configuration (FP32 passes, FP64 products) against the FP64 oracle run from
-    the FP32-rounded X0."""
+@pytest.mark.parametrize("variant,vid", [("f1", O.F1), ("tri-f1", O.TRI_F1), ("f2", O.F2),
+                                         ("tri-f2", O.TRI_F2)])
+def test_dcsbm2m_first_updates_fp32_vs_oracle(dcsbm2m, variant, vid):
+    """The set-up update and one loop update in the benchmark's configuration
+    (FP32 passes, FP64 products; the triangular variants with the descent
+    restart) against the FP64 oracle run from the FP32-rounded X0."""
     from paper_2305_10356_amd import ofm
     g, x0, lap = dcsbm2m
-    ws = ofm.Workspace(lap, 32, variant="f1", precision=ofm.OFM_FP32, check_every=10)
+    tri = variant.startswith("tri")
+    ws = ofm.Workspace(lap, 32, variant=variant, precision=ofm.OFM_FP32, check_every=10,
+                       restart=tri)
     X = torch.as_tensor(x0.astype(np.float32)).cuda()
     x = host(X)
     olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
-    opts = O.Options(variant=O.F1)
+    opts = O.Options(variant=vid, restart=tri)
     ws.init(X)
     a1 = ws.step_info()["alpha"]
     st, info = O.init(olap, x, opts)
@@ -85,11 +89,13 @@ def test_dcsbm2m_first_updates_fp32_vs_oracle(dcsbm2m):
     gi = ws.step_info()
     st2, info2 = O.step(olap, st, opts)
     e2 = np.abs(host(X) - st2.X).max() / np.abs(st2.X).max()
-    say(f"2M-node f1 FP32: X1 err {e1:.2e} alpha {a1[0]:.6e}/{info['alpha'][0]:.6e}; "
-        f"X2 err {e2:.2e} alpha {gi['alpha'][0]:.6e}/{info2['alpha'][0]:.6e}")
+    say(f"2M-node {variant} FP32: X1 err {e1:.2e}; X2 err {e2:.2e}")
     assert e1 < 1e-5 and e2 < 1e-4
-    assert a1[0] == pytest.approx(info["alpha"][0], rel=1e-4)
-    assert gi["alpha"][0] == pytest.approx(info2["alpha"][0], rel=1e-3)
+    na = 1 if not tri else 32
+    np.testing.assert_allclose(a1[:na], info["alpha"][:na], rtol=1e-4,
+                               atol=1e-6 * np.abs(info["alpha"]).max())
+    np.testing.assert_allclose(gi["alpha"][:na], info2["alpha"][:na], rtol=1e-3,
+                               atol=1e-5 * np.abs(info2["alpha"]).max())
     np.testing.assert_allclose(gi["beta"], info2["beta"], rtol=1e-3, atol=1e-6)
 
 
