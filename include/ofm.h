@@ -330,7 +330,9 @@ ofm_status ofm_objective(ofm_workspace ws, const void* X, double* f_out, void* g
 ofm_status ofm_set_timing(ofm_workspace ws, unsigned pass_mask);
 /* Synchronizing: waits for the recorded events, adds the elapsed times (ms)
  * and launch counts since the last reset into host_ms[OFM_NUM_PASSES] and
- * host_count[OFM_NUM_PASSES]; reset != 0 clears the totals afterwards. */
+ * host_count[OFM_NUM_PASSES]; reset != 0 clears the totals afterwards.  The
+ * event pairs of timed launches are held (and their events not reused) until
+ * this call, so a long timed run should call it from time to time. */
 ofm_status ofm_get_timing(ofm_workspace ws, double* host_ms, int64_t* host_count, int reset);
 
 /*
