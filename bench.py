@@ -283,8 +283,8 @@ def main():
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this "
-              f"build (the row-sharded multi-GPU design is documented, not built)", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported (the "
+              f"row-sharded multi-GPU design is described, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
