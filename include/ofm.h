@@ -336,6 +336,16 @@ ofm_status ofm_set_timing(ofm_workspace ws, unsigned pass_mask);
 ofm_status ofm_get_timing(ofm_workspace ws, double* host_ms, int64_t* host_count, int reset);
 
 /*
+ * Y = scale[0] * X elementwise over count values of the given precision
+ * (OFM_FP32 / OFM_FP64); scale is one FP64 in device memory; X == Y is
+ * allowed.  The chain rule of the differentiable objectives: the gradient of
+ * eqs. gradientf1 / gradientf2 (from ofm_objective) times the derivative that
+ * arrives from the caller's loss, without a host synchronization.
+ */
+ofm_status ofm_scale(int64_t count, int precision, const double* scale, const void* X, void* Y,
+                     hipStream_t stream);
+
+/*
  * Algorithm 1, step 4: Y_l = X_l / ||X_l||_2 for every row (a zero row stays
  * zero).  X and Y are N x k of the given precision; X == Y is allowed.
  */

@@ -3,7 +3,7 @@
 f1(X) = ||A + X X^T||_F^2 and f2(X) = tr((2I - X^T X) X^T A X) on the
 shifted normalized Laplacian A of a graph (Introduction; Sections 2.1, 2.2).
 The forward pass returns f(X) computed by the library from k x k products;
-the backward pass returns grad_out * grad f(X), where the gradient
+the backward pass returns grad_out * grad f(X) (scaled by the library), where the gradient
 (eqs. gradientf1, gradientf2) is produced by the same fused HIP kernels the
 iteration uses (SpMM with the direction epilogue for f1, SpMM then the
 direction pass for f2), during the forward call.  No CPU fallback.
@@ -27,7 +27,8 @@ class _Objective(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_out):
         (grad,) = ctx.saved_tensors
-        return grad_out.to(grad.dtype) * grad, None
+        s = grad_out.detach().to(torch.float64).reshape(1).contiguous()
+        return ofm.scale(grad, s), None
 
 
 class Objective(torch.nn.Module):

@@ -956,6 +956,15 @@ extern "C" ofm_status ofm_row_normalize(int64_t n, int k, int precision, const v
   return OFM_OK;
 }
 
+extern "C" ofm_status ofm_scale(int64_t count, int precision, const double* scale,
+                                const void* X, void* Y, hipStream_t stream) {
+  if (count < 0 || !scale || !X || !Y) return OFM_E_INVALID_ARG;
+  if (precision != OFM_FP32 && precision != OFM_FP64) return OFM_E_INVALID_ARG;
+  if (count == 0) return OFM_OK;
+  HIPCHK(launch_scale(count, precision, scale, X, Y, stream));
+  return OFM_OK;
+}
+
 extern "C" ofm_status ofm_kmeans_assign(int64_t n, int dim, int n_clusters, const float* Y,
                                         const float* centroids, int32_t* labels, float* dist2,
                                         hipStream_t stream) {

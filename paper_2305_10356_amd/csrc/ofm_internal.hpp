@@ -230,6 +230,8 @@ hipError_t launch_graph_pack(int64_t n, const int32_t* sched, const int32_t* row
 
 // Post-processing (ofm_post.hip)
 hipError_t launch_convert(int64_t count, int to_fp64, const void* src, void* dst, hipStream_t s);
+hipError_t launch_scale(int64_t count, int precision, const double* sp, const void* X, void* Y,
+                        hipStream_t s);
 hipError_t launch_row_normalize(int64_t n, int k, int precision, const void* X, void* Y,
                                 hipStream_t s);
 hipError_t launch_kmeans_assign(int64_t n, int dim, int nc, const float* Y, const float* C,

@@ -7,26 +7,86 @@
 
 namespace ofm {
 
+// Row-wise kernels: a group of kRowLanes lanes per row, element c of the row
+// in lane c % kRowLanes (k <= 64, so at most 4 elements per lane); grid-stride
+// over the rows.
+constexpr int kRowLanes = 16;
+
+__device__ inline double group_sum(double x) {
+#pragma unroll
+  for (int o = kRowLanes / 2; o >= 1; o >>= 1) x += __shfl_xor(x, o, kRowLanes);
+  return __shfl(x, 0, kRowLanes);  // every lane takes lane 0's sum
+}
+
+__device__ inline float group_sum(float x) {
+#pragma unroll
+  for (int o = kRowLanes / 2; o >= 1; o >>= 1) x += __shfl_xor(x, o, kRowLanes);
+  return __shfl(x, 0, kRowLanes);
+}
+
+static unsigned row_blocks(int64_t n) {
+  const int64_t groups_per_block = 256 / kRowLanes;
+  int64_t nb = (n + groups_per_block - 1) / groups_per_block;
+  if (nb > 4096) nb = 4096;
+  return (unsigned)(nb < 1 ? 1 : nb);
+}
+
 template <typename T>
-__global__ void row_normalize_kernel(int64_t n, int k, const T* __restrict__ X, T* __restrict__ Y) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const T* x = X + i * k;
-  double s = 0.0;
-  for (int c = 0; c < k; ++c) s += (double)x[c] * (double)x[c];
-  const double nr = sqrt(s);
-  T* y = Y + i * k;
-  for (int c = 0; c < k; ++c) y[c] = nr > 0.0 ? (T)((double)x[c] / nr) : T(0);
+__global__ void __launch_bounds__(256) row_normalize_kernel(int64_t n, int k,
+                                                            const T* __restrict__ X,
+                                                            T* __restrict__ Y) {
+  const int lane = threadIdx.x % kRowLanes;
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kRowLanes);
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes; i < n;
+       i += stride) {
+    T v[4];
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = lane + q * kRowLanes;
+      v[q] = c < k ? X[i * k + c] : T(0);
+      s += (double)v[q] * (double)v[q];
+    }
+    const double nr = sqrt(group_sum(s));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = lane + q * kRowLanes;
+      if (c < k) Y[i * k + c] = nr > 0.0 ? (T)((double)v[q] / nr) : T(0);
+    }
+  }
 }
 
 hipError_t launch_row_normalize(int64_t n, int k, int precision, const void* X, void* Y,
                                 hipStream_t s) {
-  const unsigned nb = (unsigned)((n + 255) / 256);
+  const unsigned nb = row_blocks(n);
   if (precision == OFM_FP64)
     hipLaunchKernelGGL(row_normalize_kernel<double>, dim3(nb), dim3(256), 0, s, n, k,
                        static_cast<const double*>(X), static_cast<double*>(Y));
   else
     hipLaunchKernelGGL(row_normalize_kernel<float>, dim3(nb), dim3(256), 0, s, n, k,
+                       static_cast<const float*>(X), static_cast<float*>(Y));
+  return hipGetLastError();
+}
+
+// Y = s[0] * X elementwise (s: one FP64 in device memory)
+template <typename T>
+__global__ void __launch_bounds__(256) scale_kernel(int64_t count, const double* __restrict__ sp,
+                                                    const T* X, T* Y) {
+  const double sc = sp[0];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    Y[i] = (T)(sc * (double)X[i]);
+}
+
+hipError_t launch_scale(int64_t count, int precision, const double* sp, const void* X, void* Y,
+                        hipStream_t s) {
+  int64_t nb = (count + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  if (precision == OFM_FP64)
+    hipLaunchKernelGGL(scale_kernel<double>, dim3((unsigned)nb), dim3(256), 0, s, count, sp,
+                       static_cast<const double*>(X), static_cast<double*>(Y));
+  else
+    hipLaunchKernelGGL(scale_kernel<float>, dim3((unsigned)nb), dim3(256), 0, s, count, sp,
                        static_cast<const float*>(X), static_cast<float*>(Y));
   return hipGetLastError();
 }
@@ -47,45 +107,61 @@ hipError_t launch_convert(int64_t count, int to_fp64, const void* src, void* dst
 }
 
 // one point per thread; centroids staged in LDS when they fit
-constexpr int kLdsCentroidFloats = 12288;
+constexpr int kLdsCentroidFloats = 12288;  // centroids staged in LDS up to 48 KB
 
+// label_i = argmin_c ||y_i - mu_c||^2 (lowest c on ties), FP32 distances
 __global__ void __launch_bounds__(256) kmeans_assign_kernel(int64_t n, int dim, int nc,
                                                             const float* __restrict__ Y,
                                                             const float* __restrict__ C,
                                                             int32_t* __restrict__ labels,
-                                                            float* __restrict__ dist2) {
-  __shared__ float cs[kLdsCentroidFloats];
-  const bool in_lds = nc * dim <= kLdsCentroidFloats;
-  if (in_lds)
+                                                            float* __restrict__ dist2,
+                                                            int c_in_lds) {
+  extern __shared__ float cs[];
+  if (c_in_lds)
     for (int e = threadIdx.x; e < nc * dim; e += blockDim.x) cs[e] = C[e];
   __syncthreads();
-  const float* cc = in_lds ? cs : C;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float y[64];
-  for (int d = 0; d < dim; ++d) y[d] = Y[i * dim + d];
-  float best = INFINITY;
-  int bi = 0;
-  for (int c = 0; c < nc; ++c) {
-    float s = 0.0f;
-    for (int d = 0; d < dim; ++d) {
-      const float t = y[d] - cc[c * dim + d];
-      s = fmaf(t, t, s);
+  const float* cc = c_in_lds ? cs : C;
+  const int lane = threadIdx.x % kRowLanes;
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kRowLanes);
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes; i < n;
+       i += stride) {
+    float y[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int d = lane + q * kRowLanes;
+      y[q] = d < dim ? Y[i * dim + d] : 0.0f;
     }
-    if (s < best) {
-      best = s;
-      bi = c;
+    float best = INFINITY;
+    int bi = 0;
+    for (int c = 0; c < nc; ++c) {
+      float sq = 0.0f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int d = lane + q * kRowLanes;
+        if (d < dim) {
+          const float t = y[q] - cc[c * dim + d];
+          sq = fmaf(t, t, sq);
+        }
+      }
+      sq = group_sum(sq);
+      if (sq < best) {
+        best = sq;
+        bi = c;
+      }
+    }
+    if (lane == 0) {
+      labels[i] = bi;
+      if (dist2) dist2[i] = best;
     }
   }
-  labels[i] = bi;
-  if (dist2) dist2[i] = best;
 }
 
 hipError_t launch_kmeans_assign(int64_t n, int dim, int nc, const float* Y, const float* C,
                                 int32_t* labels, float* dist2, hipStream_t s) {
-  const unsigned nb = (unsigned)((n + 255) / 256);
-  hipLaunchKernelGGL(kmeans_assign_kernel, dim3(nb), dim3(256), 0, s, n, dim, nc, Y, C, labels,
-                     dist2);
+  const int in_lds = nc * dim <= kLdsCentroidFloats ? 1 : 0;
+  const size_t smem = in_lds ? (size_t)nc * dim * sizeof(float) : 0;
+  hipLaunchKernelGGL(kmeans_assign_kernel, dim3(row_blocks(n)), dim3(256), smem, s, n, dim, nc, Y,
+                     C, labels, dist2, in_lds);
   return hipGetLastError();
 }
 

@@ -99,6 +99,7 @@ _SIGS = {
     "ofm_batch_solve": (_I, [_P, _P, _P, _P]),
     "ofm_batch_schedule": (_I, [_P, _P, _P, _P]),
     "ofm_batch_phases": (_I, [_P, _P, _P]),
+    "ofm_scale": (_I, [_I64, _I, _P, _P, _P, _P]),
     "ofm_row_normalize": (_I, [_I64, _I, _I, _P, _P, _P]),
     "ofm_kmeans_assign": (_I, [_I64, _I, _I, _P, _P, _P, _P, _P]),
     "ofm_kmeans": (_I, [_I64, _I, _I, _P, _P, _I, _P, _P, _P, _P]),
@@ -417,6 +418,20 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def scale(X, s, Y=None, stream=None):
+    """Y = s * X with s a one-element FP64 device tensor (no host sync)."""
+    torch = _torch()
+    if not (X.is_cuda and X.is_contiguous()):
+        raise ValueError("expected a contiguous device tensor")
+    if s.dtype != torch.float64 or s.numel() != 1 or not s.is_cuda:
+        raise ValueError("scale must be one FP64 value on the device")
+    if Y is None:
+        Y = torch.empty_like(X)
+    _check(load().ofm_scale(X.numel(), _prec(X), _ptr(s.contiguous()), _ptr(X), _ptr(Y),
+                            _stream(stream)), "ofm_scale")
+    return Y
 
 
 def row_normalize(X, Y=None, stream=None):

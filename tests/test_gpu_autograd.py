@@ -94,3 +94,19 @@ def test_triangular_directions_are_not_objectives(sub500):
     with pytest.raises(ofm.OfmError) as e:
         ws.objective(X)
     assert e.value.status == -8
+
+
+def test_backward_scales_by_upstream_derivative(sub500):
+    """The chain rule on the device: d(c f)/dX = c grad f, c from the caller's loss."""
+    from paper_2305_10356_amd import autograd, ofm
+    sub, olap = sub500
+    lap = ofm.Laplacian(sub.row_ptr, sub.col_idx)
+    rng = np.random.default_rng(21)
+    for dt, tol in ((torch.float64, 1e-12), (torch.float32, 1e-4)):
+        x = (rng.standard_normal((sub.n, 8)) * 0.1).astype(np.float32).astype(np.float64)
+        X = torch.tensor(x, dtype=dt, device="cuda", requires_grad=True)
+        f = autograd.Objective(lap, 8, "f2", dt)(X)
+        (-2.5 * f).backward()
+        ref = -2.5 * O.direction(O.F2, x, O.apply_A(olap, x))
+        g = X.grad.cpu().numpy().astype(np.float64)
+        assert np.abs(g - ref).max() <= tol * np.abs(ref).max()
