@@ -500,19 +500,31 @@ def main():
         if not args.no_streaming:
             extras["streaming_warm_start"] = streaming_c4(args.variant)
             extras["streaming_warm_start_recur"] = streaming_c4(args.variant, recur=True)
-        # post-processing (Algorithm 1 steps 4-5), once per solve
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
+        # post-processing (Algorithm 1 steps 4-5): event-timed averages over
+        # repeated calls on torch's current stream, against HBM bytes
         Yn = ofm.row_normalize(X3)
-        torch.cuda.synchronize()
-        t_norm = time.perf_counter() - t1
         C = Yn[torch.randperm(n, device=dev)[:k]].contiguous()
-        t1 = time.perf_counter()
         labels = ofm.kmeans_assign(Yn, C)
-        torch.cuda.synchronize()
-        t_assign = time.perf_counter() - t1
-        extras["postprocess_ms"] = {"row_normalize": round(1e3 * t_norm, 2),
-                                    "kmeans_assign": round(1e3 * t_assign, 2)}
+        esz = Yn.element_size()
+
+        def timed_us(fn, reps=10):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            e1.synchronize()
+            return 1e3 * e0.elapsed_time(e1) / reps
+
+        us_norm = timed_us(lambda: ofm.row_normalize(X3, Yn))
+        us_asg = timed_us(lambda: ofm.kmeans_assign(Yn, C))
+        b_norm = 2 * n * k * esz
+        b_asg = n * k * 4 + n * 4
+        extras["postprocess"] = {
+            "row_normalize": {"us": round(us_norm, 1), "bytes": b_norm,
+                              "GB_s": round(b_norm / us_norm / 1e3, 1)},
+            "kmeans_assign": {"us": round(us_asg, 1), "bytes": b_asg, "clusters": k,
+                              "GB_s": round(b_asg / us_asg / 1e3, 1)}}
         extras["laplacian_build_s"] = round(t_lap, 3)
         del X3, Yn, labels
 

@@ -2,6 +2,7 @@
 // Euclidean K-means (assignment, deterministic centroid update, k-means++
 // seeding from caller-supplied uniforms).
 #include <math.h>
+#include <stdint.h>
 
 #include "ofm_internal.hpp"
 
@@ -31,10 +32,10 @@ static unsigned row_blocks(int64_t n) {
   return (unsigned)(nb < 1 ? 1 : nb);
 }
 
+// X and Y may be the same block: each element is read before it is written,
+// by the same lane, so neither pointer is restrict-qualified.
 template <typename T>
-__global__ void __launch_bounds__(256) row_normalize_kernel(int64_t n, int k,
-                                                            const T* __restrict__ X,
-                                                            T* __restrict__ Y) {
+__global__ void __launch_bounds__(256) row_normalize_kernel(int64_t n, int k, const T* X, T* Y) {
   const int lane = threadIdx.x % kRowLanes;
   const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kRowLanes);
   for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes; i < n;
@@ -56,8 +57,65 @@ __global__ void __launch_bounds__(256) row_normalize_kernel(int64_t n, int k,
   }
 }
 
+// Rows whose byte length is 16 L with L a power of two (k = 32 in FP32: L = 8):
+// the block is a flat array of 16-byte vectors, lane t takes vector t, and the
+// L lanes of one row sum their squares with a width-L butterfly.  Loads and
+// stores are then 16 bytes per lane and contiguous across the wavefront.
+template <int W>
+__device__ inline double width_sum(double x) {
+#pragma unroll
+  for (int o = W / 2; o >= 1; o >>= 1) x += __shfl_xor(x, o, W);
+  return x;
+}
+
+template <typename T, int L>
+__global__ void __launch_bounds__(256) row_normalize_vec_kernel(int64_t n, const T* X, T* Y) {
+  constexpr int E = 16 / sizeof(T);
+  typedef T vec __attribute__((ext_vector_type(E)));
+  const int64_t total = n * L;  // vectors; the L of one row share a loop trip
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+    vec v = reinterpret_cast<const vec*>(X)[t];
+    double sq = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) sq += (double)v[e] * (double)v[e];
+    const double nr = sqrt(width_sum<L>(sq));
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = nr > 0.0 ? (T)((double)v[e] / nr) : T(0);
+    reinterpret_cast<vec*>(Y)[t] = v;
+  }
+}
+
+template <typename T, int L>
+static hipError_t row_normalize_vec(int64_t n, const void* X, void* Y, hipStream_t s) {
+  int64_t nb = (n * L + 255) / 256;
+  if (nb > 2048) nb = 2048;  // one resident round (8 blocks per CU)
+  hipLaunchKernelGGL((row_normalize_vec_kernel<T, L>), dim3((unsigned)nb), dim3(256), 0, s, n,
+                     static_cast<const T*>(X), static_cast<T*>(Y));
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t row_normalize_vec_any(int64_t n, int L, const void* X, void* Y, hipStream_t s) {
+  switch (L) {
+    case 1: return row_normalize_vec<T, 1>(n, X, Y, s);
+    case 2: return row_normalize_vec<T, 2>(n, X, Y, s);
+    case 4: return row_normalize_vec<T, 4>(n, X, Y, s);
+    case 8: return row_normalize_vec<T, 8>(n, X, Y, s);
+    case 16: return row_normalize_vec<T, 16>(n, X, Y, s);
+    default: return row_normalize_vec<T, 32>(n, X, Y, s);  // k = 64 in FP64
+  }
+}
+
 hipError_t launch_row_normalize(int64_t n, int k, int precision, const void* X, void* Y,
                                 hipStream_t s) {
+  const int esz = precision == OFM_FP64 ? 8 : 4;
+  const int rb = k * esz;
+  const int L = rb / 16;
+  if (rb % 16 == 0 && L >= 1 && L <= 32 && (L & (L - 1)) == 0 &&
+      reinterpret_cast<uintptr_t>(X) % 16 == 0 && reinterpret_cast<uintptr_t>(Y) % 16 == 0)
+    return precision == OFM_FP64 ? row_normalize_vec_any<double>(n, L, X, Y, s)
+                                 : row_normalize_vec_any<float>(n, L, X, Y, s);
   const unsigned nb = row_blocks(n);
   if (precision == OFM_FP64)
     hipLaunchKernelGGL(row_normalize_kernel<double>, dim3(nb), dim3(256), 0, s, n, k,
@@ -106,63 +164,128 @@ hipError_t launch_convert(int64_t count, int to_fp64, const void* src, void* dst
   return hipGetLastError();
 }
 
-// one point per thread; centroids staged in LDS when they fit
-constexpr int kLdsCentroidFloats = 12288;  // centroids staged in LDS up to 48 KB
+// One point per thread: the row sits in registers (padded with zeros to D),
+// the centroids are read from LDS with every lane at the same address (a
+// broadcast), padded with zeros to D as well, so the padding adds nothing to
+// the distances.  When all centroids do not fit in kAssignLdsFloats they are
+// staged chunk by chunk for each tile of rows.
+constexpr int kAssignLdsFloats = 8192;  // 32 KB of centroids per block
+constexpr int kAssignThreads = 256;
 
-// label_i = argmin_c ||y_i - mu_c||^2 (lowest c on ties), FP32 distances
-__global__ void __launch_bounds__(256) kmeans_assign_kernel(int64_t n, int dim, int nc,
-                                                            const float* __restrict__ Y,
-                                                            const float* __restrict__ C,
-                                                            int32_t* __restrict__ labels,
-                                                            float* __restrict__ dist2,
-                                                            int c_in_lds) {
+template <int D>
+__device__ inline void stage_centroids(float* cs, const float* __restrict__ C, int dim, int c0,
+                                       int cn) {
+  for (int e = threadIdx.x; e < cn * D; e += kAssignThreads) {
+    const int c = e / D, d = e % D;
+    cs[e] = d < dim ? C[(int64_t)(c0 + c) * dim + d] : 0.0f;
+  }
+}
+
+// label_i = argmin_c sum_d (y_id - mu_cd)^2 (lowest c on ties), FP32 distances
+template <int D>
+__global__ void __launch_bounds__(kAssignThreads) kmeans_assign_kernel(
+    int64_t n, int dim, int nc, const float* __restrict__ Y, const float* __restrict__ C,
+    int32_t* __restrict__ labels, float* __restrict__ dist2, int chunk, int vec4) {
   extern __shared__ float cs[];
-  if (c_in_lds)
-    for (int e = threadIdx.x; e < nc * dim; e += blockDim.x) cs[e] = C[e];
-  __syncthreads();
-  const float* cc = c_in_lds ? cs : C;
-  const int lane = threadIdx.x % kRowLanes;
-  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kRowLanes);
-  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes; i < n;
-       i += stride) {
-    float y[4];
+  const bool once = chunk >= nc;
+  if (once) {
+    stage_centroids<D>(cs, C, dim, 0, nc);
+    __syncthreads();
+  }
+  // the tile loop is uniform over the block so that the chunked path can
+  // synchronize inside it
+  for (int64_t base = (int64_t)blockIdx.x * kAssignThreads; base < n;
+       base += (int64_t)gridDim.x * kAssignThreads) {
+    const int64_t i = base + threadIdx.x;
+    float y[D];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int d = lane + q * kRowLanes;
-      y[q] = d < dim ? Y[i * dim + d] : 0.0f;
+    for (int d = 0; d < D; ++d) y[d] = 0.0f;
+    if (i < n) {
+      const float* row = Y + i * dim;
+      if (vec4) {
+#pragma unroll
+        for (int q = 0; q < D / 4; ++q)
+          if (4 * q < dim) {
+            const float4 v = reinterpret_cast<const float4*>(row)[q];
+            y[4 * q] = v.x;
+            y[4 * q + 1] = v.y;
+            y[4 * q + 2] = v.z;
+            y[4 * q + 3] = v.w;
+          }
+      } else {
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+          if (d < dim) y[d] = row[d];
+      }
     }
     float best = INFINITY;
     int bi = 0;
-    for (int c = 0; c < nc; ++c) {
-      float sq = 0.0f;
+    for (int c0 = 0; c0 < nc; c0 += chunk) {
+      const int cn = min(chunk, nc - c0);
+      if (!once) {
+        __syncthreads();
+        stage_centroids<D>(cs, C, dim, c0, cn);
+        __syncthreads();
+      }
+      for (int c = 0; c < cn; ++c) {
+        const float4* mu = reinterpret_cast<const float4*>(cs + c * D);
+        float sq = 0.0f;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int d = lane + q * kRowLanes;
-        if (d < dim) {
-          const float t = y[q] - cc[c * dim + d];
+        for (int q = 0; q < D / 4; ++q) {
+          const float4 m = mu[q];
+          float t = y[4 * q] - m.x;
+          sq = fmaf(t, t, sq);
+          t = y[4 * q + 1] - m.y;
+          sq = fmaf(t, t, sq);
+          t = y[4 * q + 2] - m.z;
+          sq = fmaf(t, t, sq);
+          t = y[4 * q + 3] - m.w;
           sq = fmaf(t, t, sq);
         }
-      }
-      sq = group_sum(sq);
-      if (sq < best) {
-        best = sq;
-        bi = c;
+        if (sq < best) {
+          best = sq;
+          bi = c0 + c;
+        }
       }
     }
-    if (lane == 0) {
+    if (i < n) {
       labels[i] = bi;
       if (dist2) dist2[i] = best;
     }
   }
 }
 
+template <int D>
+static hipError_t assign_with(int64_t n, int dim, int nc, const float* Y, const float* C,
+                              int32_t* labels, float* dist2, hipStream_t s) {
+  const int chunk = nc * D <= kAssignLdsFloats ? nc : kAssignLdsFloats / D;
+  const size_t smem = (size_t)chunk * D * sizeof(float);
+  const int vec4 = (dim % 4 == 0 && reinterpret_cast<uintptr_t>(Y) % 16 == 0) ? 1 : 0;
+  // one resident round of blocks (the tile loop strides over the rest), so no
+  // partial last round leaves CUs idle; the LDS size depends on the call
+  int occ = 0, dev = 0, cus = 0;
+  int64_t cap = 2048;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kmeans_assign_kernel<D>, kAssignThreads,
+                                                   smem) == hipSuccess &&
+      hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      occ > 0 && cus > 0)
+    cap = (int64_t)occ * cus;
+  int64_t nb = (n + kAssignThreads - 1) / kAssignThreads;
+  if (nb > cap) nb = cap;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(kmeans_assign_kernel<D>, dim3((unsigned)nb), dim3(kAssignThreads), smem, s,
+                     n, dim, nc, Y, C, labels, dist2, chunk, vec4);
+  return hipGetLastError();
+}
+
 hipError_t launch_kmeans_assign(int64_t n, int dim, int nc, const float* Y, const float* C,
                                 int32_t* labels, float* dist2, hipStream_t s) {
-  const int in_lds = nc * dim <= kLdsCentroidFloats ? 1 : 0;
-  const size_t smem = in_lds ? (size_t)nc * dim * sizeof(float) : 0;
-  hipLaunchKernelGGL(kmeans_assign_kernel, dim3(row_blocks(n)), dim3(256), smem, s, n, dim, nc, Y,
-                     C, labels, dist2, in_lds);
-  return hipGetLastError();
+  if (dim <= 4) return assign_with<4>(n, dim, nc, Y, C, labels, dist2, s);
+  if (dim <= 8) return assign_with<8>(n, dim, nc, Y, C, labels, dist2, s);
+  if (dim <= 16) return assign_with<16>(n, dim, nc, Y, C, labels, dist2, s);
+  if (dim <= 32) return assign_with<32>(n, dim, nc, Y, C, labels, dist2, s);
+  return assign_with<64>(n, dim, nc, Y, C, labels, dist2, s);
 }
 
 int kmeans_blocks(int64_t n) {

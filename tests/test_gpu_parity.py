@@ -415,6 +415,56 @@ def test_row_normalize_and_assign(ofm):
     np.testing.assert_allclose(host(d2), best, rtol=1e-5)
 
 
+@pytest.mark.parametrize("k", [1, 4, 6, 12, 13, 16, 32, 64])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_row_normalize_widths(ofm, k, prec):
+    """Rows of 16-byte multiples that are powers of two take the vector path,
+    the others (and a block that is not 16-byte aligned) the general one; a
+    zero row stays zero."""
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    tol = 1e-6 if prec == "fp32" else 1e-15
+    rng = np.random.default_rng(k)
+    n = 2053
+    X = rng.standard_normal((n, k))
+    X[5] = 0.0
+    if dt == torch.float32:
+        X = X.astype(np.float32).astype(np.float64)
+    ref = O.row_normalize(X)
+    Y = host(ofm.row_normalize(dev(X, dt)))
+    assert rel(Y, ref) < tol and np.all(Y[5] == 0.0)
+    # the same rows one element into a larger buffer (misaligned), in place
+    buf = torch.zeros(n * k + 1, dtype=dt, device="cuda")
+    Xm = buf[1:].view(n, k)
+    Xm.copy_(dev(X, dt))
+    ofm.row_normalize(Xm, Xm)
+    assert rel(host(Xm), ref) < tol and float(buf[0]) == 0.0
+
+
+def check_assign(lab, d2, D):
+    """Labels against the oracle's argmin where the nearest centre is clear by
+    more than FP32 rounding; at near ties, the chosen centre is a nearest one."""
+    best = D.min(axis=1)
+    srt = np.sort(D, axis=1)
+    clear = (srt[:, 1] - srt[:, 0]) > 1e-5 * srt[:, 1] if D.shape[1] > 1 else np.ones(len(lab), bool)
+    assert np.array_equal(lab[clear], np.argmin(D, axis=1)[clear])
+    assert np.all(D[np.arange(len(lab)), lab] <= best * (1 + 1e-5) + 1e-6)
+    np.testing.assert_allclose(d2, best, rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("n,dim,nc", [(1, 1, 1), (257, 3, 7), (3001, 13, 40), (5000, 8, 1),
+                                      (4099, 32, 32), (2050, 63, 9), (2500, 64, 300),
+                                      (600_001, 8, 5)])
+def test_assign_shapes(ofm, n, dim, nc):
+    """Every register width, rows that are not float4-aligned, one centre,
+    centroids staged in LDS chunks (64 x 300 floats), and more rows than one
+    sweep of the grid covers."""
+    rng = np.random.default_rng(n + dim + nc)
+    Y = rng.standard_normal((n, dim)).astype(np.float32)
+    C = rng.standard_normal((nc, dim)).astype(np.float32)
+    lab, d2 = ofm.kmeans_assign(dev(Y, torch.float32), dev(C, torch.float32), want_dist=True)
+    check_assign(lab.cpu().numpy(), host(d2), O.kmeans_dist2(Y, C))
+
+
 def test_kmeans_matches_oracle_on_blobs(ofm):
     rng = np.random.default_rng(3)
     centers = rng.standard_normal((6, 8)) * 5
