@@ -148,3 +148,32 @@ def test_batch_256_residuals(lib, recur):
         rr = O.relres(olap, host(Xs[b]))
         assert rr <= 1.05e-4, (b, rr)
         assert rr == pytest.approx(st[b]["relres"], rel=0.05, abs=2e-6), (b, rr, st[b]["relres"])
+
+
+def test_dcsbm2m_postprocess_sampled_rows(dcsbm2m):
+    """Algorithm 1 steps 4-5 on a 2M x 32 FP32 block, as the benchmark runs
+    them: row normalisation and the K-means assignment to 32 centres, checked
+    on sampled rows (and the ragged end) against the oracle's formulas."""
+    from paper_2305_10356_amd import ofm
+    g, _, _ = dcsbm2m
+    rng = np.random.default_rng(41)
+    X = rng.standard_normal((g.n, 32)).astype(np.float32)
+    X[[0, g.n - 1]] *= 1e-20                     # tiny rows still normalise
+    Xd = torch.as_tensor(X).cuda()
+    Yd = ofm.row_normalize(Xd)
+    rows = np.unique(np.concatenate([rng.choice(g.n, 20000, replace=False),
+                                     np.arange(g.n - 300, g.n), [0]]))
+    Y = host(Yd)
+    ref = O.row_normalize(X[rows].astype(np.float64))
+    assert np.abs(Y[rows] - ref).max() < 1e-6
+    C = Yd[torch.as_tensor(rng.choice(g.n, 32, replace=False)).cuda()].contiguous()
+    lab, d2 = ofm.kmeans_assign(Yd, C, want_dist=True)
+    lab = lab.cpu().numpy()
+    D = O.kmeans_dist2(Y[rows].astype(np.float32), host(C).astype(np.float32))
+    best = D.min(axis=1)
+    srt = np.sort(D, axis=1)
+    clear = (srt[:, 1] - srt[:, 0]) > 1e-5 * srt[:, 1]
+    say(f"2M-node post-processing: {rows.shape[0]} sampled rows, {int(clear.sum())} clear labels")
+    assert np.array_equal(lab[rows][clear], np.argmin(D, axis=1)[clear])
+    assert np.all(D[np.arange(len(rows)), lab[rows]] <= best * (1 + 1e-5) + 1e-6)
+    np.testing.assert_allclose(host(d2)[rows], best, rtol=1e-5, atol=1e-6)
