@@ -312,13 +312,19 @@ extern "C" ofm_status ofm_build_laplacian(int64_t n, int64_t nnz, const int32_t*
   double na = 0.0;
   for (double v : hparts) na += v;
   g.normA2 = na;
-  // row-processing order: by number of entries, descending (stable)
+  // row-processing order: by number of entries, descending, ties in row order
+  // (a counting sort over the entry counts: O(n + max count))
   std::vector<int32_t> sched(n);
-  std::iota(sched.begin(), sched.end(), 0);
   if (g.reorder) {
-    std::stable_sort(sched.begin(), sched.end(), [&](int32_t a, int32_t b) {
-      return (hrp[a + 1] - hrp[a]) > (hrp[b + 1] - hrp[b]);
-    });
+    int32_t mx = 0;
+    for (int64_t i = 0; i < n; ++i) mx = std::max(mx, hrp[i + 1] - hrp[i]);
+    std::vector<int64_t> slot((size_t)mx + 2, 0);  // slot[mx - count]: next position
+    for (int64_t i = 0; i < n; ++i) ++slot[(size_t)(mx - (hrp[i + 1] - hrp[i])) + 1];
+    for (int32_t c = 0; c <= mx; ++c) slot[(size_t)c + 1] += slot[c];
+    for (int64_t i = 0; i < n; ++i)
+      sched[(size_t)slot[(size_t)(mx - (hrp[i + 1] - hrp[i]))]++] = (int32_t)i;
+  } else {
+    std::iota(sched.begin(), sched.end(), 0);
   }
   std::vector<int32_t> sptr(n + 1), sdeg(n);
   sptr[0] = 0;
@@ -984,8 +990,8 @@ extern "C" ofm_status ofm_kmeans(int64_t n, int dim, int n_clusters, const float
   if (n_clusters > n) return OFM_E_SHAPE;
   for (int c = 0; c < n_clusters; ++c)
     if (!(host_uniforms[c] >= 0.0 && host_uniforms[c] < 1.0)) return OFM_E_INVALID_ARG;
-  const int nbk = kmeans_blocks(n);
-  const int nbs = 1024;
+  const int nbk = kmeans_blocks(n, n_clusters * (dim + 1));
+  const int nbs = kmeans_pick_chunks(n);
   float* d2 = nullptr;
   int32_t* pick = nullptr;
   double* sums = nullptr;
@@ -1019,12 +1025,13 @@ extern "C" ofm_status ofm_kmeans(int64_t n, int dim, int n_clusters, const float
   if (hipMemcpyAsync(pick, &first, sizeof(int32_t), hipMemcpyHostToDevice, stream) != hipSuccess)
     return fail(OFM_E_HIP);
   if (launch_kmeans_copy_centre(dim, Y, pick, centroids, 0, stream) != hipSuccess ||
-      launch_kmeans_mindist(n, dim, Y, centroids, d2, 1, stream) != hipSuccess)
+      launch_kmeans_mindist(n, dim, Y, centroids, d2, 1, sums, stream) != hipSuccess)
     return fail(OFM_E_HIP);
   for (int c = 1; c < n_clusters; ++c) {
-    if (launch_kmeans_pick(n, d2, host_uniforms[c], sums, nbs, pick, stream) != hipSuccess ||
+    if (launch_kmeans_pick(n, d2, host_uniforms[c], sums, pick, stream) != hipSuccess ||
         launch_kmeans_copy_centre(dim, Y, pick, centroids, c, stream) != hipSuccess ||
-        launch_kmeans_mindist(n, dim, Y, centroids + (size_t)c * dim, d2, 0, stream) != hipSuccess)
+        launch_kmeans_mindist(n, dim, Y, centroids + (size_t)c * dim, d2, 0, sums, stream) !=
+            hipSuccess)
       return fail(OFM_E_HIP);
   }
   // Lloyd iterations

@@ -242,13 +242,14 @@ hipError_t launch_kmeans_centroid_sums(int64_t n, int dim, int nc, const float* 
 hipError_t launch_kmeans_centroid_final(int dim, int nc, const double* part, int nb,
                                         const float* old_c, float* new_c, hipStream_t s);
 hipError_t launch_kmeans_mindist(int64_t n, int dim, const float* Y, const float* centre,
-                                 float* d2, int first, hipStream_t s);
-hipError_t launch_kmeans_pick(int64_t n, const float* d2, double u, double* blocksums,
-                              int nb, int32_t* pick, hipStream_t s);
+                                 float* d2, int first, double* sums, hipStream_t s);
+hipError_t launch_kmeans_pick(int64_t n, const float* d2, double u, const double* sums,
+                              int32_t* pick, hipStream_t s);
 hipError_t launch_kmeans_copy_centre(int dim, const float* Y, const int32_t* pick,
                                      float* C, int c, hipStream_t s);
 hipError_t launch_count_changes(int64_t n, const int32_t* a, const int32_t* b, int* out,
                                 hipStream_t s);
-int kmeans_blocks(int64_t n);
+int kmeans_blocks(int64_t n, int nv);
+int kmeans_pick_chunks(int64_t n);
 
 }  // namespace ofm

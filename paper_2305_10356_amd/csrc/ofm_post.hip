@@ -288,142 +288,296 @@ hipError_t launch_kmeans_assign(int64_t n, int dim, int nc, const float* Y, cons
   return assign_with<64>(n, dim, nc, Y, C, labels, dist2, s);
 }
 
-int kmeans_blocks(int64_t n) {
-  int64_t nb = (n + 1023) / 1024;
-  if (nb > 2048) nb = 2048;
+// ---------------------------------------------------------------------------
+// Lloyd centroid update: per-block sums of the rows of every cluster plus
+// counts, then means.  Every sum has a fixed order (rows in order within a
+// wave, waves and blocks in order), so the result does not depend on timing.
+// part layout: [block][nc][dim + 1].
+// ---------------------------------------------------------------------------
+constexpr int kSumWaves = 4;
+constexpr int kSumRows = 16;           // rows whose loads a wave keeps in flight
+constexpr int kSumLdsDoubles = 2048;   // per wave: nc (dim + 1) <= 2048 takes the LDS path
+constexpr int64_t kPartBytes = int64_t(256) << 20;
+
+int kmeans_blocks(int64_t n, int nv) {
+  int64_t nb = (n + 2047) / 2048;
+  if (nb > 1024) nb = 1024;
+  const int64_t cap = kPartBytes / ((int64_t)nv * (int64_t)sizeof(double));
+  if (nb > cap) nb = cap;
   if (nb < 1) nb = 1;
   return (int)nb;
 }
 
-// per-block sums of the rows of every cluster plus counts, row by row in a
-// fixed order (lane = feature), so the result does not depend on timing.
-// part layout: [block][nc][dim + 1]; accumulated in LDS when it fits.
-constexpr int kLdsSumDoubles = 6144;
+// kSumWaves waves per block, each over a contiguous quarter of the block's
+// rows with its own LDS accumulator (lane = feature); the quarters are added
+// in wave order at the end.
+__global__ void __launch_bounds__(kSumWaves * 64) kmeans_sums_lds_kernel(
+    int64_t n, int dim, int nc, const float* __restrict__ Y, const int32_t* __restrict__ labels,
+    double* __restrict__ part) {
+  extern __shared__ double acc[];
+  const int nv = nc * (dim + 1);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < kSumWaves * nv; e += blockDim.x) acc[e] = 0.0;
+  __syncthreads();
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = min(n, r0 + per);
+  const int64_t len = r1 > r0 ? r1 - r0 : 0;
+  const int64_t w0 = r0 + len * w / kSumWaves, w1 = r0 + len * (w + 1) / kSumWaves;
+  double* a = acc + (size_t)w * nv;
+  for (int64_t rb = w0; rb < w1; rb += kSumRows) {
+    int lab[kSumRows];
+    float y[kSumRows];
+#pragma unroll
+    for (int q = 0; q < kSumRows; ++q) {
+      const int64_t r = rb + q;
+      lab[q] = r < w1 ? labels[r] : -1;
+      y[q] = (r < w1 && lane < dim) ? Y[r * dim + lane] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < kSumRows; ++q) {
+      if (lab[q] >= 0) {
+        double* ac = a + (size_t)lab[q] * (dim + 1);
+        if (lane < dim) ac[lane] += (double)y[q];
+        if (lane == 0) ac[dim] += 1.0;
+      }
+    }
+  }
+  __syncthreads();
+  double* pb = part + (size_t)blockIdx.x * nv;
+  for (int e = threadIdx.x; e < nv; e += blockDim.x) {
+    double t = acc[e];
+    for (int v = 1; v < kSumWaves; ++v) t += acc[(size_t)v * nv + e];
+    pb[e] = t;
+  }
+}
 
-__global__ void __launch_bounds__(64) kmeans_sums_kernel(int64_t n, int dim, int nc,
-                                                         const float* __restrict__ Y,
-                                                         const int32_t* __restrict__ labels,
-                                                         double* __restrict__ part) {
-  __shared__ double acc_lds[kLdsSumDoubles];
+// many clusters: one wave per block accumulating into its own partial row
+__global__ void __launch_bounds__(64) kmeans_sums_global_kernel(int64_t n, int dim, int nc,
+                                                                const float* __restrict__ Y,
+                                                                const int32_t* __restrict__ labels,
+                                                                double* __restrict__ part) {
   const int lane = threadIdx.x;
   const int64_t per = (n + gridDim.x - 1) / gridDim.x;
   const int64_t r0 = (int64_t)blockIdx.x * per;
   const int64_t r1 = min(n, r0 + per);
   const int nv = nc * (dim + 1);
-  double* pb = part + (size_t)blockIdx.x * nv;
-  double* acc = nv <= kLdsSumDoubles ? acc_lds : pb;
+  double* acc = part + (size_t)blockIdx.x * nv;
   for (int e = lane; e < nv; e += 64) acc[e] = 0.0;
-  __syncthreads();
+  __syncthreads();  // zeroed by other lanes than those that accumulate
   for (int64_t r = r0; r < r1; ++r) {
     const int c = labels[r];
     if (lane < dim) acc[(size_t)c * (dim + 1) + lane] += (double)Y[r * dim + lane];
     if (lane == 0) acc[(size_t)c * (dim + 1) + dim] += 1.0;
   }
-  __syncthreads();
-  if (acc != pb)
-    for (int e = lane; e < nv; e += 64) pb[e] = acc[e];
 }
 
-__global__ void kmeans_final_kernel(int dim, int nc, const double* __restrict__ part, int nb,
-                                    const float* __restrict__ old_c, float* __restrict__ new_c) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nc * dim) return;
-  const int c = e / dim, d = e % dim;
-  double s = 0.0, cnt = 0.0;
-  for (int b = 0; b < nb; ++b) {
-    s += part[((size_t)b * nc + c) * (dim + 1) + d];
-    cnt += part[((size_t)b * nc + c) * (dim + 1) + dim];
+// centroid c = (sum of its rows) / count, or the old centroid when empty;
+// block c, lane = feature (two rounds for dim + 1 > 64), wave v sums the
+// blocks v, v + 4, ... in order, the four waves are added in order.
+__global__ void __launch_bounds__(kSumWaves * 64) kmeans_final_kernel(
+    int dim, int nc, const double* __restrict__ part, int nb, const float* __restrict__ old_c,
+    float* __restrict__ new_c) {
+  __shared__ double red[kSumWaves][2][64];
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nv = nc * (dim + 1);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int d = h * 64 + lane;
+    double s = 0.0;
+    if (d <= dim)
+      for (int b = w; b < nb; b += kSumWaves) s += part[(size_t)b * nv + (size_t)c * (dim + 1) + d];
+    red[w][h][lane] = s;
   }
-  new_c[e] = cnt > 0.0 ? (float)(s / cnt) : old_c[e];
+  __syncthreads();
+  if (w != 0) return;
+  double cnt = 0.0;
+  {
+    const int hc = dim / 64, lc = dim % 64;
+    for (int v = 0; v < kSumWaves; ++v) cnt += red[v][hc][lc];
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int d = h * 64 + lane;
+    if (d < dim) {
+      double t = 0.0;
+      for (int v = 0; v < kSumWaves; ++v) t += red[v][h][lane];
+      new_c[(size_t)c * dim + d] = cnt > 0.0 ? (float)(t / cnt) : old_c[(size_t)c * dim + d];
+    }
+  }
 }
 
 hipError_t launch_kmeans_centroid_sums(int64_t n, int dim, int nc, const float* Y,
                                        const int32_t* labels, double* part, int nb,
                                        hipStream_t s) {
-  hipLaunchKernelGGL(kmeans_sums_kernel, dim3(nb), dim3(64), 0, s, n, dim, nc, Y, labels, part);
+  const int nv = nc * (dim + 1);
+  if (nv <= kSumLdsDoubles)
+    hipLaunchKernelGGL(kmeans_sums_lds_kernel, dim3(nb), dim3(kSumWaves * 64),
+                       (size_t)kSumWaves * nv * sizeof(double), s, n, dim, nc, Y, labels, part);
+  else
+    hipLaunchKernelGGL(kmeans_sums_global_kernel, dim3(nb), dim3(64), 0, s, n, dim, nc, Y, labels,
+                       part);
   return hipGetLastError();
 }
 
 hipError_t launch_kmeans_centroid_final(int dim, int nc, const double* part, int nb,
                                         const float* old_c, float* new_c, hipStream_t s) {
-  const int tot = nc * dim;
-  hipLaunchKernelGGL(kmeans_final_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, dim, nc,
-                     part, nb, old_c, new_c);
+  hipLaunchKernelGGL(kmeans_final_kernel, dim3(nc), dim3(kSumWaves * 64), 0, s, dim, nc, part, nb,
+                     old_c, new_c);
   return hipGetLastError();
 }
 
-// d2[i] = min(d2[i], ||y_i - centre||^2)  (first: assignment)
-__global__ void kmeans_mindist_kernel(int64_t n, int dim, const float* __restrict__ Y,
-                                      const float* __restrict__ centre, float* __restrict__ d2,
-                                      int first) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float s = 0.0f;
-  for (int d = 0; d < dim; ++d) {
-    const float t = Y[i * dim + d] - centre[d];
-    s = fmaf(t, t, s);
+// ---------------------------------------------------------------------------
+// k-means++ seeding.  The points are cut into nb chunks of `per` rows.  A
+// chunk's running sums of D^2 (FP64) are formed in rounds of 256 rows with a
+// block-wide inclusive scan; the distance kernel stores the chunk totals, and
+// the pick kernel repeats the same rounds on the chosen chunk only, so both
+// see bitwise the same running sums.
+// ---------------------------------------------------------------------------
+constexpr int kScan = 256;
+constexpr int kPickChunks = 1024;
+
+int kmeans_pick_chunks(int64_t n) { return (int)(n < kPickChunks ? n : kPickChunks); }
+
+// inclusive scan of one value per thread over the block, fixed order
+__device__ inline double block_scan(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int o = 1; o < kScan; o <<= 1) {
+    const double add = t >= o ? sh[t - o] : 0.0;
+    __syncthreads();
+    v += add;
+    sh[t] = v;
+    __syncthreads();
   }
-  d2[i] = first ? s : fminf(d2[i], s);
+  return v;
+}
+
+// d2[i] = min(d2[i], ||y_i - centre||^2) (first: the distance itself), and
+// the chunk totals of d2 in sums[chunk]
+__global__ void __launch_bounds__(kScan) kmeans_mindist_kernel(int64_t n, int dim,
+                                                               const float* __restrict__ Y,
+                                                               const float* __restrict__ centre,
+                                                               float* __restrict__ d2, int first,
+                                                               int64_t per, int vec4,
+                                                               double* __restrict__ sums) {
+  __shared__ double sh[kScan];
+  __shared__ float cs[64];
+  if (threadIdx.x < dim) cs[threadIdx.x] = centre[threadIdx.x];
+  __syncthreads();
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = min(n, r0 + per);
+  double carry = 0.0;
+  for (int64_t base = r0; base < r1; base += kScan) {
+    const int64_t r = base + threadIdx.x;
+    double v = 0.0;
+    if (r < r1) {
+      float sq = 0.0f;
+      if (vec4) {
+        const float4* row = reinterpret_cast<const float4*>(Y + r * dim);
+        for (int q = 0; q < dim / 4; ++q) {
+          const float4 y = row[q];
+          float t = y.x - cs[4 * q];
+          sq = fmaf(t, t, sq);
+          t = y.y - cs[4 * q + 1];
+          sq = fmaf(t, t, sq);
+          t = y.z - cs[4 * q + 2];
+          sq = fmaf(t, t, sq);
+          t = y.w - cs[4 * q + 3];
+          sq = fmaf(t, t, sq);
+        }
+      } else {
+        for (int d = 0; d < dim; ++d) {
+          const float t = Y[r * dim + d] - cs[d];
+          sq = fmaf(t, t, sq);
+        }
+      }
+      const float nd = first ? sq : fminf(d2[r], sq);
+      d2[r] = nd;
+      v = (double)nd;
+    }
+    block_scan(v, sh);
+    const int last = (int)min((int64_t)kScan - 1, r1 - 1 - base);
+    carry += sh[last];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = carry;
 }
 
 hipError_t launch_kmeans_mindist(int64_t n, int dim, const float* Y, const float* centre,
-                                 float* d2, int first, hipStream_t s) {
-  hipLaunchKernelGGL(kmeans_mindist_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n,
-                     dim, Y, centre, d2, first);
+                                 float* d2, int first, double* sums, hipStream_t s) {
+  const int nb = kmeans_pick_chunks(n);
+  const int64_t per = (n + nb - 1) / nb;
+  const int vec4 = (dim % 4 == 0 && reinterpret_cast<uintptr_t>(Y) % 16 == 0) ? 1 : 0;
+  hipLaunchKernelGGL(kmeans_mindist_kernel, dim3(nb), dim3(kScan), 0, s, n, dim, Y, centre, d2,
+                     first, per, vec4, sums);
   return hipGetLastError();
 }
 
-// chunk sums of d2 (FP64, sequential within a chunk)
-__global__ void kmeans_chunksum_kernel(int64_t n, const float* __restrict__ d2,
-                                       double* __restrict__ sums, int nb) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
-  const int64_t per = (n + nb - 1) / nb;
-  const int64_t r0 = (int64_t)b * per;
-  const int64_t r1 = min(n, r0 + per);
-  double s = 0.0;
-  for (int64_t r = r0; r < r1; ++r) s += (double)d2[r];
-  sums[b] = s;
-}
-
-// first index whose running sum exceeds u * total (running sums in FP64)
-__global__ void kmeans_pick_kernel(int64_t n, const float* __restrict__ d2,
-                                   const double* __restrict__ sums, int nb, double u,
-                                   int32_t* pick) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double tot = 0.0;
-  for (int b = 0; b < nb; ++b) tot += sums[b];
-  if (!(tot > 0.0)) {
-    // every point coincides with a chosen centre: keep the previous pick
-    return;
+// first point whose running sum of d2 exceeds u * total; the previous pick
+// stays when the total is zero (every point sits on a chosen centre)
+__global__ void __launch_bounds__(kScan) kmeans_pick_kernel(int64_t n, const float* __restrict__ d2,
+                                                            const double* __restrict__ sums,
+                                                            int nb, int64_t per, double u,
+                                                            int32_t* pick) {
+  __shared__ double sh[kScan];
+  __shared__ double ex[kPickChunks];
+  __shared__ int best_b;
+  __shared__ unsigned long long best_r;
+  const int t = threadIdx.x;
+  // exclusive prefix sums of the chunk totals, rounds of 256 chunks
+  double carry = 0.0;
+  for (int base = 0; base < nb; base += kScan) {
+    const int b = base + t;
+    const double v = b < nb ? sums[b] : 0.0;
+    block_scan(v, sh);
+    if (b < nb) ex[b] = t == 0 ? carry : carry + sh[t - 1];
+    const int last = min(kScan - 1, nb - 1 - base);
+    carry += sh[last];
+    __syncthreads();
   }
+  const double tot = carry;
+  if (!(tot > 0.0)) return;
   const double target = u * tot;
-  const int64_t per = (n + nb - 1) / nb;
-  double run = 0.0;
-  int b = 0;
-  for (; b < nb; ++b) {
-    if (run + sums[b] > target) break;
-    run += sums[b];
+  if (t == 0) {
+    best_b = nb;
+    best_r = (unsigned long long)n;
   }
+  __syncthreads();
+  for (int b = t; b < nb; b += kScan)
+    if (ex[b] + sums[b] > target) atomicMin(&best_b, b);
+  __syncthreads();
+  const int b = best_b;
   if (b >= nb) {
-    pick[0] = (int32_t)(n - 1);
+    if (t == 0) pick[0] = (int32_t)(n - 1);
     return;
   }
+  // the same rounds as the distance kernel over chunk b
+  const double exb = ex[b];
   const int64_t r0 = (int64_t)b * per;
   const int64_t r1 = min(n, r0 + per);
-  int64_t r = r0;
-  for (; r < r1; ++r) {
-    run += (double)d2[r];
-    if (run > target) break;
+  double lc = 0.0;
+  for (int64_t base = r0; base < r1; base += kScan) {
+    const int64_t r = base + t;
+    const double v = r < r1 ? (double)d2[r] : 0.0;
+    const double incl = block_scan(v, sh);
+    if (r < r1 && exb + (lc + incl) > target) atomicMin(&best_r, (unsigned long long)r);
+    const int last = (int)min((int64_t)kScan - 1, r1 - 1 - base);
+    lc += sh[last];
+    __syncthreads();
+    if (best_r < (unsigned long long)n) break;
   }
-  pick[0] = (int32_t)min(r, n - 1);
+  if (t == 0) pick[0] = (int32_t)(best_r < (unsigned long long)n ? (int64_t)best_r : r1 - 1);
 }
 
-hipError_t launch_kmeans_pick(int64_t n, const float* d2, double u, double* blocksums, int nb,
+hipError_t launch_kmeans_pick(int64_t n, const float* d2, double u, const double* sums,
                               int32_t* pick, hipStream_t s) {
-  hipLaunchKernelGGL(kmeans_chunksum_kernel, dim3((nb + 63) / 64), dim3(64), 0, s, n, d2,
-                     blocksums, nb);
-  hipLaunchKernelGGL(kmeans_pick_kernel, dim3(1), dim3(64), 0, s, n, d2, blocksums, nb, u, pick);
+  const int nb = kmeans_pick_chunks(n);
+  const int64_t per = (n + nb - 1) / nb;
+  hipLaunchKernelGGL(kmeans_pick_kernel, dim3(1), dim3(kScan), 0, s, n, d2, sums, nb, per, u,
+                     pick);
   return hipGetLastError();
 }
 

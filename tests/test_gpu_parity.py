@@ -465,6 +465,52 @@ def test_assign_shapes(ofm, n, dim, nc):
     check_assign(lab.cpu().numpy(), host(d2), O.kmeans_dist2(Y, C))
 
 
+def means_by_label(Y, lab, nc, old):
+    """Cluster means in FP64 (an empty cluster keeps its old centre)."""
+    out = np.array(old, dtype=np.float64, copy=True)
+    for c in range(nc):
+        m = lab == c
+        if m.any():
+            out[c] = Y[m].mean(axis=0)
+    return out
+
+
+@pytest.mark.parametrize("n,dim,nc", [(7, 3, 7), (3001, 8, 6), (50_000, 64, 40), (200_003, 32, 32)])
+def test_kmeans_seeding_update_and_fixed_point(ofm, n, dim, nc):
+    """k-means++ seeds (the oracle's picks, seen through the first assignment),
+    one Lloyd update (means by the device's labels) and the converged state (a
+    fixed point of Lloyd) on blobs: n = clusters (every point a centre), a row
+    count that does not divide into the seeding chunks, more cluster sums than
+    the LDS holds (40 x 65), and a larger ragged case."""
+    rng = np.random.default_rng(n + nc)
+    centers = rng.standard_normal((nc, dim)) * 8
+    truth = rng.integers(0, nc, size=n)
+    Y = (centers[truth] + rng.standard_normal((n, dim))).astype(np.float32)
+    Y64 = Y.astype(np.float64)
+    u = O.kmeans_uniforms(5, nc)
+    seeds = O.kmeanspp_init(Y64, nc, u)
+    Yd = dev(Y, torch.float32)
+    lab1, cent1, it1 = ofm.kmeans(Yd, nc, u, max_iter=1)
+    lab1 = lab1.cpu().numpy()
+    assert it1 == 1
+    D = O.kmeans_dist2(Y64, seeds)
+    check_assign(lab1, D[np.arange(n), lab1], D)
+    np.testing.assert_allclose(host(cent1), means_by_label(Y64, lab1, nc, seeds),
+                               atol=1e-5 * max(1.0, np.abs(seeds).max()))
+    lab, cent, it = ofm.kmeans(Yd, nc, u)
+    lab = lab.cpu().numpy()
+    C = host(cent)
+    assert it < 300
+    D = O.kmeans_dist2(Y64, C)
+    check_assign(lab, D[np.arange(n), lab], D)
+    np.testing.assert_allclose(C, means_by_label(Y64, lab, nc, C),
+                               atol=1e-5 * max(1.0, np.abs(C).max()))
+    if n <= 5000:
+        lab_o, cent_o, it_o = O.kmeans_lloyd(Y64, seeds)
+        assert O.ari(lab, lab_o) == pytest.approx(1.0)
+        assert abs(it - it_o) <= 1
+
+
 def test_kmeans_matches_oracle_on_blobs(ofm):
     rng = np.random.default_rng(3)
     centers = rng.standard_normal((6, 8)) * 5
