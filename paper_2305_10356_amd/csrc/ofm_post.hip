@@ -325,14 +325,23 @@ __global__ void __launch_bounds__(kSumWaves * 64) kmeans_sums_lds_kernel(
   const int64_t len = r1 > r0 ? r1 - r0 : 0;
   const int64_t w0 = r0 + len * w / kSumWaves, w1 = r0 + len * (w + 1) / kSumWaves;
   double* a = acc + (size_t)w * nv;
+  // the loads of a batch are unconditional (row and feature clamped into
+  // range, the value masked afterwards) so that all of them are in flight
+  // together
+  const int f = lane < dim ? lane : dim - 1;
   for (int64_t rb = w0; rb < w1; rb += kSumRows) {
     int lab[kSumRows];
     float y[kSumRows];
 #pragma unroll
     for (int q = 0; q < kSumRows; ++q) {
-      const int64_t r = rb + q;
-      lab[q] = r < w1 ? labels[r] : -1;
-      y[q] = (r < w1 && lane < dim) ? Y[r * dim + lane] : 0.0f;
+      const int64_t r = rb + q < w1 ? rb + q : w1 - 1;
+      lab[q] = labels[r];
+      y[q] = Y[r * dim + f];
+    }
+#pragma unroll
+    for (int q = 0; q < kSumRows; ++q) {
+      if (rb + q >= w1) lab[q] = -1;
+      if (lane >= dim) y[q] = 0.0f;
     }
 #pragma unroll
     for (int q = 0; q < kSumRows; ++q) {
@@ -382,13 +391,24 @@ __global__ void __launch_bounds__(kSumWaves * 64) kmeans_final_kernel(
   const int c = blockIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int nv = nc * (dim + 1);
+  constexpr int kB = 8;  // partial rows whose loads are in flight together
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int d = h * 64 + lane;
+    const int dc = d <= dim ? d : dim;
     double s = 0.0;
-    if (d <= dim)
-      for (int b = w; b < nb; b += kSumWaves) s += part[(size_t)b * nv + (size_t)c * (dim + 1) + d];
-    red[w][h][lane] = s;
+    for (int b0 = w; b0 < nb; b0 += kB * kSumWaves) {
+      double x[kB];
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        const int b = b0 + q * kSumWaves;
+        x[q] = part[(size_t)(b < nb ? b : nb - 1) * nv + (size_t)c * (dim + 1) + dc];
+      }
+#pragma unroll
+      for (int q = 0; q < kB; ++q)
+        if (b0 + q * kSumWaves < nb) s += x[q];
+    }
+    red[w][h][lane] = d <= dim ? s : 0.0;
   }
   __syncthreads();
   if (w != 0) return;
@@ -597,9 +617,10 @@ hipError_t launch_kmeans_copy_centre(int dim, const float* Y, const int32_t* pic
 __global__ void count_changes_kernel(int64_t n, const int32_t* __restrict__ a,
                                      const int32_t* __restrict__ b, int* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int ch = (i < n && a[i] != b[i]) ? 1 : 0;
-  // any change is enough
-  if (__any(ch) && (threadIdx.x & 63) == 0) atomicOr(out, 1);
+  const int ch = (i < n && a[i] != b[i]) ? 1 : 0;
+  // any change is enough: one atomic per block, not one per wavefront (many
+  // atomics on one word serialize)
+  if (__syncthreads_or(ch) && threadIdx.x == 0) atomicOr(out, 1);
 }
 
 hipError_t launch_count_changes(int64_t n, const int32_t* a, const int32_t* b, int* out,
