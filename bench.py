@@ -320,6 +320,9 @@ def main():
                     help="headline loop with A X by recurrence between residual checks")
     ap.add_argument("--streaming-only", action="store_true",
                     help="run only the streaming warm-start workload; prints its JSON")
+    ap.add_argument("--gather", default="auto", choices=["auto", "default", "hot-cold"],
+                    help="cache policy of the SpMM row gathers of the headline loop (auto: "
+                         "timed at workspace creation)")
     ap.add_argument("--postprocess-only", action="store_true",
                     help="solve the 2M-node graph to residual 1e-4, then time only the "
                          "post-processing (row normalisation, K-means); prints its JSON")
@@ -392,7 +395,9 @@ def main():
         del src, dst
 
     # ---------------- headline: iterations/s of the chosen variant ----------
-    ws, X = make(args.variant, recur=args.recur)
+    gather = {"auto": ofm.GATHER_AUTO, "default": ofm.GATHER_DEFAULT,
+              "hot-cold": ofm.GATHER_HOT_COLD}[args.gather]
+    ws, X = make(args.variant, recur=args.recur, gather=gather)
     ws.init(X)
     for _ in range(args.warmup):
         ws.step(X)
@@ -510,6 +515,28 @@ def main():
         t1 = time.perf_counter()
         st7 = w7.solve(X7)
         torch.cuda.synchronize()
+        # the two gather policies of the SpMMs, each forced, same loop
+        pol = {}
+        for name, gp in (("default", ofm.GATHER_DEFAULT), ("hot/cold", ofm.GATHER_HOT_COLD)):
+            wg, Xg = make(args.variant, gather=gp)
+            wg.init(Xg)
+            for _ in range(5):
+                wg.step(Xg)
+            wg.set_timing(["spmm_x", "spmm_v"])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(30):
+                wg.step(Xg)
+            torch.cuda.synchronize()
+            rate = 30 / (time.perf_counter() - t1)
+            wg.set_timing(False)
+            tg = wg.timing(reset=True)
+            pol[name] = {"iters_per_s": round(rate, 1),
+                         "spmm_x_us": round(1e3 * tg["spmm_x"][0] / max(tg["spmm_x"][1], 1), 1),
+                         "spmm_v_us": round(1e3 * tg["spmm_v"][0] / max(tg["spmm_v"][1], 1), 1)}
+            wg.close()
+            del Xg
+        extras["gather_policy"] = pol
         extras["recur_ax"] = {
             "iters_per_s": round(rec_rate, 1),
             "pass_us": {p: round(1e3 * v[0] / v[1], 1) for p, v in tm6.items() if v[1]},
@@ -601,7 +628,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"dcsbm N={n} k={k} mean-degree 25 power-law 2.5 r=0.5 (nnz={nnz})",
                    "variant": args.variant, "precision": "fp32 passes, fp64 k x k products",
-                   "check_every": 10, "recur_ax": bool(args.recur), "graph": gstats},
+                   "check_every": 10, "recur_ax": bool(args.recur),
+                   "gather": {1: "default", 2: "hot/cold"}[stats["gather"]], "graph": gstats},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "passes": passes,

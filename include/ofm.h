@@ -107,6 +107,17 @@ typedef struct ofm_opts {
                        with A per update in between.  Same iteration in exact
                        arithmetic; rounding differs.  Needs one more N x k
                        buffer (A V).                                          */
+  int gather;       /* cache policy of the row gathers of the products with A:
+                       1: default; 2: hot/cold, rows of the less connected
+                       columns (below the top fifth of rows by entry count,
+                       marked when the Laplacian is built) loaded
+                       non-temporally so that they do not evict the rows
+                       gathered most often; 0: time both once at
+                       ofm_workspace_create and keep the faster (only when
+                       the N x k block is at least 32 MB, else 1).  Results
+                       are bitwise the same.  2 is refused (OFM_E_UNSUPPORTED)
+                       for OFM_FP32_BF16X and for blocks of 2 GB or more.
+                       The batched solver always uses 1.                      */
 } ofm_opts;
 
 typedef struct ofm_stats {
@@ -120,6 +131,8 @@ typedef struct ofm_stats {
                         -1 if none was computed yet                           */
   double objective;  /* f1 or f2 at the X of the last residual                */
   int64_t relres_iter; /* iteration whose X the residual belongs to           */
+  int32_t gather;    /* gather policy in use (1 default, 2 hot/cold)          */
+  int32_t reserved;
 } ofm_stats;
 
 /* Human-readable name of a status code (static string). */

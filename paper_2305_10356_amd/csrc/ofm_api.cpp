@@ -133,6 +133,7 @@ struct ofm_workspace_s {
   bool initialized = false;
   const TileTable* tiles = nullptr;
   const void* pk = nullptr;
+  bool hc = false;       // gathers with the hot/cold cache policy (opts.gather)
   // per-pass event timing
   unsigned timing = 0;   // bit i: record events around the kernels of pass i
   struct Pending {
@@ -217,6 +218,13 @@ static void free_lap(ofm_laplacian L) {
   for (auto& t : L->tt) dev_free(t.dev);
   delete L;
 }
+
+// Share of the rows, by entry count, whose gathers keep the default cache
+// policy when a workspace gathers with the hot/cold policy: the rows of the
+// other columns are loaded non-temporally so they do not evict the rows that
+// are gathered often (on a power-law graph the top fifth of the rows receive
+// over half of the gathers).
+constexpr double kHotShare = 0.2;
 
 static std::vector<int32_t> build_tiles(const std::vector<int32_t>& sdeg, int tr, bool reorder) {
   // tiles of consecutive positions: rows of degree >= kHeavyDeg (first when
@@ -341,8 +349,24 @@ extern "C" ofm_status ofm_build_laplacian(int64_t n, int64_t nnz, const int32_t*
       hipMemcpyAsync(g.sptr, sptr.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
                      stream) != hipSuccess)
     return fail(OFM_E_HIP);
-  if (launch_graph_pack(n, g.sched, row_ptr, col_idx, w64, g.sptr, g.pk32, g.pk64, stream) !=
-      hipSuccess)
+  // cold mark: rows with fewer entries than the top kHotShare of rows by
+  // entry count (ties at the cut count as hot); none when every row ties
+  {
+    int32_t mx = 0;
+    for (int64_t i = 0; i < n; ++i) mx = std::max(mx, hrp[i + 1] - hrp[i]);
+    std::vector<int64_t> hist((size_t)mx + 1, 0);
+    for (int64_t i = 0; i < n; ++i) ++hist[(size_t)(hrp[i + 1] - hrp[i])];
+    const int64_t want = std::max<int64_t>(1, (int64_t)(kHotShare * (double)n));
+    int64_t seen = 0;
+    int32_t cut = mx;
+    for (; cut > 0; --cut) {
+      seen += hist[(size_t)cut];
+      if (seen >= want) break;
+    }
+    g.cold_below = cut;
+  }
+  if (launch_graph_pack(n, g.sched, row_ptr, col_idx, w64, g.sptr, g.pk32, g.pk64, g.cold_below,
+                        stream) != hipSuccess)
     return fail(OFM_E_HIP);
   const int trs[3] = {16, 32, 64};
   for (int i = 0; i < 3; ++i) {
@@ -392,6 +416,7 @@ static void fill_graph(PassArgs& a, ofm_laplacian lap, const TileTable* tt, int 
   a.tiles = tt->dev;
   a.ntiles = tt->ntiles;
   a.pk = precision == OFM_FP64 ? lap->g.pk64 : lap->g.pk32;
+  a.cold_below = lap->g.cold_below;
 }
 
 extern "C" ofm_status ofm_apply_A(ofm_laplacian lap, int k, int precision, const void* Z, void* Y,
@@ -445,6 +470,56 @@ static void free_ws(ofm_workspace ws) {
   delete ws;
 }
 
+// Blocks from which the gather policy is chosen by timing (smaller ones fit
+// the caches and keep the default policy).
+constexpr size_t kHcMinBytes = size_t(32) << 20;
+
+// Times Y = A Z with the default and with the hot/cold gather policy on the
+// workspace's own buffers (Z = V[0], zeroed; Y = AX), alternating the two,
+// and reports whether hot/cold was faster by more than 3%.  Synchronizing.
+static ofm_status choose_gather(ofm_workspace ws, bool* hc) {
+  PassArgs a;
+  a.n = ws->n;
+  a.k = ws->k;
+  a.mode = kApply;
+  a.Z = ws->V[0];
+  a.Y = ws->AX;
+  fill_graph(a, ws->lap, ws->tiles, ws->prec);
+  a.nblocks = pass_blocks(ws->prec, ws->k, ws->tiles->ntiles);
+  if (hipMemset(ws->V[0], 0, (size_t)ws->n * ws->k * ws->esz) != hipSuccess)
+    return OFM_E_HIP;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess) return OFM_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return OFM_E_HIP;
+  }
+  ofm_status st = OFM_OK;
+  auto run = [&](bool with_hc, float* ms) {
+    PassArgs b = a;
+    b.flags = with_hc ? kFlagHC : 0;
+    float t = 0.0f;
+    if (hipEventRecord(e0, nullptr) != hipSuccess ||
+        launch_spmm(ws->prec, ws->k, b, nullptr) != hipSuccess ||
+        hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+      st = OFM_E_HIP;
+    if (ms) *ms += t;
+  };
+  float t_def = 0.0f, t_hc = 0.0f;
+  run(false, nullptr);  // warm-up of both
+  run(true, nullptr);
+  for (int r = 0; r < 2 && st == OFM_OK; ++r) {
+    run(false, &t_def);
+    run(true, &t_hc);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != OFM_OK) return st;
+  *hc = t_hc < 0.97f * t_def;
+  return OFM_OK;
+}
+
 extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_opts* host_opts,
                                            ofm_workspace* out) {
   if (!out) return OFM_E_INVALID_ARG;
@@ -460,6 +535,7 @@ extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_o
   if (!std::isfinite(o.alpha0) || !(o.tol >= 0.0)) return OFM_E_INVALID_ARG;
   if (o.graph != 0 && o.graph != 1) return OFM_E_INVALID_ARG;
   if (o.recur != 0 && o.recur != 1) return OFM_E_INVALID_ARG;
+  if (o.gather < 0 || o.gather > 2) return OFM_E_INVALID_ARG;
   const int prec = o.precision == OFM_FP64 ? OFM_FP64 : OFM_FP32;
   if (!supported_k(k, prec)) return prec == OFM_FP64 && k == 64 ? OFM_E_UNSUPPORTED : OFM_E_SHAPE;
   if (k > lap->g.n) return OFM_E_SHAPE;
@@ -503,6 +579,15 @@ extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_o
       hipMemset(ws->frozen, 0, sizeof(int)) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess)
     return fail(OFM_E_HIP);
+  // gather policy: the hot/cold path addresses the block with 31-bit offsets
+  const bool hc_ok = o.precision != OFM_FP32_BF16X && blk <= (size_t)0x7fffffff;
+  if (o.gather == 2 && !hc_ok) return fail(OFM_E_UNSUPPORTED);
+  ws->hc = o.gather == 2;
+  if (o.gather == 0 && hc_ok && blk >= kHcMinBytes && lap->g.cold_below > 0) {
+    bool hc = false;
+    if ((st = choose_gather(ws, &hc)) != OFM_OK) return fail(st);
+    ws->hc = hc;
+  }
   *out = ws;
   return OFM_OK;
 }
@@ -542,6 +627,7 @@ static ofm_status finalize(ofm_workspace ws, const PassArgs& a, hipStream_t s) {
 
 static ofm_status run_spmm(ofm_workspace ws, PassArgs& a, hipStream_t s) {
   fill_graph(a, ws->lap, ws->tiles, ws->prec);
+  if (ws->hc) a.flags |= kFlagHC;
   a.nblocks = pass_blocks(ws->prec, ws->k, ws->tiles->ntiles);
   HIPCHK(timed(ws, pass_kind(a.mode), s, [&] { return launch_spmm(ws->prec, ws->k, a, s); }));
   return finalize(ws, a, s);
@@ -735,6 +821,8 @@ static ofm_status read_stats(ofm_workspace ws, hipStream_t stream, ofm_stats* o)
   o->relres_iter = ws->last_check;
   o->status = (st & kStNonfinite) ? OFM_E_NONFINITE : (st & kStCholesky) ? OFM_E_NUMERIC : OFM_OK;
   o->converged = (ws->last_check >= 0 && ws->opts.tol > 0.0 && rv[0] <= ws->opts.tol) ? 1 : 0;
+  o->gather = ws->hc ? 2 : 1;
+  o->reserved = 0;
   return OFM_OK;
 }
 
@@ -1174,6 +1262,7 @@ extern "C" ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps
   if (o.max_iter < 1 || o.check_every < 1 || !(o.tol >= 0.0)) return OFM_E_INVALID_ARG;
   if (o.first_step != 0 && o.first_step != 1) return OFM_E_INVALID_ARG;
   if ((o.restart | o.graph | o.recur) & ~1) return OFM_E_INVALID_ARG;
+  if (o.gather < 0 || o.gather > 2) return OFM_E_INVALID_ARG;
   for (int i = 0; i < count; ++i) {
     if (!host_laps[i]) return OFM_E_INVALID_ARG;
     if (!supported_k(host_ks[i], OFM_FP32) || host_ks[i] > host_laps[i]->g.n) return OFM_E_SHAPE;
@@ -1313,6 +1402,7 @@ static ofm_status finish_fp64(ofm_laplacian L, int k, const ofm_opts& o, int64_t
   o64.max_iter = (int)(o.max_iter - used);
   o64.first_step = 0;
   o64.recur = 0;
+  o64.gather = 1;  // no timing runs on the shared device from the finishing threads
   ofm_workspace ws = nullptr;
   ofm_status es = ofm_workspace_create(L, k, &o64, &ws);
   if (es != OFM_OK) return es;

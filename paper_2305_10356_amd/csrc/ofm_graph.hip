@@ -119,13 +119,15 @@ struct __align__(16) PkEnt64 {
   double w;
 };
 
-// entries of the row at position p, copied to the packed stream at sptr[p]
+// entries of the row at position p, copied to the packed stream at sptr[p];
+// a column whose row has fewer than cold_below entries (a rarely gathered row)
+// is stored with its sign bit set, which the gathers mask off
 __global__ void graph_pack_kernel(int64_t n, const int32_t* __restrict__ sched,
                                   const int32_t* __restrict__ row_ptr,
                                   const int32_t* __restrict__ col_idx,
                                   const double* __restrict__ w64,
                                   const int32_t* __restrict__ sptr, PkEnt32* __restrict__ pk32,
-                                  PkEnt64* __restrict__ pk64) {
+                                  PkEnt64* __restrict__ pk64, int cold_below) {
   const int64_t p = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   const int lane = threadIdx.x & 63;
   if (p >= n) return;
@@ -133,7 +135,9 @@ __global__ void graph_pack_kernel(int64_t n, const int32_t* __restrict__ sched,
   const int64_t b = row_ptr[row], e = row_ptr[row + 1];
   const int64_t o = sptr[p];
   for (int64_t t = b + lane; t < e; t += 64) {
-    const int c = col_idx[t];
+    const int c0 = col_idx[t];
+    const int c = (row_ptr[c0 + 1] - row_ptr[c0] < cold_below) ? (int)((unsigned)c0 | 0x80000000u)
+                                                               : c0;
     const double w = w64[t];
     if (pk32) pk32[o + (t - b)] = PkEnt32{c, (float)w};
     if (pk64) pk64[o + (t - b)] = PkEnt64{c, 0, w};
@@ -175,11 +179,11 @@ hipError_t launch_graph_weights(int64_t n, const int32_t* row_ptr, const int32_t
 
 hipError_t launch_graph_pack(int64_t n, const int32_t* sched, const int32_t* row_ptr,
                              const int32_t* col_idx, const double* w64, const int32_t* sptr,
-                             void* pk32, void* pk64, hipStream_t s) {
+                             void* pk32, void* pk64, int cold_below, hipStream_t s) {
   const int64_t nb = (n + 3) / 4;
   hipLaunchKernelGGL(graph_pack_kernel, dim3((unsigned)nb), dim3(256), 0, s, n, sched, row_ptr,
                      col_idx, w64, sptr, static_cast<PkEnt32*>(pk32),
-                     static_cast<PkEnt64*>(pk64));
+                     static_cast<PkEnt64*>(pk64), cold_below);
   return hipGetLastError();
 }
 

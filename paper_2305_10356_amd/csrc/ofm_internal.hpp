@@ -105,6 +105,7 @@ struct LaplacianDev {
   int32_t* col_idx = nullptr;  // [nnz]
   double* w64_csr = nullptr;   // [nnz] w_ij in input CSR order
   bool reorder = true;
+  int cold_below = 0;          // columns of rows with fewer entries carry the cold mark
 };
 
 // Arguments of the N x k kernels (everything a mode may need).
@@ -134,6 +135,7 @@ struct PassArgs {
   const int32_t* tiles = nullptr;
   int64_t ntiles = 0;
   const void* pk = nullptr;
+  int cold_below = 0;          // rows with fewer entries are cold (kFlagHC)
   // BF16 copies: gather source of the SpMM (null: gather Z itself) and the
   // copies written by the producing passes
   const void* Zg = nullptr;
@@ -141,7 +143,8 @@ struct PassArgs {
   void* Vb = nullptr;
 };
 
-enum : int { kFlagCheck = 1, kFlagRestart = 2, kFlagFirst = 4, kFlagH = 8 };
+// kFlagHC: gathers of rows with the cold mark use the non-temporal policy
+enum : int { kFlagCheck = 1, kFlagRestart = 2, kFlagFirst = 4, kFlagH = 8, kFlagHC = 16 };
 
 // Batched solves: one launch per pass covers every graph of a width group.
 struct BatchGraph {
@@ -226,7 +229,7 @@ hipError_t launch_graph_weights(int64_t n, const int32_t* row_ptr, const int32_t
                                 double* w64, double* normA2_parts, hipStream_t s);
 hipError_t launch_graph_pack(int64_t n, const int32_t* sched, const int32_t* row_ptr,
                              const int32_t* col_idx, const double* w64, const int32_t* sptr,
-                             void* pk32, void* pk64, hipStream_t s);
+                             void* pk32, void* pk64, int cold_below, hipStream_t s);
 
 // Post-processing (ofm_post.hip)
 hipError_t launch_convert(int64_t count, int to_fp64, const void* src, void* dst, hipStream_t s);

@@ -70,6 +70,34 @@ template <typename T>
 __device__ inline void st16(T* p, const V16<T>& r) {
   *reinterpret_cast<uint4*>(p) = *reinterpret_cast<const uint4*>(&r);
 }
+// a row part read once in a pass: with NT the load carries the non-temporal
+// hint
+template <bool NT, typename T>
+__device__ inline V16<T> ld16_in(const T* p) {
+  if constexpr (NT) {
+    typedef unsigned u4v __attribute__((ext_vector_type(4)));
+    const u4v v = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(p));
+    V16<T> r;
+    __builtin_memcpy(&r, &v, 16);
+    return r;
+  } else {
+    return ld16(p);
+  }
+}
+// a streamed output row part: with NT the store carries the non-temporal
+// hint (used with the hot/cold gathers, so that outputs written once do not
+// take cache room from the rows gathered often)
+template <bool NT, typename T>
+__device__ inline void st16_out(T* p, const V16<T>& r) {
+  if constexpr (NT) {
+    typedef unsigned u4v __attribute__((ext_vector_type(4)));
+    u4v v;
+    __builtin_memcpy(&v, &r, 16);
+    __builtin_nontemporal_store(v, reinterpret_cast<u4v*>(p));
+  } else {
+    st16(p, r);
+  }
+}
 
 struct __align__(8) Ent32 {
   int col;
@@ -212,12 +240,35 @@ __device__ inline V16<T> load_row_part(const void* Z, int c, int j) {
   }
 }
 
+// lane part j of gathered row c through a buffer load whose cache policy is
+// an immediate: AUX = 2 is the non-temporal policy, 0 the default.  The byte
+// offset fits in 31 bits (the hot/cold path is taken only for such blocks).
+template <typename T, int KP, int AUX>
+__device__ inline V16<T> load_row_buf(__amdgpu_buffer_rsrc_t r, int c, int j) {
+  using G = Geo<T, KP>;
+  const int off = (c * KP + j * G::VECN) * (int)sizeof(T);
+  const auto u = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, AUX);
+  V16<T> v;
+  __builtin_memcpy(&v, &u, 16);
+  return v;
+}
+
+// buffer resource over the N x KP block Z (raw, bounds-checked by size)
+template <typename T, int KP>
+__device__ inline __amdgpu_buffer_rsrc_t block_rsrc(const void* Z, int64_t n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(Z), (short)0,
+                                           (int)(n * KP * (int64_t)sizeof(T)), 0x00020000);
+}
+
 // Sum of S_ij-weighted rows Z_j over entries [e_first, end) taken in chunks;
-// the LPR lanes of a group share every entry through lane shuffles.
-template <typename T, int KP, bool BF = false>
+// the LPR lanes of a group share every entry through lane shuffles.  The
+// sign bit of a packed column index is the cold mark: masked off, or with HC
+// it selects the non-temporal policy for that row's gather.
+template <typename T, int KP, bool BF = false, bool HC = false>
 __device__ inline void gather_rows(const typename EntT<T>::type* __restrict__ pk,
                                    const void* __restrict__ Z, int e_first, int end, int cstride,
-                                   int gbase, int j, V16<T>& acc) {
+                                   int gbase, int j, V16<T>& acc,
+                                   __amdgpu_buffer_rsrc_t zr = __amdgpu_buffer_rsrc_t()) {
   using G = Geo<T, KP>;
   constexpr int CH = G::LPR >= kGatherChunk ? G::LPR : kGatherChunk;
   constexpr int PER = CH / G::LPR;
@@ -240,9 +291,15 @@ __device__ inline void gather_rows(const typename EntT<T>::type* __restrict__ pk
 #pragma unroll
     for (int s = 0; s < CH; ++s) {
       const int src = gbase + (s % G::LPR);
-      const int c = __shfl(col[s / G::LPR], src);
+      const int cm = __shfl(col[s / G::LPR], src);
+      const int c = cm & 0x7fffffff;
       if (e0 + s < end) {
-        z[s] = load_row_part<T, KP, BF>(Z, c, j);
+        if constexpr (HC) {
+          if (cm < 0) z[s] = load_row_buf<T, KP, 2>(zr, c, j);
+          else z[s] = load_row_buf<T, KP, 0>(zr, c, j);
+        } else {
+          z[s] = load_row_part<T, KP, BF>(Z, c, j);
+        }
       } else {
 #pragma unroll
         for (int q = 0; q < G::VECN; ++q) z[s].v[q] = T(0);
@@ -450,7 +507,7 @@ __device__ inline bool all_finite(T x) {
 
 // One pass over the tiles brank, brank + nblk, ... of a graph (a grid of its
 // own, or a share of a batched launch); writes the block's partial row brank.
-template <typename T, int KP, int MODE, bool CHECK, bool BF>
+template <typename T, int KP, int MODE, bool CHECK, bool BF, bool HC = false>
 __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk,
                                           unsigned char* smem) {
   using G = Geo<T, KP>;
@@ -470,6 +527,8 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
   const bool restart = (a.flags & kFlagRestart) != 0;
   const T* __restrict__ Z = static_cast<const T*>(a.Z);
   const auto* __restrict__ pk = static_cast<const typename EntT<T>::type*>(a.pk);
+  __amdgpu_buffer_rsrc_t zr = __amdgpu_buffer_rsrc_t();
+  if constexpr (HC) zr = block_rsrc<T, KP>(a.Z, a.n);
   const int g = lane / G::LPR;
   const int j = lane % G::LPR;
   const double* sc = a.sc;
@@ -508,20 +567,22 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
           V16<T> acc;
 #pragma unroll
           for (int q = 0; q < G::VECN; ++q) acc.v[q] = T(0);
-          gather_rows<T, KP, BF>(pk, BF ? a.Zg : a.Z, beg, end,
-                                 G::LPR >= kGatherChunk ? G::LPR : kGatherChunk, g * G::LPR, j,
-                                 acc);
-          const V16<T> z = ld16(Z + (size_t)row * KP + j * G::VECN);
+          gather_rows<T, KP, BF, HC>(pk, BF ? a.Zg : a.Z, beg, end,
+                                     G::LPR >= kGatherChunk ? G::LPR : kGatherChunk, g * G::LPR,
+                                     j, acc, zr);
+          const V16<T> z = (HC && end - beg < a.cold_below)
+                                ? ld16_in<HC>(Z + (size_t)row * KP + j * G::VECN)
+                                : ld16(Z + (size_t)row * KP + j * G::VECN);
 #pragma unroll
           for (int q = 0; q < G::VECN; ++q) acc.v[q] = -z.v[q] - acc.v[q];
           if (j == 0) trow[gi] = row;
           if (MODE == kApply || MODE == kAXF2) {
-            st16(static_cast<T*>(a.Y) + (size_t)row * KP + j * G::VECN, acc);
+            st16_out<HC>(static_cast<T*>(a.Y) + (size_t)row * KP + j * G::VECN, acc);
           }
           if (MODE == kAVF1 || MODE == kAVF2) {
 #pragma unroll
             for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)z.v[q] * (double)acc.v[q];
-            if (a.Y) st16(static_cast<T*>(a.Y) + (size_t)row * KP + j * G::VECN, acc);
+            if (a.Y) st16_out<HC>(static_cast<T*>(a.Y) + (size_t)row * KP + j * G::VECN, acc);
           }
           if (SM::NB > 0) {
             tile_store_vec<T, KP>(tA, gi, j, acc);
@@ -538,25 +599,27 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
         V16<T> acc;
 #pragma unroll
         for (int q = 0; q < G::VECN; ++q) acc.v[q] = T(0);
-        gather_rows<T, KP, BF>(pk, BF ? a.Zg : a.Z, beg + g * CH, end, G::RPW * CH, g * G::LPR,
-                               j, acc);
+        gather_rows<T, KP, BF, HC>(pk, BF ? a.Zg : a.Z, beg + g * CH, end, G::RPW * CH,
+                                   g * G::LPR, j, acc, zr);
 #pragma unroll
         for (int q = 0; q < G::VECN; ++q) {
 #pragma unroll
           for (int o = G::LPR; o < kWave; o <<= 1) acc.v[q] += __shfl_xor(acc.v[q], o);
         }
         if (g == 0) {
-          const V16<T> z = ld16(Z + (size_t)row * KP + j * G::VECN);
+          const V16<T> z = (HC && end - beg < a.cold_below)
+                                ? ld16_in<HC>(Z + (size_t)row * KP + j * G::VECN)
+                                : ld16(Z + (size_t)row * KP + j * G::VECN);
 #pragma unroll
           for (int q = 0; q < G::VECN; ++q) acc.v[q] = -z.v[q] - acc.v[q];
           if (j == 0) trow[gi] = row;
           if (MODE == kApply || MODE == kAXF2) {
-            st16(static_cast<T*>(a.Y) + (size_t)row * KP + j * G::VECN, acc);
+            st16_out<HC>(static_cast<T*>(a.Y) + (size_t)row * KP + j * G::VECN, acc);
           }
           if (MODE == kAVF1 || MODE == kAVF2) {
 #pragma unroll
             for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)z.v[q] * (double)acc.v[q];
-            if (a.Y) st16(static_cast<T*>(a.Y) + (size_t)row * KP + j * G::VECN, acc);
+            if (a.Y) st16_out<HC>(static_cast<T*>(a.Y) + (size_t)row * KP + j * G::VECN, acc);
           }
           if (SM::NB > 0) {
             tile_store_vec<T, KP>(tA, gi, j, acc);
@@ -590,11 +653,11 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
 #pragma unroll
           for (int q = 0; q < G::VECN; ++q) gv.v[q] = cf * (ax.v[q] + d.v[q]);
           const size_t off = (size_t)row * KP + j * G::VECN;
-          st16(static_cast<T*>(a.G) + off, gv);
+          st16_out<HC>(static_cast<T*>(a.G) + off, gv);
 #pragma unroll
           for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)gv.v[q] * (double)gv.v[q];
           if (a.Gp) {
-            const V16<T> gp = ld16(static_cast<const T*>(a.Gp) + off);
+            const V16<T> gp = ld16_in<HC>(static_cast<const T*>(a.Gp) + off);
 #pragma unroll
             for (int q = 0; q < G::VECN; ++q) cacc[1][q] += (double)gp.v[q] * (double)gv.v[q];
           }
@@ -903,10 +966,10 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
   }
 }
 
-template <typename T, int KP, int MODE, bool CHECK, bool BF>
+template <typename T, int KP, int MODE, bool CHECK, bool BF, bool HC>
 __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64)) spmm_kernel(PassArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  spmm_body<T, KP, MODE, CHECK, BF>(a, blockIdx.x, gridDim.x, smem);
+  spmm_body<T, KP, MODE, CHECK, BF, HC>(a, blockIdx.x, gridDim.x, smem);
 }
 
 template <typename T, int KP, int MODE>
@@ -1489,22 +1552,23 @@ static hipError_t launch_rounded(PassArgs& a, int threads, int smem, hipStream_t
   return hipGetLastError();
 }
 
-template <typename T, int KP, int MODE, bool BF>
+template <typename T, int KP, int MODE, bool BF, bool HC>
 static hipError_t spmm_mode_bf(PassArgs& a, hipStream_t s) {
   using SM = Smem<T, KP, MODE>;
   // the k x k products of the residual (X^T A X, (AX)^T (AX)) are compiled in
   // only for the iterations that check it
   if ((MODE == kGF1 || MODE == kAXF2) && (a.flags & kFlagCheck))
-    return launch_rounded<spmm_kernel<T, KP, MODE, true, BF>>(a, SM::WPB * 64, SM::bytes, s);
-  return launch_rounded<spmm_kernel<T, KP, MODE, false, BF>>(a, SM::WPB * 64, SM::bytes, s);
+    return launch_rounded<spmm_kernel<T, KP, MODE, true, BF, HC>>(a, SM::WPB * 64, SM::bytes, s);
+  return launch_rounded<spmm_kernel<T, KP, MODE, false, BF, HC>>(a, SM::WPB * 64, SM::bytes, s);
 }
 
 template <typename T, int KP, int MODE>
 static hipError_t spmm_mode(PassArgs& a, hipStream_t s) {
   if constexpr (sizeof(T) == 4 && MODE != kApply) {
-    if (a.Zg) return spmm_mode_bf<T, KP, MODE, true>(a, s);
+    if (a.Zg) return spmm_mode_bf<T, KP, MODE, true, false>(a, s);
   }
-  return spmm_mode_bf<T, KP, MODE, false>(a, s);
+  if (a.flags & kFlagHC) return spmm_mode_bf<T, KP, MODE, false, true>(a, s);
+  return spmm_mode_bf<T, KP, MODE, false, false>(a, s);
 }
 
 template <typename T, int KP>

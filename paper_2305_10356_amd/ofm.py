@@ -36,6 +36,10 @@ class OfmError(RuntimeError):
         self.status = status
 
 
+# ofm_opts.gather
+GATHER_AUTO, GATHER_DEFAULT, GATHER_HOT_COLD = 0, 1, 2
+
+
 class Opts(ctypes.Structure):
     _fields_ = [
         ("variant", ctypes.c_int),
@@ -48,6 +52,7 @@ class Opts(ctypes.Structure):
         ("tol", ctypes.c_double),
         ("graph", ctypes.c_int),
         ("recur", ctypes.c_int),
+        ("gather", ctypes.c_int),
     ]
 
 
@@ -59,6 +64,8 @@ class Stats(ctypes.Structure):
         ("relres", ctypes.c_double),
         ("objective", ctypes.c_double),
         ("relres_iter", ctypes.c_int64),
+        ("gather", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -222,7 +229,7 @@ class Workspace:
     def __init__(self, lap: Laplacian, k: int, variant="f1", precision=OFM_FP32,
                  max_iter: int = 1000, check_every: int = 10, first_step: int = 0,
                  restart: bool = False, alpha0: float = 0.0, tol: float = 0.0,
-                 graph: bool = False, recur: bool = False):
+                 graph: bool = False, recur: bool = False, gather: int = GATHER_AUTO):
         lib = load()
         self._lib = lib
         self.lap = lap
@@ -230,7 +237,7 @@ class Workspace:
         v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
         self.opts = Opts(v, int(precision), int(max_iter), int(check_every), int(first_step),
                          1 if restart else 0, float(alpha0), float(tol), 1 if graph else 0,
-                         1 if recur else 0)
+                         1 if recur else 0, int(gather))
         h = ctypes.c_void_p()
         _check(lib.ofm_workspace_create(lap.handle, k, ctypes.byref(self.opts), ctypes.byref(h)),
                "ofm_workspace_create")

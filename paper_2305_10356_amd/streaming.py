@@ -9,7 +9,8 @@ initial block of stage s keeps the solution rows of stage s-1 in place and
 appends rows N(0, 1/N_s) for the new nodes.
 
 Every stage runs ``ofm_solve`` with the loop captured as HIP graphs of
-check_every updates (``graph=True``).  Host work per stage: building the
+check_every updates (``graph=True``); the gather policy of the products with
+A is timed at the first stage with a large enough block and kept afterwards.  Host work per stage: building the
 Laplacian handle and assembling the initial block; both are timed apart from
 the solve.
 """
@@ -35,7 +36,8 @@ class StreamingSolver:
 
     def __init__(self, k: int, variant="f1", precision=ofm.OFM_FP32, tol: float = 1e-4,
                  check_every: int = 10, max_iter: int = 5000, graph: bool = True,
-                 restart: bool = False, recur: bool = False, seed: int = 4):
+                 restart: bool = False, recur: bool = False, seed: int = 4,
+                 gather: int = ofm.GATHER_AUTO):
         self.k = k
         self.variant = variant
         self.precision = precision
@@ -46,6 +48,9 @@ class StreamingSolver:
         self.restart = restart
         self.recur = recur
         self.seed = seed
+        # gather policy: chosen by timing at the first stage whose block is
+        # large enough, then kept for the later stages
+        self.gather = gather
         self.X = None
         self.stage = 0
         self.records: List[dict] = []
@@ -84,7 +89,7 @@ class StreamingSolver:
         ws = ofm.Workspace(lap, self.k, variant=self.variant, precision=self.precision,
                            max_iter=self.max_iter, check_every=self.check_every,
                            tol=self.tol, graph=self.graph, restart=self.restart,
-                           recur=self.recur)
+                           recur=self.recur, gather=self.gather)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         st = ws.solve(X)
@@ -96,7 +101,11 @@ class StreamingSolver:
             "iters": int(st["iters"]), "relres": float(st["relres"]),
             "converged": int(st["converged"]), "status": int(st["status"]),
             "solve_s": t3 - t2, "laplacian_s": t1 - t0, "xinit_s": t2 - t1,
+            "gather": int(st["gather"]),
         }
+        if self.gather == ofm.GATHER_AUTO and n * self.k * (8 if self.precision == ofm.OFM_FP64
+                                                            else 4) >= 32 << 20:
+            self.gather = int(st["gather"])
         self.records.append(rec)
         self.X = X
         self.stage += 1

@@ -216,3 +216,49 @@ def test_zero_padded_width(lib, variant, vid):
     r = ws.residual(X)
     assert r["status"] == 0
     assert r["relres"] == pytest.approx(O.relres(olap, st.X), rel=1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("variant,recur", [("f1", False), ("f2", False), ("tri-f2", False),
+                                           ("f1", True)])
+def test_hot_cold_gathers_are_bitwise_default(lib, prec, variant, recur):
+    """The gather policy changes only how rows are cached: the iterates, step
+    scalars and residuals with the hot/cold policy equal those with the default
+    policy bit for bit (power-law graph, so many columns carry the cold mark;
+    residual steps included)."""
+    from paper_2305_10356_amd import graphs, ofm
+    g, x0 = graphs.workload("dcsbm-n2m-k32", n=30000)
+    lap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    p = ofm.OFM_FP64 if prec == "fp64" else ofm.OFM_FP32
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    out = []
+    for gather in (ofm.GATHER_DEFAULT, ofm.GATHER_HOT_COLD):
+        ws = ofm.Workspace(lap, 32, variant=variant, precision=p, check_every=4, max_iter=13,
+                           tol=1e-12, recur=recur, restart=variant.startswith("tri"),
+                           gather=gather)
+        X = torch.as_tensor(x0, dtype=dt).cuda()
+        st = ws.solve(X)
+        assert st["gather"] == gather
+        out.append((host(X), st["relres"], ws.step_info()["alpha"]))
+        ws.close()
+    say(f"hot/cold vs default {variant} {prec} recur={recur}: relres {out[0][1]:.3e}")
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]
+    np.testing.assert_array_equal(out[0][2], out[1][2])
+
+
+def test_gather_policy_choice_and_refusals(lib):
+    from paper_2305_10356_amd import graphs, ofm
+    g, x0 = graphs.workload("dcsbm-n2m-k32", n=30000)
+    lap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    # a block far below the size where the policy is timed keeps the default
+    ws = ofm.Workspace(lap, 32, precision=ofm.OFM_FP32, max_iter=3)
+    X = torch.as_tensor(x0, dtype=torch.float32).cuda()
+    assert ws.solve(X)["gather"] == ofm.GATHER_DEFAULT
+    ws.close()
+    with pytest.raises(ofm.OfmError) as e:
+        ofm.Workspace(lap, 32, precision=ofm.OFM_FP32, gather=3)
+    assert e.value.status == -1
+    with pytest.raises(ofm.OfmError) as e:
+        ofm.Workspace(lap, 32, precision=ofm.OFM_FP32_BF16X, gather=ofm.GATHER_HOT_COLD)
+    assert e.value.status == -8
