@@ -1556,9 +1556,11 @@ template <typename T, int KP, int MODE, bool BF, bool HC>
 static hipError_t spmm_mode_bf(PassArgs& a, hipStream_t s) {
   using SM = Smem<T, KP, MODE>;
   // the k x k products of the residual (X^T A X, (AX)^T (AX)) are compiled in
-  // only for the iterations that check it
+  // only for the iterations that check it; those keep the default gather
+  // policy (at their lower occupancy the hot/cold form measured slower)
   if ((MODE == kGF1 || MODE == kAXF2) && (a.flags & kFlagCheck))
-    return launch_rounded<spmm_kernel<T, KP, MODE, true, BF, HC>>(a, SM::WPB * 64, SM::bytes, s);
+    return launch_rounded<spmm_kernel<T, KP, MODE, true, BF, false>>(a, SM::WPB * 64, SM::bytes,
+                                                                      s);
   return launch_rounded<spmm_kernel<T, KP, MODE, false, BF, HC>>(a, SM::WPB * 64, SM::bytes, s);
 }
 

@@ -73,10 +73,11 @@ def read_traffic(summary_path: str):
     return out
 
 
-# kernel instantiation -> pass, for the FP32 k = 32 kernels of an f1 step
+# kernel instantiation (name prefix) -> pass, for the FP32 k = 32 kernels of
+# an f1 step; the last template argument of the SpMM is the gather policy
 F1_PASSES = {
-    "spmm_kernel<float, 32, 1, false, false>": "spmm_x",
-    "spmm_kernel<float, 32, 3, false, false>": "spmm_v",
+    "spmm_kernel<float, 32, 1, false, false, ": "spmm_x",
+    "spmm_kernel<float, 32, 3, false, false, ": "spmm_v",
     "dense_kernel<float, 32, 6>": "v",
     "dense_kernel<float, 32, 7>": "update",
 }
