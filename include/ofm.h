@@ -301,8 +301,11 @@ ofm_status ofm_batch_phases(ofm_batch b, double* host_loop_ms, double* host_fini
  *   0: X^T X   1: X^T A X   2: (AX)^T (AX)   3: V^T V   4: X^T V
  *   5: X^T A V 6: V^T A V
  * The values are those of the last pass that produced them (X^T X after an
- * update is that of the new X; X^T A X and (AX)^T (AX) are those of the last
- * residual evaluation, and X^T A X of the last direction for the f2 variants).
+ * update is that of the new X; (AX)^T (AX) is that of the last residual
+ * evaluation; X^T A X for the f1 variants is that of the last residual
+ * evaluation, for the f2 variants that of the current iterate: each update
+ * advances it as H + E D + D E^T + D F D with E = X^T A V, F = V^T A V and
+ * D = diag(alpha), and every residual evaluation recomputes it exactly).
  */
 ofm_status ofm_get_products(ofm_workspace ws, int which, double* host_kxk, hipStream_t stream);
 

@@ -115,6 +115,7 @@ struct ofm_workspace_s {
   void* AX = nullptr;
   void* AV = nullptr;   // A V^t kept for the recurrence of A X (opts.recur)
   bool ax_valid = false;  // AX holds A X^t of the current iterate (opts.recur)
+  bool h_valid = false;   // sc.H holds X^T A X of the current iterate (f2 without recur)
   void* Xb = nullptr;   // BF16 copies gathered by the SpMMs (OFM_FP32_BF16X)
   void* Vb = nullptr;
   int prec = 0;         // arithmetic of the kernels: OFM_FP64 or OFM_FP32
@@ -178,7 +179,8 @@ hipError_t timed(ofm_workspace ws, int kind, hipStream_t s, F&& launch) {
 int pass_kind(int mode) {
   switch (mode) {
     case kGF1:
-    case kAXF2: return OFM_PASS_SPMM_X;
+    case kAXF2:
+    case kGF2: return OFM_PASS_SPMM_X;
     case kGPassF2:
     case kGPassF1: return OFM_PASS_G;
     case kVPass: return OFM_PASS_V;
@@ -713,6 +715,18 @@ static ofm_status direction(ofm_workspace ws, void* X, const void* Gp, const voi
     a.Vp = Vp;
     OFMCHK(run_spmm(ws, a, s));
     if (check) HIPCHK(run_residual(ws, s, true));
+  } else if (ws->h_valid) {
+    // H of this iterate is known (advanced by the line search of the last
+    // step): the direction is formed in the epilogue of the SpMM; on residual
+    // steps the same pass also forms H and K exactly, replacing the advanced H
+    PassArgs a = base_args(ws, kGF2, (check ? kFlagCheck : 0) | restart);
+    a.Z = X;
+    a.Zg = ws->Xb;
+    a.G = ws->G[ws->cur];
+    a.Gp = Gp;
+    a.Vp = Vp;
+    OFMCHK(run_spmm(ws, a, s));
+    if (check) HIPCHK(run_residual(ws, s, true));
   } else {
     PassArgs a = base_args(ws, kAXF2, check ? kFlagCheck : 0);
     a.Z = X;
@@ -748,10 +762,14 @@ static ofm_status search_and_update(ofm_workspace ws, void* X, const void* Vp, b
   w.X = X;
   w.Y = ws->opts.recur ? ws->AV : nullptr;
   OFMCHK(run_spmm(ws, w, s));
+  // f2 without the recurrence: the line search also advances H to the next
+  // iterate, so the next direction needs no stored A X
+  const bool adv_h = is_f2(ws->opts.variant) && !ws->opts.recur;
   HIPCHK(timed(ws, OFM_PASS_LINESEARCH, s, [&] {
     return launch_linesearch(ws->k, ws->opts.variant, first && ws->opts.first_step == 1,
-                             ws->opts.alpha0, ws->sc, ws->status, ws->frozen, s);
+                             ws->opts.alpha0, adv_h ? 1 : 0, ws->sc, ws->status, ws->frozen, s);
   }));
+  ws->h_valid = adv_h;
   if (ws->opts.recur) {
     // X += V diag(alpha), A X += A V diag(alpha); M (and H for f2) of the new X
     PassArgs u = base_args(ws, kUpdateR, is_f2(ws->opts.variant) ? kFlagH : 0);
@@ -790,6 +808,7 @@ extern "C" ofm_status ofm_init(ofm_workspace ws, void* X, hipStream_t stream) {
   ws->t = 0;
   ws->last_check = -1;
   ws->ax_valid = false;
+  ws->h_valid = false;
   OFMCHK(gram_m(ws, X, stream));
   OFMCHK(direction(ws, X, nullptr, nullptr, 0, stream));
   OFMCHK(search_and_update(ws, X, nullptr, true, stream));
@@ -843,6 +862,7 @@ static ofm_status capture_chunk(ofm_workspace ws, void* X, hipGraphExec_t* out) 
   const int cur0 = ws->cur;
   const int64_t lc0 = ws->last_check;
   const bool axv0 = ws->ax_valid;
+  const bool hv0 = ws->h_valid;
   const unsigned timing = ws->timing;
   ws->timing = 0;
   hipGraph_t g = nullptr;
@@ -857,6 +877,7 @@ static ofm_status capture_chunk(ofm_workspace ws, void* X, hipGraphExec_t* out) 
   ws->cur = cur0;
   ws->last_check = lc0;
   ws->ax_valid = axv0;
+  ws->h_valid = hv0;
   ws->timing = timing;
   if (st == OFM_OK && hipGraphInstantiate(out, g, nullptr, nullptr, 0) != hipSuccess)
     st = OFM_E_HIP;
@@ -924,6 +945,7 @@ extern "C" ofm_status ofm_residual(ofm_workspace ws, const void* X, hipStream_t 
   HIPCHK(run_residual(ws, stream, false));
   ws->last_check = ws->t;
   ws->ax_valid = false;
+  ws->h_valid = false;  // the products above belong to the X passed in
   ofm_stats st{};
   OFMCHK(read_stats(ws, stream, &st));
   if (host_out) *host_out = st;
@@ -935,6 +957,7 @@ extern "C" ofm_status ofm_objective(ofm_workspace ws, const void* X, double* f_o
   if (!ws || !X || !f_out) return OFM_E_INVALID_ARG;
   if (ws->opts.variant == OFM_TRI_F1 || ws->opts.variant == OFM_TRI_F2) return OFM_E_UNSUPPORTED;
   ws->ax_valid = false;  // the products below overwrite A X
+  ws->h_valid = false;   // and X^T A X
   // without a caller buffer the gradient goes to the current-direction slot,
   // which the next step overwrites anyway (the CG state is in the other slot)
   void* gout = grad ? grad : ws->G[ws->cur];
@@ -989,6 +1012,7 @@ extern "C" ofm_status ofm_set_state(ofm_workspace ws, const void* X, const void*
   ws->t = t;
   ws->last_check = -1;
   ws->ax_valid = false;
+  ws->h_valid = false;
   ws->initialized = true;
   return OFM_OK;
 }

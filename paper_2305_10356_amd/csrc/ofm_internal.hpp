@@ -84,7 +84,8 @@ enum Mode : int {
   kGramM = 8,     // X^T X
   kGGP = 9,       // diag G_prev^T G_prev
   kUpdateR = 10,  // X += alpha V, AX += alpha AV, X^T X [, X^T A X]
-  kGPassF1 = 11   // G = c (AX + X M') from a stored AX, gg, gpg [, vpg]
+  kGPassF1 = 11,  // G = c (AX + X M') from a stored AX, gg, gpg [, vpg]
+  kGF2 = 12       // G = a AX - b (X H' + AX M') from the gathered AX, gg, gpg [, vpg] [, H, K]
 };
 
 struct LaplacianDev {
@@ -207,7 +208,9 @@ hipError_t launch_dense(int precision, int k, PassArgs& a, hipStream_t s);
 // out[v] for v < split, out2[v - split] for v >= split (split = nv: one range)
 hipError_t launch_finalize(const double* partials, int nb, int nv, double* out, double* lvl2,
                            hipStream_t s, int split, double* out2);
-hipError_t launch_linesearch(int k, int variant, int first, double alpha0, double* sc,
+// advance_h: also H := (X + V D)^T A (X + V D) from X^T A V, V^T A V and the
+// step sizes D (the f2 directions then need no stored A X)
+hipError_t launch_linesearch(int k, int variant, int first, double alpha0, int advance_h, double* sc,
                              int* status, const int* frozen, hipStream_t s);
 hipError_t launch_residual(int k, int variant, double normA2, double* sc, int* status,
                            double tol, int* frozen, hipStream_t s);

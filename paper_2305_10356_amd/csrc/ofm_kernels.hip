@@ -131,7 +131,7 @@ struct Cfg {
 };
 
 constexpr int nbuf_of(int mode) {
-  return mode == kGF1 ? 3
+  return (mode == kGF1 || mode == kGF2) ? 3
          : mode == kAXF2 ? 2
          : mode == kAVF2 ? 3
          : (mode == kGPassF2 || mode == kGPassF1) ? 3
@@ -140,10 +140,10 @@ constexpr int nbuf_of(int mode) {
                                                 : 0;
 }
 constexpr int nfrag_of(int mode) {
-  return (mode == kGF1 || mode == kGPassF1) ? 1 : mode == kGPassF2 ? 2 : 0;
+  return (mode == kGF1 || mode == kGPassF1) ? 1 : (mode == kGPassF2 || mode == kGF2) ? 2 : 0;
 }
 constexpr int nvec_of(int mode) {
-  return (mode == kGF1 || mode == kGPassF2 || mode == kGPassF1) ? 3
+  return (mode == kGF1 || mode == kGF2 || mode == kGPassF2 || mode == kGPassF1) ? 3
          : (mode == kVPass || mode == kAVF1 || mode == kAVF2 || mode == kGGP) ? 1
                                                                                : 0;
 }
@@ -168,7 +168,8 @@ template <int KP>
 __host__ __device__ inline int mode_nv(int mode, int flags) {
   const int KK = KP * KP;
   switch (mode) {
-    case kGF1: return 3 * KP + ((flags & kFlagCheck) ? 2 * KK : 0);
+    case kGF1:
+    case kGF2: return 3 * KP + ((flags & kFlagCheck) ? 2 * KK : 0);
     case kAXF2: return KK + ((flags & kFlagCheck) ? KK : 0);
     case kAVF1: return KP;
     case kAVF2: return KP + 2 * KK;
@@ -186,6 +187,7 @@ template <int KP>
 __host__ __device__ inline int mode_off(int mode) {
   switch (mode) {
     case kGF1:
+    case kGF2:
     case kGPassF2:
     case kGPassF1: return SC<KP>::GG;
     case kAXF2: return SC<KP>::H;
@@ -533,10 +535,18 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
   const int j = lane % G::LPR;
   const double* sc = a.sc;
 
-  T cf = T(1);
+  T cf = T(1), ca = T(0), cb = T(0);
   if (MODE == kGF1) {
     load_frags<T, KP>(frag, sc + SC<KP>::M, a.variant == OFM_TRI_F1);
     cf = (a.variant == OFM_F1) ? T(4) : T(1);
+    __syncthreads();
+  } else if (MODE == kGF2) {
+    // the f2 directions with H of the current iterate from the scalar block
+    const bool tri = a.variant == OFM_TRI_F2;
+    load_frags<T, KP>(frag, sc + SC<KP>::H, tri);                  // H'
+    load_frags<T, KP>(frag + G::FRAG_ELEMS, sc + SC<KP>::M, tri);  // M'
+    ca = tri ? T(2) : T(4);
+    cb = tri ? T(1) : T(2);
     __syncthreads();
   }
 
@@ -637,11 +647,17 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
 
-    if (MODE == kGF1) {
-      // D = X M' ; G = c (AX + D); per-column sums of G*G, G_prev*G, V_prev*G
+    if (MODE == kGF1 || MODE == kGF2) {
+      // kGF1: D = X M', G = c (AX + D); kGF2: D = X H' + AX M', G = ca AX - cb D;
+      // per-column sums of G*G, G_prev*G, V_prev*G
       tile_times_matrix<T, KP>(tZ, frag, tD, lane, false);
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      if (MODE == kGF2) {
+        tile_times_matrix<T, KP>(tA, frag + G::FRAG_ELEMS, tD, lane, true);
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      }
 #pragma unroll
       for (int pass = 0; pass < G::NPASS; ++pass) {
         const int gi = pass * G::RPW + g;
@@ -650,8 +666,13 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
           const V16<T> ax = tile_load_vec<T, KP>(tA, gi, j);
           const V16<T> d = tile_load_vec<T, KP>(tD, gi, j);
           V16<T> gv;
+          if (MODE == kGF1) {
 #pragma unroll
-          for (int q = 0; q < G::VECN; ++q) gv.v[q] = cf * (ax.v[q] + d.v[q]);
+            for (int q = 0; q < G::VECN; ++q) gv.v[q] = cf * (ax.v[q] + d.v[q]);
+          } else {
+#pragma unroll
+            for (int q = 0; q < G::VECN; ++q) gv.v[q] = ca * ax.v[q] - cb * d.v[q];
+          }
           const size_t off = (size_t)row * KP + j * G::VECN;
           st16_out<HC>(static_cast<T*>(a.G) + off, gv);
 #pragma unroll
@@ -704,7 +725,7 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
   if (MODE == kApply) return;
   double* prow = a.partials + (size_t)brank * a.nv;
   const int KK = KP * KP;
-  if (MODE == kGF1) {
+  if (MODE == kGF1 || MODE == kGF2) {
     block_vec_out<T, KP, 3>(cacc, red, prow, 0, wave, lane, WPB);
     if (check) {
       block_gram_out<T, KP, false>(gA, red, prow, 3 * KP, wave, lane, WPB);
@@ -1202,7 +1223,8 @@ __device__ inline double block_sum256(double x, double* buf) {
 // 0, so the iterate that met it is the one kept
 template <int KP>
 __device__ __forceinline__ void linesearch_body(int variant, int first, double alpha0,
-                                                double* sc, int* status, const int* frozen) {
+                                                double* sc, int* status, const int* frozen,
+                                                bool advance_h = false) {
   const bool frz = frozen != nullptr && *frozen != 0;
   __shared__ double buf[256];
   __shared__ double co[4];
@@ -1328,13 +1350,24 @@ __device__ __forceinline__ void linesearch_body(int variant, int first, double a
   // the CG denominator of the next step: diag G^T G of this step
   __syncthreads();
   if (tid < KP) sc[SC<KP>::GGP + tid] = sc[SC<KP>::GG + tid];
+  if (advance_h) {
+    // H of the next iterate, (X + V D)^T A (X + V D) with D = diag(alpha):
+    // H_ij + alpha_j E_ij + alpha_i E_ji + alpha_i alpha_j F_ij (A symmetric,
+    // so V^T A X = E^T); each entry is read and written by one thread
+    double* Hn = sc + SC<KP>::H;
+    for (int e = tid; e < KK; e += 256) {
+      const int r = e / KP, c = e % KP;
+      const double ar = alpha[r], ac = alpha[c];
+      Hn[e] += ac * E[e] + ar * E[c * KP + r] + ar * ac * F[e];
+    }
+  }
 }
 
 template <int KP>
 __global__ void __launch_bounds__(256) linesearch_kernel(int variant, int first, double alpha0,
-                                                         double* sc, int* status,
+                                                         int advance_h, double* sc, int* status,
                                                          const int* frozen) {
-  linesearch_body<KP>(variant, first, alpha0, sc, status, frozen);
+  linesearch_body<KP>(variant, first, alpha0, sc, status, frozen, advance_h != 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1558,7 +1591,7 @@ static hipError_t spmm_mode_bf(PassArgs& a, hipStream_t s) {
   // the k x k products of the residual (X^T A X, (AX)^T (AX)) are compiled in
   // only for the iterations that check it; those keep the default gather
   // policy (at their lower occupancy the hot/cold form measured slower)
-  if ((MODE == kGF1 || MODE == kAXF2) && (a.flags & kFlagCheck))
+  if ((MODE == kGF1 || MODE == kGF2 || MODE == kAXF2) && (a.flags & kFlagCheck))
     return launch_rounded<spmm_kernel<T, KP, MODE, true, BF, false>>(a, SM::WPB * 64, SM::bytes,
                                                                       s);
   return launch_rounded<spmm_kernel<T, KP, MODE, false, BF, HC>>(a, SM::WPB * 64, SM::bytes, s);
@@ -1578,6 +1611,7 @@ static hipError_t spmm_t(PassArgs& a, hipStream_t s) {
   switch (a.mode) {
     case kApply: return spmm_mode<T, KP, kApply>(a, s);
     case kGF1: return spmm_mode<T, KP, kGF1>(a, s);
+    case kGF2: return spmm_mode<T, KP, kGF2>(a, s);
     case kAXF2: return spmm_mode<T, KP, kAXF2>(a, s);
     case kAVF1: return spmm_mode<T, KP, kAVF1>(a, s);
     case kAVF2: return spmm_mode<T, KP, kAVF2>(a, s);
@@ -1663,16 +1697,21 @@ hipError_t launch_finalize(const double* partials, int nb, int nv, double* out, 
   return hipGetLastError();
 }
 
-hipError_t launch_linesearch(int k, int variant, int first, double alpha0, double* sc,
+hipError_t launch_linesearch(int k, int variant, int first, double alpha0, int advance_h, double* sc,
                              int* status, const int* frozen, hipStream_t s) {
+#define OFM_LS(KP)                                                                              \
+  hipLaunchKernelGGL(linesearch_kernel<KP>, dim3(1), dim3(256), 0, s, variant, first, alpha0, \
+                     advance_h, sc, status, frozen);                                           \
+  break;
   switch (k) {
-    case 4: hipLaunchKernelGGL(linesearch_kernel<4>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status, frozen); break;
-    case 8: hipLaunchKernelGGL(linesearch_kernel<8>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status, frozen); break;
-    case 16: hipLaunchKernelGGL(linesearch_kernel<16>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status, frozen); break;
-    case 32: hipLaunchKernelGGL(linesearch_kernel<32>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status, frozen); break;
-    case 64: hipLaunchKernelGGL(linesearch_kernel<64>, dim3(1), dim3(256), 0, s, variant, first, alpha0, sc, status, frozen); break;
+    case 4: OFM_LS(4)
+    case 8: OFM_LS(8)
+    case 16: OFM_LS(16)
+    case 32: OFM_LS(32)
+    case 64: OFM_LS(64)
     default: return hipErrorInvalidValue;
   }
+#undef OFM_LS
   return hipGetLastError();
 }
 

@@ -528,7 +528,8 @@ def test_kmeans_matches_oracle_on_blobs(ofm):
 @pytest.mark.parametrize("k,dt", [(8, "fp64"), (32, "fp64"), (32, "fp32"), (64, "fp32"), (4, "fp32")])
 def test_products_match_oracle(ofm, k, dt):
     # k x k products of one init step: X^T X of the new X; V^T V, X^T V of the
-    # first direction; X^T A V, V^T A V (f2) -- each against a plain product
+    # first direction; X^T A V, V^T A V (f2); X^T A X of the new X (advanced)
+    # -- each against a plain product
     g, _ = graphs.workload("dcsbm-n2m-k32", n=6000)
     olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     glap = ofm.Laplacian(g.row_ptr, g.col_idx)
@@ -549,7 +550,10 @@ def test_products_match_oracle(ofm, k, dt):
     assert rel(ws.product("C"), X0.T @ V0) < tol
     assert rel(ws.product("E"), X0.T @ AV) < tol * 10
     assert rel(ws.product("F"), V0.T @ AV) < tol * 10
-    assert rel(ws.product("H"), X0.T @ O.apply_A(olap, X0)) < tol * 10
+    # f2 without the recurrence: the line search advanced X^T A X to the new
+    # iterate from X^T A V, V^T A V and the step: equal to the product of the
+    # stored X1 up to its rounding
+    assert rel(ws.product("H"), X1.T @ O.apply_A(olap, X1)) < tol * 10
 
 
 def test_solve_returns_the_iterate_it_reports(ofm, sbm1k, sbm1k_lap):
