@@ -180,9 +180,11 @@ ofm_status ofm_apply_A(ofm_laplacian lap, int k, int precision, const void* Z, v
 
 /*
  * Create the iteration workspace: the direction and CG buffers V, V_prev, G,
- * G_prev, AX (f2 variants), the k x k FP64 products and the reduction scratch.
- * Allocates device memory (about (4 + [f2]) N k element slots plus O(k^2)
- * per block).  host_opts is copied.
+ * G_prev, AX, AV (with the recurrence, and for the f2 variants at k >= 32),
+ * the k x k FP64 products and the reduction scratch.  Allocates device memory
+ * (5 or 6 N x k blocks, plus BF16 copies of X and V for OFM_FP32_BF16X, plus
+ * O(k^2) per block).  host_opts is copied.  With opts.gather = 0 and a block
+ * of 32 MB or more it also runs and times six products with A (synchronizing).
  */
 ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_opts* host_opts,
                                 ofm_workspace* out);
@@ -332,15 +334,17 @@ ofm_status ofm_objective(ofm_workspace ws, const void* X, double* f_out, void* g
  * pass i, 0 turns timing off, OFM_TIMING_ALL selects every pass.
  */
 #define OFM_PASS_SPMM_X 0     /* A X with the fused direction epilogue        */
-#define OFM_PASS_G 1          /* direction from a stored A X (f2 variants,
-                                 f1 variants with the recurrence)             */
+#define OFM_PASS_G 1          /* direction from a stored A X (recurrence; f2
+                                 steps whose X^T A X is not yet known)        */
 #define OFM_PASS_V 2          /* V = -G + V_prev diag(beta) and its products  */
 #define OFM_PASS_SPMM_V 3     /* A V with the line-search products            */
 #define OFM_PASS_LINESEARCH 4 /* cubic coefficients, roots, step sizes        */
 #define OFM_PASS_UPDATE 5     /* X += V diag(alpha) and X^T X                 */
 #define OFM_PASS_REDUCE 6     /* cross-block reductions of the k x k products */
 #define OFM_PASS_RESIDUAL 7   /* residual and objective                       */
-#define OFM_PASS_OTHER 8      /* products of set-up calls                     */
+/* OFM_PASS_OTHER: products of set-up calls, and the f2 products X^T A V and
+   V^T A V formed from a stored A V (k >= 32, without the recurrence) */
+#define OFM_PASS_OTHER 8
 #define OFM_NUM_PASSES 9
 #define OFM_TIMING_ALL ((1u << OFM_NUM_PASSES) - 1u)
 ofm_status ofm_set_timing(ofm_workspace ws, unsigned pass_mask);

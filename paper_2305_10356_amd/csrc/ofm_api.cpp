@@ -188,6 +188,7 @@ int pass_kind(int mode) {
     case kAVF2: return OFM_PASS_SPMM_V;
     case kUpdate:
     case kUpdateR: return OFM_PASS_UPDATE;
+    case kEF: return OFM_PASS_OTHER;
     default: return OFM_PASS_OTHER;
   }
 }
@@ -472,6 +473,12 @@ static void free_ws(ofm_workspace ws) {
   delete ws;
 }
 
+// f2 without the recurrence at k >= 32: the SpMM of V stores A V and a
+// streaming pass forms X^T A V and V^T A V
+static bool f2_products_pass(const ofm_opts& o, int k) {
+  return (o.variant == OFM_F2 || o.variant == OFM_TRI_F2) && !o.recur && k >= 32;
+}
+
 // Blocks from which the gather policy is chosen by timing (smaller ones fit
 // the caches and keep the default policy).
 constexpr size_t kHcMinBytes = size_t(32) << 20;
@@ -565,7 +572,8 @@ extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_o
     if ((st = dev_alloc(reinterpret_cast<char**>(&ws->G[i]), blk)) != OFM_OK) return fail(st);
   }
   if ((st = dev_alloc(reinterpret_cast<char**>(&ws->AX), blk)) != OFM_OK) return fail(st);
-  if (o.recur && (st = dev_alloc(reinterpret_cast<char**>(&ws->AV), blk)) != OFM_OK)
+  if ((o.recur || f2_products_pass(o, k)) &&
+      (st = dev_alloc(reinterpret_cast<char**>(&ws->AV), blk)) != OFM_OK)
     return fail(st);
   if (o.precision == OFM_FP32_BF16X) {
     if ((st = dev_alloc(reinterpret_cast<char**>(&ws->Xb), blk / 2)) != OFM_OK) return fail(st);
@@ -756,12 +764,29 @@ static ofm_status search_and_update(ofm_workspace ws, void* X, const void* Vp, b
   v.Vb = ws->Vb;
   v.X = X;
   OFMCHK(run_dense(ws, v, s));
-  PassArgs w = base_args(ws, is_f2(ws->opts.variant) ? kAVF2 : kAVF1, 0);
-  w.Z = ws->V[cur];
-  w.Zg = ws->Vb;
-  w.X = X;
-  w.Y = ws->opts.recur ? ws->AV : nullptr;
-  OFMCHK(run_spmm(ws, w, s));
+  if (f2_products_pass(ws->opts, ws->k)) {
+    // A V stored by the SpMM of the f1 form, then X^T A V and V^T A V in a
+    // streaming pass (at k >= 32 the two FP64 products in the SpMM's epilogue
+    // cost it more occupancy than the pass costs)
+    PassArgs w = base_args(ws, kAVF1, 0);
+    w.Z = ws->V[cur];
+    w.Zg = ws->Vb;
+    w.X = X;
+    w.Y = ws->AV;
+    OFMCHK(run_spmm(ws, w, s));
+    PassArgs e = base_args(ws, kEF, 0);
+    e.X = X;
+    e.V = ws->V[cur];
+    e.Z = ws->AV;
+    OFMCHK(run_dense(ws, e, s));
+  } else {
+    PassArgs w = base_args(ws, is_f2(ws->opts.variant) ? kAVF2 : kAVF1, 0);
+    w.Z = ws->V[cur];
+    w.Zg = ws->Vb;
+    w.X = X;
+    w.Y = ws->opts.recur ? ws->AV : nullptr;
+    OFMCHK(run_spmm(ws, w, s));
+  }
   // f2 without the recurrence: the line search also advances H to the next
   // iterate, so the next direction needs no stored A X
   const bool adv_h = is_f2(ws->opts.variant) && !ws->opts.recur;

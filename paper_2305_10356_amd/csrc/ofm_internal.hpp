@@ -85,7 +85,8 @@ enum Mode : int {
   kGGP = 9,       // diag G_prev^T G_prev
   kUpdateR = 10,  // X += alpha V, AX += alpha AV, X^T X [, X^T A X]
   kGPassF1 = 11,  // G = c (AX + X M') from a stored AX, gg, gpg [, vpg]
-  kGF2 = 12       // G = a AX - b (X H' + AX M') from the gathered AX, gg, gpg [, vpg] [, H, K]
+  kGF2 = 12,      // G = a AX - b (X H' + AX M') from the gathered AX, gg, gpg [, vpg] [, H, K]
+  kEF = 13        // X^T A V, V^T A V from a stored A V
 };
 
 struct LaplacianDev {

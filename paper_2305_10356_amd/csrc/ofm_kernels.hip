@@ -131,7 +131,7 @@ struct Cfg {
 };
 
 constexpr int nbuf_of(int mode) {
-  return (mode == kGF1 || mode == kGF2) ? 3
+  return (mode == kGF1 || mode == kGF2 || mode == kEF) ? 3
          : mode == kAXF2 ? 2
          : mode == kAVF2 ? 3
          : (mode == kGPassF2 || mode == kGPassF1) ? 3
@@ -180,6 +180,7 @@ __host__ __device__ inline int mode_nv(int mode, int flags) {
     case kUpdate:
     case kGramM: return KK;
     case kGGP: return KP;
+    case kEF: return 2 * KK;
     default: return 0;
   }
 }
@@ -198,6 +199,7 @@ __host__ __device__ inline int mode_off(int mode) {
     case kUpdateR:
     case kGramM: return SC<KP>::M;
     case kGGP: return SC<KP>::GGP;
+    case kEF: return SC<KP>::E;
     default: return 0;
   }
 }
@@ -870,6 +872,21 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
           for (int q = 0; q < G::VECN; ++q) x.v[q] = T(0);
         }
         if (gi < G::TR) tile_store_vec<T, KP>(t0, gi, j, x);
+      } else if (MODE == kEF) {
+        V16<T> x, v, av;
+        if (ok) {
+          x = ld16(static_cast<const T*>(a.X) + off);
+          v = ld16(static_cast<const T*>(a.V) + off);
+          av = ld16(static_cast<const T*>(a.Z) + off);
+        } else {
+#pragma unroll
+          for (int q = 0; q < G::VECN; ++q) x.v[q] = v.v[q] = av.v[q] = T(0);
+        }
+        if (gi < G::TR) {
+          tile_store_vec<T, KP>(t0, gi, j, x);
+          tile_store_vec<T, KP>(t1, gi, j, v);
+          tile_store_vec<T, KP>(t2, gi, j, av);
+        }
       } else if (MODE == kUpdateR) {
         V16<T> x, ax;
         if (ok) {
@@ -924,6 +941,9 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
       tile_gram<T, KP, false>(t1, t0, gB, lane);  // C = X^T V
     } else if (MODE == kUpdate || MODE == kGramM) {
       tile_gram<T, KP, true>(t0, t0, gA, lane);   // M = X^T X
+    } else if (MODE == kEF) {
+      tile_gram<T, KP, false>(t0, t2, gA, lane);  // E = X^T (AV)
+      tile_gram<T, KP, true>(t1, t2, gB, lane);   // F = V^T (AV)
     } else if (MODE == kUpdateR) {
       tile_gram<T, KP, true>(t0, t0, gA, lane);                        // M = X^T X
       if (a.flags & kFlagH) tile_gram<T, KP, false>(t0, t1, gB, lane);  // H = X^T (AX)
@@ -984,6 +1004,9 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
     block_vec_out<T, KP, 1>(cacc, red, prow, 0, wave, lane, WPB);
   } else if (MODE == kGPassF2 || MODE == kGPassF1) {
     block_vec_out<T, KP, 3>(cacc, red, prow, 0, wave, lane, WPB);
+  } else if (MODE == kEF) {
+    block_gram_out<T, KP, false>(gA, red, prow, 0, wave, lane, WPB);
+    block_gram_out<T, KP, true>(gB, red, prow, KK, wave, lane, WPB);
   }
 }
 
@@ -1635,6 +1658,7 @@ static hipError_t dense_t(PassArgs& a, hipStream_t s) {
     case kUpdateR: return dense_mode<T, KP, kUpdateR>(a, s);
     case kGramM: return dense_mode<T, KP, kGramM>(a, s);
     case kGGP: return dense_mode<T, KP, kGGP>(a, s);
+    case kEF: return dense_mode<T, KP, kEF>(a, s);
   }
   return hipErrorInvalidValue;
 }
