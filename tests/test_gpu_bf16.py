@@ -61,3 +61,26 @@ def test_bf16_solve_floor_and_labels(lib):
         lab, _, _ = ofm.kmeans(Y, 32, O.kmeans_uniforms(0, 32))
         labels[prec] = lab.cpu().numpy()
     assert O.ari(labels[ofm.OFM_FP32], labels[ofm.OFM_FP32_BF16X]) > 0.9
+
+
+def test_bf16_f2_solve_floor_and_labels(lib):
+    """OFM-f2 with BF16 gathered copies: the direction formed in the SpMM
+    epilogue with the advanced X^T A X and the products pass of A V, on
+    BF16-gathered rows, still reach the BF16 residual floor and cluster like
+    the FP32 run."""
+    from paper_2305_10356_amd import ofm
+    g, x0 = graphs.workload("sbm-n50k-k32")
+    lap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    labels = {}
+    for prec in (ofm.OFM_FP32, ofm.OFM_FP32_BF16X):
+        ws = ofm.Workspace(lap, 32, variant="f2", precision=prec, max_iter=400, check_every=10)
+        X = torch.tensor(x0.astype(np.float32), device="cuda")
+        st = ws.solve(X)
+        rr = ws.residual(X)["relres"]
+        print(f"f2 precision {prec}: {st['iters']} updates, relres of the final X {rr:.2e}",
+              flush=True)
+        assert st["status"] == 0 and rr < 5e-3
+        Y = ofm.row_normalize(X)
+        lab, _, _ = ofm.kmeans(Y, 32, O.kmeans_uniforms(0, 32))
+        labels[prec] = lab.cpu().numpy()
+    assert O.ari(labels[ofm.OFM_FP32], labels[ofm.OFM_FP32_BF16X]) > 0.9
