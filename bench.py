@@ -33,19 +33,28 @@ def log(*a):
 def pass_bytes(name: str, n: int, nnz: int, k: int, esz: int, variant: str, ntiles: int,
                recur: bool = False) -> float:
     """Algorithmic HBM bytes of one launch of a pass (each array moved once).
-    With the recurrence of A X the f1 variants store A X in the SpMM of X and
-    form G in a pass of their own, the SpMM of V stores A V, and the update
-    also reads and writes A X and reads A V."""
+    Without the recurrence the SpMM of X forms the direction in its epilogue
+    (f2 with X^T A X advanced by the line search); with it, the SpMM of X runs
+    on residual steps only and stores A X, the SpMM of V stores A V, the
+    update also reads A X, A V and writes A X, and G is formed in a pass of
+    its own from the stored A X.
+    f2 at k >= 32 without the recurrence stores A V and forms X^T A V, V^T A V
+    in a streaming pass ("other")."""
     B = n * k * esz
     ent = nnz * (8 if esz == 4 else 16)          # packed (column, weight) stream
     graph = ent + 8 * n + 4 * (ntiles + 1)       # + position offsets and row ids
     f2 = variant in ("f2", "tri-f2")
+    split = f2 and not recur and k >= 32
     if name == "spmm_x":
-        # X; f1: G_prev read + G write; f2 (and the recurrence): A X write
-        return graph + (2 * B if (f2 or recur) else 3 * B)
+        # X; without the recurrence G_prev read + G write, with it A X write
+        return graph + (2 * B if recur else 3 * B)
     if name == "spmm_v":
+        if split:
+            return graph + 2 * B                 # V read, A V write
         # V; f2 also reads X; the recurrence writes A V
         return graph + (2 * B if f2 else B) + (B if recur else 0)
+    if name == "other":
+        return 3 * B if split else 0.0           # X, V, A V read
     if name == "g":
         return 4 * B                             # X, AX, G_prev read; G write
     if name == "v":
