@@ -454,7 +454,8 @@ def main():
     from paper_2305_10356_amd import profiling
     traffic = profiling.read_traffic(os.path.join(
         ROOT, "profiles", f"pmc_traffic_ofm_step_{args.variant}_dcsbm_n2m_k32_fp32.md"))
-    if args.n is not None or args.recur:
+    # the counters were taken with the hot/cold gathers; another policy moves other bytes
+    if args.n is not None or args.recur or stats["gather"] != ofm.GATHER_HOT_COLD:
         traffic = {}
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
