@@ -162,6 +162,34 @@ ofm_status ofm_build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr,
                                const int32_t* col_idx, const double* vals,
                                unsigned flags, hipStream_t stream, ofm_laplacian* out);
 
+/*
+ * As ofm_build_laplacian, with a row-processing order laid out for the eight
+ * XCDs of the chip (each with its own L2) from a grouping of the nodes, such as
+ * the cluster labels of an earlier solve of the same or a previous snapshot of
+ * the graph (Algorithm 1, step 5; the streaming experiments of the numerical
+ * results section start each stage from the previous one).  The groups are
+ * dealt to eight slots, balancing their entry counts; every SpMM then runs the
+ * rows of slot x on the workgroups that the hardware places on XCD x (workgroup
+ * ids congruent to x modulo 8), a group at a time, so that the neighbour rows a
+ * community gathers stay in that XCD's L2.  Within a slot: the rows processed a
+ * wavefront per row (64 or more entries) first, then group by group, each by
+ * entry count, descending.
+ *   host_groups  host int32[n]: group of each node; any negative value means
+ *                "no group" (such rows are dealt to the slots last).  Values
+ *                must be < n.  Only read during the call.
+ * Results of ofm_apply_A are bitwise those of ofm_build_laplacian's order; the
+ * k x k products of a workspace are summed over other workgroup partitions
+ * (differences at the rounding of the FP64 sums).  Workspaces on such a
+ * Laplacian launch one workgroup per tile group where their reduction scratch
+ * allows (up to about 3k doubles per 64 rows).
+ * Errors: as ofm_build_laplacian; OFM_E_INVALID_ARG for a null host_groups, a
+ * group id >= n, or OFM_LAP_NO_REORDER in flags.
+ */
+ofm_status ofm_build_laplacian_grouped(int64_t n, int64_t nnz, const int32_t* row_ptr,
+                                       const int32_t* col_idx, const double* vals,
+                                       unsigned flags, const int32_t* host_groups,
+                                       hipStream_t stream, ofm_laplacian* out);
+
 ofm_status ofm_laplacian_destroy(ofm_laplacian lap);
 
 /* Host copies of the basic graph quantities: n, nnz, ||A||_F^2, and (nullable

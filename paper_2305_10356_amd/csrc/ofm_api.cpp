@@ -96,6 +96,8 @@ struct TileTable {
   int tr = 0;
   int32_t* dev = nullptr;
   int64_t ntiles = 0;
+  bool xcd = false;   // grouped order: tiles [xt[x], xt[x+1]) belong to XCD slot x
+  int32_t xt[9] = {};
 };
 
 struct ofm_laplacian_s {
@@ -122,6 +124,7 @@ struct ofm_workspace_s {
   int cur = 0;
   double* sc = nullptr;
   double* partials = nullptr;
+  size_t part_cap = 0;     // doubles of partials
   double* lvl2 = nullptr;
   int* status = nullptr;
   int* frozen = nullptr;   // set on the device when the residual met tol
@@ -229,19 +232,18 @@ static void free_lap(ofm_laplacian L) {
 // over half of the gathers).
 constexpr double kHotShare = 0.2;
 
-static std::vector<int32_t> build_tiles(const std::vector<int32_t>& sdeg, int tr, bool reorder) {
-  // tiles of consecutive positions: rows of degree >= kHeavyDeg (first when
-  // rows are sorted by degree) form "heavy" tiles of at most tr rows and
-  // kHeavyTileNnz entries, processed one row per wavefront; the rest form
-  // tiles of tr rows.  The heavy flag is the sign bit.
-  std::vector<int32_t> t;
-  const int64_t n = (int64_t)sdeg.size();
-  int64_t p = 0;
+static void build_tiles(const std::vector<int32_t>& sdeg, int tr, bool reorder, int64_t p0,
+                        int64_t p1, std::vector<int32_t>& t) {
+  // tiles of consecutive positions in [p0, p1): rows of degree >= kHeavyDeg
+  // (first when rows are sorted by degree) form "heavy" tiles of at most tr
+  // rows and kHeavyTileNnz entries, processed one row per wavefront; the rest
+  // form tiles of tr rows.  The heavy flag is the sign bit.
+  int64_t p = p0;
   if (reorder) {
-    while (p < n && sdeg[p] >= kHeavyDeg) {
+    while (p < p1 && sdeg[p] >= kHeavyDeg) {
       const int64_t st = p;
       int64_t nz = 0;
-      while (p < n && sdeg[p] >= kHeavyDeg && p - st < tr &&
+      while (p < p1 && sdeg[p] >= kHeavyDeg && p - st < tr &&
              (p == st || nz + sdeg[p] <= kHeavyTileNnz)) {
         nz += sdeg[p];
         ++p;
@@ -249,18 +251,123 @@ static std::vector<int32_t> build_tiles(const std::vector<int32_t>& sdeg, int tr
       t.push_back((int32_t)st | (int32_t)0x80000000);
     }
   }
-  while (p < n) {
+  while (p < p1) {
     t.push_back((int32_t)p);
-    p = std::min<int64_t>(n, p + tr);
+    p = std::min<int64_t>(p1, p + tr);
   }
-  t.push_back((int32_t)n);
-  return t;
 }
+
+// Row-processing order from a grouping of the nodes, laid out for the eight
+// XCDs: groups, largest entry count first, each go to the slot with the least
+// work so far (entries + rows); rows without a group follow, one at a time in
+// descending entry count, to the least loaded slot.  A slot lists its rows of
+// kHeavyDeg or more entries first, then its groups in the order they were
+// assigned, then its rows without a group; each of these by entry count,
+// descending (ties by row).  Two stable counting sorts: O(n + max count +
+// number of groups).  slot_pos receives the first position of every slot.
+static void grouped_order(const std::vector<int32_t>& hrp, const int32_t* grp, int64_t n,
+                          std::vector<int32_t>& sched, int64_t slot_pos[9]) {
+  auto cnt = [&](int64_t i) { return (int64_t)(hrp[i + 1] - hrp[i]); };
+  int32_t mx = 0;
+  int64_t ng = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    mx = std::max(mx, (int32_t)cnt(i));
+    ng = std::max<int64_t>(ng, (int64_t)grp[i] + 1);
+  }
+  // rows by entry count, descending, ties in row order
+  std::vector<int32_t> bydeg(n);
+  {
+    std::vector<int64_t> slot((size_t)mx + 2, 0);
+    for (int64_t i = 0; i < n; ++i) ++slot[(size_t)(mx - cnt(i)) + 1];
+    for (int32_t c = 0; c <= mx; ++c) slot[(size_t)c + 1] += slot[c];
+    for (int64_t i = 0; i < n; ++i) bydeg[(size_t)slot[(size_t)(mx - cnt(i))]++] = (int32_t)i;
+  }
+  std::vector<int64_t> gcost((size_t)ng, 0);
+  for (int64_t i = 0; i < n; ++i)
+    if (grp[i] >= 0) gcost[(size_t)grp[i]] += cnt(i) + 1;
+  std::vector<int32_t> gorder((size_t)ng);
+  std::iota(gorder.begin(), gorder.end(), 0);
+  std::stable_sort(gorder.begin(), gorder.end(),
+                   [&](int32_t a, int32_t b) { return gcost[(size_t)a] > gcost[(size_t)b]; });
+  int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  auto least = [&] {
+    int x = 0;
+    for (int y = 1; y < 8; ++y)
+      if (load[y] < load[x]) x = y;
+    return x;
+  };
+  std::vector<int8_t> gslot((size_t)ng, -1);
+  std::vector<int32_t> gseq;  // groups in assignment order
+  gseq.reserve((size_t)ng);
+  for (int32_t gi : gorder) {
+    if (gcost[(size_t)gi] == 0) break;
+    const int x = least();
+    gslot[(size_t)gi] = (int8_t)x;
+    load[x] += gcost[(size_t)gi];
+    gseq.push_back(gi);
+  }
+  std::vector<int8_t> rslot((size_t)n);
+  for (int64_t q = 0; q < n; ++q) {
+    const int32_t i = bydeg[(size_t)q];
+    if (grp[i] >= 0) {
+      rslot[(size_t)i] = gslot[(size_t)grp[i]];
+    } else {
+      const int x = least();
+      rslot[(size_t)i] = (int8_t)x;
+      load[x] += cnt(i) + 1;
+    }
+  }
+  // bucket of a row: within slot x, 0 = heavy, 1 + r = the r-th group of the
+  // slot, last = no group
+  std::vector<int64_t> gbucket((size_t)ng, 0);
+  std::vector<int64_t> base(9, 0);
+  {
+    int64_t per[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int32_t gi : gseq) gbucket[(size_t)gi] = 1 + per[gslot[(size_t)gi]]++;
+    for (int x = 0; x < 8; ++x) base[x + 1] = base[x] + per[x] + 2;
+  }
+  auto bucket = [&](int32_t i) -> int64_t {
+    const int x = rslot[(size_t)i];
+    if (cnt(i) >= kHeavyDeg) return base[x];
+    if (grp[i] >= 0) return base[x] + gbucket[(size_t)grp[i]];
+    return base[x + 1] - 1;
+  };
+  std::vector<int64_t> next((size_t)base[8] + 1, 0);
+  for (int64_t i = 0; i < n; ++i) ++next[(size_t)bucket((int32_t)i) + 1];
+  for (int64_t b = 0; b < base[8]; ++b) next[(size_t)b + 1] += next[(size_t)b];
+  for (int x = 0; x <= 8; ++x) slot_pos[x] = next[(size_t)base[x]];
+  for (int64_t q = 0; q < n; ++q) {
+    const int32_t i = bydeg[(size_t)q];
+    sched[(size_t)next[(size_t)bucket(i)]++] = i;
+  }
+}
+
+static ofm_status build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr,
+                                  const int32_t* col_idx, const double* vals, unsigned flags,
+                                  const int32_t* groups, hipStream_t stream, ofm_laplacian* out);
 
 extern "C" ofm_status ofm_build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr,
                                           const int32_t* col_idx, const double* vals,
                                           unsigned flags, hipStream_t stream,
                                           ofm_laplacian* out) {
+  return build_laplacian(n, nnz, row_ptr, col_idx, vals, flags, nullptr, stream, out);
+}
+
+extern "C" ofm_status ofm_build_laplacian_grouped(int64_t n, int64_t nnz, const int32_t* row_ptr,
+                                                  const int32_t* col_idx, const double* vals,
+                                                  unsigned flags, const int32_t* host_groups,
+                                                  hipStream_t stream, ofm_laplacian* out) {
+  if (!out) return OFM_E_INVALID_ARG;
+  *out = nullptr;
+  if (!host_groups || (flags & OFM_LAP_NO_REORDER) || n <= 0) return OFM_E_INVALID_ARG;
+  for (int64_t i = 0; i < n; ++i)
+    if ((int64_t)host_groups[i] >= n) return OFM_E_INVALID_ARG;
+  return build_laplacian(n, nnz, row_ptr, col_idx, vals, flags, host_groups, stream, out);
+}
+
+static ofm_status build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr,
+                                  const int32_t* col_idx, const double* vals, unsigned flags,
+                                  const int32_t* groups, hipStream_t stream, ofm_laplacian* out) {
   if (!out) return OFM_E_INVALID_ARG;
   *out = nullptr;
   if (n <= 0 || nnz < 0 || !row_ptr || (nnz > 0 && !col_idx)) return OFM_E_INVALID_ARG;
@@ -326,7 +433,10 @@ extern "C" ofm_status ofm_build_laplacian(int64_t n, int64_t nnz, const int32_t*
   // row-processing order: by number of entries, descending, ties in row order
   // (a counting sort over the entry counts: O(n + max count))
   std::vector<int32_t> sched(n);
-  if (g.reorder) {
+  int64_t slot_pos[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (groups) {
+    grouped_order(hrp, groups, n, sched, slot_pos);
+  } else if (g.reorder) {
     int32_t mx = 0;
     for (int64_t i = 0; i < n; ++i) mx = std::max(mx, hrp[i + 1] - hrp[i]);
     std::vector<int64_t> slot((size_t)mx + 2, 0);  // slot[mx - count]: next position
@@ -373,7 +483,18 @@ extern "C" ofm_status ofm_build_laplacian(int64_t n, int64_t nnz, const int32_t*
     return fail(OFM_E_HIP);
   const int trs[3] = {16, 32, 64};
   for (int i = 0; i < 3; ++i) {
-    std::vector<int32_t> t = build_tiles(sdeg, trs[i], g.reorder);
+    std::vector<int32_t> t;
+    if (groups) {
+      L->tt[i].xcd = true;
+      for (int x = 0; x < 8; ++x) {
+        L->tt[i].xt[x] = (int32_t)t.size();
+        build_tiles(sdeg, trs[i], true, slot_pos[x], slot_pos[x + 1], t);
+      }
+      L->tt[i].xt[8] = (int32_t)t.size();
+    } else {
+      build_tiles(sdeg, trs[i], g.reorder, 0, n, t);
+    }
+    t.push_back((int32_t)n);
     L->tt[i].tr = trs[i];
     L->tt[i].ntiles = (int64_t)t.size() - 1;
     if ((st = dev_alloc(&L->tt[i].dev, t.size())) != OFM_OK) return fail(st);
@@ -420,6 +541,34 @@ static void fill_graph(PassArgs& a, ofm_laplacian lap, const TileTable* tt, int 
   a.ntiles = tt->ntiles;
   a.pk = precision == OFM_FP64 ? lap->g.pk64 : lap->g.pk32;
   a.cold_below = lap->g.cold_below;
+  a.xcd = tt->xcd ? 1 : 0;
+  for (int x = 0; x < 9; ++x) a.xt[x] = tt->xt[x];
+}
+
+// Workgroups of an SpMM launch.  Grouped order: one workgroup per WPB tiles of
+// the largest slot, times 8 (the hardware dispatches workgroups in order and
+// places workgroup b on XCD b % 8, so each XCD walks its slot front to back as
+// workgroups retire) when the reduction scratch holds that many partial rows
+// of nv (cap, in doubles), else kMaxBlocks workgroups striding over the slots.
+static int spmm_grid(const TileTable* tt, int precision, int k, int nv, size_t cap) {
+  if (!tt->xcd) return pass_blocks(precision, k, tt->ntiles);
+  const int w = spmm_wpb(precision, k);
+  int64_t per = 1;
+  for (int x = 0; x < 8; ++x)
+    per = std::max<int64_t>(per, ((int64_t)tt->xt[x + 1] - tt->xt[x] + w - 1) / w);
+  const int64_t one = 8 * per;
+  if (nv == 0 || (size_t)one * (size_t)nv <= cap) return (int)one;
+  return (int)std::min<int64_t>(kMaxBlocks, one);
+}
+
+// largest one-workgroup-per-tile-group grid of a tile table (see spmm_grid)
+static int64_t xcd_full_grid(const TileTable* tt, int precision, int k) {
+  if (!tt->xcd) return 0;
+  const int w = spmm_wpb(precision, k);
+  int64_t per = 1;
+  for (int x = 0; x < 8; ++x)
+    per = std::max<int64_t>(per, ((int64_t)tt->xt[x + 1] - tt->xt[x] + w - 1) / w);
+  return 8 * per;
 }
 
 extern "C" ofm_status ofm_apply_A(ofm_laplacian lap, int k, int precision, const void* Z, void* Y,
@@ -437,7 +586,7 @@ extern "C" ofm_status ofm_apply_A(ofm_laplacian lap, int k, int precision, const
   a.Z = Z;
   a.Y = Y;
   fill_graph(a, lap, tt, precision);
-  a.nblocks = pass_blocks(precision, k, tt->ntiles);
+  a.nblocks = spmm_grid(tt, precision, k, 0, 0);
   HIPCHK(launch_spmm(precision, k, a, stream));
   return OFM_OK;
 }
@@ -494,7 +643,7 @@ static ofm_status choose_gather(ofm_workspace ws, bool* hc) {
   a.Z = ws->V[0];
   a.Y = ws->AX;
   fill_graph(a, ws->lap, ws->tiles, ws->prec);
-  a.nblocks = pass_blocks(ws->prec, ws->k, ws->tiles->ntiles);
+  a.nblocks = spmm_grid(ws->tiles, ws->prec, ws->k, 0, 0);
   if (hipMemset(ws->V[0], 0, (size_t)ws->n * ws->k * ws->esz) != hipSuccess)
     return OFM_E_HIP;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -580,8 +729,18 @@ extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_o
     if ((st = dev_alloc(reinterpret_cast<char**>(&ws->Vb), blk / 2)) != OFM_OK) return fail(st);
   }
   if ((st = dev_alloc(&ws->sc, sc_total(k))) != OFM_OK) return fail(st);
-  if ((st = dev_alloc(&ws->partials, (size_t)kMaxBlocks * nvmax)) != OFM_OK) return fail(st);
-  if ((st = dev_alloc(&ws->lvl2, (size_t)ny * nvmax)) != OFM_OK) return fail(st);
+  // partial rows: kMaxBlocks of every layout, or, on a grouped Laplacian, the
+  // full grid of the plain steps (3k per row) when that is more; lvl2 then
+  // also holds the intermediate levels of the reduction
+  ws->part_cap = (size_t)kMaxBlocks * nvmax;
+  size_t lvl2_size = (size_t)ny * nvmax;
+  if (const int64_t full = xcd_full_grid(tt, prec, k)) {
+    ws->part_cap = std::max(ws->part_cap, (size_t)full * 3 * k);
+    lvl2_size = std::max(lvl2_size, ws->part_cap / kFinChunk + ws->part_cap / (kFinChunk * kFinChunk) +
+                                         (size_t)(2 + kMaxBlocks / kFinChunk) * nvmax);
+  }
+  if ((st = dev_alloc(&ws->partials, ws->part_cap)) != OFM_OK) return fail(st);
+  if ((st = dev_alloc(&ws->lvl2, lvl2_size)) != OFM_OK) return fail(st);
   if ((st = dev_alloc(&ws->status, 1)) != OFM_OK) return fail(st);
   if ((st = dev_alloc(&ws->frozen, 1)) != OFM_OK) return fail(st);
   if (hipMemset(ws->sc, 0, sc_total(k) * sizeof(double)) != hipSuccess ||
@@ -638,7 +797,7 @@ static ofm_status finalize(ofm_workspace ws, const PassArgs& a, hipStream_t s) {
 static ofm_status run_spmm(ofm_workspace ws, PassArgs& a, hipStream_t s) {
   fill_graph(a, ws->lap, ws->tiles, ws->prec);
   if (ws->hc) a.flags |= kFlagHC;
-  a.nblocks = pass_blocks(ws->prec, ws->k, ws->tiles->ntiles);
+  a.nblocks = spmm_grid(ws->tiles, ws->prec, ws->k, a.nv, ws->part_cap);
   HIPCHK(timed(ws, pass_kind(a.mode), s, [&] { return launch_spmm(ws->prec, ws->k, a, s); }));
   return finalize(ws, a, s);
 }

@@ -138,6 +138,10 @@ struct PassArgs {
   int64_t ntiles = 0;
   const void* pk = nullptr;
   int cold_below = 0;          // rows with fewer entries are cold (kFlagHC)
+  // XCD slots (grouped order): the workgroups b with b % 8 == x walk the tiles
+  // [xt[x], xt[x+1]); the grid is then a multiple of 8 workgroups
+  int xcd = 0;
+  int32_t xt[9] = {};
   // BF16 copies: gather source of the SpMM (null: gather Z itself) and the
   // copies written by the producing passes
   const void* Zg = nullptr;
@@ -219,6 +223,7 @@ hipError_t launch_objective(int k, int variant, double normA2, const double* sc,
                             hipStream_t s);
 int tile_rows(int precision, int k);
 int pass_blocks(int precision, int k, int64_t ntiles);
+int spmm_wpb(int precision, int k);
 int partial_nv(int k, int mode, int flags);
 int partial_off(int k, int mode);
 

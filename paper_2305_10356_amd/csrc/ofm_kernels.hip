@@ -561,8 +561,15 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
   zero_gram<T, KP>(gA);
   zero_gram<T, KP>(gB);
 
-  const int64_t stride = (int64_t)nblk * WPB;
-  for (int64_t t = (int64_t)brank * WPB + wave; t < a.ntiles; t += stride) {
+  int64_t t = (int64_t)brank * WPB + wave, tend = a.ntiles, stride = (int64_t)nblk * WPB;
+  if (a.xcd) {
+    // grouped order: workgroup b runs on XCD b % 8 and walks that XCD's slot
+    const int x = brank & 7;
+    t = a.xt[x] + (int64_t)(brank >> 3) * WPB + wave;
+    tend = a.xt[x + 1];
+    stride = (int64_t)(nblk >> 3) * WPB;
+  }
+  for (; t < tend; t += stride) {
     const int tinfo = a.tiles[t];
     const int start = tinfo & 0x7fffffff;
     const bool heavy = tinfo < 0;
@@ -1553,6 +1560,8 @@ static int wpb(int precision, int k) {
   return 1;
 }
 
+int spmm_wpb(int precision, int k) { return wpb(precision, k); }
+
 int pass_blocks(int precision, int k, int64_t ntiles) {
   const int w = wpb(precision, k);
   int64_t nb = (ntiles + w - 1) / w;
@@ -1603,7 +1612,8 @@ static int resident_blocks(int threads, int smem) {
 template <auto Kernel>
 static hipError_t launch_rounded(PassArgs& a, int threads, int smem, hipStream_t s) {
   const int cap = resident_blocks<Kernel>(threads, smem);
-  if (cap > 0 && a.nblocks > cap) a.nblocks = (a.nblocks / cap) * cap;
+  // the XCD slots rely on the grid as given (in-order dispatch, a multiple of 8)
+  if (!a.xcd && cap > 0 && a.nblocks > cap) a.nblocks = (a.nblocks / cap) * cap;
   hipLaunchKernelGGL(Kernel, dim3(a.nblocks), dim3(threads), smem, s, a);
   return hipGetLastError();
 }
@@ -1705,12 +1715,30 @@ hipError_t launch_dense(int precision, int k, PassArgs& a, hipStream_t s) {
 
 hipError_t launch_finalize(const double* partials, int nb, int nv, double* out, double* lvl2,
                            hipStream_t s, int split, double* out2) {
-  const int ny = (nb + kFinChunk - 1) / kFinChunk;
   if (split >= nv || !out2) {
     split = nv;
     out2 = out;
   }
   const int nx = (nv + 63) / 64;
+  // more partial rows than one two-level pass takes: sum groups of kFinChunk
+  // rows level by level (in block order) into lvl2 and the region after it
+  // (lvl2 holds ceil(nb / kFinChunk) + ceil(nb / kFinChunk^2) rows of nv)
+  if (nb > kMaxBlocks) {
+    double* buf[2] = {lvl2, lvl2 + (size_t)((nb + kFinChunk - 1) / kFinChunk) * nv};
+    int w = 0;
+    while (nb > kMaxBlocks) {
+      const int ny = (nb + kFinChunk - 1) / kFinChunk;
+      hipLaunchKernelGGL(finalize_kernel, dim3(nx, ny), dim3(64), 0, s, partials, nb, nv, buf[w],
+                         out, split, out2);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      partials = buf[w];
+      nb = ny;
+      w ^= 1;
+    }
+    lvl2 = buf[w];
+  }
+  const int ny = (nb + kFinChunk - 1) / kFinChunk;
   hipLaunchKernelGGL(finalize_kernel, dim3(nx, ny), dim3(64), 0, s, partials, nb, nv, lvl2, out,
                      split, out2);
   if (ny > 1) {

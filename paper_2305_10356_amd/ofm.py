@@ -83,6 +83,8 @@ _SIGS = {
     "ofm_status_string": (ctypes.c_char_p, [_I]),
     "ofm_version": (ctypes.c_char_p, []),
     "ofm_build_laplacian": (_I, [_I64, _I64, _P, _P, _P, ctypes.c_uint, _P, ctypes.POINTER(_P)]),
+    "ofm_build_laplacian_grouped": (_I, [_I64, _I64, _P, _P, _P, ctypes.c_uint, _P, _P,
+                                         ctypes.POINTER(_P)]),
     "ofm_laplacian_destroy": (_I, [_P]),
     "ofm_laplacian_info": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                 ctypes.POINTER(_D), _P]),
@@ -173,7 +175,10 @@ class Laplacian:
     """Handle of the shifted normalized Laplacian A = L - 2I of a graph."""
 
     def __init__(self, row_ptr, col_idx, vals=None, validate: bool = False,
-                 reorder: bool = True, stream=None):
+                 reorder: bool = True, groups=None, stream=None):
+        """``groups``: optional int32[n] host array (e.g. cluster labels of an
+        earlier solve; negative = none) that lays the row-processing order out
+        for the XCDs (``ofm_build_laplacian_grouped``)."""
         torch = _torch()
         lib = load()
         self._lib = lib
@@ -183,10 +188,21 @@ class Laplacian:
         n = rp.numel() - 1
         flags = (OFM_LAP_VALIDATE if validate else 0) | (0 if reorder else OFM_LAP_NO_REORDER)
         h = ctypes.c_void_p()
-        st = lib.ofm_build_laplacian(n, ci.numel(), _ptr(rp), _ptr(ci) if ci.numel() else None,
-                                     _ptr(vv) if vv is not None else None, flags, _stream(stream),
-                                     ctypes.byref(h))
-        _check(st, "ofm_build_laplacian")
+        if groups is None:
+            st = lib.ofm_build_laplacian(n, ci.numel(), _ptr(rp), _ptr(ci) if ci.numel() else None,
+                                         _ptr(vv) if vv is not None else None, flags,
+                                         _stream(stream), ctypes.byref(h))
+            _check(st, "ofm_build_laplacian")
+        else:
+            gr = np.ascontiguousarray(np.asarray(groups), dtype=np.int32)
+            if gr.shape != (n,):
+                raise ValueError("groups must hold one entry per node")
+            st = lib.ofm_build_laplacian_grouped(
+                n, ci.numel(), _ptr(rp), _ptr(ci) if ci.numel() else None,
+                _ptr(vv) if vv is not None else None, flags, gr.ctypes.data_as(ctypes.c_void_p),
+                _stream(stream), ctypes.byref(h))
+            _check(st, "ofm_build_laplacian_grouped")
+        self.grouped = groups is not None
         self.handle = h
         self.n = n
         self.nnz = ci.numel()
