@@ -224,12 +224,15 @@ def spmm_locality_ladder(g, k: int = 32, windows=(32768, 262144, None), reps: in
 
 
 def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10,
-                 cold_stages=(9,), recur: bool = False, check_every: int = 10):
+                 cold_stages=(9,), recur: bool = False, check_every: int = 10,
+                 grouped: bool = False):
     """Growth stream of 10 snapshots, N = 200k .. 2M, k = 64, mean degree 20,
     r = 0.3: each stage solved to residual 1e-4 (checked every 10 iterations)
     in FP32 from the previous stage's solution (new rows N(0, 1/N_s)), with
     the loop replayed as HIP graphs.  The stages in ``cold_stages`` are also
-    solved from a fresh random block for comparison."""
+    solved from a fresh random block for comparison.  ``grouped``: each stage's
+    Laplacian is built with its rows laid out for the XCDs by the clusters of
+    the previous stage (k-means on its features, timed apart as labels_s)."""
     import torch
     from paper_2305_10356_amd import graphs, ofm
     from paper_2305_10356_amd.streaming import StreamingSolver
@@ -239,7 +242,7 @@ def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10
     tri = variant.startswith("tri")
     warm = StreamingSolver(64, variant=variant, precision=ofm.OFM_FP32, tol=1e-4,
                            check_every=check_every, max_iter=5000, graph=True, restart=tri,
-                           recur=recur, seed=4)
+                           recur=recur, seed=4, grouped=grouped)
     stages_out = []
     for s in range(stages):
         g = gs.snapshot(s)
@@ -254,8 +257,9 @@ def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10
             rec["cold_solve_s"] = round(rc["solve_s"], 4)
             rec["cold_converged"] = rc["converged"]
             del cold
-        for key in ("solve_s", "laplacian_s", "xinit_s"):
-            rec[key] = round(rec[key], 4)
+        for key in ("solve_s", "laplacian_s", "xinit_s", "labels_s"):
+            if key in rec:
+                rec[key] = round(rec[key], 4)
         log(f"stream stage {s}: {rec}")
         stages_out.append(rec)
     torch.cuda.synchronize()
@@ -264,6 +268,7 @@ def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10
                     f"mean-degree 20 r=0.3, FP32, graph-replayed loop, tol 1e-4",
         "variant": variant,
         "recur_ax": recur,
+        "grouped_order": grouped,
         "check_every": check_every,
         "total_solve_s": round(sum(r["solve_s"] for r in stages_out), 4),
         "all_converged": all(r["converged"] == 1 for r in stages_out),
@@ -317,6 +322,7 @@ def grouped_order(row_ptr, col_idx, X, k: int, x0, variant: str, planted):
     XCDs by the clusters of a finished solve (k-means++ and Lloyd on the
     row-normalized features), as a re-solve or the next snapshot of a stream
     would have them."""
+    import numpy as np
     import torch
     from paper_2305_10356_amd import ofm
     u = np.random.default_rng([7, 7]).random(k)
@@ -383,7 +389,8 @@ def main():
                     help="cache policy of the SpMM row gathers of the headline loop (auto: "
                          "timed at workspace creation)")
     ap.add_argument("--grouped", action="store_true",
-                    help="with --postprocess-only: also time the step on the XCD-grouped order")
+                    help="with --postprocess-only: also time the step on the XCD-grouped order; "
+                         "with --streaming-only: group each stage by the previous one's clusters")
     ap.add_argument("--postprocess-only", action="store_true",
                     help="solve the 2M-node graph to residual 1e-4, then time only the "
                          "post-processing (row normalisation, K-means); prints its JSON")
@@ -404,7 +411,8 @@ def main():
         print(json.dumps(batched_vs_plain(args.variant, plain=False)), flush=True)
         return
     if args.streaming_only:
-        print(json.dumps(streaming_c4(args.variant, recur=args.recur)), flush=True)
+        print(json.dumps(streaming_c4(args.variant, recur=args.recur, grouped=args.grouped)),
+              flush=True)
         return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -652,6 +660,7 @@ def main():
         if not args.no_streaming:
             extras["streaming_warm_start"] = streaming_c4(args.variant)
             extras["streaming_warm_start_recur"] = streaming_c4(args.variant, recur=True)
+            extras["streaming_warm_start_grouped"] = streaming_c4(args.variant, grouped=True)
         extras["postprocess"] = postprocess(X3, k)
         extras["grouped_order"] = grouped_order(g.row_ptr, g.col_idx, X3, k, x0, args.variant,
                                                 g.labels)

@@ -545,30 +545,36 @@ static void fill_graph(PassArgs& a, ofm_laplacian lap, const TileTable* tt, int 
   for (int x = 0; x < 9; ++x) a.xt[x] = tt->xt[x];
 }
 
-// Workgroups of an SpMM launch.  Grouped order: one workgroup per WPB tiles of
-// the largest slot, times 8 (the hardware dispatches workgroups in order and
-// places workgroup b on XCD b % 8, so each XCD walks its slot front to back as
-// workgroups retire) when the reduction scratch holds that many partial rows
-// of nv (cap, in doubles), else kMaxBlocks workgroups striding over the slots.
-static int spmm_grid(const TileTable* tt, int precision, int k, int nv, size_t cap) {
-  if (!tt->xcd) return pass_blocks(precision, k, tt->ntiles);
-  const int w = spmm_wpb(precision, k);
-  int64_t per = 1;
-  for (int x = 0; x < 8; ++x)
-    per = std::max<int64_t>(per, ((int64_t)tt->xt[x + 1] - tt->xt[x] + w - 1) / w);
-  const int64_t one = 8 * per;
-  if (nv == 0 || (size_t)one * (size_t)nv <= cap) return (int)one;
-  return (int)std::min<int64_t>(kMaxBlocks, one);
-}
-
-// largest one-workgroup-per-tile-group grid of a tile table (see spmm_grid)
+// Grid of an SpMM launch (a.nblocks, a.xr).  Grouped order: one workgroup per
+// chunk of kXcdChunk tiles per wave of the largest slot, times 8 (the hardware
+// dispatches workgroups in order and places workgroup b on XCD b % 8, so each
+// XCD walks its slot front to back as workgroups retire), when the reduction
+// scratch holds that many partial rows of nv (cap, in doubles); else
+// kMaxBlocks workgroups striding over the slots a tile per wave at a time.
 static int64_t xcd_full_grid(const TileTable* tt, int precision, int k) {
   if (!tt->xcd) return 0;
-  const int w = spmm_wpb(precision, k);
+  const int64_t span = (int64_t)spmm_wpb(precision, k) * kXcdChunk;
   int64_t per = 1;
   for (int x = 0; x < 8; ++x)
-    per = std::max<int64_t>(per, ((int64_t)tt->xt[x + 1] - tt->xt[x] + w - 1) / w);
+    per = std::max<int64_t>(per, ((int64_t)tt->xt[x + 1] - tt->xt[x] + span - 1) / span);
   return 8 * per;
+}
+
+static void spmm_grid(PassArgs& a, const TileTable* tt, int precision, int k, int nv,
+                      size_t cap) {
+  a.xr = 1;
+  if (!tt->xcd) {
+    a.nblocks = pass_blocks(precision, k, tt->ntiles);
+    return;
+  }
+  const int64_t one = xcd_full_grid(tt, precision, k);
+  if (nv == 0 || (size_t)one * (size_t)nv <= cap) {
+    a.nblocks = (int)one;
+    a.xr = kXcdChunk;
+    return;
+  }
+  const int64_t w = spmm_wpb(precision, k);
+  a.nblocks = (int)std::min<int64_t>(kMaxBlocks, 8 * ((tt->ntiles + 8 * w - 1) / (8 * w)));
 }
 
 extern "C" ofm_status ofm_apply_A(ofm_laplacian lap, int k, int precision, const void* Z, void* Y,
@@ -586,7 +592,7 @@ extern "C" ofm_status ofm_apply_A(ofm_laplacian lap, int k, int precision, const
   a.Z = Z;
   a.Y = Y;
   fill_graph(a, lap, tt, precision);
-  a.nblocks = spmm_grid(tt, precision, k, 0, 0);
+  spmm_grid(a, tt, precision, k, 0, 0);
   HIPCHK(launch_spmm(precision, k, a, stream));
   return OFM_OK;
 }
@@ -643,7 +649,7 @@ static ofm_status choose_gather(ofm_workspace ws, bool* hc) {
   a.Z = ws->V[0];
   a.Y = ws->AX;
   fill_graph(a, ws->lap, ws->tiles, ws->prec);
-  a.nblocks = spmm_grid(ws->tiles, ws->prec, ws->k, 0, 0);
+  spmm_grid(a, ws->tiles, ws->prec, ws->k, 0, 0);
   if (hipMemset(ws->V[0], 0, (size_t)ws->n * ws->k * ws->esz) != hipSuccess)
     return OFM_E_HIP;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -797,7 +803,7 @@ static ofm_status finalize(ofm_workspace ws, const PassArgs& a, hipStream_t s) {
 static ofm_status run_spmm(ofm_workspace ws, PassArgs& a, hipStream_t s) {
   fill_graph(a, ws->lap, ws->tiles, ws->prec);
   if (ws->hc) a.flags |= kFlagHC;
-  a.nblocks = spmm_grid(ws->tiles, ws->prec, ws->k, a.nv, ws->part_cap);
+  spmm_grid(a, ws->tiles, ws->prec, ws->k, a.nv, ws->part_cap);
   HIPCHK(timed(ws, pass_kind(a.mode), s, [&] { return launch_spmm(ws->prec, ws->k, a, s); }));
   return finalize(ws, a, s);
 }

@@ -17,6 +17,10 @@ constexpr int kHeavyTileNnz = 1024;
 #ifndef OFM_GATHER_CH
 #define OFM_GATHER_CH 8
 #endif
+#ifndef OFM_XCD_CHUNK
+#define OFM_XCD_CHUNK 2
+#endif
+constexpr int kXcdChunk = OFM_XCD_CHUNK;  // tiles per wave of a workgroup in the grouped order
 constexpr int kMaxBlocks = OFM_MAX_BLOCKS;  // persistent grid cap for reduction kernels
 constexpr int kGatherChunk = OFM_GATHER_CH; // entries in flight per lane group and pass
 constexpr int kFinChunk = 32;     // partial rows summed per first-level finalize block
@@ -139,8 +143,10 @@ struct PassArgs {
   const void* pk = nullptr;
   int cold_below = 0;          // rows with fewer entries are cold (kFlagHC)
   // XCD slots (grouped order): the workgroups b with b % 8 == x walk the tiles
-  // [xt[x], xt[x+1]); the grid is then a multiple of 8 workgroups
+  // [xt[x], xt[x+1]) in chunks of xr * (waves per workgroup) tiles; the grid
+  // is then a multiple of 8 workgroups
   int xcd = 0;
+  int xr = 1;
   int32_t xt[9] = {};
   // BF16 copies: gather source of the SpMM (null: gather Z itself) and the
   // copies written by the producing passes

@@ -561,15 +561,21 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
   zero_gram<T, KP>(gA);
   zero_gram<T, KP>(gB);
 
-  int64_t t = (int64_t)brank * WPB + wave, tend = a.ntiles, stride = (int64_t)nblk * WPB;
+  // tiles of this wave: chunks of `span` consecutive tiles, chunk c0, c0 +
+  // cstride, ...; each wave takes every WPB-th tile of a chunk
+  int64_t c0 = (int64_t)brank * WPB, tend = a.ntiles, cstride = (int64_t)nblk * WPB;
+  int64_t span = WPB;
   if (a.xcd) {
     // grouped order: workgroup b runs on XCD b % 8 and walks that XCD's slot
+    // in chunks of xr * WPB tiles
     const int x = brank & 7;
-    t = a.xt[x] + (int64_t)(brank >> 3) * WPB + wave;
+    span = (int64_t)WPB * a.xr;
+    c0 = a.xt[x] + (int64_t)(brank >> 3) * span;
     tend = a.xt[x + 1];
-    stride = (int64_t)(nblk >> 3) * WPB;
+    cstride = (int64_t)(nblk >> 3) * span;
   }
-  for (; t < tend; t += stride) {
+  for (; c0 < tend; c0 += cstride)
+  for (int64_t t = c0 + wave, cend = c0 + span < tend ? c0 + span : tend; t < cend; t += WPB) {
     const int tinfo = a.tiles[t];
     const int start = tinfo & 0x7fffffff;
     const bool heavy = tinfo < 0;

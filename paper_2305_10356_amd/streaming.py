@@ -37,7 +37,8 @@ class StreamingSolver:
     def __init__(self, k: int, variant="f1", precision=ofm.OFM_FP32, tol: float = 1e-4,
                  check_every: int = 10, max_iter: int = 5000, graph: bool = True,
                  restart: bool = False, recur: bool = False, seed: int = 4,
-                 gather: int = ofm.GATHER_AUTO):
+                 gather: int = ofm.GATHER_AUTO, grouped: bool = False,
+                 label_iters: int = 30):
         self.k = k
         self.variant = variant
         self.precision = precision
@@ -51,6 +52,12 @@ class StreamingSolver:
         # gather policy: chosen by timing at the first stage whose block is
         # large enough, then kept for the later stages
         self.gather = gather
+        # grouped: after each stage, cluster its features (Algorithm 1, steps
+        # 4-5) and build the next stage's Laplacian with its rows laid out for
+        # the XCDs by those clusters (new nodes in no group)
+        self.grouped = grouped
+        self.label_iters = label_iters
+        self.labels = None
         self.X = None
         self.stage = 0
         self.records: List[dict] = []
@@ -82,7 +89,11 @@ class StreamingSolver:
         import torch
         n = int(row_ptr.shape[0] - 1)
         t0 = time.perf_counter()
-        lap = ofm.Laplacian(row_ptr, col_idx)
+        groups = None
+        if self.grouped and self.labels is not None and warm:
+            groups = np.full(n, -1, dtype=np.int32)
+            groups[:self.labels.shape[0]] = self.labels
+        lap = ofm.Laplacian(row_ptr, col_idx, groups=groups)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         X = self.initial_block(n, self.X if warm else None)
@@ -103,6 +114,13 @@ class StreamingSolver:
             "solve_s": t3 - t2, "laplacian_s": t1 - t0, "xinit_s": t2 - t1,
             "gather": int(st["gather"]),
         }
+        if self.grouped:
+            u = np.random.default_rng([self.seed, 3, self.stage]).random(self.k)
+            labels, _, _ = ofm.kmeans(ofm.row_normalize(X), self.k, u, max_iter=self.label_iters)
+            self.labels = labels.cpu().numpy()
+            torch.cuda.synchronize()
+            rec["labels_s"] = time.perf_counter() - t3
+            rec["grouped_order"] = groups is not None
         if self.gather == ofm.GATHER_AUTO and n * self.k * (8 if self.precision == ofm.OFM_FP64
                                                             else 4) >= 32 << 20:
             self.gather = int(st["gather"])

@@ -7,7 +7,9 @@ the graph-captured solve loop.
   stage, reaches the tolerance, and its limit matches the dense
   eigendecomposition of that stage's Laplacian (Theorem 1 for f1, Theorem 3
   for f2), checked with the FP64 oracle;
-* warm starts need fewer iterations than cold starts from N(0, 1/N)."""
+* warm starts need fewer iterations than cold starts from N(0, 1/N);
+* a stream whose stages are built in the row order grouped by the previous
+  stage's clusters converges like the plain order."""
 import sys
 
 import numpy as np
@@ -138,3 +140,28 @@ def test_streaming_fp32_k64(lib, recur):
     olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     # the FP64 residual of the FP32 iterate agrees with the library's
     assert O.relres(olap, X) == pytest.approx(rw["relres"], rel=0.05, abs=2e-6)
+
+
+def test_streaming_grouped_order_fp32(lib):
+    """Each stage after the first built with its rows grouped for the XCDs by
+    the previous stage's clusters: every stage converges, the residual of the
+    last iterate agrees with the oracle's, and the iterations match the plain
+    order's within the spread of FP32 roundings."""
+    from paper_2305_10356_amd import ofm
+    from paper_2305_10356_amd.streaming import StreamingSolver
+    gs = graphs.GrowthStream(n_final=90000, stages=3, k=64, dbar=20, r=0.3, seed=7)
+    plain = StreamingSolver(64, precision=ofm.OFM_FP32, tol=1e-4, check_every=5, max_iter=4000,
+                            graph=True, seed=7)
+    grp = StreamingSolver(64, precision=ofm.OFM_FP32, tol=1e-4, check_every=5, max_iter=4000,
+                          graph=True, seed=7, grouped=True)
+    for s in range(3):
+        g = gs.snapshot(s)
+        say(f"grouped stream stage {s} n={g.n}")
+        rp = plain.solve_stage(g.row_ptr, g.col_idx)
+        rg = grp.solve_stage(g.row_ptr, g.col_idx)
+        say("plain", rp["iters"], "grouped", rg["iters"], rg["grouped_order"])
+        assert rg["converged"] == 1 and rg["grouped_order"] == (s > 0)
+        assert grp.labels.shape == (g.n,) and grp.labels.min() >= 0 and grp.labels.max() < 64
+        assert rg["iters"] <= 2 * rp["iters"] + 20
+    olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
+    assert O.relres(olap, host(grp.X)) == pytest.approx(rg["relres"], rel=0.05, abs=2e-6)
