@@ -128,3 +128,24 @@ def test_grouped_build_errors(ofm):
         ofm.Laplacian(g.row_ptr, g.col_idx, groups=g.labels, reorder=False)
     with pytest.raises(ValueError):
         ofm.Laplacian(g.row_ptr, g.col_idx, groups=g.labels[:-1])
+
+
+def test_grouped_weighted_validated_small(ofm):
+    """Weighted similarities, the symmetry check, and a graph smaller than one
+    tile per slot (several slots empty): products with A bitwise the plain
+    order's and equal to the oracle's."""
+    g, _ = graphs.workload("sbm-n1000-k8")
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    a, b = np.minimum(rows, g.col_idx), np.maximum(rows, g.col_idx)
+    w = 1.0 + ((a * 7919 + b * 104729) % 13) / 13.0  # symmetric by construction
+    olap = O.laplacian(g.n, g.row_ptr, g.col_idx, w)
+    rng = np.random.default_rng(3)
+    Z = torch.as_tensor(rng.standard_normal((g.n, 8))).cuda()
+    plain = ofm.Laplacian(g.row_ptr, g.col_idx, vals=w, validate=True)
+    ref = plain.apply(Z)
+    for gr in (g.labels, np.where(np.arange(g.n) < 40, 3, -1).astype(np.int32)):
+        lap = ofm.Laplacian(g.row_ptr, g.col_idx, vals=w, validate=True, groups=gr)
+        Y = lap.apply(Z)
+        assert torch.equal(Y, ref)
+        np.testing.assert_allclose(host(Y), O.apply_A(olap, host(Z)), rtol=0, atol=1e-13)
+        lap.close()
