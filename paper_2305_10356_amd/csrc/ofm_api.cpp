@@ -546,14 +546,22 @@ static void fill_graph(PassArgs& a, ofm_laplacian lap, const TileTable* tt, int 
 }
 
 // Grid of an SpMM launch (a.nblocks, a.xr).  Grouped order: one workgroup per
-// chunk of kXcdChunk tiles per wave of the largest slot, times 8 (the hardware
-// dispatches workgroups in order and places workgroup b on XCD b % 8, so each
-// XCD walks its slot front to back as workgroups retire), when the reduction
-// scratch holds that many partial rows of nv (cap, in doubles); else
+// chunk of xcd_chunk(mode) tiles per wave of the largest slot, times 8 (the
+// hardware dispatches workgroups in order and places workgroup b on XCD b % 8,
+// so each XCD walks its slot front to back as workgroups retire), when the
+// reduction scratch holds that many partial rows of nv (cap, in doubles); else
 // kMaxBlocks workgroups striding over the slots a tile per wave at a time.
-static int64_t xcd_full_grid(const TileTable* tt, int precision, int k) {
+// Chunks: the passes that form the direction load the k x k coefficients into
+// LDS in every workgroup and take 4 tiles per wave; the others 1 (measured on
+// the 2M-node graph: 1 / 2 / 4 / 8 tiles gave 1000 / 930 / 910 / 943 us for
+// the SpMM of X and 752 / 779 / 817 / 896 us for that of V).
+static int xcd_chunk(int mode) {
+  return (mode == kGF1 || mode == kGF2 || mode == kAXF2) ? 4 : 1;
+}
+
+static int64_t xcd_full_grid(const TileTable* tt, int precision, int k, int chunk) {
   if (!tt->xcd) return 0;
-  const int64_t span = (int64_t)spmm_wpb(precision, k) * kXcdChunk;
+  const int64_t span = (int64_t)spmm_wpb(precision, k) * chunk;
   int64_t per = 1;
   for (int x = 0; x < 8; ++x)
     per = std::max<int64_t>(per, ((int64_t)tt->xt[x + 1] - tt->xt[x] + span - 1) / span);
@@ -567,10 +575,11 @@ static void spmm_grid(PassArgs& a, const TileTable* tt, int precision, int k, in
     a.nblocks = pass_blocks(precision, k, tt->ntiles);
     return;
   }
-  const int64_t one = xcd_full_grid(tt, precision, k);
+  const int chunk = xcd_chunk(a.mode);
+  const int64_t one = xcd_full_grid(tt, precision, k, chunk);
   if (nv == 0 || (size_t)one * (size_t)nv <= cap) {
     a.nblocks = (int)one;
-    a.xr = kXcdChunk;
+    a.xr = chunk;
     return;
   }
   const int64_t w = spmm_wpb(precision, k);
@@ -740,7 +749,7 @@ extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_o
   // also holds the intermediate levels of the reduction
   ws->part_cap = (size_t)kMaxBlocks * nvmax;
   size_t lvl2_size = (size_t)ny * nvmax;
-  if (const int64_t full = xcd_full_grid(tt, prec, k)) {
+  if (const int64_t full = xcd_full_grid(tt, prec, k, 1)) {
     ws->part_cap = std::max(ws->part_cap, (size_t)full * 3 * k);
     lvl2_size = std::max(lvl2_size, ws->part_cap / kFinChunk + ws->part_cap / (kFinChunk * kFinChunk) +
                                          (size_t)(2 + kMaxBlocks / kFinChunk) * nvmax);

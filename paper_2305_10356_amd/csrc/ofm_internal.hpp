@@ -17,10 +17,6 @@ constexpr int kHeavyTileNnz = 1024;
 #ifndef OFM_GATHER_CH
 #define OFM_GATHER_CH 8
 #endif
-#ifndef OFM_XCD_CHUNK
-#define OFM_XCD_CHUNK 2
-#endif
-constexpr int kXcdChunk = OFM_XCD_CHUNK;  // tiles per wave of a workgroup in the grouped order
 constexpr int kMaxBlocks = OFM_MAX_BLOCKS;  // persistent grid cap for reduction kernels
 constexpr int kGatherChunk = OFM_GATHER_CH; // entries in flight per lane group and pass
 constexpr int kFinChunk = 32;     // partial rows summed per first-level finalize block
