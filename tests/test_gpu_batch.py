@@ -97,3 +97,21 @@ def test_batch_escalates_fp32_straggler(lib):
         rr = O.relres(olap, X.cpu().numpy().astype(np.float64))
         # the FP64 finish leaves an X whose FP32 rounding still meets the tolerance
         assert rr <= 1.05e-4, rr
+
+
+def test_batch_on_grouped_laplacians(batch_graphs):
+    """Laplacians built in the XCD-grouped row order (groups: the planted
+    blocks) serve the batched solver unchanged: its passes walk the tile table
+    in order, so each graph converges and its residual is the oracle's."""
+    from paper_2305_10356_amd import ofm
+    gs, _ = batch_graphs
+    laps = [ofm.Laplacian(g.row_ptr, g.col_idx, groups=g.labels) for g, _, _ in gs]
+    B = ofm.Batch(laps, [k for _, _, k in gs], variant="f1", max_iter=3000, tol=1e-4,
+                  check_every=10)
+    Xs = [torch.tensor(x0.astype(np.float32), device="cuda") for _, x0, _ in gs]
+    st = B.solve(Xs)
+    for (g, x0, k), X, s in zip(gs, Xs, st):
+        olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
+        rr = O.relres(olap, X.cpu().numpy().astype(np.float64))
+        assert s["converged"] == 1 and s["status"] == 0, s
+        assert rr == pytest.approx(s["relres"], rel=0.05, abs=2e-6), (g.n, k, rr, s["relres"])
