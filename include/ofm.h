@@ -179,9 +179,12 @@ ofm_status ofm_build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr,
  *                must be < n.  Only read during the call.
  * Results of ofm_apply_A are bitwise those of ofm_build_laplacian's order; the
  * k x k products of a workspace are summed over other workgroup partitions
- * (differences at the rounding of the FP64 sums).  Workspaces on such a
- * Laplacian launch one workgroup per tile group where their reduction scratch
- * allows (up to about 3k doubles per 64 rows).
+ * (differences at the rounding of the FP64 sums).  Products with A on such a
+ * Laplacian launch one workgroup per few 16-row tiles of each slot (tens of
+ * thousands of workgroups for millions of rows); a workspace created on it
+ * therefore holds more reduction scratch: 3k doubles per workgroup of its
+ * largest such grid (about 3k doubles per 32 to 64 rows, e.g. 24 MB at
+ * N = 2M, k = 32, FP32).
  * Errors: as ofm_build_laplacian; OFM_E_INVALID_ARG for a null host_groups, a
  * group id >= n, or OFM_LAP_NO_REORDER in flags.
  */
@@ -211,7 +214,9 @@ ofm_status ofm_apply_A(ofm_laplacian lap, int k, int precision, const void* Z, v
  * G_prev, AX, AV (with the recurrence, and for the f2 variants at k >= 32),
  * the k x k FP64 products and the reduction scratch.  Allocates device memory
  * (5 or 6 N x k blocks, plus BF16 copies of X and V for OFM_FP32_BF16X, plus
- * O(k^2) per block).  host_opts is copied.  With opts.gather = 0 and a block
+ * O(k^2) per workgroup of the passes; on a Laplacian from
+ * ofm_build_laplacian_grouped, 3k doubles per 32 to 64 rows).  host_opts is
+ * copied.  With opts.gather = 0 and a block
  * of 32 MB or more it also runs and times six products with A (synchronizing).
  */
 ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_opts* host_opts,
