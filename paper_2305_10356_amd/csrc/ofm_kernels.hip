@@ -119,15 +119,24 @@ struct EntT<double> {
   typedef Ent64 type;
 };
 
-// waves per block: keep the dynamic LDS of a block under 60 KiB
+// waves per block: keep the dynamic LDS of a block under kLdsBlockCap (a
+// workgroup may hold up to 160 KB on this chip).  90 KB gives four waves per
+// workgroup to FP32 k = 64 and FP64 k = 32 (two below 67 KB): the FP32 k = 64
+// SpMM of X is then held to 2 instead of 1.5 waves per SIMD by its registers
+// rather than by its LDS (2.05 -> 1.85 ms on a 2M-node graph; the dense passes
+// lose 15-36 us), FP64 k = 32 is unchanged (215 vs 215 iterations/s).
+#ifndef OFM_LDS_BLOCK_CAP
+#define OFM_LDS_BLOCK_CAP (90 * 1024)
+#endif
+constexpr int kLdsBlockCap = OFM_LDS_BLOCK_CAP;
 template <typename T, int KP>
 struct Cfg {
   static constexpr int TB = Geo<T, KP>::TILE_ELEMS * (int)sizeof(T);
   static constexpr int FB = Geo<T, KP>::FRAG_ELEMS * (int)sizeof(T);
   static constexpr int per_wave = 3 * TB + Geo<T, KP>::TR * 4;
-  static constexpr int WPB = (2 * FB + 4 * per_wave <= 60 * 1024)   ? 4
-                             : (2 * FB + 2 * per_wave <= 60 * 1024) ? 2
-                                                                    : 1;
+  static constexpr int WPB = (2 * FB + 4 * per_wave <= kLdsBlockCap)   ? 4
+                             : (2 * FB + 2 * per_wave <= kLdsBlockCap) ? 2
+                                                                       : 1;
 };
 
 constexpr int nbuf_of(int mode) {
