@@ -661,6 +661,8 @@ def main():
             extras["streaming_warm_start"] = streaming_c4(args.variant)
             extras["streaming_warm_start_recur"] = streaming_c4(args.variant, recur=True)
             extras["streaming_warm_start_grouped"] = streaming_c4(args.variant, grouped=True)
+            extras["streaming_warm_start_grouped_recur"] = streaming_c4(args.variant, recur=True,
+                                                                        grouped=True)
         extras["postprocess"] = postprocess(X3, k)
         extras["grouped_order"] = grouped_order(g.row_ptr, g.col_idx, X3, k, x0, args.variant,
                                                 g.labels)
