@@ -176,9 +176,9 @@ class Laplacian:
 
     def __init__(self, row_ptr, col_idx, vals=None, validate: bool = False,
                  reorder: bool = True, groups=None, stream=None):
-        """``groups``: optional int32[n] host array (e.g. cluster labels of an
-        earlier solve; negative = none) that lays the row-processing order out
-        for the XCDs (``ofm_build_laplacian_grouped``)."""
+        """``groups``: optional int32[n] (a host array or a tensor, e.g. the
+        cluster labels of an earlier solve; negative = none) that lays the
+        row-processing order out for the XCDs (``ofm_build_laplacian_grouped``)."""
         torch = _torch()
         lib = load()
         self._lib = lib
@@ -194,6 +194,8 @@ class Laplacian:
                                          _stream(stream), ctypes.byref(h))
             _check(st, "ofm_build_laplacian")
         else:
+            if hasattr(groups, "detach"):  # a torch tensor, possibly on the device
+                groups = groups.detach().cpu().numpy()
             gr = np.ascontiguousarray(np.asarray(groups), dtype=np.int32)
             if gr.shape != (n,):
                 raise ValueError("groups must hold one entry per node")
