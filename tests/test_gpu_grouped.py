@@ -143,7 +143,8 @@ def test_grouped_weighted_validated_small(ofm):
     Z = torch.as_tensor(rng.standard_normal((g.n, 8))).cuda()
     plain = ofm.Laplacian(g.row_ptr, g.col_idx, vals=w, validate=True)
     ref = plain.apply(Z)
-    for gr in (g.labels, np.where(np.arange(g.n) < 40, 3, -1).astype(np.int32)):
+    for gr in (g.labels, np.where(np.arange(g.n) < 40, 3, -1).astype(np.int32),
+               torch.as_tensor(g.labels).cuda()):
         lap = ofm.Laplacian(g.row_ptr, g.col_idx, vals=w, validate=True, groups=gr)
         Y = lap.apply(Z)
         assert torch.equal(Y, ref)
