@@ -571,20 +571,22 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
   zero_gram<T, KP>(gB);
 
   // tiles of this wave: chunks of `span` consecutive tiles, chunk c0, c0 +
-  // cstride, ...; each wave takes every WPB-th tile of a chunk
-  int64_t c0 = (int64_t)brank * WPB, tend = a.ntiles, cstride = (int64_t)nblk * WPB;
-  int64_t span = WPB;
+  // cstride, ...; each wave takes every WPB-th tile of a chunk.  Tile indices
+  // fit in 32 bits (fewer than n / 16 + nnz / kHeavyDeg tiles); the wave index
+  // is made wave-uniform so that the loop lives in scalar registers.
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  int c0 = brank * WPB, tend = (int)a.ntiles, cstride = nblk * WPB, span = WPB;
   if (a.xcd) {
     // grouped order: workgroup b runs on XCD b % 8 and walks that XCD's slot
     // in chunks of xr * WPB tiles
     const int x = brank & 7;
-    span = (int64_t)WPB * a.xr;
-    c0 = a.xt[x] + (int64_t)(brank >> 3) * span;
+    span = WPB * a.xr;
+    c0 = a.xt[x] + (brank >> 3) * span;
     tend = a.xt[x + 1];
-    cstride = (int64_t)(nblk >> 3) * span;
+    cstride = (nblk >> 3) * span;
   }
   for (; c0 < tend; c0 += cstride)
-  for (int64_t t = c0 + wave, cend = c0 + span < tend ? c0 + span : tend; t < cend; t += WPB) {
+  for (int t = c0 + wv, cend = c0 + span < tend ? c0 + span : tend; t < cend; t += WPB) {
     const int tinfo = a.tiles[t];
     const int start = tinfo & 0x7fffffff;
     const bool heavy = tinfo < 0;
