@@ -193,6 +193,19 @@ ofm_status ofm_build_laplacian_grouped(int64_t n, int64_t nnz, const int32_t* ro
                                        unsigned flags, const int32_t* host_groups,
                                        hipStream_t stream, ofm_laplacian* out);
 
+/*
+ * The row-processing order that ofm_build_laplacian_grouped lays out, computed
+ * on the host alone (no device call): host_order (int32[n]) receives the rows
+ * in processing order, host_slot_start (int64[9]) the first position of each
+ * of the eight XCD slots and n.  host_row_ptr is the CSR row_ptr (int32[n+1]),
+ * host_groups as for ofm_build_laplacian_grouped.  For inspecting or reusing
+ * the order (e.g. to lay out other per-node data the same way).
+ * Errors: OFM_E_INVALID_ARG for null pointers, n <= 0 or a group id >= n;
+ * OFM_E_GRAPH for a row_ptr that does not start at 0 or decreases.
+ */
+ofm_status ofm_grouped_order(int64_t n, const int32_t* host_row_ptr, const int32_t* host_groups,
+                             int32_t* host_order, int64_t* host_slot_start);
+
 ofm_status ofm_laplacian_destroy(ofm_laplacian lap);
 
 /* Host copies of the basic graph quantities: n, nnz, ||A||_F^2, and (nullable

@@ -353,6 +353,24 @@ extern "C" ofm_status ofm_build_laplacian(int64_t n, int64_t nnz, const int32_t*
   return build_laplacian(n, nnz, row_ptr, col_idx, vals, flags, nullptr, stream, out);
 }
 
+extern "C" ofm_status ofm_grouped_order(int64_t n, const int32_t* host_row_ptr,
+                                        const int32_t* host_groups, int32_t* host_order,
+                                        int64_t* host_slot_start) {
+  if (n <= 0 || n >= (int64_t(1) << 31) || !host_row_ptr || !host_groups || !host_order ||
+      !host_slot_start)
+    return OFM_E_INVALID_ARG;
+  if (host_row_ptr[0] != 0) return OFM_E_GRAPH;
+  for (int64_t i = 0; i < n; ++i) {
+    if (host_row_ptr[i + 1] < host_row_ptr[i]) return OFM_E_GRAPH;
+    if ((int64_t)host_groups[i] >= n) return OFM_E_INVALID_ARG;
+  }
+  std::vector<int32_t> hrp(host_row_ptr, host_row_ptr + n + 1);
+  std::vector<int32_t> sched((size_t)n);
+  grouped_order(hrp, host_groups, n, sched, host_slot_start);
+  std::memcpy(host_order, sched.data(), (size_t)n * sizeof(int32_t));
+  return OFM_OK;
+}
+
 extern "C" ofm_status ofm_build_laplacian_grouped(int64_t n, int64_t nnz, const int32_t* row_ptr,
                                                   const int32_t* col_idx, const double* vals,
                                                   unsigned flags, const int32_t* host_groups,

@@ -85,6 +85,7 @@ _SIGS = {
     "ofm_build_laplacian": (_I, [_I64, _I64, _P, _P, _P, ctypes.c_uint, _P, ctypes.POINTER(_P)]),
     "ofm_build_laplacian_grouped": (_I, [_I64, _I64, _P, _P, _P, ctypes.c_uint, _P, _P,
                                          ctypes.POINTER(_P)]),
+    "ofm_grouped_order": (_I, [_I64, _P, _P, _P, _P]),
     "ofm_laplacian_destroy": (_I, [_P]),
     "ofm_laplacian_info": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                 ctypes.POINTER(_D), _P]),
@@ -443,6 +444,23 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def grouped_order(row_ptr, groups):
+    """Host-only: (order int32[n], slot_start int64[9]) of the XCD-grouped row
+    order that ``Laplacian(..., groups=groups)`` lays out."""
+    rp = np.ascontiguousarray(np.asarray(row_ptr), dtype=np.int32)
+    gr = np.ascontiguousarray(np.asarray(groups), dtype=np.int32)
+    n = rp.shape[0] - 1
+    if gr.shape != (n,):
+        raise ValueError("groups must hold one entry per node")
+    order = np.empty(n, dtype=np.int32)
+    slots = np.empty(9, dtype=np.int64)
+    _check(load().ofm_grouped_order(n, rp.ctypes.data_as(ctypes.c_void_p),
+                                    gr.ctypes.data_as(ctypes.c_void_p),
+                                    order.ctypes.data_as(ctypes.c_void_p),
+                                    slots.ctypes.data_as(ctypes.c_void_p)), "ofm_grouped_order")
+    return order, slots
 
 
 def scale(X, s, Y=None, stream=None):
