@@ -18,7 +18,7 @@ from __future__ import annotations
 
 import math
 import time
-from typing import List, Optional
+from typing import List
 
 import numpy as np
 

@@ -1,6 +1,5 @@
 """Checks of the seeded synthetic graph generators."""
 import numpy as np
-import pytest
 import scipy.sparse as sp
 from scipy.sparse.csgraph import connected_components
 
