@@ -52,6 +52,11 @@ Readings taken where the paper is silent or garbled
   falls back to the quadratic / linear; no real root gives a = 0.
 * Residual: relres = ||A U - U Lam||_F / ||U Lam||_F with (Lam, U) the Ritz
   pairs of A itself on span(X).
+* Iterating past convergence: Algorithm 2 runs a fixed t_max.  An optional
+  freeze (``freeze_eps > 0``) skips a step (every step size 0) whose direction
+  satisfies ||G||_F <= freeze_eps ||X||_F, so a converged X stays put.
+* A line search whose polynomial is not identically zero but has no real
+  root takes step 0 and is flagged (``no_root`` in the step info).
 
 Parity pins for every function live in tests/test_oracle_*.py.  Iterate
 values of long runs have no printed worked example in the paper: they are
@@ -401,10 +406,25 @@ def step_size(variant: int, lap: Laplacian, X, AX, V, G) -> Tuple[np.ndarray, np
     return np.full(k, a), co, np.array([nr])
 
 
-def _frozen(opts: Options, G, AX) -> bool:
+def _frozen(opts: Options, G, X) -> bool:
+    """Stopping once converged (a project reading: Algorithm 2 runs a fixed
+    t_max and says nothing about iterating past convergence).  With
+    freeze_eps > 0 the step is skipped (every step size 0) when the direction
+    is negligible against the iterate, ||G||_F <= freeze_eps ||X||_F; X then
+    stays at its fixed point instead of drifting along the neutral orbit that
+    rounding noise excites."""
     if opts.freeze_eps <= 0.0:
         return False
-    return float(np.linalg.norm(G)) <= opts.freeze_eps * float(np.linalg.norm(AX))
+    return float(np.linalg.norm(G)) <= opts.freeze_eps * float(np.linalg.norm(X))
+
+
+def no_root(coeffs, nroots) -> np.ndarray:
+    """Per cubic: the line search found no real root although the polynomial
+    is not identically zero (the step size is then 0).  A zero polynomial (a
+    zero search direction) is not such a case."""
+    co = np.asarray(coeffs, dtype=np.float64).reshape(4, -1)
+    nr = np.asarray(nroots).reshape(-1)
+    return (nr == 0) & np.any(co != 0.0, axis=0)
 
 
 def init(lap: Laplacian, X0: np.ndarray, opts: Options) -> Tuple[State, Dict]:
@@ -419,10 +439,12 @@ def init(lap: Laplacian, X0: np.ndarray, opts: Options) -> Tuple[State, Dict]:
         co = None
     else:
         alpha, co, _ = step_size(opts.variant, lap, X, AX, V, G)
-    if _frozen(opts, G, AX):
+    frozen = _frozen(opts, G, X)
+    if frozen:
         alpha = np.zeros(k)
     Xn = X + V * alpha[None, :]
-    return State(X=Xn, V_prev=V, G_prev=G, t=1), {"alpha": alpha, "coeffs": co, "G": G, "V": V}
+    return State(X=Xn, V_prev=V, G_prev=G, t=1), {"alpha": alpha, "coeffs": co, "G": G, "V": V,
+                                                  "frozen": frozen}
 
 
 def pr_beta(G: np.ndarray, G_prev: np.ndarray) -> np.ndarray:
@@ -451,11 +473,13 @@ def step(lap: Laplacian, state: State, opts: Options) -> Tuple[State, Dict]:
         beta = np.where(bad, 0.0, beta)
         V = -G + state.V_prev * beta[None, :]
     alpha, co, nr = step_size(opts.variant, lap, X, AX, V, G)
-    if _frozen(opts, G, AX):
+    frozen = _frozen(opts, G, X)
+    if frozen:
         alpha = np.zeros_like(alpha)
     Xn = X + V * alpha[None, :]
     return (State(X=Xn, V_prev=V, G_prev=G, t=state.t + 1),
-            {"alpha": alpha, "beta": beta, "coeffs": co, "nroots": nr, "G": G, "V": V, "AX": AX})
+            {"alpha": alpha, "beta": beta, "coeffs": co, "nroots": nr, "G": G, "V": V, "AX": AX,
+             "frozen": frozen, "no_root": bool(np.any(no_root(co, nr)))})
 
 
 def run(lap: Laplacian, X0: np.ndarray, iters: int, opts: Options, record=None):

@@ -157,3 +157,95 @@ def test_disjoint_cliques_perfect_recovery():
     truth = np.repeat(np.arange(c), m)
     _, a, nm = O.cluster(X, c, repeats=2, truth=truth)
     assert a == pytest.approx(1.0) and nm == pytest.approx(1.0)
+
+
+# ---------------------------------------------------------------------------
+# Freezing once converged (project reading of fixed-t_max Algorithm 2)
+# ---------------------------------------------------------------------------
+
+def _dense_A_from_csr(g):
+    # A = -I - D^{-1/2} S D^{-1/2} written out entry by entry from the CSR,
+    # independently of the oracle's Laplacian code
+    n = g.n
+    A = -np.eye(n)
+    d = np.diff(g.row_ptr).astype(np.float64)
+    for i in range(n):
+        for e in range(g.row_ptr[i], g.row_ptr[i + 1]):
+            j = g.col_idx[e]
+            A[i, j] -= 1.0 / np.sqrt(d[i] * d[j])
+    return A
+
+
+def _grad_f1_dense(A, X):
+    return 4.0 * (A @ X + X @ (X.T @ X))
+
+
+def test_freeze_at_theorem1_fixed_point(sbm1k):
+    # X* = U_k sqrt(2 - mu_k) is a fixed point of OFM-f1 (Theorem 1): its
+    # gradient vanishes to rounding, so a freeze threshold far above rounding
+    # keeps X* exactly, while a threshold of 0 (off) lets the step move it
+    g, x0, lap, mu, U = sbm1k
+    k = x0.shape[1]
+    A = _dense_A_from_csr(g)
+    Xs = U[:, :k] * np.sqrt(2.0 - mu[:k])[None, :]
+    G = _grad_f1_dense(A, Xs)
+    assert np.linalg.norm(G) < 1e-12 * np.linalg.norm(Xs)
+    st = O.State(X=Xs.copy(), V_prev=-G, G_prev=G, t=1)
+    nxt, info = O.step(lap, st, O.Options(variant=O.F1, freeze_eps=1e-9))
+    assert info["frozen"] and np.all(info["alpha"] == 0.0)
+    assert np.array_equal(nxt.X, Xs)
+    # away from the fixed point the same threshold does not freeze
+    Xp = Xs + 1e-3 * np.random.default_rng(5).standard_normal(Xs.shape)
+    st = O.State(X=Xp, V_prev=-_grad_f1_dense(A, Xp), G_prev=_grad_f1_dense(A, Xp), t=1)
+    nxt, info = O.step(lap, st, O.Options(variant=O.F1, freeze_eps=1e-9))
+    assert not info["frozen"] and not np.array_equal(nxt.X, Xp)
+
+
+@pytest.mark.parametrize("variant", [O.F1, O.F2])
+def test_freeze_decision_and_fixed_iterate(sbm1k, variant):
+    # a long run with the freeze on: every step's decision equals
+    # ||grad||_F <= eps ||X||_F evaluated with a dense A built from the CSR (for
+    # f2 the gradient 4AX - 2X X^T A X - 2AX X^T X), and once frozen X never
+    # changes again
+    g, x0, lap, mu, U = sbm1k
+    A = _dense_A_from_csr(g)
+    eps = 1e-7
+    opts = O.Options(variant=variant, freeze_eps=eps)
+    st, info = O.init(lap, x0, opts)
+    frozen_at = None
+    for t in range(1, 600):
+        X = st.X
+        AX = A @ X
+        if variant == O.F1:
+            Gd = _grad_f1_dense(A, X)
+        else:
+            Gd = 4.0 * AX - 2.0 * X @ (X.T @ AX) - 2.0 * AX @ (X.T @ X)
+        ratio = np.linalg.norm(Gd) / np.linalg.norm(X)
+        st, info = O.step(lap, st, opts)
+        if abs(ratio / eps - 1.0) > 1e-6:
+            assert info["frozen"] == (ratio <= eps), (t, ratio)
+        if info["frozen"]:
+            assert np.array_equal(st.X, X)
+            if frozen_at is None:
+                frozen_at = t
+        elif frozen_at is not None:
+            raise AssertionError(f"unfrozen at {t} after freezing at {frozen_at}")
+    assert frozen_at is not None and frozen_at < 600
+    assert O.relres(lap, st.X) < 1e-5
+
+
+def test_no_root_flag():
+    # a quadratic with a negative discriminant has no real root: step 0,
+    # flagged; the zero polynomial (zero direction) is not flagged; a cubic
+    # always has a real root
+    co = np.array([0.0, 1.0, 0.0, 1.0])          # x^2 + 1
+    a, nr = O.select_root(O.F1, co)
+    assert a == 0.0 and nr == 0
+    assert O.no_root(co, [nr]).tolist() == [True]
+    assert O.no_root(np.zeros(4), [0]).tolist() == [False]
+    a, nr = O.select_root(O.F1, np.array([1.0, 0.0, 1.0, 1.0]))  # x^3 + x + 1
+    assert nr == 1 and abs(a ** 3 + a + 1.0) < 1e-14
+    # per column for the triangular variants
+    co = np.stack([[1.0, 0.0, 1.0, 1.0], [0.0, 1.0, 0.0, 1.0], [0.0, 0.0, 0.0, 0.0]], axis=1)
+    nrs = [O.select_root(O.TRI_F1, co[:, i])[1] for i in range(3)]
+    assert O.no_root(co, nrs).tolist() == [False, True, False]

@@ -118,3 +118,38 @@ def test_weighted_degrees():
     np.testing.assert_allclose(lap.d, [2.0, 5.0, 3.0])
     L = O.dense_L(lap)
     np.testing.assert_allclose(L[0, 1], -2.0 / np.sqrt(2.0 * 5.0))
+
+
+def cycle_with_loops(n):
+    """C_n plus a self-loop at every node (the diagonal entry stored once)."""
+    rp, ci = cycle(n)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    rows = np.concatenate([rows, np.arange(n)])
+    cols = np.concatenate([ci, np.arange(n)])
+    order = np.lexsort((cols, rows))
+    rows, cols = rows[order], cols[order]
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, rows + 1, 1)
+    return np.cumsum(rp), cols
+
+
+@pytest.mark.parametrize("w", [1.0, 0.5, 3.0])
+@pytest.mark.parametrize("n", [6, 11])
+def test_self_loop_cycle_closed_forms(n, w):
+    # S = adjacency(C_n) + w I is (2 + w)-regular: D = (2 + w) I,
+    # A = -I - S / (2 + w), so ||A||_F^2 = n (1 + w/(2+w))^2 + 2n/(2+w)^2 and the
+    # spectrum of L is 1 - (w + 2 cos(2 pi j / n)) / (2 + w)
+    rp, ci = cycle_with_loops(n)
+    vals = np.where(ci == np.repeat(np.arange(n), np.diff(rp)), w, 1.0)
+    lap = O.laplacian(n, rp, ci, None if w == 1.0 else vals)
+    d = 2.0 + w
+    np.testing.assert_allclose(lap.d, d)
+    expect = n * (1.0 + w / d) ** 2 + 2.0 * n / d ** 2
+    np.testing.assert_allclose(O.norm_A_fro_sq(lap), expect, rtol=1e-14)
+    mus = np.sort(1.0 - (w + 2.0 * np.cos(2 * np.pi * np.arange(n) / n)) / d)
+    np.testing.assert_allclose(np.linalg.eigvalsh(O.dense_L(lap)), mus, atol=1e-13)
+    i = np.arange(n)
+    for j in range(n):
+        u = np.cos(2 * np.pi * j * i / n)
+        lam = -1.0 - (w + 2.0 * np.cos(2 * np.pi * j / n)) / d
+        np.testing.assert_allclose(O.apply_A(lap, u[:, None])[:, 0], lam * u, atol=1e-13)
