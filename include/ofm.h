@@ -27,8 +27,10 @@
  * - Every entry point returns an ofm_status and never throws.  Argument and
  *   shape errors are detected on the host before anything is enqueued.
  *   Numerical failures detected on the device (non-finite values, Cholesky
- *   failure in the residual) set a device status word that the next
- *   synchronizing call (ofm_solve, ofm_get_stats) returns.
+ *   failure in the residual, a line search without a real root) set a device
+ *   status word that the next synchronizing call (ofm_solve, ofm_get_stats)
+ *   returns; when several are set: OFM_E_NONFINITE, then OFM_E_NUMERIC, then
+ *   OFM_E_NO_ROOT.
  */
 #ifndef OFM_H
 #define OFM_H
@@ -52,7 +54,10 @@ typedef enum ofm_status {
   OFM_E_NUMERIC = -5,      /* X^T X not positive definite in the residual   */
   OFM_E_HIP = -6,          /* a HIP runtime call failed                      */
   OFM_E_NOMEM = -7,        /* device allocation failed                       */
-  OFM_E_UNSUPPORTED = -8   /* option combination not implemented             */
+  OFM_E_UNSUPPORTED = -8,  /* option combination not implemented             */
+  OFM_E_NO_ROOT = -9       /* a line-search cubic that is not identically
+                              zero had no real root (Section 3.2 gives no rule
+                              for it): that step took step size 0            */
 } ofm_status;
 
 /* The four methods (Introduction and Section 2):
@@ -118,6 +123,12 @@ typedef struct ofm_opts {
                        are bitwise the same.  2 is refused (OFM_E_UNSUPPORTED)
                        for OFM_FP32_BF16X and for blocks of 2 GB or more.
                        The batched solver always uses 1.                      */
+  double freeze_eps; /* > 0: a step whose direction is negligible against the
+                       iterate, ||G||_F <= freeze_eps ||X||_F (G = g(X^t) of
+                       the step, X^t the iterate entering it), takes step size
+                       0 in every column, so a converged X stays where it is
+                       instead of drifting with the rounding noise (Algorithm 2
+                       itself runs a fixed number of steps).  0 = off.        */
 } ofm_opts;
 
 typedef struct ofm_stats {
@@ -149,7 +160,10 @@ const char* ofm_version(void);
  *   row_ptr     int32[n+1], row_ptr[0] = 0, row_ptr[n] = nnz, non-decreasing
  *   col_idx     int32[nnz], entries in [0, n)
  *   vals        nullable: NULL means S_ij = 1 for every stored entry;
- *               otherwise FP64[nnz] weights (must be symmetric)
+ *               otherwise nnz weights S_ij >= 0 (must be symmetric) of type
+ *               vals_dtype; self-loops (i == j) count once in D_ii
+ *   vals_dtype  OFM_FP64 (double) or OFM_FP32 (float, widened exactly to
+ *               FP64 before any arithmetic); ignored when vals is NULL
  *   flags       OFM_LAP_VALIDATE, OFM_LAP_NO_REORDER
  * Computes D_ii = sum_j S_ij, D^{-1/2}, ||A||_F^2 and the normalized edge
  * weights w_ij = D_ii^{-1/2} S_ij D_jj^{-1/2} (FP64 and FP32 copies, laid out
@@ -159,7 +173,7 @@ const char* ofm_version(void);
  * degree or (when validating) an asymmetric pattern.
  */
 ofm_status ofm_build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr,
-                               const int32_t* col_idx, const double* vals,
+                               const int32_t* col_idx, const void* vals, int vals_dtype,
                                unsigned flags, hipStream_t stream, ofm_laplacian* out);
 
 /*
@@ -189,7 +203,7 @@ ofm_status ofm_build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr,
  * group id >= n, or OFM_LAP_NO_REORDER in flags.
  */
 ofm_status ofm_build_laplacian_grouped(int64_t n, int64_t nnz, const int32_t* row_ptr,
-                                       const int32_t* col_idx, const double* vals,
+                                       const int32_t* col_idx, const void* vals, int vals_dtype,
                                        unsigned flags, const int32_t* host_groups,
                                        hipStream_t stream, ofm_laplacian* out);
 
@@ -306,6 +320,20 @@ ofm_status ofm_get_step_info(ofm_workspace ws, double* host_alpha, double* host_
                              double* host_coef, int32_t* host_nroots, hipStream_t stream);
 
 /*
+ * The root rules of the exact line search (Section 3.2; the device code every
+ * step runs) applied to caller-given cubics, for checking them in isolation:
+ * coef FP64[4*count], coef[4*i + j] = a_{3-j} of cubic i, a3 x^3 + a2 x^2 +
+ * a1 x + a0 (device).  alpha FP64[count] receives the chosen real root (0 when
+ * there is none), nroots int32[count] the number of distinct real roots found
+ * (0 to 3).  variant selects the rule among three real roots: the least line
+ * objective a3 x^4/4 + a2 x^3/3 + a1 x^2/2 + a0 x (OFM_F1, OFM_F2) or the
+ * smallest |x| (OFM_TRI_F1, OFM_TRI_F2).  Asynchronous.
+ * Errors: OFM_E_INVALID_ARG for a bad variant, count < 0 or a null pointer.
+ */
+ofm_status ofm_select_roots(int variant, int64_t count, const double* coef, double* alpha,
+                            int32_t* nroots, hipStream_t stream);
+
+/*
  * Batched solves of many independent graphs (any sizes, widths k in
  * {4, 8, 16, 32, 64}): Algorithm 2 runs on all of them in lockstep, each pass
  * being one launch per width group over every graph of the group; a graph
@@ -313,7 +341,9 @@ ofm_status ofm_get_step_info(ofm_workspace ws, double* host_alpha, double* host_
  * host_laps[count], host_ks[count]: the graphs and their widths (the handles
  * must outlive the batch); host_opts: shared options (precision OFM_FP32 or
  * OFM_FP32_BF16X; variant, max_iter, check_every, tol, restart, first_step,
- * recur; graph applies to the FP64 finishing solves only).
+ * recur, freeze_eps; graph = 1 runs the lockstep loop of ofm_batch_solve, after
+ * the schedule has been chosen, as replays of one HIP graph per check_every
+ * updates of every graph, and the FP64 finishing solves as graph replays too).
  * Allocates the per-graph state.  The block schedule (blocks per graph, each
  * graph's blocks on one XCD) is chosen among a few candidates by timing the
  * first iterations of every solve.
@@ -332,16 +362,44 @@ ofm_status ofm_batch_destroy(ofm_batch b);
  * host thread.  Synchronizing. */
 ofm_status ofm_batch_solve(ofm_batch b, void* const* host_X, hipStream_t stream,
                            ofm_stats* host_stats);
+/*
+ * The lockstep iteration one step at a time (checkpoint / resume, and
+ * step-by-step comparison): ofm_batch_init runs the set-up step of Algorithm 2
+ * on every graph (host_X as for ofm_batch_solve; the blocks must stay the same
+ * until the next ofm_batch_init) and marks every graph active; ofm_batch_step
+ * runs one loop iteration of Algorithm 2 on every active graph, with the
+ * residual every check_every updates (a graph whose residual meets tol stops
+ * iterating, as in the solve; no FP64 finishing), on the schedule chosen by the
+ * last solve (the first candidate before any).  ofm_batch_init synchronizes the
+ * batch's streams; ofm_batch_step only enqueues.
+ */
+ofm_status ofm_batch_init(ofm_batch b, void* const* host_X, hipStream_t stream);
+ofm_status ofm_batch_step(ofm_batch b, hipStream_t stream);
+/* Graph i's CG state V^{t-1}, G^{t-1} (N_i x k_i FP32 each) copied into
+ * caller buffers, after ofm_batch_init / ofm_batch_solve. */
+ofm_status ofm_batch_get_state(ofm_batch b, int i, void* V_prev, void* G_prev,
+                               hipStream_t stream);
+/* Scalars of graph i's last lockstep step, as ofm_get_step_info (synchronizing;
+ * any host pointer may be NULL). */
+ofm_status ofm_batch_get_step_info(ofm_batch b, int i, double* host_alpha, double* host_beta,
+                                   double* host_coef, int32_t* host_nroots, hipStream_t stream);
 /* Schedule chosen by the last solve: host_tpw = tiles per wavefront target
  * (blocks per graph ~ tiles / (waves per block * tpw)), host_ms[4] = measured
  * time per iteration of each candidate (0 if untried), host_escalated = number
  * of graphs finished in FP64.  Any pointer may be NULL. */
 ofm_status ofm_batch_schedule(ofm_batch b, int* host_tpw, double* host_ms,
                               int* host_escalated);
+/* Fix the tiles-per-wavefront target of the block schedule (one of the
+ * candidates 2, 4, 8, 16) for the following solves and steps instead of timing
+ * the candidates at the start of every solve; 0 returns to timing them.
+ * Errors: OFM_E_INVALID_ARG for another value. */
+ofm_status ofm_batch_set_schedule(ofm_batch b, int tpw);
 /* Host wall time of the last solve's two stages: the lockstep FP32 loop
  * (host_loop_ms) and the FP64 finishing solves (host_finish_ms), which run
- * concurrently on up to 4 streams of the batch.  Either pointer may be NULL. */
-ofm_status ofm_batch_phases(ofm_batch b, double* host_loop_ms, double* host_finish_ms);
+ * concurrently on up to 4 streams of the batch; host_replays: graph replays
+ * of the lockstep loop (0 without opts.graph).  Any pointer may be NULL. */
+ofm_status ofm_batch_phases(ofm_batch b, double* host_loop_ms, double* host_finish_ms,
+                            int64_t* host_replays);
 
 /*
  * Host copy (synchronizing) of one k x k FP64 product held by the workspace,

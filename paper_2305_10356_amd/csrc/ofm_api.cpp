@@ -6,6 +6,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <numeric>
 #include <thread>
@@ -198,12 +199,21 @@ int pass_kind(int mode) {
 
 }  // namespace
 
+// device status word -> ofm_status, the most severe first
+static int device_status(int st) {
+  return (st & kStNonfinite) ? OFM_E_NONFINITE
+         : (st & kStCholesky) ? OFM_E_NUMERIC
+         : (st & kStNoRoot)   ? OFM_E_NO_ROOT
+                              : OFM_OK;
+}
+
 static const char* kStatusNames[] = {"OFM_OK",          "OFM_E_INVALID_ARG", "OFM_E_SHAPE",
                                      "OFM_E_GRAPH",     "OFM_E_NONFINITE",   "OFM_E_NUMERIC",
-                                     "OFM_E_HIP",       "OFM_E_NOMEM",       "OFM_E_UNSUPPORTED"};
+                                     "OFM_E_HIP",       "OFM_E_NOMEM",       "OFM_E_UNSUPPORTED",
+                                     "OFM_E_NO_ROOT"};
 
 extern "C" const char* ofm_status_string(int status) {
-  if (status > 0 || status < -8) return "OFM_E_UNKNOWN";
+  if (status > 0 || status < -9) return "OFM_E_UNKNOWN";
   return kStatusNames[-status];
 }
 
@@ -343,14 +353,15 @@ static void grouped_order(const std::vector<int32_t>& hrp, const int32_t* grp, i
 }
 
 static ofm_status build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr,
-                                  const int32_t* col_idx, const double* vals, unsigned flags,
-                                  const int32_t* groups, hipStream_t stream, ofm_laplacian* out);
+                                  const int32_t* col_idx, const void* vals, int vals_dtype,
+                                  unsigned flags, const int32_t* groups, hipStream_t stream,
+                                  ofm_laplacian* out);
 
 extern "C" ofm_status ofm_build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr,
-                                          const int32_t* col_idx, const double* vals,
-                                          unsigned flags, hipStream_t stream,
+                                          const int32_t* col_idx, const void* vals,
+                                          int vals_dtype, unsigned flags, hipStream_t stream,
                                           ofm_laplacian* out) {
-  return build_laplacian(n, nnz, row_ptr, col_idx, vals, flags, nullptr, stream, out);
+  return build_laplacian(n, nnz, row_ptr, col_idx, vals, vals_dtype, flags, nullptr, stream, out);
 }
 
 extern "C" ofm_status ofm_grouped_order(int64_t n, const int32_t* host_row_ptr,
@@ -372,25 +383,44 @@ extern "C" ofm_status ofm_grouped_order(int64_t n, const int32_t* host_row_ptr,
 }
 
 extern "C" ofm_status ofm_build_laplacian_grouped(int64_t n, int64_t nnz, const int32_t* row_ptr,
-                                                  const int32_t* col_idx, const double* vals,
-                                                  unsigned flags, const int32_t* host_groups,
+                                                  const int32_t* col_idx, const void* vals,
+                                                  int vals_dtype, unsigned flags,
+                                                  const int32_t* host_groups,
                                                   hipStream_t stream, ofm_laplacian* out) {
   if (!out) return OFM_E_INVALID_ARG;
   *out = nullptr;
   if (!host_groups || (flags & OFM_LAP_NO_REORDER) || n <= 0) return OFM_E_INVALID_ARG;
   for (int64_t i = 0; i < n; ++i)
     if ((int64_t)host_groups[i] >= n) return OFM_E_INVALID_ARG;
-  return build_laplacian(n, nnz, row_ptr, col_idx, vals, flags, host_groups, stream, out);
+  return build_laplacian(n, nnz, row_ptr, col_idx, vals, vals_dtype, flags, host_groups, stream,
+                         out);
 }
 
 static ofm_status build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr,
-                                  const int32_t* col_idx, const double* vals, unsigned flags,
-                                  const int32_t* groups, hipStream_t stream, ofm_laplacian* out) {
+                                  const int32_t* col_idx, const void* vals_in, int vals_dtype,
+                                  unsigned flags, const int32_t* groups, hipStream_t stream,
+                                  ofm_laplacian* out) {
   if (!out) return OFM_E_INVALID_ARG;
   *out = nullptr;
   if (n <= 0 || nnz < 0 || !row_ptr || (nnz > 0 && !col_idx)) return OFM_E_INVALID_ARG;
   if (n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 31)) return OFM_E_SHAPE;
   if (flags & ~(OFM_LAP_VALIDATE | OFM_LAP_NO_REORDER)) return OFM_E_INVALID_ARG;
+  if (vals_in && vals_dtype != OFM_FP64 && vals_dtype != OFM_FP32) return OFM_E_INVALID_ARG;
+  // FP32 weights are widened (exactly) to an FP64 copy that lives for the call
+  double* vals64 = nullptr;
+  if (vals_in && vals_dtype == OFM_FP32 && nnz > 0) {
+    ofm_status ast = dev_alloc(&vals64, nnz);
+    if (ast != OFM_OK) return ast;
+    if (launch_convert(nnz, 1, vals_in, vals64, stream) != hipSuccess) {
+      dev_free(vals64);
+      return OFM_E_HIP;
+    }
+  }
+  const double* vals = vals64 ? vals64 : static_cast<const double*>(vals_in);
+  struct Drop {
+    double*& p;
+    ~Drop() { dev_free(p); }
+  } drop_vals{vals64};
   auto* L = new ofm_laplacian_s();
   LaplacianDev& g = L->g;
   g.n = n;
@@ -727,6 +757,7 @@ extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_o
   if (o.graph != 0 && o.graph != 1) return OFM_E_INVALID_ARG;
   if (o.recur != 0 && o.recur != 1) return OFM_E_INVALID_ARG;
   if (o.gather < 0 || o.gather > 2) return OFM_E_INVALID_ARG;
+  if (!(o.freeze_eps >= 0.0) || !std::isfinite(o.freeze_eps)) return OFM_E_INVALID_ARG;
   const int prec = o.precision == OFM_FP64 ? OFM_FP64 : OFM_FP32;
   if (!supported_k(k, prec)) return prec == OFM_FP64 && k == 64 ? OFM_E_UNSUPPORTED : OFM_E_SHAPE;
   if (k > lap->g.n) return OFM_E_SHAPE;
@@ -984,7 +1015,8 @@ static ofm_status search_and_update(ofm_workspace ws, void* X, const void* Vp, b
   const bool adv_h = is_f2(ws->opts.variant) && !ws->opts.recur;
   HIPCHK(timed(ws, OFM_PASS_LINESEARCH, s, [&] {
     return launch_linesearch(ws->k, ws->opts.variant, first && ws->opts.first_step == 1,
-                             ws->opts.alpha0, adv_h ? 1 : 0, ws->sc, ws->status, ws->frozen, s);
+                             ws->opts.alpha0, adv_h ? 1 : 0, ws->sc, ws->status, ws->frozen,
+                             ws->opts.freeze_eps, s);
   }));
   ws->h_valid = adv_h;
   if (ws->opts.recur) {
@@ -1055,7 +1087,7 @@ static ofm_status read_stats(ofm_workspace ws, hipStream_t stream, ofm_stats* o)
   o->relres = ws->last_check >= 0 ? rv[0] : -1.0;
   o->objective = rv[1];
   o->relres_iter = ws->last_check;
-  o->status = (st & kStNonfinite) ? OFM_E_NONFINITE : (st & kStCholesky) ? OFM_E_NUMERIC : OFM_OK;
+  o->status = device_status(st);
   o->converged = (ws->last_check >= 0 && ws->opts.tol > 0.0 && rv[0] <= ws->opts.tol) ? 1 : 0;
   o->gather = ws->hc ? 2 : 1;
   o->reserved = 0;
@@ -1394,6 +1426,16 @@ extern "C" ofm_status ofm_kmeans(int64_t n, int dim, int n_clusters, const float
   return OFM_OK;
 }
 
+extern "C" ofm_status ofm_select_roots(int variant, int64_t count, const double* coef,
+                                       double* alpha, int32_t* nroots, hipStream_t stream) {
+  if (variant < 0 || variant > 3 || count < 0) return OFM_E_INVALID_ARG;
+  if (count == 0) return OFM_OK;
+  if (!coef || !alpha || !nroots) return OFM_E_INVALID_ARG;
+  const int tri = (variant == OFM_TRI_F1 || variant == OFM_TRI_F2) ? 1 : 0;
+  HIPCHK(launch_select_roots(tri, count, coef, alpha, nroots, stream));
+  return OFM_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Batched solves
 // ---------------------------------------------------------------------------
@@ -1416,6 +1458,7 @@ struct BatchGroup {
   int* status = nullptr;                // [n]
   double* hist = nullptr;               // [n][kBatchHist]
   int* stalled = nullptr;               // [n]
+  int64_t* tcount = nullptr;            // step counter of the group (device)
   double* sc = nullptr;                 // [n][SC total]
   double* partials = nullptr;
   double* lvl2 = nullptr;               // [n][workers / kFinChunk][nvmax]
@@ -1435,16 +1478,34 @@ struct ofm_batch_s {
   std::vector<int> ks;
   std::vector<BatchGroup> groups;
   int chosen = 0;
+  int fixed = -1;          // candidate set by ofm_batch_set_schedule (-1: timed per solve)
   double cand_ms[kBatchCand] = {};
   int escalated = 0;
   double loop_ms = 0.0;    // host time of the lockstep loop of the last solve
   double finish_ms = 0.0;  // host time of its FP64 finishing stage
   hipEvent_t start = nullptr;
   hipStream_t finish_streams[kFinishThreads] = {};
+  // step state of the lockstep iteration (ofm_batch_init / ofm_batch_step)
+  bool started = false;
+  int cur = 0;             // ping-pong slot of the next direction
+  int64_t t = 0;           // updates done
+  int64_t last_check = -1;
+  // check_every updates of every group captured as one HIP graph, per parity
+  // of the ping-pong slot at the chunk's start, for the tiles-per-wave
+  // candidate chunk_cand
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t fork = nullptr;
+  hipGraphExec_t chunk[2] = {nullptr, nullptr};
+  int chunk_cand = -1;
+  int64_t replays = 0;     // chunks replayed by the last solve
 };
 
 static void free_batch(ofm_batch b) {
   if (!b) return;
+  for (auto& e : b->chunk)
+    if (e) (void)hipGraphExecDestroy(e);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->fork) (void)hipEventDestroy(b->fork);
   for (auto s : b->finish_streams)
     if (s) (void)hipStreamDestroy(s);
   for (auto& g : b->groups) {
@@ -1456,6 +1517,7 @@ static void free_batch(ofm_batch b) {
     dev_free(g.status);
     dev_free(g.hist);
     dev_free(g.stalled);
+    dev_free(g.tcount);
     dev_free(g.sc);
     dev_free(g.partials);
     dev_free(g.lvl2);
@@ -1503,7 +1565,10 @@ extern "C" ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps
   if (o.max_iter < 1 || o.check_every < 1 || !(o.tol >= 0.0)) return OFM_E_INVALID_ARG;
   if (o.first_step != 0 && o.first_step != 1) return OFM_E_INVALID_ARG;
   if ((o.restart | o.graph | o.recur) & ~1) return OFM_E_INVALID_ARG;
+  static_assert(offsetof(ofm_opts, freeze_eps) == 56 && sizeof(ofm_opts) == 64,
+                "ofm_opts layout is part of the ABI");
   if (o.gather < 0 || o.gather > 2) return OFM_E_INVALID_ARG;
+  if (!(o.freeze_eps >= 0.0) || !std::isfinite(o.freeze_eps)) return OFM_E_INVALID_ARG;
   for (int i = 0; i < count; ++i) {
     if (!host_laps[i]) return OFM_E_INVALID_ARG;
     if (!supported_k(host_ks[i], OFM_FP32) || host_ks[i] > host_laps[i]->g.n) return OFM_E_SHAPE;
@@ -1559,6 +1624,7 @@ extern "C" ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps
     if ((st = dev_alloc(&g.status, n)) != OFM_OK) return fail(st);
     if ((st = dev_alloc(&g.hist, (size_t)n * kBatchHist)) != OFM_OK) return fail(st);
     if ((st = dev_alloc(&g.stalled, n)) != OFM_OK) return fail(st);
+    if ((st = dev_alloc(&g.tcount, 1)) != OFM_OK) return fail(st);
     if ((st = dev_alloc(&g.sc, (size_t)n * sct)) != OFM_OK) return fail(st);
     if ((st = dev_alloc(&g.partials, part_total)) != OFM_OK) return fail(st);
     const size_t lvl2_per = (size_t)((kBatchWorkers + kFinChunk - 1) / kFinChunk) * nvmax;
@@ -1627,10 +1693,27 @@ extern "C" ofm_status ofm_batch_schedule(ofm_batch b, int* host_tpw, double* hos
   return OFM_OK;
 }
 
-extern "C" ofm_status ofm_batch_phases(ofm_batch b, double* host_loop_ms, double* host_finish_ms) {
+extern "C" ofm_status ofm_batch_set_schedule(ofm_batch b, int tpw) {
+  if (!b) return OFM_E_INVALID_ARG;
+  if (tpw == 0) {
+    b->fixed = -1;
+    return OFM_OK;
+  }
+  for (int c = 0; c < kBatchCand; ++c)
+    if (kBatchTpw[c] == tpw) {
+      b->fixed = c;
+      b->chosen = c;
+      return OFM_OK;
+    }
+  return OFM_E_INVALID_ARG;
+}
+
+extern "C" ofm_status ofm_batch_phases(ofm_batch b, double* host_loop_ms, double* host_finish_ms,
+                                       int64_t* host_replays) {
   if (!b) return OFM_E_INVALID_ARG;
   if (host_loop_ms) *host_loop_ms = b->loop_ms;
   if (host_finish_ms) *host_finish_ms = b->finish_ms;
+  if (host_replays) *host_replays = b->replays;
   return OFM_OK;
 }
 
@@ -1683,10 +1766,12 @@ static ofm_status batch_iteration(ofm_batch B, BatchGroup& g, int cur, int64_t t
   base.cur = cur;
   base.bf16 = o.precision == OFM_FP32_BF16X;
   base.tol = o.tol;
+  base.freeze_eps = o.freeze_eps;
   base.t = t;
   base.graphs = g.dgraphs;
   base.xlist = g.dxlist;
   base.xoff = g.dxoff;
+  base.tcount = g.tcount;
   base.workers = kBatchWorkers;
   base.tpw = kBatchTpw[cand];
   base.check_every = o.check_every;
@@ -1721,52 +1806,239 @@ static ofm_status batch_iteration(ofm_batch B, BatchGroup& g, int cur, int64_t t
   return OFM_OK;
 }
 
+// the group streams wait for the work enqueued so far on `stream`
+static ofm_status batch_fork(ofm_batch B, hipStream_t stream) {
+  HIPCHK(hipEventRecord(B->start, stream));
+  for (auto& g : B->groups) HIPCHK(hipStreamWaitEvent(g.stream, B->start, 0));
+  return OFM_OK;
+}
+
+// `stream` waits for the work enqueued so far on the group streams
+static ofm_status batch_join(ofm_batch B, hipStream_t stream) {
+  for (auto& g : B->groups) {
+    HIPCHK(hipEventRecord(g.ev, g.stream));
+    HIPCHK(hipStreamWaitEvent(stream, g.ev, 0));
+  }
+  return OFM_OK;
+}
+
+// Per-graph state reset and the set-up step of Algorithm 2 on every graph
+// (on the group streams, after the work already on `stream`).
+static ofm_status batch_start(ofm_batch B, void* const* host_X, hipStream_t stream) {
+  for (int i = 0; i < B->count; ++i)
+    if (!host_X[i]) return OFM_E_INVALID_ARG;
+  OFMCHK(batch_fork(B, stream));
+  for (auto& g : B->groups) {
+    const int n = (int)g.idx.size();
+    for (int m = 0; m < n; ++m) g.hg[m].X = host_X[g.idx[m]];
+    std::vector<int> ones(n, 1);
+    std::vector<int64_t> minus(n, -1);
+    const int64_t zero = 0;
+    HIPCHK(hipMemcpyAsync(g.dgraphs, g.hg.data(), n * sizeof(BatchGraph), hipMemcpyHostToDevice,
+                          g.stream));
+    HIPCHK(hipMemcpyAsync(g.active, ones.data(), n * sizeof(int), hipMemcpyHostToDevice, g.stream));
+    HIPCHK(hipMemcpyAsync(g.done, minus.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, g.stream));
+    HIPCHK(hipMemcpyAsync(g.tcount, &zero, sizeof(int64_t), hipMemcpyHostToDevice, g.stream));
+    HIPCHK(hipMemsetAsync(g.status, 0, n * sizeof(int), g.stream));
+    HIPCHK(hipMemsetAsync(g.stalled, 0, n * sizeof(int), g.stream));
+    HIPCHK(hipMemsetAsync(g.hist, 0, (size_t)n * kBatchHist * sizeof(double), g.stream));
+    HIPCHK(hipStreamSynchronize(g.stream));  // the host vectors above go out of scope
+  }
+  B->cur = 0;
+  B->t = 0;
+  B->last_check = -1;
+  for (auto& g : B->groups) OFMCHK(batch_iteration(B, g, B->cur, B->t, true, false, B->chosen));
+  B->cur ^= 1;
+  B->t = 1;
+  B->started = true;
+  return OFM_OK;
+}
+
+// one loop iteration of every group with schedule candidate cand (eager, on
+// the group streams)
+static ofm_status batch_step_groups(ofm_batch B, int cand) {
+  const bool check = (B->t % B->opts.check_every) == 0;
+  for (auto& g : B->groups) OFMCHK(batch_iteration(B, g, B->cur, B->t, false, check, cand));
+  if (check) B->last_check = B->t;
+  B->cur ^= 1;
+  B->t += 1;
+  return OFM_OK;
+}
+
+// The check_every updates that start at B->t (one past a multiple of
+// check_every; the last of them evaluates the residual) of every group,
+// captured into one HIP graph: forked from a capture stream onto the group
+// streams and joined back.  The host step state is rewound after the capture.
+// Kernels read the step index from the groups' device counters, so one graph
+// serves every chunk with the same parity of the ping-pong slot.
+static ofm_status batch_capture(ofm_batch B, int cand, hipGraphExec_t* out) {
+  if (!B->cap_stream)
+    HIPCHK(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking));
+  if (!B->fork) HIPCHK(hipEventCreateWithFlags(&B->fork, hipEventDisableTiming));
+  const int64_t t0 = B->t, lc0 = B->last_check;
+  const int cur0 = B->cur;
+  hipGraph_t graph = nullptr;
+  ofm_status st = OFM_OK;
+  if (hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return OFM_E_HIP;
+  if (hipEventRecord(B->fork, B->cap_stream) != hipSuccess) st = OFM_E_HIP;
+  for (auto& g : B->groups)
+    if (st == OFM_OK && hipStreamWaitEvent(g.stream, B->fork, 0) != hipSuccess) st = OFM_E_HIP;
+  for (int i = 0; i < B->opts.check_every && st == OFM_OK; ++i) st = batch_step_groups(B, cand);
+  for (auto& g : B->groups) {
+    if (st == OFM_OK && hipEventRecord(g.ev, g.stream) != hipSuccess) st = OFM_E_HIP;
+    if (st == OFM_OK && hipStreamWaitEvent(B->cap_stream, g.ev, 0) != hipSuccess) st = OFM_E_HIP;
+  }
+  if (hipStreamEndCapture(B->cap_stream, &graph) != hipSuccess && st == OFM_OK) st = OFM_E_HIP;
+  B->t = t0;
+  B->cur = cur0;
+  B->last_check = lc0;
+  if (st == OFM_OK && hipGraphInstantiate(out, graph, nullptr, nullptr, 0) != hipSuccess)
+    st = OFM_E_HIP;
+  if (graph) (void)hipGraphDestroy(graph);
+  return st;
+}
+
+// replay one chunk on `stream` (captured on first use)
+static ofm_status batch_run_chunk(ofm_batch B, int cand, hipStream_t stream) {
+  if (B->chunk_cand != cand) {
+    for (auto& e : B->chunk) {
+      if (e) HIPCHK(hipGraphExecDestroy(e));
+      e = nullptr;
+    }
+    B->chunk_cand = cand;
+  }
+  hipGraphExec_t& e = B->chunk[B->cur];
+  if (!e) OFMCHK(batch_capture(B, cand, &e));
+  HIPCHK(hipGraphLaunch(e, stream));
+  const int ce = B->opts.check_every;
+  B->last_check = ((B->t + ce - 1) / ce) * ce;
+  B->t += ce;
+  B->cur ^= (ce & 1);
+  ++B->replays;
+  return OFM_OK;
+}
+
+// 1 when any graph of the batch still iterates (synchronizing on `stream`,
+// which must already be ordered after the work that set the flags)
+static ofm_status batch_any_active(ofm_batch B, hipStream_t stream, int* any) {
+  *any = 0;
+  for (auto& g : B->groups) {
+    std::vector<int> act(g.idx.size());
+    HIPCHK(hipMemcpyAsync(act.data(), g.active, act.size() * sizeof(int), hipMemcpyDeviceToHost,
+                          stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    for (int a : act) *any |= a;
+  }
+  return OFM_OK;
+}
+
+static bool batch_locate(ofm_batch B, int i, BatchGroup** g, int* m) {
+  for (auto& gr : B->groups)
+    for (size_t j = 0; j < gr.idx.size(); ++j)
+      if (gr.idx[j] == i) {
+        *g = &gr;
+        *m = (int)j;
+        return true;
+      }
+  return false;
+}
+
+extern "C" ofm_status ofm_batch_init(ofm_batch B, void* const* host_X, hipStream_t stream) {
+  if (!B || !host_X) return OFM_E_INVALID_ARG;
+  OFMCHK(batch_start(B, host_X, stream));
+  return batch_join(B, stream);
+}
+
+extern "C" ofm_status ofm_batch_step(ofm_batch B, hipStream_t stream) {
+  if (!B) return OFM_E_INVALID_ARG;
+  if (!B->started) return OFM_E_INVALID_ARG;
+  OFMCHK(batch_fork(B, stream));
+  OFMCHK(batch_step_groups(B, B->chosen));
+  return batch_join(B, stream);
+}
+
+extern "C" ofm_status ofm_batch_get_state(ofm_batch B, int i, void* V_prev, void* G_prev,
+                                          hipStream_t stream) {
+  if (!B || !V_prev || !G_prev || i < 0 || i >= B->count) return OFM_E_INVALID_ARG;
+  if (!B->started) return OFM_E_INVALID_ARG;
+  BatchGroup* g = nullptr;
+  int m = 0;
+  if (!batch_locate(B, i, &g, &m)) return OFM_E_INVALID_ARG;
+  const int prev = B->cur ^ 1;
+  const size_t blk = (size_t)g->hg[m].n * g->k * 4;
+  HIPCHK(hipMemcpyAsync(V_prev, g->hg[m].V[prev], blk, hipMemcpyDeviceToDevice, stream));
+  HIPCHK(hipMemcpyAsync(G_prev, g->hg[m].G[prev], blk, hipMemcpyDeviceToDevice, stream));
+  return OFM_OK;
+}
+
+extern "C" ofm_status ofm_batch_get_step_info(ofm_batch B, int i, double* host_alpha,
+                                              double* host_beta, double* host_coef,
+                                              int32_t* host_nroots, hipStream_t stream) {
+  if (!B || i < 0 || i >= B->count) return OFM_E_INVALID_ARG;
+  BatchGroup* g = nullptr;
+  int m = 0;
+  if (!batch_locate(B, i, &g, &m)) return OFM_E_INVALID_ARG;
+  const int k = g->k;
+  const SCOff so = sc_off(k);
+  std::vector<double> sc(sc_total(k));
+  HIPCHK(hipMemcpyAsync(sc.data(), g->hg[m].sc, sc.size() * sizeof(double), hipMemcpyDeviceToHost,
+                        stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  for (int c = 0; c < k; ++c) {
+    if (host_alpha) host_alpha[c] = sc[so.ALPHA + c];
+    if (host_beta) host_beta[c] = sc[so.BETA + c];
+    if (host_nroots) host_nroots[c] = (int32_t)sc[so.NROOT + c];
+  }
+  if (host_coef)
+    for (int c = 0; c < 4 * k; ++c) host_coef[c] = sc[so.COEF + c];
+  return OFM_OK;
+}
+
 extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStream_t stream,
                                       ofm_stats* host_stats) {
   if (!B || !host_X) return OFM_E_INVALID_ARG;
   for (int i = 0; i < B->count; ++i)
     if (!host_X[i]) return OFM_E_INVALID_ARG;
   const ofm_opts& o = B->opts;
+  const int ce = o.check_every;
   const auto t_solve = std::chrono::steady_clock::now();
-  HIPCHK(hipEventRecord(B->start, stream));
-  for (auto& g : B->groups) {
-    HIPCHK(hipStreamWaitEvent(g.stream, B->start, 0));
-    const int n = (int)g.idx.size();
-    for (int m = 0; m < n; ++m) g.hg[m].X = host_X[g.idx[m]];
-    HIPCHK(hipMemcpy(g.dgraphs, g.hg.data(), n * sizeof(BatchGraph), hipMemcpyHostToDevice));
-    std::vector<int> ones(n, 1);
-    std::vector<int64_t> minus(n, -1);
-    HIPCHK(hipMemcpyAsync(g.active, ones.data(), n * sizeof(int), hipMemcpyHostToDevice, g.stream));
-    HIPCHK(hipMemcpyAsync(g.done, minus.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, g.stream));
-    HIPCHK(hipMemsetAsync(g.status, 0, n * sizeof(int), g.stream));
-    HIPCHK(hipMemsetAsync(g.stalled, 0, n * sizeof(int), g.stream));
-    HIPCHK(hipMemsetAsync(g.hist, 0, (size_t)n * kBatchHist * sizeof(double), g.stream));
-    HIPCHK(hipStreamSynchronize(g.stream));
-  }
   // set-up step of Algorithm 2, then the loop; the first iterations try the
   // candidate schedules (two iterations each) and keep the fastest
-  int cur = 0;
-  int64_t t = 0;
-  for (auto& g : B->groups) OFMCHK(batch_iteration(B, g, cur, t, true, false, 0));
-  cur ^= 1;
-  t = 1;
+  B->chosen = B->fixed >= 0 ? B->fixed : 0;
+  B->replays = 0;
+  OFMCHK(batch_start(B, host_X, stream));
   for (int c = 0; c < kBatchCand; ++c) B->cand_ms[c] = 0.0;
-  int tuned = -1;
-  const int64_t tune_end = 1 + 2 * kBatchCand;
+  int tuned = B->fixed;
+  const int64_t tune_end = B->fixed >= 0 ? 0 : 1 + 2 * kBatchCand;
   double best = 1e300;
-  int64_t last_check = -1;
-  while (t < o.max_iter) {
-    const bool tuning = t < tune_end;
-    const int cand = tuning ? (int)((t - 1) / 2) : (tuned < 0 ? 0 : tuned);
-    const bool check = (t % o.check_every) == 0;
+  bool on_stream = false;  // the loop runs as graph replays on `stream`
+  while (B->t < o.max_iter) {
+    const bool tuning = B->t < tune_end;
+    const int cand = tuning ? (int)((B->t - 1) / 2) : (tuned < 0 ? 0 : tuned);
+    if (!tuning && o.graph && B->t % ce == 1 % ce && B->t + ce <= o.max_iter) {
+      if (!on_stream) {
+        OFMCHK(batch_join(B, stream));
+        on_stream = true;
+      }
+      OFMCHK(batch_run_chunk(B, cand, stream));
+      int any = 0;
+      OFMCHK(batch_any_active(B, stream, &any));
+      if (!any) break;
+      continue;
+    }
+    if (on_stream) {
+      OFMCHK(batch_fork(B, stream));
+      on_stream = false;
+    }
+    const bool check = (B->t % ce) == 0;
     auto t0 = std::chrono::steady_clock::now();
-    for (auto& g : B->groups) OFMCHK(batch_iteration(B, g, cur, t, false, check, cand));
-    if (check) last_check = t;
+    OFMCHK(batch_step_groups(B, cand));
     if (tuning) {
       for (auto& g : B->groups) HIPCHK(hipStreamSynchronize(g.stream));
       const double ms =
           std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-      if ((t - 1) % 2 == 1) {  // the second iteration of a candidate
+      if ((B->t - 2) % 2 == 1) {  // the second iteration of a candidate
         B->cand_ms[cand] = ms;
         if (ms < best) {
           best = ms;
@@ -1774,20 +2046,16 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
         }
       }
     }
-    cur ^= 1;
-    ++t;
     if (check) {
+      OFMCHK(batch_join(B, stream));
       int any = 0;
-      for (auto& g : B->groups) {
-        std::vector<int> act(g.idx.size());
-        HIPCHK(hipMemcpyAsync(act.data(), g.active, act.size() * sizeof(int),
-                              hipMemcpyDeviceToHost, g.stream));
-        HIPCHK(hipStreamSynchronize(g.stream));
-        for (int a : act) any |= a;
-      }
+      OFMCHK(batch_any_active(B, stream, &any));
       if (!any) break;
     }
   }
+  if (on_stream) OFMCHK(batch_fork(B, stream));
+  const int64_t t = B->t;
+  const int64_t last_check = B->last_check;
   B->chosen = tuned < 0 ? 0 : tuned;
   B->escalated = 0;
   // per-graph stats; a graph whose FP32 residual stopped decreasing before the
@@ -1819,8 +2087,7 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
       st.relres = last_check >= 0 ? s[so.RELRES] : -1.0;
       st.objective = s[so.FVAL];
       st.relres_iter = done[m] >= 0 ? done[m] : last_check;
-      st.status = (stt[m] & kStNonfinite) ? OFM_E_NONFINITE
-                  : (stt[m] & kStCholesky) ? OFM_E_NUMERIC : OFM_OK;
+      st.status = device_status(stt[m]);
       st.converged = (done[m] >= 0 && st.status == OFM_OK) ? 1 : 0;
       const bool escalate = !st.converged && st.status == OFM_OK && o.tol > 0.0 && g.k <= 32 &&
                             st.iters < o.max_iter;

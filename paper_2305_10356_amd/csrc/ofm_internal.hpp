@@ -69,7 +69,7 @@ struct SC {
 };
 
 // Device status bits (OR-ed by kernels, mapped to ofm_status on the host).
-enum : int { kStNonfinite = 1, kStCholesky = 2 };
+enum : int { kStNonfinite = 1, kStCholesky = 2, kStNoRoot = 4 };
 
 // Epilogue / pass modes.
 enum Mode : int {
@@ -196,7 +196,10 @@ struct BatchArgs {
   int cur = 0;       // ping-pong slot of the current direction
   int bf16 = 0;      // gather BF16 copies
   double tol = 0.0;
+  double freeze_eps = 0.0;
   int64_t t = 0;
+  int64_t* tcount = nullptr;   // the group's step counter on the device: read by the
+                               // residual, advanced by the line search of every step
   int check_every = 1;
   int nv = 0;
   int off = 0;       // first scalar slot the mode's products go to
@@ -218,7 +221,9 @@ hipError_t launch_finalize(const double* partials, int nb, int nv, double* out, 
 // advance_h: also H := (X + V D)^T A (X + V D) from X^T A V, V^T A V and the
 // step sizes D (the f2 directions then need no stored A X)
 hipError_t launch_linesearch(int k, int variant, int first, double alpha0, int advance_h, double* sc,
-                             int* status, const int* frozen, hipStream_t s);
+                             int* status, const int* frozen, double freeze_eps, hipStream_t s);
+hipError_t launch_select_roots(int tri, int64_t count, const double* coef, double* alpha,
+                               int32_t* nroots, hipStream_t s);
 hipError_t launch_residual(int k, int variant, double normA2, double* sc, int* status,
                            double tol, int* frozen, hipStream_t s);
 hipError_t launch_objective(int k, int variant, double normA2, const double* sc, double* out,

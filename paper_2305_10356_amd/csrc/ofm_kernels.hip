@@ -1267,16 +1267,26 @@ __device__ inline double block_sum256(double x, double* buf) {
 }
 
 // frozen (nullable): once the residual met the tolerance every step size is
-// 0, so the iterate that met it is the one kept
+// 0, so the iterate that met it is the one kept.  freeze_eps > 0: a step whose
+// direction is negligible against the iterate, ||G||_F <= freeze_eps ||X||_F
+// (from the column sums diag G^T G of the direction pass and tr X^T X), also
+// takes every step size 0.  A cubic that is not identically zero but has no
+// real root (Section 3.2 has no rule for it) takes step 0 and sets kStNoRoot.
 template <int KP>
 __device__ __forceinline__ void linesearch_body(int variant, int first, double alpha0,
                                                 double* sc, int* status, const int* frozen,
-                                                bool advance_h = false) {
-  const bool frz = frozen != nullptr && *frozen != 0;
+                                                bool advance_h = false, double freeze_eps = 0.0) {
+  bool frz = frozen != nullptr && *frozen != 0;
   __shared__ double buf[256];
   __shared__ double co[4];
   const int KK = KP * KP;
   const double* M = sc + SC<KP>::M;
+  if (freeze_eps > 0.0) {
+    const int t = threadIdx.x;
+    const double g2 = block_sum256(t < KP ? sc[SC<KP>::GG + t] : 0.0, buf);
+    const double x2 = block_sum256(t < KP ? M[t * KP + t] : 0.0, buf);
+    if (sqrt(g2) <= freeze_eps * sqrt(x2)) frz = true;
+  }
   const double* H = sc + SC<KP>::H;
   const double* C = sc + SC<KP>::C;
   const double* P = sc + SC<KP>::P;
@@ -1342,6 +1352,8 @@ __device__ __forceinline__ void linesearch_body(int variant, int first, double a
         bad = true;
         al = 0.0;
       }
+      if (!first && nr == 0 && (a3 != 0.0 || a2 != 0.0 || a1 != 0.0 || a0 != 0.0))
+        atomicOr(status, kStNoRoot);
       if (frz) al = 0.0;
       coef[0] = a3;
       coef[1] = a2;
@@ -1386,6 +1398,8 @@ __device__ __forceinline__ void linesearch_body(int variant, int first, double a
       atomicOr(status, kStNonfinite);
       al = 0.0;
     }
+    if (!first && nr == 0 && (a3 != 0.0 || a2 != 0.0 || a1 != 0.0 || a0 != 0.0))
+      atomicOr(status, kStNoRoot);
     if (frz) al = 0.0;
     coef[4 * i + 0] = a3;
     coef[4 * i + 1] = a2;
@@ -1413,8 +1427,22 @@ __device__ __forceinline__ void linesearch_body(int variant, int first, double a
 template <int KP>
 __global__ void __launch_bounds__(256) linesearch_kernel(int variant, int first, double alpha0,
                                                          int advance_h, double* sc, int* status,
-                                                         const int* frozen) {
-  linesearch_body<KP>(variant, first, alpha0, sc, status, frozen, advance_h != 0);
+                                                         const int* frozen, double freeze_eps) {
+  linesearch_body<KP>(variant, first, alpha0, sc, status, frozen, advance_h != 0, freeze_eps);
+}
+
+// The root rules of the line search on caller-given cubics (diagnostics):
+// coef[4 i + j] = a_{3-j} of cubic i, the same device code as the step.
+__global__ void __launch_bounds__(256) select_roots_kernel(int tri, int64_t count,
+                                                           const double* __restrict__ coef,
+                                                           double* __restrict__ alpha,
+                                                           int32_t* __restrict__ nroots) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  int nr = 0;
+  const double* c = coef + 4 * i;
+  alpha[i] = select_root(tri != 0, c[0], c[1], c[2], c[3], &nr);
+  nroots[i] = nr;
 }
 
 // ---------------------------------------------------------------------------
@@ -1767,10 +1795,10 @@ hipError_t launch_finalize(const double* partials, int nb, int nv, double* out, 
 }
 
 hipError_t launch_linesearch(int k, int variant, int first, double alpha0, int advance_h, double* sc,
-                             int* status, const int* frozen, hipStream_t s) {
+                             int* status, const int* frozen, double freeze_eps, hipStream_t s) {
 #define OFM_LS(KP)                                                                              \
   hipLaunchKernelGGL(linesearch_kernel<KP>, dim3(1), dim3(256), 0, s, variant, first, alpha0, \
-                     advance_h, sc, status, frozen);                                           \
+                     advance_h, sc, status, frozen, freeze_eps);                               \
   break;
   switch (k) {
     case 4: OFM_LS(4)
@@ -1781,6 +1809,14 @@ hipError_t launch_linesearch(int k, int variant, int first, double alpha0, int a
     default: return hipErrorInvalidValue;
   }
 #undef OFM_LS
+  return hipGetLastError();
+}
+
+hipError_t launch_select_roots(int tri, int64_t count, const double* coef, double* alpha,
+                               int32_t* nroots, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(select_roots_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                     tri, count, coef, alpha, nroots);
   return hipGetLastError();
 }
 
@@ -2000,9 +2036,13 @@ __global__ void __launch_bounds__(64) batch_finalize2_kernel(BatchArgs b) {
 template <int KP>
 __global__ void __launch_bounds__(256) batch_linesearch_kernel(BatchArgs b, double alpha0,
                                                                int first_fixed) {
+  // the group's step counter: this is the last pass that reads the step's
+  // scalars, and the residual of the next step reads the new value
+  if (blockIdx.x == 0 && threadIdx.x == 0) *b.tcount += 1;
   const BatchGraph& d = b.graphs[blockIdx.x];
   if (*d.active == 0) return;
-  linesearch_body<KP>(b.variant, first_fixed, alpha0, d.sc, d.status, nullptr);
+  linesearch_body<KP>(b.variant, first_fixed, alpha0, d.sc, d.status, nullptr, false,
+                      b.freeze_eps);
 }
 
 // residual of X^t; a graph whose residual meets the tolerance (or whose
@@ -2015,12 +2055,13 @@ __global__ void __launch_bounds__(256) batch_residual_kernel(BatchArgs b) {
   __syncthreads();
   if (threadIdx.x == 0) {
     const double rr = d.sc[SC<KP>::RELRES];
+    const int64_t t = *b.tcount;  // the step index, kept on the device (graph replays)
     if ((b.tol > 0.0 && rr <= b.tol) || *d.status != 0) {
       *d.active = 0;
-      *d.done_iter = b.t;
+      *d.done_iter = t;
     } else if (b.tol > 0.0) {
       // stall test: less than 5% decrease over the last kBatchHist checks
-      const int64_t c = b.t / b.check_every;
+      const int64_t c = t / b.check_every;
       const int slot = (int)(c % kBatchHist);
       const double old = d.hist[slot];
       if (c >= kBatchHist && rr > 0.95 * old) {

@@ -24,7 +24,7 @@ OFM_LAP_NO_REORDER = 2
 STATUS = {
     0: "OFM_OK", -1: "OFM_E_INVALID_ARG", -2: "OFM_E_SHAPE", -3: "OFM_E_GRAPH",
     -4: "OFM_E_NONFINITE", -5: "OFM_E_NUMERIC", -6: "OFM_E_HIP", -7: "OFM_E_NOMEM",
-    -8: "OFM_E_UNSUPPORTED",
+    -8: "OFM_E_UNSUPPORTED", -9: "OFM_E_NO_ROOT",
 }
 
 VARIANTS = {"f1": OFM_F1, "tri-f1": OFM_TRI_F1, "f2": OFM_F2, "tri-f2": OFM_TRI_F2}
@@ -53,6 +53,7 @@ class Opts(ctypes.Structure):
         ("graph", ctypes.c_int),
         ("recur", ctypes.c_int),
         ("gather", ctypes.c_int),
+        ("freeze_eps", ctypes.c_double),
     ]
 
 
@@ -82,9 +83,11 @@ _D = ctypes.c_double
 _SIGS = {
     "ofm_status_string": (ctypes.c_char_p, [_I]),
     "ofm_version": (ctypes.c_char_p, []),
-    "ofm_build_laplacian": (_I, [_I64, _I64, _P, _P, _P, ctypes.c_uint, _P, ctypes.POINTER(_P)]),
-    "ofm_build_laplacian_grouped": (_I, [_I64, _I64, _P, _P, _P, ctypes.c_uint, _P, _P,
+    "ofm_build_laplacian": (_I, [_I64, _I64, _P, _P, _P, _I, ctypes.c_uint, _P,
+                                 ctypes.POINTER(_P)]),
+    "ofm_build_laplacian_grouped": (_I, [_I64, _I64, _P, _P, _P, _I, ctypes.c_uint, _P, _P,
                                          ctypes.POINTER(_P)]),
+    "ofm_select_roots": (_I, [_I, _I64, _P, _P, _P, _P]),
     "ofm_grouped_order": (_I, [_I64, _P, _P, _P, _P]),
     "ofm_laplacian_destroy": (_I, [_P]),
     "ofm_laplacian_info": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
@@ -108,7 +111,12 @@ _SIGS = {
     "ofm_batch_destroy": (_I, [_P]),
     "ofm_batch_solve": (_I, [_P, _P, _P, _P]),
     "ofm_batch_schedule": (_I, [_P, _P, _P, _P]),
-    "ofm_batch_phases": (_I, [_P, _P, _P]),
+    "ofm_batch_phases": (_I, [_P, _P, _P, _P]),
+    "ofm_batch_init": (_I, [_P, _P, _P]),
+    "ofm_batch_set_schedule": (_I, [_P, _I]),
+    "ofm_batch_step": (_I, [_P, _P]),
+    "ofm_batch_get_state": (_I, [_P, _I, _P, _P, _P]),
+    "ofm_batch_get_step_info": (_I, [_P, _I, _P, _P, _P, _P, _P]),
     "ofm_scale": (_I, [_I64, _I, _P, _P, _P, _P]),
     "ofm_row_normalize": (_I, [_I64, _I, _I, _P, _P, _P]),
     "ofm_kmeans_assign": (_I, [_I64, _I, _I, _P, _P, _P, _P, _P]),
@@ -177,21 +185,28 @@ class Laplacian:
 
     def __init__(self, row_ptr, col_idx, vals=None, validate: bool = False,
                  reorder: bool = True, groups=None, stream=None):
-        """``groups``: optional int32[n] (a host array or a tensor, e.g. the
-        cluster labels of an earlier solve; negative = none) that lays the
-        row-processing order out for the XCDs (``ofm_build_laplacian_grouped``)."""
+        """``vals``: optional edge weights, FP64 or FP32 (a tensor keeps its
+        dtype; anything else is taken as FP64).  ``groups``: optional
+        int32[n] (a host array or a tensor, e.g. the cluster labels of an
+        earlier solve; negative = none) that lays the row-processing order out
+        for the XCDs (``ofm_build_laplacian_grouped``)."""
         torch = _torch()
         lib = load()
         self._lib = lib
         rp = torch.as_tensor(row_ptr, dtype=torch.int32).contiguous().cuda()
         ci = torch.as_tensor(col_idx, dtype=torch.int32).contiguous().cuda()
-        vv = None if vals is None else torch.as_tensor(vals, dtype=torch.float64).contiguous().cuda()
+        vv, vdt = None, OFM_FP64
+        if vals is not None:
+            if hasattr(vals, "dtype") and vals.dtype in (torch.float32, np.float32):
+                vv, vdt = torch.as_tensor(vals, dtype=torch.float32).contiguous().cuda(), OFM_FP32
+            else:
+                vv = torch.as_tensor(vals, dtype=torch.float64).contiguous().cuda()
         n = rp.numel() - 1
         flags = (OFM_LAP_VALIDATE if validate else 0) | (0 if reorder else OFM_LAP_NO_REORDER)
         h = ctypes.c_void_p()
         if groups is None:
             st = lib.ofm_build_laplacian(n, ci.numel(), _ptr(rp), _ptr(ci) if ci.numel() else None,
-                                         _ptr(vv) if vv is not None else None, flags,
+                                         _ptr(vv) if vv is not None else None, vdt, flags,
                                          _stream(stream), ctypes.byref(h))
             _check(st, "ofm_build_laplacian")
         else:
@@ -202,7 +217,8 @@ class Laplacian:
                 raise ValueError("groups must hold one entry per node")
             st = lib.ofm_build_laplacian_grouped(
                 n, ci.numel(), _ptr(rp), _ptr(ci) if ci.numel() else None,
-                _ptr(vv) if vv is not None else None, flags, gr.ctypes.data_as(ctypes.c_void_p),
+                _ptr(vv) if vv is not None else None, vdt, flags,
+                gr.ctypes.data_as(ctypes.c_void_p),
                 _stream(stream), ctypes.byref(h))
             _check(st, "ofm_build_laplacian_grouped")
         self.grouped = groups is not None
@@ -248,7 +264,8 @@ class Workspace:
     def __init__(self, lap: Laplacian, k: int, variant="f1", precision=OFM_FP32,
                  max_iter: int = 1000, check_every: int = 10, first_step: int = 0,
                  restart: bool = False, alpha0: float = 0.0, tol: float = 0.0,
-                 graph: bool = False, recur: bool = False, gather: int = GATHER_AUTO):
+                 graph: bool = False, recur: bool = False, gather: int = GATHER_AUTO,
+                 freeze_eps: float = 0.0):
         lib = load()
         self._lib = lib
         self.lap = lap
@@ -256,7 +273,7 @@ class Workspace:
         v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
         self.opts = Opts(v, int(precision), int(max_iter), int(check_every), int(first_step),
                          1 if restart else 0, float(alpha0), float(tol), 1 if graph else 0,
-                         1 if recur else 0, int(gather))
+                         1 if recur else 0, int(gather), float(freeze_eps))
         h = ctypes.c_void_p()
         _check(lib.ofm_workspace_create(lap.handle, k, ctypes.byref(self.opts), ctypes.byref(h)),
                "ofm_workspace_create")
@@ -387,14 +404,16 @@ class Batch:
 
     def __init__(self, laps, ks, variant="f1", precision=OFM_FP32, max_iter: int = 1000,
                  check_every: int = 10, tol: float = 1e-4, restart: bool = False,
-                 first_step: int = 0, alpha0: float = 0.0, recur: bool = False):
+                 first_step: int = 0, alpha0: float = 0.0, recur: bool = False,
+                 freeze_eps: float = 0.0, graph: bool = False):
         lib = load()
         self._lib = lib
         self.laps = list(laps)
         self.ks = [int(k) for k in ks]
         v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
         self.opts = Opts(v, int(precision), int(max_iter), int(check_every), int(first_step),
-                         1 if restart else 0, float(alpha0), float(tol), 0, 1 if recur else 0)
+                         1 if restart else 0, float(alpha0), float(tol), 1 if graph else 0,
+                         1 if recur else 0, GATHER_DEFAULT, float(freeze_eps))
         n = len(self.laps)
         handles = (ctypes.c_void_p * n)(*[l.handle.value for l in self.laps])
         kk = (ctypes.c_int * n)(*self.ks)
@@ -403,17 +422,58 @@ class Batch:
                "ofm_batch_create")
         self.handle = h
 
-    def solve(self, Xs, stream=None):
+    def _ptrs(self, Xs):
         n = len(self.laps)
+        if len(Xs) != n:
+            raise ValueError(f"expected {n} blocks")
         for X, lap, k in zip(Xs, self.laps, self.ks):
             _dev_block(X, k)
             if X.dtype != _torch().float32 or X.shape[0] != lap.n:
                 raise ValueError("X must be N x k FP32")
-        ptrs = (ctypes.c_void_p * n)(*[X.data_ptr() for X in Xs])
+        return (ctypes.c_void_p * n)(*[X.data_ptr() for X in Xs])
+
+    def init(self, Xs, stream=None):
+        """Set-up step of Algorithm 2 on every graph (the blocks are kept)."""
+        self._held = list(Xs)
+        _check(self._lib.ofm_batch_init(self.handle, self._ptrs(Xs), _stream(stream)),
+               "ofm_batch_init")
+
+    def step(self, stream=None):
+        """One lockstep loop iteration of every active graph."""
+        _check(self._lib.ofm_batch_step(self.handle, _stream(stream)), "ofm_batch_step")
+
+    def get_state(self, i: int, stream=None):
+        """(V_prev, G_prev) of graph i, FP32 device tensors."""
+        torch = _torch()
+        Vp = torch.empty((self.laps[i].n, self.ks[i]), dtype=torch.float32, device="cuda")
+        Gp = torch.empty_like(Vp)
+        _check(self._lib.ofm_batch_get_state(self.handle, int(i), _ptr(Vp), _ptr(Gp),
+                                             _stream(stream)), "ofm_batch_get_state")
+        return Vp, Gp
+
+    def step_info(self, i: int, stream=None) -> dict:
+        k = self.ks[i]
+        alpha = np.zeros(k)
+        beta = np.zeros(k)
+        coef = np.zeros(4 * k)
+        nr = np.zeros(k, dtype=np.int32)
+        _check(self._lib.ofm_batch_get_step_info(
+            self.handle, int(i), alpha.ctypes.data_as(ctypes.c_void_p),
+            beta.ctypes.data_as(ctypes.c_void_p), coef.ctypes.data_as(ctypes.c_void_p),
+            nr.ctypes.data_as(ctypes.c_void_p), _stream(stream)), "ofm_batch_get_step_info")
+        return {"alpha": alpha, "beta": beta, "coeffs": coef.reshape(k, 4).T.copy(), "nroots": nr}
+
+    def solve(self, Xs, stream=None):
+        n = len(self.laps)
+        ptrs = self._ptrs(Xs)
         stats = (Stats * n)()
         _check(self._lib.ofm_batch_solve(self.handle, ptrs, _stream(stream), stats),
                "ofm_batch_solve")
         return [s.as_dict() for s in stats]
+
+    def set_schedule(self, tpw: int):
+        """Fix the tiles-per-wavefront target (2, 4, 8 or 16; 0: timed per solve)."""
+        _check(self._lib.ofm_batch_set_schedule(self.handle, int(tpw)), "ofm_batch_set_schedule")
 
     def schedule(self):
         """(tiles-per-wavefront target chosen, ms per iteration of each
@@ -427,11 +487,14 @@ class Batch:
         return tpw.value, ms, esc.value
 
     def phases(self):
-        """(lockstep FP32 loop ms, FP64 finishing ms) of the last solve (host time)."""
+        """(lockstep FP32 loop ms, FP64 finishing ms) of the last solve (host
+        time); ``self.replays`` gets the graph replays of its lockstep loop."""
         a = ctypes.c_double()
         b = ctypes.c_double()
-        _check(self._lib.ofm_batch_phases(self.handle, ctypes.byref(a), ctypes.byref(b)),
-               "ofm_batch_phases")
+        r = ctypes.c_int64()
+        _check(self._lib.ofm_batch_phases(self.handle, ctypes.byref(a), ctypes.byref(b),
+                                          ctypes.byref(r)), "ofm_batch_phases")
+        self.replays = r.value
         return a.value, b.value
 
     def close(self):
@@ -461,6 +524,22 @@ def grouped_order(row_ptr, groups):
                                     order.ctypes.data_as(ctypes.c_void_p),
                                     slots.ctypes.data_as(ctypes.c_void_p)), "ofm_grouped_order")
     return order, slots
+
+
+def select_roots(variant, coeffs, stream=None):
+    """The device root rules of the line search on given cubics: ``coeffs``
+    [count, 4] rows (a3, a2, a1, a0); returns (alpha FP64[count], nroots
+    int32[count]) as host arrays (synchronizing)."""
+    torch = _torch()
+    v = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    co = torch.as_tensor(np.ascontiguousarray(coeffs, dtype=np.float64).reshape(-1, 4)).cuda()
+    n = co.shape[0]
+    al = torch.empty(n, dtype=torch.float64, device="cuda")
+    nr = torch.empty(n, dtype=torch.int32, device="cuda")
+    _check(load().ofm_select_roots(v, n, _ptr(co), _ptr(al), _ptr(nr), _stream(stream)),
+           "ofm_select_roots")
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return al.cpu().numpy(), nr.cpu().numpy()
 
 
 def scale(X, s, Y=None, stream=None):

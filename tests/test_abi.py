@@ -38,23 +38,35 @@ def test_status_strings(lib):
     assert lib.ofm_status_string(0) == b"OFM_OK"
     assert lib.ofm_status_string(-3) == b"OFM_E_GRAPH"
     assert lib.ofm_status_string(-8) == b"OFM_E_UNSUPPORTED"
+    assert lib.ofm_status_string(-9) == b"OFM_E_NO_ROOT"
+    assert lib.ofm_status_string(-10) == b"OFM_E_UNKNOWN"
     assert lib.ofm_status_string(5) == b"OFM_E_UNKNOWN"
 
 
 def test_host_argument_checks(lib):
     h = ctypes.c_void_p()
     # no output handle / empty graph / null pointers
-    assert lib.ofm_build_laplacian(10, 0, None, None, None, 0, None, None) == -1
-    assert lib.ofm_build_laplacian(0, 0, None, None, None, 0, None, ctypes.byref(h)) == -1
-    assert lib.ofm_build_laplacian(10, 5, None, None, None, 0, None, ctypes.byref(h)) == -1
-    assert lib.ofm_build_laplacian(10, 5, ctypes.c_void_p(16), ctypes.c_void_p(16), None, 1 << 5,
-                                   None, ctypes.byref(h)) == -1
+    assert lib.ofm_build_laplacian(10, 0, None, None, None, 0, 0, None, None) == -1
+    assert lib.ofm_build_laplacian(0, 0, None, None, None, 0, 0, None, ctypes.byref(h)) == -1
+    assert lib.ofm_build_laplacian(10, 5, None, None, None, 0, 0, None, ctypes.byref(h)) == -1
+    assert lib.ofm_build_laplacian(10, 5, ctypes.c_void_p(16), ctypes.c_void_p(16), None, 0,
+                                   1 << 5, None, ctypes.byref(h)) == -1
     assert lib.ofm_build_laplacian(1 << 31, 5, ctypes.c_void_p(16), ctypes.c_void_p(16), None, 0,
-                                   None, ctypes.byref(h)) == -2
+                                   0, None, ctypes.byref(h)) == -2
+    # weights of an unknown type are refused before anything is enqueued
+    assert lib.ofm_build_laplacian(10, 5, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                   ctypes.c_void_p(16), 7, 0, None, ctypes.byref(h)) == -1
+    # the root rules: bad variant, negative count, null arrays; nothing to do for 0
+    assert lib.ofm_select_roots(4, 1, p16 := ctypes.c_void_p(16), p16, p16, None) == -1
+    assert lib.ofm_select_roots(0, -1, p16, p16, p16, None) == -1
+    assert lib.ofm_select_roots(0, 3, None, p16, p16, None) == -1
+    assert lib.ofm_select_roots(1, 0, None, None, None, None) == 0
     assert lib.ofm_laplacian_destroy(None) == -1
     assert lib.ofm_workspace_destroy(None) == -1
     opts = ofm.Opts(0, 1, 10, 1, 0, 0, 0.0, 0.0)
     assert lib.ofm_workspace_create(None, 8, ctypes.byref(opts), ctypes.byref(h)) == -1
+    # the options struct of the binding has the header's layout
+    assert ctypes.sizeof(ofm.Opts) == 64 and ofm.Opts.freeze_eps.offset == 56
     assert lib.ofm_init(None, None, None) == -1
     assert lib.ofm_step(None, None, None) == -1
     assert lib.ofm_apply_A(None, 8, 1, None, None, None) == -1

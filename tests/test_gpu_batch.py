@@ -115,3 +115,121 @@ def test_batch_on_grouped_laplacians(batch_graphs):
         rr = O.relres(olap, X.cpu().numpy().astype(np.float64))
         assert s["converged"] == 1 and s["status"] == 0, s
         assert rr == pytest.approx(s["relres"], rel=0.05, abs=2e-6), (g.n, k, rr, s["relres"])
+
+
+# ---------------------------------------------------------------------------
+# Element-wise parity of the batched iterates with the FP64 oracle (teacher
+# forcing: every member's device state is handed to the oracle, which takes
+# one step of Algorithm 2 from it; X, alpha and beta of the batch's step are
+# compared per member at the FP32 tolerance)
+# ---------------------------------------------------------------------------
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("variant,vid,recur", [("f1", O.F1, False), ("f2", O.F2, False),
+                                               ("tri-f1", O.TRI_F1, False),
+                                               ("tri-f2", O.TRI_F2, False),
+                                               ("f1", O.F1, True)])
+def test_batch_teacher_forced_vs_oracle(batch_graphs, variant, vid, recur):
+    import stepcheck
+    from paper_2305_10356_amd import ofm
+    gs, laps = batch_graphs
+    ks = [k for _, _, k in gs]
+    restart = O.is_tri(vid)
+    B = ofm.Batch(laps, ks, variant=variant, max_iter=1000, tol=0.0, check_every=10,
+                  restart=restart, recur=recur)
+    opts = O.Options(variant=vid, restart=restart)
+    olaps = [O.laplacian(g.n, g.row_ptr, g.col_idx) for g, _, _ in gs]
+    Xs = [torch.tensor(x0.astype(np.float32), device="cuda") for _, x0, _ in gs]
+    X0 = [host(X) for X in Xs]
+    B.init(Xs)
+    for i, (olap, x) in enumerate(zip(olaps, X0)):
+        st_o, info_o = O.init(olap, x, opts)
+        assert stepcheck.rel(host(Xs[i]), st_o.X) < 1e-4, (i, "init")
+    checkpoints = {1, 2, 5, 10, 11, 20, 30}
+    flips = 0
+    for t in range(1, max(checkpoints) + 1):
+        if t not in checkpoints:
+            B.step()
+            continue
+        states = []
+        for i in range(len(gs)):
+            Vp, Gp = B.get_state(i)
+            states.append(O.State(X=host(Xs[i]), V_prev=host(Vp), G_prev=host(Gp), t=t))
+        B.step()
+        worst = (0.0, 0.0, 0.0)
+        for i, ((g, _, k), olap, state) in enumerate(zip(gs, olaps, states)):
+            st_o, info_o = O.step(olap, state, opts)
+            gi = B.step_info(i)
+            ex, ea, eb, fl = stepcheck.compare_step(vid, k, state.X, host(Xs[i]), gi, info_o,
+                                                    st_o.X, False, G_prev=state.G_prev)
+            flips += len(fl)
+            assert ex < 1e-4, (variant, t, i, g.n, k, ex)
+            worst = tuple(max(a, b) for a, b in zip(worst, (ex, ea, eb)))
+        print(f"  batch {variant} recur={recur} t={t}: worst dX {worst[0]:.2e} "
+              f"dalpha {worst[1]:.2e} dbeta {worst[2]:.2e}", flush=True)
+    assert flips <= 3, flips
+
+
+@pytest.mark.parametrize("variant,vid", [("f1", O.F1), ("f2", O.F2)])
+def test_batch_limits_vs_dense_eigh(lib, variant, vid):
+    # Theorem 1 (f1: eig X^T X -> 2 - mu_i, X X^T -> U (2 - mu) U^T) and
+    # Theorem 3 (f2: X^T X -> I, X X^T -> U U^T) on small members of a batch
+    # solved to residual 1e-6 in FP32, against the dense eigendecomposition
+    from paper_2305_10356_amd import ofm
+    rng = np.random.default_rng(52)
+    gs = []
+    for b, (n, k) in enumerate([(900, 4), (1400, 8), (2000, 16), (1200, 8)]):
+        g = graphs.sbm_plain(graphs.equal_sizes(n, k), 16.0, 0.2, np.random.default_rng([52, b, 1]))
+        gs.append((g, graphs.initial_x(n, k, np.random.default_rng([52, b, 2])), k))
+    laps = [ofm.Laplacian(g.row_ptr, g.col_idx) for g, _, _ in gs]
+    B = ofm.Batch(laps, [k for _, _, k in gs], variant=variant, max_iter=5000, tol=1e-6,
+                  check_every=10)
+    Xs = [torch.tensor(x0.astype(np.float32), device="cuda") for _, x0, _ in gs]
+    st = B.solve(Xs)
+    for (g, _, k), X, s in zip(gs, Xs, st):
+        olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
+        mu, U = O.dense_eigh(olap)
+        Xh = host(X)
+        rr = O.relres(olap, Xh)
+        assert s["converged"] == 1 and rr < 2e-6, (g.n, k, s, rr)
+        ev = np.sort(np.linalg.eigvalsh(Xh.T @ Xh))
+        Uk = U[:, :k]
+        if vid == O.F1:
+            np.testing.assert_allclose(ev, np.sort(2.0 - mu[:k]), rtol=1e-4)
+            target = (Uk * (2.0 - mu[:k])[None, :]) @ Uk.T
+        else:
+            np.testing.assert_allclose(ev, 1.0, rtol=1e-4)
+            target = Uk @ Uk.T
+        gap = mu[k] - mu[k - 1]
+        err = np.abs(Xh @ Xh.T - target).max()
+        print(f"  {variant} n={g.n} k={k}: relres {rr:.1e} gap {gap:.3f} |XX^T - lim| {err:.1e}",
+              flush=True)
+        assert err < 1e-3
+
+
+@pytest.mark.parametrize("recur", [False, True])
+def test_batch_graph_replay_bitwise_eager(batch_graphs, recur):
+    # the lockstep loop replayed as HIP graphs (one per check_every updates of
+    # every graph) gives bit for bit the eager loop's iterates and counts
+    from paper_2305_10356_amd import ofm
+    gs, laps = batch_graphs
+    ks = [k for _, _, k in gs]
+    out = []
+    for graph in (False, True):
+        B = ofm.Batch(laps, ks, variant="f1", max_iter=3000, tol=1e-4, check_every=10,
+                      recur=recur, graph=graph)
+        B.set_schedule(4)
+        Xs = [torch.tensor(x0.astype(np.float32), device="cuda") for _, x0, _ in gs]
+        st = B.solve(Xs)
+        B.phases()
+        out.append((Xs, st, B.schedule()[0], B.replays))
+    (Xe, se, te, re), (Xg, sg, tg, rg) = out
+    print(f"  recur={recur}: eager tiles/wave {te}, graph tiles/wave {tg}, replays {rg}", flush=True)
+    assert re == 0 and rg > 0 and te == tg == 4
+    for a, b, x, y in zip(se, sg, Xe, Xg):
+        assert a["iters"] == b["iters"] and a["relres"] == b["relres"], (a, b)
+        assert torch.equal(x, y)

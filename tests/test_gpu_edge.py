@@ -151,6 +151,72 @@ def test_weighted_graph(lib):
     np.testing.assert_allclose(X @ X.T, (Uk * (2.0 - mu[:8])[None, :]) @ Uk.T, atol=1e-6)
 
 
+def cycle_with_loops(n, w):
+    """C_n plus a self-loop of weight w at every node (stored once per row)."""
+    rp, ci, _ = csr(n, cycle_edges(n))
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    rows = np.concatenate([rows, np.arange(n)])
+    cols = np.concatenate([ci, np.arange(n)])
+    order = np.lexsort((cols, rows))
+    rows, cols = rows[order], cols[order]
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, rows + 1, 1)
+    vals = np.where(rows == cols, w, 1.0)
+    return np.cumsum(rp).astype(np.int32), cols.astype(np.int32), vals
+
+
+@pytest.mark.parametrize("w", [0.5, 3.0])
+@pytest.mark.parametrize("n", [11, 40])
+def test_self_loops_closed_form(lib, n, w):
+    # S = adjacency(C_n) + w I is (2 + w)-regular: ||A||_F^2 = n (1 + w/(2+w))^2
+    # + 2n/(2+w)^2, and cos(2 pi j i / n) is an eigenvector of A with eigenvalue
+    # -1 - (w + 2 cos(2 pi j / n)) / (2 + w); weights given in FP64 and in FP32
+    # (0.5 and 3 are exact in both) build the same Laplacian
+    from paper_2305_10356_amd import ofm
+    rp, ci, vals = cycle_with_loops(n, w)
+    d = 2.0 + w
+    expect = n * (1.0 + w / d) ** 2 + 2.0 * n / d ** 2
+    olap = O.laplacian(n, rp, ci, vals=vals)
+    i = np.arange(n)
+    Z = np.stack([np.cos(2 * np.pi * j * i / n) for j in range(8)], axis=1)
+    lam = -1.0 - (w + 2.0 * np.cos(2 * np.pi * np.arange(8) / n)) / d
+    outs = []
+    for vv in (vals, vals.astype(np.float32)):
+        lap = ofm.Laplacian(rp, ci, vals=vv, validate=True)
+        info = lap.info()
+        np.testing.assert_allclose(info["degrees"], d, rtol=1e-15)
+        assert info["normA2"] == pytest.approx(expect, rel=1e-13)
+        assert info["normA2"] == pytest.approx(O.norm_A_fro_sq(olap), rel=1e-13)
+        Y = host(lap.apply(torch.as_tensor(Z).cuda()))
+        np.testing.assert_allclose(Y, Z * lam[None, :], rtol=0, atol=1e-13)
+        np.testing.assert_allclose(Y, O.apply_A(olap, Z), rtol=0, atol=1e-13)
+        Y32 = host(lap.apply(torch.as_tensor(Z.astype(np.float32)).cuda()))
+        np.testing.assert_allclose(Y32, O.apply_A(olap, Z.astype(np.float32).astype(np.float64)),
+                                   rtol=0, atol=1e-6)
+        outs.append((info["normA2"], Y))
+    assert outs[0][0] == outs[1][0] and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_fp32_weights_match_fp64(lib):
+    # FP32 weights are widened exactly: the Laplacian equals the one built from
+    # the same values in FP64, bit for bit
+    from paper_2305_10356_amd import graphs, ofm
+    g, _ = graphs.workload("sbm-n1000-k8")
+    rng = np.random.default_rng(78)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    key = np.minimum(rows, g.col_idx) * g.n + np.maximum(rows, g.col_idx)
+    uniq, inv = np.unique(key, return_inverse=True)
+    w32 = rng.uniform(0.1, 3.0, size=uniq.shape[0]).astype(np.float32)[inv]
+    l32 = ofm.Laplacian(g.row_ptr, g.col_idx, vals=w32, validate=True)
+    l64 = ofm.Laplacian(g.row_ptr, g.col_idx, vals=w32.astype(np.float64), validate=True)
+    i32, i64 = l32.info(), l64.info()
+    assert np.array_equal(i32["degrees"], i64["degrees"]) and i32["normA2"] == i64["normA2"]
+    Z = torch.as_tensor(rng.standard_normal((g.n, 16))).cuda()
+    assert torch.equal(l32.apply(Z), l64.apply(Z))
+    olap = O.laplacian(g.n, g.row_ptr, g.col_idx, vals=w32.astype(np.float64))
+    assert i32["normA2"] == pytest.approx(O.norm_A_fro_sq(olap), rel=1e-12)
+
+
 def test_step_before_init_is_refused(lib):
     from paper_2305_10356_amd import graphs, ofm
     g, x0 = graphs.workload("sbm-n1000-k8")

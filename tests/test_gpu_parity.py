@@ -10,6 +10,7 @@ import sys
 import numpy as np
 import pytest
 
+import stepcheck
 from oracle import ofm_oracle as O
 from paper_2305_10356_amd import graphs
 
@@ -157,6 +158,7 @@ def test_workspace_shape_errors(ofm, sbm1k_lap):
 
 def teacher_forced(ofm, glap, olap, x0, variant, vid, precision, checkpoints, tol, restart=False):
     dt = torch.float64 if precision == ofm.OFM_FP64 else torch.float32
+    fp64 = precision == ofm.OFM_FP64
     k = x0.shape[1]
     opts = O.Options(variant=vid, restart=restart)
     ws = ofm.Workspace(glap, k, variant=variant, precision=precision, restart=restart,
@@ -178,49 +180,15 @@ def teacher_forced(ofm, glap, olap, x0, variant, vid, precision, checkpoints, to
             st_o, info_o = O.step(olap, state, opts)
             ws.step(X)
             gi = ws.step_info()
-            ex = rel(host(X), st_o.X)
-            # step scalars are compared where they are determined by the data:
-            # once a column's direction is at the rounding floor
-            # (||G_i|| <= 1e-6 ||AX_i||) its alpha_i and beta_i are set by
-            # rounding noise on both sides, while alpha_i V_i stays negligible
-            gn = np.linalg.norm(info_o["G"], axis=0)
-            an = np.linalg.norm(info_o["AX"], axis=0)
-            live = gn > 1e-6 * an if O.is_tri(vid) else np.full(k, gn.sum() > 1e-6 * an.sum())
-            ea = rel(gi["alpha"][live], info_o["alpha"][live]) if live.any() else 0.0
-            eb = rel(gi["beta"][live], info_o["beta"][live]) if live.any() else 0.0
-            # a root-choice flip: near a tie (or a near-repeated root) the two
-            # sides may take different real roots of the same cubic; it is
-            # accepted when both step sizes are roots, and X is then checked
-            # against X^t + V diag(alpha_gpu) with the oracle's V
-            ag, ao = gi["alpha"], info_o["alpha"]
-            fp64 = precision == ofm.OFM_FP64
-            ftol, rtol = (1e-6, 1e-6) if fp64 else (1e-2, 1e-3)
-            flip = live & (np.abs(ag - ao) > ftol * max(np.abs(ao).max(), 1e-30))
-            if flip.any():
-                cols = np.flatnonzero(flip) if O.is_tri(vid) else [0]
-                for i in cols:
-                    co = info_o["coeffs"][:, i] if O.is_tri(vid) else info_o["coeffs"]
-                    for a in (ag[i], ao[i]):
-                        scale = sum(abs(c) * abs(a) ** (3 - j) for j, c in enumerate(co))
-                        assert abs(np.polyval(co, a)) <= rtol * scale, (variant, t, i, "not a root")
-                ex = rel(host(X), Xh + info_o["V"] * ag[None, :])
-                flips.append((t, [int(c) for c in cols]))
-                say(f"  {variant} t={t}: root-choice flip in columns {list(cols)} "
-                    f"(gpu {ag[flip]}, oracle {ao[flip]})")
-                live = live & ~flip
-                ea = rel(ag[live], ao[live]) if live.any() else 0.0
-            say(f"  {variant} t={t} dX={ex:.2e} dalpha={ea:.2e} dbeta={eb:.2e} live={int(live.sum())}")
+            ex, ea, eb, fl = stepcheck.compare_step(vid, k, Xh, host(X), gi, info_o, st_o.X,
+                                                    fp64, say=say, G_prev=state.G_prev)
+            flips += [(t, c, why) for c, why in fl]
+            say(f"  {variant} t={t} dX={ex:.2e} dalpha={ea:.2e} dbeta={eb:.2e}")
             assert ex < tol, (variant, t, "X")
-            if precision == ofm.OFM_FP64 and live.any():
-                assert ea < 1e-8 and eb < 1e-8, (variant, t)
-                co = O.VARIANT_NAMES[vid]
-                if O.is_tri(vid):
-                    assert rel(gi["coeffs"][:, live], info_o["coeffs"][:, live]) < 1e-8, co
-                else:
-                    assert rel(gi["coeffs"][:, 0], info_o["coeffs"]) < 1e-8, co
             worst = max(worst, ex)
         else:
             ws.step(X)
+    say(f"  {variant}: {len(flips)} explained root-choice flips {flips}")
     assert len(flips) <= 2, flips
     return worst
 
