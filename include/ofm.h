@@ -502,6 +502,28 @@ ofm_status ofm_kmeans(int64_t n, int dim, int n_clusters, const float* Y,
                       const double* host_uniforms, int max_iter, int32_t* labels,
                       float* centroids, int32_t* host_iters, hipStream_t stream);
 
+/*
+ * ofm_kmeans without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, same kernels and bitwise the same results as
+ * ofm_kmeans; its temporary buffers (squared distances and previous labels,
+ * 8 bytes per point, the block partial sums of the centroids and a few small
+ * arrays: ofm_kmeans_static_bytes(n, dim, n_clusters) bytes) live in one
+ * file-scope device array of OFM_KMEANS_STATIC_BYTES (64 MiB) that every device
+ * the library runs on holds until the process ends.  Calls on one device share
+ * that array, so calls that overlap on one device (several host threads or
+ * streams) race and must be serialized by the caller; each call initializes
+ * what it reads.  Synchronizing.
+ * Errors: as ofm_kmeans; OFM_E_SHAPE when the buffers of the call would exceed
+ * OFM_KMEANS_STATIC_BYTES (e.g. n above about 7 million points at dim = 32
+ * and 32 clusters).
+ */
+#define OFM_KMEANS_STATIC_BYTES ((size_t)64 << 20)
+size_t ofm_kmeans_static_bytes(int64_t n, int dim, int n_clusters);
+ofm_status ofm_kmeans_noalloc(int64_t n, int dim, int n_clusters, const float* Y,
+                              const double* host_uniforms, int max_iter, int32_t* labels,
+                              float* centroids, int32_t* host_iters, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

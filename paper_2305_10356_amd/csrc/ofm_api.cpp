@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <thread>
 #include <vector>
@@ -1342,88 +1343,172 @@ extern "C" ofm_status ofm_kmeans_assign(int64_t n, int dim, int n_clusters, cons
   return OFM_OK;
 }
 
-extern "C" ofm_status ofm_kmeans(int64_t n, int dim, int n_clusters, const float* Y,
-                                 const double* host_uniforms, int max_iter, int32_t* labels,
-                                 float* centroids, int32_t* host_iters, hipStream_t stream) {
+// Device buffers of one K-means run (all caller- or library-owned, none
+// allocated here).
+struct KmeansBufs {
+  float* d2 = nullptr;       // [n] squared distance to the nearest chosen centre
+  int32_t* pick = nullptr;   // [1] index of the next centre
+  double* sums = nullptr;    // [nbs] chunk totals of the running sums
+  int32_t* prev = nullptr;   // [n] labels of the previous Lloyd iteration
+  double* part = nullptr;    // [nbk][n_clusters][dim + 1] block partials
+  float* cnew = nullptr;     // [n_clusters][dim] next centroids
+  int* changed = nullptr;    // [1] label change count
+};
+
+static ofm_status kmeans_check(int64_t n, int dim, int n_clusters, const float* Y,
+                               const double* host_uniforms, int max_iter, const int32_t* labels,
+                               const float* centroids) {
   if (n <= 0 || !Y || !host_uniforms || !labels || !centroids || max_iter < 1)
     return OFM_E_INVALID_ARG;
   if (dim < 1 || dim > 64 || n_clusters < 1 || n_clusters > 1024) return OFM_E_SHAPE;
   if (n_clusters > n) return OFM_E_SHAPE;
   for (int c = 0; c < n_clusters; ++c)
     if (!(host_uniforms[c] >= 0.0 && host_uniforms[c] < 1.0)) return OFM_E_INVALID_ARG;
+  return OFM_OK;
+}
+
+// k-means++ seeding, then Lloyd iterations (Algorithm 1 step 5), on the given
+// buffers.  Synchronizing.
+static ofm_status kmeans_run(int64_t n, int dim, int n_clusters, const float* Y,
+                             const double* host_uniforms, int max_iter, int32_t* labels,
+                             float* centroids, int32_t* host_iters, hipStream_t stream,
+                             const KmeansBufs& b) {
   const int nbk = kmeans_blocks(n, n_clusters * (dim + 1));
-  const int nbs = kmeans_pick_chunks(n);
-  float* d2 = nullptr;
-  int32_t* pick = nullptr;
-  double* sums = nullptr;
-  int32_t* prev = nullptr;
-  double* part = nullptr;
-  float* cnew = nullptr;
-  int* changed = nullptr;
-  ofm_status st = OFM_OK;
-  auto cleanup = [&]() {
-    dev_free(d2);
-    dev_free(pick);
-    dev_free(sums);
-    dev_free(prev);
-    dev_free(part);
-    dev_free(cnew);
-    dev_free(changed);
-  };
-  auto fail = [&](ofm_status s) {
-    cleanup();
-    return s;
-  };
-  if ((st = dev_alloc(&d2, n)) != OFM_OK) return fail(st);
-  if ((st = dev_alloc(&pick, 1)) != OFM_OK) return fail(st);
-  if ((st = dev_alloc(&sums, nbs)) != OFM_OK) return fail(st);
-  if ((st = dev_alloc(&prev, n)) != OFM_OK) return fail(st);
-  if ((st = dev_alloc(&part, (size_t)nbk * n_clusters * (dim + 1))) != OFM_OK) return fail(st);
-  if ((st = dev_alloc(&cnew, (size_t)n_clusters * dim)) != OFM_OK) return fail(st);
-  if ((st = dev_alloc(&changed, 1)) != OFM_OK) return fail(st);
   // k-means++ seeding
   int32_t first = (int32_t)std::min<int64_t>((int64_t)(host_uniforms[0] * (double)n), n - 1);
-  if (hipMemcpyAsync(pick, &first, sizeof(int32_t), hipMemcpyHostToDevice, stream) != hipSuccess)
-    return fail(OFM_E_HIP);
-  if (launch_kmeans_copy_centre(dim, Y, pick, centroids, 0, stream) != hipSuccess ||
-      launch_kmeans_mindist(n, dim, Y, centroids, d2, 1, sums, stream) != hipSuccess)
-    return fail(OFM_E_HIP);
+  HIPCHK(hipMemcpyAsync(b.pick, &first, sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  HIPCHK(launch_kmeans_copy_centre(dim, Y, b.pick, centroids, 0, stream));
+  HIPCHK(launch_kmeans_mindist(n, dim, Y, centroids, b.d2, 1, b.sums, stream));
   for (int c = 1; c < n_clusters; ++c) {
-    if (launch_kmeans_pick(n, d2, host_uniforms[c], sums, pick, stream) != hipSuccess ||
-        launch_kmeans_copy_centre(dim, Y, pick, centroids, c, stream) != hipSuccess ||
-        launch_kmeans_mindist(n, dim, Y, centroids + (size_t)c * dim, d2, 0, sums, stream) !=
-            hipSuccess)
-      return fail(OFM_E_HIP);
+    HIPCHK(launch_kmeans_pick(n, b.d2, host_uniforms[c], b.sums, b.pick, stream));
+    HIPCHK(launch_kmeans_copy_centre(dim, Y, b.pick, centroids, c, stream));
+    HIPCHK(launch_kmeans_mindist(n, dim, Y, centroids + (size_t)c * dim, b.d2, 0, b.sums, stream));
   }
   // Lloyd iterations
   int it = 0;
   for (; it < max_iter; ++it) {
-    if (launch_kmeans_assign(n, dim, n_clusters, Y, centroids, labels, nullptr, stream) !=
-        hipSuccess)
-      return fail(OFM_E_HIP);
+    HIPCHK(launch_kmeans_assign(n, dim, n_clusters, Y, centroids, labels, nullptr, stream));
     if (it > 0) {
       int h = 0;
-      if (hipMemsetAsync(changed, 0, sizeof(int), stream) != hipSuccess ||
-          launch_count_changes(n, labels, prev, changed, stream) != hipSuccess ||
-          hipMemcpyAsync(&h, changed, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
-          hipStreamSynchronize(stream) != hipSuccess)
-        return fail(OFM_E_HIP);
+      HIPCHK(hipMemsetAsync(b.changed, 0, sizeof(int), stream));
+      HIPCHK(launch_count_changes(n, labels, b.prev, b.changed, stream));
+      HIPCHK(hipMemcpyAsync(&h, b.changed, sizeof(int), hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipStreamSynchronize(stream));
       if (h == 0) break;
     }
-    if (launch_kmeans_centroid_sums(n, dim, n_clusters, Y, labels, part, nbk, stream) !=
-            hipSuccess ||
-        launch_kmeans_centroid_final(dim, n_clusters, part, nbk, centroids, cnew, stream) !=
-            hipSuccess ||
-        hipMemcpyAsync(centroids, cnew, (size_t)n_clusters * dim * sizeof(float),
-                       hipMemcpyDeviceToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(prev, labels, n * sizeof(int32_t), hipMemcpyDeviceToDevice, stream) !=
-            hipSuccess)
-      return fail(OFM_E_HIP);
+    HIPCHK(launch_kmeans_centroid_sums(n, dim, n_clusters, Y, labels, b.part, nbk, stream));
+    HIPCHK(launch_kmeans_centroid_final(dim, n_clusters, b.part, nbk, centroids, b.cnew, stream));
+    HIPCHK(hipMemcpyAsync(centroids, b.cnew, (size_t)n_clusters * dim * sizeof(float),
+                          hipMemcpyDeviceToDevice, stream));
+    HIPCHK(hipMemcpyAsync(b.prev, labels, n * sizeof(int32_t), hipMemcpyDeviceToDevice, stream));
   }
-  if (hipStreamSynchronize(stream) != hipSuccess) return fail(OFM_E_HIP);
+  HIPCHK(hipStreamSynchronize(stream));
   if (host_iters) *host_iters = it;
-  cleanup();
   return OFM_OK;
+}
+
+extern "C" ofm_status ofm_kmeans(int64_t n, int dim, int n_clusters, const float* Y,
+                                 const double* host_uniforms, int max_iter, int32_t* labels,
+                                 float* centroids, int32_t* host_iters, hipStream_t stream) {
+  OFMCHK(kmeans_check(n, dim, n_clusters, Y, host_uniforms, max_iter, labels, centroids));
+  const int nbk = kmeans_blocks(n, n_clusters * (dim + 1));
+  const int nbs = kmeans_pick_chunks(n);
+  KmeansBufs b;
+  auto cleanup = [&]() {
+    dev_free(b.d2);
+    dev_free(b.pick);
+    dev_free(b.sums);
+    dev_free(b.prev);
+    dev_free(b.part);
+    dev_free(b.cnew);
+    dev_free(b.changed);
+  };
+  ofm_status st = OFM_OK;
+  if (st == OFM_OK) st = dev_alloc(&b.d2, n);
+  if (st == OFM_OK) st = dev_alloc(&b.pick, 1);
+  if (st == OFM_OK) st = dev_alloc(&b.sums, nbs);
+  if (st == OFM_OK) st = dev_alloc(&b.prev, n);
+  if (st == OFM_OK) st = dev_alloc(&b.part, (size_t)nbk * n_clusters * (dim + 1));
+  if (st == OFM_OK) st = dev_alloc(&b.cnew, (size_t)n_clusters * dim);
+  if (st == OFM_OK) st = dev_alloc(&b.changed, 1);
+  if (st == OFM_OK)
+    st = kmeans_run(n, dim, n_clusters, Y, host_uniforms, max_iter, labels, centroids, host_iters,
+                    stream, b);
+  if (st != OFM_OK) (void)hipStreamSynchronize(stream);  // nothing in flight uses b
+  cleanup();
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// K-means without allocation: the buffers of a run live in one file-scope
+// device array (each device holds its own copy for the life of the process);
+// host code uses its address as hipGetSymbolAddress returns it per device.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[OFM_KMEANS_STATIC_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// the array's device address on the current device, looked up once per device
+ofm_status scratch_address(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return OFM_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return OFM_E_HIP;
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return OFM_OK;
+}
+}  // namespace
+
+extern "C" size_t ofm_kmeans_static_bytes(int64_t n, int dim, int n_clusters) {
+  if (n <= 0 || dim < 1 || n_clusters < 1) return 0;
+  const int nbk = kmeans_blocks(n, n_clusters * (dim + 1));
+  const int nbs = kmeans_pick_chunks(n);
+  return align256((size_t)nbk * n_clusters * (dim + 1) * sizeof(double)) +
+         align256((size_t)nbs * sizeof(double)) + align256((size_t)n * sizeof(float)) +
+         align256((size_t)n * sizeof(int32_t)) +
+         align256((size_t)n_clusters * dim * sizeof(float)) + 2 * 256;
+}
+
+extern "C" ofm_status ofm_kmeans_noalloc(int64_t n, int dim, int n_clusters, const float* Y,
+                                         const double* host_uniforms, int max_iter,
+                                         int32_t* labels, float* centroids, int32_t* host_iters,
+                                         hipStream_t stream) {
+  OFMCHK(kmeans_check(n, dim, n_clusters, Y, host_uniforms, max_iter, labels, centroids));
+  if (ofm_kmeans_static_bytes(n, dim, n_clusters) > (size_t)OFM_KMEANS_STATIC_BYTES)
+    return OFM_E_SHAPE;
+  void* base = nullptr;
+  OFMCHK(scratch_address(&base));
+  const int nbk = kmeans_blocks(n, n_clusters * (dim + 1));
+  const int nbs = kmeans_pick_chunks(n);
+  char* p = static_cast<char*>(base);
+  KmeansBufs b;
+  b.part = reinterpret_cast<double*>(p);
+  p += align256((size_t)nbk * n_clusters * (dim + 1) * sizeof(double));
+  b.sums = reinterpret_cast<double*>(p);
+  p += align256((size_t)nbs * sizeof(double));
+  b.d2 = reinterpret_cast<float*>(p);
+  p += align256((size_t)n * sizeof(float));
+  b.prev = reinterpret_cast<int32_t*>(p);
+  p += align256((size_t)n * sizeof(int32_t));
+  b.cnew = reinterpret_cast<float*>(p);
+  p += align256((size_t)n_clusters * dim * sizeof(float));
+  b.pick = reinterpret_cast<int32_t*>(p);
+  p += 256;
+  b.changed = reinterpret_cast<int*>(p);
+  return kmeans_run(n, dim, n_clusters, Y, host_uniforms, max_iter, labels, centroids, host_iters,
+                    stream, b);
 }
 
 extern "C" ofm_status ofm_select_roots(int variant, int64_t count, const double* coef,

@@ -121,6 +121,8 @@ _SIGS = {
     "ofm_row_normalize": (_I, [_I64, _I, _I, _P, _P, _P]),
     "ofm_kmeans_assign": (_I, [_I64, _I, _I, _P, _P, _P, _P, _P]),
     "ofm_kmeans": (_I, [_I64, _I, _I, _P, _P, _I, _P, _P, _P, _P]),
+    "ofm_kmeans_noalloc": (_I, [_I64, _I, _I, _P, _P, _I, _P, _P, _P, _P]),
+    "ofm_kmeans_static_bytes": (ctypes.c_size_t, [_I64, _I, _I]),
 }
 
 
@@ -578,18 +580,25 @@ def kmeans_assign(Y, centroids, want_dist: bool = False, stream=None):
     return (labels, d2) if want_dist else labels
 
 
-def kmeans(Y, n_clusters: int, uniforms, max_iter: int = 300, stream=None):
-    """K-means++ seeded by ``uniforms`` then Lloyd; returns (labels, centroids, iters)."""
+def kmeans(Y, n_clusters: int, uniforms, max_iter: int = 300, stream=None, labels=None,
+           centroids=None, noalloc: bool = False):
+    """K-means++ seeded by ``uniforms`` then Lloyd; returns (labels, centroids,
+    iters).  ``labels`` / ``centroids``: optional output tensors.  ``noalloc``:
+    ofm_kmeans_noalloc (the library allocates nothing; its buffers are a
+    fixed device array shared by every call on the device)."""
     torch = _torch()
     _dev_block(Y)
     n, dim = Y.shape
     u = np.ascontiguousarray(uniforms, dtype=np.float64)
     if u.shape[0] < n_clusters:
         raise ValueError("need one uniform per cluster")
-    labels = torch.empty(n, dtype=torch.int32, device=Y.device)
-    cent = torch.empty((n_clusters, dim), dtype=torch.float32, device=Y.device)
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=Y.device)
+    if centroids is None:
+        centroids = torch.empty((n_clusters, dim), dtype=torch.float32, device=Y.device)
     iters = ctypes.c_int32()
-    _check(load().ofm_kmeans(n, dim, n_clusters, _ptr(Y), u.ctypes.data_as(ctypes.c_void_p),
-                             max_iter, _ptr(labels), _ptr(cent), ctypes.byref(iters),
-                             _stream(stream)), "ofm_kmeans")
-    return labels, cent, iters.value
+    fn = load().ofm_kmeans_noalloc if noalloc else load().ofm_kmeans
+    _check(fn(n, dim, n_clusters, _ptr(Y), u.ctypes.data_as(ctypes.c_void_p), max_iter,
+              _ptr(labels), _ptr(centroids), ctypes.byref(iters), _stream(stream)),
+           "ofm_kmeans_noalloc" if noalloc else "ofm_kmeans")
+    return labels, centroids, iters.value
