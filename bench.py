@@ -31,8 +31,14 @@ def log(*a):
 
 
 def pass_bytes(name: str, n: int, nnz: int, k: int, esz: int, variant: str, ntiles: int,
-               recur: bool = False) -> float:
-    """Algorithmic HBM bytes of one launch of a pass (each array moved once).
+               recur: bool = False, layout: bool = False) -> float:
+    """HBM bytes of one launch of a pass, each array moved once.  The graph
+    part of an SpMM is counted as the method needs it (layout=False): the
+    pattern-only CSR of an unweighted graph, 4 B per entry, row_ptr (4 B per
+    row) and D^{-1/2} (one value per row in the working precision); with
+    layout=True as this library stores it: packed (column, normalized weight)
+    entries (8 B in FP32, 16 B in FP64), 8 B of offsets and row ids per row
+    and the tile table.
     Without the recurrence the SpMM of X forms the direction in its epilogue
     (f2 with X^T A X advanced by the line search); with it, the SpMM of X runs
     on residual steps only and stores A X, the SpMM of V stores A V, the
@@ -41,8 +47,10 @@ def pass_bytes(name: str, n: int, nnz: int, k: int, esz: int, variant: str, ntil
     f2 at k >= 32 without the recurrence stores A V and forms X^T A V, V^T A V
     in a streaming pass ("other")."""
     B = n * k * esz
-    ent = nnz * (8 if esz == 4 else 16)          # packed (column, weight) stream
-    graph = ent + 8 * n + 4 * (ntiles + 1)       # + position offsets and row ids
+    if layout:
+        graph = nnz * (8 if esz == 4 else 16) + 8 * n + 4 * (ntiles + 1)
+    else:
+        graph = 4 * nnz + 4 * (n + 1) + esz * n
     f2 = variant in ("f2", "tri-f2")
     split = f2 and not recur and k >= 32
     if name == "spmm_x":
@@ -64,9 +72,11 @@ def pass_bytes(name: str, n: int, nnz: int, k: int, esz: int, variant: str, ntil
     return 0.0
 
 
-def cpu_baseline(g, x0, k: int, variant_id: int):
-    """The FP64 oracle on the same graph and X0 (FP32-rounded), init + one
-    loop step (two X updates), on this host's cores."""
+def cpu_baseline(g, x0, k: int, variant_id: int, gpu_iters_to_tol=None, loop_iters: int = 3):
+    """The FP64 oracle on the same graph and X0 (FP32-rounded) on this host:
+    the Laplacian and the set-up step of Algorithm 2 (untimed), then
+    ``loop_iters`` timed loop iterations; s/iteration times the device's
+    iteration count to residual 1e-4 gives an extrapolated time to 1e-4."""
     import numpy as np
     from oracle import ofm_oracle as O
     try:
@@ -79,16 +89,27 @@ def cpu_baseline(g, x0, k: int, variant_id: int):
     x = x0.astype(np.float32).astype(np.float64)
     # the triangular variants run with the descent restart, as on the device
     opts = O.Options(variant=variant_id, restart=O.is_tri(variant_id))
-    t1 = time.perf_counter()
     st, _ = O.init(lap, x, opts)
-    st, _ = O.step(lap, st, opts)
+    t1 = time.perf_counter()
+    first = None
+    for i in range(loop_iters):
+        st, _ = O.step(lap, st, opts)
+        if i == 0:
+            first = st.X
     t2 = time.perf_counter()
-    cpu_baseline.last_x = st.X
-    return {"value": 2.0 / (t2 - t1), "unit": "iters/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": (f"2 X updates (Algorithm 2 set-up step + 1 loop step) of the same workload, "
-                       f"FP64 NumPy/SciPy; {t2 - t1:.1f} s, plus {t1 - t0:.1f} s Laplacian set-up; "
-                       f"SciPy CSR x dense runs on 1 thread, dense products on {threads} BLAS threads")}
+    cpu_baseline.first_step_x = first
+    s_per_it = (t2 - t1) / loop_iters
+    out = {"value": round(loop_iters / (t2 - t1), 4), "unit": "iters/s", "cores": int(threads),
+           "kind": "oracle",
+           "sample": (f"{loop_iters} loop iterations of Algorithm 2 (two products with A each) on "
+                      f"the same graph and X0, FP64 NumPy/SciPy, {t2 - t1:.1f} s; the Laplacian "
+                      f"and the set-up step ({t1 - t0:.1f} s) untimed; SciPy's CSR x dense "
+                      f"product runs on 1 thread, the dense products on {threads} BLAS threads")}
+    if gpu_iters_to_tol:
+        out["extrapolated_time_to_1e-4_s"] = round(gpu_iters_to_tol * s_per_it, 1)
+        out["extrapolated_from"] = (f"{gpu_iters_to_tol} updates (the device's count to residual "
+                                    f"1e-4) x {s_per_it:.2f} s per oracle iteration: extrapolated")
+    return out
 
 
 def read_clocks():
@@ -107,9 +128,9 @@ def read_clocks():
 def batched_vs_plain(variant: str, count: int = 256, plain: bool = True):
     """256 independent SBM graphs (N ~ U{1000..50000}, k ~ U{4,8,16,32}, mean
     degree ~ U[8,32], r = 0.3): wall time until every graph reaches residual
-    1e-4 (checked every 10 iterations), batched FP32 vs a loop of per-graph
-    FP64 solves on the same GPU.  Graph set-up and allocation are outside
-    both timed regions."""
+    1e-4 (checked every 10 iterations), batched FP32 (eager lockstep loop, and
+    the loop replayed as HIP graphs) vs a loop of per-graph FP64 solves on the
+    same GPU.  Graph set-up and allocation are outside every timed region."""
     import numpy as np
     import torch
     from paper_2305_10356_amd import graphs, ofm
@@ -120,30 +141,29 @@ def batched_vs_plain(variant: str, count: int = 256, plain: bool = True):
     laps = [ofm.Laplacian(g.row_ptr, g.col_idx) for g, _ in gl]
     ks = [sp["k"] for sp in specs]
     tri = variant.startswith("tri")
-    B = ofm.Batch(laps, ks, variant=variant, precision=ofm.OFM_FP32, max_iter=3000,
-                  check_every=10, tol=1e-4, restart=tri)
-    Xs = [torch.tensor(x0.astype(np.float32), device="cuda") for _, x0 in gl]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st_b = B.solve(Xs)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    tpw, cand, escalated = B.schedule()
-    loop_ms, finish_ms = B.phases()
-    B.close()
-    # the same with A X by recurrence between residual checks
-    Br = ofm.Batch(laps, ks, variant=variant, precision=ofm.OFM_FP32, max_iter=3000,
-                   check_every=10, tol=1e-4, restart=tri, recur=True)
-    Xr = [torch.tensor(x0.astype(np.float32), device="cuda") for _, x0 in gl]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st_r = Br.solve(Xr)
-    torch.cuda.synchronize()
-    t_rec = time.perf_counter() - t0
-    _, _, esc_r = Br.schedule()
-    loop_r, finish_r = Br.phases()
-    Br.close()
-    del Xr
+
+    def batched(graph=False, recur=False):
+        B = ofm.Batch(laps, ks, variant=variant, precision=ofm.OFM_FP32, max_iter=3000,
+                      check_every=10, tol=1e-4, restart=tri, recur=recur, graph=graph)
+        Xs = [torch.tensor(x0.astype(np.float32), device="cuda") for _, x0 in gl]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = B.solve(Xs)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tpw, cand, esc = B.schedule()
+        loop_ms, finish_ms = B.phases()
+        rec = {"s": round(dt, 4), "converged": int(sum(s["converged"] for s in st)),
+               "max_iters": int(max(s["iters"] for s in st)), "escalated_to_fp64": esc,
+               "tiles_per_wave": tpw, "schedule_candidates_ms": [round(x, 3) for x in cand],
+               "phase_ms": {"fp32_loop": round(loop_ms, 1), "fp64_finish": round(finish_ms, 1)},
+               "graph_replays": B.replays}
+        B.close()
+        return rec, st
+
+    eager, st_b = batched()
+    replayed, _ = batched(graph=True)
+    recur, _ = batched(recur=True)
     st_p, t_plain = [{"converged": 0, "iters": 0}], float("nan")
     if plain:
         wss = [ofm.Workspace(lap, k, variant=variant, precision=ofm.OFM_FP64, max_iter=3000,
@@ -156,24 +176,18 @@ def batched_vs_plain(variant: str, count: int = 256, plain: bool = True):
         t_plain = time.perf_counter() - t0
         for ws in wss:
             ws.close()
+    best = min(eager["s"], replayed["s"])
     return {
         "graphs": count, "sum_n": int(sum(g.n for g, _ in gl)),
         "sum_nnz": int(sum(g.nnz for g, _ in gl)),
-        "batched_fp32_s": round(t_batch, 4), "plain_fp64_loop_s": round(t_plain, 4),
-        "speedup": round(t_plain / t_batch, 2),
-        "batched_converged": int(sum(s["converged"] for s in st_b)),
+        "batched_fp32_s": best,
+        "batched_form": "graph-replayed" if replayed["s"] <= eager["s"] else "eager",
+        "plain_fp64_loop_s": round(t_plain, 4),
+        "speedup": round(t_plain / best, 2),
         "plain_converged": int(sum(s["converged"] for s in st_p)),
-        "batched_max_iters": int(max(s["iters"] for s in st_b)),
         "plain_max_iters": int(max(s["iters"] for s in st_p)),
-        "batched_tiles_per_wave": tpw, "schedule_candidates_ms": [round(x, 3) for x in cand],
-        "batched_escalated_to_fp64": escalated,
-        "batched_phase_ms": {"fp32_loop": round(loop_ms, 1), "fp64_finish": round(finish_ms, 1)},
-        "batched_recur_s": round(t_rec, 4),
-        "batched_recur_converged": int(sum(s["converged"] for s in st_r)),
-        "batched_recur_max_iters": int(max(s["iters"] for s in st_r)),
-        "batched_recur_escalated_to_fp64": esc_r,
-        "batched_recur_phase_ms": {"fp32_loop": round(loop_r, 1), "fp64_finish": round(finish_r, 1)},
-        "speedup_recur": round(t_plain / t_rec, 2),
+        "eager": eager, "graph_replayed": replayed, "recur_ax": recur,
+        "speedup_recur": round(t_plain / recur["s"], 2),
         "batched_not_converged": [
             {"graph": i, "n": gl[i][0].n, "k": ks[i], "relres": st_b[i]["relres"]}
             for i in range(count) if not st_b[i]["converged"]],
@@ -271,6 +285,11 @@ def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10
         "grouped_order": grouped,
         "check_every": check_every,
         "total_solve_s": round(sum(r["solve_s"] for r in stages_out), 4),
+        # end to end: the solves plus each stage's Laplacian set-up and, for the
+        # grouped order, the k-means that supplies the grouping (the warm-start
+        # rows drawn on the host are the same in every mode and left out)
+        "total_with_setup_s": round(sum(r["solve_s"] + r.get("laplacian_s", 0.0) +
+                                        r.get("labels_s", 0.0) for r in stages_out), 4),
         "all_converged": all(r["converged"] == 1 for r in stages_out),
         "stages": stages_out,
     }
@@ -394,6 +413,8 @@ def main():
     ap.add_argument("--postprocess-only", action="store_true",
                     help="solve the 2M-node graph to residual 1e-4, then time only the "
                          "post-processing (row normalisation, K-means); prints its JSON")
+    ap.add_argument("--details", default=os.path.join(ROOT, "gpurun_out", "bench_details.json"),
+                    help="file for the per-stage and per-variant detail (empty: none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -475,7 +496,7 @@ def main():
         ws.step(X)
     # per-pass breakdown: a separate run with events around every pass (the
     # events themselves cost about 2% of a step, so the timed loop below
-    # brackets only the dominant pass)
+    # brackets only the two products with A)
     breakdown_steps = 50
     torch.cuda.synchronize()
     ws.timing(reset=True)
@@ -496,10 +517,12 @@ def main():
             passes[name]["alg_bytes"] = int(b)
             passes[name]["alg_GBs"] = round(b / (avg_ms * 1e-3) / 1e9, 1)
     dom = max((p for p in passes if "alg_bytes" in passes[p]), key=lambda p: per_pass[p][0])
+    spmms = [p for p in ("spmm_x", "spmm_v") if p in passes]
 
-    # the timed region: wall time for `value`, HIP events around the dominant
-    # pass (on the stream it is launched on) for the roofline
-    ws.set_timing([dom])
+    # the timed region: wall time for `value`, HIP events around the products
+    # with A (on the stream they are launched on) for the roofline
+    timed = sorted(set(spmms + [dom]))
+    ws.set_timing(timed)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -507,28 +530,44 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ws.set_timing(False)
-    dom_ms, dom_cnt = ws.timing(reset=True)[dom]
+    tm = ws.timing(reset=True)
     stats = ws.stats()
     ms_per_step = 1e3 * elapsed / args.steps
     value = args.steps / elapsed
-    dom_avg_ms = dom_ms / dom_cnt
-    dom_bytes = pass_bytes(dom, n, nnz, k, 4, args.variant, ntiles, args.recur)
-    achieved = round(dom_bytes / (dom_avg_ms * 1e-3) / 1e9, 1)
+
+    def launch_roof(p):
+        ms, cnt = tm[p]
+        avg = ms / cnt
+        alg = pass_bytes(p, n, nnz, k, 4, args.variant, ntiles, args.recur)
+        lay = pass_bytes(p, n, nnz, k, 4, args.variant, ntiles, args.recur, layout=True)
+        ach = alg / (avg * 1e-3) / 1e9
+        return {"launches": cnt, "avg_us": round(1e3 * avg, 2), "alg_bytes_per_launch": int(alg),
+                "achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+                "layout_bytes_per_launch": int(lay),
+                "layout_GBs": round(lay / (avg * 1e-3) / 1e9, 1)}
+
     from paper_2305_10356_amd import profiling
     traffic = profiling.read_traffic(os.path.join(
         ROOT, "profiles", f"pmc_traffic_ofm_step_{args.variant}_dcsbm_n2m_k32_fp32.md"))
     # the counters were taken with the hot/cold gathers; another policy moves other bytes
     if args.n is not None or args.recur or stats["gather"] != ofm.GATHER_HOT_COLD:
         traffic = {}
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": int(traffic[dom]) if dom in traffic else None,
-                "kernel": dom, "launches": dom_cnt, "avg_us": round(1e3 * dom_avg_ms, 2),
-                "alg_bytes_per_launch": int(dom_bytes)}
-    log(f"headline {args.variant}: {value:.1f} it/s, {ms_per_step:.3f} ms/step; "
-        f"{dom} {1e3 * dom_avg_ms:.1f} us; passes {passes}")
+    d = launch_roof(dom)
+    roofline = {"bound": "hbm", "achieved": d["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": d["frac"], "traffic": int(traffic[dom]) if dom in traffic else None,
+                "kernel": dom, "launches": d["launches"], "avg_us": d["avg_us"],
+                "alg_bytes_per_launch": d["alg_bytes_per_launch"],
+                "layout_bytes_per_launch": d["layout_bytes_per_launch"]}
+    for p in spmms:
+        r = launch_roof(p)
+        r["traffic"] = int(traffic[p]) if p in traffic else None
+        roofline[p] = r
+    log(f"headline {args.variant}: {value:.1f} it/s, {ms_per_step:.3f} ms/step; roofline {roofline}; "
+        f"passes {passes}")
 
     extras = {}
+    summary = {}
+    iters_to_tol = None
     if not args.no_extras:
         # SpMM alone (Y = A Z), FP32
         Z = torch.randn(n, k, device=dev)
@@ -543,12 +582,13 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        b = 8 * nnz + 8 * n + 2 * n * k * 4
+        b = 4 * nnz + 8 * n + 2 * n * k * 4
         extras["spmm_apply_fp32"] = {"avg_us": round(1e3 * ms, 1), "alg_bytes": b,
                                      "alg_GBs": round(b / (ms * 1e-3) / 1e9, 1)}
         del Z, Y
         extras["spmm_locality_ladder"] = spmm_locality_ladder(g, k)
-        # the other variants, and the FP64 plain form
+        # the other variants, and the FP64 plain form; the triangular variants
+        # run with the descent restart (outside Algorithm 2, see the key names)
         for v, prec in (("tri-f1", ofm.OFM_FP32), ("f2", ofm.OFM_FP32), ("tri-f2", ofm.OFM_FP32),
                         ("f1", ofm.OFM_FP64)):
             if v == args.variant and prec == ofm.OFM_FP32:
@@ -562,7 +602,8 @@ def main():
             for _ in range(50):
                 w2.step(X2)
             torch.cuda.synchronize()
-            key = f"{v}_{'fp32' if prec == ofm.OFM_FP32 else 'fp64'}_iters_per_s"
+            tag = "_restart" if v.startswith("tri") else ""
+            key = f"{v}{tag}_{'fp32' if prec == ofm.OFM_FP32 else 'fp64'}_iters_per_s"
             extras[key] = round(50 / (time.perf_counter() - t1), 1)
             w2.close()
             del X2
@@ -655,30 +696,49 @@ def main():
         extras["solve_to_1e-4"] = {"seconds": round(time.perf_counter() - t1, 3),
                                    "iters": st3["iters"], "relres": st3["relres"],
                                    "converged": st3["converged"]}
+        if st3["converged"]:
+            iters_to_tol = int(st3["iters"])
+        summary["solve_to_1e-4_s"] = extras["solve_to_1e-4"]["seconds"]
         if not args.no_batched:
-            extras["batched_vs_plain"] = batched_vs_plain(args.variant)
+            bvp = batched_vs_plain(args.variant)
+            extras["batched_vs_plain"] = bvp
+            summary.update({"batched_fp32_s": bvp["batched_fp32_s"],
+                            "batched_form": bvp["batched_form"],
+                            "plain_fp64_loop_s": bvp["plain_fp64_loop_s"],
+                            "speedup": bvp["speedup"],
+                            "batched_converged": f"{bvp['eager']['converged']}/{bvp['graphs']}",
+                            "plain_converged": f"{bvp['plain_converged']}/{bvp['graphs']}"})
         if not args.no_streaming:
             extras["streaming_warm_start"] = streaming_c4(args.variant)
             extras["streaming_warm_start_recur"] = streaming_c4(args.variant, recur=True)
             extras["streaming_warm_start_grouped"] = streaming_c4(args.variant, grouped=True)
             extras["streaming_warm_start_grouped_recur"] = streaming_c4(args.variant, recur=True,
                                                                         grouped=True)
+            sw = extras["streaming_warm_start"]
+            summary["stream_total_s"] = sw["total_solve_s"]
+            summary["stream_total_with_setup_s"] = sw["total_with_setup_s"]
+            summary["stream_all_converged"] = sw["all_converged"]
         extras["postprocess"] = postprocess(X3, k)
         extras["grouped_order"] = grouped_order(g.row_ptr, g.col_idx, X3, k, x0, args.variant,
                                                 g.labels)
         extras["laplacian_build_s"] = round(t_lap, 3)
         extras["csr_upload_s"] = round(t_up, 3)
         del X3
+        for key in ("tri-f1_restart_fp32_iters_per_s", "f2_fp32_iters_per_s",
+                    "tri-f2_restart_fp32_iters_per_s", "f1_fp64_iters_per_s"):
+            if key in extras:
+                summary[key] = extras[key]
+        summary["recur_ax_iters_per_s"] = extras["recur_ax"]["iters_per_s"]
 
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         from oracle import ofm_oracle as O
         vid = {"f1": O.F1, "tri-f1": O.TRI_F1, "f2": O.F2, "tri-f2": O.TRI_F2}[args.variant]
-        cpu = cpu_baseline(g, x0, k, vid)
-        # the error of the device path against the oracle on the same two
-        # updates, per precision
-        xo = cpu_baseline.last_x
+        cpu = cpu_baseline(g, x0, k, vid, gpu_iters_to_tol=iters_to_tol)
+        # the error of the device path against the oracle on the same first
+        # two updates (set-up step + one loop iteration), per precision
+        xo = cpu_baseline.first_step_x
         prec_err = {}
         for name, prec in (("fp32", ofm.OFM_FP32), ("fp64", ofm.OFM_FP64)):
             w8, X8 = make(args.variant, prec)
@@ -708,16 +768,20 @@ def main():
         "config": {"workload": f"dcsbm N={n} k={k} mean-degree 25 power-law 2.5 r=0.5 (nnz={nnz})",
                    "variant": args.variant, "precision": "fp32 passes, fp64 k x k products",
                    "check_every": 10, "recur_ax": bool(args.recur),
-                   "gather": {1: "default", 2: "hot/cold"}[stats["gather"]], "graph": gstats},
+                   "gather": {1: "default", 2: "hot/cold"}[stats["gather"]]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        **summary,
         "passes": passes,
         "relres_last_check": stats["relres"],
-        "clocks": read_clocks(),
-        "extras": extras,
     }
+    details = {"graph": gstats, "clocks": read_clocks(), "extras": extras}
+    if args.details:
+        os.makedirs(os.path.dirname(os.path.abspath(args.details)), exist_ok=True)
+        with open(args.details, "w") as f:
+            json.dump({"headline": out, **details}, f)
+        out["details_file"] = os.path.relpath(args.details, ROOT)
     print(json.dumps(out), flush=True)
-
 
 if __name__ == "__main__":
     main()

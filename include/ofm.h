@@ -343,7 +343,7 @@ ofm_status ofm_select_roots(int variant, int64_t count, const double* coef, doub
  * OFM_FP32_BF16X; variant, max_iter, check_every, tol, restart, first_step,
  * recur, freeze_eps; graph = 1 runs the lockstep loop of ofm_batch_solve, after
  * the schedule has been chosen, as replays of one HIP graph per check_every
- * updates of every graph, and the FP64 finishing solves as graph replays too).
+ * updates of every graph; the FP64 finishing solves always run eagerly).
  * Allocates the per-graph state.  The block schedule (blocks per graph, each
  * graph's blocks on one XCD) is chosen among a few candidates by timing the
  * first iterations of every solve.

@@ -1811,6 +1811,7 @@ static ofm_status finish_fp64(ofm_laplacian L, int k, const ofm_opts& o, int64_t
   o64.max_iter = (int)(o.max_iter - used);
   o64.first_step = 0;
   o64.recur = 0;
+  o64.graph = 0;   // eager: no graph captures from the concurrent finishing threads
   o64.gather = 1;  // no timing runs on the shared device from the finishing threads
   ofm_workspace ws = nullptr;
   ofm_status es = ofm_workspace_create(L, k, &o64, &ws);

@@ -76,16 +76,19 @@ def test_batch_converges_each_graph(batch_graphs, variant, recur):
         assert rr == pytest.approx(s["relres"], rel=0.05, abs=2e-6), (g.n, k, rr, s["relres"])
 
 
-def test_batch_escalates_fp32_straggler(lib):
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_escalates_fp32_straggler(lib, graph):
     # member 64 of the 256-graph workload (N=39,756, k=16, mean degree 8.1):
     # its FP32 iteration levels off near residual 1.2e-4, so the batch finishes
-    # it in FP64 from the FP32 iterate
+    # it in FP64 from the FP32 iterate (also when the lockstep loop is replayed
+    # as HIP graphs)
     from paper_2305_10356_amd import ofm
     specs = graphs.batched_graph_specs(256)
     members = [specs[64], specs[0], specs[1]]
     gl = [graphs.batched_graph(sp) for sp in members]
     laps = [ofm.Laplacian(g.row_ptr, g.col_idx) for g, _ in gl]
-    B = ofm.Batch(laps, [sp["k"] for sp in members], variant="f1", max_iter=3000, tol=1e-4)
+    B = ofm.Batch(laps, [sp["k"] for sp in members], variant="f1", max_iter=3000, tol=1e-4,
+                  graph=graph)
     Xs = [torch.tensor(x0.astype(np.float32), device="cuda") for _, x0 in gl]
     st = B.solve(Xs)
     tpw, ms, esc = B.schedule()
