@@ -237,6 +237,65 @@ def spmm_locality_ladder(g, k: int = 32, windows=(32768, 262144, None), reps: in
     return out
 
 
+def orderings_study(g, x0, k: int, variant: str, names, steps: int = 30, gather=None):
+    """The step on the headline graph stored in other node orders (graph-only
+    preprocessing, no clustering): as generated (random ids), hub-first (ids by
+    degree, descending) and reverse Cuthill-McKee; FP32 and the BF16 gathered
+    copy.  Event-timed products with A and iterations/s per order."""
+    import numpy as np
+    import torch
+    from paper_2305_10356_amd import graphs, ofm
+    out = {}
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    for name in names:
+        t0 = time.perf_counter()
+        order = {"random": None, "hub-first": graphs.hub_first_order,
+                 "rcm": graphs.rcm_order}[name]
+        order = None if order is None else order(g)
+        t_order = time.perf_counter() - t0
+        gg = g if order is None else graphs.relabel(g, order)
+        xx = x0 if order is None else x0[order]
+        # locality of the order: share of entries within 32768 ids (a 4 MB
+        # window of X rows) of their row
+        if order is None:
+            span = np.abs(rows - g.col_idx)
+        else:
+            inv = np.empty(g.n, dtype=np.int64)
+            inv[order] = np.arange(g.n)
+            span = np.abs(inv[rows] - inv[g.col_idx])
+        near = float(np.mean(span < 32768))
+        lap = ofm.Laplacian(gg.row_ptr, gg.col_idx)
+        rec = {"order_s": round(t_order, 2), "entries_within_4MB_window": round(near, 4)}
+        for pname, prec in (("fp32", ofm.OFM_FP32), ("bf16x", ofm.OFM_FP32_BF16X)):
+            ws = ofm.Workspace(lap, k, variant=variant, precision=prec, check_every=10,
+                               restart=variant.startswith("tri"),
+                               gather=ofm.GATHER_DEFAULT if prec != ofm.OFM_FP32 else
+                               (ofm.GATHER_AUTO if gather is None else gather))
+            X = torch.as_tensor(xx, dtype=torch.float32, device="cuda").contiguous()
+            ws.init(X)
+            for _ in range(5):
+                ws.step(X)
+            ws.set_timing(["spmm_x", "spmm_v"])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(steps):
+                ws.step(X)
+            torch.cuda.synchronize()
+            rate = steps / (time.perf_counter() - t1)
+            ws.set_timing(False)
+            tm = ws.timing(reset=True)
+            rec[pname] = {"iters_per_s": round(rate, 1),
+                          "spmm_x_us": round(1e3 * tm["spmm_x"][0] / max(tm["spmm_x"][1], 1), 1),
+                          "spmm_v_us": round(1e3 * tm["spmm_v"][0] / max(tm["spmm_v"][1], 1), 1),
+                          "gather": {1: "default", 2: "hot/cold"}[ws.stats()["gather"]]}
+            ws.close()
+            del X
+        lap.close()
+        out[name] = rec
+        log(f"ordering {name}: {rec}")
+    return out
+
+
 def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10,
                  cold_stages=(9,), recur: bool = False, check_every: int = 10,
                  grouped: bool = False):
@@ -415,6 +474,9 @@ def main():
                          "post-processing (row normalisation, K-means); prints its JSON")
     ap.add_argument("--details", default=os.path.join(ROOT, "gpurun_out", "bench_details.json"),
                     help="file for the per-stage and per-variant detail (empty: none)")
+    ap.add_argument("--orderings", default=None,
+                    help="comma-separated node orders of the headline graph to time (random, "
+                         "hub-first, rcm); prints their JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -444,6 +506,24 @@ def main():
     gstats = g.stats()
     log(f"graph: {gstats} in {time.perf_counter() - t:.1f} s")
     n, nnz = g.n, g.nnz
+    if args.orderings:
+        if args.copy_calibration:
+            # a plain 256 MiB device copy: counter calibration (as below)
+            src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            for _ in range(5):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
+        print(json.dumps({"workload": f"dcsbm N={n} k={k} (nnz={nnz}) in other node orders",
+                          "orderings": orderings_study(g, x0, k, args.variant,
+                                                       args.orderings.split(","),
+                                                       steps=args.steps,
+                                                       gather={"auto": None,
+                                                               "default": ofm.GATHER_DEFAULT,
+                                                               "hot-cold": ofm.GATHER_HOT_COLD}[
+                                                           args.gather])}), flush=True)
+        return
 
     torch.cuda.synchronize()
     t = time.perf_counter()

@@ -378,6 +378,42 @@ def dcsbm_powerlaw(sizes: Sequence[int], dbar: float, r: float, rng: np.random.G
     return _finish(n, u, v, labels, rng, meta, permute=permute)
 
 
+def relabel(g: Graph, order: np.ndarray) -> Graph:
+    """The same graph with old node ``order[i]`` renamed ``i`` (``order`` a
+    permutation of 0..n-1): rows taken in that order, column ids mapped, each
+    row's columns sorted.  A node order is a storage choice, not part of the
+    method (rows of X are permuted with it)."""
+    n = g.n
+    order = np.asarray(order, dtype=np.int64)
+    inv = np.empty(n, dtype=np.int64)
+    inv[order] = np.arange(n, dtype=np.int64)
+    deg = np.diff(g.row_ptr).astype(np.int64)[order]
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(deg, out=rp[1:])
+    src = np.repeat(g.row_ptr[order].astype(np.int64) - rp[:-1], deg) + np.arange(rp[-1])
+    key = np.repeat(np.arange(n, dtype=np.int64) * n, deg) + inv[g.col_idx[src]]
+    key.sort()
+    cols = key % n
+    meta = dict(g.meta)
+    meta["relabeled"] = True
+    return Graph(n=n, row_ptr=rp.astype(np.int32), col_idx=cols.astype(np.int32),
+                 labels=g.labels[order], meta=meta)
+
+
+def hub_first_order(g: Graph) -> np.ndarray:
+    """Nodes by degree, descending (ties by id): the rows gathered most often
+    get the smallest ids, so they share memory pages."""
+    return np.argsort(-np.diff(g.row_ptr).astype(np.int64), kind="stable")
+
+
+def rcm_order(g: Graph) -> np.ndarray:
+    """Reverse Cuthill-McKee order of the (symmetric) pattern (SciPy)."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+    S = sp.csr_matrix((np.ones(g.nnz, dtype=np.int8), g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    return np.asarray(reverse_cuthill_mckee(S, symmetric_mode=True), dtype=np.int64)
+
+
 def initial_x(n: int, k: int, rng: np.random.Generator) -> np.ndarray:
     """X0 with i.i.d. N(0, 1/n) entries, FP64, row-major n x k."""
     return rng.standard_normal((n, k)) / math.sqrt(n)

@@ -116,3 +116,26 @@ def test_warm_start_rows():
     x = graphs.warm_start(old, 5000, 4, np.random.default_rng(2))
     np.testing.assert_array_equal(x[:100], old)
     assert abs(x[100:].var() * 5000 - 1.0) < 0.05
+
+
+def test_relabel_is_an_isomorphism():
+    from paper_2305_10356_amd import graphs as G
+    g, _ = G.workload("sbm-n1000-k8")
+    for order in (G.hub_first_order(g), G.rcm_order(g),
+                  np.random.default_rng(3).permutation(g.n)):
+        h = G.relabel(g, order)
+        assert h.n == g.n and h.nnz == g.nnz
+        inv = np.empty(g.n, dtype=np.int64)
+        inv[order] = np.arange(g.n)
+        # every edge (u, v) of g is the edge (inv u, inv v) of h, and back
+        rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+        e_g = set(zip(inv[rows].tolist(), inv[g.col_idx].tolist()))
+        rows_h = np.repeat(np.arange(h.n), np.diff(h.row_ptr))
+        e_h = set(zip(rows_h.tolist(), h.col_idx.tolist()))
+        assert e_g == e_h
+        for i in range(h.n):
+            c = h.col_idx[h.row_ptr[i]:h.row_ptr[i + 1]]
+            assert np.all(np.diff(c) > 0)
+        assert np.array_equal(h.labels, g.labels[order])
+    deg = np.diff(G.relabel(g, G.hub_first_order(g)).row_ptr)
+    assert np.all(np.diff(deg) <= 0)
