@@ -412,25 +412,32 @@ def grouped_order(row_ptr, col_idx, X, k: int, x0, variant: str, planted):
     lapg = ofm.Laplacian(row_ptr, col_idx, groups=lab)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    ws = ofm.Workspace(lapg, k, variant=variant, precision=ofm.OFM_FP32, check_every=10,
-                       restart=variant.startswith("tri"))
-    Xg = torch.as_tensor(x0, dtype=torch.float32, device="cuda").contiguous()
-    ws.init(Xg)
-    for _ in range(5):
-        ws.step(Xg)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(50):
-        ws.step(Xg)
-    torch.cuda.synchronize()
-    rate = 50 / (time.perf_counter() - t)
-    ws.set_timing(True)
-    for _ in range(20):
-        ws.step(Xg)
-    ws.set_timing(False)
-    tm = ws.timing(reset=True)
-    st = ws.stats()
-    ws.close()
+    def timed_rate(prec):
+        ws = ofm.Workspace(lapg, k, variant=variant, precision=prec, check_every=10,
+                           restart=variant.startswith("tri"),
+                           gather=ofm.GATHER_AUTO if prec == ofm.OFM_FP32 else
+                           ofm.GATHER_DEFAULT)
+        Xg = torch.as_tensor(x0, dtype=torch.float32, device="cuda").contiguous()
+        ws.init(Xg)
+        for _ in range(5):
+            ws.step(Xg)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(50):
+            ws.step(Xg)
+        torch.cuda.synchronize()
+        rate = 50 / (time.perf_counter() - t)
+        ws.set_timing(True)
+        for _ in range(20):
+            ws.step(Xg)
+        ws.set_timing(False)
+        tm = ws.timing(reset=True)
+        st = ws.stats()
+        ws.close()
+        return rate, tm, st
+
+    rate, tm, st = timed_rate(ofm.OFM_FP32)
+    rate_b, tm_b, _ = timed_rate(ofm.OFM_FP32_BF16X)
     lapg.close()
     # share of nodes whose cluster's majority planted block is their own
     agree = 0
@@ -443,7 +450,10 @@ def grouped_order(row_ptr, col_idx, X, k: int, x0, variant: str, planted):
             "labels_s": round(t1 - t0, 4), "lloyd_iters": int(km_iters),
             "label_purity": round(float(agree) / len(lab), 4),
             "laplacian_with_upload_s": round(t2 - t1, 3),
-            "gather": {1: "default", 2: "hot/cold"}[st["gather"]]}
+            "gather": {1: "default", 2: "hot/cold"}[st["gather"]],
+            "bf16_gather": {"iters_per_s": round(rate_b, 1),
+                            "pass_us": {p: round(1e3 * v[0] / v[1], 1)
+                                        for p, v in tm_b.items() if v[1]}}}
 
 
 def main():
@@ -453,6 +463,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--variant", default="f1", choices=["f1", "tri-f1", "f2", "tri-f2"])
     ap.add_argument("--n", type=int, default=None, help="override N (same recipe)")
+    ap.add_argument("--k", type=int, default=32, choices=[4, 8, 16, 32, 64],
+                    help="override k, the width of X (same graph)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -499,10 +511,12 @@ def main():
         return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    k = 32
+    k = args.k
     log("generating graph ...")
     t = time.perf_counter()
     g, x0 = graphs.workload("dcsbm-n2m-k32", n=args.n)
+    if k != x0.shape[1]:
+        x0 = graphs.initial_x(g.n, k, np.random.default_rng([3, 2, k]))
     gstats = g.stats()
     log(f"graph: {gstats} in {time.perf_counter() - t:.1f} s")
     n, nnz = g.n, g.nnz
@@ -630,7 +644,7 @@ def main():
     traffic = profiling.read_traffic(os.path.join(
         ROOT, "profiles", f"pmc_traffic_ofm_step_{args.variant}_dcsbm_n2m_k32_fp32.md"))
     # the counters were taken with the hot/cold gathers; another policy moves other bytes
-    if args.n is not None or args.recur or stats["gather"] != ofm.GATHER_HOT_COLD:
+    if args.n is not None or args.k != 32 or args.recur or stats["gather"] != ofm.GATHER_HOT_COLD:
         traffic = {}
     d = launch_roof(dom)
     roofline = {"bound": "hbm", "achieved": d["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",

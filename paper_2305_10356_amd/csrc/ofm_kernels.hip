@@ -431,6 +431,104 @@ __device__ inline void tile_gram(const T* Pt, const T* Qt, GramAcc<T, KP>& acc,
   }
 }
 
+// k x k products of a dense pass with the output tiles dealt to the waves of
+// the workgroup (used where one wave cannot hold every FP64 accumulator at a
+// useful occupancy, FP32 k = 64).  The WPB waves stage their row tiles in LDS
+// side by side; product p of the pass's list -- group 0's 16 x 16 tiles, then
+// group 1's, a symmetric group listing its upper triangle -- belongs to wave
+// p % WPB, which sums it over the rows of every staged tile.  Group g multiplies
+// staged tile sa_g (columns) by staged tile sb_g (rows of the output).
+template <typename T, int KP, int WPB>
+struct SplitGram {
+  using G = Geo<T, KP>;
+  static constexpr int NT = G::NT;
+  static constexpr int PER = (NT * (NT + 1) / 2 + NT * NT + WPB - 1) / WPB;
+  d4 acc[PER];
+  int offa[PER], offb[PER];  // LDS element offsets within a wave's staging area
+  int grp[PER], ti[PER], tj[PER];
+  int nprod = 0;
+
+  __device__ void setup(int wave, int lane, int sa0, int sb0, bool sym0, int sa1, int sb1,
+                        bool sym1, int ngroups) {
+    const int n0 = sym0 ? NT * (NT + 1) / 2 : NT * NT;
+    const int n1 = ngroups > 1 ? (sym1 ? NT * (NT + 1) / 2 : NT * NT) : 0;
+    nprod = n0 + n1;
+    const int f = lane & 15;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+      const int p = q * WPB + wave;
+      int g = 0, i = 0, jj = 0;
+      if (p < nprod) {
+        g = p < n0 ? 0 : 1;
+        int r = p < n0 ? p : p - n0;
+        const bool sym = g == 0 ? sym0 : sym1;
+        if (sym) {
+          while (r >= NT - i) {
+            r -= NT - i;
+            ++i;
+          }
+          jj = i + r;
+        } else {
+          i = r / NT;
+          jj = r % NT;
+        }
+      }
+      grp[q] = p < nprod ? g : -1;
+      ti[q] = i;
+      tj[q] = jj;
+      const int sa = g == 0 ? sa0 : sa1, sb = g == 0 ? sb0 : sb1;
+      offa[q] = sa * G::TILE_ELEMS + 16 * i + f;
+      offb[q] = sb * G::TILE_ELEMS + 16 * jj + f;
+    }
+  }
+
+  // every staged tile of the workgroup (waves' areas wave_elems apart)
+  __device__ void accumulate(const T* stage0, int wave_elems, int lane) {
+    for (int w = 0; w < WPB; ++w) {
+      const T* tb = stage0 + w * wave_elems;
+#pragma unroll
+      for (int s4 = 0; s4 < 4 * G::NSUB; ++s4) {
+        const int r = (4 * s4 + (lane >> 4)) * G::LDST;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          if (q * WPB >= nprod) continue;
+          if (grp[q] < 0) continue;
+          const double x = (double)tb[r + offa[q]];
+          const double y = (double)tb[r + offb[q]];
+          acc[q] = mma64(x, y, acc[q]);
+        }
+      }
+    }
+  }
+
+  // group g's products into red (KP x KP, row-major; a symmetric group also
+  // fills the lower triangle), then the block copies them to prow[off ..]
+  __device__ void out(int g, bool sym, double* red, double* prow, int off, int lane) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      if (grp[q] != g) continue;
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const int ra = 16 * ti[q] + MF<double>::out_row(lane, qq);
+        const int cb = 16 * tj[q] + (lane & 15);
+        red[ra * KP + cb] = acc[q][qq];
+        if (sym && tj[q] > ti[q]) red[cb * KP + ra] = acc[q][qq];
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < KP * KP; e += blockDim.x) prow[off + e] = red[e];
+    __syncthreads();
+  }
+};
+
+// passes whose products are dealt to the waves (FP32 k = 64)
+template <typename T, int KP, int MODE>
+constexpr bool split_gram_mode() {
+  return sizeof(T) == 4 && KP == 64 &&
+         (MODE == kVPass || MODE == kUpdate || MODE == kGramM || MODE == kUpdateR || MODE == kEF);
+}
+
 template <typename T, int KP>
 __device__ inline void zero_gram(GramAcc<T, KP>& acc) {
   using G = Geo<T, KP>;
@@ -837,15 +935,31 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
   for (int v = 0; v < 3; ++v)
 #pragma unroll
     for (int q = 0; q < G::VECN; ++q) cacc[v][q] = 0.0;
-  d4 gA[G::NT][G::NT], gB[G::NT][G::NT];
+  constexpr bool SPLIT = split_gram_mode<T, KP, MODE>();
+  d4 gA[G::NT][G::NT], gB[G::NT][G::NT];  // per-wave products (unused with SPLIT)
   zero_gram<T, KP>(gA);
   zero_gram<T, KP>(gB);
+  SplitGram<T, KP, WPB> sg;
+  if constexpr (SPLIT) {
+    // (source tiles, symmetry) of the product groups: t0 = 0, t1 = 1, t2 = 2
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    if (MODE == kVPass) sg.setup(wv, lane, 0, 0, true, 1, 0, false, 2);      // P = V^T V, C = X^T V
+    else if (MODE == kEF) sg.setup(wv, lane, 0, 2, false, 1, 2, true, 2);    // E = X^T AV, F = V^T AV
+    else if (MODE == kUpdateR)
+      sg.setup(wv, lane, 0, 0, true, 0, 1, false, (a.flags & kFlagH) ? 2 : 1);  // M [, H = X^T AX]
+    else sg.setup(wv, lane, 0, 0, true, 0, 0, false, 1);                     // M = X^T X
+  }
 
   const int64_t ntiles = (a.n + G::TR - 1) / G::TR;
   const int64_t stride = (int64_t)nblk * WPB;
-  for (int64_t t = (int64_t)brank * WPB + wave; t < ntiles; t += stride) {
+  // per wave: tiles brank * WPB + wave + i * stride.  With the split products
+  // the WPB waves run the loop together (a wave past the last tile stages
+  // zeros) and meet at a barrier before and after the products.
+  for (int64_t tb = (int64_t)brank * WPB; tb < ntiles; tb += stride) {
+    const int64_t t = tb + wave;
+    if (!SPLIT && t >= ntiles) break;
     const int64_t r0 = t * G::TR;
-    const int cnt = (int)((a.n - r0) < G::TR ? (a.n - r0) : G::TR);
+    const int cnt = t >= ntiles ? 0 : (int)((a.n - r0) < G::TR ? (a.n - r0) : G::TR);
 #pragma unroll
     for (int pass = 0; pass < G::NPASS; ++pass) {
       const int gi = pass * G::RPW + g;
@@ -958,6 +1072,13 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
       }
     }
     if (SM::NB == 0) continue;
+    if constexpr (SPLIT) {
+      __syncthreads();
+      sg.accumulate(reinterpret_cast<const T*>(smem + SM::frag_bytes),
+                    SM::wave_bytes / (int)sizeof(T), lane);
+      __syncthreads();
+      continue;
+    }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     if (MODE == kVPass) {
@@ -1015,7 +1136,21 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
   double* red = reinterpret_cast<double*>(smem);
   double* prow = a.partials + (size_t)brank * a.nv;
   const int KK = KP * KP;
-  if (MODE == kVPass) {
+  if constexpr (SPLIT) {
+    if (MODE == kVPass) {
+      sg.out(0, true, red, prow, 0, lane);
+      sg.out(1, false, red, prow, KK, lane);
+      block_vec_out<T, KP, 1>(cacc, red, prow, 2 * KK, wave, lane, WPB);
+    } else if (MODE == kEF) {
+      sg.out(0, false, red, prow, 0, lane);
+      sg.out(1, true, red, prow, KK, lane);
+    } else if (MODE == kUpdateR) {
+      sg.out(0, true, red, prow, 0, lane);
+      if (a.flags & kFlagH) sg.out(1, false, red, prow, KK, lane);
+    } else {
+      sg.out(0, true, red, prow, 0, lane);
+    }
+  } else if (MODE == kVPass) {
     block_gram_out<T, KP, true>(gA, red, prow, 0, wave, lane, WPB);
     block_gram_out<T, KP, false>(gB, red, prow, KK, wave, lane, WPB);
     block_vec_out<T, KP, 1>(cacc, red, prow, 2 * KK, wave, lane, WPB);
@@ -1482,27 +1617,43 @@ __device__ __forceinline__ void residual_body(int variant, double normA2, double
     const double dc = L[c * KP + c];
     for (int r = c + 1 + tid; r < KP; r += 256) L[r * KP + c] /= dc;
     __syncthreads();
-    for (int e = tid; e < KK; e += 256) {
-      const int r = e / KP, q = e % KP;
-      if (r > c && q > c && q <= r) L[r * KP + q] -= L[r * KP + c] * L[q * KP + c];
+    const int m = KP - 1 - c;  // trailing block, lower triangle
+    for (int e = tid; e < m * m; e += 256) {
+      const int r = c + 1 + e / m, q = c + 1 + e % m;
+      if (q <= r) L[r * KP + q] -= L[r * KP + c] * L[q * KP + c];
     }
     __syncthreads();
   }
-  // W = M^{-1} B for B = K then B = H (two triangular solves per column)
+  // With M = L L^T: tr(M^{-1} K) = tr(L^{-1} K L^{-T}) and tr((M^{-1} H)^2) =
+  // ||L^{-1} H L^{-T}||_F^2 (K, H symmetric).  W = L^{-1} B L^{-T} by two
+  // forward substitutions with a transpose between them, each eliminating one
+  // row at a time with every thread updating the rows below.
   double trMK = 0.0, trMH2 = 0.0;
   for (int which = 0; which < 2; ++which) {
     const double* B = which == 0 ? K : H;
-    if (tid < KP) {
-      const int col = tid;
-      for (int r = 0; r < KP; ++r) {          // L y = b
-        double s = B[r * KP + col];
-        for (int q = 0; q < r; ++q) s -= L[r * KP + q] * W[q * KP + col];
-        W[r * KP + col] = s / L[r * KP + r];
+    for (int e = tid; e < KK; e += 256) W[e] = B[e];
+    for (int half = 0; half < 2; ++half) {
+      __syncthreads();
+      for (int q = 0; q < KP; ++q) {
+        const double d = L[q * KP + q];
+        for (int c = tid; c < KP; c += 256) W[q * KP + c] /= d;
+        __syncthreads();
+        for (int e = tid; e < (KP - 1 - q) * KP; e += 256) {
+          const int r = q + 1 + e / KP, c = e % KP;
+          W[r * KP + c] -= L[r * KP + q] * W[q * KP + c];
+        }
+        __syncthreads();
       }
-      for (int r = KP - 1; r >= 0; --r) {     // L^T x = y
-        double s = W[r * KP + col];
-        for (int q = r + 1; q < KP; ++q) s -= L[q * KP + r] * W[q * KP + col];
-        W[r * KP + col] = s / L[r * KP + r];
+      if (half == 0) {
+        // in-place transpose: (L^{-1} B)^T = B L^{-T}
+        for (int e = tid; e < KK; e += 256) {
+          const int r = e / KP, c = e % KP;
+          if (c > r) {
+            const double x = W[r * KP + c];
+            W[r * KP + c] = W[c * KP + r];
+            W[c * KP + r] = x;
+          }
+        }
       }
     }
     __syncthreads();
@@ -1511,10 +1662,7 @@ __device__ __forceinline__ void residual_body(int variant, double normA2, double
       if (tid < KP) part = W[tid * KP + tid];
       trMK = block_sum256(part, buf);
     } else {
-      for (int e = tid; e < KK; e += 256) {
-        const int r = e / KP, q = e % KP;
-        part += W[r * KP + q] * W[q * KP + r];
-      }
+      for (int e = tid; e < KK; e += 256) part += W[e] * W[e];
       trMH2 = block_sum256(part, buf);
     }
     __syncthreads();
