@@ -298,7 +298,7 @@ def orderings_study(g, x0, k: int, variant: str, names, steps: int = 30, gather=
 
 def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10,
                  cold_stages=(9,), recur: bool = False, check_every: int = 10,
-                 grouped: bool = False):
+                 grouped: bool = False, gs=None):
     """Growth stream of 10 snapshots, N = 200k .. 2M, k = 64, mean degree 20,
     r = 0.3: each stage solved to residual 1e-4 (checked every 10 iterations)
     in FP32 from the previous stage's solution (new rows N(0, 1/N_s)), with
@@ -309,9 +309,10 @@ def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10
     import torch
     from paper_2305_10356_amd import graphs, ofm
     from paper_2305_10356_amd.streaming import StreamingSolver
-    t = time.perf_counter()
-    gs = graphs.GrowthStream(n_final=n_final, stages=stages, k=64, dbar=20, r=0.3, seed=4)
-    log(f"growth stream generated in {time.perf_counter() - t:.1f} s")
+    if gs is None:
+        t = time.perf_counter()
+        gs = graphs.GrowthStream(n_final=n_final, stages=stages, k=64, dbar=20, r=0.3, seed=4)
+        log(f"growth stream generated in {time.perf_counter() - t:.1f} s")
     tri = variant.startswith("tri")
     warm = StreamingSolver(64, variant=variant, precision=ofm.OFM_FP32, tol=1e-4,
                            check_every=check_every, max_iter=5000, graph=True, restart=tri,
@@ -352,6 +353,78 @@ def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10
         "all_converged": all(r["converged"] == 1 for r in stages_out),
         "stages": stages_out,
     }
+
+
+def streaming_edges(variant: str = "f1", n: int = 1_000_000, k: int = 32, parts: int = 10,
+                    check_every: int = 10, fixed_iters: int = 2, dbar: float = 48.0,
+                    max_iter: int = 1000):
+    """Edge-sampling stream: the undirected edges of an SBM (N = 1M, k = 32
+    equal blocks, mean degree 48 like the paper's 1M-node streaming graphs,
+    r = 0.3) dealt to ten disjoint parts, stage s the graph of parts 0..s on
+    the nodes touched so far, warm-started from the previous stage (carried
+    rows; new nodes N(0, 1/N_s)).  Two runs: to residual 1e-4 per stage (FP32,
+    graph-replayed loop, at most max_iter updates), and the numerical results'
+    setting of a fixed 2 updates per stage, with the k-means labels of each
+    stage's features scored against the planted blocks (ARI)."""
+    import numpy as np
+    import torch
+    from sklearn.metrics import adjusted_rand_score
+    from paper_2305_10356_amd import graphs, ofm
+    from paper_2305_10356_amd.streaming import StreamingSolver
+    t = time.perf_counter()
+    g = graphs.sbm_plain(graphs.equal_sizes(n, k), dbar, 0.3, np.random.default_rng([7, 1]))
+    es = graphs.EdgeStream(g, parts=parts, seed=7)
+    stage_graphs = [es.stage(s) for s in range(parts)]
+    log(f"edge stream generated in {time.perf_counter() - t:.1f} s")
+    tri = variant.startswith("tri")
+    out = {"workload": f"edge-sampling stream, {parts} parts of an SBM N={n} k={k} "
+                       f"mean-degree {dbar:g} r=0.3, FP32, graph-replayed loop",
+           "variant": variant}
+    for mode in ("tol", "fixed"):
+        sol = StreamingSolver(k, variant=variant, precision=ofm.OFM_FP32,
+                              tol=1e-4 if mode == "tol" else 0.0, check_every=check_every,
+                              max_iter=max_iter if mode == "tol" else fixed_iters,
+                              graph=mode == "tol", restart=tri, seed=7)
+        recs = []
+        ids_prev = None
+        for s, (h, ids) in enumerate(stage_graphs):
+            carry = None if ids_prev is None else graphs.EdgeStream.carry(ids_prev, ids)
+            rec = sol.solve_stage(h.row_ptr, h.col_idx, warm=True, carry=carry)
+            if mode == "fixed":
+                u = np.random.default_rng([7, 3, s]).random(k)
+                lab, _, _ = ofm.kmeans(ofm.row_normalize(sol.X), k, u, max_iter=30)
+                rec["ari"] = round(float(adjusted_rand_score(h.labels, lab.cpu().numpy())), 4)
+                rec["relres"] = sol_residual(sol, h)
+            for key in ("solve_s", "laplacian_s", "xinit_s"):
+                rec[key] = round(rec[key], 4)
+            log(f"edge stream {mode} stage {s}: {rec}")
+            recs.append(rec)
+            ids_prev = ids
+        out[mode] = {"total_solve_s": round(sum(r["solve_s"] for r in recs), 4),
+                     "total_with_setup_s": round(sum(r["solve_s"] + r["laplacian_s"]
+                                                     for r in recs), 4),
+                     "stages": recs}
+    h, _ = stage_graphs[-1]
+    cold = StreamingSolver(k, variant=variant, precision=ofm.OFM_FP32, tol=1e-4,
+                           check_every=check_every, max_iter=max_iter, graph=True,
+                           restart=tri, seed=8)
+    rc = cold.solve_stage(h.row_ptr, h.col_idx, warm=False)
+    out["last_stage_cold"] = {"iters": rc["iters"], "solve_s": round(rc["solve_s"], 4),
+                              "converged": rc["converged"]}
+    out["tol"]["all_converged"] = all(r["converged"] == 1 for r in out["tol"]["stages"])
+    torch.cuda.synchronize()
+    return out
+
+
+def sol_residual(sol, h):
+    """Residual of the solver's current features on stage graph h."""
+    from paper_2305_10356_amd import ofm
+    lap = ofm.Laplacian(h.row_ptr, h.col_idx)
+    ws = ofm.Workspace(lap, sol.k, variant=sol.variant, precision=sol.precision)
+    r = ws.residual(sol.X)["relres"]
+    ws.close()
+    lap.close()
+    return r
 
 
 def postprocess(X, k):
@@ -475,6 +548,8 @@ def main():
                     help="headline loop with A X by recurrence between residual checks")
     ap.add_argument("--streaming-only", action="store_true",
                     help="run only the streaming warm-start workload; prints its JSON")
+    ap.add_argument("--edge-stream-only", action="store_true",
+                    help="run only the edge-sampling streaming workload; prints its JSON")
     ap.add_argument("--gather", default="auto", choices=["auto", "default", "hot-cold"],
                     help="cache policy of the SpMM row gathers of the headline loop (auto: "
                          "timed at workspace creation)")
@@ -489,6 +564,8 @@ def main():
     ap.add_argument("--orderings", default=None,
                     help="comma-separated node orders of the headline graph to time (random, "
                          "hub-first, rcm); prints their JSON")
+    ap.add_argument("--ladder", action="store_true",
+                    help="also time the SpMM with the columns folded into windows of X")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -504,6 +581,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.batched_only:
         print(json.dumps(batched_vs_plain(args.variant, plain=False)), flush=True)
+        return
+    if args.edge_stream_only:
+        print(json.dumps(streaming_edges(args.variant)), flush=True)
         return
     if args.streaming_only:
         print(json.dumps(streaming_c4(args.variant, recur=args.recur, grouped=args.grouped)),
@@ -680,7 +760,8 @@ def main():
         extras["spmm_apply_fp32"] = {"avg_us": round(1e3 * ms, 1), "alg_bytes": b,
                                      "alg_GBs": round(b / (ms * 1e-3) / 1e9, 1)}
         del Z, Y
-        extras["spmm_locality_ladder"] = spmm_locality_ladder(g, k)
+        if args.ladder:
+            extras["spmm_locality_ladder"] = spmm_locality_ladder(g, k)
         # the other variants, and the FP64 plain form; the triangular variants
         # run with the descent restart (outside Algorithm 2, see the key names)
         for v, prec in (("tri-f1", ofm.OFM_FP32), ("f2", ofm.OFM_FP32), ("tri-f2", ofm.OFM_FP32),
@@ -803,15 +884,21 @@ def main():
                             "batched_converged": f"{bvp['eager']['converged']}/{bvp['graphs']}",
                             "plain_converged": f"{bvp['plain_converged']}/{bvp['graphs']}"})
         if not args.no_streaming:
-            extras["streaming_warm_start"] = streaming_c4(args.variant)
-            extras["streaming_warm_start_recur"] = streaming_c4(args.variant, recur=True)
-            extras["streaming_warm_start_grouped"] = streaming_c4(args.variant, grouped=True)
-            extras["streaming_warm_start_grouped_recur"] = streaming_c4(args.variant, recur=True,
-                                                                        grouped=True)
+            gs = graphs.GrowthStream(n_final=2_000_000, stages=10, k=64, dbar=20, r=0.3, seed=4)
+            extras["streaming_warm_start"] = streaming_c4(args.variant, gs=gs)
+            extras["streaming_warm_start_recur"] = streaming_c4(args.variant, recur=True, gs=gs)
+            extras["streaming_warm_start_grouped"] = streaming_c4(args.variant, grouped=True,
+                                                                  gs=gs)
+            del gs
             sw = extras["streaming_warm_start"]
             summary["stream_total_s"] = sw["total_solve_s"]
             summary["stream_total_with_setup_s"] = sw["total_with_setup_s"]
             summary["stream_all_converged"] = sw["all_converged"]
+            ed = streaming_edges(args.variant)
+            extras["streaming_edge_sampling"] = ed
+            summary["edge_stream_total_s"] = ed["tol"]["total_solve_s"]
+            summary["edge_stream_all_converged"] = ed["tol"]["all_converged"]
+            summary["edge_stream_2_updates_ari_last"] = ed["fixed"]["stages"][-1]["ari"]
         extras["postprocess"] = postprocess(X3, k)
         extras["grouped_order"] = grouped_order(g.row_ptr, g.col_idx, X3, k, x0, args.variant,
                                                 g.labels)

@@ -659,6 +659,56 @@ def streaming_snapshots(n_final: int = 2_000_000, stages: int = 10, k: int = 64,
         yield gs.snapshot(s), gs.bounds[s]
 
 
+class EdgeStream:
+    """Edge-sampling stream over a fixed graph: its undirected edges are dealt
+    uniformly at random to ``parts`` disjoint parts, and stage s is the graph
+    of parts 0..s (the streaming comparison of the numerical results section:
+    ten non-overlapping parts of a graph's edges, each stage adding one).
+
+    A stage holds the nodes that have at least one edge so far (a node
+    without edges has no D^{-1/2}), renumbered in the order of their ids in
+    the full graph; ``ids`` maps a stage's rows to full-graph ids.  Stages are
+    nested: every node and edge of stage s is in stage s+1, so a warm start
+    carries the previous rows to the positions ``carry`` returns."""
+
+    def __init__(self, g: Graph, parts: int = 10, seed: int = 6):
+        self.g = g
+        self.parts = int(parts)
+        rows = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+        cols = g.col_idx.astype(np.int64)
+        keep = rows < cols
+        self.u = rows[keep]
+        self.v = cols[keep]
+        self.part = np.random.default_rng([seed, 1]).integers(0, self.parts, size=self.u.shape[0])
+
+    def stage(self, s: int):
+        """(Graph of parts 0..s on its touched nodes, full-graph ids of its rows)."""
+        if not 0 <= s < self.parts:
+            raise ValueError("stage out of range")
+        m = self.part <= s
+        u, v = self.u[m], self.v[m]
+        touched = np.zeros(self.g.n, dtype=bool)
+        touched[u] = True
+        touched[v] = True
+        ids = np.flatnonzero(touched).astype(np.int64)
+        loc = np.full(self.g.n, -1, dtype=np.int64)
+        loc[ids] = np.arange(ids.shape[0], dtype=np.int64)
+        n = int(ids.shape[0])
+        rp, ci = _edges_to_csr(n, loc[u], loc[v])
+        meta = dict(self.g.meta)
+        meta.update({"edge_stream_stage": s, "edge_parts": self.parts})
+        return Graph(n=n, row_ptr=rp.astype(np.int32), col_idx=ci.astype(np.int32),
+                     labels=self.g.labels[ids], meta=meta), ids
+
+    @staticmethod
+    def carry(ids_prev: np.ndarray, ids: np.ndarray) -> np.ndarray:
+        """Positions in a stage of the previous stage's rows."""
+        pos = np.searchsorted(ids, ids_prev)
+        if pos.shape[0] and (pos.max() >= ids.shape[0] or np.any(ids[pos] != ids_prev)):
+            raise ValueError("stages are not nested")
+        return pos
+
+
 def warm_start(x_prev: Optional[np.ndarray], n: int, k: int, rng: np.random.Generator,
                dtype=np.float64) -> np.ndarray:
     """Initial block for a grown graph: the previous solution's rows in place,

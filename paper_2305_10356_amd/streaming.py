@@ -3,10 +3,12 @@
 The numerical results section (comparison on streaming graphs) feeds each
 stage's computed features to the next stage as its initial point; the methods
 then converge in a few iterations because the old features are already close
-to the new ones.  Here a stage is a snapshot of a node-arrival growth process
-(node ids are arrival order, so a snapshot is a prefix of the next one): the
-initial block of stage s keeps the solution rows of stage s-1 in place and
-appends rows N(0, 1/N_s) for the new nodes.
+to the new ones.  A stage here is either a snapshot of a node-arrival growth
+process (node ids are arrival order, so a snapshot is a prefix of the next
+one: the previous rows stay in place and rows N(0, 1/N_s) are appended for
+the new nodes) or a stage of an edge-sampling stream (the graph of the first
+s+1 edge parts on the nodes touched so far: the previous rows go to the
+positions ``carry`` gives and the newly touched nodes get rows N(0, 1/N_s)).
 
 Every stage runs ``ofm_solve`` with the loop captured as HIP graphs of
 check_every updates (``graph=True``); the gather policy of the products with
@@ -67,36 +69,52 @@ class StreamingSolver:
         import torch
         return torch.float64 if self.precision == ofm.OFM_FP64 else torch.float32
 
-    def initial_block(self, n: int, x_prev=None):
-        """Device block for a stage with n nodes: x_prev's rows, then new rows."""
+    def initial_block(self, n: int, x_prev=None, carry=None):
+        """Device block for a stage with n nodes: x_prev's rows (at positions
+        ``carry``, default the first rows), new rows N(0, 1/n) elsewhere."""
         import torch
         n_old = 0 if x_prev is None else int(x_prev.shape[0])
         if n_old > n:
             raise ValueError("a stage cannot drop nodes")
         npdt = np.float64 if self.precision == ofm.OFM_FP64 else np.float32
         X = torch.empty((n, self.k), dtype=self.dtype, device="cuda")
+        fresh = torch.from_numpy(new_rows(n_old, n, self.k, [self.seed, 2, self.stage], npdt))
+        if carry is None:
+            if n_old:
+                X[:n_old].copy_(x_prev)
+            if n > n_old:
+                X[n_old:].copy_(fresh)
+            return X
+        carry = np.asarray(carry, dtype=np.int64)
+        if carry.shape != (n_old,):
+            raise ValueError("carry must give one position per previous row")
+        new = np.ones(n, dtype=bool)
+        new[carry] = False
         if n_old:
-            X[:n_old].copy_(x_prev)
+            X[torch.from_numpy(carry).cuda()] = x_prev
         if n > n_old:
-            X[n_old:].copy_(torch.from_numpy(
-                new_rows(n_old, n, self.k, [self.seed, 2, self.stage], npdt)))
+            X[torch.from_numpy(np.flatnonzero(new)).cuda()] = fresh.cuda()
         return X
 
-    def solve_stage(self, row_ptr, col_idx, warm: bool = True) -> dict:
+    def solve_stage(self, row_ptr, col_idx, warm: bool = True, carry=None) -> dict:
         """Solve the next stage.  ``warm=False`` starts from a fresh random
         block instead (the cold-start comparison); the solver's state still
-        advances to this stage's solution."""
+        advances to this stage's solution.  ``carry``: positions in this stage
+        of the previous stage's rows (default: the first rows)."""
         import torch
         n = int(row_ptr.shape[0] - 1)
         t0 = time.perf_counter()
         groups = None
         if self.grouped and self.labels is not None and warm:
             groups = np.full(n, -1, dtype=np.int32)
-            groups[:self.labels.shape[0]] = self.labels
+            if carry is None:
+                groups[:self.labels.shape[0]] = self.labels
+            else:
+                groups[np.asarray(carry, dtype=np.int64)] = self.labels
         lap = ofm.Laplacian(row_ptr, col_idx, groups=groups)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        X = self.initial_block(n, self.X if warm else None)
+        X = self.initial_block(n, self.X if warm else None, carry if warm else None)
         ws = ofm.Workspace(lap, self.k, variant=self.variant, precision=self.precision,
                            max_iter=self.max_iter, check_every=self.check_every,
                            tol=self.tol, graph=self.graph, restart=self.restart,

@@ -165,3 +165,47 @@ def test_streaming_grouped_order_fp32(lib):
         assert rg["iters"] <= 2 * rp["iters"] + 20
     olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
     assert O.relres(olap, host(grp.X)) == pytest.approx(rg["relres"], rel=0.05, abs=2e-6)
+
+
+@pytest.mark.parametrize("variant,prec", [("f1", "fp64"), ("f2", "fp32")])
+def test_edge_sampling_stream(lib, variant, prec):
+    # ten disjoint edge parts of an SBM, each stage adding one (the nodes
+    # touched so far; the previous rows carried to their new positions): the
+    # carried rows enter the stage unchanged, and every stage from the third
+    # on reaches the tolerance with the oracle's residual of the returned X
+    # matching the device's
+    from paper_2305_10356_amd import ofm
+    from paper_2305_10356_amd.streaming import StreamingSolver
+    g = graphs.sbm_plain(graphs.equal_sizes(6000, 8), 48.0, 0.15, np.random.default_rng([61, 1]))
+    es = graphs.EdgeStream(g, parts=10, seed=61)
+    p = ofm.OFM_FP64 if prec == "fp64" else ofm.OFM_FP32
+    tol = 1e-6 if prec == "fp64" else 1e-4
+    sol = StreamingSolver(8, variant=variant, precision=p, tol=tol, check_every=10,
+                          max_iter=4000, graph=True, seed=61)
+    ids_prev, x_prev = None, None
+    for s in range(10):
+        h, ids = es.stage(s)
+        carry = None if ids_prev is None else graphs.EdgeStream.carry(ids_prev, ids)
+        if carry is not None:
+            X0 = sol.initial_block(h.n, sol.X, carry)
+            np.testing.assert_array_equal(host(X0)[carry], x_prev)
+        rec = sol.solve_stage(h.row_ptr, h.col_idx, warm=True, carry=carry)
+        olap = O.laplacian(h.n, h.row_ptr, h.col_idx)
+        x_prev = host(sol.X)
+        rr = O.relres(olap, x_prev)
+        say(f"edge stage {s}: n={h.n} nnz={h.nnz} iters={rec['iters']} relres={rec['relres']:.2e} "
+            f"oracle={rr:.2e}")
+        assert rec["status"] == 0
+        if s >= 2:
+            assert rec["converged"] == 1
+            # below ~1e-7 the Gram form of the residual is at its rounding floor
+            assert rr == pytest.approx(rec["relres"], rel=0.05, abs=1e-7 if prec == "fp64" else 2e-6)
+        ids_prev = ids
+    # the last stage is the whole graph: warm start from the ninth stage beats
+    # a cold start
+    cold = StreamingSolver(8, variant=variant, precision=p, tol=tol, check_every=10,
+                           max_iter=4000, graph=True, seed=62)
+    h, _ = es.stage(9)
+    rc = cold.solve_stage(h.row_ptr, h.col_idx, warm=False)
+    say(f"last stage warm {sol.records[-1]['iters']} vs cold {rc['iters']} updates")
+    assert sol.records[-1]["iters"] < rc["iters"]

@@ -139,3 +139,36 @@ def test_relabel_is_an_isomorphism():
         assert np.array_equal(h.labels, g.labels[order])
     deg = np.diff(G.relabel(g, G.hub_first_order(g)).row_ptr)
     assert np.all(np.diff(deg) <= 0)
+
+
+def test_edge_stream_stages_are_nested_partitions():
+    from paper_2305_10356_amd import graphs as G
+    g, _ = G.workload("sbm-n1000-k8")
+    es = G.EdgeStream(g, parts=10, seed=3)
+    full = set()
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    for a, b in zip(rows.tolist(), g.col_idx.tolist()):
+        if a < b:
+            full.add((a, b))
+    prev_ids, prev_edges = None, set()
+    sizes = []
+    for s in range(10):
+        h, ids = es.stage(s)
+        assert np.all(np.diff(ids) > 0) and h.n == ids.shape[0]
+        assert np.all(np.diff(h.row_ptr) >= 1)            # every node has an edge
+        assert np.array_equal(h.labels, g.labels[ids])
+        r = np.repeat(np.arange(h.n), np.diff(h.row_ptr))
+        edges = {(int(ids[a]), int(ids[b])) for a, b in zip(r, h.col_idx) if a < b}
+        assert all(np.diff(h.col_idx[h.row_ptr[i]:h.row_ptr[i + 1]]).min(initial=1) > 0
+                   for i in range(h.n))
+        # symmetric pattern, a subset of the graph, growing
+        assert edges <= full and prev_edges <= edges
+        assert len(edges) * 2 == h.nnz
+        if prev_ids is not None:
+            pos = G.EdgeStream.carry(prev_ids, ids)
+            assert np.array_equal(ids[pos], prev_ids)
+        sizes.append(len(edges) - len(prev_edges))
+        prev_ids, prev_edges = ids, edges
+    assert prev_edges == full
+    # ten parts of about a tenth each
+    assert min(sizes) > 0.06 * len(full) and max(sizes) < 0.14 * len(full)
