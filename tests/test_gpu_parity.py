@@ -524,6 +524,40 @@ def test_products_match_oracle(ofm, k, dt):
     assert rel(ws.product("H"), X1.T @ O.apply_A(olap, X1)) < tol * 10
 
 
+@pytest.mark.parametrize("n", [16 * 4 + 5, 16 * 4 * 3 + 17, 3001])
+@pytest.mark.parametrize("recur", [False, True])
+def test_products_k64_ragged_tile_groups(ofm, n, recur):
+    # FP32 k = 64 passes deal their k x k products to the waves of a workgroup,
+    # which stage their tiles together: sizes whose last group of tiles is
+    # partly empty (and a single partial tile) against plain products, for the
+    # update (X^T X), the V pass (V^T V, X^T V), the products pass (X^T A V,
+    # V^T A V) and, with the recurrence, the update of X and A X
+    rng = np.random.default_rng([11, n])
+    g = graphs.sbm_plain(graphs.equal_sizes(n, 4), min(12.0, n / 8), 0.3,
+                         np.random.default_rng([11, n, 1]))
+    olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
+    glap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    x0 = rng.standard_normal((g.n, 64)) / np.sqrt(g.n)
+    ws = ofm.Workspace(glap, 64, variant="f2", precision=ofm.OFM_FP32, recur=recur)
+    X = dev(x0.astype(np.float32), torch.float32)
+    X0 = host(X)
+    ws.init(X)
+    V0 = host(ws.get_state()[0])
+    X1 = host(X)
+    AV = O.apply_A(olap, V0)
+    assert rel(ws.product("M"), X1.T @ X1) < 1e-6
+    assert rel(ws.product("P"), V0.T @ V0) < 1e-6
+    assert rel(ws.product("C"), X0.T @ V0) < 1e-6
+    assert rel(ws.product("E"), X0.T @ AV) < 1e-5
+    assert rel(ws.product("F"), V0.T @ AV) < 1e-5
+    ws.step(X)
+    V1 = host(ws.get_state()[0])
+    X2 = host(X)
+    assert rel(ws.product("M"), X2.T @ X2) < 1e-6
+    assert rel(ws.product("P"), V1.T @ V1) < 1e-6
+    assert rel(ws.product("C"), X1.T @ V1) < 1e-6
+
+
 def test_solve_returns_the_iterate_it_reports(ofm, sbm1k, sbm1k_lap):
     # the residual reported by ofm_solve is that of the X it returns, also for a
     # variant whose residual is not monotone
