@@ -296,6 +296,42 @@ def orderings_study(g, x0, k: int, variant: str, names, steps: int = 30, gather=
     return out
 
 
+def gather_ceiling(nrows: int = 2_000_000, S: int = 25, reps: int = 5):
+    """How fast the chip serves random rows: nrows output rows each summing S
+    rows of a table chosen uniformly at random (50M gathers, the entry count
+    of the headline graph), for tables of 4 MB-class, 32 MB-class and 2M rows
+    and rows of 64, 128 and 256 bytes (ofm_gather_rows: the gathers of the
+    products with A without the sparse-matrix work)."""
+    import torch
+    from paper_2305_10356_amd import ofm
+    out = []
+    gen = torch.Generator(device="cuda")
+    for rows in (32768, 262144, 2_000_000):
+        gen.manual_seed(rows)
+        idx = torch.randint(0, rows, (nrows * S,), generator=gen, device="cuda",
+                            dtype=torch.int32)
+        for rf in (16, 32, 64):
+            Z = torch.zeros((rows, rf), dtype=torch.float32, device="cuda")
+            Y = torch.empty((nrows, rf), dtype=torch.float32, device="cuda")
+            for _ in range(2):
+                ofm.gather_rows(idx, Z, S, Y)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                ofm.gather_rows(idx, Z, S, Y)
+            e1.record()
+            e1.synchronize()
+            us = 1e3 * e0.elapsed_time(e1) / reps
+            out.append({"table_rows": rows, "table_MB": round(rows * rf * 4 / 2**20, 1),
+                        "row_bytes": rf * 4, "gathers": nrows * S, "avg_us": round(us, 1),
+                        "G_rows_per_s": round(nrows * S / us / 1e3, 1),
+                        "G_lines_per_s": round(nrows * S * max(1, rf * 4 // 128) / us / 1e3, 1)})
+            log(f"gather ceiling {out[-1]}")
+            del Z, Y
+        del idx
+    return out
+
+
 def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10,
                  cold_stages=(9,), recur: bool = False, check_every: int = 10,
                  grouped: bool = False, gs=None):
@@ -564,6 +600,9 @@ def main():
     ap.add_argument("--orderings", default=None,
                     help="comma-separated node orders of the headline graph to time (random, "
                          "hub-first, rcm); prints their JSON")
+    ap.add_argument("--gather-ceiling", action="store_true",
+                    help="time random row gathers alone (tables of 4, 32, 256 MB class; rows of "
+                         "64, 128, 256 B); prints their JSON")
     ap.add_argument("--ladder", action="store_true",
                     help="also time the SpMM with the columns folded into windows of X")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -581,6 +620,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.batched_only:
         print(json.dumps(batched_vs_plain(args.variant, plain=False)), flush=True)
+        return
+    if args.gather_ceiling:
+        print(json.dumps({"gather_ceiling": gather_ceiling()}), flush=True)
         return
     if args.edge_stream_only:
         print(json.dumps(streaming_edges(args.variant)), flush=True)

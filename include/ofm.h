@@ -334,6 +334,20 @@ ofm_status ofm_select_roots(int variant, int64_t count, const double* coef, doub
                             int32_t* nroots, hipStream_t stream);
 
 /*
+ * Memory-system measurement, not part of the method: Y_r = sum_e Z[idx[r S + e]]
+ * for r < nrows, e < S, with rows of row_floats FP32 values (16, 32 or 64:
+ * 64, 128 or 256 bytes; Z: zrows rows, Y: nrows rows, row-major).  This is the
+ * row-gather pattern of the products with A without their sparse-matrix
+ * bookkeeping, for measuring how fast the chip serves random rows (bench.py
+ * --gather-ceiling).  idx: int32[nrows * S], every value in [0, zrows) (not
+ * checked).  Asynchronous.
+ * Errors: OFM_E_INVALID_ARG for null pointers or sizes below 1; OFM_E_SHAPE for
+ * another row width.
+ */
+ofm_status ofm_gather_rows(int64_t nrows, int S, int row_floats, const int32_t* idx,
+                           const float* Z, int64_t zrows, float* Y, hipStream_t stream);
+
+/*
  * Batched solves of many independent graphs (any sizes, widths k in
  * {4, 8, 16, 32, 64}): Algorithm 2 runs on all of them in lockstep, each pass
  * being one launch per width group over every graph of the group; a graph

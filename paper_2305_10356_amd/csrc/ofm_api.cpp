@@ -1511,6 +1511,18 @@ extern "C" ofm_status ofm_kmeans_noalloc(int64_t n, int dim, int n_clusters, con
                     stream, b);
 }
 
+extern "C" ofm_status ofm_gather_rows(int64_t nrows, int S, int row_floats, const int32_t* idx,
+                                      const float* Z, int64_t zrows, float* Y,
+                                      hipStream_t stream) {
+  if (nrows < 0 || S < 1 || zrows < 1) return OFM_E_INVALID_ARG;
+  if (row_floats != 16 && row_floats != 32 && row_floats != 64) return OFM_E_SHAPE;
+  if (nrows == 0) return OFM_OK;
+  if (!idx || !Z || !Y) return OFM_E_INVALID_ARG;
+  (void)zrows;  // the caller guarantees 0 <= idx < zrows
+  HIPCHK(launch_gather_rows(nrows, S, row_floats, idx, Z, Y, stream));
+  return OFM_OK;
+}
+
 extern "C" ofm_status ofm_select_roots(int variant, int64_t count, const double* coef,
                                        double* alpha, int32_t* nroots, hipStream_t stream) {
   if (variant < 0 || variant > 3 || count < 0) return OFM_E_INVALID_ARG;

@@ -268,6 +268,8 @@ hipError_t launch_kmeans_copy_centre(int dim, const float* Y, const int32_t* pic
                                      float* C, int c, hipStream_t s);
 hipError_t launch_count_changes(int64_t n, const int32_t* a, const int32_t* b, int* out,
                                 hipStream_t s);
+hipError_t launch_gather_rows(int64_t nrows, int S, int row_floats, const int32_t* idx,
+                              const float* Z, float* Y, hipStream_t s);
 int kmeans_blocks(int64_t n, int nv);
 int kmeans_pick_chunks(int64_t n);
 

@@ -630,4 +630,58 @@ hipError_t launch_count_changes(int64_t n, const int32_t* a, const int32_t* b, i
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Row-gather measurement: Y_r = sum of the S rows Z[idx[r S + e]], with rows of
+// RF FP32 values read as 16-byte vectors by RF / 4 lanes (the access pattern of
+// the products with A without their sparse-matrix bookkeeping).  A group of
+// lanes per output row, CH gathers in flight per lane.
+// ---------------------------------------------------------------------------
+
+template <int RF, int CH>
+__global__ void __launch_bounds__(256) gather_rows_kernel(int64_t nrows, int S,
+                                                          const int32_t* __restrict__ idx,
+                                                          const float4* __restrict__ Z,
+                                                          float4* __restrict__ Y) {
+  constexpr int L = RF / 4;        // lanes per row
+  constexpr int G = 64 / L;        // rows per wave
+  const int lane = threadIdx.x & 63, grp = lane / L, j = lane % L;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t r = wave * G + grp; r < nrows; r += nwaves * G) {
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int32_t* ip = idx + r * S;
+    for (int e0 = 0; e0 < S; e0 += CH) {
+      int c[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) c[u] = (e0 + u < S) ? ip[e0 + u] : -1;
+      float4 z[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        z[u] = c[u] >= 0 ? Z[(int64_t)c[u] * L + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        acc.x += z[u].x;
+        acc.y += z[u].y;
+        acc.z += z[u].z;
+        acc.w += z[u].w;
+      }
+    }
+    Y[r * L + j] = acc;
+  }
+}
+
+hipError_t launch_gather_rows(int64_t nrows, int S, int row_floats, const int32_t* idx,
+                              const float* Z, float* Y, hipStream_t s) {
+  const dim3 grid(8192), block(256);
+  const float4* z = reinterpret_cast<const float4*>(Z);
+  float4* y = reinterpret_cast<float4*>(Y);
+  switch (row_floats) {
+    case 16: hipLaunchKernelGGL((gather_rows_kernel<16, 16>), grid, block, 0, s, nrows, S, idx, z, y); break;
+    case 32: hipLaunchKernelGGL((gather_rows_kernel<32, 16>), grid, block, 0, s, nrows, S, idx, z, y); break;
+    case 64: hipLaunchKernelGGL((gather_rows_kernel<64, 16>), grid, block, 0, s, nrows, S, idx, z, y); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace ofm

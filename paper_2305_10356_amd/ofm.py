@@ -88,6 +88,7 @@ _SIGS = {
     "ofm_build_laplacian_grouped": (_I, [_I64, _I64, _P, _P, _P, _I, ctypes.c_uint, _P, _P,
                                          ctypes.POINTER(_P)]),
     "ofm_select_roots": (_I, [_I, _I64, _P, _P, _P, _P]),
+    "ofm_gather_rows": (_I, [_I64, _I, _I, _P, _P, _I64, _P, _P]),
     "ofm_grouped_order": (_I, [_I64, _P, _P, _P, _P]),
     "ofm_laplacian_destroy": (_I, [_P]),
     "ofm_laplacian_info": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
@@ -542,6 +543,21 @@ def select_roots(variant, coeffs, stream=None):
            "ofm_select_roots")
     torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
     return al.cpu().numpy(), nr.cpu().numpy()
+
+
+def gather_rows(idx, Z, S: int, Y=None, stream=None):
+    """Memory-system measurement: Y_r = sum of the S rows Z[idx[r S + e]]
+    (FP32 rows of 16, 32 or 64 values); idx int32 on the device, values in
+    [0, rows of Z)."""
+    torch = _torch()
+    if idx.dtype != torch.int32 or Z.dtype != torch.float32 or not (idx.is_cuda and Z.is_cuda):
+        raise TypeError("idx int32 and Z float32 device tensors")
+    nrows = idx.numel() // S
+    if Y is None:
+        Y = torch.empty((nrows, Z.shape[1]), dtype=torch.float32, device=Z.device)
+    _check(load().ofm_gather_rows(nrows, S, Z.shape[1], _ptr(idx), _ptr(Z), Z.shape[0], _ptr(Y),
+                                  _stream(stream)), "ofm_gather_rows")
+    return Y
 
 
 def scale(X, s, Y=None, stream=None):
