@@ -151,11 +151,14 @@ def batched_vs_plain(variant: str, count: int = 256, plain: bool = True):
         st = B.solve(Xs)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        tpw, cand, esc = B.schedule()
+        sched, esc = B.schedule()
         loop_ms, finish_ms = B.phases()
         rec = {"s": round(dt, 4), "converged": int(sum(s["converged"] for s in st)),
                "max_iters": int(max(s["iters"] for s in st)), "escalated_to_fp64": esc,
-               "tiles_per_wave": tpw, "schedule_candidates_ms": [round(x, 3) for x in cand],
+               "schedule": {f"k{d['k']}": f"tpw {d['tpw']}, {d['workers']} blocks/XCD"
+                            for d in sched},
+               "schedule_candidates_ms": {f"k{d['k']}": [round(x, 3) for x in d["ms"]]
+                                          for d in sched},
                "phase_ms": {"fp32_loop": round(loop_ms, 1), "fp64_finish": round(finish_ms, 1)},
                "graph_replays": B.replays}
         B.close()

@@ -358,9 +358,12 @@ ofm_status ofm_gather_rows(int64_t nrows, int S, int row_floats, const int32_t* 
  * recur, freeze_eps; graph = 1 runs the lockstep loop of ofm_batch_solve, after
  * the schedule has been chosen, as replays of one HIP graph per check_every
  * updates of every graph; the FP64 finishing solves always run eagerly).
- * Allocates the per-graph state.  The block schedule (blocks per graph, each
- * graph's blocks on one XCD) is chosen among a few candidates by timing the
- * first iterations of every solve.
+ * Allocates the per-graph state.  The block schedule (each graph's blocks on
+ * one XCD; a target of tiles per wavefront, 2, 4, 8 or 16, which sets the
+ * blocks per graph, and at most 128 or 64 blocks per XCD) is chosen among these
+ * eight candidates by timing the first iterations of the first solve (the GPU
+ * time from the first width group's start to the last one's end, HIP events)
+ * and kept for later solves (see ofm_batch_set_schedule).
  */
 typedef struct ofm_batch_s* ofm_batch;
 ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps, const int* host_ks,
@@ -397,17 +400,22 @@ ofm_status ofm_batch_get_state(ofm_batch b, int i, void* V_prev, void* G_prev,
  * any host pointer may be NULL). */
 ofm_status ofm_batch_get_step_info(ofm_batch b, int i, double* host_alpha, double* host_beta,
                                    double* host_coef, int32_t* host_nroots, hipStream_t stream);
-/* Schedule chosen by the last solve: host_tpw = tiles per wavefront target
- * (blocks per graph ~ tiles / (waves per block * tpw)), host_ms[4] = measured
- * time per iteration of each candidate (0 if untried), host_escalated = number
- * of graphs finished in FP64.  Any pointer may be NULL. */
-ofm_status ofm_batch_schedule(ofm_batch b, int* host_tpw, double* host_ms,
+/* Schedule of width group `group` (groups in increasing k; host_ngroups
+ * receives their number): host_k its width, host_tpw the tiles per wavefront
+ * target (blocks per graph ~ tiles / (waves per block * tpw)), host_workers
+ * the blocks per XCD cap, host_ms[8] the measured GPU time of a whole batch
+ * iteration with each candidate (tpw 2, 4, 8, 16 with 128 blocks per XCD, then
+ * with 64; 0 if untried; every group runs the same candidate); host_escalated = number of graphs the last solve finished in FP64.
+ * Any pointer may be NULL; an out-of-range group fills only host_ngroups and
+ * host_escalated and returns OFM_E_INVALID_ARG. */
+ofm_status ofm_batch_schedule(ofm_batch b, int group, int* host_ngroups, int* host_k,
+                              int* host_tpw, int* host_workers, double* host_ms,
                               int* host_escalated);
-/* Fix the tiles-per-wavefront target of the block schedule (one of the
- * candidates 2, 4, 8, 16) for the following solves and steps instead of timing
- * the candidates at the start of every solve; 0 returns to timing them.
- * Errors: OFM_E_INVALID_ARG for another value. */
-ofm_status ofm_batch_set_schedule(ofm_batch b, int tpw);
+/* Fix the block schedule of every width group to tpw tiles per wavefront
+ * (2, 4, 8 or 16) with at most `workers` blocks per XCD (128 or 64) for the
+ * following solves and steps; tpw = 0 times the candidates again at the next
+ * solve.  Errors: OFM_E_INVALID_ARG for another value. */
+ofm_status ofm_batch_set_schedule(ofm_batch b, int tpw, int workers);
 /* Host wall time of the last solve's two stages: the lockstep FP32 loop
  * (host_loop_ms) and the FP64 finishing solves (host_finish_ms), which run
  * concurrently on up to 4 streams of the batch; host_replays: graph replays

@@ -1539,9 +1539,14 @@ extern "C" ofm_status ofm_select_roots(int variant, int64_t count, const double*
 
 namespace {
 
-constexpr int kBatchCand = 4;
+// schedule candidates of a width group: c -> tiles per wavefront kBatchTpw[c % 4]
+// (a graph's workers ~ its tiles / (waves per block x tpw)) with at most
+// kBatchWorkers (c < 4) or half as many (c >= 4) workers per XCD
+constexpr int kBatchCand = 8;
 constexpr int kBatchWorkers = kBatchMaxWorkers;    // blocks per XCD
-const int kBatchTpw[kBatchCand] = {2, 4, 8, 16};  // candidate tiles per wavefront
+const int kBatchTpw[4] = {2, 4, 8, 16};
+inline int cand_tpw(int c) { return kBatchTpw[c % 4]; }
+inline int cand_workers(int c) { return c < 4 ? kBatchWorkers : kBatchWorkers / 2; }
 
 struct BatchGroup {
   int k = 0;
@@ -1562,6 +1567,9 @@ struct BatchGroup {
   char* bufs = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t ev = nullptr;
+  hipEvent_t t0 = nullptr, t1 = nullptr;   // timing of the group's iterations (schedule)
+  int chosen = 0;                         // schedule candidate in use
+  double cand_ms[kBatchCand] = {};        // measured ms per iteration of every candidate
 };
 
 }  // namespace
@@ -1574,9 +1582,8 @@ struct ofm_batch_s {
   std::vector<ofm_laplacian> laps;
   std::vector<int> ks;
   std::vector<BatchGroup> groups;
-  int chosen = 0;
-  int fixed = -1;          // candidate set by ofm_batch_set_schedule (-1: timed per solve)
-  double cand_ms[kBatchCand] = {};
+  int fixed = -1;          // candidate set by ofm_batch_set_schedule (-1: timed)
+  bool tuned = false;      // the groups' candidates were timed (kept for later solves)
   int escalated = 0;
   double loop_ms = 0.0;    // host time of the lockstep loop of the last solve
   double finish_ms = 0.0;  // host time of its FP64 finishing stage
@@ -1588,12 +1595,12 @@ struct ofm_batch_s {
   int64_t t = 0;           // updates done
   int64_t last_check = -1;
   // check_every updates of every group captured as one HIP graph, per parity
-  // of the ping-pong slot at the chunk's start, for the tiles-per-wave
-  // candidate chunk_cand
+  // of the ping-pong slot at the chunk's start, for the groups' schedule
+  // candidates chunk_cand
   hipStream_t cap_stream = nullptr;
   hipEvent_t fork = nullptr;
   hipGraphExec_t chunk[2] = {nullptr, nullptr};
-  int chunk_cand = -1;
+  std::vector<int> chunk_cand;
   int64_t replays = 0;     // chunks replayed by the last solve
 };
 
@@ -1621,6 +1628,8 @@ static void free_batch(ofm_batch b) {
     dev_free(g.bufs);
     if (g.stream) (void)hipStreamDestroy(g.stream);
     if (g.ev) (void)hipEventDestroy(g.ev);
+    if (g.t0) (void)hipEventDestroy(g.t0);
+    if (g.t1) (void)hipEventDestroy(g.t1);
   }
   if (b->start) (void)hipEventDestroy(b->start);
   delete b;
@@ -1699,7 +1708,8 @@ extern "C" ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps
     const int sct = sc_total(k);
     ofm_status st;
     if (hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&g.ev, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&g.ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&g.t0) != hipSuccess || hipEventCreate(&g.t1) != hipSuccess)
       return fail(OFM_E_HIP);
     const int maxw = kBatchWorkers;
     size_t part_total = 0, buf_total = 0;
@@ -1780,26 +1790,33 @@ extern "C" ofm_status ofm_batch_destroy(ofm_batch b) {
   return OFM_OK;
 }
 
-extern "C" ofm_status ofm_batch_schedule(ofm_batch b, int* host_tpw, double* host_ms,
+extern "C" ofm_status ofm_batch_schedule(ofm_batch b, int group, int* host_ngroups, int* host_k,
+                                         int* host_tpw, int* host_workers, double* host_ms,
                                          int* host_escalated) {
   if (!b) return OFM_E_INVALID_ARG;
-  if (host_tpw) *host_tpw = kBatchTpw[b->chosen];
-  if (host_ms)
-    for (int c = 0; c < kBatchCand; ++c) host_ms[c] = b->cand_ms[c];
+  if (host_ngroups) *host_ngroups = (int)b->groups.size();
   if (host_escalated) *host_escalated = b->escalated;
+  if (group < 0 || group >= (int)b->groups.size()) return OFM_E_INVALID_ARG;
+  const BatchGroup& g = b->groups[group];
+  if (host_k) *host_k = g.k;
+  if (host_tpw) *host_tpw = cand_tpw(g.chosen);
+  if (host_workers) *host_workers = cand_workers(g.chosen);
+  if (host_ms)
+    for (int c = 0; c < kBatchCand; ++c) host_ms[c] = g.cand_ms[c];
   return OFM_OK;
 }
 
-extern "C" ofm_status ofm_batch_set_schedule(ofm_batch b, int tpw) {
+extern "C" ofm_status ofm_batch_set_schedule(ofm_batch b, int tpw, int workers) {
   if (!b) return OFM_E_INVALID_ARG;
   if (tpw == 0) {
     b->fixed = -1;
+    b->tuned = false;
     return OFM_OK;
   }
   for (int c = 0; c < kBatchCand; ++c)
-    if (kBatchTpw[c] == tpw) {
+    if (cand_tpw(c) == tpw && cand_workers(c) == workers) {
       b->fixed = c;
-      b->chosen = c;
+      for (auto& g : b->groups) g.chosen = c;
       return OFM_OK;
     }
   return OFM_E_INVALID_ARG;
@@ -1870,8 +1887,8 @@ static ofm_status batch_iteration(ofm_batch B, BatchGroup& g, int cur, int64_t t
   base.xlist = g.dxlist;
   base.xoff = g.dxoff;
   base.tcount = g.tcount;
-  base.workers = kBatchWorkers;
-  base.tpw = kBatchTpw[cand];
+  base.workers = cand_workers(cand);
+  base.tpw = cand_tpw(cand);
   base.check_every = o.check_every;
   base.ngraphs = (int)g.idx.size();
   const int rs = o.restart ? kFlagRestart : 0;
@@ -1945,18 +1962,23 @@ static ofm_status batch_start(ofm_batch B, void* const* host_X, hipStream_t stre
   B->cur = 0;
   B->t = 0;
   B->last_check = -1;
-  for (auto& g : B->groups) OFMCHK(batch_iteration(B, g, B->cur, B->t, true, false, B->chosen));
+  for (auto& g : B->groups) OFMCHK(batch_iteration(B, g, B->cur, B->t, true, false, g.chosen));
   B->cur ^= 1;
   B->t = 1;
   B->started = true;
   return OFM_OK;
 }
 
-// one loop iteration of every group with schedule candidate cand (eager, on
-// the group streams)
-static ofm_status batch_step_groups(ofm_batch B, int cand) {
+// one loop iteration of every group (eager, on the group streams) with
+// schedule candidate cand, or each group's chosen one for cand < 0; timed:
+// events around every group's launches
+static ofm_status batch_step_groups(ofm_batch B, int cand, bool timed = false) {
   const bool check = (B->t % B->opts.check_every) == 0;
-  for (auto& g : B->groups) OFMCHK(batch_iteration(B, g, B->cur, B->t, false, check, cand));
+  for (auto& g : B->groups) {
+    if (timed) HIPCHK(hipEventRecord(g.t0, g.stream));
+    OFMCHK(batch_iteration(B, g, B->cur, B->t, false, check, cand < 0 ? g.chosen : cand));
+    if (timed) HIPCHK(hipEventRecord(g.t1, g.stream));
+  }
   if (check) B->last_check = B->t;
   B->cur ^= 1;
   B->t += 1;
@@ -1969,7 +1991,7 @@ static ofm_status batch_step_groups(ofm_batch B, int cand) {
 // streams and joined back.  The host step state is rewound after the capture.
 // Kernels read the step index from the groups' device counters, so one graph
 // serves every chunk with the same parity of the ping-pong slot.
-static ofm_status batch_capture(ofm_batch B, int cand, hipGraphExec_t* out) {
+static ofm_status batch_capture(ofm_batch B, hipGraphExec_t* out) {
   if (!B->cap_stream)
     HIPCHK(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking));
   if (!B->fork) HIPCHK(hipEventCreateWithFlags(&B->fork, hipEventDisableTiming));
@@ -1982,7 +2004,7 @@ static ofm_status batch_capture(ofm_batch B, int cand, hipGraphExec_t* out) {
   if (hipEventRecord(B->fork, B->cap_stream) != hipSuccess) st = OFM_E_HIP;
   for (auto& g : B->groups)
     if (st == OFM_OK && hipStreamWaitEvent(g.stream, B->fork, 0) != hipSuccess) st = OFM_E_HIP;
-  for (int i = 0; i < B->opts.check_every && st == OFM_OK; ++i) st = batch_step_groups(B, cand);
+  for (int i = 0; i < B->opts.check_every && st == OFM_OK; ++i) st = batch_step_groups(B, -1);
   for (auto& g : B->groups) {
     if (st == OFM_OK && hipEventRecord(g.ev, g.stream) != hipSuccess) st = OFM_E_HIP;
     if (st == OFM_OK && hipStreamWaitEvent(B->cap_stream, g.ev, 0) != hipSuccess) st = OFM_E_HIP;
@@ -1997,17 +2019,20 @@ static ofm_status batch_capture(ofm_batch B, int cand, hipGraphExec_t* out) {
   return st;
 }
 
-// replay one chunk on `stream` (captured on first use)
-static ofm_status batch_run_chunk(ofm_batch B, int cand, hipStream_t stream) {
-  if (B->chunk_cand != cand) {
+// replay one chunk on `stream` (captured on first use), each group on its
+// chosen schedule
+static ofm_status batch_run_chunk(ofm_batch B, hipStream_t stream) {
+  std::vector<int> key;
+  for (auto& g : B->groups) key.push_back(g.chosen);
+  if (B->chunk_cand != key) {
     for (auto& e : B->chunk) {
       if (e) HIPCHK(hipGraphExecDestroy(e));
       e = nullptr;
     }
-    B->chunk_cand = cand;
+    B->chunk_cand = key;
   }
   hipGraphExec_t& e = B->chunk[B->cur];
-  if (!e) OFMCHK(batch_capture(B, cand, &e));
+  if (!e) OFMCHK(batch_capture(B, &e));
   HIPCHK(hipGraphLaunch(e, stream));
   const int ce = B->opts.check_every;
   B->last_check = ((B->t + ce - 1) / ce) * ce;
@@ -2052,7 +2077,7 @@ extern "C" ofm_status ofm_batch_step(ofm_batch B, hipStream_t stream) {
   if (!B) return OFM_E_INVALID_ARG;
   if (!B->started) return OFM_E_INVALID_ARG;
   OFMCHK(batch_fork(B, stream));
-  OFMCHK(batch_step_groups(B, B->chosen));
+  OFMCHK(batch_step_groups(B, -1));
   return batch_join(B, stream);
 }
 
@@ -2101,25 +2126,28 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
   const ofm_opts& o = B->opts;
   const int ce = o.check_every;
   const auto t_solve = std::chrono::steady_clock::now();
-  // set-up step of Algorithm 2, then the loop; the first iterations try the
-  // candidate schedules (two iterations each) and keep the fastest
-  B->chosen = B->fixed >= 0 ? B->fixed : 0;
+  // set-up step of Algorithm 2, then the loop.  Unless the schedule is fixed
+  // or was timed by an earlier solve, the first iterations try the candidate
+  // schedules (two iterations each, every group on the same candidate) and
+  // keep the one whose iteration spans the least GPU time from the first
+  // group's start to the last group's end (HIP events on the group streams,
+  // the faster of the two iterations).  The groups share the chip, so a
+  // group's own time under contention would favour schedules that only take
+  // more of it from the others.
   B->replays = 0;
   OFMCHK(batch_start(B, host_X, stream));
-  for (int c = 0; c < kBatchCand; ++c) B->cand_ms[c] = 0.0;
-  int tuned = B->fixed;
-  const int64_t tune_end = B->fixed >= 0 ? 0 : 1 + 2 * kBatchCand;
-  double best = 1e300;
+  const bool tune = B->fixed < 0 && !B->tuned;
+  const int64_t tune_end = tune ? 1 + 2 * kBatchCand : 0;
   bool on_stream = false;  // the loop runs as graph replays on `stream`
   while (B->t < o.max_iter) {
     const bool tuning = B->t < tune_end;
-    const int cand = tuning ? (int)((B->t - 1) / 2) : (tuned < 0 ? 0 : tuned);
+    const int cand = tuning ? (int)((B->t - 1) / 2) : -1;
     if (!tuning && o.graph && B->t % ce == 1 % ce && B->t + ce <= o.max_iter) {
       if (!on_stream) {
         OFMCHK(batch_join(B, stream));
         on_stream = true;
       }
-      OFMCHK(batch_run_chunk(B, cand, stream));
+      OFMCHK(batch_run_chunk(B, stream));
       int any = 0;
       OFMCHK(batch_any_active(B, stream, &any));
       if (!any) break;
@@ -2130,18 +2158,25 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
       on_stream = false;
     }
     const bool check = (B->t % ce) == 0;
-    auto t0 = std::chrono::steady_clock::now();
-    OFMCHK(batch_step_groups(B, cand));
+    OFMCHK(batch_step_groups(B, cand, tuning));
     if (tuning) {
-      for (auto& g : B->groups) HIPCHK(hipStreamSynchronize(g.stream));
-      const double ms =
-          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-      if ((B->t - 2) % 2 == 1) {  // the second iteration of a candidate
-        B->cand_ms[cand] = ms;
-        if (ms < best) {
-          best = ms;
-          tuned = cand;
-        }
+      const bool second = ((B->t - 2) % 2) == 1;  // B->t counts the step just enqueued
+      double span = 0.0;
+      for (auto& g : B->groups) {
+        HIPCHK(hipEventSynchronize(g.t1));
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, B->groups[0].t0, g.t1));
+        span = std::max(span, (double)ms);
+      }
+      for (auto& g : B->groups)
+        g.cand_ms[cand] = second ? std::min(g.cand_ms[cand], span) : span;
+      if (B->t == tune_end) {
+        int best = 0;
+        const double* ms = B->groups[0].cand_ms;
+        for (int c = 1; c < kBatchCand; ++c)
+          if (ms[c] < ms[best]) best = c;
+        for (auto& g : B->groups) g.chosen = best;
+        B->tuned = true;
       }
     }
     if (check) {
@@ -2154,7 +2189,6 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
   if (on_stream) OFMCHK(batch_fork(B, stream));
   const int64_t t = B->t;
   const int64_t last_check = B->last_check;
-  B->chosen = tuned < 0 ? 0 : tuned;
   B->escalated = 0;
   // per-graph stats; a graph whose FP32 residual stopped decreasing before the
   // tolerance (or ran out of iterations) is finished in FP64 from its FP32 X

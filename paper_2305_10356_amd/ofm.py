@@ -111,10 +111,10 @@ _SIGS = {
     "ofm_batch_create": (_I, [_I, _P, _P, ctypes.POINTER(Opts), ctypes.POINTER(_P)]),
     "ofm_batch_destroy": (_I, [_P]),
     "ofm_batch_solve": (_I, [_P, _P, _P, _P]),
-    "ofm_batch_schedule": (_I, [_P, _P, _P, _P]),
+    "ofm_batch_schedule": (_I, [_P, _I, _P, _P, _P, _P, _P, _P]),
     "ofm_batch_phases": (_I, [_P, _P, _P, _P]),
     "ofm_batch_init": (_I, [_P, _P, _P]),
-    "ofm_batch_set_schedule": (_I, [_P, _I]),
+    "ofm_batch_set_schedule": (_I, [_P, _I, _I]),
     "ofm_batch_step": (_I, [_P, _P]),
     "ofm_batch_get_state": (_I, [_P, _I, _P, _P, _P]),
     "ofm_batch_get_step_info": (_I, [_P, _I, _P, _P, _P, _P, _P]),
@@ -474,20 +474,29 @@ class Batch:
                "ofm_batch_solve")
         return [s.as_dict() for s in stats]
 
-    def set_schedule(self, tpw: int):
-        """Fix the tiles-per-wavefront target (2, 4, 8 or 16; 0: timed per solve)."""
-        _check(self._lib.ofm_batch_set_schedule(self.handle, int(tpw)), "ofm_batch_set_schedule")
+    def set_schedule(self, tpw: int, workers: int = 128):
+        """Fix every group's schedule: tiles per wavefront (2, 4, 8 or 16) and
+        blocks per XCD (128 or 64); tpw = 0: time the candidates again."""
+        _check(self._lib.ofm_batch_set_schedule(self.handle, int(tpw), int(workers)),
+               "ofm_batch_set_schedule")
 
     def schedule(self):
-        """(tiles-per-wavefront target chosen, ms per iteration of each
-        candidate, graphs finished in FP64) of the last solve."""
-        tpw = ctypes.c_int()
+        """([{k, tpw, workers, ms[8]} per width group], graphs finished in
+        FP64 by the last solve)."""
+        ng = ctypes.c_int()
         esc = ctypes.c_int()
-        ms = np.zeros(4)
-        _check(self._lib.ofm_batch_schedule(self.handle, ctypes.byref(tpw),
-                                            ms.ctypes.data_as(ctypes.c_void_p), ctypes.byref(esc)),
-               "ofm_batch_schedule")
-        return tpw.value, ms, esc.value
+        self._lib.ofm_batch_schedule(self.handle, -1, ctypes.byref(ng), None, None, None, None,
+                                     ctypes.byref(esc))
+        out = []
+        for gi in range(ng.value):
+            k, tpw, wk = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+            ms = np.zeros(8)
+            _check(self._lib.ofm_batch_schedule(self.handle, gi, None, ctypes.byref(k),
+                                                ctypes.byref(tpw), ctypes.byref(wk),
+                                                ms.ctypes.data_as(ctypes.c_void_p), None),
+                   "ofm_batch_schedule")
+            out.append({"k": k.value, "tpw": tpw.value, "workers": wk.value, "ms": ms})
+        return out, esc.value
 
     def phases(self):
         """(lockstep FP32 loop ms, FP64 finishing ms) of the last solve (host

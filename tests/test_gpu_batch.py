@@ -64,9 +64,9 @@ def test_batch_converges_each_graph(batch_graphs, variant, recur):
                   check_every=10, restart=variant.startswith("tri"), recur=recur)
     Xs = [torch.tensor(x0.astype(np.float32), device="cuda") for _, x0, _ in gs]
     st = B.solve(Xs)
-    tpw, ms, esc = B.schedule()
-    print(f"{variant}: iterations {[s['iters'] for s in st]} tiles/wave {tpw} {ms} "
-          f"escalated {esc}", flush=True)
+    sched, esc = B.schedule()
+    print(f"{variant}: iterations {[s['iters'] for s in st]} schedule "
+          f"{[(d['k'], d['tpw'], d['workers']) for d in sched]} escalated {esc}", flush=True)
     for (g, x0, k), X, s in zip(gs, Xs, st):
         olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
         rr = O.relres(olap, X.cpu().numpy().astype(np.float64))
@@ -91,7 +91,7 @@ def test_batch_escalates_fp32_straggler(lib, graph):
                   graph=graph)
     Xs = [torch.tensor(x0.astype(np.float32), device="cuda") for _, x0 in gl]
     st = B.solve(Xs)
-    tpw, ms, esc = B.schedule()
+    _, esc = B.schedule()
     print(f"straggler batch: {[(s['iters'], s['relres']) for s in st]} escalated {esc}", flush=True)
     assert esc >= 1
     for (g, _), X, s in zip(gl, Xs, st):
@@ -225,14 +225,43 @@ def test_batch_graph_replay_bitwise_eager(batch_graphs, recur):
     for graph in (False, True):
         B = ofm.Batch(laps, ks, variant="f1", max_iter=3000, tol=1e-4, check_every=10,
                       recur=recur, graph=graph)
-        B.set_schedule(4)
+        B.set_schedule(4, 128)
         Xs = [torch.tensor(x0.astype(np.float32), device="cuda") for _, x0, _ in gs]
         st = B.solve(Xs)
         B.phases()
-        out.append((Xs, st, B.schedule()[0], B.replays))
+        out.append((Xs, st, [(d["tpw"], d["workers"]) for d in B.schedule()[0]], B.replays))
     (Xe, se, te, re), (Xg, sg, tg, rg) = out
-    print(f"  recur={recur}: eager tiles/wave {te}, graph tiles/wave {tg}, replays {rg}", flush=True)
-    assert re == 0 and rg > 0 and te == tg == 4
+    print(f"  recur={recur}: eager schedule {te}, graph schedule {tg}, replays {rg}", flush=True)
+    assert re == 0 and rg > 0 and te == tg and all(c == (4, 128) for c in te)
     for a, b, x, y in zip(se, sg, Xe, Xg):
         assert a["iters"] == b["iters"] and a["relres"] == b["relres"], (a, b)
         assert torch.equal(x, y)
+
+
+def test_batch_schedule_per_group_and_kept(batch_graphs):
+    # the first solve times the eight candidates (whole batch iterations) and
+    # keeps the fastest for every width group; a second solve reuses the
+    # choice (no timing) and converges as well
+    from paper_2305_10356_amd import ofm
+    gs, laps = batch_graphs
+    ks = [k for _, _, k in gs]
+    B = ofm.Batch(laps, ks, variant="f1", max_iter=3000, tol=1e-4, check_every=10)
+    Xs = [torch.tensor(x0.astype(np.float32), device="cuda") for _, x0, _ in gs]
+    st = B.solve(Xs)
+    sched, _ = B.schedule()
+    assert sorted(d["k"] for d in sched) == sorted(set(ks))
+    for d in sched:
+        assert np.all(d["ms"] > 0.0), d
+        assert np.array_equal(d["ms"], sched[0]["ms"])
+        best = int(np.argmin(d["ms"]))
+        assert (d["tpw"], d["workers"]) == ([2, 4, 8, 16][best % 4], 128 if best < 4 else 64)
+    print(f"  schedule per group {[(d['k'], d['tpw'], d['workers']) for d in sched]}", flush=True)
+    Ys = [torch.tensor(x0.astype(np.float32), device="cuda") for _, x0, _ in gs]
+    st2 = B.solve(Ys)
+    sched2, _ = B.schedule()
+    assert [(d["tpw"], d["workers"]) for d in sched2] == [(d["tpw"], d["workers"]) for d in sched]
+    assert all(s["converged"] == 1 for s in st + st2)
+    with pytest.raises(ofm.OfmError):
+        B.set_schedule(3, 128)
+    with pytest.raises(ofm.OfmError):
+        B.set_schedule(4, 100)
