@@ -1590,83 +1590,94 @@ __global__ void __launch_bounds__(256) select_roots_kernel(int tri, int64_t coun
 template <int KP>
 __device__ __forceinline__ void residual_body(int variant, double normA2, double* sc,
                                               int* status, double tol, int* frozen) {
+  // L: Cholesky factor of M; W: [K | H] side by side (KP x 2KP)
   __shared__ double L[KP * KP];
-  __shared__ double W[KP * KP];
+  __shared__ double W[KP * 2 * KP];
   __shared__ double buf[256];
   __shared__ int fail;
   const int tid = threadIdx.x;
   const int KK = KP * KP;
+  constexpr int W2 = 2 * KP;
   const double* M = sc + SC<KP>::M;
   const double* H = sc + SC<KP>::H;
   const double* K = sc + SC<KP>::K;
-  for (int e = tid; e < KK; e += 256) L[e] = M[e];
+  for (int e = tid; e < KK; e += 256) {
+    L[e] = M[e];
+    const int r = e / KP, c = e % KP;
+    W[r * W2 + c] = K[e];
+    W[r * W2 + KP + c] = H[e];
+  }
   if (tid == 0) fail = 0;
   __syncthreads();
   // an exactly zero column of X (a zero-padded width) has a zero row and
   // column in M, H and K; a unit pivot there leaves it out of both traces
   if (tid < KP && L[tid * KP + tid] == 0.0) L[tid * KP + tid] = 1.0;
   __syncthreads();
-  // Cholesky M = L L^T (lower triangle of L), column by column
+  // Cholesky M = L L^T by outer products on the unscaled columns: step c
+  // subtracts A_rc A_qc / A_cc from the trailing lower triangle (one barrier
+  // per step), leaving A_rc (r >= c) as it stood at step c.  The factor is
+  // then L_cc = sqrt(A_cc), L_rc = A_rc / sqrt(A_cc), so L_rc / L_cc =
+  // A_rc / A_cc: kept in place of L below the diagonal, with 1 / L_rr in rd.
+  __shared__ double rd[KP];
   for (int c = 0; c < KP; ++c) {
-    if (tid == 0) {
-      const double d = L[c * KP + c];
-      if (!(d > 0.0) || !isfinite(d)) fail = 1;
-      L[c * KP + c] = (d > 0.0) ? sqrt(d) : 1.0;
-    }
-    __syncthreads();
-    const double dc = L[c * KP + c];
-    for (int r = c + 1 + tid; r < KP; r += 256) L[r * KP + c] /= dc;
-    __syncthreads();
-    const int m = KP - 1 - c;  // trailing block, lower triangle
+    const double d = L[c * KP + c];
+    const double inv = 1.0 / ((d > 0.0) ? d : 1.0);
+    if (tid == 0 && (!(d > 0.0) || !isfinite(d))) fail = 1;
+    const int m = KP - 1 - c;
     for (int e = tid; e < m * m; e += 256) {
       const int r = c + 1 + e / m, q = c + 1 + e % m;
-      if (q <= r) L[r * KP + q] -= L[r * KP + c] * L[q * KP + c];
+      if (q <= r) L[r * KP + q] -= L[r * KP + c] * L[q * KP + c] * inv;
     }
     __syncthreads();
   }
+  if (tid < KP) {
+    const double d = L[tid * KP + tid];
+    buf[tid] = 1.0 / ((d > 0.0) ? d : 1.0);
+    rd[tid] = 1.0 / ((d > 0.0) ? sqrt(d) : 1.0);
+  }
+  __syncthreads();
+  for (int e = tid; e < KK; e += 256) {
+    const int r = e / KP, c = e % KP;
+    if (r > c) L[e] *= buf[c];
+  }
+  __syncthreads();
   // With M = L L^T: tr(M^{-1} K) = tr(L^{-1} K L^{-T}) and tr((M^{-1} H)^2) =
-  // ||L^{-1} H L^{-T}||_F^2 (K, H symmetric).  W = L^{-1} B L^{-T} by two
-  // forward substitutions with a transpose between them, each eliminating one
-  // row at a time with every thread updating the rows below.
-  double trMK = 0.0, trMH2 = 0.0;
-  for (int which = 0; which < 2; ++which) {
-    const double* B = which == 0 ? K : H;
-    for (int e = tid; e < KK; e += 256) W[e] = B[e];
-    for (int half = 0; half < 2; ++half) {
+  // ||L^{-1} H L^{-T}||_F^2 (K, H symmetric).  Both by two forward
+  // substitutions with a transpose between them.  A substitution eliminates
+  // one row at a time on unscaled rows, z_r -= (L_rq / L_qq) z_q (one barrier
+  // per row, every thread updating the rows below), and scales row r by
+  // 1 / L_rr at the end.
+  for (int half = 0; half < 2; ++half) {
+    for (int q = 0; q < KP - 1; ++q) {
+      for (int e = tid; e < (KP - 1 - q) * W2; e += 256) {
+        const int r = q + 1 + e / W2, c = e % W2;
+        W[r * W2 + c] -= L[r * KP + q] * W[q * W2 + c];
+      }
       __syncthreads();
-      for (int q = 0; q < KP; ++q) {
-        const double d = L[q * KP + q];
-        for (int c = tid; c < KP; c += 256) W[q * KP + c] /= d;
-        __syncthreads();
-        for (int e = tid; e < (KP - 1 - q) * KP; e += 256) {
-          const int r = q + 1 + e / KP, c = e % KP;
-          W[r * KP + c] -= L[r * KP + q] * W[q * KP + c];
-        }
-        __syncthreads();
-      }
-      if (half == 0) {
-        // in-place transpose: (L^{-1} B)^T = B L^{-T}
-        for (int e = tid; e < KK; e += 256) {
-          const int r = e / KP, c = e % KP;
-          if (c > r) {
-            const double x = W[r * KP + c];
-            W[r * KP + c] = W[c * KP + r];
-            W[c * KP + r] = x;
-          }
+    }
+    for (int e = tid; e < KP * W2; e += 256) W[e] *= rd[e / W2];
+    __syncthreads();
+    if (half == 0) {
+      // in-place transpose of each block: (L^{-1} B)^T = B L^{-T}
+      for (int e = tid; e < 2 * KK; e += 256) {
+        const int b = e / KK, r = (e % KK) / KP, c = e % KP;
+        if (c > r) {
+          const double x = W[r * W2 + b * KP + c];
+          W[r * W2 + b * KP + c] = W[c * W2 + b * KP + r];
+          W[c * W2 + b * KP + r] = x;
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
-    double part = 0.0;
-    if (which == 0) {
-      if (tid < KP) part = W[tid * KP + tid];
-      trMK = block_sum256(part, buf);
-    } else {
-      for (int e = tid; e < KK; e += 256) part += W[e] * W[e];
-      trMH2 = block_sum256(part, buf);
-    }
-    __syncthreads();
   }
+  double pk = 0.0, ph = 0.0;
+  if (tid < KP) pk = W[tid * W2 + tid];
+  for (int e = tid; e < KK; e += 256) {
+    const double x = W[(e / KP) * W2 + KP + e % KP];
+    ph += x * x;
+  }
+  const double trMK = block_sum256(pk, buf);
+  const double trMH2 = block_sum256(ph, buf);
   // objective: f1 = ||A||^2 + 2 tr(H) + ||M||_F^2 ; f2 = 2 tr(H) - tr(M H)
   double trH = (tid < KP) ? H[tid * KP + tid] : 0.0;
   double mm = 0.0;
