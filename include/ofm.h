@@ -85,6 +85,7 @@ typedef enum ofm_precision { OFM_FP64 = 0, OFM_FP32 = 1, OFM_FP32_BF16X = 2 } of
 /* ofm_build_laplacian flags */
 #define OFM_LAP_VALIDATE 1u   /* also check that the pattern is symmetric    */
 #define OFM_LAP_NO_REORDER 2u /* process rows in index order, not by degree  */
+#define OFM_LAP_NO_UPPER 4u   /* build no upper-triangle copy (see below)     */
 
 typedef struct ofm_laplacian_s* ofm_laplacian;
 typedef struct ofm_workspace_s* ofm_workspace;
@@ -164,10 +165,20 @@ const char* ofm_version(void);
  *               vals_dtype; self-loops (i == j) count once in D_ii
  *   vals_dtype  OFM_FP64 (double) or OFM_FP32 (float, widened exactly to
  *               FP64 before any arithmetic); ignored when vals is NULL
- *   flags       OFM_LAP_VALIDATE, OFM_LAP_NO_REORDER
+ *   flags       OFM_LAP_VALIDATE, OFM_LAP_NO_REORDER, OFM_LAP_NO_UPPER
  * Computes D_ii = sum_j S_ij, D^{-1/2}, ||A||_F^2 and the normalized edge
  * weights w_ij = D_ii^{-1/2} S_ij D_jj^{-1/2} (FP64 and FP32 copies, laid out
  * in the row-processing order).  Synchronizing (the checks are read back).
+ * Upper-triangle copy: unless OFM_LAP_NO_UPPER or OFM_LAP_NO_REORDER is given
+ * or some row has a self-loop, the entries with column > row are also packed
+ * (about half of nnz, 24 B per entry for the FP32 and FP64 copies together),
+ * rows by that count, descending.  The f1 variants' line searches need only
+ * the per-column quadratic forms diag(V^T A V) (Section 3.2), which for a
+ * symmetric A equal -diag(V^T V) - 2 sum_i V_ic sum_{j>i} w_ij V_jc: a
+ * workspace on such a Laplacian gathers only those entries for them (half the
+ * gathers of the product A V).  The symmetry of the pattern and the weights
+ * that the method assumes is then also what the step relies on
+ * (OFM_LAP_VALIDATE checks it).
  * The input arrays are only read during the call.
  * Errors: OFM_E_GRAPH for a malformed CSR, an out-of-range column, a zero
  * degree or (when validating) an asymmetric pattern.
@@ -226,6 +237,12 @@ ofm_status ofm_laplacian_destroy(ofm_laplacian lap);
  * outputs) the degrees D_ii as FP64[n] into host_degrees. Synchronizing. */
 ofm_status ofm_laplacian_info(ofm_laplacian lap, int64_t* host_n, int64_t* host_nnz,
                               double* host_normA2, double* host_degrees);
+
+/* Size of the upper-triangle copy (see ofm_build_laplacian): its rows (those
+ * with at least one entry above the diagonal) and entries; both 0 when none
+ * was built.  Either output may be NULL.  Errors: OFM_E_INVALID_ARG for a null
+ * handle. */
+ofm_status ofm_laplacian_upper(ofm_laplacian lap, int64_t* host_rows, int64_t* host_nnz);
 
 /*
  * Y = A Z for an N x k block Z (the sparse-times-tall-skinny product of the

@@ -105,6 +105,7 @@ struct TileTable {
 struct ofm_laplacian_s {
   LaplacianDev g;
   TileTable tt[3];  // TR = 16, 32, 64
+  TileTable ut[3];  // tiles of the upper-triangle copy (g.nu > 0)
   std::vector<double> host_deg;
 };
 
@@ -139,6 +140,9 @@ struct ofm_workspace_s {
   bool initialized = false;
   const TileTable* tiles = nullptr;
   const void* pk = nullptr;
+  // tiles of the Laplacian's upper-triangle copy when the line search's
+  // diag(V^T A V) comes from it (f1 variants without the recurrence)
+  const TileTable* utiles = nullptr;
   bool hc = false;       // gathers with the hot/cold cache policy (opts.gather)
   // per-pass event timing
   unsigned timing = 0;   // bit i: record events around the kernels of pass i
@@ -232,7 +236,12 @@ static void free_lap(ofm_laplacian L) {
   dev_free(L->g.sptr);
   dev_free(L->g.pk32);
   dev_free(L->g.pk64);
+  dev_free(L->g.usched);
+  dev_free(L->g.usptr);
+  dev_free(L->g.upk32);
+  dev_free(L->g.upk64);
   for (auto& t : L->tt) dev_free(t.dev);
+  for (auto& t : L->ut) dev_free(t.dev);
   delete L;
 }
 
@@ -405,7 +414,8 @@ static ofm_status build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr
   *out = nullptr;
   if (n <= 0 || nnz < 0 || !row_ptr || (nnz > 0 && !col_idx)) return OFM_E_INVALID_ARG;
   if (n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 31)) return OFM_E_SHAPE;
-  if (flags & ~(OFM_LAP_VALIDATE | OFM_LAP_NO_REORDER)) return OFM_E_INVALID_ARG;
+  if (flags & ~(OFM_LAP_VALIDATE | OFM_LAP_NO_REORDER | OFM_LAP_NO_UPPER))
+    return OFM_E_INVALID_ARG;
   if (vals_in && vals_dtype != OFM_FP64 && vals_dtype != OFM_FP32) return OFM_E_INVALID_ARG;
   // FP32 weights are widened (exactly) to an FP64 copy that lives for the call
   double* vals64 = nullptr;
@@ -551,6 +561,70 @@ static ofm_status build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr
                        stream) != hipSuccess)
       return fail(OFM_E_HIP);
   }
+  // upper-triangle copy for the f1 line searches (degree order only, no
+  // self-loops): rows with entries above the diagonal, by their count
+  if (g.reorder && !groups && !(flags & OFM_LAP_NO_UPPER) && nnz > 0) {
+    int32_t* ucnt = nullptr;
+    if ((st = dev_alloc(&ucnt, n)) != OFM_OK) return fail(st);
+    std::vector<int32_t> hu(n);
+    int loops = 0;
+    const bool ok =
+        hipMemsetAsync(dflags, 0, sizeof(int), stream) == hipSuccess &&
+        launch_graph_upper_count(n, row_ptr, col_idx, ucnt, dflags, stream) == hipSuccess &&
+        hipMemcpyAsync(hu.data(), ucnt, n * sizeof(int32_t), hipMemcpyDeviceToHost, stream) ==
+            hipSuccess &&
+        hipMemcpyAsync(&loops, dflags, sizeof(int), hipMemcpyDeviceToHost, stream) == hipSuccess &&
+        hipStreamSynchronize(stream) == hipSuccess;
+    dev_free(ucnt);
+    if (!ok) return fail(OFM_E_HIP);
+    if (!loops) {
+      int32_t mx = 0;
+      for (int64_t i = 0; i < n; ++i) mx = std::max(mx, hu[(size_t)i]);
+      std::vector<int64_t> slot((size_t)mx + 2, 0);  // slot[mx - count]: next position
+      for (int64_t i = 0; i < n; ++i) ++slot[(size_t)(mx - hu[(size_t)i]) + 1];
+      for (int32_t c = 0; c <= mx; ++c) slot[(size_t)c + 1] += slot[c];
+      std::vector<int32_t> usched(n);
+      for (int64_t i = 0; i < n; ++i) usched[(size_t)slot[(size_t)(mx - hu[(size_t)i])]++] = (int32_t)i;
+      int64_t nu = 0;
+      while (nu < n && hu[(size_t)usched[(size_t)nu]] > 0) ++nu;
+      std::vector<int32_t> usptr(nu + 1), udeg(nu);
+      usptr[0] = 0;
+      for (int64_t p = 0; p < nu; ++p) {
+        udeg[p] = hu[(size_t)usched[(size_t)p]];
+        usptr[p + 1] = usptr[p] + udeg[p];
+      }
+      g.nu = nu;
+      g.nnzu = nu > 0 ? usptr[nu] : 0;
+      if (nu > 0) {
+        if ((st = dev_alloc(&g.usched, nu)) != OFM_OK) return fail(st);
+        if ((st = dev_alloc(&g.usptr, nu + 1)) != OFM_OK) return fail(st);
+        if ((st = dev_alloc(reinterpret_cast<int64_t**>(&g.upk32), g.nnzu)) != OFM_OK)
+          return fail(st);
+        if ((st = dev_alloc(reinterpret_cast<double**>(&g.upk64), 2 * g.nnzu)) != OFM_OK)
+          return fail(st);
+        if (hipMemcpyAsync(g.usched, usched.data(), nu * sizeof(int32_t), hipMemcpyHostToDevice,
+                           stream) != hipSuccess ||
+            hipMemcpyAsync(g.usptr, usptr.data(), (nu + 1) * sizeof(int32_t),
+                           hipMemcpyHostToDevice, stream) != hipSuccess ||
+            launch_graph_pack_upper(nu, g.usched, row_ptr, col_idx, w64, g.usptr, g.upk32,
+                                    g.upk64, g.cold_below, stream) != hipSuccess)
+          return fail(OFM_E_HIP);
+        for (int i = 0; i < 3; ++i) {
+          std::vector<int32_t> t;
+          build_tiles(udeg, trs[i], true, 0, nu, t);
+          t.push_back((int32_t)nu);
+          L->ut[i].tr = trs[i];
+          L->ut[i].ntiles = (int64_t)t.size() - 1;
+          if ((st = dev_alloc(&L->ut[i].dev, t.size())) != OFM_OK) return fail(st);
+          // the host arrays of this block end here: wait for their copies
+          if (hipMemcpyAsync(L->ut[i].dev, t.data(), t.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, stream) != hipSuccess ||
+              hipStreamSynchronize(stream) != hipSuccess)
+            return fail(OFM_E_HIP);
+        }
+      }
+    }
+  }
   if (hipStreamSynchronize(stream) != hipSuccess) return fail(OFM_E_HIP);
   dev_free(dflags);
   dev_free(w64);
@@ -562,6 +636,14 @@ static ofm_status build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr
 extern "C" ofm_status ofm_laplacian_destroy(ofm_laplacian lap) {
   if (!lap) return OFM_E_INVALID_ARG;
   free_lap(lap);
+  return OFM_OK;
+}
+
+extern "C" ofm_status ofm_laplacian_upper(ofm_laplacian lap, int64_t* host_rows,
+                                          int64_t* host_nnz) {
+  if (!lap) return OFM_E_INVALID_ARG;
+  if (host_rows) *host_rows = lap->g.nu;
+  if (host_nnz) *host_nnz = lap->g.nnzu;
   return OFM_OK;
 }
 
@@ -686,6 +768,8 @@ static void free_ws(ofm_workspace ws) {
   delete ws;
 }
 
+static bool is_f2(int v) { return v == OFM_F2 || v == OFM_TRI_F2; }
+
 // f2 without the recurrence at k >= 32: the SpMM of V stores A V and a
 // streaming pass forms X^T A V and V^T A V
 static bool f2_products_pass(const ofm_opts& o, int k) {
@@ -773,6 +857,10 @@ extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_o
   ws->esz = prec == OFM_FP64 ? 8 : 4;
   ws->tiles = tt;
   ws->pk = prec == OFM_FP64 ? lap->g.pk64 : lap->g.pk32;
+  if (lap->g.nu > 0 && !is_f2(o.variant) && !o.recur) {
+    for (auto& t : lap->ut)
+      if (t.tr == tt->tr) ws->utiles = &t;
+  }
   const size_t blk = (size_t)ws->n * k * ws->esz;
   const int nvmax = 2 * k * k + 3 * k;
   const int ny = (kMaxBlocks + kFinChunk - 1) / kFinChunk;
@@ -867,6 +955,23 @@ static ofm_status run_spmm(ofm_workspace ws, PassArgs& a, hipStream_t s) {
   return finalize(ws, a, s);
 }
 
+// a kFlagUpper pass over the upper-triangle copy (same rows of Z, fewer
+// entries, its own processing order)
+static ofm_status run_spmm_upper(ofm_workspace ws, PassArgs& a, hipStream_t s) {
+  const LaplacianDev& g = ws->lap->g;
+  a.sched = g.usched;
+  a.sptr = g.usptr;
+  a.tiles = ws->utiles->dev;
+  a.ntiles = ws->utiles->ntiles;
+  a.pk = ws->prec == OFM_FP64 ? g.upk64 : g.upk32;
+  a.cold_below = g.cold_below;
+  a.xcd = 0;
+  if (ws->hc) a.flags |= kFlagHC;
+  spmm_grid(a, ws->utiles, ws->prec, ws->k, a.nv, ws->part_cap);
+  HIPCHK(timed(ws, pass_kind(a.mode), s, [&] { return launch_spmm(ws->prec, ws->k, a, s); }));
+  return finalize(ws, a, s);
+}
+
 static ofm_status run_dense(ofm_workspace ws, PassArgs& a, hipStream_t s) {
   const int tr = tile_rows(ws->prec, ws->k);
   a.nblocks = pass_blocks(ws->prec, ws->k, (ws->n + tr - 1) / tr);
@@ -911,8 +1016,6 @@ extern "C" ofm_status ofm_get_timing(ofm_workspace ws, double* host_ms, int64_t*
   }
   return OFM_OK;
 }
-
-static bool is_f2(int v) { return v == OFM_F2 || v == OFM_TRI_F2; }
 
 // G = g(X) into G[cur] with the per-column sums; f2 variants go through AX.
 static ofm_status direction(ofm_workspace ws, void* X, const void* Gp, const void* Vp, int check,
@@ -1003,6 +1106,12 @@ static ofm_status search_and_update(ofm_workspace ws, void* X, const void* Vp, b
     e.V = ws->V[cur];
     e.Z = ws->AV;
     OFMCHK(run_dense(ws, e, s));
+  } else if (ws->utiles) {
+    // diag(V^T A V) over the entries above the diagonal (half the gathers)
+    PassArgs w = base_args(ws, kAVF1, kFlagUpper);
+    w.Z = ws->V[cur];
+    w.Zg = ws->Vb;
+    OFMCHK(run_spmm_upper(ws, w, s));
   } else {
     PassArgs w = base_args(ws, is_f2(ws->opts.variant) ? kAVF2 : kAVF1, 0);
     w.Z = ws->V[cur];
@@ -1016,8 +1125,8 @@ static ofm_status search_and_update(ofm_workspace ws, void* X, const void* Vp, b
   const bool adv_h = is_f2(ws->opts.variant) && !ws->opts.recur;
   HIPCHK(timed(ws, OFM_PASS_LINESEARCH, s, [&] {
     return launch_linesearch(ws->k, ws->opts.variant, first && ws->opts.first_step == 1,
-                             ws->opts.alpha0, adv_h ? 1 : 0, ws->sc, ws->status, ws->frozen,
-                             ws->opts.freeze_eps, s);
+                             ws->opts.alpha0, adv_h ? 1 : 0, ws->utiles ? 1 : 0, ws->sc,
+                             ws->status, ws->frozen, ws->opts.freeze_eps, s);
   }));
   ws->h_valid = adv_h;
   if (ws->opts.recur) {

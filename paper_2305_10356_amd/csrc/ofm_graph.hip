@@ -144,6 +144,80 @@ __global__ void graph_pack_kernel(int64_t n, const int32_t* __restrict__ sched,
   }
 }
 
+// Upper-triangle copy (entries with column > row), used for the per-column
+// quadratic forms diag(V^T A V) of the f1 line searches: with A symmetric,
+// sum_ij w_ij V_ic V_jc = 2 sum_{i<j} w_ij V_ic V_jc when no row has a
+// self-loop.  Per row: the number of such entries; flags |= 1 if any row has
+// a self-loop (the copy is then not built).
+__global__ void graph_upper_count_kernel(int64_t n, const int32_t* __restrict__ row_ptr,
+                                         const int32_t* __restrict__ col_idx,
+                                         int32_t* __restrict__ ucnt, int* flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c = 0;
+  bool loop = false;
+  for (int64_t t = row_ptr[i]; t < row_ptr[i + 1]; ++t) {
+    const int j = col_idx[t];
+    c += j > i ? 1 : 0;
+    loop = loop || j == i;
+  }
+  ucnt[i] = c;
+  if (loop) atomicOr(flags, 1);
+}
+
+// entries with column > row of the row at upper position p (a wavefront per
+// position), in their CSR order, compacted to the packed stream at usptr[p];
+// cold marks as in graph_pack_kernel
+__global__ void graph_pack_upper_kernel(int64_t nu, const int32_t* __restrict__ usched,
+                                        const int32_t* __restrict__ row_ptr,
+                                        const int32_t* __restrict__ col_idx,
+                                        const double* __restrict__ w64,
+                                        const int32_t* __restrict__ usptr,
+                                        PkEnt32* __restrict__ pk32, PkEnt64* __restrict__ pk64,
+                                        int cold_below) {
+  const int64_t p = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const int lane = threadIdx.x & 63;
+  if (p >= nu) return;  // uniform over the wavefront
+  const int row = usched[p];
+  const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+  int64_t o = usptr[p];
+  for (int64_t base = b; base < e; base += 64) {
+    const int64_t t = base + lane;
+    const int c0 = t < e ? col_idx[t] : -1;
+    const bool keep = c0 > row;
+    const unsigned long long m = __ballot(keep);
+    if (keep) {
+      const int64_t at = o + __popcll(m & ((1ull << lane) - 1ull));
+      const int c = (row_ptr[c0 + 1] - row_ptr[c0] < cold_below)
+                        ? (int)((unsigned)c0 | 0x80000000u)
+                        : c0;
+      const double w = w64[t];
+      if (pk32) pk32[at] = PkEnt32{c, (float)w};
+      if (pk64) pk64[at] = PkEnt64{c, 0, w};
+    }
+    o += __popcll(m);
+  }
+}
+
+hipError_t launch_graph_upper_count(int64_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                                    int32_t* ucnt, int* flags, hipStream_t s) {
+  const int64_t nb = (n + 255) / 256;
+  hipLaunchKernelGGL(graph_upper_count_kernel, dim3((unsigned)nb), dim3(256), 0, s, n, row_ptr,
+                     col_idx, ucnt, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_graph_pack_upper(int64_t nu, const int32_t* usched, const int32_t* row_ptr,
+                                   const int32_t* col_idx, const double* w64,
+                                   const int32_t* usptr, void* pk32, void* pk64, int cold_below,
+                                   hipStream_t s) {
+  const int64_t nb = (nu + 3) / 4;
+  hipLaunchKernelGGL(graph_pack_upper_kernel, dim3((unsigned)nb), dim3(256), 0, s, nu, usched,
+                     row_ptr, col_idx, w64, usptr, static_cast<PkEnt32*>(pk32),
+                     static_cast<PkEnt64*>(pk64), cold_below);
+  return hipGetLastError();
+}
+
 hipError_t launch_graph_check(int64_t n, int64_t nnz, const int32_t* row_ptr,
                               const int32_t* col_idx, const double* vals, double* deg,
                               int* flags, hipStream_t s) {

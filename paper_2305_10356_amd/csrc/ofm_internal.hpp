@@ -108,6 +108,14 @@ struct LaplacianDev {
   double* w64_csr = nullptr;   // [nnz] w_ij in input CSR order
   bool reorder = true;
   int cold_below = 0;          // columns of rows with fewer entries carry the cold mark
+  // upper-triangle copy (column > row) for diag(V^T A V): rows with at least
+  // one such entry, by that count, descending (nu rows, nnzu entries; none
+  // when nu == 0)
+  int64_t nu = 0, nnzu = 0;
+  int32_t* usched = nullptr;   // [nu] upper position -> row
+  int32_t* usptr = nullptr;    // [nu+1]
+  void* upk32 = nullptr;       // [nnzu] {int col, float w}
+  void* upk64 = nullptr;       // [nnzu] {int col, int pad, double w}
 };
 
 // Arguments of the N x k kernels (everything a mode may need).
@@ -152,7 +160,11 @@ struct PassArgs {
 };
 
 // kFlagHC: gathers of rows with the cold mark use the non-temporal policy
-enum : int { kFlagCheck = 1, kFlagRestart = 2, kFlagFirst = 4, kFlagH = 8, kFlagHC = 16 };
+// kFlagUpper (kAVF1): the graph is the upper-triangle copy and the pass sums
+// V_ic (sum_{j > i} w_ij V_jc) per column; the line search then takes
+// diag(V^T A V)_c = -(V^T V)_cc - 2 x that sum
+enum : int { kFlagCheck = 1, kFlagRestart = 2, kFlagFirst = 4, kFlagH = 8, kFlagHC = 16,
+             kFlagUpper = 32 };
 
 // Batched solves: one launch per pass covers every graph of a width group.
 struct BatchGraph {
@@ -220,8 +232,11 @@ hipError_t launch_finalize(const double* partials, int nb, int nv, double* out, 
                            hipStream_t s, int split, double* out2);
 // advance_h: also H := (X + V D)^T A (X + V D) from X^T A V, V^T A V and the
 // step sizes D (the f2 directions then need no stored A X)
-hipError_t launch_linesearch(int k, int variant, int first, double alpha0, int advance_h, double* sc,
-                             int* status, const int* frozen, double freeze_eps, hipStream_t s);
+// upper_fd: the diag(V^T A V) slot holds the upper-triangle sums of a
+// kFlagUpper pass, turned into diag(V^T A V) first
+hipError_t launch_linesearch(int k, int variant, int first, double alpha0, int advance_h,
+                             int upper_fd, double* sc, int* status, const int* frozen,
+                             double freeze_eps, hipStream_t s);
 hipError_t launch_select_roots(int tri, int64_t count, const double* coef, double* alpha,
                                int32_t* nroots, hipStream_t s);
 hipError_t launch_residual(int k, int variant, double normA2, double* sc, int* status,
@@ -246,6 +261,12 @@ hipError_t launch_graph_weights(int64_t n, const int32_t* row_ptr, const int32_t
 hipError_t launch_graph_pack(int64_t n, const int32_t* sched, const int32_t* row_ptr,
                              const int32_t* col_idx, const double* w64, const int32_t* sptr,
                              void* pk32, void* pk64, int cold_below, hipStream_t s);
+hipError_t launch_graph_upper_count(int64_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                                    int32_t* ucnt, int* flags, hipStream_t s);
+hipError_t launch_graph_pack_upper(int64_t nu, const int32_t* usched, const int32_t* row_ptr,
+                                   const int32_t* col_idx, const double* w64,
+                                   const int32_t* usptr, void* pk32, void* pk64, int cold_below,
+                                   hipStream_t s);
 
 // Post-processing (ofm_post.hip)
 hipError_t launch_convert(int64_t count, int to_fp64, const void* src, void* dst, hipStream_t s);

@@ -636,6 +636,8 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
 
   constexpr bool check = CHECK;
   const bool restart = (a.flags & kFlagRestart) != 0;
+  // upper-triangle pass: V_i times its sum over the entries above the diagonal
+  const bool upper = MODE == kAVF1 && (a.flags & kFlagUpper) != 0;
   const T* __restrict__ Z = static_cast<const T*>(a.Z);
   const auto* __restrict__ pk = static_cast<const typename EntT<T>::type*>(a.pk);
   __amdgpu_buffer_rsrc_t zr = __amdgpu_buffer_rsrc_t();
@@ -707,6 +709,11 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
           const V16<T> z = (HC && end - beg < a.cold_below)
                                 ? ld16_in<HC>(Z + (size_t)row * KP + j * G::VECN)
                                 : ld16(Z + (size_t)row * KP + j * G::VECN);
+          if (upper) {
+#pragma unroll
+            for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)z.v[q] * (double)acc.v[q];
+            continue;
+          }
 #pragma unroll
           for (int q = 0; q < G::VECN; ++q) acc.v[q] = -z.v[q] - acc.v[q];
           if (j == 0) trow[gi] = row;
@@ -744,6 +751,11 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
           const V16<T> z = (HC && end - beg < a.cold_below)
                                 ? ld16_in<HC>(Z + (size_t)row * KP + j * G::VECN)
                                 : ld16(Z + (size_t)row * KP + j * G::VECN);
+          if (upper) {
+#pragma unroll
+            for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)z.v[q] * (double)acc.v[q];
+            continue;
+          }
 #pragma unroll
           for (int q = 0; q < G::VECN; ++q) acc.v[q] = -z.v[q] - acc.v[q];
           if (j == 0) trow[gi] = row;
@@ -1410,12 +1422,19 @@ __device__ inline double block_sum256(double x, double* buf) {
 template <int KP>
 __device__ __forceinline__ void linesearch_body(int variant, int first, double alpha0,
                                                 double* sc, int* status, const int* frozen,
-                                                bool advance_h = false, double freeze_eps = 0.0) {
+                                                bool advance_h = false, double freeze_eps = 0.0,
+                                                bool upper_fd = false) {
   bool frz = frozen != nullptr && *frozen != 0;
   __shared__ double buf[256];
   __shared__ double co[4];
   const int KK = KP * KP;
   const double* M = sc + SC<KP>::M;
+  if (upper_fd) {
+    // diag(V^T A V)_c = -(V^T V)_cc - 2 sum_i V_ic sum_{j > i} w_ij V_jc
+    const int t = threadIdx.x;
+    if (t < KP) sc[SC<KP>::FD + t] = -sc[SC<KP>::P + t * KP + t] - 2.0 * sc[SC<KP>::FD + t];
+    __syncthreads();
+  }
   if (freeze_eps > 0.0) {
     const int t = threadIdx.x;
     const double g2 = block_sum256(t < KP ? sc[SC<KP>::GG + t] : 0.0, buf);
@@ -1561,9 +1580,11 @@ __device__ __forceinline__ void linesearch_body(int variant, int first, double a
 
 template <int KP>
 __global__ void __launch_bounds__(256) linesearch_kernel(int variant, int first, double alpha0,
-                                                         int advance_h, double* sc, int* status,
-                                                         const int* frozen, double freeze_eps) {
-  linesearch_body<KP>(variant, first, alpha0, sc, status, frozen, advance_h != 0, freeze_eps);
+                                                         int advance_h, int upper_fd, double* sc,
+                                                         int* status, const int* frozen,
+                                                         double freeze_eps) {
+  linesearch_body<KP>(variant, first, alpha0, sc, status, frozen, advance_h != 0, freeze_eps,
+                      upper_fd != 0);
 }
 
 // The root rules of the line search on caller-given cubics (diagnostics):
@@ -1953,11 +1974,12 @@ hipError_t launch_finalize(const double* partials, int nb, int nv, double* out, 
   return hipGetLastError();
 }
 
-hipError_t launch_linesearch(int k, int variant, int first, double alpha0, int advance_h, double* sc,
-                             int* status, const int* frozen, double freeze_eps, hipStream_t s) {
+hipError_t launch_linesearch(int k, int variant, int first, double alpha0, int advance_h,
+                             int upper_fd, double* sc, int* status, const int* frozen,
+                             double freeze_eps, hipStream_t s) {
 #define OFM_LS(KP)                                                                              \
   hipLaunchKernelGGL(linesearch_kernel<KP>, dim3(1), dim3(256), 0, s, variant, first, alpha0, \
-                     advance_h, sc, status, frozen, freeze_eps);                               \
+                     advance_h, upper_fd, sc, status, frozen, freeze_eps);                     \
   break;
   switch (k) {
     case 4: OFM_LS(4)

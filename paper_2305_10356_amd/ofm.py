@@ -20,6 +20,7 @@ OFM_F1, OFM_TRI_F1, OFM_F2, OFM_TRI_F2 = 0, 1, 2, 3
 OFM_FP64, OFM_FP32, OFM_FP32_BF16X = 0, 1, 2
 OFM_LAP_VALIDATE = 1
 OFM_LAP_NO_REORDER = 2
+OFM_LAP_NO_UPPER = 4
 
 STATUS = {
     0: "OFM_OK", -1: "OFM_E_INVALID_ARG", -2: "OFM_E_SHAPE", -3: "OFM_E_GRAPH",
@@ -93,6 +94,7 @@ _SIGS = {
     "ofm_laplacian_destroy": (_I, [_P]),
     "ofm_laplacian_info": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                 ctypes.POINTER(_D), _P]),
+    "ofm_laplacian_upper": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "ofm_apply_A": (_I, [_P, _I, _I, _P, _P, _P]),
     "ofm_workspace_create": (_I, [_P, _I, ctypes.POINTER(Opts), ctypes.POINTER(_P)]),
     "ofm_workspace_destroy": (_I, [_P]),
@@ -187,12 +189,14 @@ class Laplacian:
     """Handle of the shifted normalized Laplacian A = L - 2I of a graph."""
 
     def __init__(self, row_ptr, col_idx, vals=None, validate: bool = False,
-                 reorder: bool = True, groups=None, stream=None):
+                 reorder: bool = True, groups=None, stream=None, upper: bool = True):
         """``vals``: optional edge weights, FP64 or FP32 (a tensor keeps its
         dtype; anything else is taken as FP64).  ``groups``: optional
         int32[n] (a host array or a tensor, e.g. the cluster labels of an
         earlier solve; negative = none) that lays the row-processing order out
-        for the XCDs (``ofm_build_laplacian_grouped``)."""
+        for the XCDs (``ofm_build_laplacian_grouped``).  ``upper=False``
+        builds no upper-triangle copy (``OFM_LAP_NO_UPPER``): the f1 line
+        searches then take diag(V^T A V) from the full product A V."""
         torch = _torch()
         lib = load()
         self._lib = lib
@@ -205,7 +209,8 @@ class Laplacian:
             else:
                 vv = torch.as_tensor(vals, dtype=torch.float64).contiguous().cuda()
         n = rp.numel() - 1
-        flags = (OFM_LAP_VALIDATE if validate else 0) | (0 if reorder else OFM_LAP_NO_REORDER)
+        flags = ((OFM_LAP_VALIDATE if validate else 0) | (0 if reorder else OFM_LAP_NO_REORDER)
+                 | (0 if upper else OFM_LAP_NO_UPPER))
         h = ctypes.c_void_p()
         if groups is None:
             st = lib.ofm_build_laplacian(n, ci.numel(), _ptr(rp), _ptr(ci) if ci.numel() else None,
@@ -238,6 +243,14 @@ class Laplacian:
                                             ctypes.byref(na), deg.ctypes.data_as(ctypes.c_void_p)),
                "ofm_laplacian_info")
         return {"n": n.value, "nnz": nnz.value, "normA2": na.value, "degrees": deg}
+
+    def upper(self):
+        """(rows, entries) of the upper-triangle copy; (0, 0) when none."""
+        r = ctypes.c_int64()
+        e = ctypes.c_int64()
+        _check(self._lib.ofm_laplacian_upper(self.handle, ctypes.byref(r), ctypes.byref(e)),
+               "ofm_laplacian_upper")
+        return r.value, e.value
 
     def apply(self, Z, Y=None, stream=None):
         """Y = A Z (same dtype as Z)."""

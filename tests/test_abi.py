@@ -62,6 +62,7 @@ def test_host_argument_checks(lib):
     assert lib.ofm_select_roots(0, 3, None, p16, p16, None) == -1
     assert lib.ofm_select_roots(1, 0, None, None, None, None) == 0
     assert lib.ofm_laplacian_destroy(None) == -1
+    assert lib.ofm_laplacian_upper(None, None, None) == -1
     assert lib.ofm_workspace_destroy(None) == -1
     opts = ofm.Opts(0, 1, 10, 1, 0, 0, 0.0, 0.0)
     assert lib.ofm_workspace_create(None, 8, ctypes.byref(opts), ctypes.byref(h)) == -1

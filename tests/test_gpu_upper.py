@@ -1,0 +1,175 @@
+"""The upper-triangle copy of the Laplacian (entries with column > row) and the
+f1 line searches that take diag(V^T A V) from it (Section 3.2: the OFM-f1 and
+TriOFM-f1 cubics need only those quadratic forms of V; with A symmetric,
+diag(V^T A V) = -diag(V^T V) - 2 sum_i V_i sum_{j>i} w_ij V_j).
+
+* its size, and the Laplacians that build none (self-loops, index order,
+  grouped order, the opt-out flag);
+* teacher-forced steps through it against the FP64 oracle, and against the
+  same step with the full product A V from the same state."""
+import sys
+
+import numpy as np
+import pytest
+
+import stepcheck
+from oracle import ofm_oracle as O
+from paper_2305_10356_amd import graphs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ofm(lib):
+    from paper_2305_10356_amd import ofm as m
+    return m
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def upper_size(rp, ci):
+    """(rows with an entry above the diagonal, entries above the diagonal)"""
+    n = len(rp) - 1
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    up = ci > rows
+    return int(np.count_nonzero(np.bincount(rows[up], minlength=n))), int(up.sum())
+
+
+@pytest.fixture(scope="module")
+def dcsbm20k():
+    g, _ = graphs.workload("dcsbm-n2m-k32", n=20000)
+    return g
+
+
+def test_upper_copy_size(ofm, dcsbm20k):
+    g = dcsbm20k
+    lap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    rows, ents = lap.upper()
+    say(f"upper copy: {rows} rows, {ents} entries of {len(g.col_idx)}")
+    assert (rows, ents) == upper_size(g.row_ptr, g.col_idx)
+    assert 2 * ents == len(g.col_idx)      # symmetric, no self-loops
+    assert rows < g.n                      # the last node has nothing above it
+    for kw in ({"upper": False}, {"reorder": False}, {"groups": g.labels}):
+        assert ofm.Laplacian(g.row_ptr, g.col_idx, **kw).upper() == (0, 0), kw
+    # one self-loop: no copy (the identity above needs w_ii = 0)
+    n = 6
+    ent = sorted([(i, (i + 1) % n) for i in range(n)] + [((i + 1) % n, i) for i in range(n)]
+                 + [(2, 2)])
+    rp = np.zeros(n + 1, dtype=np.int32)
+    for a, _ in ent:
+        rp[a + 1] += 1
+    rp = np.cumsum(rp).astype(np.int32)
+    ci = np.array([b for _, b in ent], dtype=np.int32)
+    assert ofm.Laplacian(rp, ci).upper() == (0, 0)
+
+
+F1_VARS = [("f1", O.F1), ("tri-f1", O.TRI_F1)]
+
+
+def teacher_forced_pair(ofm, g, x0, variant, vid, precision, checkpoints, tol, restart):
+    """Steps of a workspace on the Laplacian with the upper copy, each checked
+    against the oracle's step from the same state and against a workspace on
+    the Laplacian without it, set to that state."""
+    dt = torch.float64 if precision == ofm.OFM_FP64 else torch.float32
+    fp64 = precision == ofm.OFM_FP64
+    k = x0.shape[1]
+    olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
+    lu = ofm.Laplacian(g.row_ptr, g.col_idx)
+    lf = ofm.Laplacian(g.row_ptr, g.col_idx, upper=False)
+    assert lu.upper()[1] > 0 and lf.upper() == (0, 0)
+    opts = O.Options(variant=vid, restart=restart)
+    wu = ofm.Workspace(lu, k, variant=variant, precision=precision, restart=restart,
+                       check_every=1000000)
+    wf = ofm.Workspace(lf, k, variant=variant, precision=precision, restart=restart,
+                       check_every=1000000)
+    x0 = x0.astype(np.float32) if not fp64 else x0
+    Xu, Xf = dev(x0, dt), dev(x0, dt)
+    X0h = host(Xu)
+    wu.init(Xu)
+    wf.init(Xf)
+    st_o, info_o = O.init(olap, X0h, opts)
+    assert stepcheck.rel(host(Xu), st_o.X) < tol
+    assert stepcheck.rel(host(Xu), host(Xf)) < (1e-12 if fp64 else 1e-5)
+    flips = []
+    for t in range(1, max(checkpoints) + 1):
+        if t not in checkpoints:
+            wu.step(Xu)
+            continue
+        Xh = host(Xu)
+        Vp, Gp = wu.get_state()
+        state = O.State(X=Xh, V_prev=host(Vp), G_prev=host(Gp), t=t)
+        st_o, info_o = O.step(olap, state, opts)
+        # the full-product workspace from the same state
+        Xf = Xu.clone()
+        wf.set_state(Xf, Vp.clone(), Gp.clone(), t)
+        wu.step(Xu)
+        wf.step(Xf)
+        gu, gf = wu.step_info(), wf.step_info()
+        ex, ea, eb, fl = stepcheck.compare_step(vid, k, Xh, host(Xu), gu, info_o, st_o.X, fp64,
+                                                say=say, G_prev=state.G_prev)
+        flips += [(t, c, why) for c, why in fl]
+        # coefficients of the two device forms: the same cubics up to the
+        # rounding of the quadratic forms
+        du = stepcheck.rel(gu["coeffs"], gf["coeffs"])
+        say(f"  {variant} t={t} dX={ex:.2e} dalpha={ea:.2e} coeffs upper/full {du:.2e}")
+        assert ex < tol, (variant, t, "X")
+        assert du < (1e-12 if fp64 else 1e-4), (variant, t, "coefficients upper vs full")
+        if not fl:
+            assert stepcheck.rel(host(Xu), host(Xf)) < (1e-12 if fp64 else 1e-4)
+    assert len(flips) <= 2, flips
+
+
+@pytest.mark.parametrize("variant,vid", F1_VARS)
+@pytest.mark.parametrize("k", [8, 32])
+def test_teacher_forced_upper_fp64(ofm, dcsbm20k, variant, vid, k):
+    g = dcsbm20k
+    x0 = graphs.initial_x(g.n, k, np.random.default_rng([21, k]))
+    say(f"teacher-forced FP64 upper copy, 20k-node DC-SBM, k={k} {variant}")
+    teacher_forced_pair(ofm, g, x0, variant, vid, ofm.OFM_FP64, {1, 2, 5, 12, 30}, 1e-10,
+                        restart=O.is_tri(vid))
+
+
+@pytest.mark.parametrize("variant,vid", F1_VARS)
+@pytest.mark.parametrize("k", [4, 16, 64])
+def test_teacher_forced_upper_fp32(ofm, dcsbm20k, variant, vid, k):
+    g = dcsbm20k
+    x0 = graphs.initial_x(g.n, k, np.random.default_rng([22, k]))
+    say(f"teacher-forced FP32 upper copy, 20k-node DC-SBM, k={k} {variant}")
+    teacher_forced_pair(ofm, g, x0, variant, vid, ofm.OFM_FP32, {1, 2, 5, 12}, 1e-4,
+                        restart=O.is_tri(vid))
+
+
+def test_upper_small_graphs(ofm):
+    # fewer rows than one tile, a hub above every other node (a row processed
+    # a wavefront at a time in the upper copy) and rows with nothing above them
+    rng = np.random.default_rng(5)
+    n = 150
+    edges = {(0, j) for j in range(1, n)}
+    edges |= {(int(a), int(b)) for a, b in rng.integers(1, n, size=(200, 2)) if a != b}
+    edges = {(min(a, b), max(a, b)) for a, b in edges}
+    ent = sorted(list(edges) + [(b, a) for a, b in edges])
+    rp = np.zeros(n + 1, dtype=np.int32)
+    for a, _ in ent:
+        rp[a + 1] += 1
+    rp = np.cumsum(rp).astype(np.int32)
+    ci = np.array([b for _, b in ent], dtype=np.int32)
+    g = graphs.Graph(n=n, row_ptr=rp, col_idx=ci, labels=np.zeros(n, dtype=np.int32), meta={})
+    lap = ofm.Laplacian(rp, ci)
+    assert lap.upper() == upper_size(rp, ci)
+    for variant, vid in F1_VARS:
+        x0 = graphs.initial_x(n, 8, np.random.default_rng(6))
+        teacher_forced_pair(ofm, g, x0, variant, vid, ofm.OFM_FP64, {1, 3, 10}, 1e-10,
+                            restart=O.is_tri(vid))
