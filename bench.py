@@ -31,7 +31,7 @@ def log(*a):
 
 
 def pass_bytes(name: str, n: int, nnz: int, k: int, esz: int, variant: str, ntiles: int,
-               recur: bool = False, layout: bool = False) -> float:
+               recur: bool = False, layout: bool = False, upper=None) -> float:
     """HBM bytes of one launch of a pass, each array moved once.  The graph
     part of an SpMM is counted as the method needs it (layout=False): the
     pattern-only CSR of an unweighted graph, 4 B per entry, row_ptr (4 B per
@@ -45,8 +45,20 @@ def pass_bytes(name: str, n: int, nnz: int, k: int, esz: int, variant: str, ntil
     update also reads A X, A V and writes A X, and G is formed in a pass of
     its own from the stored A X.
     f2 at k >= 32 without the recurrence stores A V and forms X^T A V, V^T A V
-    in a streaming pass ("other")."""
+    in a streaming pass ("other").
+    upper = (rows, entries) of the Laplacian's upper-triangle copy, from which
+    the f1 variants without the recurrence take diag(V^T A V): their SpMM of V
+    then reads the entries above the diagonal (pattern-only: 4 B each, n + 1
+    row offsets and D^{-1/2}; layout: packed entries, offsets and row ids of
+    the copy's rows) and V."""
     B = n * k * esz
+    f1_upper = (upper is not None and upper[1] > 0 and not recur
+                and variant in ("f1", "tri-f1"))
+    if name == "spmm_v" and f1_upper:
+        nu, nnzu = upper
+        if layout:
+            return nnzu * (8 if esz == 4 else 16) + 8 * nu + 4 * ((nu + 15) // 16 + 1) + B
+        return 4 * nnzu + 4 * (n + 1) + esz * n + B
     if layout:
         graph = nnz * (8 if esz == 4 else 16) + 8 * n + 4 * (ntiles + 1)
     else:
@@ -676,6 +688,7 @@ def main():
     t_lap = time.perf_counter() - t
     del d_rp, d_ci
     ntiles = (n + 15) // 16
+    upper = lap.upper()
     if args.postprocess_only:
         wsp = ofm.Workspace(lap, k, variant=args.variant, precision=ofm.OFM_FP32, check_every=10,
                             tol=1e-4, max_iter=3000, restart=args.variant.startswith("tri"))
@@ -729,7 +742,7 @@ def main():
         if cnt == 0:
             continue
         avg_ms = ms / cnt
-        b = pass_bytes(name, n, nnz, k, 4, args.variant, ntiles, args.recur)
+        b = pass_bytes(name, n, nnz, k, 4, args.variant, ntiles, args.recur, upper=upper)
         passes[name] = {"launches": cnt, "avg_us": round(1e3 * avg_ms, 2),
                         "ms_per_step": round(ms / breakdown_steps, 4)}
         if b > 0:
@@ -757,8 +770,9 @@ def main():
     def launch_roof(p):
         ms, cnt = tm[p]
         avg = ms / cnt
-        alg = pass_bytes(p, n, nnz, k, 4, args.variant, ntiles, args.recur)
-        lay = pass_bytes(p, n, nnz, k, 4, args.variant, ntiles, args.recur, layout=True)
+        alg = pass_bytes(p, n, nnz, k, 4, args.variant, ntiles, args.recur, upper=upper)
+        lay = pass_bytes(p, n, nnz, k, 4, args.variant, ntiles, args.recur, layout=True,
+                         upper=upper)
         ach = alg / (avg * 1e-3) / 1e9
         return {"launches": cnt, "avg_us": round(1e3 * avg, 2), "alg_bytes_per_launch": int(alg),
                 "achieved": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),

@@ -1858,6 +1858,16 @@ extern "C" ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps
       d.tiles = tt->dev;
       d.ntiles = tt->ntiles;
       d.pk = L->g.pk32;
+      if (L->g.nu > 0) {
+        for (auto& ut : L->ut)
+          if (ut.tr == tt->tr) {
+            d.usched = L->g.usched;
+            d.usptr = L->g.usptr;
+            d.utiles = ut.dev;
+            d.untiles = ut.ntiles;
+            d.upk = L->g.upk32;
+          }
+      }
       const size_t blk = (size_t)L->g.n * k * 4;
       char* p = g.bufs + buf_off[m];
       d.V[0] = p;
@@ -2000,6 +2010,7 @@ static ofm_status batch_iteration(ofm_batch B, BatchGroup& g, int cur, int64_t t
   base.tpw = cand_tpw(cand);
   base.check_every = o.check_every;
   base.ngraphs = (int)g.idx.size();
+  base.upper = (o.variant == OFM_F1 || o.variant == OFM_TRI_F1) && !o.recur;
   const int rs = o.restart ? kFlagRestart : 0;
   const int fs = first ? kFlagFirst : 0;
   if (first) OFMCHK(bpass(g, base, kGramM, 0, false));
@@ -2020,7 +2031,7 @@ static ofm_status batch_iteration(ofm_batch B, BatchGroup& g, int cur, int64_t t
     if (f2) OFMCHK(bpass(g, base, kGPassF2, rs | fs, false));
   }
   OFMCHK(bpass(g, base, kVPass, rs | fs, false));
-  OFMCHK(bpass(g, base, f2 ? kAVF2 : kAVF1, 0, true));
+  OFMCHK(bpass(g, base, f2 ? kAVF2 : kAVF1, base.upper ? kFlagUpper : 0, true));
   HIPCHK(launch_batch_linesearch(g.k, base, o.alpha0, first && o.first_step == 1, g.stream));
   if (o.recur) {
     OFMCHK(bpass(g, base, kUpdateR, f2 ? kFlagH : 0, false));

@@ -174,6 +174,12 @@ struct BatchGraph {
   const int32_t* tiles = nullptr;
   int64_t ntiles = 0;
   const void* pk = nullptr;
+  // upper-triangle copy of the Laplacian (upk null: none)
+  const int32_t* usched = nullptr;
+  const int32_t* usptr = nullptr;
+  const int32_t* utiles = nullptr;
+  int64_t untiles = 0;
+  const void* upk = nullptr;
   void* X = nullptr;
   void* V[2] = {nullptr, nullptr};
   void* G[2] = {nullptr, nullptr};
@@ -215,6 +221,7 @@ struct BatchArgs {
   int check_every = 1;
   int nv = 0;
   int off = 0;       // first scalar slot the mode's products go to
+  int upper = 0;     // f1: diag(V^T A V) from the upper-triangle copies (graphs that have one)
 };
 hipError_t launch_batch_spmm(int k, BatchArgs& b, hipStream_t s);
 hipError_t launch_batch_dense(int k, BatchArgs& b, hipStream_t s);

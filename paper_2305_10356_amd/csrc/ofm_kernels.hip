@@ -2087,6 +2087,19 @@ __device__ inline PassArgs batch_pass_args(const BatchArgs& b, const BatchGraph&
       a.Zg = b.bf16 ? d.Vb : nullptr;
       a.X = d.X;
       a.Y = d.AV;
+      if (b.mode == kAVF1 && (b.flags & kFlagUpper)) {
+        if (d.upk) {
+          // the upper-triangle copy, over the workers the full graph uses
+          a.sched = d.usched;
+          a.sptr = d.usptr;
+          a.tiles = d.utiles;
+          a.ntiles = d.untiles;
+          a.pk = d.upk;
+          a.Y = nullptr;
+        } else {
+          a.flags &= ~kFlagUpper;
+        }
+      }
       break;
     case kUpdate:
       a.X = d.X;
@@ -2223,7 +2236,7 @@ __global__ void __launch_bounds__(256) batch_linesearch_kernel(BatchArgs b, doub
   const BatchGraph& d = b.graphs[blockIdx.x];
   if (*d.active == 0) return;
   linesearch_body<KP>(b.variant, first_fixed, alpha0, d.sc, d.status, nullptr, false,
-                      b.freeze_eps);
+                      b.freeze_eps, b.upper != 0 && d.upk != nullptr);
 }
 
 // residual of X^t; a graph whose residual meets the tolerance (or whose

@@ -137,9 +137,26 @@ def host(t):
                                                ("tri-f2", O.TRI_F2, False),
                                                ("f1", O.F1, True)])
 def test_batch_teacher_forced_vs_oracle(batch_graphs, variant, vid, recur):
+    gs, laps = batch_graphs
+    teacher_forced_batch(gs, laps, variant, vid, recur)
+
+
+@pytest.mark.parametrize("variant,vid", [("f1", O.F1), ("tri-f1", O.TRI_F1)])
+def test_batch_teacher_forced_mixed_upper(batch_graphs, variant, vid):
+    """Members with and without the upper-triangle copy in one batch: the f1
+    line searches take diag(V^T A V) from the copy where a member has one and
+    from the full product A V where it does not."""
+    from paper_2305_10356_amd import ofm
+    gs, _ = batch_graphs
+    laps = [ofm.Laplacian(g.row_ptr, g.col_idx, upper=(i % 2 == 0))
+            for i, (g, _, _) in enumerate(gs)]
+    assert [lap.upper()[1] > 0 for lap in laps] == [i % 2 == 0 for i in range(len(gs))]
+    teacher_forced_batch(gs, laps, variant, vid, False)
+
+
+def teacher_forced_batch(gs, laps, variant, vid, recur):
     import stepcheck
     from paper_2305_10356_amd import ofm
-    gs, laps = batch_graphs
     ks = [k for _, _, k in gs]
     restart = O.is_tri(vid)
     B = ofm.Batch(laps, ks, variant=variant, max_iter=1000, tol=0.0, check_every=10,
