@@ -47,24 +47,32 @@ def pass_bytes(name: str, n: int, nnz: int, k: int, esz: int, variant: str, ntil
     f2 at k >= 32 without the recurrence stores A V and forms X^T A V, V^T A V
     in a streaming pass ("other").
     upper = (rows, entries) of the Laplacian's upper-triangle copy, from which
-    the f1 variants without the recurrence take diag(V^T A V): their SpMM of V
-    then reads the entries above the diagonal (pattern-only: 4 B each, n + 1
-    row offsets and D^{-1/2}; layout: packed entries, offsets and row ids of
-    the copy's rows) and V."""
+    the variants without the recurrence take their products with A V (f1:
+    diag(V^T A V); f2 at k <= 32: V^T A V, with X^T A V = (AX)^T V formed in
+    the V pass, which then also reads the A X that the SpMM of X writes): the
+    SpMM of V then reads the entries above the diagonal (pattern-only: 4 B
+    each, n + 1 row offsets and D^{-1/2}; layout: packed entries, offsets and
+    row ids of the copy's rows) and V."""
     B = n * k * esz
-    f1_upper = (upper is not None and upper[1] > 0 and not recur
-                and variant in ("f1", "tri-f1"))
-    if name == "spmm_v" and f1_upper:
+    f2 = variant in ("f2", "tri-f2")
+    use_upper = (upper is not None and upper[1] > 0 and not recur and (not f2 or k <= 32))
+    f2u = use_upper and f2
+    if name == "spmm_v" and use_upper:
         nu, nnzu = upper
         if layout:
             return nnzu * (8 if esz == 4 else 16) + 8 * nu + 4 * ((nu + 15) // 16 + 1) + B
         return 4 * nnzu + 4 * (n + 1) + esz * n + B
+    if f2u and name == "v":
+        return 5 * B                             # G, V_prev, X, A X read; V write
+    if f2u and name == "spmm_x":
+        graph = (nnz * (8 if esz == 4 else 16) + 8 * n + 4 * (ntiles + 1) if layout
+                 else 4 * nnz + 4 * (n + 1) + esz * n)
+        return graph + 4 * B                     # X, G_prev read; G, A X write
     if layout:
         graph = nnz * (8 if esz == 4 else 16) + 8 * n + 4 * (ntiles + 1)
     else:
         graph = 4 * nnz + 4 * (n + 1) + esz * n
-    f2 = variant in ("f2", "tri-f2")
-    split = f2 and not recur and k >= 32
+    split = f2 and not recur and k >= 32 and not f2u
     if name == "spmm_x":
         # X; without the recurrence G_prev read + G write, with it A X write
         return graph + (2 * B if recur else 3 * B)

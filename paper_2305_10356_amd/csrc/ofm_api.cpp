@@ -141,8 +141,12 @@ struct ofm_workspace_s {
   const TileTable* tiles = nullptr;
   const void* pk = nullptr;
   // tiles of the Laplacian's upper-triangle copy when the line search's
-  // diag(V^T A V) comes from it (f1 variants without the recurrence)
+  // products with A V come from it (without the recurrence: diag(V^T A V) for
+  // f1; V^T A V for f2 at k <= 32, with X^T A V = (AX)^T V in the V pass from
+  // the A X the SpMM of X stores)
   const TileTable* utiles = nullptr;
+  bool f2u = false;       // the f2 form above
+  bool products = false;  // f2 at k >= 32 otherwise: A V stored, products in a pass
   bool hc = false;       // gathers with the hot/cold cache policy (opts.gather)
   // per-pass event timing
   unsigned timing = 0;   // bit i: record events around the kernels of pass i
@@ -192,9 +196,11 @@ int pass_kind(int mode) {
     case kGF2: return OFM_PASS_SPMM_X;
     case kGPassF2:
     case kGPassF1: return OFM_PASS_G;
-    case kVPass: return OFM_PASS_V;
+    case kVPass:
+    case kVPassE: return OFM_PASS_V;
     case kAVF1:
-    case kAVF2: return OFM_PASS_SPMM_V;
+    case kAVF2:
+    case kSF2: return OFM_PASS_SPMM_V;
     case kUpdate:
     case kUpdateR: return OFM_PASS_UPDATE;
     case kEF: return OFM_PASS_OTHER;
@@ -857,12 +863,15 @@ extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_o
   ws->esz = prec == OFM_FP64 ? 8 : 4;
   ws->tiles = tt;
   ws->pk = prec == OFM_FP64 ? lap->g.pk64 : lap->g.pk32;
-  if (lap->g.nu > 0 && !is_f2(o.variant) && !o.recur) {
+  if (lap->g.nu > 0 && !o.recur && (!is_f2(o.variant) || k <= 32)) {
     for (auto& t : lap->ut)
       if (t.tr == tt->tr) ws->utiles = &t;
   }
+  ws->f2u = ws->utiles != nullptr && is_f2(o.variant);
+  ws->products = f2_products_pass(o, k) && !ws->f2u;
   const size_t blk = (size_t)ws->n * k * ws->esz;
-  const int nvmax = 2 * k * k + 3 * k;
+  // widest partial row: the V pass with X^T A V, [P | C | diag V^T G | 0 | E]
+  const int nvmax = 3 * k * k + 3 * k;
   const int ny = (kMaxBlocks + kFinChunk - 1) / kFinChunk;
   ofm_status st = OFM_OK;
   auto fail = [&](ofm_status s) {
@@ -874,7 +883,7 @@ extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_o
     if ((st = dev_alloc(reinterpret_cast<char**>(&ws->G[i]), blk)) != OFM_OK) return fail(st);
   }
   if ((st = dev_alloc(reinterpret_cast<char**>(&ws->AX), blk)) != OFM_OK) return fail(st);
-  if ((o.recur || f2_products_pass(o, k)) &&
+  if ((o.recur || ws->products) &&
       (st = dev_alloc(reinterpret_cast<char**>(&ws->AV), blk)) != OFM_OK)
     return fail(st);
   if (o.precision == OFM_FP32_BF16X) {
@@ -1060,6 +1069,7 @@ static ofm_status direction(ofm_workspace ws, void* X, const void* Gp, const voi
     a.G = ws->G[ws->cur];
     a.Gp = Gp;
     a.Vp = Vp;
+    a.Y = ws->f2u ? ws->AX : nullptr;  // X^T A V of the V pass reads it
     OFMCHK(run_spmm(ws, a, s));
     if (check) HIPCHK(run_residual(ws, s, true));
   } else {
@@ -1084,14 +1094,22 @@ static ofm_status direction(ofm_workspace ws, void* X, const void* Gp, const voi
 static ofm_status search_and_update(ofm_workspace ws, void* X, const void* Vp, bool first,
                                     hipStream_t s) {
   const int cur = ws->cur;
-  PassArgs v = base_args(ws, kVPass, (first ? kFlagFirst : 0) | (ws->opts.restart ? kFlagRestart : 0));
+  PassArgs v = base_args(ws, ws->f2u ? kVPassE : kVPass,
+                         (first ? kFlagFirst : 0) | (ws->opts.restart ? kFlagRestart : 0));
   v.G = ws->G[cur];
   v.Vp = Vp;
   v.V = ws->V[cur];
   v.Vb = ws->Vb;
   v.X = X;
+  v.AX = ws->f2u ? ws->AX : nullptr;
   OFMCHK(run_dense(ws, v, s));
-  if (f2_products_pass(ws->opts, ws->k)) {
+  if (ws->f2u) {
+    // V^T A V from the upper-triangle copy (X^T A V came with the V pass)
+    PassArgs w = base_args(ws, kSF2, 0);
+    w.Z = ws->V[cur];
+    w.Zg = ws->Vb;
+    OFMCHK(run_spmm_upper(ws, w, s));
+  } else if (ws->products) {
     // A V stored by the SpMM of the f1 form, then X^T A V and V^T A V in a
     // streaming pass (at k >= 32 the two FP64 products in the SpMM's epilogue
     // cost it more occupancy than the pass costs)
@@ -1125,7 +1143,7 @@ static ofm_status search_and_update(ofm_workspace ws, void* X, const void* Vp, b
   const bool adv_h = is_f2(ws->opts.variant) && !ws->opts.recur;
   HIPCHK(timed(ws, OFM_PASS_LINESEARCH, s, [&] {
     return launch_linesearch(ws->k, ws->opts.variant, first && ws->opts.first_step == 1,
-                             ws->opts.alpha0, adv_h ? 1 : 0, ws->utiles ? 1 : 0, ws->sc,
+                             ws->opts.alpha0, adv_h ? 1 : 0, ws->f2u ? 2 : ws->utiles ? 1 : 0, ws->sc,
                              ws->status, ws->frozen, ws->opts.freeze_eps, s);
   }));
   ws->h_valid = adv_h;

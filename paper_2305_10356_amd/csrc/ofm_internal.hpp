@@ -86,7 +86,10 @@ enum Mode : int {
   kUpdateR = 10,  // X += alpha V, AX += alpha AV, X^T X [, X^T A X]
   kGPassF1 = 11,  // G = c (AX + X M') from a stored AX, gg, gpg [, vpg]
   kGF2 = 12,      // G = a AX - b (X H' + AX M') from the gathered AX, gg, gpg [, vpg] [, H, K]
-  kEF = 13        // X^T A V, V^T A V from a stored A V
+  kEF = 13,       // X^T A V, V^T A V from a stored A V
+  kSF2 = 14,      // S = V^T U, U_i = sum_{j > i} w_ij V_j (upper-triangle copy), in F's slot
+  kVPassE = 15    // kVPass and E = (AX)^T V = X^T A V (A symmetric) from a stored A X (k <= 32);
+                  // writes [P | C | diag V^T G | 0 (diag V^T A V, unused by f2) | E]
 };
 
 struct LaplacianDev {
@@ -239,8 +242,9 @@ hipError_t launch_finalize(const double* partials, int nb, int nv, double* out, 
                            hipStream_t s, int split, double* out2);
 // advance_h: also H := (X + V D)^T A (X + V D) from X^T A V, V^T A V and the
 // step sizes D (the f2 directions then need no stored A X)
-// upper_fd: the diag(V^T A V) slot holds the upper-triangle sums of a
-// kFlagUpper pass, turned into diag(V^T A V) first
+// upper_fd = 1: the diag(V^T A V) slot holds the upper-triangle sums of a
+// kFlagUpper pass, turned into diag(V^T A V) first; 2: the V^T A V slot holds
+// S of a kSF2 pass, turned into V^T A V = -V^T V - S - S^T first
 hipError_t launch_linesearch(int k, int variant, int first, double alpha0, int advance_h,
                              int upper_fd, double* sc, int* status, const int* frozen,
                              double freeze_eps, hipStream_t s);

@@ -141,9 +141,10 @@ struct Cfg {
 
 constexpr int nbuf_of(int mode) {
   return (mode == kGF1 || mode == kGF2 || mode == kEF) ? 3
-         : mode == kAXF2 ? 2
+         : (mode == kAXF2 || mode == kSF2) ? 2
          : mode == kAVF2 ? 3
          : (mode == kGPassF2 || mode == kGPassF1) ? 3
+         : mode == kVPassE ? 3
          : (mode == kVPass || mode == kUpdateR) ? 2
          : (mode == kUpdate || mode == kGramM) ? 1
                                                 : 0;
@@ -153,7 +154,7 @@ constexpr int nfrag_of(int mode) {
 }
 constexpr int nvec_of(int mode) {
   return (mode == kGF1 || mode == kGF2 || mode == kGPassF2 || mode == kGPassF1) ? 3
-         : (mode == kVPass || mode == kAVF1 || mode == kAVF2 || mode == kGGP) ? 1
+         : (mode == kVPass || mode == kVPassE || mode == kAVF1 || mode == kAVF2 || mode == kGGP) ? 1
                                                                                : 0;
 }
 
@@ -185,6 +186,8 @@ __host__ __device__ inline int mode_nv(int mode, int flags) {
     case kGPassF2:
     case kGPassF1: return 3 * KP;
     case kVPass: return 2 * KK + KP;
+    case kVPassE: return 3 * KK + 2 * KP;
+    case kSF2: return KK;
     case kUpdateR: return KK + ((flags & kFlagH) ? KK : 0);
     case kUpdate:
     case kGramM: return KK;
@@ -203,12 +206,14 @@ __host__ __device__ inline int mode_off(int mode) {
     case kAXF2: return SC<KP>::H;
     case kAVF1:
     case kAVF2: return SC<KP>::FD;
-    case kVPass: return SC<KP>::P;
+    case kVPass:
+    case kVPassE: return SC<KP>::P;
     case kUpdate:
     case kUpdateR:
     case kGramM: return SC<KP>::M;
     case kGGP: return SC<KP>::GGP;
     case kEF: return SC<KP>::E;
+    case kSF2: return SC<KP>::F;
     default: return 0;
   }
 }
@@ -714,10 +719,12 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
             for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)z.v[q] * (double)acc.v[q];
             continue;
           }
+          if (MODE != kSF2) {
 #pragma unroll
-          for (int q = 0; q < G::VECN; ++q) acc.v[q] = -z.v[q] - acc.v[q];
+            for (int q = 0; q < G::VECN; ++q) acc.v[q] = -z.v[q] - acc.v[q];
+          }
           if (j == 0) trow[gi] = row;
-          if (MODE == kApply || MODE == kAXF2) {
+          if (MODE == kApply || MODE == kAXF2 || (MODE == kGF2 && a.Y)) {
             st16_out<HC>(static_cast<T*>(a.Y) + (size_t)row * KP + j * G::VECN, acc);
           }
           if (MODE == kAVF1 || MODE == kAVF2) {
@@ -756,10 +763,12 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
             for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)z.v[q] * (double)acc.v[q];
             continue;
           }
+          if (MODE != kSF2) {
 #pragma unroll
-          for (int q = 0; q < G::VECN; ++q) acc.v[q] = -z.v[q] - acc.v[q];
+            for (int q = 0; q < G::VECN; ++q) acc.v[q] = -z.v[q] - acc.v[q];
+          }
           if (j == 0) trow[gi] = row;
-          if (MODE == kApply || MODE == kAXF2) {
+          if (MODE == kApply || MODE == kAXF2 || (MODE == kGF2 && a.Y)) {
             st16_out<HC>(static_cast<T*>(a.Y) + (size_t)row * KP + j * G::VECN, acc);
           }
           if (MODE == kAVF1 || MODE == kAVF2) {
@@ -832,6 +841,8 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
     } else if (MODE == kAXF2) {
       tile_gram<T, KP, false>(tZ, tA, gA, lane);
       if (check) tile_gram<T, KP, true>(tA, tA, gB, lane);
+    } else if (MODE == kSF2) {
+      tile_gram<T, KP, false>(tZ, tA, gA, lane);  // S = V^T U
     } else if (MODE == kAVF2) {
       // own X rows of the tile
 #pragma unroll
@@ -872,6 +883,8 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
     if (check) block_gram_out<T, KP, true>(gB, red, prow, KK, wave, lane, WPB);
   } else if (MODE == kAVF1) {
     block_vec_out<T, KP, 1>(cacc, red, prow, 0, wave, lane, WPB);
+  } else if (MODE == kSF2) {
+    block_gram_out<T, KP, false>(gA, red, prow, 0, wave, lane, WPB);
   } else if (MODE == kAVF2) {
     block_vec_out<T, KP, 1>(cacc, red, prow, 0, wave, lane, WPB);
     block_gram_out<T, KP, false>(gA, red, prow, KP, wave, lane, WPB);
@@ -903,13 +916,15 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
   const double* sc = a.sc;
   const bool restart = (a.flags & kFlagRestart) != 0;
   const bool first = (a.flags & kFlagFirst) != 0;
+  constexpr bool VP = MODE == kVPass || MODE == kVPassE;
+  constexpr bool HASE = MODE == kVPassE;  // the V pass that also forms E
 
   // per-column scalars of this pass (beta for V, alpha for the update)
   T colscal[G::VECN];
 #pragma unroll
   for (int q = 0; q < G::VECN; ++q) colscal[q] = T(0);
   T ca = T(0), cb = T(0);
-  if (MODE == kVPass) {
+  if (VP) {
 #pragma unroll
     for (int q = 0; q < G::VECN; ++q) {
       const int c = j * G::VECN + q;
@@ -951,6 +966,12 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
   d4 gA[G::NT][G::NT], gB[G::NT][G::NT];  // per-wave products (unused with SPLIT)
   zero_gram<T, KP>(gA);
   zero_gram<T, KP>(gB);
+  constexpr int NTE = HASE ? G::NT : 1;
+  d4 gE[NTE][NTE];                         // E = (AX)^T V (kVPassE)
+#pragma unroll
+  for (int ti = 0; ti < NTE; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < NTE; ++tj) gE[ti][tj] = d4{0.0, 0.0, 0.0, 0.0};
   SplitGram<T, KP, WPB> sg;
   if constexpr (SPLIT) {
     // (source tiles, symmetry) of the product groups: t0 = 0, t1 = 1, t2 = 2
@@ -977,7 +998,7 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
       const int gi = pass * G::RPW + g;
       const bool ok = gi < cnt;
       const size_t off = (size_t)(r0 + gi) * KP + j * G::VECN;
-      if (MODE == kVPass) {
+      if (VP) {
         V16<T> v, gv, x;
         if (ok) {
           gv = ld16(static_cast<const T*>(a.G) + off);
@@ -1003,6 +1024,16 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
         if (gi < G::TR) {
           tile_store_vec<T, KP>(t0, gi, j, v);
           tile_store_vec<T, KP>(t1, gi, j, x);
+        }
+        if constexpr (HASE) {
+          V16<T> ax;
+          if (ok) {
+            ax = ld16(static_cast<const T*>(a.AX) + off);
+          } else {
+#pragma unroll
+            for (int q = 0; q < G::VECN; ++q) ax.v[q] = T(0);
+          }
+          if (gi < G::TR) tile_store_vec<T, KP>(t2, gi, j, ax);
         }
       } else if (MODE == kUpdate || MODE == kGramM) {
         V16<T> x;
@@ -1093,9 +1124,10 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    if (MODE == kVPass) {
+    if (VP) {
       tile_gram<T, KP, true>(t0, t0, gA, lane);   // P = V^T V
       tile_gram<T, KP, false>(t1, t0, gB, lane);  // C = X^T V
+      if constexpr (HASE) tile_gram<T, KP, false>(t2, t0, gE, lane);  // E = (AX)^T V
     } else if (MODE == kUpdate || MODE == kGramM) {
       tile_gram<T, KP, true>(t0, t0, gA, lane);   // M = X^T X
     } else if (MODE == kEF) {
@@ -1162,10 +1194,15 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
     } else {
       sg.out(0, true, red, prow, 0, lane);
     }
-  } else if (MODE == kVPass) {
+  } else if (VP) {
     block_gram_out<T, KP, true>(gA, red, prow, 0, wave, lane, WPB);
     block_gram_out<T, KP, false>(gB, red, prow, KK, wave, lane, WPB);
     block_vec_out<T, KP, 1>(cacc, red, prow, 2 * KK, wave, lane, WPB);
+    if constexpr (HASE) {
+      // [.. | diag V^T G | 0 (the diag V^T A V slot, unused by f2) | E]
+      for (int e = threadIdx.x; e < KP; e += blockDim.x) prow[2 * KK + KP + e] = 0.0;
+      block_gram_out<T, KP, false>(gE, red, prow, 2 * KK + 2 * KP, wave, lane, WPB);
+    }
   } else if (MODE == kUpdate || MODE == kGramM) {
     block_gram_out<T, KP, true>(gA, red, prow, 0, wave, lane, WPB);
   } else if (MODE == kUpdateR) {
@@ -1423,16 +1460,30 @@ template <int KP>
 __device__ __forceinline__ void linesearch_body(int variant, int first, double alpha0,
                                                 double* sc, int* status, const int* frozen,
                                                 bool advance_h = false, double freeze_eps = 0.0,
-                                                bool upper_fd = false) {
+                                                int upper_fd = 0) {
   bool frz = frozen != nullptr && *frozen != 0;
   __shared__ double buf[256];
   __shared__ double co[4];
   const int KK = KP * KP;
   const double* M = sc + SC<KP>::M;
-  if (upper_fd) {
+  if (upper_fd == 1) {
     // diag(V^T A V)_c = -(V^T V)_cc - 2 sum_i V_ic sum_{j > i} w_ij V_jc
     const int t = threadIdx.x;
     if (t < KP) sc[SC<KP>::FD + t] = -sc[SC<KP>::P + t * KP + t] - 2.0 * sc[SC<KP>::FD + t];
+    __syncthreads();
+  } else if (upper_fd == 2) {
+    // V^T A V = -V^T V - (S + S^T), S = sum_i V_i^T sum_{j > i} w_ij V_j;
+    // each pair (r, c), (c, r) is rewritten by one thread
+    double* F = sc + SC<KP>::F;
+    const double* P = sc + SC<KP>::P;
+    for (int e = threadIdx.x; e < KK; e += blockDim.x) {
+      const int r = e / KP, c = e % KP;
+      if (r <= c) {
+        const double w = F[r * KP + c] + F[c * KP + r];
+        F[r * KP + c] = -P[r * KP + c] - w;
+        F[c * KP + r] = -P[c * KP + r] - w;
+      }
+    }
     __syncthreads();
   }
   if (freeze_eps > 0.0) {
@@ -1584,7 +1635,7 @@ __global__ void __launch_bounds__(256) linesearch_kernel(int variant, int first,
                                                          int* status, const int* frozen,
                                                          double freeze_eps) {
   linesearch_body<KP>(variant, first, alpha0, sc, status, frozen, advance_h != 0, freeze_eps,
-                      upper_fd != 0);
+                      upper_fd);
 }
 
 // The root rules of the line search on caller-given cubics (diagnostics):
@@ -1873,6 +1924,9 @@ static hipError_t spmm_t(PassArgs& a, hipStream_t s) {
     case kAXF2: return spmm_mode<T, KP, kAXF2>(a, s);
     case kAVF1: return spmm_mode<T, KP, kAVF1>(a, s);
     case kAVF2: return spmm_mode<T, KP, kAVF2>(a, s);
+    case kSF2:
+      if constexpr (KP <= 32) return spmm_mode<T, KP, kSF2>(a, s);
+      break;
   }
   return hipErrorInvalidValue;
 }
@@ -1889,6 +1943,9 @@ static hipError_t dense_t(PassArgs& a, hipStream_t s) {
     case kGPassF2: return dense_mode<T, KP, kGPassF2>(a, s);
     case kGPassF1: return dense_mode<T, KP, kGPassF1>(a, s);
     case kVPass: return dense_mode<T, KP, kVPass>(a, s);
+    case kVPassE:
+      if constexpr (KP <= 32) return dense_mode<T, KP, kVPassE>(a, s);
+      break;
     case kUpdate: return dense_mode<T, KP, kUpdate>(a, s);
     case kUpdateR: return dense_mode<T, KP, kUpdateR>(a, s);
     case kGramM: return dense_mode<T, KP, kGramM>(a, s);
@@ -2236,7 +2293,7 @@ __global__ void __launch_bounds__(256) batch_linesearch_kernel(BatchArgs b, doub
   const BatchGraph& d = b.graphs[blockIdx.x];
   if (*d.active == 0) return;
   linesearch_body<KP>(b.variant, first_fixed, alpha0, d.sc, d.status, nullptr, false,
-                      b.freeze_eps, b.upper != 0 && d.upk != nullptr);
+                      b.freeze_eps, (b.upper != 0 && d.upk != nullptr) ? 1 : 0);
 }
 
 // residual of X^t; a graph whose residual meets the tolerance (or whose

@@ -1,7 +1,9 @@
 """The upper-triangle copy of the Laplacian (entries with column > row) and the
-f1 line searches that take diag(V^T A V) from it (Section 3.2: the OFM-f1 and
-TriOFM-f1 cubics need only those quadratic forms of V; with A symmetric,
-diag(V^T A V) = -diag(V^T V) - 2 sum_i V_i sum_{j>i} w_ij V_j).
+line searches that take their products with A V from it (Section 3.2).  With
+A symmetric and U_i = sum_{j>i} w_ij V_j: the OFM-f1 and TriOFM-f1 cubics need
+only diag(V^T A V) = -diag(V^T V) - 2 diag(V^T U); the f2 cubics need
+V^T A V = -V^T V - (V^T U + U^T V) and X^T A V = (AX)^T V, the latter formed
+in the V pass from the A X that the SpMM of X stores (k <= 32).
 
 * its size, and the Laplacians that build none (self-loops, index order,
   grouped order, the opt-out flag);
@@ -77,6 +79,7 @@ def test_upper_copy_size(ofm, dcsbm20k):
 
 
 F1_VARS = [("f1", O.F1), ("tri-f1", O.TRI_F1)]
+ALL_VARS = F1_VARS + [("f2", O.F2), ("tri-f2", O.TRI_F2)]
 
 
 def teacher_forced_pair(ofm, g, x0, variant, vid, precision, checkpoints, tol, restart):
@@ -132,7 +135,7 @@ def teacher_forced_pair(ofm, g, x0, variant, vid, precision, checkpoints, tol, r
     assert len(flips) <= 2, flips
 
 
-@pytest.mark.parametrize("variant,vid", F1_VARS)
+@pytest.mark.parametrize("variant,vid", ALL_VARS)
 @pytest.mark.parametrize("k", [8, 32])
 def test_teacher_forced_upper_fp64(ofm, dcsbm20k, variant, vid, k):
     g = dcsbm20k
@@ -142,8 +145,8 @@ def test_teacher_forced_upper_fp64(ofm, dcsbm20k, variant, vid, k):
                         restart=O.is_tri(vid))
 
 
-@pytest.mark.parametrize("variant,vid", F1_VARS)
-@pytest.mark.parametrize("k", [4, 16, 64])
+@pytest.mark.parametrize("variant,vid", ALL_VARS)
+@pytest.mark.parametrize("k", [4, 16, 32, 64])
 def test_teacher_forced_upper_fp32(ofm, dcsbm20k, variant, vid, k):
     g = dcsbm20k
     x0 = graphs.initial_x(g.n, k, np.random.default_rng([22, k]))
@@ -169,7 +172,7 @@ def test_upper_small_graphs(ofm):
     g = graphs.Graph(n=n, row_ptr=rp, col_idx=ci, labels=np.zeros(n, dtype=np.int32), meta={})
     lap = ofm.Laplacian(rp, ci)
     assert lap.upper() == upper_size(rp, ci)
-    for variant, vid in F1_VARS:
+    for variant, vid in ALL_VARS:
         x0 = graphs.initial_x(n, 8, np.random.default_rng(6))
         teacher_forced_pair(ofm, g, x0, variant, vid, ofm.OFM_FP64, {1, 3, 10}, 1e-10,
                             restart=O.is_tri(vid))
