@@ -438,26 +438,29 @@ __device__ inline void tile_gram(const T* Pt, const T* Qt, GramAcc<T, KP>& acc,
 
 // k x k products of a dense pass with the output tiles dealt to the waves of
 // the workgroup (used where one wave cannot hold every FP64 accumulator at a
-// useful occupancy, FP32 k = 64).  The WPB waves stage their row tiles in LDS
-// side by side; product p of the pass's list -- group 0's 16 x 16 tiles, then
-// group 1's, a symmetric group listing its upper triangle -- belongs to wave
-// p % WPB, which sums it over the rows of every staged tile.  Group g multiplies
-// staged tile sa_g (columns) by staged tile sb_g (rows of the output).
-template <typename T, int KP, int WPB>
+// useful occupancy: FP32 k = 64, and the FP32 k = 32 V pass with X^T A V).
+// The WPB waves stage their row tiles in LDS side by side; product p of the
+// pass's list -- group 0's 16 x 16 tiles, then group 1's, then group 2's, a
+// symmetric group listing its upper triangle -- belongs to wave p % WPB, which
+// sums it over the rows of every staged tile.  Group g multiplies staged tile
+// sa_g (rows of the output) by staged tile sb_g (columns of the output).  At
+// most NG groups, the first of which may be symmetric.
+template <typename T, int KP, int WPB, int NG = 2>
 struct SplitGram {
   using G = Geo<T, KP>;
   static constexpr int NT = G::NT;
-  static constexpr int PER = (NT * (NT + 1) / 2 + NT * NT + WPB - 1) / WPB;
+  static constexpr int PER = (NT * (NT + 1) / 2 + (NG - 1) * NT * NT + WPB - 1) / WPB;
   d4 acc[PER];
   int offa[PER], offb[PER];  // LDS element offsets within a wave's staging area
   int grp[PER], ti[PER], tj[PER];
   int nprod = 0;
 
   __device__ void setup(int wave, int lane, int sa0, int sb0, bool sym0, int sa1, int sb1,
-                        bool sym1, int ngroups) {
+                        bool sym1, int ngroups, int sa2 = 0, int sb2 = 0) {
     const int n0 = sym0 ? NT * (NT + 1) / 2 : NT * NT;
     const int n1 = ngroups > 1 ? (sym1 ? NT * (NT + 1) / 2 : NT * NT) : 0;
-    nprod = n0 + n1;
+    const int n2 = ngroups > 2 ? NT * NT : 0;  // a third group is a full product
+    nprod = n0 + n1 + n2;
     const int f = lane & 15;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -465,9 +468,9 @@ struct SplitGram {
       const int p = q * WPB + wave;
       int g = 0, i = 0, jj = 0;
       if (p < nprod) {
-        g = p < n0 ? 0 : 1;
-        int r = p < n0 ? p : p - n0;
-        const bool sym = g == 0 ? sym0 : sym1;
+        g = p < n0 ? 0 : p < n0 + n1 ? 1 : 2;
+        int r = g == 0 ? p : g == 1 ? p - n0 : p - n0 - n1;
+        const bool sym = g == 0 ? sym0 : g == 1 ? sym1 : false;
         if (sym) {
           while (r >= NT - i) {
             r -= NT - i;
@@ -482,7 +485,8 @@ struct SplitGram {
       grp[q] = p < nprod ? g : -1;
       ti[q] = i;
       tj[q] = jj;
-      const int sa = g == 0 ? sa0 : sa1, sb = g == 0 ? sb0 : sb1;
+      const int sa = g == 0 ? sa0 : g == 1 ? sa1 : sa2;
+      const int sb = g == 0 ? sb0 : g == 1 ? sb1 : sb2;
       offa[q] = sa * G::TILE_ELEMS + 16 * i + f;
       offb[q] = sb * G::TILE_ELEMS + 16 * jj + f;
     }
@@ -527,11 +531,14 @@ struct SplitGram {
   }
 };
 
-// passes whose products are dealt to the waves (FP32 k = 64)
+// passes whose products are dealt to the waves (FP32 k = 64; the FP32 V pass
+// with X^T A V at k = 32)
 template <typename T, int KP, int MODE>
 constexpr bool split_gram_mode() {
-  return sizeof(T) == 4 && KP == 64 &&
-         (MODE == kVPass || MODE == kUpdate || MODE == kGramM || MODE == kUpdateR || MODE == kEF);
+  return sizeof(T) == 4 &&
+         ((KP == 64 && (MODE == kVPass || MODE == kUpdate || MODE == kGramM ||
+                        MODE == kUpdateR || MODE == kEF)) ||
+          (KP == 32 && MODE == kVPassE));
 }
 
 template <typename T, int KP>
@@ -972,11 +979,13 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
   for (int ti = 0; ti < NTE; ++ti)
 #pragma unroll
     for (int tj = 0; tj < NTE; ++tj) gE[ti][tj] = d4{0.0, 0.0, 0.0, 0.0};
-  SplitGram<T, KP, WPB> sg;
+  SplitGram<T, KP, WPB, HASE ? 3 : 2> sg;
   if constexpr (SPLIT) {
     // (source tiles, symmetry) of the product groups: t0 = 0, t1 = 1, t2 = 2
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     if (MODE == kVPass) sg.setup(wv, lane, 0, 0, true, 1, 0, false, 2);      // P = V^T V, C = X^T V
+    else if (MODE == kVPassE)                                                 // P, C, E = (AX)^T V
+      sg.setup(wv, lane, 0, 0, true, 1, 0, false, 3, 2, 0);
     else if (MODE == kEF) sg.setup(wv, lane, 0, 2, false, 1, 2, true, 2);    // E = X^T AV, F = V^T AV
     else if (MODE == kUpdateR)
       sg.setup(wv, lane, 0, 0, true, 0, 1, false, (a.flags & kFlagH) ? 2 : 1);  // M [, H = X^T AX]
@@ -1181,10 +1190,14 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
   double* prow = a.partials + (size_t)brank * a.nv;
   const int KK = KP * KP;
   if constexpr (SPLIT) {
-    if (MODE == kVPass) {
+    if (VP) {
       sg.out(0, true, red, prow, 0, lane);
       sg.out(1, false, red, prow, KK, lane);
       block_vec_out<T, KP, 1>(cacc, red, prow, 2 * KK, wave, lane, WPB);
+      if (HASE) {
+        for (int e = threadIdx.x; e < KP; e += blockDim.x) prow[2 * KK + KP + e] = 0.0;
+        sg.out(2, false, red, prow, 2 * KK + 2 * KP, lane);
+      }
     } else if (MODE == kEF) {
       sg.out(0, false, red, prow, 0, lane);
       sg.out(1, true, red, prow, KK, lane);
