@@ -567,9 +567,10 @@ static ofm_status build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr
                        stream) != hipSuccess)
       return fail(OFM_E_HIP);
   }
-  // upper-triangle copy for the f1 line searches (degree order only, no
-  // self-loops): rows with entries above the diagonal, by their count
-  if (g.reorder && !groups && !(flags & OFM_LAP_NO_UPPER) && nnz > 0) {
+  // upper-triangle copy for the line searches (no self-loops): the rows with
+  // entries above the diagonal, by that count (descending), or, on a grouped
+  // Laplacian, in the grouped order with the same eight XCD slots
+  if (g.reorder && !(flags & OFM_LAP_NO_UPPER) && nnz > 0) {
     int32_t* ucnt = nullptr;
     if ((st = dev_alloc(&ucnt, n)) != OFM_OK) return fail(st);
     std::vector<int32_t> hu(n);
@@ -584,15 +585,27 @@ static ofm_status build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr
     dev_free(ucnt);
     if (!ok) return fail(OFM_E_HIP);
     if (!loops) {
-      int32_t mx = 0;
-      for (int64_t i = 0; i < n; ++i) mx = std::max(mx, hu[(size_t)i]);
-      std::vector<int64_t> slot((size_t)mx + 2, 0);  // slot[mx - count]: next position
-      for (int64_t i = 0; i < n; ++i) ++slot[(size_t)(mx - hu[(size_t)i]) + 1];
-      for (int32_t c = 0; c <= mx; ++c) slot[(size_t)c + 1] += slot[c];
       std::vector<int32_t> usched(n);
-      for (int64_t i = 0; i < n; ++i) usched[(size_t)slot[(size_t)(mx - hu[(size_t)i])]++] = (int32_t)i;
       int64_t nu = 0;
-      while (nu < n && hu[(size_t)usched[(size_t)nu]] > 0) ++nu;
+      int64_t upos[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      if (groups) {
+        // the grouped order without the rows that have nothing above them
+        for (int x = 0; x < 8; ++x) {
+          upos[x] = nu;
+          for (int64_t p = slot_pos[x]; p < slot_pos[x + 1]; ++p)
+            if (hu[(size_t)sched[(size_t)p]] > 0) usched[(size_t)nu++] = sched[(size_t)p];
+        }
+        upos[8] = nu;
+      } else {
+        int32_t mx = 0;
+        for (int64_t i = 0; i < n; ++i) mx = std::max(mx, hu[(size_t)i]);
+        std::vector<int64_t> slot((size_t)mx + 2, 0);  // slot[mx - count]: next position
+        for (int64_t i = 0; i < n; ++i) ++slot[(size_t)(mx - hu[(size_t)i]) + 1];
+        for (int32_t c = 0; c <= mx; ++c) slot[(size_t)c + 1] += slot[c];
+        for (int64_t i = 0; i < n; ++i)
+          usched[(size_t)slot[(size_t)(mx - hu[(size_t)i])]++] = (int32_t)i;
+        while (nu < n && hu[(size_t)usched[(size_t)nu]] > 0) ++nu;
+      }
       std::vector<int32_t> usptr(nu + 1), udeg(nu);
       usptr[0] = 0;
       for (int64_t p = 0; p < nu; ++p) {
@@ -617,7 +630,16 @@ static ofm_status build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr
           return fail(OFM_E_HIP);
         for (int i = 0; i < 3; ++i) {
           std::vector<int32_t> t;
-          build_tiles(udeg, trs[i], true, 0, nu, t);
+          if (groups) {
+            L->ut[i].xcd = true;
+            for (int x = 0; x < 8; ++x) {
+              L->ut[i].xt[x] = (int32_t)t.size();
+              build_tiles(udeg, trs[i], true, upos[x], upos[x + 1], t);
+            }
+            L->ut[i].xt[8] = (int32_t)t.size();
+          } else {
+            build_tiles(udeg, trs[i], true, 0, nu, t);
+          }
           t.push_back((int32_t)nu);
           L->ut[i].tr = trs[i];
           L->ut[i].ntiles = (int64_t)t.size() - 1;
@@ -974,7 +996,8 @@ static ofm_status run_spmm_upper(ofm_workspace ws, PassArgs& a, hipStream_t s) {
   a.ntiles = ws->utiles->ntiles;
   a.pk = ws->prec == OFM_FP64 ? g.upk64 : g.upk32;
   a.cold_below = g.cold_below;
-  a.xcd = 0;
+  a.xcd = ws->utiles->xcd ? 1 : 0;
+  for (int x = 0; x < 9; ++x) a.xt[x] = ws->utiles->xt[x];
   if (ws->hc) a.flags |= kFlagHC;
   spmm_grid(a, ws->utiles, ws->prec, ws->k, a.nv, ws->part_cap);
   HIPCHK(timed(ws, pass_kind(a.mode), s, [&] { return launch_spmm(ws->prec, ws->k, a, s); }));

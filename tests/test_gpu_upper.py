@@ -6,7 +6,7 @@ V^T A V = -V^T V - (V^T U + U^T V) and X^T A V = (AX)^T V, the latter formed
 in the V pass from the A X that the SpMM of X stores (k <= 32).
 
 * its size, and the Laplacians that build none (self-loops, index order,
-  grouped order, the opt-out flag);
+  the opt-out flag);
 * teacher-forced steps through it against the FP64 oracle, and against the
   same step with the full product A V from the same state."""
 import sys
@@ -64,8 +64,10 @@ def test_upper_copy_size(ofm, dcsbm20k):
     assert (rows, ents) == upper_size(g.row_ptr, g.col_idx)
     assert 2 * ents == len(g.col_idx)      # symmetric, no self-loops
     assert rows < g.n                      # the last node has nothing above it
-    for kw in ({"upper": False}, {"reorder": False}, {"groups": g.labels}):
+    for kw in ({"upper": False}, {"reorder": False}):
         assert ofm.Laplacian(g.row_ptr, g.col_idx, **kw).upper() == (0, 0), kw
+    # the grouped order keeps the same copy, laid out in its XCD slots
+    assert ofm.Laplacian(g.row_ptr, g.col_idx, groups=g.labels).upper() == (rows, ents)
     # one self-loop: no copy (the identity above needs w_ii = 0)
     n = 6
     ent = sorted([(i, (i + 1) % n) for i in range(n)] + [((i + 1) % n, i) for i in range(n)]
@@ -176,3 +178,37 @@ def test_upper_small_graphs(ofm):
         x0 = graphs.initial_x(n, 8, np.random.default_rng(6))
         teacher_forced_pair(ofm, g, x0, variant, vid, ofm.OFM_FP64, {1, 3, 10}, 1e-10,
                             restart=O.is_tri(vid))
+
+
+@pytest.mark.parametrize("variant,vid", ALL_VARS)
+def test_teacher_forced_upper_grouped(ofm, dcsbm20k, variant, vid):
+    # the copy in the grouped order (planted blocks as groups, XCD slots)
+    # against the oracle and the full product on a plain Laplacian
+    g = dcsbm20k
+    k = 16
+    x0 = graphs.initial_x(g.n, k, np.random.default_rng([23, k]))
+    olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
+    lg = ofm.Laplacian(g.row_ptr, g.col_idx, groups=g.labels)
+    lf = ofm.Laplacian(g.row_ptr, g.col_idx, upper=False)
+    restart = O.is_tri(vid)
+    opts = O.Options(variant=vid, restart=restart)
+    wg = ofm.Workspace(lg, k, variant=variant, precision=ofm.OFM_FP32, restart=restart,
+                       check_every=1000000)
+    wf = ofm.Workspace(lf, k, variant=variant, precision=ofm.OFM_FP32, restart=restart,
+                       check_every=1000000)
+    X = dev(x0.astype(np.float32), torch.float32)
+    wg.init(X)
+    for t in range(1, 8):
+        Xh = host(X)
+        Vp, Gp = wg.get_state()
+        state = O.State(X=Xh, V_prev=host(Vp), G_prev=host(Gp), t=t)
+        st_o, info_o = O.step(olap, state, opts)
+        Xf = X.clone()
+        wf.set_state(Xf, Vp.clone(), Gp.clone(), t)
+        wg.step(X)
+        wf.step(Xf)
+        gg, gf = wg.step_info(), wf.step_info()
+        ex, ea, eb, fl = stepcheck.compare_step(vid, k, Xh, host(X), gg, info_o, st_o.X, False,
+                                                say=say, G_prev=state.G_prev)
+        assert ex < 1e-4, (variant, t, ex)
+        assert stepcheck.rel(gg["coeffs"], gf["coeffs"]) < 1e-4, (variant, t)
