@@ -170,13 +170,16 @@ const char* ofm_version(void);
  * weights w_ij = D_ii^{-1/2} S_ij D_jj^{-1/2} (FP64 and FP32 copies, laid out
  * in the row-processing order).  Synchronizing (the checks are read back).
  * Upper-triangle copy: unless OFM_LAP_NO_UPPER or OFM_LAP_NO_REORDER is given
- * or some row has a self-loop, the entries with column > row are also packed
- * (about half of nnz, 24 B per entry for the FP32 and FP64 copies together),
- * rows by that count, descending.  The f1 variants' line searches need only
- * the per-column quadratic forms diag(V^T A V) (Section 3.2), which for a
- * symmetric A equal -diag(V^T V) - 2 sum_i V_ic sum_{j>i} w_ij V_jc: a
- * workspace on such a Laplacian gathers only those entries for them (half the
- * gathers of the product A V).  The symmetry of the pattern and the weights
+ * or some row has a self-loop, an upper-triangle copy is also packed: of every
+ * stored pair (i, j), (j, i) the entry whose column j comes later in the order
+ * of the nodes by (degree, id) (half of nnz, 24 B per entry for the FP32 and
+ * FP64 copies together), rows by their count of such entries, descending (in
+ * the grouped order for ofm_build_laplacian_grouped).  With A symmetric and
+ * U_i = sum over row i of the copy of w_ij V_j, the line searches' products
+ * with A V (Section 3.2) are diag(V^T A V) = -diag(V^T V) - 2 diag(V^T U),
+ * V^T A V = -V^T V - V^T U - U^T V and X^T A V = (AX)^T V: a workspace on such
+ * a Laplacian gathers only the copy's entries for them (half the gathers of
+ * the product A V, and those go to the rows of larger degree).  The symmetry of the pattern and the weights
  * that the method assumes is then also what the step relies on
  * (OFM_LAP_VALIDATE checks it).
  * The input arrays are only read during the call.
@@ -239,8 +242,7 @@ ofm_status ofm_laplacian_info(ofm_laplacian lap, int64_t* host_n, int64_t* host_
                               double* host_normA2, double* host_degrees);
 
 /* Size of the upper-triangle copy (see ofm_build_laplacian): its rows (those
- * with at least one entry above the diagonal) and entries; both 0 when none
- * was built.  Either output may be NULL.  Errors: OFM_E_INVALID_ARG for a null
+ * with at least one entry in it) and entries; both 0 when none was built.  Either output may be NULL.  Errors: OFM_E_INVALID_ARG for a null
  * handle. */
 ofm_status ofm_laplacian_upper(ofm_laplacian lap, int64_t* host_rows, int64_t* host_nnz);
 

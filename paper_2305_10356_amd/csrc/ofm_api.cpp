@@ -568,7 +568,7 @@ static ofm_status build_laplacian(int64_t n, int64_t nnz, const int32_t* row_ptr
       return fail(OFM_E_HIP);
   }
   // upper-triangle copy for the line searches (no self-loops): the rows with
-  // entries above the diagonal, by that count (descending), or, on a grouped
+  // entries in it, by that count (descending), or, on a grouped
   // Laplacian, in the grouped order with the same eight XCD slots
   if (g.reorder && !(flags & OFM_LAP_NO_UPPER) && nnz > 0) {
     int32_t* ucnt = nullptr;
@@ -1148,7 +1148,7 @@ static ofm_status search_and_update(ofm_workspace ws, void* X, const void* Vp, b
     e.Z = ws->AV;
     OFMCHK(run_dense(ws, e, s));
   } else if (ws->utiles) {
-    // diag(V^T A V) over the entries above the diagonal (half the gathers)
+    // diag(V^T A V) over the upper-triangle copy (half the gathers)
     PassArgs w = base_args(ws, kAVF1, kFlagUpper);
     w.Z = ws->V[cur];
     w.Zg = ws->Vb;

@@ -144,11 +144,20 @@ __global__ void graph_pack_kernel(int64_t n, const int32_t* __restrict__ sched,
   }
 }
 
-// Upper-triangle copy (entries with column > row), used for the per-column
-// quadratic forms diag(V^T A V) of the f1 line searches: with A symmetric,
-// sum_ij w_ij V_ic V_jc = 2 sum_{i<j} w_ij V_ic V_jc when no row has a
-// self-loop.  Per row: the number of such entries; flags |= 1 if any row has
-// a self-loop (the copy is then not built).
+// Upper-triangle copy: of every stored pair (i, j), (j, i) the one entry whose
+// column comes later in the order of the nodes by (degree, id) -- the strict
+// upper triangle of A with the nodes in that order.  With A symmetric and no
+// self-loop, sum_ij w_ij V_ic V_jd = sum over the copy of w_ij (V_ic V_jd +
+// V_jc V_id), so the products with A V of the line searches need only these
+// entries, and each row gathers its neighbours of larger degree: the rows that
+// are gathered most anyway.  Per row: the number of such entries; flags |= 1
+// if any row has a self-loop (the copy is then not built).
+// whether column j of row i (degree di) belongs to the copy: j after i by (degree, id)
+__device__ inline bool upper_of(const int32_t* __restrict__ row_ptr, int i, int di, int j) {
+  const int dj = row_ptr[j + 1] - row_ptr[j];
+  return dj > di || (dj == di && j > i);
+}
+
 __global__ void graph_upper_count_kernel(int64_t n, const int32_t* __restrict__ row_ptr,
                                          const int32_t* __restrict__ col_idx,
                                          int32_t* __restrict__ ucnt, int* flags) {
@@ -156,16 +165,17 @@ __global__ void graph_upper_count_kernel(int64_t n, const int32_t* __restrict__ 
   if (i >= n) return;
   int c = 0;
   bool loop = false;
+  const int di = row_ptr[i + 1] - row_ptr[i];
   for (int64_t t = row_ptr[i]; t < row_ptr[i + 1]; ++t) {
     const int j = col_idx[t];
-    c += j > i ? 1 : 0;
+    c += upper_of(row_ptr, (int)i, di, j) ? 1 : 0;
     loop = loop || j == i;
   }
   ucnt[i] = c;
   if (loop) atomicOr(flags, 1);
 }
 
-// entries with column > row of the row at upper position p (a wavefront per
+// the copy's entries of the row at upper position p (a wavefront per
 // position), in their CSR order, compacted to the packed stream at usptr[p];
 // cold marks as in graph_pack_kernel
 __global__ void graph_pack_upper_kernel(int64_t nu, const int32_t* __restrict__ usched,
@@ -180,11 +190,12 @@ __global__ void graph_pack_upper_kernel(int64_t nu, const int32_t* __restrict__ 
   if (p >= nu) return;  // uniform over the wavefront
   const int row = usched[p];
   const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+  const int drow = (int)(e - b);
   int64_t o = usptr[p];
   for (int64_t base = b; base < e; base += 64) {
     const int64_t t = base + lane;
     const int c0 = t < e ? col_idx[t] : -1;
-    const bool keep = c0 > row;
+    const bool keep = c0 >= 0 && c0 != row && upper_of(row_ptr, row, drow, c0);
     const unsigned long long m = __ballot(keep);
     if (keep) {
       const int64_t at = o + __popcll(m & ((1ull << lane) - 1ull));

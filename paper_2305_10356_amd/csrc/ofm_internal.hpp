@@ -87,7 +87,7 @@ enum Mode : int {
   kGPassF1 = 11,  // G = c (AX + X M') from a stored AX, gg, gpg [, vpg]
   kGF2 = 12,      // G = a AX - b (X H' + AX M') from the gathered AX, gg, gpg [, vpg] [, H, K]
   kEF = 13,       // X^T A V, V^T A V from a stored A V
-  kSF2 = 14,      // S = V^T U, U_i = sum_{j > i} w_ij V_j (upper-triangle copy), in F's slot
+  kSF2 = 14,      // S = V^T U, U_i = sum_{j in copy row i} w_ij V_j (upper-triangle copy), in F's slot
   kVPassE = 15    // kVPass and E = (AX)^T V = X^T A V (A symmetric) from a stored A X (k <= 32);
                   // writes [P | C | diag V^T G | 0 (diag V^T A V, unused by f2) | E]
 };
@@ -111,9 +111,10 @@ struct LaplacianDev {
   double* w64_csr = nullptr;   // [nnz] w_ij in input CSR order
   bool reorder = true;
   int cold_below = 0;          // columns of rows with fewer entries carry the cold mark
-  // upper-triangle copy (column > row) for diag(V^T A V): rows with at least
-  // one such entry, by that count, descending (nu rows, nnzu entries; none
-  // when nu == 0)
+  // upper-triangle copy for the products with A V: of each pair (i, j), (j, i)
+  // the entry whose column is later by (degree, id); rows with at least one
+  // such entry, by that count, descending, or in the grouped order (nu rows,
+  // nnzu entries; none when nu == 0)
   int64_t nu = 0, nnzu = 0;
   int32_t* usched = nullptr;   // [nu] upper position -> row
   int32_t* usptr = nullptr;    // [nu+1]
@@ -164,7 +165,7 @@ struct PassArgs {
 
 // kFlagHC: gathers of rows with the cold mark use the non-temporal policy
 // kFlagUpper (kAVF1): the graph is the upper-triangle copy and the pass sums
-// V_ic (sum_{j > i} w_ij V_jc) per column; the line search then takes
+// V_ic (sum_{j in copy row i} w_ij V_jc) per column; the line search then takes
 // diag(V^T A V)_c = -(V^T V)_cc - 2 x that sum
 enum : int { kFlagCheck = 1, kFlagRestart = 2, kFlagFirst = 4, kFlagH = 8, kFlagHC = 16,
              kFlagUpper = 32 };

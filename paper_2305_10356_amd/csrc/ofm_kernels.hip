@@ -648,7 +648,7 @@ __device__ __forceinline__ void spmm_body(const PassArgs& a, int brank, int nblk
 
   constexpr bool check = CHECK;
   const bool restart = (a.flags & kFlagRestart) != 0;
-  // upper-triangle pass: V_i times its sum over the entries above the diagonal
+  // upper-triangle pass: V_i times its sum over the row's entries in the copy
   const bool upper = MODE == kAVF1 && (a.flags & kFlagUpper) != 0;
   const T* __restrict__ Z = static_cast<const T*>(a.Z);
   const auto* __restrict__ pk = static_cast<const typename EntT<T>::type*>(a.pk);
@@ -1480,12 +1480,12 @@ __device__ __forceinline__ void linesearch_body(int variant, int first, double a
   const int KK = KP * KP;
   const double* M = sc + SC<KP>::M;
   if (upper_fd == 1) {
-    // diag(V^T A V)_c = -(V^T V)_cc - 2 sum_i V_ic sum_{j > i} w_ij V_jc
+    // diag(V^T A V)_c = -(V^T V)_cc - 2 sum_i V_ic sum_{j in copy row i} w_ij V_jc
     const int t = threadIdx.x;
     if (t < KP) sc[SC<KP>::FD + t] = -sc[SC<KP>::P + t * KP + t] - 2.0 * sc[SC<KP>::FD + t];
     __syncthreads();
   } else if (upper_fd == 2) {
-    // V^T A V = -V^T V - (S + S^T), S = sum_i V_i^T sum_{j > i} w_ij V_j;
+    // V^T A V = -V^T V - (S + S^T), S = sum_i V_i^T sum_{j in copy row i} w_ij V_j;
     // each pair (r, c), (c, r) is rewritten by one thread
     double* F = sc + SC<KP>::F;
     const double* P = sc + SC<KP>::P;

@@ -34,12 +34,17 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCE = os.path.join(HERE, "csrc", "ofm_kernels.hip")
+# the kernels and the graph layout they read (the counters depend on both)
+KERNEL_SOURCES = (os.path.join(HERE, "csrc", "ofm_kernels.hip"),
+                  os.path.join(HERE, "csrc", "ofm_graph.hip"))
 
 
-def source_hash(path: str = KERNEL_SOURCE) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+def source_hash(paths=KERNEL_SOURCES) -> str:
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def counter_means(paths):
@@ -56,7 +61,7 @@ def counter_means(paths):
 def read_traffic(summary_path: str):
     """Per-pass traffic lines ``traffic_bytes <pass> <bytes>`` of a committed
     counter summary, valid only if its ``source_sha256`` matches the current
-    kernel source; returns {} otherwise."""
+    kernel and graph-layout sources (``source_hash``); returns {} otherwise."""
     if not os.path.exists(summary_path):
         return {}
     out = {}

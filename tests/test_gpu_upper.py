@@ -1,7 +1,9 @@
-"""The upper-triangle copy of the Laplacian (entries with column > row) and the
-line searches that take their products with A V from it (Section 3.2).  With
-A symmetric and U_i = sum_{j>i} w_ij V_j: the OFM-f1 and TriOFM-f1 cubics need
-only diag(V^T A V) = -diag(V^T V) - 2 diag(V^T U); the f2 cubics need
+"""The upper-triangle copy of the Laplacian and the line searches that take
+their products with A V from it (Section 3.2).  The copy keeps, of every
+stored pair (i, j), (j, i), the entry whose column comes later in the order of
+the nodes by (degree, id).  With A symmetric and U_i = sum over row i of the
+copy of w_ij V_j: the OFM-f1 and TriOFM-f1 cubics need only
+diag(V^T A V) = -diag(V^T V) - 2 diag(V^T U); the f2 cubics need
 V^T A V = -V^T V - (V^T U + U^T V) and X^T A V = (AX)^T V, the latter formed
 in the V pass from the A X that the SpMM of X stores (k <= 32).
 
@@ -43,10 +45,12 @@ def host(t):
 
 
 def upper_size(rp, ci):
-    """(rows with an entry above the diagonal, entries above the diagonal)"""
+    """(rows with an entry in the copy, entries in the copy): entry (i, j) is
+    in it when node j comes after node i by (degree, id)"""
     n = len(rp) - 1
-    rows = np.repeat(np.arange(n), np.diff(rp))
-    up = ci > rows
+    deg = np.diff(rp)
+    rows = np.repeat(np.arange(n), deg)
+    up = (deg[ci] > deg[rows]) | ((deg[ci] == deg[rows]) & (ci > rows))
     return int(np.count_nonzero(np.bincount(rows[up], minlength=n))), int(up.sum())
 
 
@@ -63,7 +67,7 @@ def test_upper_copy_size(ofm, dcsbm20k):
     say(f"upper copy: {rows} rows, {ents} entries of {len(g.col_idx)}")
     assert (rows, ents) == upper_size(g.row_ptr, g.col_idx)
     assert 2 * ents == len(g.col_idx)      # symmetric, no self-loops
-    assert rows < g.n                      # the last node has nothing above it
+    assert rows < g.n                      # the last node by (degree, id) has nothing after it
     for kw in ({"upper": False}, {"reorder": False}):
         assert ofm.Laplacian(g.row_ptr, g.col_idx, **kw).upper() == (0, 0), kw
     # the grouped order keeps the same copy, laid out in its XCD slots
@@ -158,13 +162,17 @@ def test_teacher_forced_upper_fp32(ofm, dcsbm20k, variant, vid, k):
 
 
 def test_upper_small_graphs(ofm):
-    # fewer rows than one tile, a hub above every other node (a row processed
-    # a wavefront at a time in the upper copy) and rows with nothing above them
-    rng = np.random.default_rng(5)
+    # a 70-node clique (equal degrees: the copy keeps the later ids, so node 0
+    # keeps 69 entries, a row processed a wavefront at a time), 80 nodes hung
+    # on five clique nodes (entries toward the clique) and the last node by
+    # (degree, id) with nothing in the copy
     n = 150
-    edges = {(0, j) for j in range(1, n)}
-    edges |= {(int(a), int(b)) for a, b in rng.integers(1, n, size=(200, 2)) if a != b}
-    edges = {(min(a, b), max(a, b)) for a, b in edges}
+    edges = {(a, b) for a in range(70) for b in range(a + 1, 70)}
+    edges |= {(65 + i % 5, i) for i in range(70, n)}
+    # and some leaf-leaf edges, which break the clique's symmetry
+    rng = np.random.default_rng(5)
+    edges |= {(int(min(a, b)), int(max(a, b))) for a, b in rng.integers(70, n, size=(60, 2))
+              if a != b}
     ent = sorted(list(edges) + [(b, a) for a, b in edges])
     rp = np.zeros(n + 1, dtype=np.int32)
     for a, _ in ent:
@@ -173,7 +181,12 @@ def test_upper_small_graphs(ofm):
     ci = np.array([b for _, b in ent], dtype=np.int32)
     g = graphs.Graph(n=n, row_ptr=rp, col_idx=ci, labels=np.zeros(n, dtype=np.int32), meta={})
     lap = ofm.Laplacian(rp, ci)
-    assert lap.upper() == upper_size(rp, ci)
+    rows, ents = upper_size(rp, ci)
+    assert lap.upper() == (rows, ents) and rows == n - 1
+    deg = np.diff(rp)
+    r = np.repeat(np.arange(n), deg)
+    up = (deg[ci] > deg[r]) | ((deg[ci] == deg[r]) & (ci > r))
+    assert np.bincount(r[up], minlength=n).max() >= 64
     for variant, vid in ALL_VARS:
         x0 = graphs.initial_x(n, 8, np.random.default_rng(6))
         teacher_forced_pair(ofm, g, x0, variant, vid, ofm.OFM_FP64, {1, 3, 10}, 1e-10,
