@@ -1991,32 +1991,46 @@ extern "C" ofm_status ofm_batch_phases(ofm_batch b, double* host_loop_ms, double
   return OFM_OK;
 }
 
-// FP64 solve of one graph from its FP32 block, on its own stream; the FP32
-// block receives the result.  Synchronizing on that stream.
-static ofm_status finish_fp64(ofm_laplacian L, int k, const ofm_opts& o, int64_t used,
-                              void* X32, hipStream_t s, ofm_stats* out) {
+// FP64 solve of one graph from its FP32 block, in three parts: the workspace
+// and the FP64 block are made on the calling thread before the finishing
+// threads start, so that the threads neither allocate, free nor synchronize
+// the device; the solve runs on the graph's own stream (synchronizing on it)
+// and the FP32 block receives the result; the release follows the join.
+struct Finish {
+  ofm_workspace ws = nullptr;
+  double* X64 = nullptr;
+};
+
+static ofm_status finish_prepare(ofm_laplacian L, int k, const ofm_opts& o, int64_t used,
+                                 Finish* f) {
   ofm_opts o64 = o;
   o64.precision = OFM_FP64;
   o64.max_iter = (int)(o.max_iter - used);
   o64.first_step = 0;
   o64.recur = 0;
-  o64.graph = 0;   // eager: no graph captures from the concurrent finishing threads
-  o64.gather = 1;  // no timing runs on the shared device from the finishing threads
-  ofm_workspace ws = nullptr;
-  ofm_status es = ofm_workspace_create(L, k, &o64, &ws);
-  if (es != OFM_OK) return es;
-  double* X64 = nullptr;
-  const int64_t cnt = L->g.n * k;
-  es = dev_alloc(&X64, cnt);
-  if (es == OFM_OK && launch_convert(cnt, 1, X32, X64, s) != hipSuccess) es = OFM_E_HIP;
-  if (es == OFM_OK) es = ofm_solve(ws, X64, s, out);
+  // eager steps: replayed as HIP graphs the finishing solves measured the same
+  // (their time is the kernels of the slowest graph's iterations, not launches)
+  o64.graph = 0;
+  o64.gather = 1;  // no timing runs on the shared device
+  OFMCHK(ofm_workspace_create(L, k, &o64, &f->ws));
+  return dev_alloc(&f->X64, L->g.n * k);
+}
+
+static ofm_status finish_run(Finish& f, void* X32, hipStream_t s, ofm_stats* out) {
+  const int64_t cnt = f.ws->n * f.ws->k;
+  if (launch_convert(cnt, 1, X32, f.X64, s) != hipSuccess) return OFM_E_HIP;
+  ofm_status es = ofm_solve(f.ws, f.X64, s, out);
   if (es == OFM_OK || es == OFM_E_NONFINITE || es == OFM_E_NUMERIC) {
-    if (launch_convert(cnt, 0, X64, X32, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    if (launch_convert(cnt, 0, f.X64, X32, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
       es = OFM_E_HIP;
   }
-  dev_free(X64);
-  ofm_workspace_destroy(ws);
   return es;
+}
+
+static void finish_release(Finish& f) {
+  dev_free(f.X64);
+  if (f.ws) ofm_workspace_destroy(f.ws);
+  f = Finish{};
 }
 
 // the passes of one batched group: a dense or SpMM launch plus its per-graph
@@ -2395,6 +2409,15 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
   if (!jobs.empty()) {
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
+    std::vector<Finish> fin(jobs.size());
+    struct Release {
+      std::vector<Finish>& f;
+      ~Release() {
+        for (auto& x : f) finish_release(x);
+      }
+    } release{fin};
+    for (size_t j = 0; j < jobs.size(); ++j)
+      OFMCHK(finish_prepare(B->laps[jobs[j].graph], jobs[j].k, o, jobs[j].st.iters, &fin[j]));
     std::atomic<int> next(0);
     auto worker = [&](hipStream_t s) {
       const bool on_device = hipSetDevice(dev) == hipSuccess;
@@ -2405,7 +2428,7 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
           continue;
         }
         ofm_stats s64{};
-        jb.es = finish_fp64(B->laps[jb.graph], jb.k, o, jb.st.iters, host_X[jb.graph], s, &s64);
+        jb.es = finish_run(fin[j], host_X[jb.graph], s, &s64);
         if (jb.es == OFM_OK || jb.es == OFM_E_NONFINITE || jb.es == OFM_E_NUMERIC) {
           jb.st.iters += s64.iters;
           jb.st.relres = s64.relres;
