@@ -7,7 +7,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstddef>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <numeric>
 #include <thread>
@@ -2033,6 +2035,79 @@ static void finish_release(Finish& f) {
   f = Finish{};
 }
 
+// The finishing solves of a batched solve: a graph whose FP32 residual has
+// stalled is queued as soon as a residual check finds it (its workspace made
+// on the solving thread) and solved by one of kFinishThreads threads, each on
+// a stream of its own, while the FP32 loop of the other graphs goes on; the
+// graphs that end the loop unconverged follow.  Jobs live in a deque, whose
+// elements keep their addresses as jobs are added.
+struct FinishPool {
+  struct Job {
+    int graph = 0;
+    ofm_stats st{};   // FP32 stats on entry, combined with the FP64 solve's
+    ofm_status es = OFM_OK;
+    Finish fin;
+  };
+  std::deque<Job> jobs;
+  std::mutex mu;
+  std::condition_variable cv;
+  size_t next = 0;
+  bool closed = false;
+  std::vector<std::thread> threads;
+
+  void start(int dev, const hipStream_t* streams, void* const* host_X) {
+    for (int i = 0; i < kFinishThreads; ++i)
+      threads.emplace_back([this, dev, s = streams[i], host_X] {
+        const bool on_device = hipSetDevice(dev) == hipSuccess;
+        for (;;) {
+          Job* jb = nullptr;
+          {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait(lk, [this] { return next < jobs.size() || closed; });
+            if (next >= jobs.size()) return;
+            jb = &jobs[next++];
+          }
+          if (!on_device) {
+            jb->es = OFM_E_HIP;
+            continue;
+          }
+          ofm_stats s64{};
+          jb->es = finish_run(jb->fin, host_X[jb->graph], s, &s64);
+          if (jb->es == OFM_OK || jb->es == OFM_E_NONFINITE || jb->es == OFM_E_NUMERIC) {
+            jb->st.iters += s64.iters;
+            jb->st.relres = s64.relres;
+            jb->st.objective = s64.objective;
+            jb->st.relres_iter = jb->st.iters - s64.iters + s64.relres_iter;
+            jb->st.status = s64.status;
+            jb->st.converged = s64.converged;
+          }
+        }
+      });
+  }
+  // queue a prepared job (starts the threads on first use)
+  void push(Job&& j, int dev, const hipStream_t* streams, void* const* host_X) {
+    if (threads.empty()) start(dev, streams, host_X);
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      jobs.push_back(std::move(j));
+    }
+    cv.notify_one();
+  }
+  void join() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      closed = true;
+    }
+    cv.notify_all();
+    for (auto& t : threads) t.join();
+    threads.clear();
+  }
+  ~FinishPool() {
+    join();
+    for (auto& j : jobs) finish_release(j.fin);
+  }
+};
+
 // the passes of one batched group: a dense or SpMM launch plus its per-graph
 // reduction
 static ofm_status bpass(BatchGroup& g, BatchArgs base, int mode, int flags, bool spmm) {
@@ -2311,6 +2386,37 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
   // more of it from the others.
   B->replays = 0;
   OFMCHK(batch_start(B, host_X, stream));
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  FinishPool pool;
+  std::vector<char> queued(B->count, 0);
+  // at a residual check (the host has synchronized with it): queue the graphs
+  // whose residual has stalled since the last one
+  auto escalate_stalled = [&]() -> ofm_status {
+    if (!(o.tol > 0.0)) return OFM_OK;
+    for (auto& g : B->groups) {
+      if (g.k > 32) continue;
+      const int n = (int)g.idx.size();
+      std::vector<int> stl(n);
+      HIPCHK(hipMemcpy(stl.data(), g.stalled, n * sizeof(int), hipMemcpyDeviceToHost));
+      for (int m = 0; m < n; ++m) {
+        const int i = g.idx[m];
+        if (!stl[m] || queued[i] || B->t >= o.max_iter) continue;
+        queued[i] = 1;
+        FinishPool::Job jb;
+        jb.graph = i;
+        jb.st.iters = B->t;
+        jb.st.status = OFM_OK;
+        const ofm_status ps = finish_prepare(B->laps[i], g.k, o, B->t, &jb.fin);
+        if (ps != OFM_OK) {
+          finish_release(jb.fin);
+          return ps;
+        }
+        pool.push(std::move(jb), dev, B->finish_streams, host_X);
+      }
+    }
+    return OFM_OK;
+  };
   const bool tune = B->fixed < 0 && !B->tuned;
   const int64_t tune_end = tune ? 1 + 2 * kBatchCand : 0;
   bool on_stream = false;  // the loop runs as graph replays on `stream`
@@ -2326,6 +2432,7 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
       int any = 0;
       OFMCHK(batch_any_active(B, stream, &any));
       if (!any) break;
+      OFMCHK(escalate_stalled());
       continue;
     }
     if (on_stream) {
@@ -2359,6 +2466,7 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
       int any = 0;
       OFMCHK(batch_any_active(B, stream, &any));
       if (!any) break;
+      OFMCHK(escalate_stalled());
     }
   }
   if (on_stream) OFMCHK(batch_fork(B, stream));
@@ -2366,14 +2474,8 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
   const int64_t last_check = B->last_check;
   B->escalated = 0;
   // per-graph stats; a graph whose FP32 residual stopped decreasing before the
-  // tolerance (or ran out of iterations) is finished in FP64 from its FP32 X
-  struct Job {
-    int graph;
-    int k;
-    ofm_stats st;
-    ofm_status es;
-  };
-  std::vector<Job> jobs;
+  // tolerance (or ran out of iterations) is finished in FP64 from its FP32 X:
+  // queued at the check that found it stalled, or now
   std::vector<ofm_stats> all(B->count);
   for (auto& g : B->groups) {
     HIPCHK(hipStreamSynchronize(g.stream));
@@ -2397,59 +2499,33 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
       st.status = device_status(stt[m]);
       st.converged = (done[m] >= 0 && st.status == OFM_OK) ? 1 : 0;
       const bool escalate = !st.converged && st.status == OFM_OK && o.tol > 0.0 && g.k <= 32 &&
-                            st.iters < o.max_iter;
-      if (escalate) jobs.push_back({g.idx[m], g.k, st, OFM_OK});
-      all[g.idx[m]] = st;
+                            st.iters < o.max_iter && !queued[g.idx[m]];
+      if (escalate) {
+        queued[g.idx[m]] = 1;
+        FinishPool::Job jb;
+        jb.graph = g.idx[m];
+        jb.st = st;
+        const ofm_status ps = finish_prepare(B->laps[jb.graph], g.k, o, st.iters, &jb.fin);
+        if (ps != OFM_OK) {
+          finish_release(jb.fin);
+          return ps;
+        }
+        pool.push(std::move(jb), dev, B->finish_streams, host_X);
+      }
+      if (!queued[g.idx[m]]) all[g.idx[m]] = st;
     }
   }
   const auto t_loop = std::chrono::steady_clock::now();
   B->loop_ms = std::chrono::duration<double, std::milli>(t_loop - t_solve).count();
-  // the finishing solves run concurrently, each on a stream of its own (the
-  // batch's groups have completed: every group stream was synchronized above)
-  if (!jobs.empty()) {
-    int dev = 0;
-    HIPCHK(hipGetDevice(&dev));
-    std::vector<Finish> fin(jobs.size());
-    struct Release {
-      std::vector<Finish>& f;
-      ~Release() {
-        for (auto& x : f) finish_release(x);
-      }
-    } release{fin};
-    for (size_t j = 0; j < jobs.size(); ++j)
-      OFMCHK(finish_prepare(B->laps[jobs[j].graph], jobs[j].k, o, jobs[j].st.iters, &fin[j]));
-    std::atomic<int> next(0);
-    auto worker = [&](hipStream_t s) {
-      const bool on_device = hipSetDevice(dev) == hipSuccess;
-      for (int j = next++; j < (int)jobs.size(); j = next++) {
-        Job& jb = jobs[j];
-        if (!on_device) {
-          jb.es = OFM_E_HIP;
-          continue;
-        }
-        ofm_stats s64{};
-        jb.es = finish_run(fin[j], host_X[jb.graph], s, &s64);
-        if (jb.es == OFM_OK || jb.es == OFM_E_NONFINITE || jb.es == OFM_E_NUMERIC) {
-          jb.st.iters += s64.iters;
-          jb.st.relres = s64.relres;
-          jb.st.objective = s64.objective;
-          jb.st.relres_iter = jb.st.iters - s64.iters + s64.relres_iter;
-          jb.st.status = s64.status;
-          jb.st.converged = s64.converged;
-        }
-      }
-    };
-    const int nt = std::min<int>(kFinishThreads, (int)jobs.size());
-    std::vector<std::thread> threads;
-    for (int i = 0; i < nt; ++i) threads.emplace_back(worker, B->finish_streams[i]);
-    for (auto& th : threads) th.join();
-    for (auto& jb : jobs) {
-      if (jb.es == OFM_E_HIP || jb.es == OFM_E_NOMEM || jb.es == OFM_E_INVALID_ARG ||
-          jb.es == OFM_E_SHAPE || jb.es == OFM_E_UNSUPPORTED)
-        return jb.es;
-      all[jb.graph] = jb.st;
-      ++B->escalated;
-    }
+  // the remaining finishing solves (the batch's groups have completed: every
+  // group stream was synchronized above)
+  pool.join();
+  for (auto& jb : pool.jobs) {
+    if (jb.es == OFM_E_HIP || jb.es == OFM_E_NOMEM || jb.es == OFM_E_INVALID_ARG ||
+        jb.es == OFM_E_SHAPE || jb.es == OFM_E_UNSUPPORTED)
+      return jb.es;
+    all[jb.graph] = jb.st;
+    ++B->escalated;
   }
   B->finish_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_loop).count();
