@@ -50,13 +50,20 @@ def test_bf16_solve_floor_and_labels(lib):
     g, x0 = graphs.workload("sbm-n50k-k32")
     lap = ofm.Laplacian(g.row_ptr, g.col_idx)
     labels = {}
+    # solved to a tolerance: on this graph the update count to residual 1e-4
+    # moves by up to 3x between rounding paths (200 to 2,300 in FP32 over
+    # starting blocks), so a fixed count says little about either floor
     for prec in (ofm.OFM_FP32, ofm.OFM_FP32_BF16X):
-        ws = ofm.Workspace(lap, 32, variant="f1", precision=prec, max_iter=400, check_every=10)
+        fp32 = prec == ofm.OFM_FP32
+        ws = ofm.Workspace(lap, 32, variant="f1", precision=prec, max_iter=3000, check_every=10,
+                           tol=1e-4 if fp32 else 1e-3)
         X = torch.tensor(x0.astype(np.float32), device="cuda")
-        ws.solve(X)
+        st = ws.solve(X)
         rr = ws.residual(X)["relres"]
-        print(f"precision {prec}: relres of the final X {rr:.2e}", flush=True)
-        assert rr < (2e-4 if prec == ofm.OFM_FP32 else 5e-3)
+        print(f"precision {prec}: {st['iters']} updates, relres of the final X {rr:.2e}",
+              flush=True)
+        assert st["status"] == 0
+        assert rr < (2e-4 if fp32 else 5e-3)
         Y = ofm.row_normalize(X)
         lab, _, _ = ofm.kmeans(Y, 32, O.kmeans_uniforms(0, 32))
         labels[prec] = lab.cpu().numpy()
@@ -73,7 +80,8 @@ def test_bf16_f2_solve_floor_and_labels(lib):
     lap = ofm.Laplacian(g.row_ptr, g.col_idx)
     labels = {}
     for prec in (ofm.OFM_FP32, ofm.OFM_FP32_BF16X):
-        ws = ofm.Workspace(lap, 32, variant="f2", precision=prec, max_iter=400, check_every=10)
+        ws = ofm.Workspace(lap, 32, variant="f2", precision=prec, max_iter=3000, check_every=10,
+                           tol=1e-3)
         X = torch.tensor(x0.astype(np.float32), device="cuda")
         st = ws.solve(X)
         rr = ws.residual(X)["relres"]
