@@ -2084,14 +2084,19 @@ struct FinishPool {
         }
       });
   }
-  // queue a prepared job (starts the threads on first use)
-  void push(Job&& j, int dev, const hipStream_t* streams, void* const* host_X) {
-    if (threads.empty()) start(dev, streams, host_X);
-    {
+  // queue a prepared job (starts the threads on first use); false if the
+  // threads cannot be started (the job is then released)
+  bool push(Job&& j, int dev, const hipStream_t* streams, void* const* host_X) {
+    try {
+      if (threads.empty()) start(dev, streams, host_X);
       std::lock_guard<std::mutex> lk(mu);
       jobs.push_back(std::move(j));
+    } catch (...) {
+      finish_release(j.fin);
+      return false;
     }
     cv.notify_one();
+    return true;
   }
   void join() {
     {
@@ -2412,7 +2417,7 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
           finish_release(jb.fin);
           return ps;
         }
-        pool.push(std::move(jb), dev, B->finish_streams, host_X);
+        if (!pool.push(std::move(jb), dev, B->finish_streams, host_X)) return OFM_E_NOMEM;
       }
     }
     return OFM_OK;
@@ -2510,7 +2515,7 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
           finish_release(jb.fin);
           return ps;
         }
-        pool.push(std::move(jb), dev, B->finish_streams, host_X);
+        if (!pool.push(std::move(jb), dev, B->finish_streams, host_X)) return OFM_E_NOMEM;
       }
       if (!queued[g.idx[m]]) all[g.idx[m]] = st;
     }
