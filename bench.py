@@ -355,6 +355,34 @@ def gather_ceiling(nrows: int = 2_000_000, S: int = 25, reps: int = 5):
     return out
 
 
+def gather_ceiling_for(n: int, nnz: int, k: int, kernel_us: float, reps: int = 5):
+    """The random-row rate that bounds a product with A of this size: n output
+    rows each summing S = nnz / n rows (k FP32 values) drawn uniformly from an
+    n-row table, timed with HIP events (ofm_gather_rows); `kernel_frac` is this
+    time over the kernel's own (1.0 = the kernel gathers as fast as the memory
+    system serves random rows)."""
+    import torch
+    from paper_2305_10356_amd import ofm
+    S = max(1, round(nnz / n))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(n)
+    idx = torch.randint(0, n, (n * S,), generator=gen, device="cuda", dtype=torch.int32)
+    Z = torch.zeros((n, k), dtype=torch.float32, device="cuda")
+    Y = torch.empty((n, k), dtype=torch.float32, device="cuda")
+    for _ in range(2):
+        ofm.gather_rows(idx, Z, S, Y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ofm.gather_rows(idx, Z, S, Y)
+    e1.record()
+    e1.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / reps
+    del idx, Z, Y
+    return {"gathers": n * S, "row_bytes": 4 * k, "table_rows": n, "avg_us": round(us, 1),
+            "G_rows_per_s": round(n * S / us / 1e3, 1), "kernel_frac": round(us / kernel_us, 3)}
+
+
 def streaming_c4(variant: str = "f1", n_final: int = 2_000_000, stages: int = 10,
                  cold_stages=(9,), recur: bool = False, check_every: int = 10,
                  grouped: bool = False, gs=None):
@@ -803,6 +831,11 @@ def main():
         r = launch_roof(p)
         r["traffic"] = int(traffic[p]) if p in traffic else None
         roofline[p] = r
+    if not args.no_extras and dom == "spmm_x" and k in (16, 32, 64):
+        # what the memory system allows the dominant kernel: the same number of
+        # random row gathers (nnz, rows of k FP32 values from an N-row table,
+        # uniform at random) with no sparse-matrix work, timed now
+        roofline["gather_ceiling"] = gather_ceiling_for(n, nnz, k, d["avg_us"])
     log(f"headline {args.variant}: {value:.1f} it/s, {ms_per_step:.3f} ms/step; roofline {roofline}; "
         f"passes {passes}")
 
