@@ -377,7 +377,8 @@ ofm_status ofm_gather_rows(int64_t nrows, int S, int row_floats, const int32_t* 
  * recur, freeze_eps; graph = 1 runs the lockstep loop of ofm_batch_solve, after
  * the schedule has been chosen, as replays of one HIP graph per check_every
  * updates of every graph; the FP64 finishing solves always run eagerly).
- * Allocates the per-graph state.  The block schedule (each graph's blocks on
+ * Allocates the per-graph state (with tol > 0 also a copy of the starting
+ * block of every graph with k <= 32, for the finishing solves below).  The block schedule (each graph's blocks on
  * one XCD; a target of tiles per wavefront, 2, 4, 8 or 16, which sets the
  * blocks per graph, and at most 128 or 64 blocks per XCD) is chosen among these
  * eight candidates by timing the first iterations of the first solve (the GPU
@@ -392,10 +393,12 @@ ofm_status ofm_batch_destroy(ofm_batch b);
  * FP32 block, updated in place); host_stats[count] receives the per-graph
  * stats (iters = updates done, relres of the X it stopped at).  A graph whose
  * FP32 residual decreases by less than 5% over 10 checks before reaching tol
- * (or that reaches max_iter) is finished by an FP64 solve (k <= 32) started
- * from its FP32 X with a fresh CG state; that stage allocates a workspace per
- * finished graph and runs up to 4 of them at once, each on its own stream and
- * host thread.  Synchronizing. */
+ * (or that reaches max_iter) is finished in FP64 (k <= 32) by two solves that
+ * race, one from its FP32 X with a fresh CG state and one from its starting
+ * block: the first to reach tol wins (the other stops at its next residual
+ * check), and with none the first one's result is kept.  That stage allocates
+ * a workspace per solve and runs up to 4 of them at once, each on its own
+ * stream and host thread, once the FP32 loop has ended.  Synchronizing. */
 ofm_status ofm_batch_solve(ofm_batch b, void* const* host_X, hipStream_t stream,
                            ofm_stats* host_stats);
 /*
@@ -436,8 +439,9 @@ ofm_status ofm_batch_schedule(ofm_batch b, int group, int* host_ngroups, int* ho
  * solve.  Errors: OFM_E_INVALID_ARG for another value. */
 ofm_status ofm_batch_set_schedule(ofm_batch b, int tpw, int workers);
 /* Host wall time of the last solve's two stages: the lockstep FP32 loop
- * (host_loop_ms) and the FP64 finishing solves (host_finish_ms), which run
- * concurrently on up to 4 streams of the batch; host_replays: graph replays
+ * (host_loop_ms, to the end of its last iteration) and what follows it
+ * (host_finish_ms: the per-graph statistics and the FP64 finishing solves,
+ * which run concurrently on up to 4 streams of the batch); host_replays: graph replays
  * of the lockstep loop (0 without opts.graph).  Any pointer may be NULL. */
 ofm_status ofm_batch_phases(ofm_batch b, double* host_loop_ms, double* host_finish_ms,
                             int64_t* host_replays);

@@ -10,6 +10,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <numeric>
 #include <thread>
@@ -929,10 +930,13 @@ extern "C" ofm_status ofm_workspace_create(ofm_laplacian lap, int k, const ofm_o
   if ((st = dev_alloc(&ws->lvl2, lvl2_size)) != OFM_OK) return fail(st);
   if ((st = dev_alloc(&ws->status, 1)) != OFM_OK) return fail(st);
   if ((st = dev_alloc(&ws->frozen, 1)) != OFM_OK) return fail(st);
-  if (hipMemset(ws->sc, 0, sc_total(k) * sizeof(double)) != hipSuccess ||
-      hipMemset(ws->status, 0, sizeof(int)) != hipSuccess ||
-      hipMemset(ws->frozen, 0, sizeof(int)) != hipSuccess ||
-      hipDeviceSynchronize() != hipSuccess)
+  // cleared on the null stream, which the library's non-blocking streams do
+  // not wait for, and waited for alone: creating a workspace does not wait
+  // for work in flight elsewhere on the device
+  if (hipMemsetAsync(ws->sc, 0, sc_total(k) * sizeof(double), nullptr) != hipSuccess ||
+      hipMemsetAsync(ws->status, 0, sizeof(int), nullptr) != hipSuccess ||
+      hipMemsetAsync(ws->frozen, 0, sizeof(int), nullptr) != hipSuccess ||
+      hipStreamSynchronize(nullptr) != hipSuccess)
     return fail(OFM_E_HIP);
   // gather policy: the hot/cold path addresses the block with 31-bit offsets
   const bool hc_ok = o.precision != OFM_FP32_BF16X && blk <= (size_t)0x7fffffff;
@@ -1306,9 +1310,9 @@ static ofm_status run_chunk(ofm_workspace ws, void* X, hipStream_t stream) {
   return OFM_OK;
 }
 
-extern "C" ofm_status ofm_solve(ofm_workspace ws, void* X, hipStream_t stream,
-                                ofm_stats* host_out) {
-  if (!ws || !X) return OFM_E_INVALID_ARG;
+// The solve loop; `stop` (nullable) ends it at a residual check once nonzero.
+static ofm_status solve_loop(ofm_workspace ws, void* X, hipStream_t stream, ofm_stats* host_out,
+                             const std::atomic<int>* stop) {
   OFMCHK(ofm_init(ws, X, stream));
   ofm_stats st{};
   const int ce = ws->opts.check_every;
@@ -1329,11 +1333,18 @@ extern "C" ofm_status ofm_solve(ofm_workspace ws, void* X, hipStream_t stream,
         ws->t = st.relres_iter;
         break;
       }
+      if (stop && stop->load() != 0) break;
     }
   }
   OFMCHK(read_stats(ws, stream, &st));
   if (host_out) *host_out = st;
   return (ofm_status)st.status;
+}
+
+extern "C" ofm_status ofm_solve(ofm_workspace ws, void* X, hipStream_t stream,
+                                ofm_stats* host_out) {
+  if (!ws || !X) return OFM_E_INVALID_ARG;
+  return solve_loop(ws, X, stream, host_out, nullptr);
 }
 
 extern "C" ofm_status ofm_residual(ofm_workspace ws, const void* X, hipStream_t stream,
@@ -1754,10 +1765,15 @@ struct ofm_batch_s {
   hipGraphExec_t chunk[2] = {nullptr, nullptr};
   std::vector<int> chunk_cand;
   int64_t replays = 0;     // chunks replayed by the last solve
+  // copies of the starting blocks of the graphs that may be finished in FP64
+  // (k <= 32, with a tolerance), taken when a solve starts: x0 + x0_off[i]
+  float* x0 = nullptr;
+  std::vector<int64_t> x0_off;  // -1: no copy
 };
 
 static void free_batch(ofm_batch b) {
   if (!b) return;
+  dev_free(b->x0);
   for (auto& e : b->chunk)
     if (e) (void)hipGraphExecDestroy(e);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
@@ -1942,6 +1958,19 @@ extern "C" ofm_status ofm_batch_create(int count, const ofm_laplacian* host_laps
         hipMemcpy(g.dxoff, xoff.data(), 9 * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
       return fail(OFM_E_HIP);
   }
+  B->x0_off.assign(count, -1);
+  if (o.tol > 0.0) {
+    int64_t tot = 0;
+    for (int i = 0; i < count; ++i)
+      if (host_ks[i] <= 32) {
+        B->x0_off[i] = tot;
+        tot += ((host_laps[i]->g.n * host_ks[i] + 63) / 64) * 64;
+      }
+    if (tot > 0) {
+      ofm_status st2 = dev_alloc(&B->x0, tot);
+      if (st2 != OFM_OK) return fail(st2);
+    }
+  }
   *out = B;
   return OFM_OK;
 }
@@ -1993,11 +2022,12 @@ extern "C" ofm_status ofm_batch_phases(ofm_batch b, double* host_loop_ms, double
   return OFM_OK;
 }
 
-// FP64 solve of one graph from its FP32 block, in three parts: the workspace
-// and the FP64 block are made on the calling thread before the finishing
-// threads start, so that the threads neither allocate, free nor synchronize
-// the device; the solve runs on the graph's own stream (synchronizing on it)
-// and the FP32 block receives the result; the release follows the join.
+// FP64 solves of one graph that the FP32 loop did not finish, in three parts:
+// the workspace and the FP64 block are made on the calling thread before the
+// finishing threads start, so that the threads neither allocate, free nor
+// synchronize the device; the solve runs on a thread's own stream; the result
+// is written back to the graph's FP32 block on the calling thread after the
+// threads have joined.
 struct Finish {
   ofm_workspace ws = nullptr;
   double* X64 = nullptr;
@@ -2018,13 +2048,19 @@ static ofm_status finish_prepare(ofm_laplacian L, int k, const ofm_opts& o, int6
   return dev_alloc(&f->X64, L->g.n * k);
 }
 
-static ofm_status finish_run(Finish& f, void* X32, hipStream_t s, ofm_stats* out) {
+// solve from the FP32 block src until converged, out of updates, or `claim`
+// turns nonzero (the other solve of the same graph converged first); a
+// converged solve claims the graph with `me` unless the other one has
+static ofm_status finish_run(Finish& f, const void* src, hipStream_t s, ofm_stats* out,
+                             std::atomic<int>* claim, int me) {
+  if (claim->load() != 0) return OFM_OK;  // decided before this solve started
   const int64_t cnt = f.ws->n * f.ws->k;
-  if (launch_convert(cnt, 1, X32, f.X64, s) != hipSuccess) return OFM_E_HIP;
-  ofm_status es = ofm_solve(f.ws, f.X64, s, out);
-  if (es == OFM_OK || es == OFM_E_NONFINITE || es == OFM_E_NUMERIC) {
-    if (launch_convert(cnt, 0, f.X64, X32, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
-      es = OFM_E_HIP;
+  if (launch_convert(cnt, 1, src, f.X64, s) != hipSuccess) return OFM_E_HIP;
+  const ofm_status es = solve_loop(f.ws, f.X64, s, out, claim);
+  if (hipStreamSynchronize(s) != hipSuccess) return OFM_E_HIP;
+  if (es == OFM_OK && out->converged) {
+    int none = 0;
+    claim->compare_exchange_strong(none, me);
   }
   return es;
 }
@@ -2035,29 +2071,43 @@ static void finish_release(Finish& f) {
   f = Finish{};
 }
 
-// The finishing solves of a batched solve: a graph whose FP32 residual has
-// stalled is queued as soon as a residual check finds it (its workspace made
-// on the solving thread) and solved by one of kFinishThreads threads, each on
-// a stream of its own, while the FP32 loop of the other graphs goes on; the
-// graphs that end the loop unconverged follow.  Jobs live in a deque, whose
-// elements keep their addresses as jobs are added.
+// The FP64 finishing solves of a batched solve.  A graph that the FP32 loop
+// leaves unconverged gets two solves that race: one continues from its FP32
+// iterate (fast when the FP32 iteration stopped at its rounding floor), one
+// restarts from its starting block (the FP32 rounding path can lead into a
+// region where the iteration creeps, which an FP64 run from the start need not
+// meet); the first to reach the tolerance wins and stops the other at its next
+// residual check; with no winner the continued solve's result is kept.  The
+// solves start once the FP32 loop has ended (run beside it, they slowed it by
+// more than they gained).  kFinishThreads threads, each with a stream of its
+// own, take the jobs in order.  Jobs live in a deque, whose elements keep
+// their addresses as jobs are added.
 struct FinishPool {
+  enum : int { kContinue = 1, kRestart = 2 };
   struct Job {
     int graph = 0;
-    ofm_stats st{};   // FP32 stats on entry, combined with the FP64 solve's
+    int kind = kContinue;
+    const void* src = nullptr;  // FP32 block the solve starts from
+    ofm_stats st{};             // FP32 stats on entry
+    ofm_stats s64{};            // the FP64 solve's
     ofm_status es = OFM_OK;
     Finish fin;
   };
   std::deque<Job> jobs;
+  std::unique_ptr<std::atomic<int>[]> claim;  // per graph: 0, or the winning kind
   std::mutex mu;
   std::condition_variable cv;
   size_t next = 0;
   bool closed = false;
   std::vector<std::thread> threads;
 
-  void start(int dev, const hipStream_t* streams, void* const* host_X) {
+  explicit FinishPool(int count) : claim(new std::atomic<int>[count]) {
+    for (int i = 0; i < count; ++i) claim[i].store(0);
+  }
+
+  void start(int dev, const hipStream_t* streams) {
     for (int i = 0; i < kFinishThreads; ++i)
-      threads.emplace_back([this, dev, s = streams[i], host_X] {
+      threads.emplace_back([this, dev, s = streams[i]] {
         const bool on_device = hipSetDevice(dev) == hipSuccess;
         for (;;) {
           Job* jb = nullptr;
@@ -2067,28 +2117,16 @@ struct FinishPool {
             if (next >= jobs.size()) return;
             jb = &jobs[next++];
           }
-          if (!on_device) {
-            jb->es = OFM_E_HIP;
-            continue;
-          }
-          ofm_stats s64{};
-          jb->es = finish_run(jb->fin, host_X[jb->graph], s, &s64);
-          if (jb->es == OFM_OK || jb->es == OFM_E_NONFINITE || jb->es == OFM_E_NUMERIC) {
-            jb->st.iters += s64.iters;
-            jb->st.relres = s64.relres;
-            jb->st.objective = s64.objective;
-            jb->st.relres_iter = jb->st.iters - s64.iters + s64.relres_iter;
-            jb->st.status = s64.status;
-            jb->st.converged = s64.converged;
-          }
+          jb->es = on_device ? finish_run(jb->fin, jb->src, s, &jb->s64, &claim[jb->graph], jb->kind)
+                             : OFM_E_HIP;
         }
       });
   }
   // queue a prepared job (starts the threads on first use); false if the
   // threads cannot be started (the job is then released)
-  bool push(Job&& j, int dev, const hipStream_t* streams, void* const* host_X) {
+  bool push(Job&& j, int dev, const hipStream_t* streams) {
     try {
-      if (threads.empty()) start(dev, streams, host_X);
+      if (threads.empty()) start(dev, streams);
       std::lock_guard<std::mutex> lk(mu);
       jobs.push_back(std::move(j));
     } catch (...) {
@@ -2112,6 +2150,27 @@ struct FinishPool {
     for (auto& j : jobs) finish_release(j.fin);
   }
 };
+
+// both finishing solves of graph i (FP32 stats st on entry, used updates done)
+static ofm_status queue_finish(ofm_batch B, FinishPool& pool, int i, int k, const ofm_stats& st,
+                               int dev, void* const* host_X) {
+  for (int kind : {FinishPool::kContinue, FinishPool::kRestart}) {
+    if (kind == FinishPool::kRestart && (!B->x0 || B->x0_off[i] < 0)) continue;
+    FinishPool::Job jb;
+    jb.graph = i;
+    jb.kind = kind;
+    jb.src = kind == FinishPool::kContinue ? host_X[i]
+                                           : static_cast<const void*>(B->x0 + B->x0_off[i]);
+    jb.st = st;
+    const ofm_status ps = finish_prepare(B->laps[i], k, B->opts, st.iters, &jb.fin);
+    if (ps != OFM_OK) {
+      finish_release(jb.fin);
+      return ps;
+    }
+    if (!pool.push(std::move(jb), dev, B->finish_streams)) return OFM_E_NOMEM;
+  }
+  return OFM_OK;
+}
 
 // the passes of one batched group: a dense or SpMM launch plus its per-graph
 // reduction
@@ -2390,38 +2449,18 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
   // group's own time under contention would favour schedules that only take
   // more of it from the others.
   B->replays = 0;
+  // the starting blocks of the graphs that may need a finishing solve
+  if (B->x0)
+    for (int i = 0; i < B->count; ++i)
+      if (B->x0_off[i] >= 0)
+        HIPCHK(hipMemcpyAsync(B->x0 + B->x0_off[i], host_X[i],
+                              (size_t)B->laps[i]->g.n * B->ks[i] * sizeof(float),
+                              hipMemcpyDeviceToDevice, stream));
   OFMCHK(batch_start(B, host_X, stream));
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
-  FinishPool pool;
+  FinishPool pool(B->count);
   std::vector<char> queued(B->count, 0);
-  // at a residual check (the host has synchronized with it): queue the graphs
-  // whose residual has stalled since the last one
-  auto escalate_stalled = [&]() -> ofm_status {
-    if (!(o.tol > 0.0)) return OFM_OK;
-    for (auto& g : B->groups) {
-      if (g.k > 32) continue;
-      const int n = (int)g.idx.size();
-      std::vector<int> stl(n);
-      HIPCHK(hipMemcpy(stl.data(), g.stalled, n * sizeof(int), hipMemcpyDeviceToHost));
-      for (int m = 0; m < n; ++m) {
-        const int i = g.idx[m];
-        if (!stl[m] || queued[i] || B->t >= o.max_iter) continue;
-        queued[i] = 1;
-        FinishPool::Job jb;
-        jb.graph = i;
-        jb.st.iters = B->t;
-        jb.st.status = OFM_OK;
-        const ofm_status ps = finish_prepare(B->laps[i], g.k, o, B->t, &jb.fin);
-        if (ps != OFM_OK) {
-          finish_release(jb.fin);
-          return ps;
-        }
-        if (!pool.push(std::move(jb), dev, B->finish_streams, host_X)) return OFM_E_NOMEM;
-      }
-    }
-    return OFM_OK;
-  };
   const bool tune = B->fixed < 0 && !B->tuned;
   const int64_t tune_end = tune ? 1 + 2 * kBatchCand : 0;
   bool on_stream = false;  // the loop runs as graph replays on `stream`
@@ -2437,7 +2476,6 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
       int any = 0;
       OFMCHK(batch_any_active(B, stream, &any));
       if (!any) break;
-      OFMCHK(escalate_stalled());
       continue;
     }
     if (on_stream) {
@@ -2471,16 +2509,17 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
       int any = 0;
       OFMCHK(batch_any_active(B, stream, &any));
       if (!any) break;
-      OFMCHK(escalate_stalled());
     }
   }
   if (on_stream) OFMCHK(batch_fork(B, stream));
+  for (auto& g : B->groups) HIPCHK(hipStreamSynchronize(g.stream));
+  const auto t_loop = std::chrono::steady_clock::now();
+  B->loop_ms = std::chrono::duration<double, std::milli>(t_loop - t_solve).count();
   const int64_t t = B->t;
   const int64_t last_check = B->last_check;
   B->escalated = 0;
   // per-graph stats; a graph whose FP32 residual stopped decreasing before the
-  // tolerance (or ran out of iterations) is finished in FP64 from its FP32 X:
-  // queued at the check that found it stalled, or now
+  // tolerance (or ran out of iterations) is finished in FP64
   std::vector<ofm_stats> all(B->count);
   for (auto& g : B->groups) {
     HIPCHK(hipStreamSynchronize(g.stream));
@@ -2507,31 +2546,39 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
                             st.iters < o.max_iter && !queued[g.idx[m]];
       if (escalate) {
         queued[g.idx[m]] = 1;
-        FinishPool::Job jb;
-        jb.graph = g.idx[m];
-        jb.st = st;
-        const ofm_status ps = finish_prepare(B->laps[jb.graph], g.k, o, st.iters, &jb.fin);
-        if (ps != OFM_OK) {
-          finish_release(jb.fin);
-          return ps;
-        }
-        if (!pool.push(std::move(jb), dev, B->finish_streams, host_X)) return OFM_E_NOMEM;
+        OFMCHK(queue_finish(B, pool, g.idx[m], g.k, st, dev, host_X));
       }
       if (!queued[g.idx[m]]) all[g.idx[m]] = st;
     }
   }
-  const auto t_loop = std::chrono::steady_clock::now();
-  B->loop_ms = std::chrono::duration<double, std::milli>(t_loop - t_solve).count();
   // the remaining finishing solves (the batch's groups have completed: every
   // group stream was synchronized above)
   pool.join();
-  for (auto& jb : pool.jobs) {
+  for (auto& jb : pool.jobs)
     if (jb.es == OFM_E_HIP || jb.es == OFM_E_NOMEM || jb.es == OFM_E_INVALID_ARG ||
         jb.es == OFM_E_SHAPE || jb.es == OFM_E_UNSUPPORTED)
       return jb.es;
-    all[jb.graph] = jb.st;
+  // per finished graph: the winning solve, else the one continued from the
+  // FP32 iterate; its FP64 block goes back to the graph's FP32 block
+  for (auto& jb : pool.jobs) {
+    const int won = pool.claim[jb.graph].load();
+    if (won != 0 ? jb.kind != won : jb.kind != FinishPool::kContinue) continue;
+    ofm_stats st = jb.st;
+    if (jb.es == OFM_OK || jb.es == OFM_E_NONFINITE || jb.es == OFM_E_NUMERIC) {
+      const ofm_stats& r = jb.s64;
+      st.iters += r.iters;
+      st.relres = r.relres;
+      st.objective = r.objective;
+      st.relres_iter = st.iters - r.iters + r.relres_iter;
+      st.status = r.status;
+      st.converged = r.converged;
+      const int64_t cnt = jb.fin.ws->n * jb.fin.ws->k;
+      HIPCHK(launch_convert(cnt, 0, jb.fin.X64, host_X[jb.graph], stream));
+    }
+    all[jb.graph] = st;
     ++B->escalated;
   }
+  HIPCHK(hipStreamSynchronize(stream));
   B->finish_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_loop).count();
   if (host_stats)
