@@ -2460,7 +2460,6 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   FinishPool pool(B->count);
-  std::vector<char> queued(B->count, 0);
   const bool tune = B->fixed < 0 && !B->tuned;
   const int64_t tune_end = tune ? 1 + 2 * kBatchCand : 0;
   bool on_stream = false;  // the loop runs as graph replays on `stream`
@@ -2543,16 +2542,13 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
       st.status = device_status(stt[m]);
       st.converged = (done[m] >= 0 && st.status == OFM_OK) ? 1 : 0;
       const bool escalate = !st.converged && st.status == OFM_OK && o.tol > 0.0 && g.k <= 32 &&
-                            st.iters < o.max_iter && !queued[g.idx[m]];
-      if (escalate) {
-        queued[g.idx[m]] = 1;
-        OFMCHK(queue_finish(B, pool, g.idx[m], g.k, st, dev, host_X));
-      }
-      if (!queued[g.idx[m]]) all[g.idx[m]] = st;
+                            st.iters < o.max_iter;
+      if (escalate) OFMCHK(queue_finish(B, pool, g.idx[m], g.k, st, dev, host_X));
+      all[g.idx[m]] = st;  // replaced below for the finished graphs
     }
   }
-  // the remaining finishing solves (the batch's groups have completed: every
-  // group stream was synchronized above)
+  // the finishing solves (the batch's groups have completed: every group
+  // stream was synchronized above)
   pool.join();
   for (auto& jb : pool.jobs)
     if (jb.es == OFM_E_HIP || jb.es == OFM_E_NOMEM || jb.es == OFM_E_INVALID_ARG ||
