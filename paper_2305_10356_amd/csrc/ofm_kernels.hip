@@ -994,10 +994,89 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
 
   const int64_t ntiles = (a.n + G::TR - 1) / G::TR;
   const int64_t stride = (int64_t)nblk * WPB;
+  // The k = 32 V pass with X^T A V (split products) prefetches: each wave
+  // issues the global loads of its next tile before the workgroup's products
+  // over the staged tiles (a workgroup barrier waits for the LDS only, so the
+  // loads stay in flight through the products): 299 -> 267 us at N = 2M.  The
+  // loop below then does not run.  At k = 64 the prefetch registers cost the V
+  // pass a wave per SIMD and it measured slower (678 -> 753 us).
+  constexpr bool PF = SPLIT && MODE == kVPassE;
+  if constexpr (PF) {
+    V16<T> pg[G::NPASS], px[G::NPASS], pv[G::NPASS], pa[G::NPASS];
+    auto fetch = [&](int64_t tbn) {
+      const int64_t tn = tbn + wave;
+      const int64_t rn = tn * G::TR;
+      const int cn = tn >= ntiles ? 0 : (int)((a.n - rn) < G::TR ? (a.n - rn) : G::TR);
+#pragma unroll
+      for (int pass = 0; pass < G::NPASS; ++pass) {
+        const int gi = pass * G::RPW + g;
+        if (gi < cn) {
+          const size_t off = (size_t)(rn + gi) * KP + j * G::VECN;
+          pg[pass] = ld16(static_cast<const T*>(a.G) + off);
+          px[pass] = ld16(static_cast<const T*>(a.X) + off);
+          if (!first) pv[pass] = ld16(static_cast<const T*>(a.Vp) + off);
+          if constexpr (HASE) pa[pass] = ld16(static_cast<const T*>(a.AX) + off);
+        }
+      }
+    };
+    int64_t tb = (int64_t)brank * WPB;
+    if (tb < ntiles) fetch(tb);
+    for (; tb < ntiles; tb += stride) {
+      const int64_t t = tb + wave;
+      const int64_t r0 = t * G::TR;
+      const int cnt = t >= ntiles ? 0 : (int)((a.n - r0) < G::TR ? (a.n - r0) : G::TR);
+#pragma unroll
+      for (int pass = 0; pass < G::NPASS; ++pass) {
+        const int gi = pass * G::RPW + g;
+        const bool ok = gi < cnt;
+        const size_t off = (size_t)(r0 + gi) * KP + j * G::VECN;
+        V16<T> v, x;
+        if (ok) {
+          const V16<T> gv = pg[pass];
+          x = px[pass];
+          if (!first) {
+#pragma unroll
+            for (int q = 0; q < G::VECN; ++q) v.v[q] = fma(colscal[q], pv[pass].v[q], -gv.v[q]);
+          } else {
+#pragma unroll
+            for (int q = 0; q < G::VECN; ++q) v.v[q] = -gv.v[q];
+          }
+          st16(static_cast<T*>(a.V) + off, v);
+          if constexpr (sizeof(T) == 4) {
+            if (a.Vb) st_bf16<KP>(a.Vb, (size_t)(r0 + gi), j, v);
+          }
+#pragma unroll
+          for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)v.v[q] * (double)gv.v[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < G::VECN; ++q) v.v[q] = x.v[q] = T(0);
+        }
+        if (gi < G::TR) {
+          tile_store_vec<T, KP>(t0, gi, j, v);
+          tile_store_vec<T, KP>(t1, gi, j, x);
+        }
+        if constexpr (HASE) {
+          V16<T> ax;
+          if (ok) {
+            ax = pa[pass];
+          } else {
+#pragma unroll
+            for (int q = 0; q < G::VECN; ++q) ax.v[q] = T(0);
+          }
+          if (gi < G::TR) tile_store_vec<T, KP>(t2, gi, j, ax);
+        }
+      }
+      if (tb + stride < ntiles) fetch(tb + stride);
+      __syncthreads();
+      sg.accumulate(reinterpret_cast<const T*>(smem + SM::frag_bytes),
+                    SM::wave_bytes / (int)sizeof(T), lane);
+      __syncthreads();
+    }
+  }
   // per wave: tiles brank * WPB + wave + i * stride.  With the split products
   // the WPB waves run the loop together (a wave past the last tile stages
   // zeros) and meet at a barrier before and after the products.
-  for (int64_t tb = (int64_t)brank * WPB; tb < ntiles; tb += stride) {
+  for (int64_t tb = PF ? ntiles : (int64_t)brank * WPB; tb < ntiles; tb += stride) {
     const int64_t t = tb + wave;
     if (!SPLIT && t >= ntiles) break;
     const int64_t r0 = t * G::TR;
