@@ -531,14 +531,14 @@ struct SplitGram {
   }
 };
 
-// passes whose products are dealt to the waves (FP32 k = 64; the FP32 V pass
-// with X^T A V at k = 32)
+// passes whose products are dealt to the waves (FP32 k = 64; the FP32 V
+// passes at k = 32, which also prefetch)
 template <typename T, int KP, int MODE>
 constexpr bool split_gram_mode() {
   return sizeof(T) == 4 &&
          ((KP == 64 && (MODE == kVPass || MODE == kUpdate || MODE == kGramM ||
                         MODE == kUpdateR || MODE == kEF)) ||
-          (KP == 32 && MODE == kVPassE));
+          (KP == 32 && (MODE == kVPassE || MODE == kVPass)));
 }
 
 template <typename T, int KP>
@@ -994,13 +994,14 @@ __device__ __forceinline__ void dense_body(const PassArgs& a, int brank, int nbl
 
   const int64_t ntiles = (a.n + G::TR - 1) / G::TR;
   const int64_t stride = (int64_t)nblk * WPB;
-  // The k = 32 V pass with X^T A V (split products) prefetches: each wave
-  // issues the global loads of its next tile before the workgroup's products
-  // over the staged tiles (a workgroup barrier waits for the LDS only, so the
-  // loads stay in flight through the products): 299 -> 267 us at N = 2M.  The
-  // loop below then does not run.  At k = 64 the prefetch registers cost the V
-  // pass a wave per SIMD and it measured slower (678 -> 753 us).
-  constexpr bool PF = SPLIT && MODE == kVPassE;
+  // The FP32 k = 32 V passes (split products) prefetch: each wave issues the
+  // global loads of its next tile before the workgroup's products over the
+  // staged tiles (a workgroup barrier waits for the LDS only, so the loads
+  // stay in flight through the products): at N = 2M the V pass with X^T A V
+  // 299 -> 267 us, the plain one 202 (unsplit) -> 194 us.  The loop below then
+  // does not run.  At k = 64 the prefetch registers cost the V pass a wave per
+  // SIMD and it measured slower (678 -> 753 us).
+  constexpr bool PF = SPLIT && VP && KP <= 32;
   if constexpr (PF) {
     V16<T> pg[G::NPASS], px[G::NPASS], pv[G::NPASS], pa[G::NPASS];
     auto fetch = [&](int64_t tbn) {
