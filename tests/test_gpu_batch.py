@@ -80,8 +80,9 @@ def test_batch_converges_each_graph(batch_graphs, variant, recur):
 def test_batch_escalates_fp32_straggler(lib, graph):
     # member 64 of the 256-graph workload (N=39,756, k=16, mean degree 8.1):
     # its FP32 iteration levels off near residual 1.2e-4, so the batch finishes
-    # it in FP64 from the FP32 iterate (also when the lockstep loop is replayed
-    # as HIP graphs)
+    # it in FP64, by the two racing solves (from the FP32 iterate and from the
+    # starting block), also when the lockstep loop is replayed as HIP graphs;
+    # whichever wins, the X written back meets the tolerance
     from paper_2305_10356_amd import ofm
     specs = graphs.batched_graph_specs(256)
     members = [specs[64], specs[0], specs[1]]
