@@ -95,6 +95,10 @@ def test_batch_escalates_fp32_straggler(lib, graph):
     _, esc = B.schedule()
     print(f"straggler batch: {[(s['iters'], s['relres']) for s in st]} escalated {esc}", flush=True)
     assert esc >= 1
+    # continued from its FP32 iterate this member needs about 590 more FP64
+    # updates (the FP32 path led it where the iteration creeps); restarted from
+    # its starting block in FP64, about 160: the race keeps the faster one
+    assert st[0]["iters"] < 600, st[0]
     for (g, _), X, s in zip(gl, Xs, st):
         assert s["converged"] == 1
         olap = O.laplacian(g.n, g.row_ptr, g.col_idx)
