@@ -451,60 +451,73 @@ struct SplitGram {
   static constexpr int NT = G::NT;
   static constexpr int PER = (NT * (NT + 1) / 2 + (NG - 1) * NT * NT + WPB - 1) / WPB;
   d4 acc[PER];
-  int offa[PER], offb[PER];  // LDS element offsets within a wave's staging area
-  int grp[PER], ti[PER], tj[PER];
-  int nprod = 0;
+  // LDS element offsets of the operands within a staging area (wave-uniform:
+  // the lane's own row and column are added when reading)
+  int offa[PER], offb[PER];
+  int wv = 0, nprod = 0, n0 = 0, n1 = 0;
+  bool sym0 = false, sym1 = false;
 
-  __device__ void setup(int wave, int lane, int sa0, int sb0, bool sym0, int sa1, int sb1,
-                        bool sym1, int ngroups, int sa2 = 0, int sb2 = 0) {
-    const int n0 = sym0 ? NT * (NT + 1) / 2 : NT * NT;
-    const int n1 = ngroups > 1 ? (sym1 ? NT * (NT + 1) / 2 : NT * NT) : 0;
+  // group g and output tile (i, jj) of product p
+  __device__ void locate(int p, int& g, int& i, int& jj) const {
+    g = p < n0 ? 0 : p < n0 + n1 ? 1 : 2;
+    int r = g == 0 ? p : g == 1 ? p - n0 : p - n0 - n1;
+    const bool sym = g == 0 ? sym0 : g == 1 ? sym1 : false;
+    i = 0;
+    if (sym) {
+      while (r >= NT - i) {
+        r -= NT - i;
+        ++i;
+      }
+      jj = i + r;
+    } else {
+      i = r / NT;
+      jj = r % NT;
+    }
+  }
+
+  __device__ void setup(int wave, int lane, int sa0, int sb0, bool s0, int sa1, int sb1,
+                        bool s1, int ngroups, int sa2 = 0, int sb2 = 0) {
+    wv = wave;
+    sym0 = s0;
+    sym1 = s1;
+    n0 = s0 ? NT * (NT + 1) / 2 : NT * NT;
+    n1 = ngroups > 1 ? (s1 ? NT * (NT + 1) / 2 : NT * NT) : 0;
     const int n2 = ngroups > 2 ? NT * NT : 0;  // a third group is a full product
     nprod = n0 + n1 + n2;
-    const int f = lane & 15;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       acc[q] = d4{0.0, 0.0, 0.0, 0.0};
       const int p = q * WPB + wave;
       int g = 0, i = 0, jj = 0;
-      if (p < nprod) {
-        g = p < n0 ? 0 : p < n0 + n1 ? 1 : 2;
-        int r = g == 0 ? p : g == 1 ? p - n0 : p - n0 - n1;
-        const bool sym = g == 0 ? sym0 : g == 1 ? sym1 : false;
-        if (sym) {
-          while (r >= NT - i) {
-            r -= NT - i;
-            ++i;
-          }
-          jj = i + r;
-        } else {
-          i = r / NT;
-          jj = r % NT;
-        }
-      }
-      grp[q] = p < nprod ? g : -1;
-      ti[q] = i;
-      tj[q] = jj;
+      if (p < nprod) locate(p, g, i, jj);
       const int sa = g == 0 ? sa0 : g == 1 ? sa1 : sa2;
       const int sb = g == 0 ? sb0 : g == 1 ? sb1 : sb2;
-      offa[q] = sa * G::TILE_ELEMS + 16 * i + f;
-      offb[q] = sb * G::TILE_ELEMS + 16 * jj + f;
+      offa[q] = __builtin_amdgcn_readfirstlane(sa * G::TILE_ELEMS + 16 * i);
+      offb[q] = __builtin_amdgcn_readfirstlane(sb * G::TILE_ELEMS + 16 * jj);
     }
   }
+  // a wave that holds no products (it still takes part in out's barriers)
+  __device__ void none() { nprod = 0; }
 
-  // every staged tile of the workgroup (waves' areas wave_elems apart)
+  // every staged tile of the workgroup (waves' areas wave_elems apart), in
+  // steps of 4 rows.  FREE: a slot this wave does not own is multiplied too
+  // (from valid offsets, never written out), so that no branch separates the
+  // matrix instructions and the LDS reads of later products overlap them
+  // (vpass_ws_kernel at 2M rows: 591 us with a branch per product, 565 us
+  // without; 546 us once the offsets were also wave-uniform).  The other
+  // passes keep the branch, with the register use their occupancy was set by.
+  template <bool FREE = false>
   __device__ void accumulate(const T* stage0, int wave_elems, int lane) {
+    const T* lb = stage0 + (lane >> 4) * G::LDST + (lane & 15);
     for (int w = 0; w < WPB; ++w) {
-      const T* tb = stage0 + w * wave_elems;
 #pragma unroll
       for (int s4 = 0; s4 < 4 * G::NSUB; ++s4) {
-        const int r = (4 * s4 + (lane >> 4)) * G::LDST;
+        const T* tb = lb + w * wave_elems + 4 * s4 * G::LDST;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-          if (q * WPB >= nprod) continue;
-          if (grp[q] < 0) continue;
-          const double x = (double)tb[r + offa[q]];
-          const double y = (double)tb[r + offb[q]];
+          if (q * WPB >= nprod || (!FREE && q * WPB + wv >= nprod)) continue;
+          const double x = (double)tb[offa[q]];
+          const double y = (double)tb[offb[q]];
           acc[q] = mma64(x, y, acc[q]);
         }
       }
@@ -516,13 +529,17 @@ struct SplitGram {
   __device__ void out(int g, bool sym, double* red, double* prow, int off, int lane) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      if (grp[q] != g) continue;
+      const int p = q * WPB + wv;
+      if (p >= nprod) continue;
+      int gq, ti, tj;
+      locate(p, gq, ti, tj);
+      if (gq != g) continue;
 #pragma unroll
       for (int qq = 0; qq < 4; ++qq) {
-        const int ra = 16 * ti[q] + MF<double>::out_row(lane, qq);
-        const int cb = 16 * tj[q] + (lane & 15);
+        const int ra = 16 * ti + MF<double>::out_row(lane, qq);
+        const int cb = 16 * tj + (lane & 15);
         red[ra * KP + cb] = acc[q][qq];
-        if (sym && tj[q] > ti[q]) red[cb * KP + ra] = acc[q][qq];
+        if (sym && tj > ti) red[cb * KP + ra] = acc[q][qq];
       }
     }
     __syncthreads();
@@ -1323,6 +1340,149 @@ __global__ void __launch_bounds__((Cfg<T, KP>::WPB * 64)) dense_kernel(PassArgs 
   dense_body<T, KP, MODE>(a, blockIdx.x, gridDim.x, smem);
 }
 
+// The FP32 k = 64 V pass with the waves of a workgroup given one job each.
+// Waves 0-3 (loaders) stream G, V_prev and X of one 16-row tile each per
+// round, form V = -G + V_prev diag(beta), store it and stage the V and X tiles
+// in LDS; waves 4-7 hold the FP64 products (V^T V upper triangle and X^T V,
+// dealt as in SplitGram) and multiply the tiles staged in the round before.
+// The rounds alternate between two staging buffers with one workgroup barrier
+// each, so the matrix cores run while the loaders wait for memory, and no
+// wave holds both the accumulators and loads in flight.  Partial row:
+// [P | C | diag V^T G], as the V pass writes it.
+constexpr int kVpwLoaders = 4;
+struct VPassWS {
+  using G = Geo<float, 64>;
+  static constexpr int AREA = 2 * G::TILE_ELEMS;  // V and X tiles of one loader (floats)
+  static constexpr int BUF = kVpwLoaders * AREA;  // one round's tiles (floats)
+  static constexpr int main_bytes = 2 * BUF * (int)sizeof(float);
+  static constexpr int red_bytes = 64 * 64 * 8;
+  static constexpr int bytes = main_bytes > red_bytes ? main_bytes : red_bytes;
+};
+
+__global__ void __launch_bounds__(2 * kVpwLoaders * 64, 4) vpass_ws_kernel(PassArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int KP = 64;
+  using T = float;
+  using G = Geo<T, KP>;
+  using W = VPassWS;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const bool loader = wv < kVpwLoaders;
+  const int g = lane / G::LPR;
+  const int j = lane % G::LPR;
+  const double* sc = a.sc;
+  const bool restart = (a.flags & kFlagRestart) != 0;
+  const bool first = (a.flags & kFlagFirst) != 0;
+
+  T beta_c[G::VECN];
+#pragma unroll
+  for (int q = 0; q < G::VECN; ++q) {
+    const int c = j * G::VECN + q;
+    double beta = 0.0;
+    if (!first) {
+      const double den = sc[SC<KP>::GGP + c];
+      const double num = sc[SC<KP>::GG + c] - sc[SC<KP>::GPG + c];
+      beta = (den != 0.0) ? num / den : 0.0;
+      if (restart && (-sc[SC<KP>::GG + c] + beta * sc[SC<KP>::VPG + c]) >= 0.0) beta = 0.0;
+    }
+    beta_c[q] = (T)beta;
+    if (blockIdx.x == 0 && threadIdx.x < G::LPR) const_cast<double*>(sc)[SC<KP>::BETA + c] = beta;
+  }
+
+  double cacc[3][G::VECN];
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int q = 0; q < G::VECN; ++q) cacc[v][q] = 0.0;
+  SplitGram<T, KP, kVpwLoaders, 2> sg;
+  if (loader) {
+    sg.none();
+  } else {
+    sg.setup(wv - kVpwLoaders, lane, 0, 0, true, 1, 0, false, 2);  // P = V^T V, C = X^T V
+  }
+
+  const int64_t ntiles = (a.n + G::TR - 1) / G::TR;
+  const int64_t stride = (int64_t)gridDim.x * kVpwLoaders;
+  const int64_t tb0 = (int64_t)blockIdx.x * kVpwLoaders;
+  const int rounds = tb0 < ntiles ? (int)((ntiles - tb0 + stride - 1) / stride) : 0;
+  T* stage = reinterpret_cast<T*>(smem);
+  // Both roles run rounds + 1 iterations with one barrier each.  A loader
+  // issues the loads of its next tile as soon as the current one is staged,
+  // so they are in flight through the barrier and the products; the two
+  // loops keep the loaders' registers apart from the accumulators.
+  if (loader) {
+    V16<T> pg[G::NPASS], px[G::NPASS], pv[G::NPASS];
+    auto rows_of = [&](int r) {
+      const int64_t t = tb0 + (int64_t)r * stride + wv;
+      return t >= ntiles ? 0 : (int)((a.n - t * G::TR) < G::TR ? (a.n - t * G::TR) : G::TR);
+    };
+    auto fetch = [&](int r) {
+      const int64_t r0 = (tb0 + (int64_t)r * stride + wv) * G::TR;
+      const int cnt = rows_of(r);
+#pragma unroll
+      for (int pass = 0; pass < G::NPASS; ++pass) {
+        const int gi = pass * G::RPW + g;
+        if (gi < cnt) {
+          const size_t off = (size_t)(r0 + gi) * KP + j * G::VECN;
+          pg[pass] = ld16(static_cast<const T*>(a.G) + off);
+          px[pass] = ld16(static_cast<const T*>(a.X) + off);
+          if (!first) pv[pass] = ld16(static_cast<const T*>(a.Vp) + off);
+        }
+      }
+    };
+    if (rounds > 0) fetch(0);
+    for (int r = 0; r <= rounds; ++r) {
+      if (r < rounds) {
+        const int64_t r0 = (tb0 + (int64_t)r * stride + wv) * G::TR;
+        const int cnt = rows_of(r);
+        T* tv = stage + (r & 1) * W::BUF + wv * W::AREA;
+        T* tx = tv + G::TILE_ELEMS;
+#pragma unroll
+        for (int pass = 0; pass < G::NPASS; ++pass) {
+          const int gi = pass * G::RPW + g;
+          const size_t off = (size_t)(r0 + gi) * KP + j * G::VECN;
+          V16<T> v, x;
+          if (gi < cnt) {
+            const V16<T> gv = pg[pass];
+            x = px[pass];
+            if (!first) {
+#pragma unroll
+              for (int q = 0; q < G::VECN; ++q) v.v[q] = fma(beta_c[q], pv[pass].v[q], -gv.v[q]);
+            } else {
+#pragma unroll
+              for (int q = 0; q < G::VECN; ++q) v.v[q] = -gv.v[q];
+            }
+            st16(static_cast<T*>(a.V) + off, v);
+            if (a.Vb) st_bf16<KP>(a.Vb, (size_t)(r0 + gi), j, v);
+#pragma unroll
+            for (int q = 0; q < G::VECN; ++q) cacc[0][q] += (double)v.v[q] * (double)gv.v[q];
+          } else {
+#pragma unroll
+            for (int q = 0; q < G::VECN; ++q) v.v[q] = x.v[q] = T(0);
+          }
+          tile_store_vec<T, KP>(tv, gi, j, v);
+          tile_store_vec<T, KP>(tx, gi, j, x);
+        }
+        if (r + 1 < rounds) fetch(r + 1);
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int r = 0; r <= rounds; ++r) {
+      if (r > 0) sg.template accumulate<true>(stage + ((r - 1) & 1) * W::BUF, W::AREA, lane);
+      __syncthreads();
+    }
+  }
+
+  double* red = reinterpret_cast<double*>(smem);
+  double* prow = a.partials + (size_t)blockIdx.x * a.nv;
+  constexpr int KK = KP * KP;
+  sg.out(0, true, red, prow, 0, lane);
+  sg.out(1, false, red, prow, KK, lane);
+  block_vec_out<T, KP, 1>(cacc, red, prow, 2 * KK, wave, lane, kVpwLoaders);
+}
+
 // ---------------------------------------------------------------------------
 // Deterministic two-level reduction of partial rows:
 // out[v] = sum_b partials[b][v], summed in block order.  The first level sums
@@ -2027,7 +2187,10 @@ static hipError_t spmm_t(PassArgs& a, hipStream_t s) {
 template <typename T, int KP, int MODE>
 static hipError_t dense_mode(PassArgs& a, hipStream_t s) {
   using SM = Smem<T, KP, MODE>;
-  return launch_rounded<dense_kernel<T, KP, MODE>>(a, SM::WPB * 64, SM::bytes, s);
+  if constexpr (sizeof(T) == 4 && KP == 64 && MODE == kVPass)
+    return launch_rounded<vpass_ws_kernel>(a, 2 * kVpwLoaders * 64, VPassWS::bytes, s);
+  else
+    return launch_rounded<dense_kernel<T, KP, MODE>>(a, SM::WPB * 64, SM::bytes, s);
 }
 
 template <typename T, int KP>
