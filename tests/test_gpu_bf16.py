@@ -92,3 +92,31 @@ def test_bf16_f2_solve_floor_and_labels(lib):
         lab, _, _ = ofm.kmeans(Y, 32, O.kmeans_uniforms(0, 32))
         labels[prec] = lab.cpu().numpy()
     assert O.ari(labels[ofm.OFM_FP32], labels[ofm.OFM_FP32_BF16X]) > 0.9
+
+
+def test_bf16_k64_v_copy(lib):
+    """At k = 64 the V pass (its loader waves) also writes the BF16 copy of V
+    that the SpMM of V gathers.  Steps from the same state with and without
+    BF16 storage: beta (formed before any BF16 gather of V) agrees to the
+    rounding of G, alpha (its cubic takes the products over BF16-gathered V
+    rows) closely: a copy left unwritten or misplaced would move it."""
+    from paper_2305_10356_amd import ofm
+    g = graphs.sbm_plain(graphs.equal_sizes(12000, 64), 16.0, 0.2, np.random.default_rng([31, 1]))
+    lap = ofm.Laplacian(g.row_ptr, g.col_idx)
+    x0 = graphs.initial_x(g.n, 64, np.random.default_rng([31, 2])).astype(np.float32)
+    wb = ofm.Workspace(lap, 64, variant="f1", precision=ofm.OFM_FP32_BF16X, check_every=1000000)
+    wf = ofm.Workspace(lap, 64, variant="f1", precision=ofm.OFM_FP32, check_every=1000000)
+    X = torch.tensor(x0, device="cuda")
+    wb.init(X)
+    for t in range(1, 6):
+        Vp, Gp = wb.get_state()
+        Xf = X.clone()
+        wf.set_state(Xf, Vp.clone(), Gp.clone(), t)
+        wb.step(X)
+        wf.step(Xf)
+        ib, if_ = wb.step_info(), wf.step_info()
+        da = np.abs(ib["alpha"] - if_["alpha"]).max() / np.abs(if_["alpha"]).max()
+        db = np.abs(ib["beta"] - if_["beta"]).max() / max(np.abs(if_["beta"]).max(), 1e-30)
+        print(f"k=64 BF16 step {t}: alpha {ib['alpha'][0]:.6e} vs {if_['alpha'][0]:.6e} "
+              f"(rel {da:.1e}), beta rel {db:.1e}", flush=True)
+        assert da < 1e-3 and db < 1e-2, (t, da, db)
