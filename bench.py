@@ -162,9 +162,11 @@ def batched_vs_plain(variant: str, count: int = 256, plain: bool = True):
     ks = [sp["k"] for sp in specs]
     tri = variant.startswith("tri")
 
-    def batched(graph=False, recur=False):
+    def batched(graph=False, recur=False, persistent=False):
         B = ofm.Batch(laps, ks, variant=variant, precision=ofm.OFM_FP32, max_iter=3000,
                       check_every=10, tol=1e-4, restart=tri, recur=recur, graph=graph)
+        if persistent:
+            B.set_persistent(True)
         Xs = [torch.tensor(x0.astype(np.float32), device="cuda") for _, x0 in gl]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -181,12 +183,16 @@ def batched_vs_plain(variant: str, count: int = 256, plain: bool = True):
                                           for d in sched},
                "phase_ms": {"fp32_loop": round(loop_ms, 1), "fp64_finish": round(finish_ms, 1)},
                "graph_replays": B.replays}
+        if persistent:
+            rec["persistent_launches"], rec["persistent_min_workers"] = B.persist_info()
         B.close()
         return rec, st
 
     eager, st_b = batched()
     replayed, _ = batched(graph=True)
     recur, _ = batched(recur=True)
+    # one persistent launch per width group and chunk of 10 updates (f1 forms)
+    persistent = batched(persistent=True)[0] if variant in ("f1", "tri-f1") else None
     st_p, t_plain = [{"converged": 0, "iters": 0}], float("nan")
     if plain:
         wss = [ofm.Workspace(lap, k, variant=variant, precision=ofm.OFM_FP64, max_iter=3000,
@@ -210,6 +216,8 @@ def batched_vs_plain(variant: str, count: int = 256, plain: bool = True):
         "plain_converged": int(sum(s["converged"] for s in st_p)),
         "plain_max_iters": int(max(s["iters"] for s in st_p)),
         "eager": eager, "graph_replayed": replayed, "recur_ax": recur,
+        "persistent": persistent,
+        "persistent_s": persistent["s"] if persistent else None,
         "speedup_recur": round(t_plain / recur["s"], 2),
         "batched_not_converged": [
             {"graph": i, "n": gl[i][0].n, "k": ks[i], "relres": st_b[i]["relres"]}
@@ -979,6 +987,7 @@ def main():
             extras["batched_vs_plain"] = bvp
             summary.update({"batched_fp32_s": bvp["batched_fp32_s"],
                             "batched_form": bvp["batched_form"],
+                            "batched_persistent_s": bvp["persistent_s"],
                             "plain_fp64_loop_s": bvp["plain_fp64_loop_s"],
                             "speedup": bvp["speedup"],
                             "batched_converged": f"{bvp['eager']['converged']}/{bvp['graphs']}",

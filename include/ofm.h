@@ -434,9 +434,10 @@ ofm_status ofm_batch_schedule(ofm_batch b, int group, int* host_ngroups, int* ho
                               int* host_tpw, int* host_workers, double* host_ms,
                               int* host_escalated);
 /* Fix the block schedule of every width group to tpw tiles per wavefront
- * (2, 4, 8 or 16) with at most `workers` blocks per XCD (128 or 64) for the
- * following solves and steps; tpw = 0 times the candidates again at the next
- * solve.  Errors: OFM_E_INVALID_ARG for another value. */
+ * (2, 4, 8 or 16) with at most `workers` blocks per XCD (128 or 64, or any
+ * count from 8 to 63, e.g. to match what a persistent launch keeps resident)
+ * for the following solves and steps; tpw = 0 times the candidates again at
+ * the next solve.  Errors: OFM_E_INVALID_ARG for another value. */
 ofm_status ofm_batch_set_schedule(ofm_batch b, int tpw, int workers);
 /* Host wall time of the last solve's two stages: the lockstep FP32 loop
  * (host_loop_ms, to the end of its last iteration) and what follows it
@@ -445,6 +446,24 @@ ofm_status ofm_batch_set_schedule(ofm_batch b, int tpw, int workers);
  * of the lockstep loop (0 without opts.graph).  Any pointer may be NULL. */
 ofm_status ofm_batch_phases(ofm_batch b, double* host_loop_ms, double* host_finish_ms,
                             int64_t* host_replays);
+/* Persistent form of the lockstep loop: the batched iteration of Algorithm 2
+ * as one launch per width group and chunk instead of one per pass.  on = 1: every check_every updates of the loop after the schedule timing run
+ * as one cooperative launch per width group that walks the passes of an
+ * update (SpMM of X with the direction, [residual], V pass, SpMM of V over the
+ * upper-triangle copy, line search, update) with a grid-wide barrier after
+ * each pass and after each of its per-graph reductions; the groups run one
+ * after another on the solve's stream, each with as many workers per XCD as
+ * its schedule gives and stay resident.  With the same workers per XCD the
+ * iterates are bitwise those of the per-pass launches.  on = 0: per-pass
+ * launches (eager or graph-replayed by opts.graph).  Supported for OFM-f1 and
+ * TriOFM-f1, OFM_FP32, recur = 0, every k <= 32 (else OFM_E_UNSUPPORTED;
+ * OFM_E_INVALID_ARG for on not 0 or 1).  A barrier wait beyond its spin limit
+ * (2^24 polls) lets the launch run to its end and makes ofm_batch_solve return
+ * OFM_E_HIP.  Allocates two small device words on the first call with on = 1. */
+ofm_status ofm_batch_set_persistent(ofm_batch b, int on);
+/* Persistent launches of the last ofm_batch_solve and the fewest workers per
+ * XCD any of them used (0 when none ran).  Either pointer may be NULL. */
+ofm_status ofm_batch_persist_info(ofm_batch b, int64_t* host_launches, int* host_workers);
 
 /*
  * Host copy (synchronizing) of one k x k FP64 product held by the workspace,

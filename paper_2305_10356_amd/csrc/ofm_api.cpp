@@ -1746,6 +1746,7 @@ struct ofm_batch_s {
   std::vector<int> ks;
   std::vector<BatchGroup> groups;
   int fixed = -1;          // candidate set by ofm_batch_set_schedule (-1: timed)
+  int wcap = 0;            // blocks per XCD below 64 set by ofm_batch_set_schedule (0: none)
   bool tuned = false;      // the groups' candidates were timed (kept for later solves)
   int escalated = 0;
   double loop_ms = 0.0;    // host time of the lockstep loop of the last solve
@@ -1765,6 +1766,12 @@ struct ofm_batch_s {
   hipGraphExec_t chunk[2] = {nullptr, nullptr};
   std::vector<int> chunk_cand;
   int64_t replays = 0;     // chunks replayed by the last solve
+  // persistent form of the lockstep loop (ofm_batch_set_persistent)
+  bool persistent = false;
+  unsigned* pbar = nullptr;  // [2] barrier words of the persistent launches
+  int* perr = nullptr;       // set by a barrier wait that timed out
+  int64_t plaunches = 0;     // persistent launches of the last solve
+  int pworkers = 0;          // fewest workers per XCD a persistent launch used
   // copies of the starting blocks of the graphs that may be finished in FP64
   // (k <= 32, with a tolerance), taken when a solve starts: x0 + x0_off[i]
   float* x0 = nullptr;
@@ -1774,6 +1781,8 @@ struct ofm_batch_s {
 static void free_batch(ofm_batch b) {
   if (!b) return;
   dev_free(b->x0);
+  dev_free(b->pbar);
+  dev_free(b->perr);
   for (auto& e : b->chunk)
     if (e) (void)hipGraphExecDestroy(e);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
@@ -1991,7 +2000,8 @@ extern "C" ofm_status ofm_batch_schedule(ofm_batch b, int group, int* host_ngrou
   const BatchGroup& g = b->groups[group];
   if (host_k) *host_k = g.k;
   if (host_tpw) *host_tpw = cand_tpw(g.chosen);
-  if (host_workers) *host_workers = cand_workers(g.chosen);
+  if (host_workers)
+    *host_workers = b->wcap > 0 ? std::min(b->wcap, cand_workers(g.chosen)) : cand_workers(g.chosen);
   if (host_ms)
     for (int c = 0; c < kBatchCand; ++c) host_ms[c] = g.cand_ms[c];
   return OFM_OK;
@@ -2002,10 +2012,14 @@ extern "C" ofm_status ofm_batch_set_schedule(ofm_batch b, int tpw, int workers) 
   if (tpw == 0) {
     b->fixed = -1;
     b->tuned = false;
+    b->wcap = 0;
     return OFM_OK;
   }
+  const int cap = (workers >= 8 && workers < 64) ? workers : 0;
+  if (cap) workers = 64;
   for (int c = 0; c < kBatchCand; ++c)
     if (cand_tpw(c) == tpw && cand_workers(c) == workers) {
+      b->wcap = cap;
       b->fixed = c;
       for (auto& g : b->groups) g.chosen = c;
       return OFM_OK;
@@ -2019,6 +2033,29 @@ extern "C" ofm_status ofm_batch_phases(ofm_batch b, double* host_loop_ms, double
   if (host_loop_ms) *host_loop_ms = b->loop_ms;
   if (host_finish_ms) *host_finish_ms = b->finish_ms;
   if (host_replays) *host_replays = b->replays;
+  return OFM_OK;
+}
+
+extern "C" ofm_status ofm_batch_set_persistent(ofm_batch b, int on) {
+  if (!b || (on != 0 && on != 1)) return OFM_E_INVALID_ARG;
+  if (on) {
+    const ofm_opts& o = b->opts;
+    if ((o.variant != OFM_F1 && o.variant != OFM_TRI_F1) || o.precision != OFM_FP32 || o.recur)
+      return OFM_E_UNSUPPORTED;
+    for (auto& g : b->groups)
+      if (g.k > 32) return OFM_E_UNSUPPORTED;
+    if (!b->pbar) OFMCHK(dev_alloc(&b->pbar, 2));
+    if (!b->perr) OFMCHK(dev_alloc(&b->perr, 1));
+  }
+  b->persistent = on != 0;
+  return OFM_OK;
+}
+
+extern "C" ofm_status ofm_batch_persist_info(ofm_batch b, int64_t* host_launches,
+                                             int* host_workers) {
+  if (!b) return OFM_E_INVALID_ARG;
+  if (host_launches) *host_launches = b->plaunches;
+  if (host_workers) *host_workers = b->pworkers;
   return OFM_OK;
 }
 
@@ -2200,7 +2237,7 @@ static ofm_status batch_iteration(ofm_batch B, BatchGroup& g, int cur, int64_t t
   base.xlist = g.dxlist;
   base.xoff = g.dxoff;
   base.tcount = g.tcount;
-  base.workers = cand_workers(cand);
+  base.workers = B->wcap > 0 ? std::min(B->wcap, cand_workers(cand)) : cand_workers(cand);
   base.tpw = cand_tpw(cand);
   base.check_every = o.check_every;
   base.ngraphs = (int)g.idx.size();
@@ -2356,6 +2393,64 @@ static ofm_status batch_run_chunk(ofm_batch B, hipStream_t stream) {
   return OFM_OK;
 }
 
+// The check_every updates that start at B->t (as batch_run_chunk) as one
+// persistent launch per width group, the groups one after another on
+// `stream` (a cooperative launch needs its whole grid resident, so the groups
+// do not share the chip).
+static ofm_status batch_run_persistent(ofm_batch B, hipStream_t stream) {
+  const ofm_opts& o = B->opts;
+  const int rs = o.restart ? kFlagRestart : 0;
+  for (auto& g : B->groups) {
+    BatchArgs base;
+    base.k = g.k;
+    base.variant = o.variant;
+    base.tol = o.tol;
+    base.freeze_eps = o.freeze_eps;
+    base.graphs = g.dgraphs;
+    base.xlist = g.dxlist;
+    base.xoff = g.dxoff;
+    base.tcount = g.tcount;
+    base.workers = B->wcap > 0 ? std::min(B->wcap, cand_workers(g.chosen)) : cand_workers(g.chosen);
+    base.tpw = cand_tpw(g.chosen);
+    base.check_every = o.check_every;
+    base.ngraphs = (int)g.idx.size();
+    base.upper = 1;
+    BatchPersistArgs p;
+    auto pass = [&](int which, int mode, int flags) {
+      for (int c = 0; c < 2; ++c) {
+        BatchArgs& a = p.pass[which][c];
+        a = base;
+        a.mode = mode;
+        a.flags = flags;
+        a.cur = c;
+        a.nv = partial_nv(g.k, mode, flags);
+        a.off = partial_off(g.k, mode);
+      }
+    };
+    pass(kPGF1, kGF1, rs);
+    pass(kPGF1C, kGF1, kFlagCheck | rs);
+    pass(kPVPass, kVPass, rs);
+    pass(kPAV, kAVF1, kFlagUpper);
+    pass(kPUpdate, kUpdate, 0);
+    p.t0 = B->t;
+    p.cur0 = B->cur;
+    p.steps = o.check_every;
+    p.alpha0 = o.alpha0;
+    p.bar = B->pbar;
+    p.err = B->perr;
+    HIPCHK(hipMemsetAsync(B->pbar, 0, 2 * sizeof(unsigned), stream));
+    int used = 0;
+    HIPCHK(launch_batch_persist(g.k, p, base.workers, &used, stream));
+    B->pworkers = B->pworkers == 0 ? used : std::min(B->pworkers, used);
+    ++B->plaunches;
+  }
+  const int ce = o.check_every;
+  B->last_check = ((B->t + ce - 1) / ce) * ce;
+  B->t += ce;
+  B->cur ^= (ce & 1);
+  return OFM_OK;
+}
+
 // 1 when any graph of the batch still iterates (synchronizing on `stream`,
 // which must already be ordered after the work that set the flags)
 static ofm_status batch_any_active(ofm_batch B, hipStream_t stream, int* any) {
@@ -2449,6 +2544,9 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
   // group's own time under contention would favour schedules that only take
   // more of it from the others.
   B->replays = 0;
+  B->plaunches = 0;
+  B->pworkers = 0;
+  if (B->persistent) HIPCHK(hipMemsetAsync(B->perr, 0, sizeof(int), stream));
   // the starting blocks of the graphs that may need a finishing solve
   if (B->x0)
     for (int i = 0; i < B->count; ++i)
@@ -2466,12 +2564,14 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
   while (B->t < o.max_iter) {
     const bool tuning = B->t < tune_end;
     const int cand = tuning ? (int)((B->t - 1) / 2) : -1;
-    if (!tuning && o.graph && B->t % ce == 1 % ce && B->t + ce <= o.max_iter) {
+    if (!tuning && (o.graph || B->persistent) && B->t % ce == 1 % ce &&
+        B->t + ce <= o.max_iter) {
       if (!on_stream) {
         OFMCHK(batch_join(B, stream));
         on_stream = true;
       }
-      OFMCHK(batch_run_chunk(B, stream));
+      if (B->persistent) OFMCHK(batch_run_persistent(B, stream));
+      else OFMCHK(batch_run_chunk(B, stream));
       int any = 0;
       OFMCHK(batch_any_active(B, stream, &any));
       if (!any) break;
@@ -2512,6 +2612,11 @@ extern "C" ofm_status ofm_batch_solve(ofm_batch B, void* const* host_X, hipStrea
   }
   if (on_stream) OFMCHK(batch_fork(B, stream));
   for (auto& g : B->groups) HIPCHK(hipStreamSynchronize(g.stream));
+  if (B->persistent) {
+    int err = 0;
+    HIPCHK(hipMemcpy(&err, B->perr, sizeof(int), hipMemcpyDeviceToHost));
+    if (err) return OFM_E_HIP;  // a grid barrier of a persistent launch timed out
+  }
   const auto t_loop = std::chrono::steady_clock::now();
   B->loop_ms = std::chrono::duration<double, std::milli>(t_loop - t_solve).count();
   const int64_t t = B->t;

@@ -227,6 +227,24 @@ struct BatchArgs {
   int off = 0;       // first scalar slot the mode's products go to
   int upper = 0;     // f1: diag(V^T A V) from the upper-triangle copies (graphs that have one)
 };
+// Persistent form of the lockstep loop (f1 / TriOFM-f1, FP32 without BF16
+// copies, two products with A per update, k <= 32): `steps` updates from step
+// t0 (slot cur0) of one width group in one cooperative launch.  The BatchArgs
+// of each pass carry its mode, flags, nv and off, one copy per ping-pong slot.
+enum { kPGF1 = 0, kPGF1C, kPVPass, kPAV, kPUpdate, kPPasses };  // kPGF1C: a checked step
+struct BatchPersistArgs {
+  BatchArgs pass[kPPasses][2];  // [pass][cur]
+  int64_t t0 = 0;
+  int cur0 = 0;
+  int steps = 0;
+  double alpha0 = 0.0;
+  unsigned* bar = nullptr;  // [2] zeroed: arrivals, generation
+  int* err = nullptr;       // set when a barrier wait timed out
+};
+// workers per XCD: at most max_workers and what stays resident; the count
+// used is returned in *used_workers
+hipError_t launch_batch_persist(int k, BatchPersistArgs& p, int max_workers, int* used_workers,
+                                hipStream_t s);
 hipError_t launch_batch_spmm(int k, BatchArgs& b, hipStream_t s);
 hipError_t launch_batch_dense(int k, BatchArgs& b, hipStream_t s);
 hipError_t launch_batch_finalize(BatchArgs& b, hipStream_t s);

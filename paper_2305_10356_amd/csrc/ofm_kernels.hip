@@ -2453,11 +2453,12 @@ __device__ __host__ inline int batch_graph_workers(int64_t ntiles, int wpb, int 
   return (int)(w < 1 ? 1 : (w > workers ? workers : w));
 }
 
+// the share of workgroup blk of a batched SpMM pass (blk = blockIdx.x of the
+// per-pass launch, or of the persistent launch)
 template <int KP, int MODE, bool CHECK, bool BF>
-__global__ void __launch_bounds__((Cfg<float, KP>::WPB * 64)) batch_spmm_kernel(BatchArgs b) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int x = blockIdx.x & 7;
-  const int w = blockIdx.x >> 3;
+__device__ __forceinline__ void batch_spmm_run(const BatchArgs& b, int blk, unsigned char* smem) {
+  const int x = blk & 7;
+  const int w = blk >> 3;
   int base = 0;
   for (int i = b.xoff[x]; i < b.xoff[x + 1]; ++i) {
     const BatchGraph& d = b.graphs[b.xlist[i]];
@@ -2471,11 +2472,16 @@ __global__ void __launch_bounds__((Cfg<float, KP>::WPB * 64)) batch_spmm_kernel(
   }
 }
 
-template <int KP, int MODE>
-__global__ void __launch_bounds__((Cfg<float, KP>::WPB * 64)) batch_dense_kernel(BatchArgs b) {
+template <int KP, int MODE, bool CHECK, bool BF>
+__global__ void __launch_bounds__((Cfg<float, KP>::WPB * 64)) batch_spmm_kernel(BatchArgs b) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int x = blockIdx.x & 7;
-  const int w = blockIdx.x >> 3;
+  batch_spmm_run<KP, MODE, CHECK, BF>(b, blockIdx.x, smem);
+}
+
+template <int KP, int MODE>
+__device__ __forceinline__ void batch_dense_run(const BatchArgs& b, int blk, unsigned char* smem) {
+  const int x = blk & 7;
+  const int w = blk >> 3;
   int base = 0;
   for (int i = b.xoff[x]; i < b.xoff[x + 1]; ++i) {
     const BatchGraph& d = b.graphs[b.xlist[i]];
@@ -2489,6 +2495,12 @@ __global__ void __launch_bounds__((Cfg<float, KP>::WPB * 64)) batch_dense_kernel
   }
 }
 
+template <int KP, int MODE>
+__global__ void __launch_bounds__((Cfg<float, KP>::WPB * 64)) batch_dense_kernel(BatchArgs b) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  batch_dense_run<KP, MODE>(b, blockIdx.x, smem);
+}
+
 // Per-graph sum of its block partial rows, in block order: rows are summed in
 // groups of kFinChunk (blockIdx.z = group); with more than one group the group
 // sums go to the graph's lvl2 rows and batch_finalize2_kernel adds them in
@@ -2500,15 +2512,16 @@ __device__ inline void batch_store(const BatchArgs& b, const BatchGraph& d, int 
   d.sc[v < split ? b.off + v : SC<KP>::H + (v - split)] = s;
 }
 
+// (bx, by, bz): the 64-lane block of the per-pass launch's grid, lane < 64
 template <int KP>
-__global__ void __launch_bounds__(64) batch_finalize_kernel(BatchArgs b) {
-  const BatchGraph& d = b.graphs[blockIdx.y];
+__device__ inline void batch_finalize_run(const BatchArgs& b, int bx, int by, int bz, int lane) {
+  const BatchGraph& d = b.graphs[by];
   if (*d.active == 0) return;
-  const int v = blockIdx.x * 64 + threadIdx.x;
+  const int v = bx * 64 + lane;
   if (v >= b.nv) return;
   const int nw = batch_graph_workers(d.ntiles, Cfg<float, KP>::WPB, b.tpw, b.workers);
   const int ng = (nw + kFinChunk - 1) / kFinChunk;
-  const int b0 = blockIdx.z * kFinChunk;
+  const int b0 = bz * kFinChunk;
   if (b0 >= nw) return;
   double x[kFinChunk];
 #pragma unroll
@@ -2518,14 +2531,19 @@ __global__ void __launch_bounds__(64) batch_finalize_kernel(BatchArgs b) {
 #pragma unroll
   for (int q = 0; q < kFinChunk; ++q) s += x[q];
   if (ng == 1) batch_store<KP>(b, d, v, s);
-  else d.lvl2[(size_t)blockIdx.z * b.nv + v] = s;
+  else d.lvl2[(size_t)bz * b.nv + v] = s;
 }
 
 template <int KP>
-__global__ void __launch_bounds__(64) batch_finalize2_kernel(BatchArgs b) {
-  const BatchGraph& d = b.graphs[blockIdx.y];
+__global__ void __launch_bounds__(64) batch_finalize_kernel(BatchArgs b) {
+  batch_finalize_run<KP>(b, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x);
+}
+
+template <int KP>
+__device__ inline void batch_finalize2_run(const BatchArgs& b, int bx, int by, int lane) {
+  const BatchGraph& d = b.graphs[by];
   if (*d.active == 0) return;
-  const int v = blockIdx.x * 64 + threadIdx.x;
+  const int v = bx * 64 + lane;
   if (v >= b.nv) return;
   const int nw = batch_graph_workers(d.ntiles, Cfg<float, KP>::WPB, b.tpw, b.workers);
   const int ng = (nw + kFinChunk - 1) / kFinChunk;
@@ -2541,22 +2559,35 @@ __global__ void __launch_bounds__(64) batch_finalize2_kernel(BatchArgs b) {
 }
 
 template <int KP>
-__global__ void __launch_bounds__(256) batch_linesearch_kernel(BatchArgs b, double alpha0,
-                                                               int first_fixed) {
-  // the group's step counter: this is the last pass that reads the step's
-  // scalars, and the residual of the next step reads the new value
-  if (blockIdx.x == 0 && threadIdx.x == 0) *b.tcount += 1;
-  const BatchGraph& d = b.graphs[blockIdx.x];
+__global__ void __launch_bounds__(64) batch_finalize2_kernel(BatchArgs b) {
+  batch_finalize2_run<KP>(b, blockIdx.x, blockIdx.y, threadIdx.x);
+}
+
+// line search of graph gi (a 256-thread workgroup)
+template <int KP>
+__device__ inline void batch_linesearch_run(const BatchArgs& b, int gi, double alpha0,
+                                            int first_fixed) {
+  const BatchGraph& d = b.graphs[gi];
   if (*d.active == 0) return;
   linesearch_body<KP>(b.variant, first_fixed, alpha0, d.sc, d.status, nullptr, false,
                       b.freeze_eps, (b.upper != 0 && d.upk != nullptr) ? 1 : 0);
 }
 
-// residual of X^t; a graph whose residual meets the tolerance (or whose
-// status turned non-zero) stops iterating with this X
 template <int KP>
-__global__ void __launch_bounds__(256) batch_residual_kernel(BatchArgs b) {
-  const BatchGraph& d = b.graphs[blockIdx.x];
+__global__ void __launch_bounds__(256) batch_linesearch_kernel(BatchArgs b, double alpha0,
+                                                               int first_fixed) {
+  // the group's step counter: this is the last pass that reads the step's
+  // scalars, and the residual of the next step reads the new value
+  if (blockIdx.x == 0 && threadIdx.x == 0) *b.tcount += 1;
+  batch_linesearch_run<KP>(b, blockIdx.x, alpha0, first_fixed);
+}
+
+// residual of X^t of graph gi (a 256-thread workgroup); a graph whose
+// residual meets the tolerance (or whose status turned non-zero) stops
+// iterating with this X
+template <int KP>
+__device__ inline void batch_residual_run(const BatchArgs& b, int gi) {
+  const BatchGraph& d = b.graphs[gi];
   if (*d.active == 0) return;
   residual_body<KP>(b.variant, d.normA2, d.sc, d.status, 0.0, nullptr);
   __syncthreads();
@@ -2578,6 +2609,177 @@ __global__ void __launch_bounds__(256) batch_residual_kernel(BatchArgs b) {
       d.hist[slot] = rr;
     }
   }
+}
+
+template <int KP>
+__global__ void __launch_bounds__(256) batch_residual_kernel(BatchArgs b) {
+  batch_residual_run<KP>(b, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent form of the batched lockstep loop (f1 and TriOFM-f1, FP32, two
+// products with A per update): one cooperative launch per width group runs a
+// chunk of updates, the passes of the per-pass launches one after another
+// with a grid-wide barrier between them (every pass ends in a per-graph
+// reduction that the next pass reads).  Workgroup blk does what workgroup blk
+// of a per-pass launch with the same number of workers does, so the results
+// are bitwise those of the per-pass launches; the 64-lane reductions are
+// dealt to the waves, the line searches and residuals to the workgroups.
+// ---------------------------------------------------------------------------
+
+// Sense-reversing barrier over the nblk workgroups of a cooperative launch
+// (bar[0]: arrivals, bar[1]: generation).  The agent-scope release / acquire
+// fences make each workgroup's global writes visible to every XCD.  A wait
+// longer than kBarrierSpins polls sets *err and lets the workgroup go on
+// (then every later barrier of the launch is skipped), so the kernel always
+// ends; the host reports the flag as an error.
+constexpr long kBarrierSpins = 1L << 24;
+__device__ inline void grid_barrier(unsigned* bar, int* err, unsigned nblk) {
+  // every wave's stores have reached its XCD's L2 before the release below
+  // writes the dirty lines back
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+      const unsigned gen = __hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const unsigned arrived =
+          __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (arrived == nblk - 1) {
+        __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(bar + 1, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        long spins = 0;
+        while (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > kBarrierSpins) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+  }
+  __syncthreads();
+}
+
+// the per-graph reduction of a pass: first level, then (more than kFinChunk
+// workers) the second, each 64-lane block of the per-pass grid taken by a wave
+template <int KP>
+__device__ inline void persist_finalize(const BatchArgs& b, unsigned* bar, int* err) {
+  constexpr int WPB = Cfg<float, KP>::WPB;
+  const int lane = threadIdx.x & 63;
+  const int gw = blockIdx.x * WPB + (threadIdx.x >> 6);
+  const int nwv = gridDim.x * WPB;
+  const int nx = (b.nv + 63) / 64;
+  const int groups = (b.workers + kFinChunk - 1) / kFinChunk;
+  const int n1 = nx * b.ngraphs * groups;
+  for (int q = gw; q < n1; q += nwv)
+    batch_finalize_run<KP>(b, q % nx, (q / nx) % b.ngraphs, q / (nx * b.ngraphs), lane);
+  grid_barrier(bar, err, gridDim.x);
+  if (groups > 1) {
+    for (int q = gw; q < nx * b.ngraphs; q += nwv)
+      batch_finalize2_run<KP>(b, q % nx, q / nx, lane);
+    grid_barrier(bar, err, gridDim.x);
+  }
+}
+
+// Compiled for two waves per SIMD (two workgroups per CU): with every pass
+// inlined the compiler would otherwise take the whole register file, one wave
+// per SIMD, too few gathers in flight for the products with A.
+template <int KP>
+__global__ void __launch_bounds__((Cfg<float, KP>::WPB * 64), 2)
+    batch_persist_kernel(BatchPersistArgs p) {
+  static_assert(Cfg<float, KP>::WPB * 64 == 256, "the line search and residual need 256 threads");
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int s = 0; s < p.steps; ++s) {
+    const int64_t t = p.t0 + s;
+    const int cur = p.cur0 ^ (s & 1);
+    const bool check = (t % p.pass[kPGF1][0].check_every) == 0;
+    {
+      const BatchArgs& b = p.pass[check ? kPGF1C : kPGF1][cur];
+      if (check) batch_spmm_run<KP, kGF1, true, false>(b, blockIdx.x, smem);
+      else batch_spmm_run<KP, kGF1, false, false>(b, blockIdx.x, smem);
+      grid_barrier(p.bar, p.err, gridDim.x);
+      persist_finalize<KP>(b, p.bar, p.err);
+      if (check) {
+        for (int gi = blockIdx.x; gi < b.ngraphs; gi += gridDim.x) {
+          batch_residual_run<KP>(b, gi);
+          __syncthreads();
+        }
+        grid_barrier(p.bar, p.err, gridDim.x);
+      }
+    }
+    {
+      const BatchArgs& b = p.pass[kPVPass][cur];
+      batch_dense_run<KP, kVPass>(b, blockIdx.x, smem);
+      grid_barrier(p.bar, p.err, gridDim.x);
+      persist_finalize<KP>(b, p.bar, p.err);
+    }
+    {
+      const BatchArgs& b = p.pass[kPAV][cur];
+      batch_spmm_run<KP, kAVF1, false, false>(b, blockIdx.x, smem);
+      grid_barrier(p.bar, p.err, gridDim.x);
+      persist_finalize<KP>(b, p.bar, p.err);
+      // the step counter is read by the residual of the next step only
+      if (blockIdx.x == 0 && threadIdx.x == 0) *b.tcount += 1;
+      for (int gi = blockIdx.x; gi < b.ngraphs; gi += gridDim.x) {
+        batch_linesearch_run<KP>(b, gi, p.alpha0, 0);
+        __syncthreads();
+      }
+      grid_barrier(p.bar, p.err, gridDim.x);
+    }
+    {
+      const BatchArgs& b = p.pass[kPUpdate][cur];
+      batch_dense_run<KP, kUpdate>(b, blockIdx.x, smem);
+      grid_barrier(p.bar, p.err, gridDim.x);
+      persist_finalize<KP>(b, p.bar, p.err);
+    }
+  }
+}
+
+template <int KP>
+static int persist_smem() {
+  int m = Smem<float, KP, kGF1>::bytes;
+  m = m > Smem<float, KP, kVPass>::bytes ? m : Smem<float, KP, kVPass>::bytes;
+  m = m > Smem<float, KP, kAVF1>::bytes ? m : Smem<float, KP, kAVF1>::bytes;
+  m = m > Smem<float, KP, kUpdate>::bytes ? m : Smem<float, KP, kUpdate>::bytes;
+  return m;
+}
+
+template <int KP>
+static hipError_t persist_launch_t(BatchPersistArgs& p, int max_workers, int* used_workers,
+                                   hipStream_t s) {
+  const int smem = persist_smem<KP>();
+  int occ = 0, dev = 0, cus = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_persist_kernel<KP>,
+                                                              256, smem);
+  if (e != hipSuccess) return e;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return e;
+  // every workgroup must be resident at once (the barriers wait for all)
+  int workers = (occ * cus) / 8;
+  if (workers > max_workers) workers = max_workers;
+  if (workers < 1) return hipErrorCooperativeLaunchTooLarge;
+  for (auto& row : p.pass)
+    for (auto& a : row) a.workers = workers;
+  *used_workers = workers;
+  void* args[] = {&p};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(batch_persist_kernel<KP>),
+                                    dim3(8 * workers), dim3(256), args, smem, s);
+}
+
+hipError_t launch_batch_persist(int k, BatchPersistArgs& p, int max_workers, int* used_workers,
+                                hipStream_t s) {
+  switch (k) {
+    case 4: return persist_launch_t<4>(p, max_workers, used_workers, s);
+    case 8: return persist_launch_t<8>(p, max_workers, used_workers, s);
+    case 16: return persist_launch_t<16>(p, max_workers, used_workers, s);
+    case 32: return persist_launch_t<32>(p, max_workers, used_workers, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 // A batched pass runs 8 x workers workgroups; workers is trimmed so that the

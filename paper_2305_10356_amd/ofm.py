@@ -117,6 +117,8 @@ _SIGS = {
     "ofm_batch_phases": (_I, [_P, _P, _P, _P]),
     "ofm_batch_init": (_I, [_P, _P, _P]),
     "ofm_batch_set_schedule": (_I, [_P, _I, _I]),
+    "ofm_batch_set_persistent": (_I, [_P, _I]),
+    "ofm_batch_persist_info": (_I, [_P, _P, _P]),
     "ofm_batch_step": (_I, [_P, _P]),
     "ofm_batch_get_state": (_I, [_P, _I, _P, _P, _P]),
     "ofm_batch_get_step_info": (_I, [_P, _I, _P, _P, _P, _P, _P]),
@@ -489,9 +491,23 @@ class Batch:
 
     def set_schedule(self, tpw: int, workers: int = 128):
         """Fix every group's schedule: tiles per wavefront (2, 4, 8 or 16) and
-        blocks per XCD (128 or 64); tpw = 0: time the candidates again."""
+        blocks per XCD (128, 64 or 8-63); tpw = 0: time the candidates again."""
         _check(self._lib.ofm_batch_set_schedule(self.handle, int(tpw), int(workers)),
                "ofm_batch_set_schedule")
+
+    def set_persistent(self, on: bool = True):
+        """Run the lockstep loop as one persistent launch per width group and
+        chunk of check_every updates (f1 / tri-f1, FP32, no recurrence, k <= 32)."""
+        _check(self._lib.ofm_batch_set_persistent(self.handle, 1 if on else 0),
+               "ofm_batch_set_persistent")
+
+    def persist_info(self):
+        """(persistent launches of the last solve, fewest workers per XCD used)."""
+        n = ctypes.c_int64()
+        w = ctypes.c_int()
+        _check(self._lib.ofm_batch_persist_info(self.handle, ctypes.byref(n), ctypes.byref(w)),
+               "ofm_batch_persist_info")
+        return n.value, w.value
 
     def schedule(self):
         """([{k, tpw, workers, ms[8]} per width group], graphs finished in

@@ -287,3 +287,52 @@ def test_batch_schedule_per_group_and_kept(batch_graphs):
         B.set_schedule(3, 128)
     with pytest.raises(ofm.OfmError):
         B.set_schedule(4, 100)
+
+
+@pytest.mark.parametrize("variant,restart", [("f1", False), ("tri-f1", True)])
+def test_batch_persistent_bitwise_per_pass(batch_graphs, variant, restart):
+    # one persistent launch per width group and chunk of check_every updates
+    # (grid barriers between the passes) gives bit for bit the iterates and
+    # counts of the per-pass launches with the same workers per XCD
+    from paper_2305_10356_amd import ofm
+    gs, laps = batch_graphs
+    ks = [k for _, _, k in gs]
+
+    def run(persistent, workers):
+        B = ofm.Batch(laps, ks, variant=variant, max_iter=3000, tol=1e-4, check_every=10,
+                      restart=restart)
+        B.set_schedule(4, workers)
+        if persistent:
+            B.set_persistent(True)
+        Xs = [torch.tensor(x0.astype(np.float32), device="cuda") for _, x0, _ in gs]
+        print(f"  {variant}: persistent={persistent} workers<={workers} solving", flush=True)
+        st = B.solve(Xs)
+        torch.cuda.synchronize()
+        info = B.persist_info()
+        B.close()
+        return Xs, st, info
+
+    _, _, (n0, w) = run(True, 64)   # the workers per XCD the persistent launch keeps resident
+    print(f"  {variant}: persistent launches {n0}, workers per XCD {w}", flush=True)
+    assert n0 > 0 and 8 <= w <= 64
+    Xe, se, ie = run(False, w)
+    Xp, sp, ip = run(True, w)
+    assert ie == (0, 0) and ip == (n0, w)
+    for a, b, x, y in zip(se, sp, Xe, Xp):
+        assert a["converged"] and b["converged"]
+        assert a["iters"] == b["iters"] and a["relres"] == b["relres"], (a, b)
+        assert torch.equal(x, y)
+
+
+def test_batch_persistent_refused_where_unsupported(batch_graphs):
+    from paper_2305_10356_amd import ofm
+    gs, laps = batch_graphs
+    ks = [k for _, _, k in gs]
+    for kw in ({"variant": "f2"}, {"variant": "f1", "recur": True},
+               {"variant": "f1", "precision": ofm.OFM_FP32_BF16X}):
+        B = ofm.Batch(laps, ks, **kw)
+        with pytest.raises(ofm.OfmError) as e:
+            B.set_persistent(True)
+        assert e.value.status == -8  # OFM_E_UNSUPPORTED
+        B.set_persistent(False)
+        B.close()
