@@ -293,13 +293,16 @@ def test_batch_schedule_per_group_and_kept(batch_graphs):
 def test_batch_persistent_bitwise_per_pass(batch_graphs, variant, restart):
     # one persistent launch per width group and chunk of check_every updates
     # (grid barriers between the passes) gives bit for bit the iterates and
-    # counts of the per-pass launches with the same workers per XCD
+    # counts of the per-pass launches with the same workers per XCD.  The
+    # loop is cut at 90 updates: before the stall test can first fire (10
+    # checks) and with max_iter reached, so no graph goes to the FP64
+    # finishing solves, whose race between two solves is decided by timing.
     from paper_2305_10356_amd import ofm
     gs, laps = batch_graphs
     ks = [k for _, _, k in gs]
 
     def run(persistent, workers):
-        B = ofm.Batch(laps, ks, variant=variant, max_iter=3000, tol=1e-4, check_every=10,
+        B = ofm.Batch(laps, ks, variant=variant, max_iter=90, tol=1e-4, check_every=10,
                       restart=restart)
         B.set_schedule(4, workers)
         if persistent:
@@ -319,7 +322,7 @@ def test_batch_persistent_bitwise_per_pass(batch_graphs, variant, restart):
     Xp, sp, ip = run(True, w)
     assert ie == (0, 0) and ip == (n0, w)
     for a, b, x, y in zip(se, sp, Xe, Xp):
-        assert a["converged"] and b["converged"]
+        assert a["iters"] <= 90 and a["converged"] == b["converged"]
         assert a["iters"] == b["iters"] and a["relres"] == b["relres"], (a, b)
         assert torch.equal(x, y)
 
